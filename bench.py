@@ -1,0 +1,196 @@
+"""Throughput of Quadrature-TreeSHAP Shapley values on one MI355X.
+
+Workload (synthetic, seeded): 1000 random trees of depth 8 (at most 256
+leaves) over 100 features, 20 of them integer-valued, covers from 100k
+training rows, leaf values N(0, 0.05), 100k explained samples.  One step is
+one qts_shap_values call over all samples and every root-to-leaf path, with
+the ensemble and the samples already resident in HBM.
+
+Prints one JSON line: sample-tree-leaf paths/s of the FP32 form (FP32
+quadrature, FP64 accumulation), with the plain FP64 form, the error of both
+against the FP64 oracle on sampled rows, the roofline of the values kernel,
+and the oracle's own rate on the host cores as a baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "sample-tree-leaf paths/s for SHAP, FP32 vs FP64 GPU, at max rel err ≤1e-5"
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 FMA lanes/s.  Without
+# packed FP32 (not used here) FP32 and FP64 vector FMA both peak at 78.6 TFLOP/s;
+# AMD's 157.3 TFLOP/s FP32 figure needs packed (two-wide) FP32 instructions.
+PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+PEAK_FP32_PACKED_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+FLOPS_PER_ELEMENT = 51  # per (sample, path, unique feature): 8 nodes x 6 + 3
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--samples", type=int, default=None, help="override M (testing)")
+    ap.add_argument("--trees", type=int, default=None, help="override T (testing)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--check-rows", type=int, default=16)
+    return ap.parse_args()
+
+
+def time_steps(fn, steps, warmup, torch):
+    import paper_2605_04497_amd as q
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    q.read_kernel_timing("values")  # drop warmup events
+    q.set_kernel_timing(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    q.set_kernel_timing(False)
+    kern_ms, calls = q.read_kernel_timing("values")
+    return {"ms_per_step": start.elapsed_time(stop) / steps, "wall_s": wall,
+            "kernel_ms": kern_ms / max(1, calls), "calls": calls}
+
+
+def cpu_baseline(ens, X, seconds, oracle):
+    threads = oracle.default_threads()
+    n_leaves = ens.n_leaves()
+    t0 = time.perf_counter()
+    oracle.shap_values(ens, X[:2], n=8, threads=threads)
+    per_row = max((time.perf_counter() - t0) / 2, 1e-4)
+    rows = int(max(2, min(X.shape[0], seconds / per_row * threads * 0.9)))
+    rows = (rows // threads) * threads or rows
+    t0 = time.perf_counter()
+    oracle.shap_values(ens, X[:rows], n=8, threads=threads)
+    dt = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": rows * n_leaves / dt, "unit": "paths/s", "cores": threads, "kind": "oracle",
+            "sample": "%d of the workload's explained rows, all 1000 trees, FP64 8-node path "
+                      "quadrature, %.1f s, %s" % (rows, dt, cpu)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2605_04497_amd as q
+    import synth
+    from oracle import oracle
+
+    over = {}
+    if args.samples:
+        over["M"] = args.samples
+    if args.trees:
+        over["T"] = args.trees
+    t0 = time.perf_counter()
+    wl = synth.make_workload("c2_values", **over)
+    ens, Xh = wl.ensemble, wl.X
+    log("workload generated in %.1f s: %d trees, %d leaves, M=%d" % (
+        time.perf_counter() - t0, ens.n_trees, ens.n_leaves(), Xh.shape[0]))
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    e = q.Ensemble(ens, device=dev)
+    X = torch.from_numpy(Xh).to(dev)
+    M = X.shape[0]
+    units = M * e.n_leaves
+    n_el = e.info["n_elements"]
+
+    out32 = torch.empty((M, e.n_features), dtype=torch.float32, device=dev)
+    out64 = torch.empty((M, e.n_features), dtype=torch.float64, device=dev)
+    r32 = time_steps(lambda: e.shap_values(X, "fp32", out=out32), args.steps, args.warmup, torch)
+    log("fp32: %.3f ms/step (kernel %.3f ms)" % (r32["ms_per_step"], r32["kernel_ms"]))
+    r64 = time_steps(lambda: e.shap_values(X, "fp64", out=out64),
+                     args.fp64_steps or args.steps, args.warmup, torch)
+    log("fp64: %.3f ms/step (kernel %.3f ms)" % (r64["ms_per_step"], r64["kernel_ms"]))
+
+    # accuracy on sampled rows against the FP64 oracle
+    rows = np.random.default_rng(1).choice(M, min(args.check_rows, M), replace=False)
+    want = oracle.shap_values(ens, Xh[rows], n=8)
+    got32 = out32[torch.from_numpy(rows).to(dev)].double().cpu().numpy()
+    got64 = out64[torch.from_numpy(rows).to(dev)].cpu().numpy()
+
+    def rel(g):
+        return float((np.abs(g - want).max(1) / np.maximum(np.abs(want).max(1), 1e-30)).max())
+
+    err32, err64 = rel(got32), rel(got64)
+    log("row-normwise rel err vs oracle: fp32 %.2e fp64 %.2e" % (err32, err64))
+
+    flops = FLOPS_PER_ELEMENT * float(M) * n_el
+    achieved = flops / (r32["kernel_ms"] * 1e-3) / 1e12
+    result = {
+        "metric": METRIC,
+        "value": units / (r32["ms_per_step"] * 1e-3),
+        "unit": "paths/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "c2_values: 1000 random trees depth 8, 100 features (20 "
+                               "integer-valued), covers from 100k rows, 100k explained samples",
+                   "trees": ens.n_trees, "leaves": e.n_leaves, "features": e.n_features,
+                   "samples": M, "unique_features_per_path": n_el / max(1, e.info["n_paths"]),
+                   "max_unique": e.info["max_unique"]},
+        "max_rel_err": {"fp32": err32, "fp64": err64, "rows_checked": int(len(rows)),
+                        "measure": "row-normwise vs FP64 oracle (8 nodes)"},
+        "fp64": {"value": units / (r64["ms_per_step"] * 1e-3), "ms_per_step": r64["ms_per_step"],
+                 "kernel_ms": r64["kernel_ms"], "dtype": "f64",
+                 "speedup_fp32_over_fp64": r64["ms_per_step"] / r32["ms_per_step"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
+                     "kernel": "values_kernel<float,8,...>", "kernel_ms": r32["kernel_ms"],
+                     "flops_per_launch": flops,
+                     "peak_fp32_packed": PEAK_FP32_PACKED_TFLOPS,
+                     "frac_of_packed_peak": achieved / PEAK_FP32_PACKED_TFLOPS},
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(ens, Xh, args.cpu_seconds, oracle)
+        log("cpu baseline: %.3e paths/s on %d cores" % (result["cpu_baseline"]["value"],
+                                                        result["cpu_baseline"]["cores"]))
+    e.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

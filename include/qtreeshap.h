@@ -1,0 +1,183 @@
+/* qtreeshap: Path-Dependent TreeSHAP as Gauss-Legendre quadrature of the
+ * weighted-Banzhaf polynomial, on AMD Instinct MI355X (gfx950).
+ *
+ * Method (Wettenstein, Mitchell, Yu, "Quadrature-TreeSHAP"):
+ *   For a leaf v reached by a root-to-leaf path, each unique feature j on the
+ *   path has a cover ratio b_j (the product of the path's edge weights
+ *   w_e = cover(child)/cover(parent) on splits of j, section 2) and a follow
+ *   indicator o_j (1 iff the sample satisfies every split on j, Eq. 2).
+ *   Theorem 1 gives the weighted-Banzhaf interaction of a set S at inclusion
+ *   probability p; multiplied through by prod_j b_j it reads
+ *     B_p(S) = val(v) prod_{j in S}(o_j - b_j) prod_{j notin S}(b_j (1-p) + o_j p).
+ *   Shapley values (|S|=1) and pairwise Shapley interaction indices (|S|=2)
+ *   are its integrals over p in [0,1] (Eq. 9), computed with the fixed
+ *   8-node Gauss-Legendre rule on [0,1] (Eq. 10, section 5).  The rule is
+ *   exact whenever the path has at most 16 unique features for values and 17
+ *   for pairs (Theorem 2, Eq. 12); beyond that it is the paper's quadrature
+ *   approximation.
+ *
+ * Conventions used by this library (the paper leaves them to the tree format):
+ *   - a sample goes to the left child iff x[feature] < threshold (float32
+ *     compare; ties go right); NaN means "missing" and follows default_left;
+ *   - w_e = 0 when the parent cover is 0;
+ *   - interaction matrix Phi[i][k] = SII_ik / 2 for i != k and
+ *     Phi[i][i] = phi_i - sum_{k != i} Phi[i][k], so rows sum to phi and Phi is
+ *     symmetric (the layout of XGBoost's pred_interactions, which the paper's
+ *     implementation keeps, section 1);
+ *   - outputs exclude the bias: expected_value() returns sum_T E_T[f] + base_score,
+ *     so phi.sum(-1) + expected_value = prediction.
+ *
+ * Memory: every X, output and gradient pointer is DEVICE memory owned by the
+ * caller; host arrays passed to qts_load_ensemble are copied and may be freed
+ * after it returns.  Outputs are overwritten, never accumulated into.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  Compute
+ * calls are asynchronous on that stream; the caller synchronises before
+ * reading outputs.  An ensemble is read-only after loading and may be used
+ * from several streams concurrently.  qts_free_ensemble requires that no work
+ * on the ensemble is still in flight.
+ *
+ * Errors: every call returns QTS_OK (0) or a negative code below; the text of
+ * the last error on the calling thread is available from qts_last_error().
+ * No C++ exception crosses this interface.
+ */
+#ifndef QTREESHAP_H
+#define QTREESHAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  QTS_OK = 0,
+  QTS_E_INVALID_ARG = -1,   /* null pointer, negative size, ldx < n_features, ... */
+  QTS_E_INVALID_MODEL = -2, /* child out of range, cycle, one-child node, feature >= F,
+                               negative or NaN cover, NaN threshold */
+  QTS_E_UNSUPPORTED = -3,   /* tree deeper than 128, path with > 64 unique features,
+                               n_features too large for this entry point */
+  QTS_E_HIP = -4,           /* a HIP runtime error; its text is in qts_last_error() */
+  QTS_E_OOM = -5            /* host or device allocation failed */
+};
+
+typedef enum { QTS_FP32 = 0, QTS_FP64 = 1 } qts_precision;
+
+typedef struct qts_ensemble qts_ensemble; /* opaque, owned by the library */
+
+/* A tree ensemble as structure-of-arrays host memory (node ids local to each
+ * tree, root = node 0 of each tree). */
+typedef struct {
+  int32_t n_trees;
+  const int64_t* tree_offsets; /* [n_trees+1]: tree t owns nodes [off[t], off[t+1]) */
+  const int32_t* left;         /* [N] local child id, -1 for a leaf */
+  const int32_t* right;        /* [N] local child id, -1 for a leaf */
+  const int32_t* feature;      /* [N] split feature in [0, n_features) (internal nodes) */
+  const float* threshold;      /* [N] left iff x < threshold (internal nodes) */
+  const uint8_t* default_left; /* [N] missing-value direction; NULL = all go right */
+  const double* cover;         /* [N] training rows (or weight) reaching the node, >= 0 */
+  const double* value;         /* [N] leaf value (leaves only) */
+} qts_tree_arrays;
+
+/* Validate the model, build its path table and copy it to the current HIP
+ * device (the device current on the calling thread).  Per leaf, the path is
+ * collapsed to its unique features (Eq. 2) with b_j in FP64, 1-b_j computed in
+ * FP64, and the interval of x values that follows every split on j.  Paths
+ * are grouped by unique-feature count.  Synchronous with respect to host
+ * memory.  `stream` orders the uploads. */
+int qts_load_ensemble(const qts_tree_arrays* trees, int32_t n_features, double base_score,
+                      void* stream, qts_ensemble** out);
+
+/* Same validation and path table, host memory only (no device is touched).
+ * Usable with the query calls and qts_export_paths; compute calls reject it. */
+int qts_build_host(const qts_tree_arrays* trees, int32_t n_features, double base_score,
+                   qts_ensemble** out);
+
+int qts_free_ensemble(qts_ensemble* ens);
+
+/* sum over trees of E_T[f] = v(empty set) (Eq. 1, Eq. 3) plus base_score, FP64. */
+int qts_expected_value(const qts_ensemble* ens, double* out);
+
+/* Number of leaves = length of grad_leaf and of a leaf_values override, in
+ * tree-major, node-id order. */
+int qts_num_leaves(const qts_ensemble* ens, int64_t* out);
+
+typedef struct {
+  int32_t n_features;
+  int32_t n_trees;
+  int64_t n_leaves;    /* leaves in tree-major node-id order (incl. unreachable slots) */
+  int64_t n_paths;     /* root-to-leaf paths with at least one split (table rows) */
+  int64_t n_elements;  /* sum over paths of unique features */
+  int32_t max_depth;   /* D */
+  int32_t max_unique;  /* d */
+  int32_t n_buckets;
+  int32_t device;      /* -1 for a host-only ensemble */
+} qts_info;
+
+int qts_get_info(const qts_ensemble* ens, qts_info* out);
+
+/* Copy the collapsed path table to caller host arrays, in path order:
+ *   path_leaf[n_paths], path_len[n_paths], path_off[n_paths]   (int32)
+ *   feat[n_elements] (int32), lo[n_elements], hi[n_elements] (float32),
+ *   missing_ok[n_elements] (uint8), b[n_elements], one_minus_b[n_elements] (FP64).
+ * Element e of a path follows iff lo <= x < hi (hi = NaN means no upper
+ * bound), or x is NaN and missing_ok.  Any pointer may be NULL. */
+int qts_export_paths(const qts_ensemble* ens, int32_t* path_leaf, int32_t* path_len,
+                     int32_t* path_off, int32_t* feat, float* lo, float* hi,
+                     uint8_t* missing_ok, double* b, double* one_minus_b);
+
+/* The n-node Gauss-Legendre rule on [0,1] used by the kernels (Eq. 10), built
+ * on the host in FP64 by the Golub-Welsch eigenvalue method: nodes t, 1-t
+ * (computed separately, not by subtraction) and weights.  n in [1, 64]. */
+int qts_gauss_legendre(int32_t n, double* t, double* one_minus_t, double* weight);
+
+/* Shapley values phi[M, F] (row-major, F = n_features) of every sample.
+ *   X            [M, ldx] float32 device rows (ldx >= F); NaN = missing.
+ *   leaf_values  NULL, or [n_leaves] FP64 device array replacing the model's leaf
+ *                values (phi is linear in them; used by the autograd wrapper).
+ *   phi          [M, F] device output: float32 for QTS_FP32, double for QTS_FP64.
+ * QTS_FP32 evaluates the quadrature in FP32 and accumulates across paths and
+ * trees in FP64; QTS_FP64 does everything in FP64.  M = 0 is a no-op. */
+int qts_shap_values(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
+                    const double* leaf_values, void* phi, qts_precision precision,
+                    void* stream);
+
+/* Pairwise interaction matrices Phi[M, F, F] (and optionally phi[M, F]) with the
+ * convention above.  Pair indices are the |S|=2 case of Theorem 1 and Eq. 9.
+ * Output types follow `precision` as for qts_shap_values; phi may be NULL. */
+int qts_shap_interactions(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
+                          const double* leaf_values, void* phi, void* Phi,
+                          qts_precision precision, void* stream);
+
+/* Adjoint of qts_shap_values with respect to the leaf values: phi is linear
+ * in val(v) (Eq. 1, Eq. 10), so
+ *   grad_leaf[v] = sum_s sum_{j on path(v)} grad_phi[s, f_j] (o_j - b_j)
+ *                  * sum_m w_m prod_{k != j} (b_k (1 - t_m) + o_k t_m).
+ *   grad_phi   [M, F] device array, float32 for QTS_FP32, double for QTS_FP64.
+ *   grad_leaf  [n_leaves] FP64 device output (overwritten). */
+int qts_shap_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
+                      const void* grad_phi, double* grad_leaf, qts_precision precision,
+                      void* stream);
+
+/* Time the candidate launch shapes of qts_shap_values on synthetic rows of
+ * this ensemble (M_hint rows, capped) and keep the fastest for this ensemble
+ * and precision.  Optional: untuned ensembles use a size-based default. */
+int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, void* stream);
+
+/* Measurement aid.  While enabled, each compute call records a HIP event pair
+ * on its stream around the launches of its main kernel (kind 0: the values
+ * kernel, 1: the interactions kernel, 2: the adjoint kernel), excluding the
+ * zero-fill and cast kernels around them.  qts_kernel_timing_read waits for
+ * the recorded events of one kind, returns their summed duration in
+ * milliseconds and the number of calls since the last read, and clears them.
+ * Not meant to be enabled while a HIP graph is being captured. */
+int qts_set_kernel_timing(int32_t enable);
+int qts_kernel_timing_read(int32_t kind, double* total_ms, int64_t* calls);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char* qts_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QTREESHAP_H */

@@ -1,0 +1,199 @@
+"""Python binding of the qtreeshap C-ABI: ensembles, Shapley values, pairwise
+interactions and the leaf-value adjoint on MI355X.
+
+Argument marshalling only: every computation runs in the HIP library.  PyTorch
+supplies device memory and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_PREC = {"fp32": L.QTS_FP32, "fp64": L.QTS_FP64}
+_DTYPE = {"fp32": torch.float32, "fp64": torch.float64}
+
+
+def _stream_ptr(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def gauss_legendre(n: int = 8):
+    """(t, 1-t, w): the n-node Gauss-Legendre rule on [0,1] built by the library."""
+    t, s, w = np.zeros(n), np.zeros(n), np.zeros(n)
+    L.check(L.lib().qts_gauss_legendre(n, t.ctypes.data, s.ctypes.data, w.ctypes.data))
+    return t, s, w
+
+
+KERNEL_KINDS = {"values": 0, "interactions": 1, "backward": 2}
+
+
+def set_kernel_timing(enable: bool) -> None:
+    """Record HIP events around the main kernel launches of each call."""
+    L.check(L.lib().qts_set_kernel_timing(1 if enable else 0))
+
+
+def read_kernel_timing(kind: str = "values"):
+    """(total_ms, calls) of the main kernel of `kind` since the last read."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    L.check(L.lib().qts_kernel_timing_read(KERNEL_KINDS[kind], ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, int(n.value)
+
+
+class Ensemble:
+    """A tree ensemble loaded into the library.
+
+    `model` is any object with the structure-of-arrays fields tree_offsets,
+    left, right, feature, threshold, default_left, cover, value, n_features
+    (and optionally base_score); see include/qtreeshap.h for their meaning.
+    With host_only=True the path table is built but no device is touched.
+    """
+
+    def __init__(self, model, host_only: bool = False, device=None):
+        a = {k: np.ascontiguousarray(getattr(model, k), dt) for k, dt in (
+            ("tree_offsets", np.int64), ("left", np.int32), ("right", np.int32),
+            ("feature", np.int32), ("threshold", np.float32), ("default_left", np.uint8),
+            ("cover", np.float64), ("value", np.float64))}
+        self.n_features = int(model.n_features)
+        self.base_score = float(getattr(model, "base_score", 0.0))
+        ta = L.TreeArrays(int(a["tree_offsets"].shape[0] - 1),
+                          *[a[k].ctypes.data for k in ("tree_offsets", "left", "right", "feature",
+                                                       "threshold", "default_left", "cover",
+                                                       "value")])
+        h = ctypes.c_void_p()
+        if host_only:
+            self.device = None
+            L.check(L.lib().qts_build_host(ctypes.byref(ta), self.n_features, self.base_score,
+                                           ctypes.byref(h)))
+        else:
+            self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+                else torch.device(device)
+            with torch.cuda.device(self.device):
+                L.check(L.lib().qts_load_ensemble(ctypes.byref(ta), self.n_features,
+                                                  self.base_score, _stream_ptr(self.device),
+                                                  ctypes.byref(h)))
+        self._h = h
+        info = L.Info()
+        L.check(L.lib().qts_get_info(self._h, ctypes.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in L.Info._fields_}
+        ev = ctypes.c_double()
+        L.check(L.lib().qts_expected_value(self._h, ctypes.byref(ev)))
+        self.expected_value = ev.value
+        self.n_leaves = int(info.n_leaves)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            if self.device is not None:
+                torch.cuda.synchronize(self.device)
+            L.check(L.lib().qts_free_ensemble(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- checks
+    def _rows(self, X: torch.Tensor):
+        if not isinstance(X, torch.Tensor) or X.device.type != "cuda":
+            raise TypeError("X must be a CUDA/HIP float32 tensor")
+        if X.dtype != torch.float32 or X.dim() != 2:
+            raise TypeError("X must be a 2-D float32 tensor")
+        if X.shape[1] < self.n_features:
+            raise ValueError("X has %d columns, the model needs %d" % (X.shape[1],
+                                                                        self.n_features))
+        if X.stride(1) != 1:
+            X = X.contiguous()
+        return X, X.shape[0], X.stride(0)
+
+    def _leaf(self, leaf_values):
+        if leaf_values is None:
+            return None
+        if (leaf_values.dtype != torch.float64 or leaf_values.device.type != "cuda"
+                or leaf_values.numel() != self.n_leaves):
+            raise TypeError("leaf_values must be a float64 device tensor of n_leaves values")
+        return leaf_values.contiguous()
+
+    # ---------------------------------------------------------------- compute
+    def shap_values(self, X: torch.Tensor, precision: str = "fp32", leaf_values=None,
+                    out=None) -> torch.Tensor:
+        """phi[M, F]; float32 for 'fp32', float64 for 'fp64'."""
+        X, M, ldx = self._rows(X)
+        lv = self._leaf(leaf_values)
+        if out is None:
+            out = torch.empty((M, self.n_features), dtype=_DTYPE[precision], device=X.device)
+        L.check(L.lib().qts_shap_values(self._h, _ptr(X), M, ldx, _ptr(lv), _ptr(out),
+                                        _PREC[precision], _stream_ptr(X.device)))
+        return out
+
+    def shap_interactions(self, X: torch.Tensor, precision: str = "fp32", leaf_values=None,
+                          with_phi: bool = False):
+        """Phi[M, F, F] (and phi[M, F] when with_phi)."""
+        X, M, ldx = self._rows(X)
+        lv = self._leaf(leaf_values)
+        F = self.n_features
+        Phi = torch.empty((M, F, F), dtype=_DTYPE[precision], device=X.device)
+        phi = torch.empty((M, F), dtype=_DTYPE[precision], device=X.device) if with_phi else None
+        L.check(L.lib().qts_shap_interactions(self._h, _ptr(X), M, ldx, _ptr(lv), _ptr(phi),
+                                              _ptr(Phi), _PREC[precision],
+                                              _stream_ptr(X.device)))
+        return (Phi, phi) if with_phi else Phi
+
+    def shap_backward(self, X: torch.Tensor, grad_phi: torch.Tensor,
+                      precision: str = "fp32") -> torch.Tensor:
+        """grad_leaf[n_leaves] (float64) = J^T grad_phi."""
+        X, M, ldx = self._rows(X)
+        g = grad_phi.to(_DTYPE[precision]).contiguous()
+        if tuple(g.shape) != (M, self.n_features):
+            raise ValueError("grad_phi must be [M, F]")
+        out = torch.empty(self.n_leaves, dtype=torch.float64, device=X.device)
+        L.check(L.lib().qts_shap_backward(self._h, _ptr(X), M, ldx, _ptr(g), _ptr(out),
+                                          _PREC[precision], _stream_ptr(X.device)))
+        return out
+
+    def autotune(self, M_hint: int, precision: str = "fp32"):
+        L.check(L.lib().qts_autotune(self._h, int(M_hint), _PREC[precision],
+                                     _stream_ptr(self.device)))
+
+    # ---------------------------------------------------------------- inspection
+    def export_paths(self) -> dict:
+        """The collapsed path table (host copies)."""
+        n_p, n_e = self.info["n_paths"], self.info["n_elements"]
+        out = {"path_leaf": np.zeros(n_p, np.int32), "path_len": np.zeros(n_p, np.int32),
+               "path_off": np.zeros(n_p, np.int32), "feat": np.zeros(n_e, np.int32),
+               "lo": np.zeros(n_e, np.float32), "hi": np.zeros(n_e, np.float32),
+               "missing_ok": np.zeros(n_e, np.uint8), "b": np.zeros(n_e),
+               "one_minus_b": np.zeros(n_e)}
+        L.check(L.lib().qts_export_paths(self._h, *[out[k].ctypes.data for k in (
+            "path_leaf", "path_len", "path_off", "feat", "lo", "hi", "missing_ok", "b",
+            "one_minus_b")]))
+        return out
+
+
+class ShapValues(torch.autograd.Function):
+    """phi = ShapValues.apply(leaf_values, X, ensemble, precision).
+
+    phi is linear in the leaf values; backward calls the library's adjoint.
+    It is piecewise constant in X, so X receives no gradient."""
+
+    @staticmethod
+    def forward(ctx, leaf_values, X, ensemble, precision="fp32"):
+        ctx.ensemble = ensemble
+        ctx.precision = precision
+        ctx.save_for_backward(X)
+        return ensemble.shap_values(X, precision, leaf_values=leaf_values.detach())
+
+    @staticmethod
+    def backward(ctx, grad_phi):
+        (X,) = ctx.saved_tensors
+        g = ctx.ensemble.shap_backward(X, grad_phi, ctx.precision)
+        return g, None, None, None

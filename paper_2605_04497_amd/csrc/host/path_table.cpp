@@ -1,0 +1,229 @@
+// Model validation and the collapsed, bucketed path table (host side).
+//
+// For each leaf the root-to-leaf path is collapsed to its unique features, in
+// order of first appearance.  For feature j (Eq. 2 and section 2):
+//   b_j        = product of w_e = cover(child)/cover(parent) over the path's
+//                splits on j (w_e = 0 when the parent cover is 0), in FP64;
+//   1 - b_j    computed in FP64 (not from a rounded b_j);
+//   [lo, hi)   the x values that satisfy every split on j: a left edge needs
+//              x < threshold, a right edge x >= threshold (hi = NaN: no bound);
+//   missing_ok a NaN value follows every split on j (all default directions
+//              along the path agree with the path).
+// E[f] = sum over leaves of val * prod_j b_j  (Eq. 1, the game at S = empty).
+// Paths with the same unique-feature capacity (8, 16, 32, 64) are stored
+// contiguously so one kernel instance with a fixed register budget serves them.
+#include <algorithm>
+#include <cmath>
+#include <limits>
+
+#include "../qts_internal.h"
+
+namespace qts {
+
+namespace {
+
+struct Edge {
+  int32_t f;
+  bool left;
+  float thr;
+  bool dleft;
+  double w;
+};
+
+struct RawPath {
+  int32_t leaf;
+  int32_t tree;
+  std::vector<int32_t> feat;
+  std::vector<float> lo, hi;
+  std::vector<uint8_t> mok;
+  std::vector<double> b;
+};
+
+int bucket_capacity(int d) {
+  if (d <= 8) return 8;
+  if (d <= 16) return 16;
+  if (d <= 32) return 32;
+  return 64;
+}
+
+class Builder {
+ public:
+  Builder(const qts_tree_arrays& t, int32_t F) : t_(t), F_(F) {}
+
+  void tree(int32_t ti) {
+    const int64_t a = t_.tree_offsets[ti], e = t_.tree_offsets[ti + 1];
+    if (e <= a) fail(QTS_E_INVALID_MODEL, "tree " + std::to_string(ti) + " has no nodes");
+    if (e - a > (int64_t)std::numeric_limits<int32_t>::max())
+      fail(QTS_E_UNSUPPORTED, "tree " + std::to_string(ti) + " is too large");
+    base_ = a;
+    n_ = (int32_t)(e - a);
+    tree_ = ti;
+    visited_.assign((size_t)n_, 0);
+    // leaf ordinals in node-id order (every node with left < 0 is a leaf slot)
+    leaf_ord_.assign((size_t)n_, -1);
+    for (int32_t i = 0; i < n_; ++i)
+      if (t_.left[a + i] < 0) leaf_ord_[(size_t)i] = (int32_t)(n_leaves_++);
+    path_.clear();
+    visit(0, 0);
+  }
+
+  std::vector<RawPath> paths;
+  std::vector<double> leaf_value;
+  double expected = 0.0;
+  int32_t max_depth = 0;
+  int32_t max_unique = 0;
+  int64_t n_leaves_ = 0;
+
+ private:
+  void visit(int32_t node, int32_t depth) {
+    if (node < 0 || node >= n_)
+      fail(QTS_E_INVALID_MODEL, "tree " + std::to_string(tree_) + ": child id out of range");
+    if (visited_[(size_t)node])
+      fail(QTS_E_INVALID_MODEL,
+           "tree " + std::to_string(tree_) + ": node reached twice (cycle or shared child)");
+    visited_[(size_t)node] = 1;
+    if (depth > kMaxDepth)
+      fail(QTS_E_UNSUPPORTED, "tree " + std::to_string(tree_) + " is deeper than 128");
+    const int64_t g = base_ + node;
+    const double cov = t_.cover[g];
+    if (!(cov >= 0.0))
+      fail(QTS_E_INVALID_MODEL, "tree " + std::to_string(tree_) + ": negative or NaN cover");
+    const int32_t l = t_.left[g], r = t_.right[g];
+    if (l < 0 || r < 0) {
+      if (l >= 0 || r >= 0)
+        fail(QTS_E_INVALID_MODEL, "tree " + std::to_string(tree_) + ": node with one child");
+      leaf(node, depth);
+      return;
+    }
+    const int32_t f = t_.feature[g];
+    if (f < 0 || f >= F_)
+      fail(QTS_E_INVALID_MODEL, "tree " + std::to_string(tree_) + ": feature out of range");
+    const float thr = t_.threshold[g];
+    if (std::isnan(thr))
+      fail(QTS_E_INVALID_MODEL, "tree " + std::to_string(tree_) + ": NaN threshold");
+    if (l >= n_ || r >= n_)
+      fail(QTS_E_INVALID_MODEL, "tree " + std::to_string(tree_) + ": child id out of range");
+    const bool dl = t_.default_left ? (t_.default_left[g] != 0) : false;
+    for (int c = 0; c < 2; ++c) {
+      const int32_t child = c == 0 ? l : r;
+      const double cc = t_.cover[base_ + child];
+      const double w = cov == 0.0 ? 0.0 : cc / cov;
+      path_.push_back(Edge{f, c == 0, thr, dl, w});
+      visit(child, depth + 1);
+      path_.pop_back();
+    }
+  }
+
+  void leaf(int32_t node, int32_t depth) {
+    const int64_t g = base_ + node;
+    max_depth = std::max(max_depth, depth);
+    RawPath p;
+    p.leaf = leaf_ord_[(size_t)node];
+    p.tree = tree_;
+    const float kNoBound = std::numeric_limits<float>::quiet_NaN();
+    for (const Edge& e : path_) {
+      size_t k = 0;
+      while (k < p.feat.size() && p.feat[k] != e.f) ++k;
+      if (k == p.feat.size()) {
+        p.feat.push_back(e.f);
+        p.lo.push_back(-std::numeric_limits<float>::infinity());
+        p.hi.push_back(kNoBound);
+        p.mok.push_back(1);
+        p.b.push_back(1.0);
+      }
+      p.b[k] *= e.w;
+      if (e.left) {
+        p.hi[k] = std::isnan(p.hi[k]) ? e.thr : std::min(p.hi[k], e.thr);
+        p.mok[k] &= (uint8_t)(e.dleft ? 1 : 0);
+      } else {
+        p.lo[k] = std::max(p.lo[k], e.thr);
+        p.mok[k] &= (uint8_t)(e.dleft ? 0 : 1);
+      }
+    }
+    const int d = (int)p.feat.size();
+    if (d > kMaxUnique)
+      fail(QTS_E_UNSUPPORTED, "a path has more than 64 unique features");
+    max_unique = std::max(max_unique, d);
+    const double val = t_.value[g];
+    if (leaf_value.size() <= (size_t)p.leaf) leaf_value.resize((size_t)p.leaf + 1, 0.0);
+    leaf_value[(size_t)p.leaf] = val;
+    double prod = val;
+    for (double bj : p.b) prod *= bj;
+    expected += prod;
+    if (d > 0) paths.push_back(std::move(p));
+  }
+
+  const qts_tree_arrays& t_;
+  int32_t F_;
+  int64_t base_ = 0;
+  int32_t n_ = 0;
+  int32_t tree_ = 0;
+  std::vector<uint8_t> visited_;
+  std::vector<int32_t> leaf_ord_;
+  std::vector<Edge> path_;
+};
+
+}  // namespace
+
+HostTable build_host_table(const qts_tree_arrays& t, int32_t F, double base_score) {
+  if (F < 1) fail(QTS_E_INVALID_ARG, "n_features must be >= 1");
+  if (t.n_trees < 0) fail(QTS_E_INVALID_ARG, "n_trees must be >= 0");
+  if (t.n_trees > 0 && (!t.tree_offsets || !t.left || !t.right || !t.feature || !t.threshold ||
+                        !t.cover || !t.value))
+    fail(QTS_E_INVALID_ARG, "null tree array");
+  if (t.n_trees > 0 && t.tree_offsets[0] != 0)
+    fail(QTS_E_INVALID_MODEL, "tree_offsets[0] must be 0");
+  Builder bld(t, F);
+  for (int32_t ti = 0; ti < t.n_trees; ++ti) bld.tree(ti);
+  if (bld.n_leaves_ > (int64_t)std::numeric_limits<int32_t>::max() / 2)
+    fail(QTS_E_UNSUPPORTED, "too many leaves");
+
+  HostTable h;
+  h.F = F;
+  h.n_trees = t.n_trees;
+  h.max_depth = bld.max_depth;
+  h.max_unique = bld.max_unique;
+  h.base_score = base_score;
+  h.expected = bld.expected + base_score;
+  h.leaf_value = std::move(bld.leaf_value);
+  h.leaf_value.resize((size_t)bld.n_leaves_, 0.0);
+
+  // group paths by capacity, keeping tree-major order inside a group
+  std::vector<size_t> order(bld.paths.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+    return bucket_capacity((int)bld.paths[x].feat.size()) <
+           bucket_capacity((int)bld.paths[y].feat.size());
+  });
+  int64_t n_el = 0;
+  for (const RawPath& p : bld.paths) n_el += (int64_t)p.feat.size();
+  if (n_el > (int64_t)std::numeric_limits<int32_t>::max())
+    fail(QTS_E_UNSUPPORTED, "path table too large");
+  h.hdr.reserve(order.size());
+  h.feat.reserve((size_t)n_el);
+  h.lo.reserve((size_t)n_el);
+  h.hi.reserve((size_t)n_el);
+  h.b.reserve((size_t)n_el);
+  h.cb.reserve((size_t)n_el);
+  for (size_t idx : order) {
+    const RawPath& p = bld.paths[idx];
+    const int d = (int)p.feat.size();
+    const int cap = bucket_capacity(d);
+    const int32_t pi = (int32_t)h.hdr.size();
+    if (h.buckets.empty() || h.buckets.back().dmax != cap)
+      h.buckets.push_back(Bucket{cap, pi, pi, 0});
+    h.buckets.back().path_end = pi + 1;
+    h.buckets.back().elems += d;
+    h.hdr.push_back(PathHdr{(int32_t)h.feat.size(), d, p.leaf, p.tree});
+    for (int k = 0; k < d; ++k) {
+      h.feat.push_back(p.feat[k] | (p.mok[k] ? kMissingOkBit : 0));
+      h.lo.push_back(p.lo[k]);
+      h.hi.push_back(p.hi[k]);
+      h.b.push_back(p.b[k]);
+      h.cb.push_back(1.0 - p.b[k]);
+    }
+  }
+  return h;
+}
+
+}  // namespace qts

@@ -1,0 +1,40 @@
+// Small element-wise kernels: zero fill (used instead of hipMemsetAsync so
+// the call sequence stays safe to capture in a HIP graph) and FP64 -> FP32.
+#include <hip/hip_runtime.h>
+
+#include "../qts_device.h"
+
+namespace qts {
+
+__global__ void __launch_bounds__(256) fill_zero_kernel(double* __restrict__ p, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0.0;
+}
+
+__global__ void __launch_bounds__(256) cast_kernel(const double* __restrict__ src,
+                                                   float* __restrict__ dst, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    dst[i] = (float)src[i];
+}
+
+static unsigned grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+void launch_fill_zero(double* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n);
+  check_hip(hipGetLastError(), "fill_zero launch");
+}
+
+void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(cast_kernel, dim3(grid_for(n)), dim3(256), 0, s, src, dst, n);
+  check_hip(hipGetLastError(), "cast launch");
+}
+
+}  // namespace qts

@@ -1,0 +1,305 @@
+// First-order Shapley values: phi[s, f] accumulated over every root-to-leaf
+// path of the ensemble (Theorem 1 with |S| = 1, Eq. 9-10, 8 nodes).
+//
+// Work mapping (gfx950, wave64):
+//   * a workgroup owns a tile of 64 explained samples (one per lane) and a
+//     contiguous chunk of paths from one bucket; its wavefronts split the
+//     chunk path by path;
+//   * a wavefront processes one path at a time for all 64 samples, so every
+//     path quantity (features, bounds, b_j, 1-b_j, leaf value) is uniform
+//     across the wave and is fetched with scalar loads;
+//   * the sample tile is staged transposed in LDS ([F][65] floats), so the
+//     per-lane gather x[s, f_j] is a conflict-free LDS read;
+//   * contributions are added into an FP64 LDS accumulator ([F][65] doubles,
+//     shared by the workgroup's waves) and flushed to the FP64 global
+//     accumulator with one atomic per (sample, feature) at the end.
+//
+// Per (sample, path) with unique features j = 0..d-1 and nodes m:
+//   o_j    = x in [lo_j, hi_j) ? 1 : 0   (NaN: missing_ok_j)            (Eq. 2)
+//   F_j(m) = b_j (1 - t_m) + o_j t_m = (1 - t_m) (b_j + o_j tau_m)
+//   LOO_j  = sum_m w_m prod_{k != j} F_k(m)    by prefix x suffix products
+//   phi[s, f_j] += val (o_j - b_j) LOO_j       (o_j - b_j = 1 - b_j or -b_j)
+// With TAU the (1 - t_m)^(d-1) factor common to every leave-one-out product
+// is folded into the node weights (wtab), so each factor costs one FMA; it is
+// used for paths of at most 16 unique features, where the products stay far
+// from the FP32 range limits.  Longer paths use b_j s_m + o_j t_m directly.
+// NH < 8 splits the nodes over several passes to bound the registers held
+// by the prefix array (linearity: the node sum is additive).
+#include <hip/hip_runtime.h>
+
+#include "../qts_device.h"
+
+namespace qts {
+
+template <typename T>
+__device__ __forceinline__ T fmaT(T a, T b, T c) {
+  return __builtin_fma(a, b, c);
+}
+template <>
+__device__ __forceinline__ float fmaT<float>(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+
+// Copy a wave-uniform value into a VGPR the compiler cannot fold back.
+__device__ __forceinline__ float to_vgpr(float v) {
+  float r;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(v));
+  return r;
+}
+__device__ __forceinline__ double to_vgpr(double v) {
+  double r;
+  asm volatile("v_mov_b64 %0, %1" : "=v"(r) : "s"(v));
+  return r;
+}
+
+// Factor of element j at node m (slot j >= d carries o = 0, b = 1).
+template <typename T, bool TAU>
+__device__ __forceinline__ T factor(T o, T b, T tau, T t, T s) {
+  return TAU ? fmaT(o, tau, b) : fmaT(o, t, b * s);
+}
+
+template <typename T, int DMAX, int NH, bool TAU, bool STORE_G>
+__global__ void __launch_bounds__(256)
+values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
+              const float* __restrict__ lo, const float* __restrict__ hi,
+              const T* __restrict__ bb, const T* __restrict__ cbb,
+              const double* __restrict__ leaf_val, const T* __restrict__ wtab,
+              const float* __restrict__ X, int64_t M, int64_t ldx, int32_t F,
+              int32_t path_begin, int32_t path_end, int32_t chunk, int32_t nsb,
+              double* __restrict__ acc, NodeConsts<T> nc) {
+  constexpr int NB = DMAX / 8;  // feature batches
+  extern __shared__ __align__(16) unsigned char smem[];
+  float* xs = reinterpret_cast<float*>(smem);
+  size_t xs_bytes = ((size_t)F * kTileStride * sizeof(float) + 15) & ~(size_t)15;
+  double* as = reinterpret_cast<double*>(smem + xs_bytes);
+
+  const int item = blockIdx.x;
+  const int sb = item % nsb;
+  const int ch = item / nsb;
+  const int64_t s0 = (int64_t)sb * kSamplesPerBlock;
+  const int p0 = path_begin + ch * chunk;
+  const int p1 = min(path_end, p0 + chunk);
+
+  // stage the sample tile transposed; zero the accumulator
+  const int tile = kSamplesPerBlock * F;
+  for (int i = threadIdx.x; i < tile; i += blockDim.x) {
+    const int r = i / F;
+    const int f = i - r * F;
+    const int64_t s = s0 + r;
+    xs[f * kTileStride + r] = (s < M) ? X[s * ldx + f] : 0.0f;
+    as[f * kTileStride + r] = 0.0;
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  // wave-uniform loop bounds (kept in SGPRs so the path loads are scalar)
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nw = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
+  const int pb = __builtin_amdgcn_readfirstlane(p0);
+  const int pe = __builtin_amdgcn_readfirstlane(p1);
+
+  // node constants pinned in VGPRs: a VALU op may read only one SGPR on
+  // gfx9-class hardware, and b_j arrives in an SGPR
+  T tv[kNodes], sv[kNodes], tauv[kNodes];
+#pragma unroll
+  for (int m = 0; m < kNodes; ++m) {
+    tv[m] = to_vgpr(nc.t[m]);
+    sv[m] = to_vgpr(nc.s[m]);
+    tauv[m] = to_vgpr(nc.tau[m]);
+  }
+
+  for (int p = pb + wave; p < pe; p += nw) {
+    const int d = ldu(&hdr[p].d);
+    const int off = ldu(&hdr[p].off);
+    const T val = (T)ldu(leaf_val + ldu(&hdr[p].leaf));
+    const int nb = (d + 7) >> 3;  // batches in use
+
+    // Follow indicators, eight elements per batch.  The element arrays are
+    // padded at the end, so a whole batch can be loaded even past the last
+    // path; slots j >= d get o = 0 (and b = 1 below): their factor is 1.
+    T o[DMAX];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if (b < nb) {
+        const int jb = 8 * b;
+        int fm[8];
+        float l[8], u[8], x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          fm[k] = ldu(feat + off + jb + k);
+          l[k] = ldu(lo + off + jb + k);
+          u[k] = ldu(hi + off + jb + k);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = xs[(fm[k] & kFeatureMask) * kTileStride + lane];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          // NaN x: the unordered lower compare accepts it iff missing_ok;
+          // hi = NaN (no upper bound) makes the upper compare true
+          const bool miss = (fm[k] & kMissingOkBit) != 0;
+          const bool lower = miss ? !(x[k] < l[k]) : (x[k] >= l[k]);
+          const bool upper = !(x[k] >= u[k]);
+          const bool live = jb + k < d;
+          o[jb + k] = (live & lower & upper) ? T(1) : T(0);
+        }
+      }
+    }
+
+#pragma unroll
+    for (int pass = 0; pass < kNodes / NH; ++pass) {
+      const int m0 = pass * NH;
+      // checkpoints: ck[b][m] = w'_m prod_{k < 8b} F_k(m)
+      T ck[NB][NH];
+#pragma unroll
+      for (int m = 0; m < NH; ++m) ck[0][m] = TAU ? ldu(wtab + d * kNodes + m0 + m) : nc.w[m0 + m];
+#pragma unroll
+      for (int b = 1; b < NB; ++b) {
+        if (b < nb) {
+#pragma unroll
+          for (int m = 0; m < NH; ++m) ck[b][m] = ck[b - 1][m];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int j = 8 * (b - 1) + k;
+            const T bj = ldu(bb + off + j);
+#pragma unroll
+            for (int m = 0; m < NH; ++m)
+              ck[b][m] *= factor<T, TAU>(o[j], bj, tauv[m0 + m], tv[m0 + m], sv[m0 + m]);
+          }
+        }
+      }
+      // backward sweep, last batch first: rebuild the batch's prefixes from
+      // its checkpoint, then suffix products and leave-one-out sums
+      T S[NH];
+#pragma unroll
+      for (int m = 0; m < NH; ++m) S[m] = T(1);
+#pragma unroll
+      for (int b = NB - 1; b >= 0; --b) {
+        if (b < nb) {
+          const int jb = 8 * b;
+          T bj[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const T bl = ldu(bb + off + jb + k);
+            bj[k] = (jb + k < d) ? bl : T(1);
+          }
+          T Pb[8][NH];
+          T Gb[STORE_G ? 8 : 1][NH];
+          T run[NH];
+#pragma unroll
+          for (int m = 0; m < NH; ++m) run[m] = ck[b][m];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+#pragma unroll
+            for (int m = 0; m < NH; ++m) {
+              const T g = factor<T, TAU>(o[jb + k], bj[k], tauv[m0 + m], tv[m0 + m], sv[m0 + m]);
+              Pb[k][m] = run[m];
+              if (STORE_G) Gb[STORE_G ? k : 0][m] = g;
+              run[m] *= g;
+            }
+          }
+#pragma unroll
+          for (int k = 7; k >= 0; --k) {
+            const int j = jb + k;
+            if (j < d) {
+              T dot = Pb[k][0] * S[0];
+#pragma unroll
+              for (int m = 1; m < NH; ++m) dot = fmaT(Pb[k][m], S[m], dot);
+              const int f = ldu(feat + off + j) & kFeatureMask;
+              const T coef = (o[j] != T(0)) ? ldu(cbb + off + j) : -bj[k];
+              const double c = (double)(val * coef * dot);
+              __hip_atomic_fetch_add(&as[f * kTileStride + lane], c, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            if (j > 0) {
+#pragma unroll
+              for (int m = 0; m < NH; ++m) {
+                const T g = STORE_G ? Gb[STORE_G ? k : 0][m]
+                                    : factor<T, TAU>(o[j], bj[k], tauv[m0 + m], tv[m0 + m],
+                                                     sv[m0 + m]);
+                S[m] *= g;
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // flush: consecutive threads take consecutive features of one sample
+  for (int i = threadIdx.x; i < tile; i += blockDim.x) {
+    const int r = i / F;
+    const int f = i - r * F;
+    const int64_t s = s0 + r;
+    if (s < M) {
+      const double v = as[f * kTileStride + r];
+      if (v != 0.0) unsafeAtomicAdd(&acc[s * F + f], v);
+    }
+  }
+}
+
+namespace {
+
+template <typename T, int DMAX, int NH, bool TAU, bool STORE_G>
+void launch_one(const HostTable& h, const DeviceTable& d, const Bucket& bk, const float* X,
+                int64_t M, int64_t ldx, const double* leaf_val, double* acc,
+                const ValuesShape& shape, hipStream_t s) {
+  const int F = h.F;
+  const int nsb = (int)((M + kSamplesPerBlock - 1) / kSamplesPerBlock);
+  const int n_paths = bk.path_end - bk.path_begin;
+  int chunk = shape.chunk;
+  if (chunk <= 0) {
+    // enough work items to fill 256 CUs several times over, chunks >= 64 paths
+    const int64_t want_items = 8 * 256;
+    int64_t n_chunks = (want_items + nsb - 1) / nsb;
+    n_chunks = std::max<int64_t>(1, std::min<int64_t>(n_chunks, (n_paths + 63) / 64));
+    chunk = (int)((n_paths + n_chunks - 1) / n_chunks);
+  }
+  const int n_chunks = (n_paths + chunk - 1) / chunk;
+  const int64_t grid = (int64_t)nsb * n_chunks;
+  if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "grid too large");
+  const size_t lds = values_lds_bytes(F);
+  const int threads = 64 * shape.waves_per_block;
+  const T* b = std::is_same<T, float>::value ? (const T*)d.b32 : (const T*)d.b64;
+  const T* cb = std::is_same<T, float>::value ? (const T*)d.cb32 : (const T*)d.cb64;
+  const T* wtab = std::is_same<T, float>::value ? (const T*)d.wtab32 : (const T*)d.wtab64;
+  NodeConsts<T> nc;
+  if constexpr (std::is_same<T, float>::value) nc = d.n32; else nc = d.n64;
+  static bool attr_set = false;  // allow more than the default 64 KiB of dynamic LDS
+  if (!attr_set) {
+    check_hip(hipFuncSetAttribute((const void*)values_kernel<T, DMAX, NH, TAU, STORE_G>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes),
+              "hipFuncSetAttribute");
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((values_kernel<T, DMAX, NH, TAU, STORE_G>), dim3((unsigned)grid),
+                     dim3(threads), lds, s, d.hdr, d.feat, d.lo, d.hi, b, cb, leaf_val, wtab, X,
+                     M, ldx, F, bk.path_begin, bk.path_end, chunk, nsb, acc, nc);
+  check_hip(hipGetLastError(), "values_kernel launch");
+}
+
+}  // namespace
+
+void launch_values(const HostTable& h, const DeviceTable& d, const Bucket& bk, bool fp64,
+                   const float* X, int64_t M, int64_t ldx, const double* leaf_val, double* acc,
+                   const ValuesShape& shape, hipStream_t s) {
+  if (values_lds_bytes(h.F) > (size_t)kMaxLdsBytes)
+    fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
+  if (!fp64) {
+    switch (bk.dmax) {
+      case 8: launch_one<float, 8, 8, true, true>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 16: launch_one<float, 16, 8, true, true>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 32: launch_one<float, 32, 8, false, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      default: launch_one<float, 64, 4, false, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+    }
+  } else {
+    switch (bk.dmax) {
+      case 8: launch_one<double, 8, 8, true, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 16: launch_one<double, 16, 8, true, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 32: launch_one<double, 32, 4, false, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      default: launch_one<double, 64, 2, false, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+    }
+  }
+}
+
+}  // namespace qts

@@ -1,0 +1,77 @@
+// Device-side tables and kernel launchers (HIP, gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "qts_internal.h"
+
+namespace qts {
+
+// The 8-node rule on [0,1] in the two precisions used by the kernels.
+// tau_m = t_m / (1 - t_m) lets a factor b (1-t) + o t be written as
+// (1-t) (b + o tau), so the per-lane factor is one FMA; the (1-t)^(d-1)
+// product that this pulls out of a path is folded into the weights wtab.
+template <typename T>
+struct NodeConsts {
+  T t[kNodes];
+  T s[kNodes];  // 1 - t, rounded from FP64 separately
+  T tau[kNodes];
+  T w[kNodes];
+};
+
+// Device copy of the path table.  Element arrays are shared by all buckets.
+struct DeviceTable {
+  int device = -1;
+  PathHdr* hdr = nullptr;
+  int32_t* feat = nullptr;
+  float* lo = nullptr;
+  float* hi = nullptr;
+  float* b32 = nullptr;
+  float* cb32 = nullptr;
+  double* b64 = nullptr;
+  double* cb64 = nullptr;
+  double* leaf_val = nullptr;  // the model's own leaf values
+  float* wtab32 = nullptr;     // [kMaxUnique+1][kNodes]: w_m (1-t_m)^(d-1)
+  double* wtab64 = nullptr;
+  NodeConsts<float> n32;
+  NodeConsts<double> n64;
+};
+
+// Launch shape of the first-order kernel for one bucket.
+struct ValuesShape {
+  int waves_per_block = 4;  // wavefronts sharing one 64-sample tile
+  int chunk = 0;            // paths per work item (0 = derive from size)
+};
+
+constexpr int kTileStride = kSamplesPerBlock + 1;  // padded LDS row (bank spread)
+
+inline size_t values_lds_bytes(int F) {
+  size_t xs = (size_t)F * kTileStride * sizeof(float);
+  xs = (xs + 15) & ~(size_t)15;
+  return xs + (size_t)F * kTileStride * sizeof(double);
+}
+
+// Largest F whose tile + FP64 accumulator fit in one workgroup's LDS.
+constexpr int kMaxLdsBytes = 160 * 1024;
+
+// Wave-uniform load through the scalar data cache: reading through the
+// constant address space lets the compiler emit s_load for an address that is
+// uniform across the wave (path data read by every lane of a wavefront).
+template <class T>
+__device__ __forceinline__ T ldu(const T* p) {
+  return *reinterpret_cast<const __attribute__((address_space(4))) T*>(
+      reinterpret_cast<const __attribute__((address_space(4))) char*>(
+          (const __attribute__((address_space(4))) void*)p));
+}
+
+void launch_fill_zero(double* p, int64_t n, hipStream_t s);
+void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+
+// Accumulate phi (FP64, [M,F], pre-zeroed) over the paths of one bucket.
+void launch_values(const HostTable& h, const DeviceTable& d, const Bucket& bk, bool fp64,
+                   const float* X, int64_t M, int64_t ldx, const double* leaf_val,
+                   double* acc, const ValuesShape& shape, hipStream_t s);
+
+void check_hip(hipError_t e, const char* what);
+
+}  // namespace qts

@@ -1,0 +1,67 @@
+// Internal structures shared by the host library and the kernel launchers.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "qtreeshap.h"
+
+namespace qts {
+
+constexpr int kNodes = 8;          // fixed Gauss-Legendre node count (section 5)
+constexpr int kMaxDepth = 128;     // deeper trees are rejected (QTS_E_UNSUPPORTED)
+constexpr int kMaxUnique = 64;     // longer collapsed paths are rejected
+constexpr int kSamplesPerBlock = 64;  // one explained sample per wavefront lane
+
+// Error raised inside the library; converted to a return code at the C-ABI.
+struct Error {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg);
+
+// Per-path header, 16 bytes so one scalar load fetches it.
+struct alignas(16) PathHdr {
+  int32_t off;   // first element of the path in the element arrays
+  int32_t d;     // unique features on the path
+  int32_t leaf;  // leaf ordinal (tree-major, node-id order)
+  int32_t tree;
+};
+
+// Element flag: bit 30 of the packed feature word marks "a NaN follows every
+// split of this feature on the path" (missing_ok).
+constexpr int32_t kMissingOkBit = 1 << 30;
+constexpr int32_t kFeatureMask = kMissingOkBit - 1;
+
+// Paths with the same unique-feature capacity are stored contiguously.
+struct Bucket {
+  int32_t dmax;        // capacity of the kernel instance (8, 16, 32 or 64)
+  int32_t path_begin;  // [path_begin, path_end) in path order
+  int32_t path_end;
+  int64_t elems;       // sum of d over the bucket's paths
+};
+
+// Collapsed path table in host memory (built once per model).
+struct HostTable {
+  int32_t F = 0;
+  int32_t n_trees = 0;
+  int32_t max_depth = 0;
+  int32_t max_unique = 0;
+  double base_score = 0.0;
+  double expected = 0.0;  // sum_T E_T[f] + base_score
+  std::vector<PathHdr> hdr;
+  std::vector<int32_t> feat;  // packed: feature | missing_ok bit
+  std::vector<float> lo, hi;
+  std::vector<double> b, cb;  // b_j and 1 - b_j, FP64
+  std::vector<double> leaf_value;
+  std::vector<Bucket> buckets;
+};
+
+HostTable build_host_table(const qts_tree_arrays& t, int32_t n_features, double base_score);
+
+// Golub-Welsch: n-node Gauss-Legendre rule on [0,1] in FP64.
+void gauss_legendre(int n, double* t, double* one_minus_t, double* w);
+
+}  // namespace qts

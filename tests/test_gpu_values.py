@@ -1,0 +1,149 @@
+"""GPU parity of qts_shap_values against the FP64 oracle (8-node rule), on the
+shapes of the five workloads scaled down, on sampled rows of the full-size
+headline workload in the benchmark's launch configuration, and on edge cases."""
+import functools
+
+import numpy as np
+import pytest
+
+import synth
+from tests.parity import check, row_normwise
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@functools.lru_cache(maxsize=2)
+def _full_c2():
+    return synth.make_workload("c2_values")
+
+
+@pytest.fixture(scope="module")
+def q():
+    import paper_2605_04497_amd as q
+    return q
+
+
+def _run(q, ens, X, precision, leaf_values=None):
+    e = q.Ensemble(ens)
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    lv = None if leaf_values is None else torch.from_numpy(leaf_values).cuda()
+    phi = e.shap_values(Xd, precision, leaf_values=lv)
+    torch.cuda.synchronize()
+    return phi.cpu().numpy().astype(np.float64), e
+
+
+CASES = [
+    ("c1_small", dict()),                                   # whole workload
+    ("c2_values", dict(T=40, M=333, n_train=20000)),        # ragged tail, int ties
+    ("c3_interactions", dict(T=6, M=130, n_train=20000)),   # depths 3..20: buckets 8/16/32
+    ("c4_adjoint", dict(T=20, M=200, n_train=20000)),
+    ("c5_deep", dict(T=4, M=70, n_train=30000)),            # d up to ~30
+]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("name,over", CASES, ids=[c[0] for c in CASES])
+def test_values_match_oracle(q, oracle_mod, name, over, precision):
+    print("case", name, over, precision, flush=True)
+    wl = synth.make_workload(name, **over)
+    got, e = _run(q, wl.ensemble, wl.X, precision)
+    want = oracle_mod.shap_values(wl.ensemble, wl.X, n=8)
+    check(got, want, precision, name)
+    # efficiency (exact only where the 8-node rule is exact: d <= 16)
+    if e.info["max_unique"] <= 16:
+        fx = oracle_mod.predict(wl.ensemble, wl.X)
+        res = np.abs(got.sum(1) + e.expected_value - fx).max()
+        scale = max(1.0, np.abs(fx).max())
+        assert res <= (1e-4 if precision == "fp32" else 1e-10) * scale
+
+
+def test_c1_fp64_matches_enumeration(q):
+    """FP64 GPU vs subset enumeration of the Shapley definition (F = 8)."""
+    from oracle import brute
+    wl = synth.make_workload("c1_small", M=24)
+    got, _ = _run(q, wl.ensemble, wl.X, "fp64")
+    assert row_normwise(got, brute.shap_values(wl.ensemble, wl.X)) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_full_size_headline_sampled_rows(q, oracle_mod, precision):
+    """The benchmark's workload at full size (1000 trees, 100k samples, same
+    launch configuration), checked on seeded sampled rows."""
+    print("full-size c2_values", precision, flush=True)
+    wl = _full_c2()
+    got, e = _run(q, wl.ensemble, wl.X, precision)
+    rows = np.random.default_rng(5).choice(wl.X.shape[0], 24, replace=False)
+    rows = np.concatenate([rows, [0, 63, 64, wl.X.shape[0] - 1]])
+    want = oracle_mod.shap_values(wl.ensemble, wl.X[rows], n=8)
+    check(got[rows], want, precision, "c2 full")
+    fx = oracle_mod.predict(wl.ensemble, wl.X[rows])
+    assert np.abs(got[rows].sum(1) + e.expected_value - fx).max() <= 1e-4 * max(
+        1.0, np.abs(fx).max())
+
+
+def test_edge_cases(q, oracle_mod):
+    wl = synth.make_workload("c4_adjoint", T=5, M=130, n_train=5000)
+    ens, X = wl.ensemble, wl.X.copy()
+    X[3, :] = np.nan
+    X[5, ::2] = np.nan
+    X[7, 1] = np.inf
+    X[8, 2] = -np.inf
+    e = q.Ensemble(ens)
+    # M = 0 is a no-op
+    out = e.shap_values(torch.zeros((0, ens.n_features), device="cuda"))
+    assert out.shape == (0, ens.n_features)
+    for precision in ("fp32", "fp64"):
+        want = oracle_mod.shap_values(ens, X, n=8)
+        Xd = torch.from_numpy(X).cuda()
+        got = e.shap_values(Xd, precision).cpu().numpy()
+        check(got, want, precision, "nan/inf rows")
+        # single row, and a row stride larger than F
+        got1 = e.shap_values(Xd[7:8], precision).cpu().numpy()
+        check(got1, want[7:8], precision, "M=1")
+        wide = torch.zeros((X.shape[0], ens.n_features + 9), device="cuda")
+        wide[:, :ens.n_features] = Xd
+        got_w = e.shap_values(wide[:, :ens.n_features], precision).cpu().numpy()
+        check(got_w, want, precision, "ldx > F")
+
+
+def test_leaf_value_override_and_linearity(q, oracle_mod):
+    wl = synth.make_workload("c2_values", T=10, M=100, n_train=5000)
+    ens = wl.ensemble
+    rng = np.random.default_rng(9)
+    v = rng.normal(size=ens.n_leaves())
+    want = oracle_mod.shap_values(ens.with_leaf_values(v), wl.X)
+    for precision in ("fp32", "fp64"):
+        got, _ = _run(q, ens, wl.X, precision, leaf_values=v)
+        check(got, want, precision, "leaf override")
+
+
+def test_zero_covers_and_repeated_features(q, oracle_mod):
+    for seed in range(3):
+        rng = np.random.default_rng(300 + seed)
+        ens = synth.random_small_ensemble(rng, 6, 7, 7, zero_cover=True)
+        X = (np.round(rng.standard_normal((90, 7)) * 2) / 2).astype(np.float32)
+        X[::7, 2] = np.nan
+        want = oracle_mod.shap_values(ens, X, n=8)
+        for precision in ("fp32", "fp64"):
+            got, _ = _run(q, ens, X, precision)
+            check(got, want, precision, "zero covers")
+
+
+@pytest.mark.parametrize("d", [1, 8, 9, 16, 17, 31, 32, 33, 48, 64])
+def test_bucket_boundaries_single_path_closed_form(q, oracle_mod, d):
+    """A followed chain with all b_j = 0.5: every bucket capacity and its
+    boundaries; compared with the oracle's 8-node value (exact for d <= 16)."""
+    b = 0.5
+    node = ("leaf", 1.0, b ** d)
+    for j in reversed(range(d)):
+        node = ("split", j, 0.0, b ** j, node, ("leaf", 0.3, b ** j * (1 - b)))
+    ens = synth.from_nested([node], n_features=d + 1)
+    X = np.full((3, d + 1), -1.0, np.float32)
+    X[1, d // 2] = 1.0   # leaves the chain half way
+    X[2, :] = np.nan     # missing everywhere: goes right at the root
+    want = oracle_mod.shap_values(ens, X, n=8)
+    for precision in ("fp32", "fp64"):
+        got, _ = _run(q, ens, X, precision)
+        check(got, want, precision, "chain d=%d" % d)

@@ -1,0 +1,197 @@
+"""CPU tests of the host side of the library: the C-ABI exports, the
+Gauss-Legendre rule, the collapsed path table, E[f] and model validation.
+No GPU is used (ensembles are built with qts_build_host)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as O
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def q():
+    import paper_2605_04497_amd as q
+    return q
+
+
+def test_library_exports_every_declared_symbol(q):
+    header = open(os.path.join(ROOT, "include", "qtreeshap.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|const char\*)\s+(qts_\w+)\s*\(", header, re.M))
+    assert {"qts_load_ensemble", "qts_shap_values", "qts_shap_interactions",
+            "qts_shap_backward", "qts_last_error"} <= declared
+    lib = ctypes.CDLL(q._lib.LIB_PATH)
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert set(q._lib.SIGNATURES) == declared
+
+
+def test_gauss_legendre_rule(q, oracle_mod):
+    """Golub-Welsch rule (library) vs Newton rule (oracle); both exact to degree 15."""
+    for n in (1, 2, 5, 8, 16):
+        t, s, w = q.gauss_legendre(n)
+        t2, s2, w2 = oracle_mod.gauss_legendre(n)
+        np.testing.assert_allclose(t, t2, atol=2e-15)
+        np.testing.assert_allclose(s, s2, atol=2e-15)
+        np.testing.assert_allclose(w, w2, rtol=5e-14)
+        for k in range(2 * n):
+            assert abs(np.sum(w * t ** k) - 1.0 / (k + 1)) < 1e-14 * (k + 1)
+    t, s, w = q.gauss_legendre(8)
+    assert np.all(np.diff(t) > 0) and np.all(t > 0) and np.all(s > 0)
+    np.testing.assert_allclose(t[::-1], s, atol=1e-16)  # symmetric rule
+    with pytest.raises(q.QtsError):
+        q.gauss_legendre(0)
+
+
+def _phi_from_table(tab, leaf_values, X, F):
+    """Re-evaluate phi from the exported table in numpy (test-only path form)."""
+    x, wq = np.polynomial.legendre.leggauss(8)
+    t, w = (1 + x) / 2, wq / 2
+    M = X.shape[0]
+    phi = np.zeros((M, F))
+    for p in range(tab["path_len"].shape[0]):
+        a, d = tab["path_off"][p], tab["path_len"][p]
+        f = tab["feat"][a:a + d]
+        lo, hi, mok = tab["lo"][a:a + d], tab["hi"][a:a + d], tab["missing_ok"][a:a + d] != 0
+        b, cb = tab["b"][a:a + d], tab["one_minus_b"][a:a + d]
+        xv = X[:, f]
+        with np.errstate(invalid="ignore"):
+            inside = (xv >= lo) & (np.isnan(hi) | (xv < hi))
+        o = np.where(np.isnan(xv), mok, inside).astype(float)          # [M, d]
+        fac = b[None, :, None] * (1 - t) + o[:, :, None] * t           # [M, d, 8]
+        val = leaf_values[tab["path_leaf"][p]]
+        for j in range(d):
+            loo = np.prod(np.delete(fac, j, axis=1), axis=1)            # [M, 8]
+            coef = np.where(o[:, j] > 0, cb[j], -b[j])
+            phi[:, f[j]] += val * coef * (loo @ w)
+    return phi
+
+
+@pytest.mark.parametrize("name,over", [
+    ("c1_small", dict(M=40)),
+    ("c2_values", dict(T=4, M=30, n_train=4000)),
+    ("c5_deep", dict(T=3, M=12, n_train=20000)),
+])
+def test_path_table_reproduces_oracle(q, oracle_mod, name, over):
+    wl = synth.make_workload(name, **over)
+    ens, X = wl.ensemble, wl.X.copy()
+    X[0, :] = np.nan
+    X[1, ::3] = np.nan
+    e = q.Ensemble(ens, host_only=True)
+    tab = e.export_paths()
+    assert e.info["device"] == -1 and e.n_leaves == ens.n_leaves()
+    assert e.info["max_unique"] <= e.info["max_depth"]
+    np.testing.assert_allclose(tab["b"] + tab["one_minus_b"], 1.0, atol=1e-15)
+    phi = _phi_from_table(tab, ens.leaf_values(), X, ens.n_features)
+    want = oracle_mod.shap_values(ens, X, n=8)
+    np.testing.assert_allclose(phi, want, atol=1e-12 * max(1.0, np.abs(want).max()))
+    assert e.expected_value == pytest.approx(oracle_mod.expected_value(ens), abs=1e-13)
+
+
+def test_expected_value_includes_base_score(q, oracle_mod):
+    ens = synth.stump()
+    ens.base_score = 0.25
+    e = q.Ensemble(ens, host_only=True)
+    assert e.expected_value == pytest.approx(-1.1 + 0.25, abs=1e-15)
+
+
+def test_single_leaf_tree_and_null_default_left(q):
+    ens = synth.from_nested([("leaf", 3.0, 10.0), ("split", 0, 0.0, 10.0, ("leaf", 1.0, 4.0),
+                                                   ("leaf", 2.0, 6.0))], n_features=1)
+    e = q.Ensemble(ens, host_only=True)
+    assert e.n_leaves == 3 and e.info["n_paths"] == 2
+    assert e.expected_value == pytest.approx(3.0 + 0.4 + 1.2)
+    # default_left = NULL means every missing value goes right
+    L = q._lib
+    a = {k: np.ascontiguousarray(getattr(ens, k)) for k in (
+        "tree_offsets", "left", "right", "feature", "threshold", "cover", "value")}
+    ta = L.TreeArrays(ens.n_trees, a["tree_offsets"].ctypes.data, a["left"].ctypes.data,
+                      a["right"].ctypes.data, a["feature"].ctypes.data,
+                      a["threshold"].ctypes.data, None, a["cover"].ctypes.data,
+                      a["value"].ctypes.data)
+    h = ctypes.c_void_p()
+    L.check(L.lib().qts_build_host(ctypes.byref(ta), 1, 0.0, ctypes.byref(h)))
+    mok = np.zeros(2, np.uint8)
+    L.check(L.lib().qts_export_paths(h, None, None, None, None, None, None,
+                                     mok.ctypes.data, None, None))
+    assert list(mok) == [0, 1]  # left path: NaN goes right -> not ok; right path ok
+    L.check(L.lib().qts_free_ensemble(h))
+
+
+def _arrays(**over):
+    base = dict(tree_offsets=[0, 3], left=[1, -1, -1], right=[2, -1, -1], feature=[0, 0, 0],
+                threshold=[0.0, 0.0, 0.0], default_left=[0, 0, 0], cover=[10.0, 4.0, 6.0],
+                value=[0.0, 1.0, 2.0])
+    base.update(over)
+    return synth.Ensemble(np.asarray(base["tree_offsets"], np.int64),
+                          np.asarray(base["left"], np.int32), np.asarray(base["right"], np.int32),
+                          np.asarray(base["feature"], np.int32),
+                          np.asarray(base["threshold"], np.float32),
+                          np.asarray(base["default_left"], np.uint8),
+                          np.asarray(base["cover"], np.float64),
+                          np.asarray(base["value"], np.float64), base.get("F", 2))
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(left=[1, 1, -1]), -2),                      # node reached twice
+    (dict(left=[0, -1, -1]), -2),                     # cycle back to the root
+    (dict(left=[1, -1, -1], right=[-1, -1, -1]), -2),  # one child
+    (dict(left=[5, -1, -1]), -2),                     # child out of range
+    (dict(feature=[2, 0, 0]), -2),                    # feature >= F
+    (dict(feature=[-1, 0, 0]), -2),
+    (dict(cover=[10.0, -1.0, 6.0]), -2),              # negative cover
+    (dict(cover=[10.0, np.nan, 6.0]), -2),            # NaN cover
+    (dict(threshold=[np.nan, 0.0, 0.0]), -2),         # NaN threshold
+    (dict(tree_offsets=[0, 0]), -2),                  # empty tree
+    (dict(tree_offsets=[1, 3]), -2),
+    (dict(F=0), -1),                                  # no features
+])
+def test_invalid_models_are_rejected(q, over, code):
+    with pytest.raises(q.QtsError) as ei:
+        q.Ensemble(_arrays(**over), host_only=True)
+    assert ei.value.code == code
+    assert len(q._lib.lib().qts_last_error()) > 0
+
+
+def _chain(depth, n_features, distinct=True):
+    node = ("leaf", 1.0, 1.0)
+    for j in reversed(range(depth)):
+        node = ("split", j if distinct else 0, 0.0, 2.0, node, ("leaf", 0.0, 1.0))
+    return synth.from_nested([node], n_features=n_features)
+
+
+def test_limits(q):
+    q.Ensemble(_chain(64, 64), host_only=True)          # 64 unique features: fine
+    with pytest.raises(q.QtsError) as ei:
+        q.Ensemble(_chain(65, 65), host_only=True)      # 65 unique features
+    assert ei.value.code == -3
+    e = q.Ensemble(_chain(128, 1, distinct=False), host_only=True)
+    assert e.info["max_depth"] == 128 and e.info["max_unique"] == 1
+    with pytest.raises(q.QtsError) as ei:
+        q.Ensemble(_chain(129, 1, distinct=False), host_only=True)
+    assert ei.value.code == -3
+
+
+def test_null_arguments_and_host_only_compute(q):
+    L = q._lib
+    h = ctypes.c_void_p()
+    assert L.lib().qts_build_host(None, 1, 0.0, ctypes.byref(h)) == -1
+    assert L.lib().qts_expected_value(None, None) == -1
+    assert L.lib().qts_free_ensemble(None) == 0
+    e = q.Ensemble(synth.stump(), host_only=True)
+    rc = L.lib().qts_shap_values(e._h, None, 0, 1, None, None, 0, None)
+    assert rc == -1  # host-only ensembles cannot compute
+    assert b"host-only" in L.lib().qts_last_error()
+    rc = L.lib().qts_shap_values(e._h, None, -1, 1, None, None, 0, None)
+    assert rc == -1
+    rc = L.lib().qts_shap_values(e._h, None, 1, 0, None, None, 0, None)
+    assert rc == -1  # ldx < F
+    rc = L.lib().qts_shap_values(e._h, None, 0, 1, None, None, 7, None)
+    assert rc == -1  # unknown precision
