@@ -80,11 +80,14 @@ def time_steps(fn, steps, warmup, torch):
 def cpu_baseline(ens, X, seconds, oracle):
     threads = oracle.default_threads()
     n_leaves = ens.n_leaves()
+    # probe with two rows per thread (the oracle threads over rows), then size
+    # the timed sample for about `seconds` of work
+    probe = min(X.shape[0], 2 * threads)
     t0 = time.perf_counter()
-    oracle.shap_values(ens, X[:2], n=8, threads=threads)
-    per_row = max((time.perf_counter() - t0) / 2, 1e-4)
-    rows = int(max(2, min(X.shape[0], seconds / per_row * threads * 0.9)))
-    rows = (rows // threads) * threads or rows
+    oracle.shap_values(ens, X[:probe], n=8, threads=threads)
+    rate = probe / max(time.perf_counter() - t0, 1e-6)   # rows per second
+    rows = int(max(probe, min(X.shape[0], rate * seconds)))
+    rows = max(threads, (rows // threads) * threads)
     t0 = time.perf_counter()
     oracle.shap_values(ens, X[:rows], n=8, threads=threads)
     dt = time.perf_counter() - t0

@@ -72,31 +72,21 @@ std::vector<T> narrow(const std::vector<double>& v) {
 }
 
 void free_device(DeviceTable& d) {
-  void* ptrs[] = {d.hdr, d.feat, d.lo, d.hi, d.b32, d.cb32, d.b64, d.cb64, d.leaf_val,
-                  d.wtab32, d.wtab64};
+  void* ptrs[] = {d.hdr, d.feat, d.lo, d.hi, d.b32, d.cb32, d.b64, d.cb64, d.leaf_val};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   d = DeviceTable{};
 }
 
-void build_nodes(DeviceTable& d, std::vector<double>& wtab) {
+void build_nodes(DeviceTable& d) {
   double t[kNodes], s[kNodes], w[kNodes];
   gauss_legendre(kNodes, t, s, w);
   for (int m = 0; m < kNodes; ++m) {
-    const double tau = t[m] / s[m];
     d.n32.t[m] = (float)t[m];
-    d.n32.s[m] = (float)s[m];
-    d.n32.tau[m] = (float)tau;
     d.n32.w[m] = (float)w[m];
     d.n64.t[m] = t[m];
-    d.n64.s[m] = s[m];
-    d.n64.tau[m] = tau;
     d.n64.w[m] = w[m];
   }
-  wtab.assign((size_t)(kMaxUnique + 1) * kNodes, 0.0);
-  for (int dd = 0; dd <= kMaxUnique; ++dd)
-    for (int m = 0; m < kNodes; ++m)
-      wtab[(size_t)dd * kNodes + m] = w[m] * std::pow(s[m], (double)(dd > 0 ? dd - 1 : 0));
 }
 
 void require_device(const qts_ensemble* ens) {
@@ -218,9 +208,7 @@ int qts_load_ensemble(const qts_tree_arrays* trees, int32_t n_features, double b
       hipStream_t s = (hipStream_t)stream;
       DeviceTable& d = e->dev;
       check_hip(hipGetDevice(&d.device), "hipGetDevice");
-      std::vector<double> wtab;
-      build_nodes(d, wtab);
-      std::vector<float> wtab32 = narrow<float>(wtab);
+      build_nodes(d);
       // Element arrays get kPad trailing slots (feature 0, no bounds, b = 1):
       // kernels load whole batches of elements past the end of a path.
       std::vector<int32_t> feat = padded(h.feat, 0);
@@ -236,8 +224,6 @@ int qts_load_ensemble(const qts_tree_arrays* trees, int32_t n_features, double b
       d.b64 = upload(b64, s);
       d.cb64 = upload(cb64, s);
       d.leaf_val = upload(h.leaf_value, s);
-      d.wtab32 = upload(wtab32, s);
-      d.wtab64 = upload(wtab, s);
       check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
       e->on_device = true;
     } catch (...) {

@@ -16,15 +16,15 @@
 //
 // Per (sample, path) with unique features j = 0..d-1 and nodes m:
 //   o_j    = x in [lo_j, hi_j) ? 1 : 0   (NaN: missing_ok_j)            (Eq. 2)
-//   F_j(m) = b_j (1 - t_m) + o_j t_m = (1 - t_m) (b_j + o_j tau_m)
+//   c_j    = o_j - b_j, taken as the stored FP64-derived 1 - b_j or as -b_j
+//   F_j(m) = b_j (1 - t_m) + o_j t_m = b_j + t_m c_j      (one FMA per node)
 //   LOO_j  = sum_m w_m prod_{k != j} F_k(m)    by prefix x suffix products
-//   phi[s, f_j] += val (o_j - b_j) LOO_j       (o_j - b_j = 1 - b_j or -b_j)
-// With TAU the (1 - t_m)^(d-1) factor common to every leave-one-out product
-// is folded into the node weights (wtab), so each factor costs one FMA; it is
-// used for paths of at most 16 unique features, where the products stay far
-// from the FP32 range limits.  Longer paths use b_j s_m + o_j t_m directly.
-// NH < 8 splits the nodes over several passes to bound the registers held
-// by the prefix array (linearity: the node sum is additive).
+//   phi[s, f_j] += val c_j LOO_j
+// Slots past the end of a path get c = 0 and b = 1, a factor of exactly 1, so
+// whole batches of eight features run without branches.  The prefix products
+// are kept only at batch checkpoints and rebuilt batch by batch in the
+// backward sweep, which bounds the registers for long paths; NH < 8 splits the
+// nodes over several passes (the node sum is additive).
 #include <hip/hip_runtime.h>
 
 #include "../qts_device.h"
@@ -52,21 +52,14 @@ __device__ __forceinline__ double to_vgpr(double v) {
   return r;
 }
 
-// Factor of element j at node m (slot j >= d carries o = 0, b = 1).
-template <typename T, bool TAU>
-__device__ __forceinline__ T factor(T o, T b, T tau, T t, T s) {
-  return TAU ? fmaT(o, tau, b) : fmaT(o, t, b * s);
-}
-
-template <typename T, int DMAX, int NH, bool TAU, bool STORE_G>
+template <typename T, int DMAX, int NH, bool STORE_G>
 __global__ void __launch_bounds__(256)
 values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
               const float* __restrict__ lo, const float* __restrict__ hi,
               const T* __restrict__ bb, const T* __restrict__ cbb,
-              const double* __restrict__ leaf_val, const T* __restrict__ wtab,
-              const float* __restrict__ X, int64_t M, int64_t ldx, int32_t F,
-              int32_t path_begin, int32_t path_end, int32_t chunk, int32_t nsb,
-              double* __restrict__ acc, NodeConsts<T> nc) {
+              const double* __restrict__ leaf_val, const float* __restrict__ X, int64_t M,
+              int64_t ldx, int32_t F, int32_t path_begin, int32_t path_end, int32_t chunk,
+              int32_t nsb, double* __restrict__ acc, NodeConsts<T> nc) {
   constexpr int NB = DMAX / 8;  // feature batches
   extern __shared__ __align__(16) unsigned char smem[];
   float* xs = reinterpret_cast<float*>(smem);
@@ -98,15 +91,11 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
   const int pb = __builtin_amdgcn_readfirstlane(p0);
   const int pe = __builtin_amdgcn_readfirstlane(p1);
 
-  // node constants pinned in VGPRs: a VALU op may read only one SGPR on
-  // gfx9-class hardware, and b_j arrives in an SGPR
-  T tv[kNodes], sv[kNodes], tauv[kNodes];
+  // nodes pinned in VGPRs: a VALU op may read only one SGPR on gfx9-class
+  // hardware, and b_j arrives in an SGPR
+  T tv[kNodes];
 #pragma unroll
-  for (int m = 0; m < kNodes; ++m) {
-    tv[m] = to_vgpr(nc.t[m]);
-    sv[m] = to_vgpr(nc.s[m]);
-    tauv[m] = to_vgpr(nc.tau[m]);
-  }
+  for (int m = 0; m < kNodes; ++m) tv[m] = to_vgpr(nc.t[m]);
 
   for (int p = pb + wave; p < pe; p += nw) {
     const int d = ldu(&hdr[p].d);
@@ -114,21 +103,23 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
     const T val = (T)ldu(leaf_val + ldu(&hdr[p].leaf));
     const int nb = (d + 7) >> 3;  // batches in use
 
-    // Follow indicators, eight elements per batch.  The element arrays are
-    // padded at the end, so a whole batch can be loaded even past the last
-    // path; slots j >= d get o = 0 (and b = 1 below): their factor is 1.
-    T o[DMAX];
+    // c_j per slot, eight slots per batch.  The element arrays are padded at
+    // the end, so a whole batch can be loaded even past the last path.
+    T cf[DMAX];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       if (b < nb) {
         const int jb = 8 * b;
         int fm[8];
         float l[8], u[8], x[8];
+        T bl[8], cbl[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
           fm[k] = ldu(feat + off + jb + k);
           l[k] = ldu(lo + off + jb + k);
           u[k] = ldu(hi + off + jb + k);
+          bl[k] = ldu(bb + off + jb + k);
+          cbl[k] = ldu(cbb + off + jb + k);
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) x[k] = xs[(fm[k] & kFeatureMask) * kTileStride + lane];
@@ -139,8 +130,8 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
           const bool miss = (fm[k] & kMissingOkBit) != 0;
           const bool lower = miss ? !(x[k] < l[k]) : (x[k] >= l[k]);
           const bool upper = !(x[k] >= u[k]);
-          const bool live = jb + k < d;
-          o[jb + k] = (live & lower & upper) ? T(1) : T(0);
+          const T c = (lower & upper) ? cbl[k] : -bl[k];
+          cf[jb + k] = (jb + k < d) ? c : T(0);
         }
       }
     }
@@ -148,10 +139,10 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
 #pragma unroll
     for (int pass = 0; pass < kNodes / NH; ++pass) {
       const int m0 = pass * NH;
-      // checkpoints: ck[b][m] = w'_m prod_{k < 8b} F_k(m)
+      // checkpoints: ck[b][m] = w_m prod_{k < 8b} F_k(m)
       T ck[NB][NH];
 #pragma unroll
-      for (int m = 0; m < NH; ++m) ck[0][m] = TAU ? ldu(wtab + d * kNodes + m0 + m) : nc.w[m0 + m];
+      for (int m = 0; m < NH; ++m) ck[0][m] = nc.w[m0 + m];
 #pragma unroll
       for (int b = 1; b < NB; ++b) {
         if (b < nb) {
@@ -159,11 +150,10 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
           for (int m = 0; m < NH; ++m) ck[b][m] = ck[b - 1][m];
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
-            const int j = 8 * (b - 1) + k;
+            const int j = 8 * (b - 1) + k;  // always < d here
             const T bj = ldu(bb + off + j);
 #pragma unroll
-            for (int m = 0; m < NH; ++m)
-              ck[b][m] *= factor<T, TAU>(o[j], bj, tauv[m0 + m], tv[m0 + m], sv[m0 + m]);
+            for (int m = 0; m < NH; ++m) ck[b][m] *= fmaT(tv[m0 + m], cf[j], bj);
           }
         }
       }
@@ -191,7 +181,7 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
           for (int k = 0; k < 8; ++k) {
 #pragma unroll
             for (int m = 0; m < NH; ++m) {
-              const T g = factor<T, TAU>(o[jb + k], bj[k], tauv[m0 + m], tv[m0 + m], sv[m0 + m]);
+              const T g = fmaT(tv[m0 + m], cf[jb + k], bj[k]);
               Pb[k][m] = run[m];
               if (STORE_G) Gb[STORE_G ? k : 0][m] = g;
               run[m] *= g;
@@ -205,17 +195,14 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
 #pragma unroll
               for (int m = 1; m < NH; ++m) dot = fmaT(Pb[k][m], S[m], dot);
               const int f = ldu(feat + off + j) & kFeatureMask;
-              const T coef = (o[j] != T(0)) ? ldu(cbb + off + j) : -bj[k];
-              const double c = (double)(val * coef * dot);
+              const double c = (double)(val * cf[j] * dot);
               __hip_atomic_fetch_add(&as[f * kTileStride + lane], c, __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_WORKGROUP);
             }
             if (j > 0) {
 #pragma unroll
               for (int m = 0; m < NH; ++m) {
-                const T g = STORE_G ? Gb[STORE_G ? k : 0][m]
-                                    : factor<T, TAU>(o[j], bj[k], tauv[m0 + m], tv[m0 + m],
-                                                     sv[m0 + m]);
+                const T g = STORE_G ? Gb[STORE_G ? k : 0][m] : fmaT(tv[m0 + m], cf[j], bj[k]);
                 S[m] *= g;
               }
             }
@@ -240,7 +227,7 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
 
 namespace {
 
-template <typename T, int DMAX, int NH, bool TAU, bool STORE_G>
+template <typename T, int DMAX, int NH, bool STORE_G>
 void launch_one(const HostTable& h, const DeviceTable& d, const Bucket& bk, const float* X,
                 int64_t M, int64_t ldx, const double* leaf_val, double* acc,
                 const ValuesShape& shape, hipStream_t s) {
@@ -262,19 +249,18 @@ void launch_one(const HostTable& h, const DeviceTable& d, const Bucket& bk, cons
   const int threads = 64 * shape.waves_per_block;
   const T* b = std::is_same<T, float>::value ? (const T*)d.b32 : (const T*)d.b64;
   const T* cb = std::is_same<T, float>::value ? (const T*)d.cb32 : (const T*)d.cb64;
-  const T* wtab = std::is_same<T, float>::value ? (const T*)d.wtab32 : (const T*)d.wtab64;
   NodeConsts<T> nc;
   if constexpr (std::is_same<T, float>::value) nc = d.n32; else nc = d.n64;
   static bool attr_set = false;  // allow more than the default 64 KiB of dynamic LDS
   if (!attr_set) {
-    check_hip(hipFuncSetAttribute((const void*)values_kernel<T, DMAX, NH, TAU, STORE_G>,
+    check_hip(hipFuncSetAttribute((const void*)values_kernel<T, DMAX, NH, STORE_G>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes),
               "hipFuncSetAttribute");
     attr_set = true;
   }
-  hipLaunchKernelGGL((values_kernel<T, DMAX, NH, TAU, STORE_G>), dim3((unsigned)grid),
-                     dim3(threads), lds, s, d.hdr, d.feat, d.lo, d.hi, b, cb, leaf_val, wtab, X,
-                     M, ldx, F, bk.path_begin, bk.path_end, chunk, nsb, acc, nc);
+  hipLaunchKernelGGL((values_kernel<T, DMAX, NH, STORE_G>), dim3((unsigned)grid),
+                     dim3(threads), lds, s, d.hdr, d.feat, d.lo, d.hi, b, cb, leaf_val, X, M,
+                     ldx, F, bk.path_begin, bk.path_end, chunk, nsb, acc, nc);
   check_hip(hipGetLastError(), "values_kernel launch");
 }
 
@@ -287,17 +273,17 @@ void launch_values(const HostTable& h, const DeviceTable& d, const Bucket& bk, b
     fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
   if (!fp64) {
     switch (bk.dmax) {
-      case 8: launch_one<float, 8, 8, true, true>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      case 16: launch_one<float, 16, 8, true, true>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      case 32: launch_one<float, 32, 8, false, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      default: launch_one<float, 64, 4, false, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 8: launch_one<float, 8, 8, true>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 16: launch_one<float, 16, 8, true>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 32: launch_one<float, 32, 8, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      default: launch_one<float, 64, 4, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
     }
   } else {
     switch (bk.dmax) {
-      case 8: launch_one<double, 8, 8, true, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      case 16: launch_one<double, 16, 8, true, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      case 32: launch_one<double, 32, 4, false, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      default: launch_one<double, 64, 2, false, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 8: launch_one<double, 8, 8, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 16: launch_one<double, 16, 8, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 32: launch_one<double, 32, 4, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      default: launch_one<double, 64, 2, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
     }
   }
 }

@@ -8,14 +8,9 @@
 namespace qts {
 
 // The 8-node rule on [0,1] in the two precisions used by the kernels.
-// tau_m = t_m / (1 - t_m) lets a factor b (1-t) + o t be written as
-// (1-t) (b + o tau), so the per-lane factor is one FMA; the (1-t)^(d-1)
-// product that this pulls out of a path is folded into the weights wtab.
 template <typename T>
 struct NodeConsts {
   T t[kNodes];
-  T s[kNodes];  // 1 - t, rounded from FP64 separately
-  T tau[kNodes];
   T w[kNodes];
 };
 
@@ -31,8 +26,6 @@ struct DeviceTable {
   double* b64 = nullptr;
   double* cb64 = nullptr;
   double* leaf_val = nullptr;  // the model's own leaf values
-  float* wtab32 = nullptr;     // [kMaxUnique+1][kNodes]: w_m (1-t_m)^(d-1)
-  double* wtab64 = nullptr;
   NodeConsts<float> n32;
   NodeConsts<double> n64;
 };

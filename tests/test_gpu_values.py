@@ -131,18 +131,29 @@ def test_zero_covers_and_repeated_features(q, oracle_mod):
             check(got, want, precision, "zero covers")
 
 
-@pytest.mark.parametrize("d", [1, 8, 9, 16, 17, 31, 32, 33, 48, 64])
-def test_bucket_boundaries_single_path_closed_form(q, oracle_mod, d):
-    """A followed chain with all b_j = 0.5: every bucket capacity and its
-    boundaries; compared with the oracle's 8-node value (exact for d <= 16)."""
-    b = 0.5
+def chain_model(d, b=0.5):
+    """A chain of d distinct features; every left branch continues (cover ratio
+    b), every right branch is a leaf whose value varies with its depth."""
     node = ("leaf", 1.0, b ** d)
     for j in reversed(range(d)):
-        node = ("split", j, 0.0, b ** j, node, ("leaf", 0.3, b ** j * (1 - b)))
-    ens = synth.from_nested([node], n_features=d + 1)
+        val = (0.2 + 0.05 * (j % 7)) * (-1) ** j
+        node = ("split", j, 0.0, b ** j, node, ("leaf", val, b ** j * (1 - b)))
+    return synth.from_nested([node], n_features=d + 1)
+
+
+def chain_rows(d):
     X = np.full((3, d + 1), -1.0, np.float32)
     X[1, d // 2] = 1.0   # leaves the chain half way
     X[2, :] = np.nan     # missing everywhere: goes right at the root
+    return X
+
+
+@pytest.mark.parametrize("d", [1, 8, 9, 16, 17, 24, 25, 31, 32, 33, 48, 64])
+def test_bucket_boundaries_chain(q, oracle_mod, d):
+    """Every bucket capacity and batch count at and around its boundaries
+    (paths padded to whole batches of eight), against the oracle's 8-node
+    value (exact for d <= 16)."""
+    ens, X = chain_model(d), chain_rows(d)
     want = oracle_mod.shap_values(ens, X, n=8)
     for precision in ("fp32", "fp64"):
         got, _ = _run(q, ens, X, precision)
