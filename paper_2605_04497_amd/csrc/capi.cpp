@@ -209,13 +209,40 @@ int qts_load_ensemble(const qts_tree_arrays* trees, int32_t n_features, double b
       DeviceTable& d = e->dev;
       check_hip(hipGetDevice(&d.device), "hipGetDevice");
       build_nodes(d);
-      // Element arrays get kPad trailing slots (feature 0, no bounds, b = 1):
-      // kernels load whole batches of elements past the end of a path.
-      std::vector<int32_t> feat = padded(h.feat, 0);
-      std::vector<float> lo = padded(h.lo, -INFINITY), hi = padded(h.hi, NAN);
-      std::vector<double> b64 = padded(h.b, 1.0), cb64 = padded(h.cb, 0.0);
+      // Device layout: every path is padded to whole batches of eight
+      // elements with inert slots (feature 0, no bounds, missing_ok, b = 1,
+      // 1-b = 0): their factor is exactly 1 and their contribution 0, so the
+      // kernels process whole batches without per-slot tests.
+      std::vector<PathHdr> hdr = h.hdr;
+      std::vector<int32_t> feat;
+      std::vector<float> lo, hi;
+      std::vector<double> b64, cb64;
+      size_t n_pad = 0;
+      for (const PathHdr& p : h.hdr) n_pad += (size_t)((p.d + 7) / 8) * 8;
+      feat.reserve(n_pad); lo.reserve(n_pad); hi.reserve(n_pad);
+      b64.reserve(n_pad); cb64.reserve(n_pad);
+      for (size_t i = 0; i < h.hdr.size(); ++i) {
+        const PathHdr& p = h.hdr[i];
+        hdr[i].off = (int32_t)feat.size();
+        const int padded_d = (p.d + 7) / 8 * 8;
+        for (int k = 0; k < padded_d; ++k) {
+          const bool real = k < p.d;
+          const size_t e = (size_t)p.off + (size_t)k;
+          feat.push_back(real ? h.feat[e] : kMissingOkBit);
+          lo.push_back(real ? h.lo[e] : -INFINITY);
+          hi.push_back(real ? h.hi[e] : NAN);
+          b64.push_back(real ? h.b[e] : 1.0);
+          cb64.push_back(real ? h.cb[e] : 0.0);
+        }
+      }
+      if (feat.size() > (size_t)0x7fffffff) fail(QTS_E_UNSUPPORTED, "path table too large");
+      feat = padded(feat, (int32_t)kMissingOkBit);
+      lo = padded(lo, -INFINITY);
+      hi = padded(hi, NAN);
+      b64 = padded(b64, 1.0);
+      cb64 = padded(cb64, 0.0);
       std::vector<float> b32 = narrow<float>(b64), cb32 = narrow<float>(cb64);
-      d.hdr = upload(h.hdr, s);
+      d.hdr = upload(hdr, s);
       d.feat = upload(feat, s);
       d.lo = upload(lo, s);
       d.hi = upload(hi, s);

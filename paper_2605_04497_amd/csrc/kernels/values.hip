@@ -52,59 +52,22 @@ __device__ __forceinline__ double to_vgpr(double v) {
   return r;
 }
 
-template <typename T, int DMAX, int NH, bool STORE_G>
-__global__ void __launch_bounds__(256)
-values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
-              const float* __restrict__ lo, const float* __restrict__ hi,
-              const T* __restrict__ bb, const T* __restrict__ cbb,
-              const double* __restrict__ leaf_val, const float* __restrict__ X, int64_t M,
-              int64_t ldx, int32_t F, int32_t path_begin, int32_t path_end, int32_t chunk,
-              int32_t nsb, double* __restrict__ acc, NodeConsts<T> nc) {
+// The path loop of one workgroup.  NANS: the tile holds a NaN, so the
+// missing-value rule is evaluated; otherwise plain interval tests suffice.
+template <typename T, int DMAX, int NH, bool STORE_G, bool NANS>
+__device__ __forceinline__ void values_paths(
+    const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
+    const float* __restrict__ lo, const float* __restrict__ hi, const T* __restrict__ bb,
+    const T* __restrict__ cbb, const double* __restrict__ leaf_val, const float* xs, double* as,
+    int pb, int pe, int wave, int nw, int lane, const T* tv, const NodeConsts<T>& nc) {
   constexpr int NB = DMAX / 8;  // feature batches
-  extern __shared__ __align__(16) unsigned char smem[];
-  float* xs = reinterpret_cast<float*>(smem);
-  size_t xs_bytes = ((size_t)F * kTileStride * sizeof(float) + 15) & ~(size_t)15;
-  double* as = reinterpret_cast<double*>(smem + xs_bytes);
-
-  const int item = blockIdx.x;
-  const int sb = item % nsb;
-  const int ch = item / nsb;
-  const int64_t s0 = (int64_t)sb * kSamplesPerBlock;
-  const int p0 = path_begin + ch * chunk;
-  const int p1 = min(path_end, p0 + chunk);
-
-  // stage the sample tile transposed; zero the accumulator
-  const int tile = kSamplesPerBlock * F;
-  for (int i = threadIdx.x; i < tile; i += blockDim.x) {
-    const int r = i / F;
-    const int f = i - r * F;
-    const int64_t s = s0 + r;
-    xs[f * kTileStride + r] = (s < M) ? X[s * ldx + f] : 0.0f;
-    as[f * kTileStride + r] = 0.0;
-  }
-  __syncthreads();
-
-  const int lane = threadIdx.x & 63;
-  // wave-uniform loop bounds (kept in SGPRs so the path loads are scalar)
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nw = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
-  const int pb = __builtin_amdgcn_readfirstlane(p0);
-  const int pe = __builtin_amdgcn_readfirstlane(p1);
-
-  // nodes pinned in VGPRs: a VALU op may read only one SGPR on gfx9-class
-  // hardware, and b_j arrives in an SGPR
-  T tv[kNodes];
-#pragma unroll
-  for (int m = 0; m < kNodes; ++m) tv[m] = to_vgpr(nc.t[m]);
-
   for (int p = pb + wave; p < pe; p += nw) {
     const int d = ldu(&hdr[p].d);
     const int off = ldu(&hdr[p].off);
     const T val = (T)ldu(leaf_val + ldu(&hdr[p].leaf));
-    const int nb = (d + 7) >> 3;  // batches in use
+    const int nb = (d + 7) >> 3;  // batches in use; slots [d, 8 nb) are inert
 
-    // c_j per slot, eight slots per batch.  The element arrays are padded at
-    // the end, so a whole batch can be loaded even past the last path.
+    // c_j per slot, eight slots per batch
     T cf[DMAX];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -125,13 +88,17 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
         for (int k = 0; k < 8; ++k) x[k] = xs[(fm[k] & kFeatureMask) * kTileStride + lane];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-          // NaN x: the unordered lower compare accepts it iff missing_ok;
-          // hi = NaN (no upper bound) makes the upper compare true
-          const bool miss = (fm[k] & kMissingOkBit) != 0;
-          const bool lower = miss ? !(x[k] < l[k]) : (x[k] >= l[k]);
+          // hi = NaN (no upper bound) makes the upper compare true; a NaN x
+          // passes the unordered lower compare iff missing_ok
+          bool lower;
+          if (NANS) {
+            const bool miss = (fm[k] & kMissingOkBit) != 0;
+            lower = miss ? !(x[k] < l[k]) : (x[k] >= l[k]);
+          } else {
+            lower = x[k] >= l[k];
+          }
           const bool upper = !(x[k] >= u[k]);
-          const T c = (lower & upper) ? cbl[k] : -bl[k];
-          cf[jb + k] = (jb + k < d) ? c : T(0);
+          cf[jb + k] = (lower & upper) ? cbl[k] : -bl[k];
         }
       }
     }
@@ -150,7 +117,7 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
           for (int m = 0; m < NH; ++m) ck[b][m] = ck[b - 1][m];
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
-            const int j = 8 * (b - 1) + k;  // always < d here
+            const int j = 8 * (b - 1) + k;
             const T bj = ldu(bb + off + j);
 #pragma unroll
             for (int m = 0; m < NH; ++m) ck[b][m] *= fmaT(tv[m0 + m], cf[j], bj);
@@ -168,10 +135,7 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
           const int jb = 8 * b;
           T bj[8];
 #pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            const T bl = ldu(bb + off + jb + k);
-            bj[k] = (jb + k < d) ? bl : T(1);
-          }
+          for (int k = 0; k < 8; ++k) bj[k] = ldu(bb + off + jb + k);
           T Pb[8][NH];
           T Gb[STORE_G ? 8 : 1][NH];
           T run[NH];
@@ -211,6 +175,61 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
       }
     }
   }
+}
+
+template <typename T, int DMAX, int NH, bool STORE_G>
+__global__ void __launch_bounds__(512)
+values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
+              const float* __restrict__ lo, const float* __restrict__ hi,
+              const T* __restrict__ bb, const T* __restrict__ cbb,
+              const double* __restrict__ leaf_val, const float* __restrict__ X, int64_t M,
+              int64_t ldx, int32_t F, int32_t path_begin, int32_t path_end, int32_t chunk,
+              int32_t nsb, double* __restrict__ acc, NodeConsts<T> nc) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  float* xs = reinterpret_cast<float*>(smem);
+  size_t xs_bytes = ((size_t)F * kTileStride * sizeof(float) + 15) & ~(size_t)15;
+  double* as = reinterpret_cast<double*>(smem + xs_bytes);
+
+  const int item = blockIdx.x;
+  const int sb = item % nsb;
+  const int ch = item / nsb;
+  const int64_t s0 = (int64_t)sb * kSamplesPerBlock;
+  const int p0 = path_begin + ch * chunk;
+  const int p1 = min(path_end, p0 + chunk);
+
+  // stage the sample tile transposed; zero the accumulator; note any NaN
+  const int tile = kSamplesPerBlock * F;
+  int nan_seen = 0;
+  for (int i = threadIdx.x; i < tile; i += blockDim.x) {
+    const int r = i / F;
+    const int f = i - r * F;
+    const int64_t s = s0 + r;
+    const float v = (s < M) ? X[s * ldx + f] : 0.0f;
+    nan_seen |= (v != v);
+    xs[f * kTileStride + r] = v;
+    as[f * kTileStride + r] = 0.0;
+  }
+  const bool any_nan = __syncthreads_or(nan_seen) != 0;
+
+  const int lane = threadIdx.x & 63;
+  // wave-uniform loop bounds (kept in SGPRs so the path loads are scalar)
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nw = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
+  const int pb = __builtin_amdgcn_readfirstlane(p0);
+  const int pe = __builtin_amdgcn_readfirstlane(p1);
+
+  // nodes pinned in VGPRs: a VALU op may read only one SGPR on gfx9-class
+  // hardware, and b_j arrives in an SGPR
+  T tv[kNodes];
+#pragma unroll
+  for (int m = 0; m < kNodes; ++m) tv[m] = to_vgpr(nc.t[m]);
+
+  if (any_nan)
+    values_paths<T, DMAX, NH, STORE_G, true>(hdr, feat, lo, hi, bb, cbb, leaf_val, xs, as, pb,
+                                             pe, wave, nw, lane, tv, nc);
+  else
+    values_paths<T, DMAX, NH, STORE_G, false>(hdr, feat, lo, hi, bb, cbb, leaf_val, xs, as, pb,
+                                              pe, wave, nw, lane, tv, nc);
   __syncthreads();
 
   // flush: consecutive threads take consecutive features of one sample
@@ -236,10 +255,12 @@ void launch_one(const HostTable& h, const DeviceTable& d, const Bucket& bk, cons
   const int n_paths = bk.path_end - bk.path_begin;
   int chunk = shape.chunk;
   if (chunk <= 0) {
-    // enough work items to fill 256 CUs several times over, chunks >= 64 paths
-    const int64_t want_items = 8 * 256;
+    // about 32 rounds of the ~512 resident workgroups (small tail), with
+    // chunks of at least 256 paths so the per-item tile load and flush stay
+    // small next to the path work
+    const int64_t want_items = 32 * 512;
     int64_t n_chunks = (want_items + nsb - 1) / nsb;
-    n_chunks = std::max<int64_t>(1, std::min<int64_t>(n_chunks, (n_paths + 63) / 64));
+    n_chunks = std::max<int64_t>(1, std::min<int64_t>(n_chunks, (n_paths + 255) / 256));
     chunk = (int)((n_paths + n_chunks - 1) / n_chunks);
   }
   const int n_chunks = (n_paths + chunk - 1) / chunk;
@@ -251,13 +272,20 @@ void launch_one(const HostTable& h, const DeviceTable& d, const Bucket& bk, cons
   const T* cb = std::is_same<T, float>::value ? (const T*)d.cb32 : (const T*)d.cb64;
   NodeConsts<T> nc;
   if constexpr (std::is_same<T, float>::value) nc = d.n32; else nc = d.n64;
-  static bool attr_set = false;  // allow more than the default 64 KiB of dynamic LDS
-  if (!attr_set) {
+  // raise the dynamic-LDS limit once per instance (default 64 KiB); the
+  // kernel's static LDS (the block-wide vote) shares the CU's 160 KiB
+  static size_t lds_limit = 0;
+  if (lds_limit == 0) {
+    hipFuncAttributes fa;
+    check_hip(hipFuncGetAttributes(&fa, (const void*)values_kernel<T, DMAX, NH, STORE_G>),
+              "hipFuncGetAttributes");
+    const size_t limit = (size_t)kMaxLdsBytes - fa.sharedSizeBytes;
     check_hip(hipFuncSetAttribute((const void*)values_kernel<T, DMAX, NH, STORE_G>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)limit),
               "hipFuncSetAttribute");
-    attr_set = true;
+    lds_limit = limit;
   }
+  if (lds > lds_limit) fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
   hipLaunchKernelGGL((values_kernel<T, DMAX, NH, STORE_G>), dim3((unsigned)grid),
                      dim3(threads), lds, s, d.hdr, d.feat, d.lo, d.hi, b, cb, leaf_val, X, M,
                      ldx, F, bk.path_begin, bk.path_end, chunk, nsb, acc, nc);
@@ -281,7 +309,7 @@ void launch_values(const HostTable& h, const DeviceTable& d, const Bucket& bk, b
   } else {
     switch (bk.dmax) {
       case 8: launch_one<double, 8, 8, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      case 16: launch_one<double, 16, 8, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 16: launch_one<double, 16, 4, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
       case 32: launch_one<double, 32, 4, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
       default: launch_one<double, 64, 2, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
     }

@@ -32,7 +32,7 @@ struct DeviceTable {
 
 // Launch shape of the first-order kernel for one bucket.
 struct ValuesShape {
-  int waves_per_block = 4;  // wavefronts sharing one 64-sample tile
+  int waves_per_block = 8;  // wavefronts sharing one 64-sample tile
   int chunk = 0;            // paths per work item (0 = derive from size)
 };
 
