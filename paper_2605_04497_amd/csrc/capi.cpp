@@ -15,6 +15,7 @@
 
 struct qts_ensemble {
   qts::HostTable host;
+  std::vector<qts::PairClass> pair_classes;
   qts::DeviceTable dev;
   bool on_device = false;
   // launch shapes per bucket capacity index (8, 16, 32, 64) and precision
@@ -72,7 +73,9 @@ std::vector<T> narrow(const std::vector<double>& v) {
 }
 
 void free_device(DeviceTable& d) {
-  void* ptrs[] = {d.hdr, d.feat, d.lo, d.hi, d.b32, d.cb32, d.b64, d.cb64, d.leaf_val};
+  void* ptrs[] = {d.hdr,    d.feat,    d.lo,      d.hi,      d.b32,     d.cb32,
+                  d.b64,    d.cb64,    d.leaf_val, d.pr_d,   d.pr_leaf, d.pr_feat,
+                  d.pr_lo,  d.pr_hi,   d.pr_b32,  d.pr_cb32, d.pr_b64,  d.pr_cb64};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   d = DeviceTable{};
@@ -251,6 +254,21 @@ int qts_load_ensemble(const qts_tree_arrays* trees, int32_t n_features, double b
       d.b64 = upload(b64, s);
       d.cb64 = upload(cb64, s);
       d.leaf_val = upload(h.leaf_value, s);
+      {
+        PairTable pt = build_pair_table(h);
+        e->pair_classes = pt.classes;
+        d.pr_d = upload(pt.d, s);
+        d.pr_leaf = upload(pt.leaf, s);
+        d.pr_feat = upload(pt.feat, s);
+        d.pr_lo = upload(pt.lo, s);
+        d.pr_hi = upload(pt.hi, s);
+        d.pr_b32 = upload(narrow<float>(pt.b), s);
+        d.pr_cb32 = upload(narrow<float>(pt.cb), s);
+        d.pr_b64 = upload(pt.b, s);
+        d.pr_cb64 = upload(pt.cb, s);
+        // the uploads above are asynchronous: wait before the host vectors die
+        check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+      }
       check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
       e->on_device = true;
     } catch (...) {
@@ -369,7 +387,6 @@ int qts_shap_values(const qts_ensemble* ens, const float* X, int64_t M, int64_t 
 int qts_shap_interactions(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
                           const double* leaf_values, void* phi, void* Phi,
                           qts_precision precision, void* stream) {
-  (void)leaf_values; (void)phi; (void)stream;
   return guarded([&] {
     if (!ens) fail(QTS_E_INVALID_ARG, "null ensemble");
     if (precision != QTS_FP32 && precision != QTS_FP64)
@@ -378,7 +395,22 @@ int qts_shap_interactions(const qts_ensemble* ens, const float* X, int64_t M, in
     if (M > 0 && !Phi) fail(QTS_E_INVALID_ARG, "null Phi");
     require_device(ens);
     if (M == 0) return;
-    fail(QTS_E_UNSUPPORTED, "interactions are not available in this build");
+    const HostTable& h = ens->host;
+    const DeviceTable& d = ens->dev;
+    hipStream_t s = (hipStream_t)stream;
+    const bool fp64 = precision == QTS_FP64;
+    const int64_t F = h.F;
+    const int64_t ntri = F * (F - 1) / 2;
+    const double* leaf = leaf_values ? leaf_values : d.leaf_val;
+    Scratch acc(sizeof(double) * (size_t)(M * ntri + M * F), s);
+    double* tri64 = (double*)acc.p;
+    double* phi64 = tri64 + M * ntri;
+    launch_fill_zero(tri64, M * ntri + M * F, s);
+    TimedScope ts(1, s);
+    for (const PairClass& pc : ens->pair_classes)
+      launch_pairs(h, d, pc, fp64, X, M, ldx, leaf, tri64, phi64, s);
+    ts.done();
+    launch_pairs_finalize(tri64, phi64, M, (int)F, fp64, Phi, phi, s);
   });
 }
 

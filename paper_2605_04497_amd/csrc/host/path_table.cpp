@@ -227,3 +227,70 @@ HostTable build_host_table(const qts_tree_arrays& t, int32_t F, double base_scor
 }
 
 }  // namespace qts
+
+namespace qts {
+
+PairTable build_pair_table(const HostTable& h) {
+  PairTable pt;
+  const size_t n = h.hdr.size();
+  std::vector<size_t> order(n);
+  for (size_t i = 0; i < n; ++i) order[i] = i;
+  // capacities of the interactions kernel instances
+  auto cap_of = [](int d) {
+    static const int caps[] = {4, 8, 12, 16, 20, 24, 28, 32, 36, 40, 48, 64};
+    for (int c : caps)
+      if (d <= c) return c;
+    return 64;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+    const int cx = cap_of(h.hdr[x].d), cy = cap_of(h.hdr[y].d);
+    if (cx != cy) return cx < cy;
+    return h.hdr[x].d < h.hdr[y].d;
+  });
+  // class boundaries
+  size_t i = 0;
+  int64_t el = 0;
+  while (i < n) {
+    const int cap = cap_of(h.hdr[order[i]].d);
+    size_t j = i;
+    while (j < n && cap_of(h.hdr[order[j]].d) == cap) ++j;
+    pt.classes.push_back(PairClass{cap, (int32_t)(j - i), el, (int32_t)i});
+    el += (int64_t)cap * (int64_t)(j - i);
+    i = j;
+  }
+  if (el > (int64_t)std::numeric_limits<int32_t>::max())
+    fail(QTS_E_UNSUPPORTED, "pair table too large");
+  pt.d.resize(n);
+  pt.leaf.resize(n);
+  pt.feat.assign((size_t)el, kMissingOkBit);
+  pt.lo.assign((size_t)el, -std::numeric_limits<float>::infinity());
+  pt.hi.assign((size_t)el, std::numeric_limits<float>::quiet_NaN());
+  pt.b.assign((size_t)el, 1.0);
+  pt.cb.assign((size_t)el, 0.0);
+  std::vector<int> idx;
+  for (const PairClass& c : pt.classes) {
+    for (int32_t q = 0; q < c.np; ++q) {
+      const PathHdr& p = h.hdr[order[(size_t)c.pbase + (size_t)q]];
+      pt.d[(size_t)c.pbase + (size_t)q] = p.d;
+      pt.leaf[(size_t)c.pbase + (size_t)q] = p.leaf;
+      idx.resize((size_t)p.d);
+      for (int k = 0; k < p.d; ++k) idx[(size_t)k] = k;
+      std::sort(idx.begin(), idx.end(), [&](int x, int y) {
+        return (h.feat[(size_t)p.off + (size_t)x] & kFeatureMask) <
+               (h.feat[(size_t)p.off + (size_t)y] & kFeatureMask);
+      });
+      for (int k = 0; k < p.d; ++k) {
+        const size_t src = (size_t)p.off + (size_t)idx[(size_t)k];
+        const size_t dst = (size_t)c.base + (size_t)k * (size_t)c.np + (size_t)q;
+        pt.feat[dst] = h.feat[src];
+        pt.lo[dst] = h.lo[src];
+        pt.hi[dst] = h.hi[src];
+        pt.b[dst] = h.b[src];
+        pt.cb[dst] = h.cb[src];
+      }
+    }
+  }
+  return pt;
+}
+
+}  // namespace qts

@@ -26,6 +26,16 @@ struct DeviceTable {
   double* b64 = nullptr;
   double* cb64 = nullptr;
   double* leaf_val = nullptr;  // the model's own leaf values
+  // slot-major pair table (interactions)
+  int32_t* pr_d = nullptr;
+  int32_t* pr_leaf = nullptr;
+  int32_t* pr_feat = nullptr;
+  float* pr_lo = nullptr;
+  float* pr_hi = nullptr;
+  float* pr_b32 = nullptr;
+  float* pr_cb32 = nullptr;
+  double* pr_b64 = nullptr;
+  double* pr_cb64 = nullptr;
   NodeConsts<float> n32;
   NodeConsts<double> n64;
 };
@@ -64,6 +74,15 @@ void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s
 void launch_values(const HostTable& h, const DeviceTable& d, const Bucket& bk, bool fp64,
                    const float* X, int64_t M, int64_t ldx, const double* leaf_val,
                    double* acc, const ValuesShape& shape, hipStream_t s);
+
+// Interactions: accumulate the FP64 pair triangle [M][F(F-1)/2] and phi [M][F]
+// (both pre-zeroed) over the paths of one capacity class.
+void launch_pairs(const HostTable& h, const DeviceTable& d, const PairClass& pc, bool fp64,
+                  const float* X, int64_t M, int64_t ldx, const double* leaf_val, double* tri64,
+                  double* phi64, hipStream_t s);
+// Phi[M][F][F] (and phi[M][F] when non-null) in FP32 or FP64 from the accumulators.
+void launch_pairs_finalize(const double* tri64, const double* phi64, int64_t M, int F, bool fp64,
+                           void* Phi, void* phi, hipStream_t s);
 
 void check_hip(hipError_t e, const char* what);
 

@@ -61,6 +61,29 @@ struct HostTable {
 
 HostTable build_host_table(const qts_tree_arrays& t, int32_t n_features, double base_score);
 
+// Path table for the interactions kernel: paths grouped by capacity class
+// (4, 8, ..., 40, 48, 64 slots: the kernel instances), sorted by length
+// inside a class, features sorted ascending inside a path, stored slot-major
+// ([slot][path] within a class) so one lane per path reads coalesced.  Slots
+// past a path's end are inert (feature 0, no bounds, missing_ok, b = 1,
+// 1-b = 0).
+struct PairClass {
+  int32_t cap;    // slots per path
+  int32_t np;     // paths in the class
+  int64_t base;   // first element of the class (slot-major block of cap * np)
+  int32_t pbase;  // first path of the class in the per-path arrays
+};
+
+struct PairTable {
+  std::vector<PairClass> classes;
+  std::vector<int32_t> d, leaf;          // per path
+  std::vector<int32_t> feat;             // packed: feature | missing_ok bit
+  std::vector<float> lo, hi;
+  std::vector<double> b, cb;
+};
+
+PairTable build_pair_table(const HostTable& h);
+
 // Golub-Welsch: n-node Gauss-Legendre rule on [0,1] in FP64.
 void gauss_legendre(int n, double* t, double* one_minus_t, double* w);
 

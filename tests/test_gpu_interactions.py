@@ -1,0 +1,114 @@
+"""GPU parity of qts_shap_interactions (Phi[M,F,F], and phi) against the FP64
+oracle's 8-node pair indices, with the convention Phi_ik = SII_ik / 2 (i != k)
+and Phi_ii = phi_i - sum_{k != i} Phi_ik."""
+import functools
+
+import numpy as np
+import pytest
+
+import synth
+from tests.parity import check, row_normwise
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def q():
+    import paper_2605_04497_amd as q
+    return q
+
+
+def _run(q, ens, X, precision, leaf_values=None):
+    e = q.Ensemble(ens)
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    lv = None if leaf_values is None else torch.from_numpy(leaf_values).cuda()
+    Phi, phi = e.shap_interactions(Xd, precision, leaf_values=lv, with_phi=True)
+    torch.cuda.synchronize()
+    return Phi.cpu().numpy().astype(np.float64), phi.cpu().numpy().astype(np.float64), e
+
+
+CASES = [
+    ("c1_small", dict(M=70)),
+    ("c3_interactions", dict(T=4, M=20, n_train=20000)),   # F=200, depths 3..20
+    ("c4_adjoint", dict(T=10, M=70, n_train=20000)),
+    ("c5_deep", dict(T=3, M=12, n_train=30000)),           # long paths: generic kernel
+]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("name,over", CASES, ids=[c[0] for c in CASES])
+def test_interactions_match_oracle(q, oracle_mod, name, over, precision):
+    print("case", name, over, precision, flush=True)
+    wl = synth.make_workload(name, **over)
+    Phi, phi, e = _run(q, wl.ensemble, wl.X, precision)
+    phi_o, Phi_o = oracle_mod.shap_interactions(wl.ensemble, wl.X, n=8)
+    check(Phi, Phi_o, precision, name + " Phi")
+    check(phi, phi_o, precision, name + " phi")
+    np.testing.assert_array_equal(Phi, np.transpose(Phi, (0, 2, 1)))  # symmetric by construction
+    tol = 1e-5 if precision == "fp32" else 1e-10
+    scale = np.maximum(np.abs(phi_o).max(1, keepdims=True), 1e-30)
+    assert np.all(np.abs(Phi.sum(2) - phi) <= tol * scale)            # rows sum to phi
+
+
+def test_c1_pairs_match_enumeration(q):
+    """Pair indices from the GPU vs subset enumeration of the Shapley
+    interaction index definition (F = 8, exact at d <= 4)."""
+    from oracle import brute
+    wl = synth.make_workload("c1_small", M=10)
+    Phi, phi, _ = _run(q, wl.ensemble, wl.X, "fp64")
+    sii = brute.shap_sii(wl.ensemble, wl.X)
+    off = ~np.eye(wl.ensemble.n_features, dtype=bool)
+    assert row_normwise(2 * Phi * off, sii) <= 1e-10
+    assert row_normwise(phi, brute.shap_values(wl.ensemble, wl.X)) <= 1e-10
+
+
+def test_interactions_phi_matches_values_kernel(q):
+    wl = synth.make_workload("c2_values", T=20, M=100, n_train=20000)
+    e = q.Ensemble(wl.ensemble)
+    X = torch.from_numpy(wl.X).cuda()
+    for precision in ("fp32", "fp64"):
+        _, phi = e.shap_interactions(X, precision, with_phi=True)
+        phi2 = e.shap_values(X, precision)
+        assert row_normwise(phi.double().cpu().numpy(), phi2.double().cpu().numpy()) <= (
+            2e-6 if precision == "fp32" else 1e-12)
+
+
+def test_interactions_edge_cases(q, oracle_mod):
+    # zero covers (paths whose factor vanishes), repeated features, NaN rows
+    for seed in range(3):
+        rng = np.random.default_rng(400 + seed)
+        ens = synth.random_small_ensemble(rng, 5, 9, 7, zero_cover=True)
+        X = (np.round(rng.standard_normal((67, 9)) * 2) / 2).astype(np.float32)
+        X[::5, 3] = np.nan
+        X[7, :] = np.nan
+        phi_o, Phi_o = oracle_mod.shap_interactions(ens, X, n=8)
+        for precision in ("fp32", "fp64"):
+            Phi, phi, _ = _run(q, ens, X, precision)
+            check(Phi, Phi_o, precision, "zero covers Phi")
+            check(phi, phi_o, precision, "zero covers phi")
+    # leaf-value override, M = 1 and M = 0
+    wl = synth.make_workload("c4_adjoint", T=4, M=9, n_train=5000)
+    v = np.random.default_rng(2).normal(size=wl.ensemble.n_leaves())
+    phi_o, Phi_o = oracle_mod.shap_interactions(wl.ensemble.with_leaf_values(v), wl.X)
+    for precision in ("fp32", "fp64"):
+        Phi, _, _ = _run(q, wl.ensemble, wl.X, precision, leaf_values=v)
+        check(Phi, Phi_o, precision, "leaf override")
+        Phi1, _, _ = _run(q, wl.ensemble, wl.X[4:5], precision, leaf_values=v)
+        check(Phi1, Phi_o[4:5], precision, "M=1")
+    e = q.Ensemble(wl.ensemble)
+    out = e.shap_interactions(torch.zeros((0, wl.ensemble.n_features), device="cuda"))
+    assert out.shape == (0, wl.ensemble.n_features, wl.ensemble.n_features)
+
+
+@pytest.mark.parametrize("d", [3, 12, 13, 24, 25, 40, 41, 48, 64])
+def test_interaction_capacity_classes(q, oracle_mod, d):
+    """A chain of d features covers each capacity class boundary, including the
+    long-path (generic) classes."""
+    from tests.test_gpu_values import chain_model, chain_rows
+    ens, X = chain_model(d), chain_rows(d)
+    phi_o, Phi_o = oracle_mod.shap_interactions(ens, X, n=8)
+    for precision in ("fp32", "fp64"):
+        Phi, phi, _ = _run(q, ens, X, precision)
+        check(Phi, Phi_o, precision, "chain d=%d" % d)
