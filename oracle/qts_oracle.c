@@ -126,15 +126,24 @@ static int collapse(const edge_t* e, int ne, int32_t* fu, double* b, double* o) 
 typedef void (*leaf_fn)(void* ctx, const int32_t* fu, const double* b, const double* o,
                         int d, double val, int64_t leaf_ord);
 
+/* Leaves are numbered in tree-major node-id order (the order of the model's
+ * leaf values): the ordinal of a leaf is the number of leaf nodes with a
+ * smaller id in its tree. */
+static int64_t leaf_ordinal(const orc_model* m, int64_t base, int32_t node) {
+  int64_t k = 0;
+  for (int64_t g = base; g < base + node; ++g) k += (m->left[g] < 0);
+  return k;
+}
+
 static void walk(const orc_model* m, int64_t base, int32_t node, const float* x,
                  edge_t* path, int depth, void* ctx, leaf_fn fn, int64_t* leaf_ord) {
   int64_t g = base + node;
+  (void)leaf_ord;
   if (m->left[g] < 0) {
     int32_t fu[ORC_MAX_DEPTH];
     double b[ORC_MAX_DEPTH], o[ORC_MAX_DEPTH];
     int d = collapse(path, depth, fu, b, o);
-    fn(ctx, fu, b, o, d, m->value[g], *leaf_ord);
-    ++*leaf_ord;
+    fn(ctx, fu, b, o, d, m->value[g], leaf_ordinal(m, base, node));
     return;
   }
   int32_t f = m->feature[g];

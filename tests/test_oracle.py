@@ -244,14 +244,26 @@ def test_duplicated_subtrees_make_a_dummy(oracle_mod):
     np.testing.assert_allclose(Phi[:, 0, :], 0.0, atol=1e-15)
 
 
-def test_leaf_gradient_is_transposed_jacobian(oracle_mod):
+@pytest.mark.parametrize("layout", ["depth_first", "breadth_first", "grown"])
+def test_leaf_gradient_is_transposed_jacobian(oracle_mod, layout):
     """phi is linear in the leaf values, so its Jacobian column for a leaf is
     phi of the model with that leaf set to 1 and all others 0; compare
-    J^T G against that, column by column, from subset enumeration."""
+    J^T G against that, column by column, from subset enumeration.  Leaves are
+    indexed in tree-major node-id order; the three layouts number nodes
+    depth-first, breadth-first with leaves at several depths, and depth-first
+    bigger-child-first, so node-id order and visit order differ."""
     rng = np.random.default_rng(11)
-    ens = synth.random_small_ensemble(rng, 2, 4, 3)
-    X = (np.round(rng.standard_normal((3, 4)) * 2) / 2).astype(np.float32)
-    G = rng.normal(size=(3, 4))
+    if layout == "depth_first":
+        ens = synth.random_small_ensemble(rng, 2, 4, 3)
+    elif layout == "breadth_first":
+        ens = synth.make_workload("c2_values", T=2, M=1, n_train=300, F=5, depth=4).ensemble
+        assert ens.n_leaves() < 2 * 16  # some leaves above the last level
+    else:
+        ens = synth.make_workload("c5_deep", T=2, M=1, n_train=400, F=5, depth=4,
+                                  leaf_cap=9).ensemble
+    F = ens.n_features
+    X = (np.round(rng.standard_normal((3, F)) * 2) / 2).astype(np.float32)
+    G = rng.normal(size=(3, F))
     L = ens.n_leaves()
     want = np.zeros(L)
     for leaf in range(L):

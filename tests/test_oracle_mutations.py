@@ -34,6 +34,7 @@ MUTATIONS = {
     "ties_go_left": ("return xv < m->threshold[g];", "return xv <= m->threshold[g];"),
     "nan_wrong_direction": ("return m->default_left[g] != 0;", "return m->default_left[g] == 0;"),
     "edge_weight_of_parent": ("return m->cover[child] / cp;", "return m->cover[child] / (cp + 1.0);"),
+    "leaf_ordinal_in_visit_order": ("leaf_ordinal(m, base, node));", "(*leaf_ord)++);"),
 }
 
 
@@ -72,6 +73,17 @@ def _pins_pass() -> bool:
                 J[leaf] = np.sum(G * brute.shap_values(ens.with_leaf_values(e), X))
             if not np.allclose(O.leaf_grad(ens, X, G), J, atol=1e-12):
                 return False
+        # leaf order on a breadth-first tree with leaves at several depths
+        ens = synth.make_workload("c2_values", T=2, M=1, n_train=300, F=5, depth=4).ensemble
+        X = np.random.default_rng(8).standard_normal((3, 5)).astype(np.float32)
+        G = np.random.default_rng(9).normal(size=(3, 5))
+        J = np.zeros(ens.n_leaves())
+        for leaf in range(ens.n_leaves()):
+            e = np.zeros(ens.n_leaves())
+            e[leaf] = 1.0
+            J[leaf] = np.sum(G * brute.shap_values(ens.with_leaf_values(e), X))
+        if not np.allclose(O.leaf_grad(ens, X, G), J, atol=1e-12):
+            return False
         return True
     except (RuntimeError, ValueError, FloatingPointError):
         return False
