@@ -417,7 +417,6 @@ int qts_shap_interactions(const qts_ensemble* ens, const float* X, int64_t M, in
 int qts_shap_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
                       const void* grad_phi, double* grad_leaf, qts_precision precision,
                       void* stream) {
-  (void)stream;
   return guarded([&] {
     if (!ens) fail(QTS_E_INVALID_ARG, "null ensemble");
     if (precision != QTS_FP32 && precision != QTS_FP64)
@@ -426,7 +425,17 @@ int qts_shap_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_
     if (!grad_leaf) fail(QTS_E_INVALID_ARG, "null grad_leaf");
     if (M > 0 && !grad_phi) fail(QTS_E_INVALID_ARG, "null grad_phi");
     require_device(ens);
-    fail(QTS_E_UNSUPPORTED, "backward is not available in this build");
+    const HostTable& h = ens->host;
+    const DeviceTable& d = ens->dev;
+    hipStream_t s = (hipStream_t)stream;
+    const bool fp64 = precision == QTS_FP64;
+    launch_fill_zero(grad_leaf, (int64_t)h.leaf_value.size(), s);
+    if (M == 0) return;
+    TimedScope ts(2, s);
+    for (const Bucket& bk : h.buckets)
+      launch_adjoint(h, d, bk, fp64, X, grad_phi, M, ldx, grad_leaf,
+                     ens->vshape[fp64 ? 1 : 0][cap_index(bk.dmax)], s);
+    ts.done();
   });
 }
 

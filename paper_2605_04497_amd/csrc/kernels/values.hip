@@ -54,17 +54,24 @@ __device__ __forceinline__ double to_vgpr(double v) {
 
 // The path loop of one workgroup.  NANS: the tile holds a NaN, so the
 // missing-value rule is evaluated; otherwise plain interval tests suffice.
-template <typename T, int DMAX, int NH, bool STORE_G, bool NANS>
+// ADJ: adjoint mode.  phi is linear in the leaf value, so d phi[s, f_j] /
+// d val = c_j LOO_j; instead of scattering val c_j LOO_j into the phi tile,
+// each lane gathers g[s, f_j] c_j LOO_j from the upstream-gradient tile gs,
+// the wave sums its 64 samples in FP64 and adds the result to grad_leaf.
+template <typename T, int DMAX, int NH, bool STORE_G, bool NANS, bool ADJ>
 __device__ __forceinline__ void values_paths(
     const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
     const float* __restrict__ lo, const float* __restrict__ hi, const T* __restrict__ bb,
     const T* __restrict__ cbb, const double* __restrict__ leaf_val, const float* xs, double* as,
-    int pb, int pe, int wave, int nw, int lane, const T* tv, const NodeConsts<T>& nc) {
+    const T* gs, double* __restrict__ grad_leaf, int pb, int pe, int wave, int nw, int lane,
+    const T* tv, const NodeConsts<T>& nc) {
   constexpr int NB = DMAX / 8;  // feature batches
   for (int p = pb + wave; p < pe; p += nw) {
     const int d = ldu(&hdr[p].d);
     const int off = ldu(&hdr[p].off);
-    const T val = (T)ldu(leaf_val + ldu(&hdr[p].leaf));
+    const int leaf = ldu(&hdr[p].leaf);
+    const T val = ADJ ? T(1) : (T)ldu(leaf_val + leaf);
+    double gacc = 0.0;
     const int nb = (d + 7) >> 3;  // batches in use; slots [d, 8 nb) are inert
 
     // c_j per slot, eight slots per batch
@@ -159,9 +166,13 @@ __device__ __forceinline__ void values_paths(
 #pragma unroll
               for (int m = 1; m < NH; ++m) dot = fmaT(Pb[k][m], S[m], dot);
               const int f = ldu(feat + off + j) & kFeatureMask;
-              const double c = (double)(val * cf[j] * dot);
-              __hip_atomic_fetch_add(&as[f * kTileStride + lane], c, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+              if (ADJ) {
+                gacc += (double)(gs[f * kTileStride + lane] * cf[j] * dot);
+              } else {
+                const double c = (double)(val * cf[j] * dot);
+                __hip_atomic_fetch_add(&as[f * kTileStride + lane], c, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+              }
             }
             if (j > 0) {
 #pragma unroll
@@ -173,6 +184,11 @@ __device__ __forceinline__ void values_paths(
           }
         }
       }
+    }
+    if (ADJ) {
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) gacc += __shfl_xor(gacc, o, 64);
+      if (lane == 0 && gacc != 0.0) unsafeAtomicAdd(&grad_leaf[leaf], gacc);
     }
   }
 }
@@ -225,11 +241,13 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
   for (int m = 0; m < kNodes; ++m) tv[m] = to_vgpr(nc.t[m]);
 
   if (any_nan)
-    values_paths<T, DMAX, NH, STORE_G, true>(hdr, feat, lo, hi, bb, cbb, leaf_val, xs, as, pb,
-                                             pe, wave, nw, lane, tv, nc);
+    values_paths<T, DMAX, NH, STORE_G, true, false>(hdr, feat, lo, hi, bb, cbb, leaf_val, xs,
+                                                    as, nullptr, nullptr, pb, pe, wave, nw, lane,
+                                                    tv, nc);
   else
-    values_paths<T, DMAX, NH, STORE_G, false>(hdr, feat, lo, hi, bb, cbb, leaf_val, xs, as, pb,
-                                              pe, wave, nw, lane, tv, nc);
+    values_paths<T, DMAX, NH, STORE_G, false, false>(hdr, feat, lo, hi, bb, cbb, leaf_val, xs,
+                                                     as, nullptr, nullptr, pb, pe, wave, nw, lane,
+                                                     tv, nc);
   __syncthreads();
 
   // flush: consecutive threads take consecutive features of one sample
@@ -244,7 +262,86 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
   }
 }
 
+// Adjoint to the leaf values (same tiling as values_kernel): the tile holds
+// the samples' rows and their upstream gradient rows g[s, :].
+template <typename T, int DMAX, int NH, bool STORE_G>
+__global__ void __launch_bounds__(512)
+adjoint_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
+               const float* __restrict__ lo, const float* __restrict__ hi,
+               const T* __restrict__ bb, const T* __restrict__ cbb, const float* __restrict__ X,
+               const T* __restrict__ G, int64_t M, int64_t ldx, int32_t F, int32_t path_begin,
+               int32_t path_end, int32_t chunk, int32_t nsb, double* __restrict__ grad_leaf,
+               NodeConsts<T> nc) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  float* xs = reinterpret_cast<float*>(smem);
+  size_t xs_bytes = ((size_t)F * kTileStride * sizeof(float) + 15) & ~(size_t)15;
+  T* gs = reinterpret_cast<T*>(smem + xs_bytes);
+
+  const int item = blockIdx.x;
+  const int sb = item % nsb;
+  const int ch = item / nsb;
+  const int64_t s0 = (int64_t)sb * kSamplesPerBlock;
+  const int p0 = path_begin + ch * chunk;
+  const int p1 = min(path_end, p0 + chunk);
+
+  // stage the sample rows and gradient rows transposed (padding rows get a
+  // zero gradient, so they add nothing); note any NaN
+  const int tile = kSamplesPerBlock * F;
+  int nan_seen = 0;
+  for (int i = threadIdx.x; i < tile; i += blockDim.x) {
+    const int r = i / F;
+    const int f = i - r * F;
+    const int64_t s = s0 + r;
+    const float v = (s < M) ? X[s * ldx + f] : 0.0f;
+    nan_seen |= (v != v);
+    xs[f * kTileStride + r] = v;
+    gs[f * kTileStride + r] = (s < M) ? G[s * F + f] : T(0);
+  }
+  const bool any_nan = __syncthreads_or(nan_seen) != 0;
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nw = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
+  const int pb = __builtin_amdgcn_readfirstlane(p0);
+  const int pe = __builtin_amdgcn_readfirstlane(p1);
+  T tv[kNodes];
+#pragma unroll
+  for (int m = 0; m < kNodes; ++m) tv[m] = to_vgpr(nc.t[m]);
+  if (any_nan)
+    values_paths<T, DMAX, NH, STORE_G, true, true>(hdr, feat, lo, hi, bb, cbb, nullptr, xs,
+                                                   nullptr, gs, grad_leaf, pb, pe, wave, nw,
+                                                   lane, tv, nc);
+  else
+    values_paths<T, DMAX, NH, STORE_G, false, true>(hdr, feat, lo, hi, bb, cbb, nullptr, xs,
+                                                    nullptr, gs, grad_leaf, pb, pe, wave, nw,
+                                                    lane, tv, nc);
+}
+
 namespace {
+
+// Paths per work item: about 32 rounds of the ~512 resident workgroups
+// (small tail), chunks of at least 256 paths so the per-item tile load and
+// flush stay small next to the path work.
+int values_chunk(int n_paths, int nsb, int requested) {
+  if (requested > 0) return requested;
+  const int64_t want_items = 32 * 512;
+  int64_t n_chunks = (want_items + nsb - 1) / nsb;
+  n_chunks = std::max<int64_t>(1, std::min<int64_t>(n_chunks, (n_paths + 255) / 256));
+  return (int)((n_paths + n_chunks - 1) / n_chunks);
+}
+
+// Raise a kernel's dynamic-LDS limit once; returns the usable bytes.
+size_t values_lds_limit(const void* fn, size_t* cache) {
+  if (*cache == 0) {
+    hipFuncAttributes fa;
+    check_hip(hipFuncGetAttributes(&fa, fn), "hipFuncGetAttributes");
+    const size_t limit = (size_t)kMaxLdsBytes - fa.sharedSizeBytes;
+    check_hip(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)limit),
+              "hipFuncSetAttribute");
+    *cache = limit;
+  }
+  return *cache;
+}
 
 template <typename T, int DMAX, int NH, bool STORE_G>
 void launch_one(const HostTable& h, const DeviceTable& d, const Bucket& bk, const float* X,
@@ -253,16 +350,7 @@ void launch_one(const HostTable& h, const DeviceTable& d, const Bucket& bk, cons
   const int F = h.F;
   const int nsb = (int)((M + kSamplesPerBlock - 1) / kSamplesPerBlock);
   const int n_paths = bk.path_end - bk.path_begin;
-  int chunk = shape.chunk;
-  if (chunk <= 0) {
-    // about 32 rounds of the ~512 resident workgroups (small tail), with
-    // chunks of at least 256 paths so the per-item tile load and flush stay
-    // small next to the path work
-    const int64_t want_items = 32 * 512;
-    int64_t n_chunks = (want_items + nsb - 1) / nsb;
-    n_chunks = std::max<int64_t>(1, std::min<int64_t>(n_chunks, (n_paths + 255) / 256));
-    chunk = (int)((n_paths + n_chunks - 1) / n_chunks);
-  }
+  const int chunk = values_chunk(n_paths, nsb, shape.chunk);
   const int n_chunks = (n_paths + chunk - 1) / chunk;
   const int64_t grid = (int64_t)nsb * n_chunks;
   if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "grid too large");
@@ -272,27 +360,63 @@ void launch_one(const HostTable& h, const DeviceTable& d, const Bucket& bk, cons
   const T* cb = std::is_same<T, float>::value ? (const T*)d.cb32 : (const T*)d.cb64;
   NodeConsts<T> nc;
   if constexpr (std::is_same<T, float>::value) nc = d.n32; else nc = d.n64;
-  // raise the dynamic-LDS limit once per instance (default 64 KiB); the
-  // kernel's static LDS (the block-wide vote) shares the CU's 160 KiB
-  static size_t lds_limit = 0;
-  if (lds_limit == 0) {
-    hipFuncAttributes fa;
-    check_hip(hipFuncGetAttributes(&fa, (const void*)values_kernel<T, DMAX, NH, STORE_G>),
-              "hipFuncGetAttributes");
-    const size_t limit = (size_t)kMaxLdsBytes - fa.sharedSizeBytes;
-    check_hip(hipFuncSetAttribute((const void*)values_kernel<T, DMAX, NH, STORE_G>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)limit),
-              "hipFuncSetAttribute");
-    lds_limit = limit;
-  }
-  if (lds > lds_limit) fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
+  static size_t cache = 0;
+  if (lds > values_lds_limit((const void*)values_kernel<T, DMAX, NH, STORE_G>, &cache))
+    fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
   hipLaunchKernelGGL((values_kernel<T, DMAX, NH, STORE_G>), dim3((unsigned)grid),
                      dim3(threads), lds, s, d.hdr, d.feat, d.lo, d.hi, b, cb, leaf_val, X, M,
                      ldx, F, bk.path_begin, bk.path_end, chunk, nsb, acc, nc);
   check_hip(hipGetLastError(), "values_kernel launch");
 }
 
+template <typename T, int DMAX, int NH, bool STORE_G>
+void launch_adj_one(const HostTable& h, const DeviceTable& d, const Bucket& bk, const float* X,
+                    const void* G, int64_t M, int64_t ldx, double* grad_leaf,
+                    const ValuesShape& shape, hipStream_t s) {
+  const int F = h.F;
+  const int nsb = (int)((M + kSamplesPerBlock - 1) / kSamplesPerBlock);
+  const int n_paths = bk.path_end - bk.path_begin;
+  const int chunk = values_chunk(n_paths, nsb, shape.chunk);
+  const int n_chunks = (n_paths + chunk - 1) / chunk;
+  const int64_t grid = (int64_t)nsb * n_chunks;
+  if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "grid too large");
+  size_t xs = ((size_t)F * kTileStride * sizeof(float) + 15) & ~(size_t)15;
+  const size_t lds = xs + (size_t)F * kTileStride * sizeof(T);
+  const int threads = 64 * shape.waves_per_block;
+  const T* b = std::is_same<T, float>::value ? (const T*)d.b32 : (const T*)d.b64;
+  const T* cb = std::is_same<T, float>::value ? (const T*)d.cb32 : (const T*)d.cb64;
+  NodeConsts<T> nc;
+  if constexpr (std::is_same<T, float>::value) nc = d.n32; else nc = d.n64;
+  static size_t cache = 0;
+  if (lds > values_lds_limit((const void*)adjoint_kernel<T, DMAX, NH, STORE_G>, &cache))
+    fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
+  hipLaunchKernelGGL((adjoint_kernel<T, DMAX, NH, STORE_G>), dim3((unsigned)grid),
+                     dim3(threads), lds, s, d.hdr, d.feat, d.lo, d.hi, b, cb, X, (const T*)G, M,
+                     ldx, F, bk.path_begin, bk.path_end, chunk, nsb, grad_leaf, nc);
+  check_hip(hipGetLastError(), "adjoint_kernel launch");
+}
+
 }  // namespace
+
+void launch_adjoint(const HostTable& h, const DeviceTable& d, const Bucket& bk, bool fp64,
+                    const float* X, const void* G, int64_t M, int64_t ldx, double* grad_leaf,
+                    const ValuesShape& shape, hipStream_t s) {
+  if (!fp64) {
+    switch (bk.dmax) {
+      case 8: launch_adj_one<float, 8, 8, true>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      case 16: launch_adj_one<float, 16, 8, true>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      case 32: launch_adj_one<float, 32, 8, false>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      default: launch_adj_one<float, 64, 4, false>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+    }
+  } else {
+    switch (bk.dmax) {
+      case 8: launch_adj_one<double, 8, 8, false>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      case 16: launch_adj_one<double, 16, 4, false>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      case 32: launch_adj_one<double, 32, 4, false>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      default: launch_adj_one<double, 64, 2, false>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+    }
+  }
+}
 
 void launch_values(const HostTable& h, const DeviceTable& d, const Bucket& bk, bool fp64,
                    const float* X, int64_t M, int64_t ldx, const double* leaf_val, double* acc,
