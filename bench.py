@@ -36,6 +36,14 @@ PEAK_HBM_GBS = 8000.0
 FLOPS_PER_ELEMENT = 51  # per (sample, path, unique feature): 8 nodes x 6 + 3
 
 
+def pair_flops(d):
+    """Algorithmic flops of one (sample, path) in the interactions kernel: per
+    node, d factors (FMA), d-1 products, d reciprocals, d scalings into r and
+    g, d additions into phi, and d(d-1)/2 pair FMAs."""
+    d = np.asarray(d, np.float64)
+    return 8.0 * (2 * d + (d - 1) + 4 * d + d * (d - 1))
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -51,15 +59,21 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check-rows", type=int, default=16)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the interactions and adjoint measurements")
+    ap.add_argument("--pair-samples", type=int, default=1024)
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="first run a plain device-to-device copy of this many MB (a "
+                         "known-size reference for the memory counters)")
     return ap.parse_args()
 
 
-def time_steps(fn, steps, warmup, torch):
+def time_steps(fn, steps, warmup, torch, kind="values"):
     import paper_2605_04497_amd as q
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    q.read_kernel_timing("values")  # drop warmup events
+    q.read_kernel_timing(kind)  # drop warmup events
     q.set_kernel_timing(True)
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -72,7 +86,7 @@ def time_steps(fn, steps, warmup, torch):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     q.set_kernel_timing(False)
-    kern_ms, calls = q.read_kernel_timing("values")
+    kern_ms, calls = q.read_kernel_timing(kind)
     return {"ms_per_step": start.elapsed_time(stop) / steps, "wall_s": wall,
             "kernel_ms": kern_ms / max(1, calls), "calls": calls}
 
@@ -105,6 +119,68 @@ def cpu_baseline(ens, X, seconds, oracle):
                       "quadrature, %.1f s, %s" % (rows, dt, cpu)}
 
 
+def measure_interactions(args, torch, q, synth, oracle, dev):
+    """Pairwise interactions on the full 500-tree, 200-feature ensemble (depths
+    3..20), over a slice of its explained samples; FP32 form."""
+    wl = synth.make_workload("c3_interactions", M=args.pair_samples)
+    ens = wl.ensemble
+    e = q.Ensemble(ens, device=dev)
+    X = torch.from_numpy(wl.X).to(dev)
+    M = X.shape[0]
+    tab = e.export_paths()
+    flops = float(M) * float(pair_flops(tab["path_len"]).sum())
+    res = {}
+    for prec in ("fp32", "fp64"):
+        r = time_steps(lambda: e.shap_interactions(X, prec), 3, 1, torch, "interactions")
+        res[prec] = r
+    Phi = e.shap_interactions(X[:2], "fp32").double().cpu().numpy()
+    _, Phi_o = oracle.shap_interactions(ens, wl.X[:2], n=8)
+    err = float((np.abs(Phi - Phi_o).reshape(2, -1).max(1)
+                 / np.abs(Phi_o).reshape(2, -1).max(1)).max())
+    ach = flops / (res["fp32"]["kernel_ms"] * 1e-3) / 1e12
+    out = {"workload": "c3_interactions: 500 grown trees, depths 3..20, leaf cap 4096, 200 "
+                       "features; first %d of the 50k explained samples" % M,
+           "samples": M, "leaves": e.n_leaves, "mean_unique": float(tab["path_len"].mean()),
+           "value": M * e.n_leaves / (res["fp32"]["ms_per_step"] * 1e-3), "unit": "paths/s",
+           "ms_per_step": res["fp32"]["ms_per_step"], "kernel_ms": res["fp32"]["kernel_ms"],
+           "fp64_ms_per_step": res["fp64"]["ms_per_step"],
+           "max_rel_err_fp32": err, "rows_checked": 2,
+           "alu_tflops": ach, "frac_of_valu_peak": ach / PEAK_VALU_TFLOPS}
+    e.close()
+    return out
+
+
+def measure_adjoint(args, torch, q, synth, oracle, dev):
+    """Adjoint to the 12,800 leaf values of 200 full depth-6 trees, 20k samples."""
+    wl = synth.make_workload("c4_adjoint")
+    ens = wl.ensemble
+    e = q.Ensemble(ens, device=dev)
+    X = torch.from_numpy(wl.X).to(dev)
+    M = X.shape[0]
+    G = torch.from_numpy(2.0 * (np.zeros_like(wl.target, dtype=np.float64)
+                                - wl.target.astype(np.float64))).to(dev)
+    G32 = G.float()
+    res = {}
+    for prec, g in (("fp32", G32), ("fp64", G)):
+        res[prec] = time_steps(lambda: e.shap_backward(X, g, prec), 10, 2, torch, "backward")
+    rows = np.arange(0, M, 10)
+    want = oracle.leaf_grad(ens, wl.X[rows], G32.double().cpu().numpy()[rows])
+    got = e.shap_backward(X[torch.from_numpy(rows).to(dev)], G32[torch.from_numpy(rows).to(dev)],
+                          "fp32").cpu().numpy()
+    err = float(np.abs(got - want).max() / np.abs(want).max())
+    flops = FLOPS_PER_ELEMENT * float(M) * e.info["n_elements"]
+    ach = flops / (res["fp32"]["kernel_ms"] * 1e-3) / 1e12
+    out = {"workload": "c4_adjoint: 200 full depth-6 trees (12,800 leaves), 50 features, "
+                       "20k samples, grad of ||phi - target||^2",
+           "value": M * e.n_leaves / (res["fp32"]["ms_per_step"] * 1e-3), "unit": "paths/s",
+           "ms_per_step": res["fp32"]["ms_per_step"], "kernel_ms": res["fp32"]["kernel_ms"],
+           "fp64_ms_per_step": res["fp64"]["ms_per_step"],
+           "max_rel_err_fp32": err, "rows_checked": int(len(rows)),
+           "alu_tflops": ach, "frac_of_valu_peak": ach / PEAK_VALU_TFLOPS}
+    e.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -129,6 +205,15 @@ def main():
         time.perf_counter() - t0, ens.n_trees, ens.n_leaves(), Xh.shape[0]))
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration_mb > 0:
+        n = args.copy_calibration_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 copies of %d MB" % args.copy_calibration_mb)
+        del src, dst
     e = q.Ensemble(ens, device=dev)
     X = torch.from_numpy(Xh).to(dev)
     M = X.shape[0]
@@ -187,6 +272,16 @@ def main():
                      "peak_fp32_packed": PEAK_FP32_PACKED_TFLOPS,
                      "frac_of_packed_peak": achieved / PEAK_FP32_PACKED_TFLOPS},
     }
+    if not args.no_extras:
+        for key, fn in (("interactions", measure_interactions), ("adjoint", measure_adjoint)):
+            try:
+                result[key] = fn(args, torch, q, synth, oracle, dev)
+                log("%s: %.3e paths/s, kernel %.2f ms, err %.2e" % (
+                    key, result[key]["value"], result[key]["kernel_ms"],
+                    result[key]["max_rel_err_fp32"]))
+            except Exception as exc:  # report, keep the headline line
+                result[key] = {"error": repr(exc)}
+                log("%s failed: %r" % (key, exc))
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(ens, Xh, args.cpu_seconds, oracle)
         log("cpu baseline: %.3e paths/s on %d cores" % (result["cpu_baseline"]["value"],

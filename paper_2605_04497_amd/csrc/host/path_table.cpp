@@ -242,10 +242,22 @@ PairTable build_pair_table(const HostTable& h) {
       if (d <= c) return c;
     return 64;
   };
-  std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+  // Inside a class: by length, then by the path's rank among its tree's paths
+  // of that length, then by tree.  Neighbouring paths (one per lane) then come
+  // from different trees, so a wave's lanes rarely add into the same pair
+  // entry at the same time (sibling leaves share most of their features).
+  std::vector<int32_t> rank(n, 0);
+  {
+    std::vector<int32_t> count((size_t)h.n_trees * (kMaxUnique + 1), 0);
+    for (size_t i = 0; i < n; ++i)
+      rank[i] = count[(size_t)h.hdr[i].tree * (kMaxUnique + 1) + (size_t)h.hdr[i].d]++;
+  }
+  std::sort(order.begin(), order.end(), [&](size_t x, size_t y) {
     const int cx = cap_of(h.hdr[x].d), cy = cap_of(h.hdr[y].d);
     if (cx != cy) return cx < cy;
-    return h.hdr[x].d < h.hdr[y].d;
+    if (h.hdr[x].d != h.hdr[y].d) return h.hdr[x].d < h.hdr[y].d;
+    if (rank[x] != rank[y]) return rank[x] < rank[y];
+    return h.hdr[x].tree < h.hdr[y].tree;
   });
   // class boundaries
   size_t i = 0;

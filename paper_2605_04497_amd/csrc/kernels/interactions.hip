@@ -130,18 +130,31 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
           const int fi = feat[(int64_t)i * np + pc] & kFeatureMask;
           if (live)
             __hip_atomic_fetch_add(&phis[fi], ph, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          // pairs (i, k > i) in groups of four: the four values are computed
+          // into separate registers before their atomics issue, so the LDS
+          // queue sees back-to-back atomics instead of one per dependency
+          // chain (inert slots k >= d have r = 0 and are not stored)
 #pragma unroll
-          for (int k = i + 1; k < C; ++k) {
-            if (k < d) {
-              T pr = g[0] * r[k][0];
+          for (int kb = i + 1; kb < C; kb += 4) {
+            T pr[4];
 #pragma unroll
-              for (int m = 1; m < NH; ++m) pr = fmaP(g[m], r[k][m], pr);
-              if (live) {
+            for (int u = 0; u < 4; ++u) {
+              const int k = kb + u;
+              if (k < C) {
+                pr[u] = g[0] * r[k < C ? k : 0][0];
+#pragma unroll
+                for (int m = 1; m < NH; ++m) pr[u] = fmaP(g[m], r[k < C ? k : 0][m], pr[u]);
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int k = kb + u;
+              if (k < C && k < d && live) {
                 if (TRI_LDS)
-                  __hip_atomic_fetch_add(&tris[rb[k] + fi], pr, __ATOMIC_RELAXED,
+                  __hip_atomic_fetch_add(&tris[rb[k < C ? k : 0] + fi], pr[u], __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_WORKGROUP);
                 else
-                  unsafeAtomicAdd(&tri64[s * ntri + rb[k] + fi], (double)pr);
+                  unsafeAtomicAdd(&tri64[s * ntri + rb[k < C ? k : 0] + fi], (double)pr[u]);
               }
             }
           }

@@ -63,7 +63,8 @@ HostTable build_host_table(const qts_tree_arrays& t, int32_t n_features, double 
 
 // Path table for the interactions kernel: paths grouped by capacity class
 // (4, 8, ..., 40, 48, 64 slots: the kernel instances), sorted by length
-// inside a class, features sorted ascending inside a path, stored slot-major
+// inside a class with neighbouring paths taken from different trees,
+// features sorted ascending inside a path, stored slot-major
 // ([slot][path] within a class) so one lane per path reads coalesced.  Slots
 // past a path's end are inert (feature 0, no bounds, missing_ok, b = 1,
 // 1-b = 0).
