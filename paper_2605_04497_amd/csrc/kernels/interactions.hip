@@ -11,17 +11,19 @@
 // the whole path contributes exactly zero: such lanes are masked (their zero
 // factor is replaced by 1 to keep the reciprocals finite).
 //
-// Work mapping (gfx950, wave64): a workgroup owns one explained sample and a
-// chunk of paths of one capacity class; each lane takes one path (the table
-// is slot-major, so a wave's 64 paths load coalesced).  The sample's pair
+// Accumulation.  A workgroup owns one explained sample; the sample's pair
 // triangle (pair i < k at k(k-1)/2 + i; features are sorted inside a path, so
-// f_i < f_k) and its phi row accumulate in LDS with atomics, then flush to the
-// FP64 global accumulators: the sum within a chunk of at most 64k paths is in
-// the kernel precision, the sum across chunks in FP64.  When the FP64 triangle
-// does not fit in LDS (TRI_LDS = false) pairs go straight to the global FP64
-// triangle.  NH < 8 splits the nodes over passes to bound the registers held
-// by r (the node sum is additive).
+// f_i < f_k) and its phi row accumulate in LDS in FP64 and are flushed with
+// FP64 atomics to the global accumulators.  FP64 is the accumulation type
+// for both kernel precisions: besides the precision, gfx950's LDS FP64 atomic
+// add sustains about seven times the lane rate of its FP32 one.  When the
+// triangle does not fit in LDS it is cut into ranges of rows k (the larger
+// feature of the pair), one launch per range; a launch adds only the pairs
+// whose larger feature falls in its range, and phi only in the first one.
 #include <hip/hip_runtime.h>
+
+#include <utility>
+#include <vector>
 
 #include "../qts_device.h"
 
@@ -41,34 +43,69 @@ __device__ __forceinline__ float fmaP<float>(float a, float b, float c) {
 __device__ __forceinline__ float rcpP(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcpP(double x) { return 1.0 / x; }
 
+__device__ __forceinline__ void lds_add(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ int64_t tri_row(int64_t k) { return k * (k - 1) / 2; }
+
+// Zero the LDS accumulators and stage the sample row.
+__device__ __forceinline__ void pairs_prologue(double* phis, double* tris, int64_t ntri_r,
+                                               float* xrow, const float* X, int64_t s,
+                                               int64_t ldx, int F) {
+  for (int i = threadIdx.x; i < F; i += blockDim.x) {
+    xrow[i] = X[s * ldx + i];
+    phis[i] = 0.0;
+  }
+  for (int64_t e = threadIdx.x; e < ntri_r; e += blockDim.x) tris[e] = 0.0;
+  __syncthreads();
+}
+
+// Flush the LDS accumulators of sample s into the global FP64 ones.
+__device__ __forceinline__ void pairs_epilogue(const double* phis, const double* tris,
+                                               int64_t ntri_r, int64_t base, int64_t ntri,
+                                               bool with_phi, int64_t s, int F,
+                                               double* tri64, double* phi64) {
+  __syncthreads();
+  if (with_phi)
+    for (int i = threadIdx.x; i < F; i += blockDim.x) {
+      const double v = phis[i];
+      if (v != 0.0) unsafeAtomicAdd(&phi64[s * F + i], v);
+    }
+  for (int64_t e = threadIdx.x; e < ntri_r; e += blockDim.x) {
+    const double v = tris[e];
+    if (v != 0.0) unsafeAtomicAdd(&tri64[s * ntri + base + e], v);
+  }
+}
+
 }  // namespace
 
-template <typename T, int C, int NH, bool TRI_LDS>
+// Lane-per-path form for short paths (capacity C, register resident).  Each
+// lane takes one path of the class (the table is slot-major, so a wave's 64
+// paths load coalesced).  NH < 8 splits the nodes over passes to bound the
+// registers held by r (the node sum is additive).
+template <typename T, int C, int NH>
 __global__ void __launch_bounds__(512)
 pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
              const int32_t* __restrict__ feat, const float* __restrict__ lo,
              const float* __restrict__ hi, const T* __restrict__ bb, const T* __restrict__ cbb,
              int32_t np, int32_t chunk, const double* __restrict__ leaf_val,
-             const float* __restrict__ X, int64_t M, int64_t ldx, int32_t F,
-             double* __restrict__ tri64, double* __restrict__ phi64, NodeConsts<T> nc) {
+             const float* __restrict__ X, int64_t M, int64_t ldx, int32_t F, int32_t r0,
+             int32_t r1, int32_t with_phi, double* __restrict__ tri64,
+             double* __restrict__ phi64, NodeConsts<T> nc) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int64_t ntri = (int64_t)F * (F - 1) / 2;
-  T* phis = reinterpret_cast<T*>(smem);                 // [F]
-  T* tris = phis + F;                                   // [ntri] when TRI_LDS
-  float* xrow = reinterpret_cast<float*>(tris + (TRI_LDS ? ntri : 0));  // [F]
+  const int64_t ntri = tri_row(F + 1) - F;         // F(F-1)/2
+  const int64_t base0 = tri_row(r0);
+  const int64_t ntri_r = tri_row(r1) - base0;      // rows [r0, r1)
+  double* phis = reinterpret_cast<double*>(smem);  // [F]
+  double* tris = phis + F;                         // [ntri_r]
+  float* xrow = reinterpret_cast<float*>(tris + ntri_r);  // [F]
 
   const int64_t s = (int64_t)blockIdx.x % M;
   const int ch = (int)((int64_t)blockIdx.x / M);
   const int p0 = ch * chunk;
   const int p1 = min(np, p0 + chunk);
-
-  for (int i = threadIdx.x; i < F; i += blockDim.x) {
-    xrow[i] = X[s * ldx + i];
-    phis[i] = T(0);
-  }
-  if (TRI_LDS)
-    for (int64_t e = threadIdx.x; e < ntri; e += blockDim.x) tris[e] = T(0);
-  __syncthreads();
+  pairs_prologue(phis, tris, ntri_r, xrow, X, s, ldx, F);
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -77,8 +114,38 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
     const int p = base + lane;
     const bool valid = p < p1;
     const int pc = valid ? p : p1 - 1;  // clamped index for the loads
-    const int d = valid ? pd[pc] : 0;
-    T val = valid ? (T)leaf_val[pleaf[pc]] : T(0);
+    // every table load of the path issues before the first use, and none is
+    // conditional, so a wave waits for memory once per path instead of once
+    // per slot
+    int fm[C];
+    float lov[C], hiv[C];
+    T bv[C], cbv[C];
+    const int d0 = pd[pc];
+    const int leaf = pleaf[pc];
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int64_t e = (int64_t)j * np + pc;
+      fm[j] = feat[e];
+      lov[j] = lo[e];
+      hiv[j] = hi[e];
+      bv[j] = bb[e];
+      cbv[j] = cbb[e];
+    }
+    const double val0 = leaf_val[leaf];
+    const int d = valid ? d0 : 0;
+    T val = valid ? (T)val0 : T(0);
+    // feature, row offset of its pairs in this launch's triangle rows, and
+    // whether those rows are in range
+    int f[C], rb[C];
+    bool inr[C];
+    float xv[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      f[j] = fm[j] & kFeatureMask;
+      rb[j] = (int)(tri_row(f[j]) - base0);
+      inr[j] = (f[j] >= r0) & (f[j] < r1) & (j < d);
+      xv[j] = xrow[f[j]];
+    }
 
 #pragma unroll
     for (int pass = 0; pass < kNodes / NH; ++pass) {
@@ -87,23 +154,18 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
 #pragma unroll
       for (int m = 0; m < NH; ++m) H[m] = T(1);
       T r[C][NH];
-      int rb[C];
       bool dead = false;
 #pragma unroll
       for (int j = 0; j < C; ++j) {
-        const int64_t e = (int64_t)j * np + pc;
-        const int fm = feat[e];
-        const int f = fm & kFeatureMask;
-        const float x = xrow[f];
-        const bool miss = (fm & kMissingOkBit) != 0;
-        const bool lower = miss ? !(x < lo[e]) : (x >= lo[e]);
-        const bool upper = !(x >= hi[e]);
-        const T b = bb[e];
-        const T c = (lower & upper) ? cbb[e] : -b;
+        const float x = xv[j];
+        const bool miss = (fm[j] & kMissingOkBit) != 0;
+        const bool lower = miss ? !(x < lov[j]) : (x >= lov[j]);
+        const bool upper = !(x >= hiv[j]);
+        const T b = bv[j];
+        const T c = (lower & upper) ? cbv[j] : -b;
         const bool z = (b == T(0)) & (c == T(0));
         dead |= z;
         const T bz = z ? T(1) : b;
-        rb[j] = (f * (f - 1)) >> 1;
 #pragma unroll
         for (int m = 0; m < NH; ++m) {
           const T Fv = fmaP(nc.t[m0 + m], c, bz);
@@ -119,7 +181,7 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
 
 #pragma unroll
       for (int i = 0; i < C; ++i) {
-        if (i < d) {
+        if (i < d && live) {
           T g[NH];
           T ph = T(0);
 #pragma unroll
@@ -127,9 +189,8 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
             g[m] = G[m] * r[i][m];
             ph += g[m];
           }
-          const int fi = feat[(int64_t)i * np + pc] & kFeatureMask;
-          if (live)
-            __hip_atomic_fetch_add(&phis[fi], ph, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          const int fi = f[i];
+          if (with_phi) lds_add(&phis[fi], (double)ph);
           // pairs (i, k > i) in groups of four: the four values are computed
           // into separate registers before their atomics issue, so the LDS
           // queue sees back-to-back atomics instead of one per dependency
@@ -139,62 +200,46 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
             T pr[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-              const int k = kb + u;
-              if (k < C) {
-                pr[u] = g[0] * r[k < C ? k : 0][0];
+              const int k = kb + u < C ? kb + u : 0;
+              pr[u] = g[0] * r[k][0];
 #pragma unroll
-                for (int m = 1; m < NH; ++m) pr[u] = fmaP(g[m], r[k < C ? k : 0][m], pr[u]);
-              }
+              for (int m = 1; m < NH; ++m) pr[u] = fmaP(g[m], r[k][m], pr[u]);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-              const int k = kb + u;
-              if (k < C && k < d && live) {
-                if (TRI_LDS)
-                  __hip_atomic_fetch_add(&tris[rb[k < C ? k : 0] + fi], pr[u], __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_WORKGROUP);
-                else
-                  unsafeAtomicAdd(&tri64[s * ntri + rb[k < C ? k : 0] + fi], (double)pr[u]);
-              }
+              const int k = kb + u < C ? kb + u : 0;
+              if (kb + u < C && inr[k]) lds_add(&tris[rb[k] + fi], (double)pr[u]);
             }
           }
         }
       }
     }
   }
-  __syncthreads();
-
-  for (int i = threadIdx.x; i < F; i += blockDim.x) {
-    const T v = phis[i];
-    if (v != T(0)) unsafeAtomicAdd(&phi64[s * F + i], (double)v);
-  }
-  if (TRI_LDS) {
-    for (int64_t e = threadIdx.x; e < ntri; e += blockDim.x) {
-      const T v = tris[e];
-      if (v != T(0)) unsafeAtomicAdd(&tri64[s * ntri + e], (double)v);
-    }
-  }
+  pairs_epilogue(phis, tris, ntri_r, base0, ntri, with_phi != 0, s, F, tri64, phi64);
 }
 
 // Generic form for long paths (any capacity up to 64): one wavefront per
 // path.  Lane j owns slot j (o_j, c_j, F_j(m), r_j(m) = c_j / F_j(m)); the
 // node products H(m) are reduced across lanes; then the wave's lanes take the
 // d(d-1)/2 pairs of the path in turn, reading r from a per-wave LDS area.
-template <typename T, bool TRI_LDS>
+template <typename T>
 __global__ void __launch_bounds__(256)
 pairs_generic_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
                      const int32_t* __restrict__ feat, const float* __restrict__ lo,
                      const float* __restrict__ hi, const T* __restrict__ bb,
                      const T* __restrict__ cbb, int32_t np, int32_t chunk,
                      const double* __restrict__ leaf_val, const float* __restrict__ X, int64_t M,
-                     int64_t ldx, int32_t F, double* __restrict__ tri64,
-                     double* __restrict__ phi64, NodeConsts<T> nc) {
+                     int64_t ldx, int32_t F, int32_t r0, int32_t r1, int32_t with_phi,
+                     double* __restrict__ tri64, double* __restrict__ phi64,
+                     NodeConsts<T> nc) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int64_t ntri = (int64_t)F * (F - 1) / 2;
+  const int64_t ntri = tri_row(F + 1) - F;
+  const int64_t base0 = tri_row(r0);
+  const int64_t ntri_r = tri_row(r1) - base0;
   const int nw = blockDim.x >> 6;
-  T* phis = reinterpret_cast<T*>(smem);                     // [F]
-  T* tris = phis + F;                                       // [ntri] when TRI_LDS
-  T* rall = tris + (TRI_LDS ? ntri : 0);                    // [nw][64][8]
+  double* phis = reinterpret_cast<double*>(smem);           // [F]
+  double* tris = phis + F;                                  // [ntri_r]
+  T* rall = reinterpret_cast<T*>(tris + ntri_r);            // [nw][64][8]
   int* fall = reinterpret_cast<int*>(rall + (size_t)nw * 64 * kNodes);  // [nw][64]
   float* xrow = reinterpret_cast<float*>(fall + nw * 64);   // [F]
 
@@ -202,13 +247,7 @@ pairs_generic_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__
   const int ch = (int)((int64_t)blockIdx.x / M);
   const int p0 = ch * chunk;
   const int p1 = min(np, p0 + chunk);
-  for (int i = threadIdx.x; i < F; i += blockDim.x) {
-    xrow[i] = X[s * ldx + i];
-    phis[i] = T(0);
-  }
-  if (TRI_LDS)
-    for (int64_t e = threadIdx.x; e < ntri; e += blockDim.x) tris[e] = T(0);
-  __syncthreads();
+  pairs_prologue(phis, tris, ntri_r, xrow, X, s, ldx, F);
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -222,13 +261,14 @@ pairs_generic_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__
     if (lane < d) {
       const int64_t e = (int64_t)lane * np + p;
       const int fm = feat[e];
+      const float lov = lo[e], hiv = hi[e];
+      const T b = bb[e], cb = cbb[e];
       const int f = fm & kFeatureMask;
       const float x = xrow[f];
       const bool miss = (fm & kMissingOkBit) != 0;
-      const bool lower = miss ? !(x < lo[e]) : (x >= lo[e]);
-      const bool upper = !(x >= hi[e]);
-      const T b = bb[e];
-      const T c = (lower & upper) ? cbb[e] : -b;
+      const bool lower = miss ? !(x < lov) : (x >= lov);
+      const bool upper = !(x >= hiv);
+      const T c = (lower & upper) ? cb : -b;
       z = (b == T(0)) & (c == T(0));
       const T bz = z ? T(1) : b;
 #pragma unroll
@@ -254,11 +294,11 @@ pairs_generic_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (lane < d) {
+    if (lane < d && with_phi) {
       T ph = T(0);
 #pragma unroll
       for (int m = 0; m < kNodes; ++m) ph = fmaP(G[m], rw[lane * kNodes + m], ph);
-      __hip_atomic_fetch_add(&phis[fw[lane]], ph, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      lds_add(&phis[fw[lane]], (double)ph);
     }
     const int npair = d * (d - 1) / 2;
     for (int q = lane; q < npair; q += 64) {
@@ -267,34 +307,20 @@ pairs_generic_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__
       while (k * (k - 1) / 2 > q) --k;
       while ((k + 1) * k / 2 <= q) ++k;
       const int i = q - k * (k - 1) / 2;
+      const int fi = fw[i], fk = fw[k];
+      if (fk < r0 || fk >= r1) continue;
       T pr = T(0);
 #pragma unroll
       for (int m = 0; m < kNodes; ++m)
         pr = fmaP(G[m] * rw[i * kNodes + m], rw[k * kNodes + m], pr);
-      const int fi = fw[i], fk = fw[k];
-      const int64_t idx = (int64_t)fk * (fk - 1) / 2 + fi;
-      if (TRI_LDS)
-        __hip_atomic_fetch_add(&tris[idx], pr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      else
-        unsafeAtomicAdd(&tri64[s * ntri + idx], (double)pr);
+      lds_add(&tris[tri_row(fk) - base0 + fi], (double)pr);
     }
     // the next path overwrites this wave's r and feature slots
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  __syncthreads();
-
-  for (int i = threadIdx.x; i < F; i += blockDim.x) {
-    const T v = phis[i];
-    if (v != T(0)) unsafeAtomicAdd(&phi64[s * F + i], (double)v);
-  }
-  if (TRI_LDS) {
-    for (int64_t e = threadIdx.x; e < ntri; e += blockDim.x) {
-      const T v = tris[e];
-      if (v != T(0)) unsafeAtomicAdd(&tri64[s * ntri + e], (double)v);
-    }
-  }
+  pairs_epilogue(phis, tris, ntri_r, base0, ntri, with_phi != 0, s, F, tri64, phi64);
 }
 
 // Phi[s] from the FP64 accumulators: off-diagonal SII/2, diagonal
@@ -337,22 +363,40 @@ pairs_finalize_kernel(const double* __restrict__ tri64, const double* __restrict
 
 namespace {
 
-size_t pairs_lds_bytes(int F, size_t tsize, bool tri_lds) {
-  const size_t ntri = (size_t)F * (F - 1) / 2;
-  return (size_t)F * tsize + (tri_lds ? ntri * tsize : 0) + (size_t)F * sizeof(float);
-}
-
 constexpr int kGenericThreads = 256;
 
-size_t generic_lds_bytes(int F, size_t tsize, bool tri_lds) {
-  const int nw = kGenericThreads / 64;
-  return pairs_lds_bytes(F, tsize, tri_lds) + (size_t)nw * 64 * kNodes * tsize +
-         (size_t)nw * 64 * sizeof(int);
+// LDS bytes besides the triangle rows: the FP64 phi row, the sample row and,
+// for the generic kernel, each wave's r and feature slots.
+size_t pairs_fixed_lds(int F, size_t tsize, bool generic) {
+  size_t b = (size_t)F * sizeof(double) + (size_t)F * sizeof(float);
+  if (generic) {
+    const int nw = kGenericThreads / 64;
+    b += (size_t)nw * 64 * kNodes * tsize + (size_t)nw * 64 * sizeof(int);
+  }
+  return b;
+}
+
+int64_t tri_row_h(int64_t k) { return k * (k - 1) / 2; }
+
+// Cut the triangle rows [0, F) into ranges whose FP64 entries fit in
+// `budget` bytes of LDS (row k holds k entries).
+std::vector<std::pair<int, int>> row_ranges(int F, size_t budget) {
+  std::vector<std::pair<int, int>> out;
+  const int64_t cap = (int64_t)(budget / sizeof(double));
+  if (cap < F) fail(QTS_E_UNSUPPORTED, "n_features too large for the interactions kernel");
+  int r0 = 0;
+  while (r0 < F) {
+    int r1 = r0 + 1;
+    while (r1 < F && tri_row_h(r1 + 1) - tri_row_h(r0) <= cap) ++r1;
+    out.emplace_back(r0, r1);
+    r0 = r1;
+  }
+  return out;
 }
 
 int pair_chunk(int np, int64_t M, int64_t* n_chunks_out) {
-  // chunks: at most 64k paths (bounds the in-kernel precision sum), and
-  // enough work items to fill the chip when there are few samples
+  // chunks of at most 64k paths, and enough work items to fill the chip
+  // when there are few samples
   int64_t n_chunks = (np + 65535) / 65536;
   const int64_t fill = (2048 + M - 1) / M;
   n_chunks = std::max<int64_t>(n_chunks, std::min<int64_t>(fill, (np + 1023) / 1024));
@@ -397,18 +441,24 @@ void launch_pairs_fast(const HostTable& h, const DeviceTable& d, const PairClass
   const int64_t grid = M * n_chunks;
   if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "interactions grid too large");
   static size_t cache = 0;
-  const size_t lds = pairs_lds_bytes(F, sizeof(T), true);
-  if (lds > lds_limit_of((const void*)pairs_kernel<T, C, NH, true>, &cache))
-    fail(QTS_E_UNSUPPORTED, "n_features too large for the interactions kernel");
-  hipLaunchKernelGGL((pairs_kernel<T, C, NH, true>), dim3((unsigned)grid), dim3(512), lds, s,
-                     d.pr_d + pc.pbase, d.pr_leaf + pc.pbase, d.pr_feat + pc.base,
-                     d.pr_lo + pc.base, d.pr_hi + pc.base, table_b<T>(d) + pc.base,
-                     table_cb<T>(d) + pc.base, pc.np, chunk, leaf_val, X, M, ldx, F, tri64, phi64,
-                     node_consts<T>(d));
-  check_hip(hipGetLastError(), "pairs_kernel launch");
+  const void* fn = (const void*)pairs_kernel<T, C, NH>;
+  const size_t limit = lds_limit_of(fn, &cache);
+  const size_t fixed = pairs_fixed_lds(F, sizeof(T), false);
+  if (fixed >= limit) fail(QTS_E_UNSUPPORTED, "n_features too large for the interactions kernel");
+  bool first = true;
+  for (const auto& rg : row_ranges(F, limit - fixed)) {
+    const size_t lds = fixed + (size_t)(tri_row_h(rg.second) - tri_row_h(rg.first)) * 8;
+    hipLaunchKernelGGL((pairs_kernel<T, C, NH>), dim3((unsigned)grid), dim3(512), lds, s,
+                       d.pr_d + pc.pbase, d.pr_leaf + pc.pbase, d.pr_feat + pc.base,
+                       d.pr_lo + pc.base, d.pr_hi + pc.base, table_b<T>(d) + pc.base,
+                       table_cb<T>(d) + pc.base, pc.np, chunk, leaf_val, X, M, ldx, F, rg.first,
+                       rg.second, (int)first, tri64, phi64, node_consts<T>(d));
+    check_hip(hipGetLastError(), "pairs_kernel launch");
+    first = false;
+  }
 }
 
-template <typename T, bool TRI>
+template <typename T>
 void launch_pairs_generic(const HostTable& h, const DeviceTable& d, const PairClass& pc,
                           const float* X, int64_t M, int64_t ldx, const double* leaf_val,
                           double* tri64, double* phi64, hipStream_t s) {
@@ -418,15 +468,21 @@ void launch_pairs_generic(const HostTable& h, const DeviceTable& d, const PairCl
   const int64_t grid = M * n_chunks;
   if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "interactions grid too large");
   static size_t cache = 0;
-  const size_t lds = generic_lds_bytes(F, sizeof(T), TRI);
-  if (lds > lds_limit_of((const void*)pairs_generic_kernel<T, TRI>, &cache))
-    fail(QTS_E_UNSUPPORTED, "n_features too large for the interactions kernel");
-  hipLaunchKernelGGL((pairs_generic_kernel<T, TRI>), dim3((unsigned)grid),
-                     dim3(kGenericThreads), lds, s, d.pr_d + pc.pbase, d.pr_leaf + pc.pbase,
-                     d.pr_feat + pc.base, d.pr_lo + pc.base, d.pr_hi + pc.base,
-                     table_b<T>(d) + pc.base, table_cb<T>(d) + pc.base, pc.np, chunk, leaf_val,
-                     X, M, ldx, F, tri64, phi64, node_consts<T>(d));
-  check_hip(hipGetLastError(), "pairs_generic_kernel launch");
+  const void* fn = (const void*)pairs_generic_kernel<T>;
+  const size_t limit = lds_limit_of(fn, &cache);
+  const size_t fixed = pairs_fixed_lds(F, sizeof(T), true);
+  if (fixed >= limit) fail(QTS_E_UNSUPPORTED, "n_features too large for the interactions kernel");
+  bool first = true;
+  for (const auto& rg : row_ranges(F, limit - fixed)) {
+    const size_t lds = fixed + (size_t)(tri_row_h(rg.second) - tri_row_h(rg.first)) * 8;
+    hipLaunchKernelGGL((pairs_generic_kernel<T>), dim3((unsigned)grid), dim3(kGenericThreads),
+                       lds, s, d.pr_d + pc.pbase, d.pr_leaf + pc.pbase, d.pr_feat + pc.base,
+                       d.pr_lo + pc.base, d.pr_hi + pc.base, table_b<T>(d) + pc.base,
+                       table_cb<T>(d) + pc.base, pc.np, chunk, leaf_val, X, M, ldx, F, rg.first,
+                       rg.second, (int)first, tri64, phi64, node_consts<T>(d));
+    check_hip(hipGetLastError(), "pairs_generic_kernel launch");
+    first = false;
+  }
 }
 
 }  // namespace
@@ -442,24 +498,15 @@ void launch_pairs(const HostTable& h, const DeviceTable& d, const PairClass& pc,
       case 12: return launch_pairs_fast<float, 12, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
       case 16: return launch_pairs_fast<float, 16, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
       case 20: return launch_pairs_fast<float, 20, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
-      case 24: return launch_pairs_fast<float, 24, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
-      default: break;
-    }
-    if (generic_lds_bytes(h.F, sizeof(float), true) > (size_t)kMaxLdsBytes - 1024)
-      fail(QTS_E_UNSUPPORTED, "n_features too large for the interactions kernel");
-    return launch_pairs_generic<float, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
-  }
-  if (pairs_lds_bytes(h.F, sizeof(double), true) <= (size_t)kMaxLdsBytes - 1024) {
-    switch (pc.cap) {
-      case 4: return launch_pairs_fast<double, 4, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
-      case 8: return launch_pairs_fast<double, 8, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
-      default: break;
+      case 24: return launch_pairs_fast<float, 24, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
+      default: return launch_pairs_generic<float>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
     }
   }
-  if (generic_lds_bytes(h.F, sizeof(double), true) <= (size_t)kMaxLdsBytes - 1024)
-    launch_pairs_generic<double, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
-  else
-    launch_pairs_generic<double, false>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
+  switch (pc.cap) {
+    case 4: return launch_pairs_fast<double, 4, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
+    case 8: return launch_pairs_fast<double, 8, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
+    default: return launch_pairs_generic<double>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
+  }
 }
 
 void launch_pairs_finalize(const double* tri64, const double* phi64, int64_t M, int F, bool fp64,

@@ -112,3 +112,19 @@ def test_interaction_capacity_classes(q, oracle_mod, d):
     for precision in ("fp32", "fp64"):
         Phi, phi, _ = _run(q, ens, X, precision)
         check(Phi, Phi_o, precision, "chain d=%d" % d)
+
+
+@pytest.mark.parametrize("F", [202, 300])
+def test_interactions_split_triangle(q, oracle_mod, F):
+    """More features than one FP64 pair triangle fits in LDS: the triangle is
+    cut into row ranges, one launch each; every range must add its pairs once
+    and phi must be added by the first range only."""
+    rng = np.random.default_rng(600 + F)
+    ens = synth.random_small_ensemble(rng, 12, F, 9)
+    X = rng.standard_normal((37, F)).astype(np.float32)
+    X[::4, ::7] = np.nan
+    phi_o, Phi_o = oracle_mod.shap_interactions(ens, X, n=8)
+    for precision in ("fp32", "fp64"):
+        Phi, phi, _ = _run(q, ens, X, precision)
+        check(Phi, Phi_o, precision, "F=%d Phi" % F)
+        check(phi, phi_o, precision, "F=%d phi" % F)
