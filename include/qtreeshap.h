@@ -112,6 +112,8 @@ typedef struct {
   int32_t max_unique;  /* d */
   int32_t n_buckets;
   int32_t device;      /* -1 for a host-only ensemble */
+  int32_t n_pair_classes;  /* capacity classes of the interactions table */
+  int32_t n_graphs;        /* graphs held by the replay cache */
 } qts_info;
 
 int qts_get_info(const qts_ensemble* ens, qts_info* out);
@@ -159,10 +161,38 @@ int qts_shap_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_
                       const void* grad_phi, double* grad_leaf, qts_precision precision,
                       void* stream);
 
-/* Time the candidate launch shapes of qts_shap_values on synthetic rows of
- * this ensemble (M_hint rows, capped) and keep the fastest for this ensemble
- * and precision.  Optional: untuned ensembles use a size-based default. */
+/* Launch-shape autotuner.  Times, with HIP events on `stream`, candidate
+ * launch shapes on M_hint synthetic rows (uniform in [-3, 3), M_hint capped to
+ * [64, 32768]; interactions on at most 256 of them) and keeps the fastest for
+ * this ensemble and precision:
+ *   first-order and adjoint kernels, per length bucket: wavefronts per
+ *     workgroup {4, 8} x target work items {4096 .. 65536};
+ *   interactions, per capacity class: largest path chunk {8192, 32768,
+ *     131072} x least work items {1024, 4096}.
+ * Synchronises `stream`; drops the ensemble's cached graphs.  Optional:
+ * untuned ensembles use fixed defaults.  Not thread-safe against concurrent
+ * compute calls on the same ensemble. */
 int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, void* stream);
+
+/* The launch shape in use: kind 0 = first-order/adjoint bucket `index`
+ * (0..3 for lengths <= 8, 16, 32, 64) -> (*a, *b) = (wavefronts per
+ * workgroup, target work items); kind 1 = interactions capacity class `index`
+ * (0 .. n_pair_classes-1) -> (largest path chunk, least work items). */
+int qts_get_launch_shape(const qts_ensemble* ens, int32_t kind, qts_precision precision,
+                         int32_t index, int32_t* a, int32_t* b);
+
+/* HIP graph replay.  While enabled, each compute call on this ensemble is
+ * captured once (on an internal stream, with its per-bucket or per-class
+ * launches as parallel branches) into a graph keyed by (call kind, precision,
+ * X, M, ldx, leaf values or grad_phi, output pointers, stream), and replayed
+ * with hipGraphLaunch on the caller's stream on every later call with the same
+ * key.  A graph owns its FP64 accumulators, so a replay allocates nothing.
+ * The graphs contain kernel nodes only (zeroing is a kernel, not a memset).
+ * At most 16 graphs are kept (least recently used evicted, after waiting for
+ * its stream).  The caller keeps the keyed buffers alive and at the same size
+ * while their graph may replay; disabling drops every graph.  Calls of one
+ * ensemble are serialised by the cache. */
+int qts_set_graph_replay(qts_ensemble* ens, int32_t enable);
 
 /* Measurement aid.  While enabled, each compute call records a HIP event pair
  * on its stream around the launches of its main kernel (kind 0: the values
@@ -170,7 +200,8 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
  * zero-fill and cast kernels around them.  qts_kernel_timing_read waits for
  * the recorded events of one kind, returns their summed duration in
  * milliseconds and the number of calls since the last read, and clears them.
- * Not meant to be enabled while a HIP graph is being captured. */
+ * With graph replay on, the pair spans the whole replay (zero-fill and cast
+ * included).  Not meant to be enabled while a HIP graph is being captured. */
 int qts_set_kernel_timing(int32_t enable);
 int qts_kernel_timing_read(int32_t kind, double* total_ms, int64_t* calls);
 

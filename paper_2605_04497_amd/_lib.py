@@ -38,7 +38,8 @@ class Info(ctypes.Structure):
                 ("n_leaves", ctypes.c_int64), ("n_paths", ctypes.c_int64),
                 ("n_elements", ctypes.c_int64), ("max_depth", ctypes.c_int32),
                 ("max_unique", ctypes.c_int32), ("n_buckets", ctypes.c_int32),
-                ("device", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("n_pair_classes", ctypes.c_int32),
+                ("n_graphs", ctypes.c_int32)]
 
 
 # exported symbol -> (restype, argtypes)
@@ -60,6 +61,10 @@ SIGNATURES = {
     "qts_shap_backward": (ctypes.c_int, [P, P, ctypes.c_int64, ctypes.c_int64, P, P,
                                          ctypes.c_int, P]),
     "qts_autotune": (ctypes.c_int, [P, ctypes.c_int64, ctypes.c_int, P]),
+    "qts_get_launch_shape": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int, ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32)]),
+    "qts_set_graph_replay": (ctypes.c_int, [P, ctypes.c_int32]),
     "qts_set_kernel_timing": (ctypes.c_int, [ctypes.c_int32]),
     "qts_kernel_timing_read": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_int64)]),

@@ -136,33 +136,61 @@ class Ensemble:
         return out
 
     def shap_interactions(self, X: torch.Tensor, precision: str = "fp32", leaf_values=None,
-                          with_phi: bool = False):
+                          with_phi: bool = False, out=None, out_phi=None):
         """Phi[M, F, F] (and phi[M, F] when with_phi)."""
         X, M, ldx = self._rows(X)
         lv = self._leaf(leaf_values)
         F = self.n_features
-        Phi = torch.empty((M, F, F), dtype=_DTYPE[precision], device=X.device)
-        phi = torch.empty((M, F), dtype=_DTYPE[precision], device=X.device) if with_phi else None
+        Phi = out if out is not None else torch.empty((M, F, F), dtype=_DTYPE[precision],
+                                                      device=X.device)
+        phi = None
+        if with_phi:
+            phi = out_phi if out_phi is not None else torch.empty(
+                (M, F), dtype=_DTYPE[precision], device=X.device)
         L.check(L.lib().qts_shap_interactions(self._h, _ptr(X), M, ldx, _ptr(lv), _ptr(phi),
                                               _ptr(Phi), _PREC[precision],
                                               _stream_ptr(X.device)))
         return (Phi, phi) if with_phi else Phi
 
     def shap_backward(self, X: torch.Tensor, grad_phi: torch.Tensor,
-                      precision: str = "fp32") -> torch.Tensor:
+                      precision: str = "fp32", out=None) -> torch.Tensor:
         """grad_leaf[n_leaves] (float64) = J^T grad_phi."""
         X, M, ldx = self._rows(X)
         g = grad_phi.to(_DTYPE[precision]).contiguous()
         if tuple(g.shape) != (M, self.n_features):
             raise ValueError("grad_phi must be [M, F]")
-        out = torch.empty(self.n_leaves, dtype=torch.float64, device=X.device)
+        if out is None:
+            out = torch.empty(self.n_leaves, dtype=torch.float64, device=X.device)
         L.check(L.lib().qts_shap_backward(self._h, _ptr(X), M, ldx, _ptr(g), _ptr(out),
                                           _PREC[precision], _stream_ptr(X.device)))
         return out
 
     def autotune(self, M_hint: int, precision: str = "fp32"):
+        """Time candidate launch shapes on M_hint synthetic rows; keep the fastest."""
         L.check(L.lib().qts_autotune(self._h, int(M_hint), _PREC[precision],
                                      _stream_ptr(self.device)))
+
+    def launch_shape(self, kind: str, precision: str = "fp32", index: int = 0):
+        """(waves per workgroup, target work items) of first-order bucket `index`
+        (kind 'values'), or (largest path chunk, least work items) of
+        interactions class `index` (kind 'interactions')."""
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        L.check(L.lib().qts_get_launch_shape(self._h, {"values": 0, "interactions": 1}[kind],
+                                             _PREC[precision], int(index), ctypes.byref(a),
+                                             ctypes.byref(b)))
+        return a.value, b.value
+
+    def set_graph_replay(self, enable: bool = True):
+        """Capture each call once into a HIP graph and replay it on later calls
+        with the same tensors (pass `out=` to reuse output buffers)."""
+        with torch.cuda.device(self.device):
+            L.check(L.lib().qts_set_graph_replay(self._h, int(bool(enable))))
+
+    def refresh_info(self) -> dict:
+        info = L.Info()
+        L.check(L.lib().qts_get_info(self._h, ctypes.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in L.Info._fields_}
+        return self.info
 
     # ---------------------------------------------------------------- inspection
     def export_paths(self) -> dict:

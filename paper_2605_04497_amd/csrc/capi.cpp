@@ -1,6 +1,7 @@
 // C-ABI entry points (declared in include/qtreeshap.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -13,13 +14,58 @@
 #include "qts_internal.h"
 #include "qtreeshap.h"
 
+namespace qts {
+
+constexpr int kSideStreams = 3;  // extra branches of a captured graph
+constexpr size_t kMaxGraphs = 16;
+
+// One captured call: its launches depend only on these arguments.
+struct GraphKey {
+  int kind = 0;  // 0 values, 1 interactions, 2 adjoint
+  int fp64 = 0;
+  const void* X = nullptr;
+  int64_t M = 0, ldx = 0;
+  const void* in = nullptr;    // leaf-value override or grad_phi
+  const void* out0 = nullptr;  // phi / Phi / grad_leaf
+  const void* out1 = nullptr;  // phi of the interactions call
+  hipStream_t stream = nullptr;
+  bool operator==(const GraphKey& o) const {
+    return kind == o.kind && fp64 == o.fp64 && X == o.X && M == o.M && ldx == o.ldx &&
+           in == o.in && out0 == o.out0 && out1 == o.out1 && stream == o.stream;
+  }
+};
+
+struct GraphEntry {
+  GraphKey key;
+  hipGraphExec_t exec = nullptr;
+  void* scratch = nullptr;  // the call's FP64 accumulators, owned by this graph
+  uint64_t stamp = 0;
+};
+
+// Per-ensemble cache of instantiated graphs (see qts_set_graph_replay).
+struct GraphCache {
+  std::mutex mu;
+  bool on = false;
+  hipStream_t cap = nullptr;  // capture stream
+  hipStream_t side[kSideStreams] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kSideStreams] = {};
+  std::vector<GraphEntry> entries;
+  uint64_t clock = 0;
+};
+
+}  // namespace qts
+
 struct qts_ensemble {
   qts::HostTable host;
   std::vector<qts::PairClass> pair_classes;
   qts::DeviceTable dev;
   bool on_device = false;
-  // launch shapes per bucket capacity index (8, 16, 32, 64) and precision
+  // launch shapes per bucket capacity index (8, 16, 32, 64) and precision,
+  // and per pair capacity class and precision (defaults until autotuned)
   qts::ValuesShape vshape[2][4];
+  std::vector<qts::PairShape> pshape[2];
+  qts::GraphCache graphs;
 };
 
 namespace qts {
@@ -136,7 +182,8 @@ Timing& timing() {
 // Records an event pair around a scope when timing is enabled.
 class TimedScope {
  public:
-  TimedScope(int kind, hipStream_t s) : kind_(kind), s_(s) {
+  TimedScope(int kind, hipStream_t s, bool enable = true) : kind_(kind), s_(s) {
+    if (!enable) return;
     Timing& t = timing();
     std::lock_guard<std::mutex> g(t.mu);
     if (!t.on) return;
@@ -166,6 +213,179 @@ class TimedScope {
   hipEvent_t a_ = nullptr, b_ = nullptr;
   bool active_ = false;
 };
+
+// The streams one call's launches go to: the call's own stream, plus, while
+// a graph is captured, side streams forked from it so that the per-bucket
+// (per-class) launches become parallel branches of the graph.  Buckets add
+// into the same FP64 accumulators with atomics, so their order is free.
+struct Lanes {
+  hipStream_t main = nullptr;
+  GraphCache* g = nullptr;  // non-null while capturing
+  int n_side = 0;
+  void fork(int n_launches) {
+    n_side = g ? std::min(kSideStreams, n_launches - 1) : 0;
+    if (n_side <= 0) return;
+    check_hip(hipEventRecord(g->fork, main), "hipEventRecord");
+    for (int k = 0; k < n_side; ++k)
+      check_hip(hipStreamWaitEvent(g->side[k], g->fork, 0), "hipStreamWaitEvent");
+  }
+  hipStream_t pick(int i) const {
+    const int k = n_side > 0 ? i % (n_side + 1) : 0;
+    return k == 0 ? main : g->side[k - 1];
+  }
+  void join() {
+    for (int k = 0; k < n_side; ++k) {
+      check_hip(hipEventRecord(g->join[k], g->side[k]), "hipEventRecord");
+      check_hip(hipStreamWaitEvent(main, g->join[k], 0), "hipStreamWaitEvent");
+    }
+    n_side = 0;
+  }
+};
+
+const PairShape& pair_shape(const qts_ensemble* ens, bool fp64, size_t i) {
+  static const PairShape kDefault{};
+  const auto& v = ens->pshape[fp64 ? 1 : 0];
+  return i < v.size() ? v[i] : kDefault;
+}
+
+// The launches of one call, on `ln` (acc: the FP64 accumulators of the call).
+void issue_values(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
+                  const double* leaf, void* phi, bool fp64, double* acc, Lanes& ln,
+                  bool timed) {
+  const HostTable& h = ens->host;
+  const int64_t n = M * h.F;
+  double* a = fp64 ? (double*)phi : acc;
+  launch_fill_zero(a, n, ln.main);
+  TimedScope ts(0, timed ? ln.main : nullptr, timed);
+  ln.fork((int)h.buckets.size());
+  for (size_t i = 0; i < h.buckets.size(); ++i) {
+    const Bucket& bk = h.buckets[i];
+    launch_values(h, ens->dev, bk, fp64, X, M, ldx, leaf, a,
+                  ens->vshape[fp64 ? 1 : 0][cap_index(bk.dmax)], ln.pick((int)i));
+  }
+  ln.join();
+  ts.done();
+  if (!fp64) launch_cast_f64_f32(a, (float*)phi, n, ln.main);
+}
+
+void issue_interactions(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
+                        const double* leaf, void* phi, void* Phi, bool fp64, double* acc,
+                        Lanes& ln, bool timed) {
+  const HostTable& h = ens->host;
+  const int64_t F = h.F;
+  const int64_t ntri = F * (F - 1) / 2;
+  double* tri64 = acc;
+  double* phi64 = tri64 + M * ntri;
+  launch_fill_zero(tri64, M * ntri + M * F, ln.main);
+  TimedScope ts(1, timed ? ln.main : nullptr, timed);
+  ln.fork((int)ens->pair_classes.size());
+  for (size_t i = 0; i < ens->pair_classes.size(); ++i)
+    launch_pairs(h, ens->dev, ens->pair_classes[i], fp64, X, M, ldx, leaf, tri64, phi64,
+                 pair_shape(ens, fp64, i), ln.pick((int)i));
+  ln.join();
+  ts.done();
+  launch_pairs_finalize(tri64, phi64, M, (int)F, fp64, Phi, phi, ln.main);
+}
+
+void issue_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
+                    const void* grad_phi, double* grad_leaf, bool fp64, Lanes& ln, bool timed) {
+  const HostTable& h = ens->host;
+  launch_fill_zero(grad_leaf, (int64_t)h.leaf_value.size(), ln.main);
+  if (M == 0) return;
+  TimedScope ts(2, timed ? ln.main : nullptr, timed);
+  ln.fork((int)h.buckets.size());
+  for (size_t i = 0; i < h.buckets.size(); ++i) {
+    const Bucket& bk = h.buckets[i];
+    launch_adjoint(h, ens->dev, bk, fp64, X, grad_phi, M, ldx, grad_leaf,
+                   ens->vshape[fp64 ? 1 : 0][cap_index(bk.dmax)], ln.pick((int)i));
+  }
+  ln.join();
+  ts.done();
+}
+
+void destroy_entry(GraphEntry& e) {
+  // the graph may still run on its stream: wait before releasing it
+  (void)hipStreamSynchronize(e.key.stream);
+  if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  if (e.scratch) (void)hipFree(e.scratch);
+  e.exec = nullptr;
+  e.scratch = nullptr;
+}
+
+void clear_graphs(GraphCache& g) {
+  for (GraphEntry& e : g.entries) destroy_entry(e);
+  g.entries.clear();
+}
+
+void release_graph_cache(GraphCache& g) {
+  clear_graphs(g);
+  if (g.cap) (void)hipStreamDestroy(g.cap);
+  for (hipStream_t& st : g.side)
+    if (st) (void)hipStreamDestroy(st);
+  if (g.fork) (void)hipEventDestroy(g.fork);
+  for (hipEvent_t& ev : g.join)
+    if (ev) (void)hipEventDestroy(ev);
+  g.cap = nullptr;
+  g.fork = nullptr;
+  for (int k = 0; k < kSideStreams; ++k) {
+    g.side[k] = nullptr;
+    g.join[k] = nullptr;
+  }
+  g.on = false;
+}
+
+// Replay the graph of `key`, capturing it first (with `issue(lanes, scratch)`
+// on the cache's capture stream) if it is not cached.  The graph is launched
+// on the caller's stream, so it orders after the work already queued there.
+template <class Issue>
+void run_graph(qts_ensemble* ens, const GraphKey& key, size_t scratch_bytes, int kind,
+               Issue&& issue) {
+  GraphCache& g = ens->graphs;
+  std::lock_guard<std::mutex> lock(g.mu);
+  GraphEntry* hit = nullptr;
+  for (GraphEntry& e : g.entries)
+    if (e.key == key) hit = &e;
+  if (!hit) {
+    GraphEntry ne;
+    ne.key = key;
+    if (scratch_bytes) check_hip(hipMalloc(&ne.scratch, scratch_bytes), "hipMalloc");
+    hipGraph_t graph = nullptr;
+    try {
+      check_hip(hipStreamBeginCapture(g.cap, hipStreamCaptureModeRelaxed),
+                "hipStreamBeginCapture");
+      try {
+        Lanes ln{g.cap, &g};
+        issue(ln, (double*)ne.scratch);
+      } catch (...) {
+        hipGraph_t dead = nullptr;
+        (void)hipStreamEndCapture(g.cap, &dead);
+        if (dead) (void)hipGraphDestroy(dead);
+        throw;
+      }
+      check_hip(hipStreamEndCapture(g.cap, &graph), "hipStreamEndCapture");
+      check_hip(hipGraphInstantiate(&ne.exec, graph, nullptr, nullptr, 0),
+                "hipGraphInstantiate");
+      (void)hipGraphDestroy(graph);
+    } catch (...) {
+      if (graph) (void)hipGraphDestroy(graph);
+      if (ne.scratch) (void)hipFree(ne.scratch);
+      throw;
+    }
+    if (g.entries.size() >= kMaxGraphs) {
+      size_t victim = 0;
+      for (size_t i = 1; i < g.entries.size(); ++i)
+        if (g.entries[i].stamp < g.entries[victim].stamp) victim = i;
+      destroy_entry(g.entries[victim]);
+      g.entries.erase(g.entries.begin() + (std::ptrdiff_t)victim);
+    }
+    g.entries.push_back(ne);
+    hit = &g.entries.back();
+  }
+  hit->stamp = ++g.clock;
+  TimedScope ts(kind, key.stream, true);
+  check_hip(hipGraphLaunch(hit->exec, key.stream), "hipGraphLaunch");
+  ts.done();
+}
 
 }  // namespace
 
@@ -283,6 +503,10 @@ int qts_load_ensemble(const qts_tree_arrays* trees, int32_t n_features, double b
 int qts_free_ensemble(qts_ensemble* ens) {
   return guarded([&] {
     if (!ens) return;
+    {
+      std::lock_guard<std::mutex> lock(ens->graphs.mu);
+      release_graph_cache(ens->graphs);
+    }
     if (ens->on_device) free_device(ens->dev);
     delete ens;
   });
@@ -315,6 +539,8 @@ int qts_get_info(const qts_ensemble* ens, qts_info* out) {
     out->max_unique = h.max_unique;
     out->n_buckets = (int32_t)h.buckets.size();
     out->device = ens->on_device ? ens->dev.device : -1;
+    out->n_pair_classes = (int32_t)ens->pair_classes.size();
+    out->n_graphs = (int32_t)ens->graphs.entries.size();
   });
 }
 
@@ -358,28 +584,24 @@ int qts_shap_values(const qts_ensemble* ens, const float* X, int64_t M, int64_t 
     if (M > 0 && !phi) fail(QTS_E_INVALID_ARG, "null phi");
     require_device(ens);
     if (M == 0) return;
-    const HostTable& h = ens->host;
-    const DeviceTable& d = ens->dev;
     hipStream_t s = (hipStream_t)stream;
     const bool fp64 = precision == QTS_FP64;
-    const int64_t n = M * h.F;
-    const double* leaf = leaf_values ? leaf_values : d.leaf_val;
+    const double* leaf = leaf_values ? leaf_values : ens->dev.leaf_val;
+    const size_t acc_bytes = fp64 ? 0 : sizeof(double) * (size_t)(M * ens->host.F);
+    qts_ensemble* me = const_cast<qts_ensemble*>(ens);  // the graph cache only
+    if (ens->graphs.on) {
+      GraphKey key{0, fp64, X, M, ldx, leaf, phi, nullptr, s};
+      run_graph(me, key, acc_bytes, 0, [&](Lanes& ln, double* acc) {
+        issue_values(ens, X, M, ldx, leaf, phi, fp64, acc, ln, false);
+      });
+      return;
+    }
+    Lanes ln{s, nullptr};
     if (fp64) {
-      double* acc = (double*)phi;
-      launch_fill_zero(acc, n, s);
-      TimedScope ts(0, s);
-      for (const Bucket& bk : h.buckets)
-        launch_values(h, d, bk, true, X, M, ldx, leaf, acc, ens->vshape[1][cap_index(bk.dmax)], s);
-      ts.done();
+      issue_values(ens, X, M, ldx, leaf, phi, true, nullptr, ln, true);
     } else {
-      Scratch acc(sizeof(double) * (size_t)n, s);
-      double* a = (double*)acc.p;
-      launch_fill_zero(a, n, s);
-      TimedScope ts(0, s);
-      for (const Bucket& bk : h.buckets)
-        launch_values(h, d, bk, false, X, M, ldx, leaf, a, ens->vshape[0][cap_index(bk.dmax)], s);
-      ts.done();
-      launch_cast_f64_f32(a, (float*)phi, n, s);
+      Scratch acc(acc_bytes, s);
+      issue_values(ens, X, M, ldx, leaf, phi, false, (double*)acc.p, ln, true);
     }
   });
 }
@@ -395,22 +617,22 @@ int qts_shap_interactions(const qts_ensemble* ens, const float* X, int64_t M, in
     if (M > 0 && !Phi) fail(QTS_E_INVALID_ARG, "null Phi");
     require_device(ens);
     if (M == 0) return;
-    const HostTable& h = ens->host;
-    const DeviceTable& d = ens->dev;
     hipStream_t s = (hipStream_t)stream;
     const bool fp64 = precision == QTS_FP64;
-    const int64_t F = h.F;
-    const int64_t ntri = F * (F - 1) / 2;
-    const double* leaf = leaf_values ? leaf_values : d.leaf_val;
-    Scratch acc(sizeof(double) * (size_t)(M * ntri + M * F), s);
-    double* tri64 = (double*)acc.p;
-    double* phi64 = tri64 + M * ntri;
-    launch_fill_zero(tri64, M * ntri + M * F, s);
-    TimedScope ts(1, s);
-    for (const PairClass& pc : ens->pair_classes)
-      launch_pairs(h, d, pc, fp64, X, M, ldx, leaf, tri64, phi64, s);
-    ts.done();
-    launch_pairs_finalize(tri64, phi64, M, (int)F, fp64, Phi, phi, s);
+    const int64_t F = ens->host.F;
+    const double* leaf = leaf_values ? leaf_values : ens->dev.leaf_val;
+    const size_t acc_bytes = sizeof(double) * (size_t)(M * (F * (F - 1) / 2) + M * F);
+    qts_ensemble* me = const_cast<qts_ensemble*>(ens);
+    if (ens->graphs.on) {
+      GraphKey key{1, fp64, X, M, ldx, leaf, Phi, phi, s};
+      run_graph(me, key, acc_bytes, 1, [&](Lanes& ln, double* acc) {
+        issue_interactions(ens, X, M, ldx, leaf, phi, Phi, fp64, acc, ln, false);
+      });
+      return;
+    }
+    Lanes ln{s, nullptr};
+    Scratch acc(acc_bytes, s);
+    issue_interactions(ens, X, M, ldx, leaf, phi, Phi, fp64, (double*)acc.p, ln, true);
   });
 }
 
@@ -425,27 +647,171 @@ int qts_shap_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_
     if (!grad_leaf) fail(QTS_E_INVALID_ARG, "null grad_leaf");
     if (M > 0 && !grad_phi) fail(QTS_E_INVALID_ARG, "null grad_phi");
     require_device(ens);
-    const HostTable& h = ens->host;
-    const DeviceTable& d = ens->dev;
     hipStream_t s = (hipStream_t)stream;
     const bool fp64 = precision == QTS_FP64;
-    launch_fill_zero(grad_leaf, (int64_t)h.leaf_value.size(), s);
-    if (M == 0) return;
-    TimedScope ts(2, s);
-    for (const Bucket& bk : h.buckets)
-      launch_adjoint(h, d, bk, fp64, X, grad_phi, M, ldx, grad_leaf,
-                     ens->vshape[fp64 ? 1 : 0][cap_index(bk.dmax)], s);
-    ts.done();
+    qts_ensemble* me = const_cast<qts_ensemble*>(ens);
+    if (ens->graphs.on && M > 0) {
+      GraphKey key{2, fp64, X, M, ldx, grad_phi, grad_leaf, nullptr, s};
+      run_graph(me, key, 0, 2, [&](Lanes& ln, double*) {
+        issue_backward(ens, X, M, ldx, grad_phi, grad_leaf, fp64, ln, false);
+      });
+      return;
+    }
+    Lanes ln{s, nullptr};
+    issue_backward(ens, X, M, ldx, grad_phi, grad_leaf, fp64, ln, true);
+  });
+}
+
+int qts_set_graph_replay(qts_ensemble* ens, int32_t enable) {
+  return guarded([&] {
+    if (!ens) fail(QTS_E_INVALID_ARG, "null ensemble");
+    require_device(ens);
+    GraphCache& g = ens->graphs;
+    std::lock_guard<std::mutex> lock(g.mu);
+    if (!enable) {
+      clear_graphs(g);
+      g.on = false;
+      return;
+    }
+    if (!g.cap) {
+      try {
+        check_hip(hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking), "hipStreamCreate");
+        for (int k = 0; k < kSideStreams; ++k)
+          check_hip(hipStreamCreateWithFlags(&g.side[k], hipStreamNonBlocking),
+                    "hipStreamCreate");
+        check_hip(hipEventCreateWithFlags(&g.fork, hipEventDisableTiming), "hipEventCreate");
+        for (int k = 0; k < kSideStreams; ++k)
+          check_hip(hipEventCreateWithFlags(&g.join[k], hipEventDisableTiming),
+                    "hipEventCreate");
+      } catch (...) {
+        release_graph_cache(g);
+        throw;
+      }
+    }
+    g.on = true;
   });
 }
 
 int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, void* stream) {
-  (void)M_hint; (void)stream;
   return guarded([&] {
     if (!ens) fail(QTS_E_INVALID_ARG, "null ensemble");
     if (precision != QTS_FP32 && precision != QTS_FP64)
       fail(QTS_E_INVALID_ARG, "unknown precision");
     require_device(ens);
+    const HostTable& h = ens->host;
+    const DeviceTable& d = ens->dev;
+    hipStream_t s = (hipStream_t)stream;
+    const bool fp64 = precision == QTS_FP64;
+    const int pi = fp64 ? 1 : 0;
+    const int64_t F = h.F;
+    // synthetic rows: uniform in [-3, 3), M_hint rows capped to [64, 32768]
+    const int64_t Mt = std::max<int64_t>(64, std::min<int64_t>(M_hint > 0 ? M_hint : 16384,
+                                                               32768));
+    Scratch xs(sizeof(float) * (size_t)(Mt * F), s);
+    const float* X = (const float*)xs.p;
+    launch_fill_uniform((float*)xs.p, Mt * F, 0x2605u, s);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    check_hip(hipEventCreate(&e0), "hipEventCreate");
+    struct EvGuard {
+      hipEvent_t* a;
+      hipEvent_t* b;
+      ~EvGuard() {
+        if (*a) (void)hipEventDestroy(*a);
+        if (*b) (void)hipEventDestroy(*b);
+      }
+    } guard{&e0, &e1};
+    check_hip(hipEventCreate(&e1), "hipEventCreate");
+    // one untimed launch, then the mean of `reps` timed ones
+    auto time_ms = [&](int reps, auto&& launch) {
+      launch();
+      check_hip(hipEventRecord(e0, s), "hipEventRecord");
+      for (int r = 0; r < reps; ++r) launch();
+      check_hip(hipEventRecord(e1, s), "hipEventRecord");
+      check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+      float ms = 0.f;
+      check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+      return ms / reps;
+    };
+
+    // first-order kernel (its shapes also serve the adjoint), per bucket
+    {
+      Scratch acc(sizeof(double) * (size_t)(Mt * F), s);
+      launch_fill_zero((double*)acc.p, Mt * F, s);
+      for (const Bucket& bk : h.buckets) {
+        ValuesShape best;
+        float best_ms = 1e30f;
+        for (int waves : {4, 8})
+          for (int items : {4096, 8192, 16384, 32768, 65536}) {
+            const ValuesShape cand{waves, items};
+            const float ms = time_ms(3, [&] {
+              launch_values(h, d, bk, fp64, X, Mt, F, d.leaf_val, (double*)acc.p, cand, s);
+            });
+            if (ms < best_ms) {
+              best_ms = ms;
+              best = cand;
+            }
+          }
+        ens->vshape[pi][cap_index(bk.dmax)] = best;
+      }
+    }
+    // interactions, per capacity class, on at most 256 of the rows (and an
+    // accumulator of at most 512 MiB)
+    if (!ens->pair_classes.empty() && F >= 2) {
+      const int64_t per_row = F * (F - 1) / 2 + F;
+      const int64_t Mp = std::max<int64_t>(
+          1, std::min<int64_t>({Mt, (int64_t)256, ((int64_t)512 << 20) / (8 * per_row)}));
+      Scratch acc(sizeof(double) * (size_t)(Mp * per_row), s);
+      double* tri64 = (double*)acc.p;
+      double* phi64 = tri64 + Mp * (F * (F - 1) / 2);
+      launch_fill_zero(tri64, Mp * per_row, s);
+      std::vector<PairShape>& out = ens->pshape[pi];
+      out.assign(ens->pair_classes.size(), PairShape{});
+      for (size_t i = 0; i < ens->pair_classes.size(); ++i) {
+        const PairClass& pc = ens->pair_classes[i];
+        PairShape best;
+        float best_ms = 1e30f;
+        for (int max_chunk : {8192, 32768, 131072})
+          for (int fill : {1024, 4096}) {
+            const PairShape cand{max_chunk, fill};
+            const float ms = time_ms(1, [&] {
+              launch_pairs(h, d, pc, fp64, X, Mp, F, d.leaf_val, tri64, phi64, cand, s);
+            });
+            if (ms < best_ms) {
+              best_ms = ms;
+              best = cand;
+            }
+          }
+        out[i] = best;
+      }
+    }
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    // cached graphs hold the old shapes
+    std::lock_guard<std::mutex> lock(ens->graphs.mu);
+    clear_graphs(ens->graphs);
+  });
+}
+
+int qts_get_launch_shape(const qts_ensemble* ens, int32_t kind, qts_precision precision,
+                         int32_t index, int32_t* a, int32_t* b) {
+  return guarded([&] {
+    if (!ens || !a || !b) fail(QTS_E_INVALID_ARG, "null argument");
+    if (precision != QTS_FP32 && precision != QTS_FP64)
+      fail(QTS_E_INVALID_ARG, "unknown precision");
+    const bool fp64 = precision == QTS_FP64;
+    if (kind == 0) {
+      if (index < 0 || index > 3) fail(QTS_E_INVALID_ARG, "bucket index out of range");
+      const ValuesShape& v = ens->vshape[fp64 ? 1 : 0][index];
+      *a = v.waves_per_block;
+      *b = v.items;
+    } else if (kind == 1) {
+      if (index < 0 || (size_t)index >= ens->pair_classes.size())
+        fail(QTS_E_INVALID_ARG, "class index out of range");
+      const PairShape& v = pair_shape(ens, fp64, (size_t)index);
+      *a = v.max_chunk;
+      *b = v.fill;
+    } else {
+      fail(QTS_E_INVALID_ARG, "unknown kind");
+    }
   });
 }
 

@@ -18,6 +18,17 @@ __global__ void __launch_bounds__(256) cast_kernel(const double* __restrict__ sr
     dst[i] = (float)src[i];
 }
 
+// Counter-based hash (the "lowbias32" integer mixer) to uniform floats.
+__global__ void __launch_bounds__(256) fill_uniform_kernel(float* __restrict__ p, int64_t n,
+                                                           uint32_t seed) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    uint32_t x = (uint32_t)i ^ (uint32_t)(i >> 32) * 0x9e3779b9u ^ seed;
+    x ^= x >> 16; x *= 0x7feb352du; x ^= x >> 15; x *= 0x846ca68bu; x ^= x >> 16;
+    p[i] = -3.0f + 6.0f * (float)(x >> 8) * (1.0f / 16777216.0f);
+  }
+}
+
 static unsigned grid_for(int64_t n) {
   int64_t g = (n + 255) / 256;
   if (g > 8192) g = 8192;
@@ -29,6 +40,12 @@ void launch_fill_zero(double* p, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n);
   check_hip(hipGetLastError(), "fill_zero launch");
+}
+
+void launch_fill_uniform(float* p, int64_t n, uint32_t seed, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_uniform_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n, seed);
+  check_hip(hipGetLastError(), "fill_uniform launch");
 }
 
 void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s) {

@@ -394,11 +394,12 @@ std::vector<std::pair<int, int>> row_ranges(int F, size_t budget) {
   return out;
 }
 
-int pair_chunk(int np, int64_t M, int64_t* n_chunks_out) {
-  // chunks of at most 64k paths, and enough work items to fill the chip
-  // when there are few samples
-  int64_t n_chunks = (np + 65535) / 65536;
-  const int64_t fill = (2048 + M - 1) / M;
+int pair_chunk(int np, int64_t M, const PairShape& shape, int64_t* n_chunks_out) {
+  // chunks of at most max_chunk paths, and at least `fill` work items when
+  // there are few samples (chunks of no fewer than 1024 paths)
+  const int64_t max_chunk = std::max(1024, shape.max_chunk);
+  int64_t n_chunks = (np + max_chunk - 1) / max_chunk;
+  const int64_t fill = (std::max(1, shape.fill) + M - 1) / M;
   n_chunks = std::max<int64_t>(n_chunks, std::min<int64_t>(fill, (np + 1023) / 1024));
   n_chunks = std::max<int64_t>(1, n_chunks);
   *n_chunks_out = n_chunks;
@@ -434,10 +435,10 @@ NodeConsts<T> node_consts(const DeviceTable& d) {
 template <typename T, int C, int NH>
 void launch_pairs_fast(const HostTable& h, const DeviceTable& d, const PairClass& pc,
                        const float* X, int64_t M, int64_t ldx, const double* leaf_val,
-                       double* tri64, double* phi64, hipStream_t s) {
+                       double* tri64, double* phi64, const PairShape& shape, hipStream_t s) {
   const int F = h.F;
   int64_t n_chunks = 1;
-  const int chunk = pair_chunk(pc.np, M, &n_chunks);
+  const int chunk = pair_chunk(pc.np, M, shape, &n_chunks);
   const int64_t grid = M * n_chunks;
   if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "interactions grid too large");
   static size_t cache = 0;
@@ -461,10 +462,10 @@ void launch_pairs_fast(const HostTable& h, const DeviceTable& d, const PairClass
 template <typename T>
 void launch_pairs_generic(const HostTable& h, const DeviceTable& d, const PairClass& pc,
                           const float* X, int64_t M, int64_t ldx, const double* leaf_val,
-                          double* tri64, double* phi64, hipStream_t s) {
+                          double* tri64, double* phi64, const PairShape& shape, hipStream_t s) {
   const int F = h.F;
   int64_t n_chunks = 1;
-  const int chunk = pair_chunk(pc.np, M, &n_chunks);
+  const int chunk = pair_chunk(pc.np, M, shape, &n_chunks);
   const int64_t grid = M * n_chunks;
   if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "interactions grid too large");
   static size_t cache = 0;
@@ -489,23 +490,23 @@ void launch_pairs_generic(const HostTable& h, const DeviceTable& d, const PairCl
 
 void launch_pairs(const HostTable& h, const DeviceTable& d, const PairClass& pc, bool fp64,
                   const float* X, int64_t M, int64_t ldx, const double* lv, double* tri64,
-                  double* phi64, hipStream_t s) {
+                  double* phi64, const PairShape& sh, hipStream_t s) {
   // register-resident lane-per-path instances exist where they do not spill
   if (!fp64) {
     switch (pc.cap) {
-      case 4: return launch_pairs_fast<float, 4, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
-      case 8: return launch_pairs_fast<float, 8, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
-      case 12: return launch_pairs_fast<float, 12, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
-      case 16: return launch_pairs_fast<float, 16, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
-      case 20: return launch_pairs_fast<float, 20, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
-      case 24: return launch_pairs_fast<float, 24, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
-      default: return launch_pairs_generic<float>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
+      case 4: return launch_pairs_fast<float, 4, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+      case 8: return launch_pairs_fast<float, 8, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+      case 12: return launch_pairs_fast<float, 12, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+      case 16: return launch_pairs_fast<float, 16, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+      case 20: return launch_pairs_fast<float, 20, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+      case 24: return launch_pairs_fast<float, 24, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+      default: return launch_pairs_generic<float>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     }
   }
   switch (pc.cap) {
-    case 4: return launch_pairs_fast<double, 4, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
-    case 8: return launch_pairs_fast<double, 8, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
-    default: return launch_pairs_generic<double>(h, d, pc, X, M, ldx, lv, tri64, phi64, s);
+    case 4: return launch_pairs_fast<double, 4, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+    case 8: return launch_pairs_fast<double, 8, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+    default: return launch_pairs_generic<double>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
   }
 }
 

@@ -322,9 +322,8 @@ namespace {
 // Paths per work item: about 32 rounds of the ~512 resident workgroups
 // (small tail), chunks of at least 256 paths so the per-item tile load and
 // flush stay small next to the path work.
-int values_chunk(int n_paths, int nsb, int requested) {
-  if (requested > 0) return requested;
-  const int64_t want_items = 32 * 512;
+int values_chunk(int n_paths, int nsb, int items) {
+  const int64_t want_items = items > 0 ? items : 16384;
   int64_t n_chunks = (want_items + nsb - 1) / nsb;
   n_chunks = std::max<int64_t>(1, std::min<int64_t>(n_chunks, (n_paths + 255) / 256));
   return (int)((n_paths + n_chunks - 1) / n_chunks);
@@ -350,7 +349,7 @@ void launch_one(const HostTable& h, const DeviceTable& d, const Bucket& bk, cons
   const int F = h.F;
   const int nsb = (int)((M + kSamplesPerBlock - 1) / kSamplesPerBlock);
   const int n_paths = bk.path_end - bk.path_begin;
-  const int chunk = values_chunk(n_paths, nsb, shape.chunk);
+  const int chunk = values_chunk(n_paths, nsb, shape.items);
   const int n_chunks = (n_paths + chunk - 1) / chunk;
   const int64_t grid = (int64_t)nsb * n_chunks;
   if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "grid too large");
@@ -376,7 +375,7 @@ void launch_adj_one(const HostTable& h, const DeviceTable& d, const Bucket& bk, 
   const int F = h.F;
   const int nsb = (int)((M + kSamplesPerBlock - 1) / kSamplesPerBlock);
   const int n_paths = bk.path_end - bk.path_begin;
-  const int chunk = values_chunk(n_paths, nsb, shape.chunk);
+  const int chunk = values_chunk(n_paths, nsb, shape.items);
   const int n_chunks = (n_paths + chunk - 1) / chunk;
   const int64_t grid = (int64_t)nsb * n_chunks;
   if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "grid too large");

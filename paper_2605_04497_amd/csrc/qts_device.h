@@ -40,10 +40,16 @@ struct DeviceTable {
   NodeConsts<double> n64;
 };
 
-// Launch shape of the first-order kernel for one bucket.
+// Launch shape of the first-order (and adjoint) kernel for one bucket.
 struct ValuesShape {
   int waves_per_block = 8;  // wavefronts sharing one 64-sample tile
-  int chunk = 0;            // paths per work item (0 = derive from size)
+  int items = 16384;        // target number of (sample block, path chunk) work items
+};
+
+// Launch shape of the interactions kernel for one capacity class.
+struct PairShape {
+  int max_chunk = 65536;  // most paths per (sample, chunk) work item
+  int fill = 2048;        // least work items when there are few samples
 };
 
 constexpr int kTileStride = kSamplesPerBlock + 1;  // padded LDS row (bank spread)
@@ -68,6 +74,8 @@ __device__ __forceinline__ T ldu(const T* p) {
 }
 
 void launch_fill_zero(double* p, int64_t n, hipStream_t s);
+// Seeded uniform values in [-3, 3) (inputs for timing launch shapes).
+void launch_fill_uniform(float* p, int64_t n, uint32_t seed, hipStream_t s);
 void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 
 // Accumulate phi (FP64, [M,F], pre-zeroed) over the paths of one bucket.
@@ -85,7 +93,7 @@ void launch_adjoint(const HostTable& h, const DeviceTable& d, const Bucket& bk, 
 // (both pre-zeroed) over the paths of one capacity class.
 void launch_pairs(const HostTable& h, const DeviceTable& d, const PairClass& pc, bool fp64,
                   const float* X, int64_t M, int64_t ldx, const double* leaf_val, double* tri64,
-                  double* phi64, hipStream_t s);
+                  double* phi64, const PairShape& shape, hipStream_t s);
 // Phi[M][F][F] (and phi[M][F] when non-null) in FP32 or FP64 from the accumulators.
 void launch_pairs_finalize(const double* tri64, const double* phi64, int64_t M, int F, bool fp64,
                            void* Phi, void* phi, hipStream_t s);

@@ -1,0 +1,153 @@
+"""Batching and launch: the launch-shape autotuner and HIP graph replay.
+
+Every tuned shape must keep parity with the FP64 oracle, and every graph
+replay must equal the eager call on the same inputs, replay after replay, with
+other eager GPU work and host synchronisations in between (a graph reads its
+input buffers at replay time, so new contents of the same X must show)."""
+import numpy as np
+import pytest
+
+import synth
+from tests.parity import check, row_normwise
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def q():
+    import paper_2605_04497_amd as q
+    return q
+
+
+VALUES_WAVES = {4, 8}
+VALUES_ITEMS = {4096, 8192, 16384, 32768, 65536}
+PAIR_CHUNKS = {8192, 32768, 131072}
+PAIR_FILL = {1024, 4096}
+
+
+def test_default_shapes(q):
+    wl = synth.make_workload("c1_small", M=8)
+    e = q.Ensemble(wl.ensemble)
+    assert e.launch_shape("values", "fp32", 0) == (8, 16384)
+    assert e.launch_shape("interactions", "fp32", 0) == (65536, 2048)
+    with pytest.raises(q.QtsError):
+        e.launch_shape("values", "fp32", 4)
+
+
+@pytest.mark.parametrize("name,over", [
+    ("c2_values", dict(T=40, M=3000, n_train=20000)),
+    ("c5_deep", dict(T=3, M=200, n_train=30000)),      # buckets 8..64 and long classes
+])
+def test_autotune_keeps_parity(q, oracle_mod, name, over):
+    print("case", name, over, flush=True)
+    wl = synth.make_workload(name, **over)
+    e = q.Ensemble(wl.ensemble)
+    X = torch.from_numpy(wl.X).cuda()
+    rows = slice(0, 24)
+    phi_o, Phi_o = oracle_mod.shap_interactions(wl.ensemble, wl.X[rows], n=8)
+    want = oracle_mod.shap_values(wl.ensemble, wl.X, n=8)
+    for precision in ("fp32", "fp64"):
+        e.autotune(wl.X.shape[0], precision)
+        for i in range(4):
+            w, items = e.launch_shape("values", precision, i)
+            assert w in VALUES_WAVES and items in VALUES_ITEMS, (w, items)
+        for i in range(e.info["n_pair_classes"]):
+            mc, fill = e.launch_shape("interactions", precision, i)
+            assert mc in PAIR_CHUNKS and fill in PAIR_FILL, (mc, fill)
+        phi = e.shap_values(X, precision).double().cpu().numpy()
+        check(phi, want, precision, name + " tuned phi")
+        Phi = e.shap_interactions(X[rows], precision).double().cpu().numpy()
+        check(Phi, Phi_o, precision, name + " tuned Phi")
+
+
+def _eager_values(q, ens, X, precision):
+    e = q.Ensemble(ens)
+    out = e.shap_values(X, precision).clone()
+    e.close()
+    return out
+
+
+@pytest.mark.parametrize("name,over", [
+    ("c1_small", dict(M=300)),
+    ("c5_deep", dict(T=3, M=150, n_train=30000)),     # four buckets: parallel branches
+])
+def test_graph_replay_values(q, oracle_mod, name, over):
+    print("case", name, over, flush=True)
+    wl = synth.make_workload(name, **over)
+    e = q.Ensemble(wl.ensemble)
+    e.set_graph_replay(True)
+    X = torch.from_numpy(wl.X).cuda()
+    rng = np.random.default_rng(5)
+    X2h = rng.standard_normal(wl.X.shape).astype(np.float32)
+    for precision in ("fp32", "fp64"):
+        out = torch.empty((X.shape[0], e.n_features), dtype=torch.float32 if precision == "fp32"
+                          else torch.float64, device="cuda")
+        ref1 = _eager_values(q, wl.ensemble, X, precision)
+        ref2 = _eager_values(q, wl.ensemble, torch.from_numpy(X2h).cuda(), precision)
+        Xbuf = X.clone()
+        n0 = e.refresh_info()["n_graphs"]
+        tol = 1e-6 if precision == "fp32" else 1e-13
+        for rep in range(4):
+            # eager GPU work and a host synchronisation between replays
+            junk = torch.randn(1 << 16, device="cuda").cumsum(0)
+            torch.cuda.synchronize()
+            if rep == 2:                       # same buffer, new contents
+                Xbuf.copy_(torch.from_numpy(X2h).cuda())
+            e.shap_values(Xbuf, precision, out=out)
+            torch.cuda.synchronize()
+            ref = ref2 if rep >= 2 else ref1
+            assert row_normwise(out.double().cpu().numpy(), ref.double().cpu().numpy()) <= tol
+            del junk
+        assert e.refresh_info()["n_graphs"] == n0 + 1   # captured once, replayed after
+        check(out.double().cpu().numpy(), oracle_mod.shap_values(wl.ensemble, X2h, n=8),
+              precision, name + " replay vs oracle")
+    e.set_graph_replay(False)
+    assert e.refresh_info()["n_graphs"] == 0
+
+
+def test_graph_replay_interactions_and_backward(q, oracle_mod):
+    wl = synth.make_workload("c3_interactions", T=4, M=20, n_train=20000)
+    ens = wl.ensemble
+    e = q.Ensemble(ens)
+    X = torch.from_numpy(wl.X).cuda()
+    phi_o, Phi_o = oracle_mod.shap_interactions(ens, wl.X, n=8)
+    G = np.random.default_rng(8).normal(size=(wl.X.shape[0], ens.n_features))
+    e.set_graph_replay(True)
+    for precision in ("fp32", "fp64"):
+        dt = torch.float32 if precision == "fp32" else torch.float64
+        Phi = torch.empty((X.shape[0], e.n_features, e.n_features), dtype=dt, device="cuda")
+        phi = torch.empty((X.shape[0], e.n_features), dtype=dt, device="cuda")
+        Gd = torch.from_numpy(G).cuda().to(dt)
+        gl = torch.empty(e.n_leaves, dtype=torch.float64, device="cuda")
+        Gw = Gd.double().cpu().numpy()
+        want_g = oracle_mod.leaf_grad(ens, wl.X, Gw)
+        for rep in range(3):
+            torch.randn(4096, device="cuda").sum()
+            torch.cuda.synchronize()
+            e.shap_interactions(X, precision, with_phi=True, out=Phi, out_phi=phi)
+            e.shap_backward(X, Gd, precision, out=gl)
+            torch.cuda.synchronize()
+            check(Phi.double().cpu().numpy(), Phi_o, precision, "replay Phi %d" % rep)
+            check(phi.double().cpu().numpy(), phi_o, precision, "replay phi %d" % rep)
+            g = gl.cpu().numpy()
+            err = np.abs(g - want_g).max() / np.abs(want_g).max()
+            assert err <= (1e-5 if precision == "fp32" else 1e-10), err
+    assert e.refresh_info()["n_graphs"] == 4
+
+
+def test_graph_cache_eviction(q, oracle_mod):
+    """More keys than the cache holds: the least recently used graphs are
+    dropped and every call still returns the right result."""
+    wl = synth.make_workload("c1_small", M=40)
+    e = q.Ensemble(wl.ensemble)
+    e.set_graph_replay(True)
+    X = torch.from_numpy(wl.X).cuda()
+    want = oracle_mod.shap_values(wl.ensemble, wl.X, n=8)
+    for k in range(20):
+        m = 20 + k            # a new (M) key each time
+        out = e.shap_values(X[:m], "fp64")
+        torch.cuda.synchronize()
+        assert row_normwise(out.cpu().numpy(), want[:m]) <= 1e-10
+    assert e.refresh_info()["n_graphs"] == 16
