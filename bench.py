@@ -33,6 +33,9 @@ METRIC = "sample-tree-leaf paths/s for SHAP, FP32 vs FP64 GPU, at max rel err â‰
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PEAK_FP32_PACKED_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+# LDS FP64 atomic add, measured on MI355X: 2.45 lanes per clock per CU, random
+# addresses in an 80 KB table (the interactions kernel's accumulator)
+LDS_F64_ATOMIC_RATE = 2.45 * 256 * 2.4e9
 FLOPS_PER_ELEMENT = 51  # per (sample, path, unique feature): 8 nodes x 6 + 3
 
 
@@ -62,6 +65,10 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the interactions and adjoint measurements")
     ap.add_argument("--pair-samples", type=int, default=1024)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes")
+    ap.add_argument("--eager", action="store_true",
+                    help="launch eagerly instead of replaying a captured HIP graph")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MB (a "
                          "known-size reference for the memory counters)")
@@ -69,26 +76,31 @@ def parse():
 
 
 def time_steps(fn, steps, warmup, torch, kind="values"):
+    """Run `warmup` untimed steps, then `steps` timed ones on the current
+    stream: HIP events around each step (spread) and around the whole run,
+    and the library's own event pairs around its launches (kernel time)."""
     import paper_2605_04497_amd as q
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     q.read_kernel_timing(kind)  # drop warmup events
     q.set_kernel_timing(True)
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    start.record()
-    for _ in range(steps):
+    ev[0].record()
+    for i in range(steps):
         fn()
-    stop.record()
+        ev[i + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     q.set_kernel_timing(False)
     kern_ms, calls = q.read_kernel_timing(kind)
-    return {"ms_per_step": start.elapsed_time(stop) / steps, "wall_s": wall,
-            "kernel_ms": kern_ms / max(1, calls), "calls": calls}
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    return {"ms_per_step": ev[0].elapsed_time(ev[steps]) / steps, "wall_s": wall,
+            "kernel_ms": kern_ms / max(1, calls), "calls": calls,
+            "step_ms_median": float(np.median(per)), "step_ms_min": float(min(per)),
+            "step_ms_max": float(max(per))}
 
 
 def cpu_baseline(ens, X, seconds, oracle):
@@ -128,16 +140,26 @@ def measure_interactions(args, torch, q, synth, oracle, dev):
     X = torch.from_numpy(wl.X).to(dev)
     M = X.shape[0]
     tab = e.export_paths()
-    flops = float(M) * float(pair_flops(tab["path_len"]).sum())
+    d = tab["path_len"].astype(np.float64)
+    flops = float(M) * float(pair_flops(d).sum())
+    pairs = float(M) * float((d * (d - 1) / 2).sum())
+    F = e.n_features
     res = {}
-    for prec in ("fp32", "fp64"):
-        r = time_steps(lambda: e.shap_interactions(X, prec), 3, 1, torch, "interactions")
-        res[prec] = r
+    for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+        if not args.no_autotune:
+            e.autotune(M, prec)
+        e.set_graph_replay(not args.eager)
+        Phi = torch.empty((M, F, F), dtype=dt, device=dev)
+        res[prec] = time_steps(lambda: e.shap_interactions(X, prec, out=Phi), 3, 1, torch,
+                               "interactions")
+        del Phi
+        e.set_graph_replay(False)
     Phi = e.shap_interactions(X[:2], "fp32").double().cpu().numpy()
     _, Phi_o = oracle.shap_interactions(ens, wl.X[:2], n=8)
     err = float((np.abs(Phi - Phi_o).reshape(2, -1).max(1)
                  / np.abs(Phi_o).reshape(2, -1).max(1)).max())
     ach = flops / (res["fp32"]["kernel_ms"] * 1e-3) / 1e12
+    lds_rate = pairs / (res["fp32"]["kernel_ms"] * 1e-3)
     out = {"workload": "c3_interactions: 500 grown trees, depths 3..20, leaf cap 4096, 200 "
                        "features; first %d of the 50k explained samples" % M,
            "samples": M, "leaves": e.n_leaves, "mean_unique": float(tab["path_len"].mean()),
@@ -145,7 +167,11 @@ def measure_interactions(args, torch, q, synth, oracle, dev):
            "ms_per_step": res["fp32"]["ms_per_step"], "kernel_ms": res["fp32"]["kernel_ms"],
            "fp64_ms_per_step": res["fp64"]["ms_per_step"],
            "max_rel_err_fp32": err, "rows_checked": 2,
-           "alu_tflops": ach, "frac_of_valu_peak": ach / PEAK_VALU_TFLOPS}
+           "alu_tflops": ach, "frac_of_valu_peak": ach / PEAK_VALU_TFLOPS,
+           "pair_updates_per_s": lds_rate,
+           "frac_of_lds_f64_atomic_rate": lds_rate / LDS_F64_ATOMIC_RATE,
+           "fp64_kernel_ms": res["fp64"]["kernel_ms"],
+           "launch": "hipGraph replay" if not args.eager else "eager"}
     e.close()
     return out
 
@@ -161,8 +187,14 @@ def measure_adjoint(args, torch, q, synth, oracle, dev):
                                 - wl.target.astype(np.float64))).to(dev)
     G32 = G.float()
     res = {}
+    gl = torch.empty(e.n_leaves, dtype=torch.float64, device=dev)
     for prec, g in (("fp32", G32), ("fp64", G)):
-        res[prec] = time_steps(lambda: e.shap_backward(X, g, prec), 10, 2, torch, "backward")
+        if not args.no_autotune:
+            e.autotune(M, prec)
+        e.set_graph_replay(not args.eager)
+        res[prec] = time_steps(lambda: e.shap_backward(X, g, prec, out=gl), 10, 2, torch,
+                               "backward")
+        e.set_graph_replay(False)
     rows = np.arange(0, M, 10)
     want = oracle.leaf_grad(ens, wl.X[rows], G32.double().cpu().numpy()[rows])
     got = e.shap_backward(X[torch.from_numpy(rows).to(dev)], G32[torch.from_numpy(rows).to(dev)],
@@ -219,6 +251,15 @@ def main():
     M = X.shape[0]
     units = M * e.n_leaves
     n_el = e.info["n_elements"]
+    tune_s = 0.0
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        for prec in ("fp32", "fp64"):
+            e.autotune(M, prec)
+        tune_s = time.perf_counter() - t0
+        log("autotune: %.1f s; fp32 shape %s, fp64 shape %s" % (
+            tune_s, e.launch_shape("values", "fp32", 0), e.launch_shape("values", "fp64", 0)))
+    e.set_graph_replay(not args.eager)
 
     out32 = torch.empty((M, e.n_features), dtype=torch.float32, device=dev)
     out64 = torch.empty((M, e.n_features), dtype=torch.float64, device=dev)
@@ -262,12 +303,21 @@ def main():
                    "max_unique": e.info["max_unique"]},
         "max_rel_err": {"fp32": err32, "fp64": err64, "rows_checked": int(len(rows)),
                         "measure": "row-normwise vs FP64 oracle (8 nodes)"},
+        "launch": {"mode": "hipGraph replay" if not args.eager else "eager",
+                   "autotuned": not args.no_autotune, "autotune_s": tune_s,
+                   "values_shape_fp32": list(e.launch_shape("values", "fp32", 0)),
+                   "values_shape_fp64": list(e.launch_shape("values", "fp64", 0)),
+                   "step_ms_median": r32["step_ms_median"], "step_ms_min": r32["step_ms_min"],
+                   "step_ms_max": r32["step_ms_max"]},
         "fp64": {"value": units / (r64["ms_per_step"] * 1e-3), "ms_per_step": r64["ms_per_step"],
                  "kernel_ms": r64["kernel_ms"], "dtype": "f64",
                  "speedup_fp32_over_fp64": r64["ms_per_step"] / r32["ms_per_step"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
-                     "kernel": "values_kernel<float,8,...>", "kernel_ms": r32["kernel_ms"],
+                     "kernel": "values_kernel<float, 8, 8, true>", "kernel_ms": r32["kernel_ms"],
+                     "kernel_ms_scope": "event pair around each graph replay (zero-fill, "
+                                        "values kernel, cast)" if not args.eager else
+                                        "event pair around the values kernel launches",
                      "flops_per_launch": flops,
                      "peak_fp32_packed": PEAK_FP32_PACKED_TFLOPS,
                      "frac_of_packed_peak": achieved / PEAK_FP32_PACKED_TFLOPS},

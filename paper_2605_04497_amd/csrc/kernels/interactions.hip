@@ -135,17 +135,29 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
     const int d = valid ? d0 : 0;
     T val = valid ? (T)val0 : T(0);
     // feature, row offset of its pairs in this launch's triangle rows, and
-    // whether those rows are in range
+    // whether those rows are in range; then the slot's c = o - b and b (a
+    // slot with b = 0 and o = 0 zeroes the path: its b is replaced by 1)
     int f[C], rb[C];
     bool inr[C];
-    float xv[C];
+    T cj[C], bj[C];
+    bool dead = false;
 #pragma unroll
     for (int j = 0; j < C; ++j) {
       f[j] = fm[j] & kFeatureMask;
       rb[j] = (int)(tri_row(f[j]) - base0);
       inr[j] = (f[j] >= r0) & (f[j] < r1) & (j < d);
-      xv[j] = xrow[f[j]];
+      const float x = xrow[f[j]];
+      const bool miss = (fm[j] & kMissingOkBit) != 0;
+      const bool lower = miss ? !(x < lov[j]) : (x >= lov[j]);
+      const bool upper = !(x >= hiv[j]);
+      const T b = bv[j];
+      const T c = (lower & upper) ? cbv[j] : -b;
+      const bool z = (b == T(0)) & (c == T(0));
+      dead |= z;
+      cj[j] = c;
+      bj[j] = z ? T(1) : b;
     }
+    if (dead) val = T(0);
 
 #pragma unroll
     for (int pass = 0; pass < kNodes / NH; ++pass) {
@@ -154,26 +166,15 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
 #pragma unroll
       for (int m = 0; m < NH; ++m) H[m] = T(1);
       T r[C][NH];
-      bool dead = false;
 #pragma unroll
       for (int j = 0; j < C; ++j) {
-        const float x = xv[j];
-        const bool miss = (fm[j] & kMissingOkBit) != 0;
-        const bool lower = miss ? !(x < lov[j]) : (x >= lov[j]);
-        const bool upper = !(x >= hiv[j]);
-        const T b = bv[j];
-        const T c = (lower & upper) ? cbv[j] : -b;
-        const bool z = (b == T(0)) & (c == T(0));
-        dead |= z;
-        const T bz = z ? T(1) : b;
 #pragma unroll
         for (int m = 0; m < NH; ++m) {
-          const T Fv = fmaP(nc.t[m0 + m], c, bz);
+          const T Fv = fmaP(nc.t[m0 + m], cj[j], bj[j]);
           H[m] *= Fv;
-          r[j][m] = c * rcpP(Fv);
+          r[j][m] = cj[j] * rcpP(Fv);
         }
       }
-      if (dead) val = T(0);
       T G[NH];
 #pragma unroll
       for (int m = 0; m < NH; ++m) G[m] = nc.w[m0 + m] * val * H[m];
@@ -506,6 +507,9 @@ void launch_pairs(const HostTable& h, const DeviceTable& d, const PairClass& pc,
   switch (pc.cap) {
     case 4: return launch_pairs_fast<double, 4, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     case 8: return launch_pairs_fast<double, 8, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+    case 12: return launch_pairs_fast<double, 12, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+    case 16: return launch_pairs_fast<double, 16, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+    case 20: return launch_pairs_fast<double, 20, 2>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     default: return launch_pairs_generic<double>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
   }
 }
