@@ -114,6 +114,9 @@ typedef struct {
   int32_t device;      /* -1 for a host-only ensemble */
   int32_t n_pair_classes;  /* capacity classes of the interactions table */
   int32_t n_graphs;        /* graphs held by the replay cache */
+  int64_t n_merged;        /* sibling-leaf pairs merged in the first-order table */
+  int64_t n_value_paths;   /* rows of the first-order table (n_paths - n_merged) */
+  int64_t n_value_elements;  /* sum of d over those rows */
 } qts_info;
 
 int qts_get_info(const qts_ensemble* ens, qts_info* out);
@@ -180,6 +183,21 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
  * (0 .. n_pair_classes-1) -> (largest path chunk, least work items). */
 int qts_get_launch_shape(const qts_ensemble* ens, int32_t kind, qts_precision precision,
                          int32_t index, int32_t* a, int32_t* b);
+
+/* Sibling merging for qts_shap_values (on by default).  Two leaves A, B that
+ * are the two children of one node have the same collapsed feature set and
+ * differ only in the element of the node's split feature L.  Their
+ * polynomials of Eq. 7 (multiplied through by b) therefore share every factor
+ * but L's, and since phi is linear in each path's polynomial,
+ *   vA prod_j F^A_j(p) + vB prod_j F^B_j(p)
+ *     = (vA F^A_L(p) + vB F^B_L(p)) prod_{j != L} F_j(p),
+ * which is again linear in p in the L factor.  With merging on, the first-order
+ * kernel walks one path per such pair, carrying that combined factor (built
+ * in FP64 from the current leaf values) and a leaf value of 1: the same
+ * result up to rounding, with about half the work on full trees.  The
+ * interactions and adjoint calls always walk every path.  Changing the
+ * setting drops the ensemble's cached graphs. */
+int qts_set_sibling_merge(qts_ensemble* ens, int32_t enable);
 
 /* HIP graph replay.  While enabled, each compute call on this ensemble is
  * captured once (on an internal stream, with its per-bucket or per-class

@@ -39,7 +39,8 @@ class Info(ctypes.Structure):
                 ("n_elements", ctypes.c_int64), ("max_depth", ctypes.c_int32),
                 ("max_unique", ctypes.c_int32), ("n_buckets", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("n_pair_classes", ctypes.c_int32),
-                ("n_graphs", ctypes.c_int32)]
+                ("n_graphs", ctypes.c_int32), ("n_merged", ctypes.c_int64),
+                ("n_value_paths", ctypes.c_int64), ("n_value_elements", ctypes.c_int64)]
 
 
 # exported symbol -> (restype, argtypes)
@@ -65,6 +66,7 @@ SIGNATURES = {
                                             ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_int32)]),
     "qts_set_graph_replay": (ctypes.c_int, [P, ctypes.c_int32]),
+    "qts_set_sibling_merge": (ctypes.c_int, [P, ctypes.c_int32]),
     "qts_set_kernel_timing": (ctypes.c_int, [ctypes.c_int32]),
     "qts_kernel_timing_read": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_int64)]),

@@ -186,6 +186,11 @@ class Ensemble:
         with torch.cuda.device(self.device):
             L.check(L.lib().qts_set_graph_replay(self._h, int(bool(enable))))
 
+    def set_sibling_merge(self, enable: bool = True):
+        """First-order calls walk one merged path per pair of sibling leaves
+        (default) or every path (exact same values up to rounding)."""
+        L.check(L.lib().qts_set_sibling_merge(self._h, int(bool(enable))))
+
     def refresh_info(self) -> dict:
         info = L.Info()
         L.check(L.lib().qts_get_info(self._h, ctypes.byref(info)))

@@ -65,6 +65,7 @@ struct qts_ensemble {
   // and per pair capacity class and precision (defaults until autotuned)
   qts::ValuesShape vshape[2][4];
   std::vector<qts::PairShape> pshape[2];
+  bool merge_siblings = true;  // first-order calls walk the merged table
   qts::GraphCache graphs;
 };
 
@@ -118,10 +119,66 @@ std::vector<T> narrow(const std::vector<double>& v) {
   return out;
 }
 
+// Device layout of a first-order path table: every path is padded to whole
+// batches of eight elements with inert slots (feature 0, no bounds,
+// missing_ok, b = 1, 1-b = 0): their factor is exactly 1 and their
+// contribution 0, so the kernels process whole batches without per-slot
+// tests.  Eight more inert slots follow the last path.  Synchronous with
+// respect to the host vectors (waits on the stream).
+void upload_paths(const std::vector<PathHdr>& hdr_in, const std::vector<int32_t>& feat_in,
+                  const std::vector<float>& lo_in, const std::vector<float>& hi_in,
+                  const std::vector<double>& b_in, const std::vector<double>& cb_in,
+                  hipStream_t s, PathHdr** o_hdr, int32_t** o_feat, float** o_lo, float** o_hi,
+                  float** o_b32, float** o_cb32, double** o_b64, double** o_cb64) {
+  std::vector<PathHdr> hdr = hdr_in;
+  std::vector<int32_t> feat;
+  std::vector<float> lo, hi;
+  std::vector<double> b64, cb64;
+  size_t n_pad = 0;
+  for (const PathHdr& p : hdr_in) n_pad += (size_t)((p.d + 7) / 8) * 8;
+  feat.reserve(n_pad + kPad);
+  lo.reserve(n_pad + kPad);
+  hi.reserve(n_pad + kPad);
+  b64.reserve(n_pad + kPad);
+  cb64.reserve(n_pad + kPad);
+  for (size_t i = 0; i < hdr_in.size(); ++i) {
+    const PathHdr& p = hdr_in[i];
+    hdr[i].off = (int32_t)feat.size();
+    const int padded_d = (p.d + 7) / 8 * 8;
+    for (int k = 0; k < padded_d; ++k) {
+      const bool real = k < p.d;
+      const size_t e = (size_t)p.off + (size_t)k;
+      feat.push_back(real ? feat_in[e] : kMissingOkBit);
+      lo.push_back(real ? lo_in[e] : -INFINITY);
+      hi.push_back(real ? hi_in[e] : NAN);
+      b64.push_back(real ? b_in[e] : 1.0);
+      cb64.push_back(real ? cb_in[e] : 0.0);
+    }
+  }
+  if (feat.size() > (size_t)0x7fffffff) fail(QTS_E_UNSUPPORTED, "path table too large");
+  feat = padded(feat, (int32_t)kMissingOkBit);
+  lo = padded(lo, -INFINITY);
+  hi = padded(hi, NAN);
+  b64 = padded(b64, 1.0);
+  cb64 = padded(cb64, 0.0);
+  std::vector<float> b32 = narrow<float>(b64), cb32 = narrow<float>(cb64);
+  *o_hdr = upload(hdr, s);
+  *o_feat = upload(feat, s);
+  *o_lo = upload(lo, s);
+  *o_hi = upload(hi, s);
+  *o_b32 = upload(b32, s);
+  *o_cb32 = upload(cb32, s);
+  *o_b64 = upload(b64, s);
+  *o_cb64 = upload(cb64, s);
+  check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
 void free_device(DeviceTable& d) {
   void* ptrs[] = {d.hdr,    d.feat,    d.lo,      d.hi,      d.b32,     d.cb32,
                   d.b64,    d.cb64,    d.leaf_val, d.pr_d,   d.pr_leaf, d.pr_feat,
-                  d.pr_lo,  d.pr_hi,   d.pr_b32,  d.pr_cb32, d.pr_b64,  d.pr_cb64};
+                  d.pr_lo,  d.pr_hi,   d.pr_b32,  d.pr_cb32, d.pr_b64,  d.pr_cb64,
+                  d.mhdr,   d.mfeat,   d.mlo,     d.mhi,     d.mb32,    d.mcb32,
+                  d.mb64,   d.mcb64,   d.side};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   d = DeviceTable{};
@@ -257,10 +314,12 @@ void issue_values(const qts_ensemble* ens, const float* X, int64_t M, int64_t ld
   double* a = fp64 ? (double*)phi : acc;
   launch_fill_zero(a, n, ln.main);
   TimedScope ts(0, timed ? ln.main : nullptr, timed);
-  ln.fork((int)h.buckets.size());
-  for (size_t i = 0; i < h.buckets.size(); ++i) {
-    const Bucket& bk = h.buckets[i];
-    launch_values(h, ens->dev, bk, fp64, X, M, ldx, leaf, a,
+  const std::vector<Bucket>& bks = ens->merge_siblings ? h.mbuckets : h.buckets;
+  const PathArrays arr = ens->merge_siblings ? merged_arrays(ens->dev) : plain_arrays(ens->dev);
+  ln.fork((int)bks.size());
+  for (size_t i = 0; i < bks.size(); ++i) {
+    const Bucket& bk = bks[i];
+    launch_values(h, ens->dev, arr, bk, fp64, X, M, ldx, leaf, a,
                   ens->vshape[fp64 ? 1 : 0][cap_index(bk.dmax)], ln.pick((int)i));
   }
   ln.join();
@@ -432,47 +491,11 @@ int qts_load_ensemble(const qts_tree_arrays* trees, int32_t n_features, double b
       DeviceTable& d = e->dev;
       check_hip(hipGetDevice(&d.device), "hipGetDevice");
       build_nodes(d);
-      // Device layout: every path is padded to whole batches of eight
-      // elements with inert slots (feature 0, no bounds, missing_ok, b = 1,
-      // 1-b = 0): their factor is exactly 1 and their contribution 0, so the
-      // kernels process whole batches without per-slot tests.
-      std::vector<PathHdr> hdr = h.hdr;
-      std::vector<int32_t> feat;
-      std::vector<float> lo, hi;
-      std::vector<double> b64, cb64;
-      size_t n_pad = 0;
-      for (const PathHdr& p : h.hdr) n_pad += (size_t)((p.d + 7) / 8) * 8;
-      feat.reserve(n_pad); lo.reserve(n_pad); hi.reserve(n_pad);
-      b64.reserve(n_pad); cb64.reserve(n_pad);
-      for (size_t i = 0; i < h.hdr.size(); ++i) {
-        const PathHdr& p = h.hdr[i];
-        hdr[i].off = (int32_t)feat.size();
-        const int padded_d = (p.d + 7) / 8 * 8;
-        for (int k = 0; k < padded_d; ++k) {
-          const bool real = k < p.d;
-          const size_t e = (size_t)p.off + (size_t)k;
-          feat.push_back(real ? h.feat[e] : kMissingOkBit);
-          lo.push_back(real ? h.lo[e] : -INFINITY);
-          hi.push_back(real ? h.hi[e] : NAN);
-          b64.push_back(real ? h.b[e] : 1.0);
-          cb64.push_back(real ? h.cb[e] : 0.0);
-        }
-      }
-      if (feat.size() > (size_t)0x7fffffff) fail(QTS_E_UNSUPPORTED, "path table too large");
-      feat = padded(feat, (int32_t)kMissingOkBit);
-      lo = padded(lo, -INFINITY);
-      hi = padded(hi, NAN);
-      b64 = padded(b64, 1.0);
-      cb64 = padded(cb64, 0.0);
-      std::vector<float> b32 = narrow<float>(b64), cb32 = narrow<float>(cb64);
-      d.hdr = upload(hdr, s);
-      d.feat = upload(feat, s);
-      d.lo = upload(lo, s);
-      d.hi = upload(hi, s);
-      d.b32 = upload(b32, s);
-      d.cb32 = upload(cb32, s);
-      d.b64 = upload(b64, s);
-      d.cb64 = upload(cb64, s);
+      upload_paths(h.hdr, h.feat, h.lo, h.hi, h.b, h.cb, s, &d.hdr, &d.feat, &d.lo, &d.hi,
+                   &d.b32, &d.cb32, &d.b64, &d.cb64);
+      upload_paths(h.mhdr, h.mfeat, h.mlo, h.mhi, h.mb, h.mcb, s, &d.mhdr, &d.mfeat, &d.mlo,
+                   &d.mhi, &d.mb32, &d.mcb32, &d.mb64, &d.mcb64);
+      d.side = upload(h.side, s);
       d.leaf_val = upload(h.leaf_value, s);
       {
         PairTable pt = build_pair_table(h);
@@ -482,8 +505,9 @@ int qts_load_ensemble(const qts_tree_arrays* trees, int32_t n_features, double b
         d.pr_feat = upload(pt.feat, s);
         d.pr_lo = upload(pt.lo, s);
         d.pr_hi = upload(pt.hi, s);
-        d.pr_b32 = upload(narrow<float>(pt.b), s);
-        d.pr_cb32 = upload(narrow<float>(pt.cb), s);
+        const std::vector<float> pb32 = narrow<float>(pt.b), pcb32 = narrow<float>(pt.cb);
+        d.pr_b32 = upload(pb32, s);
+        d.pr_cb32 = upload(pcb32, s);
         d.pr_b64 = upload(pt.b, s);
         d.pr_cb64 = upload(pt.cb, s);
         // the uploads above are asynchronous: wait before the host vectors die
@@ -541,6 +565,9 @@ int qts_get_info(const qts_ensemble* ens, qts_info* out) {
     out->device = ens->on_device ? ens->dev.device : -1;
     out->n_pair_classes = (int32_t)ens->pair_classes.size();
     out->n_graphs = (int32_t)ens->graphs.entries.size();
+    out->n_merged = (int64_t)h.side.size();
+    out->n_value_paths = (int64_t)h.mhdr.size();
+    out->n_value_elements = (int64_t)h.mfeat.size();
   });
 }
 
@@ -692,6 +719,15 @@ int qts_set_graph_replay(qts_ensemble* ens, int32_t enable) {
   });
 }
 
+int qts_set_sibling_merge(qts_ensemble* ens, int32_t enable) {
+  return guarded([&] {
+    if (!ens) fail(QTS_E_INVALID_ARG, "null ensemble");
+    std::lock_guard<std::mutex> lock(ens->graphs.mu);
+    if (ens->merge_siblings != (enable != 0)) clear_graphs(ens->graphs);
+    ens->merge_siblings = enable != 0;
+  });
+}
+
 int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, void* stream) {
   return guarded([&] {
     if (!ens) fail(QTS_E_INVALID_ARG, "null ensemble");
@@ -737,14 +773,17 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
     {
       Scratch acc(sizeof(double) * (size_t)(Mt * F), s);
       launch_fill_zero((double*)acc.p, Mt * F, s);
-      for (const Bucket& bk : h.buckets) {
+      const std::vector<Bucket>& bks = ens->merge_siblings ? h.mbuckets : h.buckets;
+      const PathArrays arr = ens->merge_siblings ? merged_arrays(d) : plain_arrays(d);
+      for (const Bucket& bk : bks) {
         ValuesShape best;
         float best_ms = 1e30f;
         for (int waves : {4, 8})
           for (int items : {4096, 8192, 16384, 32768, 65536}) {
             const ValuesShape cand{waves, items};
             const float ms = time_ms(3, [&] {
-              launch_values(h, d, bk, fp64, X, Mt, F, d.leaf_val, (double*)acc.p, cand, s);
+              launch_values(h, d, arr, bk, fp64, X, Mt, F, d.leaf_val, (double*)acc.p, cand,
+                            s);
             });
             if (ms < best_ms) {
               best_ms = ms;

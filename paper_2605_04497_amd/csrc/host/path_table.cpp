@@ -12,6 +12,14 @@
 // E[f] = sum over leaves of val * prod_j b_j  (Eq. 1, the game at S = empty).
 // Paths with the same unique-feature capacity (8, 16, 32, 64) are stored
 // contiguously so one kernel instance with a fixed register budget serves them.
+//
+// A second table serves the first-order kernel: there, two leaves that are
+// the children of one node are one merged path (see SidePath).  Their
+// polynomials differ only in the factor of the parent's split feature L, and
+// phi is linear in each leaf's polynomial, so
+//   vA prod_j F^A_j + vB prod_j F^B_j = prod_{j != L} F_j * (vA F^A_L + vB F^B_L)
+// exactly: the merged path carries the combined factor in slot 0 and a leaf
+// value of 1.
 #include <algorithm>
 #include <cmath>
 #include <limits>
@@ -28,11 +36,14 @@ struct Edge {
   float thr;
   bool dleft;
   double w;
+  int32_t parent;  // node the edge leaves
 };
 
 struct RawPath {
   int32_t leaf;
   int32_t tree;
+  int32_t parent = -1;     // parent node of the leaf (-1: the root is the leaf)
+  bool left_child = false;
   std::vector<int32_t> feat;
   std::vector<float> lo, hi;
   std::vector<uint8_t> mok;
@@ -108,7 +119,7 @@ class Builder {
       const int32_t child = c == 0 ? l : r;
       const double cc = t_.cover[base_ + child];
       const double w = cov == 0.0 ? 0.0 : cc / cov;
-      path_.push_back(Edge{f, c == 0, thr, dl, w});
+      path_.push_back(Edge{f, c == 0, thr, dl, w, node});
       visit(child, depth + 1);
       path_.pop_back();
     }
@@ -120,6 +131,10 @@ class Builder {
     RawPath p;
     p.leaf = leaf_ord_[(size_t)node];
     p.tree = tree_;
+    if (!path_.empty()) {
+      p.parent = path_.back().parent;
+      p.left_child = path_.back().left;
+    }
     const float kNoBound = std::numeric_limits<float>::quiet_NaN();
     for (const Edge& e : path_) {
       size_t k = 0;
@@ -221,6 +236,72 @@ HostTable build_host_table(const qts_tree_arrays& t, int32_t F, double base_scor
       h.hi.push_back(p.hi[k]);
       h.b.push_back(p.b[k]);
       h.cb.push_back(1.0 - p.b[k]);
+    }
+  }
+
+  // Merged first-order table.  Leaves are visited left child first, so two
+  // leaf siblings are consecutive in bld.paths.
+  struct Unit {
+    size_t a;
+    int side;  // -1: a single path
+  };
+  std::vector<Unit> units;
+  std::vector<size_t> slot0;  // per unit: the element that goes to slot 0
+  for (size_t i = 0; i < bld.paths.size(); ++i) {
+    const RawPath& A = bld.paths[i];
+    if (i + 1 < bld.paths.size()) {
+      const RawPath& B = bld.paths[i + 1];
+      if (A.parent >= 0 && B.parent == A.parent && B.tree == A.tree && A.left_child &&
+          !B.left_child && A.feat.size() == B.feat.size()) {
+        // the parent's split feature: the only element where A and B differ
+        const int32_t L = t.feature[t.tree_offsets[A.tree] + A.parent];
+        size_t kL = 0;
+        while (kL < A.feat.size() && A.feat[kL] != L) ++kL;
+        if (kL == A.feat.size()) fail(QTS_E_INVALID_MODEL, "internal: split feature not on path");
+        SidePath sp;
+        sp.lo_b = B.lo[kL];
+        sp.hi_b = B.hi[kL];
+        sp.leaf_b = B.leaf;
+        sp.mok_b = B.mok[kL] ? 1 : 0;
+        sp.b_a = A.b[kL];
+        sp.cb_a = 1.0 - A.b[kL];
+        sp.b_b = B.b[kL];
+        sp.cb_b = 1.0 - B.b[kL];
+        units.push_back(Unit{i, (int)h.side.size()});
+        h.side.push_back(sp);
+        slot0.push_back(kL);
+        ++i;
+        continue;
+      }
+    }
+    units.push_back(Unit{i, -1});
+    slot0.push_back(0);
+  }
+  std::vector<size_t> morder(units.size());
+  for (size_t i = 0; i < morder.size(); ++i) morder[i] = i;
+  std::stable_sort(morder.begin(), morder.end(), [&](size_t x, size_t y) {
+    return bucket_capacity((int)bld.paths[units[x].a].feat.size()) <
+           bucket_capacity((int)bld.paths[units[y].a].feat.size());
+  });
+  for (size_t ui : morder) {
+    const RawPath& p = bld.paths[units[ui].a];
+    const int d = (int)p.feat.size();
+    const int cap = bucket_capacity(d);
+    const int32_t pi = (int32_t)h.mhdr.size();
+    if (h.mbuckets.empty() || h.mbuckets.back().dmax != cap)
+      h.mbuckets.push_back(Bucket{cap, pi, pi, 0});
+    h.mbuckets.back().path_end = pi + 1;
+    h.mbuckets.back().elems += d;
+    h.mhdr.push_back(PathHdr{(int32_t)h.mfeat.size(), d, p.leaf, units[ui].side});
+    // element order: the merged slot first, the others in path order
+    const size_t kL = slot0[ui];
+    for (int r = 0; r < d; ++r) {
+      const size_t k = r == 0 ? kL : ((size_t)r <= kL ? (size_t)r - 1 : (size_t)r);
+      h.mfeat.push_back(p.feat[k] | (p.mok[k] ? kMissingOkBit : 0));
+      h.mlo.push_back(p.lo[k]);
+      h.mhi.push_back(p.hi[k]);
+      h.mb.push_back(p.b[k]);
+      h.mcb.push_back(1.0 - p.b[k]);
     }
   }
   return h;

@@ -62,15 +62,42 @@ template <typename T, int DMAX, int NH, bool STORE_G, bool NANS, bool ADJ>
 __device__ __forceinline__ void values_paths(
     const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
     const float* __restrict__ lo, const float* __restrict__ hi, const T* __restrict__ bb,
-    const T* __restrict__ cbb, const double* __restrict__ leaf_val, const float* xs, double* as,
-    const T* gs, double* __restrict__ grad_leaf, int pb, int pe, int wave, int nw, int lane,
-    const T* tv, const NodeConsts<T>& nc) {
+    const T* __restrict__ cbb, const SidePath* __restrict__ side,
+    const double* __restrict__ leaf_val, const float* xs, double* as, const T* gs,
+    double* __restrict__ grad_leaf, int pb, int pe, int wave, int nw, int lane, const T* tv,
+    const NodeConsts<T>& nc) {
   constexpr int NB = DMAX / 8;  // feature batches
   for (int p = pb + wave; p < pe; p += nw) {
     const int d = ldu(&hdr[p].d);
     const int off = ldu(&hdr[p].off);
     const int leaf = ldu(&hdr[p].leaf);
-    const T val = ADJ ? T(1) : (T)ldu(leaf_val + leaf);
+    T val = ADJ ? T(1) : (T)ldu(leaf_val + leaf);
+    // A merged sibling pair (first order only): slot 0 is the parent's split
+    // feature L with factor vA F_A + vB F_B = bm + t c, where c is cA when
+    // the sample follows A's interval, cB when it follows B's, else -bm;
+    // the path's leaf value is then 1.  Built here in FP64 from the leaf
+    // values (which a call may override), then rounded to T.
+    const int sidx = (ADJ || side == nullptr) ? -1 : ldu(&hdr[p].tree);
+    const bool merged = sidx >= 0;
+    T bm = T(0), cA = T(0), cB = T(0);
+    float loB = 0.f, hiB = 0.f;
+    bool mokB = false;
+    if (merged) {
+      const SidePath* sp = side + sidx;
+      const double va = ldu(leaf_val + leaf);
+      const double vb = ldu(leaf_val + ldu(&sp->leaf_b));
+      const double ba = ldu(&sp->b_a), cba = ldu(&sp->cb_a);
+      const double bb2 = ldu(&sp->b_b), cbb2 = ldu(&sp->cb_b);
+      bm = (T)(va * ba + vb * bb2);
+      cA = (T)(va * cba - vb * bb2);
+      cB = (T)(vb * cbb2 - va * ba);
+      loB = ldu(&sp->lo_b);
+      hiB = ldu(&sp->hi_b);
+      mokB = ldu(&sp->mok_b) != 0;
+      val = T(1);
+    }
+    // b_j of slot j (slot 0 of a merged path: bm)
+    auto bload = [&](int j) -> T { return (j == 0 && merged) ? bm : ldu(bb + off + j); };
     double gacc = 0.0;
     const int nb = (d + 7) >> 3;  // batches in use; slots [d, 8 nb) are inert
 
@@ -106,6 +133,13 @@ __device__ __forceinline__ void values_paths(
           }
           const bool upper = !(x[k] >= u[k]);
           cf[jb + k] = (lower & upper) ? cbl[k] : -bl[k];
+          if (b == 0 && k == 0 && merged) {
+            bool lowerB;
+            if (NANS) lowerB = mokB ? !(x[0] < loB) : (x[0] >= loB);
+            else lowerB = x[0] >= loB;
+            const bool upperB = !(x[0] >= hiB);
+            cf[0] = (lower & upper) ? cA : ((lowerB & upperB) ? cB : -bm);
+          }
         }
       }
     }
@@ -125,7 +159,7 @@ __device__ __forceinline__ void values_paths(
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
             const int j = 8 * (b - 1) + k;
-            const T bj = ldu(bb + off + j);
+            const T bj = bload(j);
 #pragma unroll
             for (int m = 0; m < NH; ++m) ck[b][m] *= fmaT(tv[m0 + m], cf[j], bj);
           }
@@ -142,7 +176,7 @@ __device__ __forceinline__ void values_paths(
           const int jb = 8 * b;
           T bj[8];
 #pragma unroll
-          for (int k = 0; k < 8; ++k) bj[k] = ldu(bb + off + jb + k);
+          for (int k = 0; k < 8; ++k) bj[k] = bload(jb + k);
           T Pb[8][NH];
           T Gb[STORE_G ? 8 : 1][NH];
           T run[NH];
@@ -198,6 +232,7 @@ __global__ void __launch_bounds__(512)
 values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
               const float* __restrict__ lo, const float* __restrict__ hi,
               const T* __restrict__ bb, const T* __restrict__ cbb,
+              const SidePath* __restrict__ side,
               const double* __restrict__ leaf_val, const float* __restrict__ X, int64_t M,
               int64_t ldx, int32_t F, int32_t path_begin, int32_t path_end, int32_t chunk,
               int32_t nsb, double* __restrict__ acc, NodeConsts<T> nc) {
@@ -241,11 +276,11 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
   for (int m = 0; m < kNodes; ++m) tv[m] = to_vgpr(nc.t[m]);
 
   if (any_nan)
-    values_paths<T, DMAX, NH, STORE_G, true, false>(hdr, feat, lo, hi, bb, cbb, leaf_val, xs,
+    values_paths<T, DMAX, NH, STORE_G, true, false>(hdr, feat, lo, hi, bb, cbb, side, leaf_val, xs,
                                                     as, nullptr, nullptr, pb, pe, wave, nw, lane,
                                                     tv, nc);
   else
-    values_paths<T, DMAX, NH, STORE_G, false, false>(hdr, feat, lo, hi, bb, cbb, leaf_val, xs,
+    values_paths<T, DMAX, NH, STORE_G, false, false>(hdr, feat, lo, hi, bb, cbb, side, leaf_val, xs,
                                                      as, nullptr, nullptr, pb, pe, wave, nw, lane,
                                                      tv, nc);
   __syncthreads();
@@ -308,11 +343,11 @@ adjoint_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat
 #pragma unroll
   for (int m = 0; m < kNodes; ++m) tv[m] = to_vgpr(nc.t[m]);
   if (any_nan)
-    values_paths<T, DMAX, NH, STORE_G, true, true>(hdr, feat, lo, hi, bb, cbb, nullptr, xs,
+    values_paths<T, DMAX, NH, STORE_G, true, true>(hdr, feat, lo, hi, bb, cbb, nullptr, nullptr, xs,
                                                    nullptr, gs, grad_leaf, pb, pe, wave, nw,
                                                    lane, tv, nc);
   else
-    values_paths<T, DMAX, NH, STORE_G, false, true>(hdr, feat, lo, hi, bb, cbb, nullptr, xs,
+    values_paths<T, DMAX, NH, STORE_G, false, true>(hdr, feat, lo, hi, bb, cbb, nullptr, nullptr, xs,
                                                     nullptr, gs, grad_leaf, pb, pe, wave, nw,
                                                     lane, tv, nc);
 }
@@ -343,8 +378,8 @@ size_t values_lds_limit(const void* fn, size_t* cache) {
 }
 
 template <typename T, int DMAX, int NH, bool STORE_G>
-void launch_one(const HostTable& h, const DeviceTable& d, const Bucket& bk, const float* X,
-                int64_t M, int64_t ldx, const double* leaf_val, double* acc,
+void launch_one(const HostTable& h, const DeviceTable& d, const PathArrays& a, const Bucket& bk,
+                const float* X, int64_t M, int64_t ldx, const double* leaf_val, double* acc,
                 const ValuesShape& shape, hipStream_t s) {
   const int F = h.F;
   const int nsb = (int)((M + kSamplesPerBlock - 1) / kSamplesPerBlock);
@@ -355,16 +390,16 @@ void launch_one(const HostTable& h, const DeviceTable& d, const Bucket& bk, cons
   if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "grid too large");
   const size_t lds = values_lds_bytes(F);
   const int threads = 64 * shape.waves_per_block;
-  const T* b = std::is_same<T, float>::value ? (const T*)d.b32 : (const T*)d.b64;
-  const T* cb = std::is_same<T, float>::value ? (const T*)d.cb32 : (const T*)d.cb64;
+  const T* b = std::is_same<T, float>::value ? (const T*)a.b32 : (const T*)a.b64;
+  const T* cb = std::is_same<T, float>::value ? (const T*)a.cb32 : (const T*)a.cb64;
   NodeConsts<T> nc;
   if constexpr (std::is_same<T, float>::value) nc = d.n32; else nc = d.n64;
   static size_t cache = 0;
   if (lds > values_lds_limit((const void*)values_kernel<T, DMAX, NH, STORE_G>, &cache))
     fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
   hipLaunchKernelGGL((values_kernel<T, DMAX, NH, STORE_G>), dim3((unsigned)grid),
-                     dim3(threads), lds, s, d.hdr, d.feat, d.lo, d.hi, b, cb, leaf_val, X, M,
-                     ldx, F, bk.path_begin, bk.path_end, chunk, nsb, acc, nc);
+                     dim3(threads), lds, s, a.hdr, a.feat, a.lo, a.hi, b, cb, a.side, leaf_val, X,
+                     M, ldx, F, bk.path_begin, bk.path_end, chunk, nsb, acc, nc);
   check_hip(hipGetLastError(), "values_kernel launch");
 }
 
@@ -417,24 +452,24 @@ void launch_adjoint(const HostTable& h, const DeviceTable& d, const Bucket& bk, 
   }
 }
 
-void launch_values(const HostTable& h, const DeviceTable& d, const Bucket& bk, bool fp64,
-                   const float* X, int64_t M, int64_t ldx, const double* leaf_val, double* acc,
-                   const ValuesShape& shape, hipStream_t s) {
+void launch_values(const HostTable& h, const DeviceTable& d, const PathArrays& a,
+                   const Bucket& bk, bool fp64, const float* X, int64_t M, int64_t ldx,
+                   const double* leaf_val, double* acc, const ValuesShape& shape, hipStream_t s) {
   if (values_lds_bytes(h.F) > (size_t)kMaxLdsBytes)
     fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
   if (!fp64) {
     switch (bk.dmax) {
-      case 8: launch_one<float, 8, 8, true>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      case 16: launch_one<float, 16, 8, true>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      case 32: launch_one<float, 32, 8, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      default: launch_one<float, 64, 4, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 8: launch_one<float, 8, 8, true>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 16: launch_one<float, 16, 8, true>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 32: launch_one<float, 32, 8, false>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      default: launch_one<float, 64, 4, false>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
     }
   } else {
     switch (bk.dmax) {
-      case 8: launch_one<double, 8, 8, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      case 16: launch_one<double, 16, 4, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      case 32: launch_one<double, 32, 4, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      default: launch_one<double, 64, 2, false>(h, d, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 8: launch_one<double, 8, 8, false>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 16: launch_one<double, 16, 4, false>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 32: launch_one<double, 32, 4, false>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      default: launch_one<double, 64, 2, false>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
     }
   }
 }

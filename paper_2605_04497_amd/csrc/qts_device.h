@@ -36,9 +36,39 @@ struct DeviceTable {
   float* pr_cb32 = nullptr;
   double* pr_b64 = nullptr;
   double* pr_cb64 = nullptr;
+  // first-order table with sibling leaves merged (same element layout)
+  PathHdr* mhdr = nullptr;
+  int32_t* mfeat = nullptr;
+  float* mlo = nullptr;
+  float* mhi = nullptr;
+  float* mb32 = nullptr;
+  float* mcb32 = nullptr;
+  double* mb64 = nullptr;
+  double* mcb64 = nullptr;
+  SidePath* side = nullptr;
   NodeConsts<float> n32;
   NodeConsts<double> n64;
 };
+
+// The arrays one first-order (or adjoint) launch walks.
+struct PathArrays {
+  const PathHdr* hdr;
+  const int32_t* feat;
+  const float* lo;
+  const float* hi;
+  const float* b32;
+  const float* cb32;
+  const double* b64;
+  const double* cb64;
+  const SidePath* side;  // null: no merged paths (hdr.tree is then ignored)
+};
+
+inline PathArrays plain_arrays(const DeviceTable& d) {
+  return PathArrays{d.hdr, d.feat, d.lo, d.hi, d.b32, d.cb32, d.b64, d.cb64, nullptr};
+}
+inline PathArrays merged_arrays(const DeviceTable& d) {
+  return PathArrays{d.mhdr, d.mfeat, d.mlo, d.mhi, d.mb32, d.mcb32, d.mb64, d.mcb64, d.side};
+}
 
 // Launch shape of the first-order (and adjoint) kernel for one bucket.
 struct ValuesShape {
@@ -79,9 +109,10 @@ void launch_fill_uniform(float* p, int64_t n, uint32_t seed, hipStream_t s);
 void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 
 // Accumulate phi (FP64, [M,F], pre-zeroed) over the paths of one bucket.
-void launch_values(const HostTable& h, const DeviceTable& d, const Bucket& bk, bool fp64,
-                   const float* X, int64_t M, int64_t ldx, const double* leaf_val,
-                   double* acc, const ValuesShape& shape, hipStream_t s);
+// `a` is plain_arrays() or, with `bk` from HostTable::mbuckets, merged_arrays().
+void launch_values(const HostTable& h, const DeviceTable& d, const PathArrays& a,
+                   const Bucket& bk, bool fp64, const float* X, int64_t M, int64_t ldx,
+                   const double* leaf_val, double* acc, const ValuesShape& shape, hipStream_t s);
 
 // Adjoint: add J^T G over the paths of one bucket into grad_leaf (pre-zeroed).
 // G is [M, F] float (fp64 = false) or double.

@@ -43,6 +43,20 @@ struct Bucket {
   int64_t elems;       // sum of d over the bucket's paths
 };
 
+// Sibling record of a merged path.  Two leaves A (left) and B (right) of one
+// parent have the same collapsed feature set and the same elements except the
+// one of the parent's split feature L; the val-weighted sum of their
+// polynomials is one polynomial whose L factor is vA F_A + vB F_B (linear in
+// p, like any factor).  The merged path keeps A's elements with L moved to
+// slot 0 (A's interval there) and this record holds B's side of slot 0.
+struct alignas(16) SidePath {
+  float lo_b, hi_b;  // B's interval on L (hi = NaN: no upper bound)
+  int32_t leaf_b;    // B's leaf ordinal
+  int32_t mok_b;     // 1: a NaN follows B's splits on L
+  double b_a, cb_a;  // A's b_L and 1 - b_L (FP64)
+  double b_b, cb_b;  // B's b_L and 1 - b_L (FP64)
+};
+
 // Collapsed path table in host memory (built once per model).
 struct HostTable {
   int32_t F = 0;
@@ -57,6 +71,14 @@ struct HostTable {
   std::vector<double> b, cb;  // b_j and 1 - b_j, FP64
   std::vector<double> leaf_value;
   std::vector<Bucket> buckets;
+  // The first-order table with sibling leaves merged: same layout; a merged
+  // path has hdr.tree = its SidePath index (-1 for an unmerged path).
+  std::vector<PathHdr> mhdr;
+  std::vector<int32_t> mfeat;
+  std::vector<float> mlo, mhi;
+  std::vector<double> mb, mcb;
+  std::vector<Bucket> mbuckets;
+  std::vector<SidePath> side;
 };
 
 HostTable build_host_table(const qts_tree_arrays& t, int32_t n_features, double base_score);

@@ -158,3 +158,67 @@ def test_bucket_boundaries_chain(q, oracle_mod, d):
     for precision in ("fp32", "fp64"):
         got, _ = _run(q, ens, X, precision)
         check(got, want, precision, "chain d=%d" % d)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("name,over", CASES, ids=[c[0] for c in CASES])
+def test_sibling_merge_matches_unmerged(q, oracle_mod, name, over, precision):
+    """The merged first-order table (one row per pair of sibling leaves) and
+    the plain one (one row per leaf) give the oracle's values."""
+    print("case", name, over, precision, flush=True)
+    wl = synth.make_workload(name, **over)
+    e = q.Ensemble(wl.ensemble)
+    assert e.info["n_merged"] > 0
+    X = torch.from_numpy(wl.X).cuda()
+    merged = e.shap_values(X, precision).double().cpu().numpy()
+    e.set_sibling_merge(False)
+    plain = e.shap_values(X, precision).double().cpu().numpy()
+    e.set_sibling_merge(True)
+    want = oracle_mod.shap_values(wl.ensemble, wl.X, n=8)
+    check(merged, want, precision, name + " merged")
+    check(plain, want, precision, name + " plain")
+
+
+def _sibling_leaf_pairs(ens):
+    """(left, right) leaf ordinals of every node whose two children are leaves."""
+    left, right = np.asarray(ens.left), np.asarray(ens.right)
+    offs = np.asarray(ens.tree_offsets)
+    pairs, base = [], 0
+    for t in range(ens.n_trees):
+        a, b = offs[t], offs[t + 1]
+        lt, rt = left[a:b], right[a:b]
+        is_leaf = lt < 0
+        ordinal = np.cumsum(is_leaf) - 1 + base
+        for v in np.nonzero(~is_leaf)[0]:
+            if is_leaf[lt[v]] and is_leaf[rt[v]]:
+                pairs.append((ordinal[lt[v]], ordinal[rt[v]]))
+        base += int(is_leaf.sum())
+    return pairs
+
+
+def test_sibling_merge_cancellation_and_overrides(q, oracle_mod):
+    """Sibling leaves with equal and opposite values (the combined factor's
+    constant term cancels), equal values, one zero value, zero covers and
+    NaN rows, through the model's leaf values and through an override."""
+    for seed in range(3):
+        rng = np.random.default_rng(700 + seed)
+        ens = synth.random_small_ensemble(rng, 8, 7, 6, zero_cover=(seed == 2))
+        v = ens.leaf_values().copy()
+        pairs = _sibling_leaf_pairs(ens)
+        assert pairs
+        for n, (a, b) in enumerate(pairs):
+            if n % 3 == 0:
+                v[b] = -v[a]
+            elif n % 3 == 1:
+                v[b] = v[a]
+            else:
+                v[a] = 0.0
+        X = (np.round(rng.standard_normal((75, 7)) * 2) / 2).astype(np.float32)
+        X[::5, 3] = np.nan
+        X[11, :] = np.nan
+        want = oracle_mod.shap_values(ens.with_leaf_values(v), X, n=8)
+        for precision in ("fp32", "fp64"):
+            got, _ = _run(q, ens.with_leaf_values(v), X, precision)
+            check(got, want, precision, "sibling values")
+            got, _ = _run(q, ens, X, precision, leaf_values=v)
+            check(got, want, precision, "sibling values via override")

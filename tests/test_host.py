@@ -195,3 +195,33 @@ def test_null_arguments_and_host_only_compute(q):
     assert rc == -1  # ldx < F
     rc = L.lib().qts_shap_values(e._h, None, 0, 1, None, None, 7, None)
     assert rc == -1  # unknown precision
+
+
+@pytest.mark.parametrize("name,over", [
+    ("c1_small", dict(M=4)),
+    ("c3_interactions", dict(T=6, M=4, n_train=20000)),
+    ("c5_deep", dict(T=3, M=4, n_train=30000)),
+])
+def test_sibling_merge_counts(q, name, over):
+    """The first-order table merges exactly the pairs of leaves that are the
+    two children of one node (a node whose children are both leaves), and
+    keeps every other path."""
+    wl = synth.make_workload(name, **over)
+    ens = wl.ensemble
+    left, right = np.asarray(ens.left), np.asarray(ens.right)
+    offs = np.asarray(ens.tree_offsets)
+    want = 0
+    for t in range(ens.n_trees):
+        a, b = offs[t], offs[t + 1]
+        lt, rt = left[a:b], right[a:b]
+        inner = lt >= 0
+        want += int(np.sum(inner & (lt[np.maximum(lt, 0)] < 0) & (lt[np.maximum(rt, 0)] < 0)))
+    e = q.Ensemble(ens, host_only=True)
+    info = e.info
+    assert info["n_merged"] == want
+    assert info["n_value_paths"] == info["n_paths"] - want
+    # a merged pair has one row of the same length as each of its two paths
+    d = e.export_paths()["path_len"]
+    assert info["n_value_elements"] <= info["n_elements"]
+    assert info["n_elements"] - info["n_value_elements"] >= want   # each pair drops >= 1 element
+    assert d.min() >= 1
