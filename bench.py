@@ -36,6 +36,32 @@ PEAK_HBM_GBS = 8000.0
 # LDS FP64 atomic add, measured on MI355X: 2.45 lanes per clock per CU, random
 # addresses in an 80 KB table (the interactions kernel's accumulator)
 LDS_F64_ATOMIC_RATE = 2.45 * 256 * 2.4e9
+# VALU lane operations of the method per (sample, element) unit: 4 per node
+# (factor FMA, prefix product, suffix product, FMA into the node sum) + 3
+LANE_OPS_PER_ELEMENT = 35
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+
+# HBM bytes per launch of the first-order kernel on this workload in its timed
+# launch shape, from two rocprofv3 --pmc runs (FETCH_SIZE x 2 and WRITE_SIZE x 1,
+# the factors a 1 GiB device copy reads in the same runs); see
+# profiles/values_kernel_c2_values.md.  Valid only for the kernel source they
+# were measured on (its SHA-256 prefix); otherwise traffic is reported as null.
+TRAFFIC = {"kernel_source": "paper_2605_04497_amd/csrc/kernels/values.hip",
+           "sha256_16": "70317672b0d9c5d7", "fetch_bytes": 1.3253e9, "write_bytes": 1.6800e9,
+           "shape": [8, 32768]}
+
+
+def measured_traffic(shape):
+    import hashlib
+    path = os.path.join(ROOT, TRAFFIC["kernel_source"])
+    try:
+        with open(path, "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if h != TRAFFIC["sha256_16"] or list(shape) != TRAFFIC["shape"]:
+        return None
+    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
 FLOPS_PER_ELEMENT = 51  # per (sample, path, unique feature): 8 nodes x 6 + 3
 
 
@@ -67,6 +93,8 @@ def parse():
     ap.add_argument("--pair-samples", type=int, default=1024)
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes")
+    ap.add_argument("--no-merge", action="store_true",
+                    help="first-order calls walk every leaf's path (no sibling merging)")
     ap.add_argument("--eager", action="store_true",
                     help="launch eagerly instead of replaying a captured HIP graph")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -251,6 +279,10 @@ def main():
     M = X.shape[0]
     units = M * e.n_leaves
     n_el = e.info["n_elements"]
+    # elements the first-order kernel walks: one row per pair of sibling
+    # leaves (merged), one per other leaf
+    n_vel = e.info["n_value_elements"] if not args.no_merge else n_el
+    e.set_sibling_merge(not args.no_merge)
     tune_s = 0.0
     if not args.no_autotune:
         t0 = time.perf_counter()
@@ -281,7 +313,19 @@ def main():
     err32, err64 = rel(got32), rel(got64)
     log("row-normwise rel err vs oracle: fp32 %.2e fp64 %.2e" % (err32, err64))
 
-    flops = FLOPS_PER_ELEMENT * float(M) * n_el
+    flops = FLOPS_PER_ELEMENT * float(M) * n_vel
+    plain = None
+    if not args.no_merge and not args.no_extras:
+        # the same call walking every leaf's path (no sibling merging)
+        e.set_sibling_merge(False)
+        rp = time_steps(lambda: e.shap_values(X, "fp32", out=out32), max(2, args.steps // 2),
+                        1, torch)
+        e.set_sibling_merge(True)
+        plain = {"value": units / (rp["ms_per_step"] * 1e-3), "ms_per_step": rp["ms_per_step"],
+                 "kernel_ms": rp["kernel_ms"], "dtype": "f32",
+                 "alu_tflops": FLOPS_PER_ELEMENT * float(M) * n_el / (rp["kernel_ms"] * 1e-3)
+                 / 1e12}
+        log("fp32 without sibling merging: %.3f ms/step" % rp["ms_per_step"])
     achieved = flops / (r32["kernel_ms"] * 1e-3) / 1e12
     result = {
         "metric": METRIC,
@@ -300,6 +344,10 @@ def main():
                                "integer-valued), covers from 100k rows, 100k explained samples",
                    "trees": ens.n_trees, "leaves": e.n_leaves, "features": e.n_features,
                    "samples": M, "unique_features_per_path": n_el / max(1, e.info["n_paths"]),
+                   "sibling_merge": not args.no_merge,
+                   "kernel_rows": e.info["n_value_paths"] if not args.no_merge
+                   else e.info["n_paths"],
+                   "kernel_elements": n_vel,
                    "max_unique": e.info["max_unique"]},
         "max_rel_err": {"fp32": err32, "fp64": err64, "rows_checked": int(len(rows)),
                         "measure": "row-normwise vs FP64 oracle (8 nodes)"},
@@ -309,11 +357,17 @@ def main():
                    "values_shape_fp64": list(e.launch_shape("values", "fp64", 0)),
                    "step_ms_median": r32["step_ms_median"], "step_ms_min": r32["step_ms_min"],
                    "step_ms_max": r32["step_ms_max"]},
+        "fp32_without_sibling_merge": plain,
         "fp64": {"value": units / (r64["ms_per_step"] * 1e-3), "ms_per_step": r64["ms_per_step"],
                  "kernel_ms": r64["kernel_ms"], "dtype": "f64",
                  "speedup_fp32_over_fp64": r64["ms_per_step"] / r32["ms_per_step"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
+                     "traffic": measured_traffic(e.launch_shape("values", "fp32", 0)),
+                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
+                     "lane_ops_per_launch": LANE_OPS_PER_ELEMENT * float(M) * n_vel,
+                     "lane_op_frac": LANE_OPS_PER_ELEMENT * float(M) * n_vel
+                     / (r32["kernel_ms"] * 1e-3) / PEAK_LANE_OPS,
                      "kernel": "values_kernel<float, 8, 8, true>", "kernel_ms": r32["kernel_ms"],
                      "kernel_ms_scope": "event pair around each graph replay (zero-fill, "
                                         "values kernel, cast)" if not args.eager else
