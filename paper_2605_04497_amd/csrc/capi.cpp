@@ -178,7 +178,7 @@ void free_device(DeviceTable& d) {
                   d.b64,    d.cb64,    d.leaf_val, d.pr_d,   d.pr_leaf, d.pr_feat,
                   d.pr_lo,  d.pr_hi,   d.pr_b32,  d.pr_cb32, d.pr_b64,  d.pr_cb64,
                   d.mhdr,   d.mfeat,   d.mlo,     d.mhi,     d.mb32,    d.mcb32,
-                  d.mb64,   d.mcb64,   d.side};
+                  d.mb64,   d.mcb64,   d.side,    d.pr_side};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   d = DeviceTable{};
@@ -502,6 +502,7 @@ int qts_load_ensemble(const qts_tree_arrays* trees, int32_t n_features, double b
         e->pair_classes = pt.classes;
         d.pr_d = upload(pt.d, s);
         d.pr_leaf = upload(pt.leaf, s);
+        d.pr_side = upload(pt.side, s);
         d.pr_feat = upload(pt.feat, s);
         d.pr_lo = upload(pt.lo, s);
         d.pr_hi = upload(pt.hi, s);

@@ -313,9 +313,6 @@ namespace qts {
 
 PairTable build_pair_table(const HostTable& h) {
   PairTable pt;
-  const size_t n = h.hdr.size();
-  std::vector<size_t> order(n);
-  for (size_t i = 0; i < n; ++i) order[i] = i;
   // capacities of the interactions kernel instances
   auto cap_of = [](int d) {
     static const int caps[] = {4, 8, 12, 16, 20, 24, 28, 32, 36, 40, 48, 64};
@@ -323,30 +320,58 @@ PairTable build_pair_table(const HostTable& h) {
       if (d <= c) return c;
     return 64;
   };
-  // Inside a class: by length, then by the path's rank among its tree's paths
-  // of that length, then by tree.  Neighbouring paths (one per lane) then come
+  // Rows: one per merged pair of sibling leaves of at most kPairMergeMax
+  // features (the register-resident kernel instances take them), one per
+  // other path.  A merged row of the first-order table that is longer is
+  // split back into its two paths: A keeps the row's elements, B differs in
+  // slot 0 (the parent's split feature) only.
+  std::vector<int32_t> tree_of_leaf(h.leaf_value.size(), 0);
+  for (const PathHdr& p : h.hdr) tree_of_leaf[(size_t)p.leaf] = p.tree;
+  struct Row {
+    int32_t m;     // row of the merged first-order table
+    int32_t side;  // SidePath index of a merged row, else -1
+    bool as_b;     // the B path of a split merged row
+    int32_t d, leaf, tree;
+  };
+  std::vector<Row> rows;
+  rows.reserve(h.mhdr.size() + h.side.size());
+  for (size_t m = 0; m < h.mhdr.size(); ++m) {
+    const PathHdr& p = h.mhdr[m];
+    const int32_t tree = tree_of_leaf[(size_t)p.leaf];
+    if (p.tree >= 0 && p.d > kPairMergeMax) {
+      rows.push_back(Row{(int32_t)m, -1, false, p.d, p.leaf, tree});
+      rows.push_back(Row{(int32_t)m, p.tree, true, p.d, h.side[(size_t)p.tree].leaf_b, tree});
+    } else {
+      rows.push_back(Row{(int32_t)m, p.tree, false, p.d, p.leaf, tree});
+    }
+  }
+  const size_t n = rows.size();
+  std::vector<size_t> order(n);
+  for (size_t i = 0; i < n; ++i) order[i] = i;
+  // Inside a class: by length, then by the row's rank among its tree's rows
+  // of that length, then by tree.  Neighbouring rows (one per lane) then come
   // from different trees, so a wave's lanes rarely add into the same pair
-  // entry at the same time (sibling leaves share most of their features).
+  // entry at the same time (paths of one tree share most of their features).
   std::vector<int32_t> rank(n, 0);
   {
     std::vector<int32_t> count((size_t)h.n_trees * (kMaxUnique + 1), 0);
     for (size_t i = 0; i < n; ++i)
-      rank[i] = count[(size_t)h.hdr[i].tree * (kMaxUnique + 1) + (size_t)h.hdr[i].d]++;
+      rank[i] = count[(size_t)rows[i].tree * (kMaxUnique + 1) + (size_t)rows[i].d]++;
   }
   std::sort(order.begin(), order.end(), [&](size_t x, size_t y) {
-    const int cx = cap_of(h.hdr[x].d), cy = cap_of(h.hdr[y].d);
+    const int cx = cap_of(rows[x].d), cy = cap_of(rows[y].d);
     if (cx != cy) return cx < cy;
-    if (h.hdr[x].d != h.hdr[y].d) return h.hdr[x].d < h.hdr[y].d;
+    if (rows[x].d != rows[y].d) return rows[x].d < rows[y].d;
     if (rank[x] != rank[y]) return rank[x] < rank[y];
-    return h.hdr[x].tree < h.hdr[y].tree;
+    return rows[x].tree < rows[y].tree;
   });
   // class boundaries
   size_t i = 0;
   int64_t el = 0;
   while (i < n) {
-    const int cap = cap_of(h.hdr[order[i]].d);
+    const int cap = cap_of(rows[order[i]].d);
     size_t j = i;
-    while (j < n && cap_of(h.hdr[order[j]].d) == cap) ++j;
+    while (j < n && cap_of(rows[order[j]].d) == cap) ++j;
     pt.classes.push_back(PairClass{cap, (int32_t)(j - i), el, (int32_t)i});
     el += (int64_t)cap * (int64_t)(j - i);
     i = j;
@@ -355,6 +380,11 @@ PairTable build_pair_table(const HostTable& h) {
     fail(QTS_E_UNSUPPORTED, "pair table too large");
   pt.d.resize(n);
   pt.leaf.resize(n);
+  SidePath none{};
+  none.leaf_b = -1;
+  none.hi_b = std::numeric_limits<float>::quiet_NaN();
+  none.lo_b = -std::numeric_limits<float>::infinity();
+  pt.side.assign(n, none);
   pt.feat.assign((size_t)el, kMissingOkBit);
   pt.lo.assign((size_t)el, -std::numeric_limits<float>::infinity());
   pt.hi.assign((size_t)el, std::numeric_limits<float>::quiet_NaN());
@@ -363,23 +393,46 @@ PairTable build_pair_table(const HostTable& h) {
   std::vector<int> idx;
   for (const PairClass& c : pt.classes) {
     for (int32_t q = 0; q < c.np; ++q) {
-      const PathHdr& p = h.hdr[order[(size_t)c.pbase + (size_t)q]];
-      pt.d[(size_t)c.pbase + (size_t)q] = p.d;
-      pt.leaf[(size_t)c.pbase + (size_t)q] = p.leaf;
+      const size_t r = (size_t)c.pbase + (size_t)q;
+      const Row& row = rows[order[r]];
+      const PathHdr& p = h.mhdr[(size_t)row.m];
+      pt.d[r] = row.d;
+      pt.leaf[r] = row.leaf;
+      const bool merged = row.side >= 0 && !row.as_b;
+      if (merged) pt.side[r] = h.side[(size_t)row.side];
+      // element k of the merged first-order row, with B's slot 0 for as_b
+      auto fe = [&](int k) {
+        if (row.as_b && k == 0) {
+          const SidePath& sp = h.side[(size_t)row.side];
+          return (h.mfeat[(size_t)p.off] & kFeatureMask) | (sp.mok_b ? kMissingOkBit : 0);
+        }
+        return h.mfeat[(size_t)p.off + (size_t)k];
+      };
+      // slot order: a merged row keeps its combined element in slot 0;
+      // every other slot is sorted by feature (a single path: all of them)
+      const int first = merged ? 1 : 0;
       idx.resize((size_t)p.d);
       for (int k = 0; k < p.d; ++k) idx[(size_t)k] = k;
-      std::sort(idx.begin(), idx.end(), [&](int x, int y) {
-        return (h.feat[(size_t)p.off + (size_t)x] & kFeatureMask) <
-               (h.feat[(size_t)p.off + (size_t)y] & kFeatureMask);
+      std::sort(idx.begin() + first, idx.end(), [&](int x, int y) {
+        return (fe(x) & kFeatureMask) < (fe(y) & kFeatureMask);
       });
       for (int k = 0; k < p.d; ++k) {
-        const size_t src = (size_t)p.off + (size_t)idx[(size_t)k];
+        const int e = idx[(size_t)k];
+        const size_t src = (size_t)p.off + (size_t)e;
         const size_t dst = (size_t)c.base + (size_t)k * (size_t)c.np + (size_t)q;
-        pt.feat[dst] = h.feat[src];
-        pt.lo[dst] = h.lo[src];
-        pt.hi[dst] = h.hi[src];
-        pt.b[dst] = h.b[src];
-        pt.cb[dst] = h.cb[src];
+        pt.feat[dst] = fe(e);
+        if (row.as_b && e == 0) {
+          const SidePath& sp = h.side[(size_t)row.side];
+          pt.lo[dst] = sp.lo_b;
+          pt.hi[dst] = sp.hi_b;
+          pt.b[dst] = sp.b_b;
+          pt.cb[dst] = sp.cb_b;
+        } else {
+          pt.lo[dst] = h.mlo[src];
+          pt.hi[dst] = h.mhi[src];
+          pt.b[dst] = h.mb[src];
+          pt.cb[dst] = h.mcb[src];
+        }
       }
     }
   }

@@ -11,6 +11,17 @@
 // the whole path contributes exactly zero: such lanes are masked (their zero
 // factor is replaced by 1 to keep the reciprocals finite).
 //
+// Slot 0 is never divided by: with H0 = prod_{j >= 1} F_j,
+//   g_0 = w val H0 c_0   and   g_i = w val H0 F_0 r_i  (i >= 1),
+// which holds for any path.  It lets slot 0 carry the combined factor of a
+// merged pair of sibling leaves A, B (split feature L):
+//   vA F^A_L + vB F^B_L = bm + t c,  bm = vA b_A + vB b_B,
+//   c = vA (1-b_A) - vB b_B (A followed), vB (1-b_B) - vA b_A (B followed),
+//   else -bm,
+// with the row's leaf value 1; that factor may vanish at a node, which the
+// H0 form never divides by.  Slots 1.. are sorted by feature; slot 0 is any
+// feature, so its pairs take the smaller/larger of the two features.
+//
 // Accumulation.  A workgroup owns one explained sample; the sample's pair
 // triangle (pair i < k at k(k-1)/2 + i; features are sorted inside a path, so
 // f_i < f_k) and its phi row accumulate in LDS in FP64 and are flushed with
@@ -84,11 +95,12 @@ __device__ __forceinline__ void pairs_epilogue(const double* phis, const double*
 // lane takes one path of the class (the table is slot-major, so a wave's 64
 // paths load coalesced).  NH < 8 splits the nodes over passes to bound the
 // registers held by r (the node sum is additive).
-template <typename T, int C, int NH>
+template <typename T, int C, int NH, bool MERGE>
 __global__ void __launch_bounds__(512)
 pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
-             const int32_t* __restrict__ feat, const float* __restrict__ lo,
-             const float* __restrict__ hi, const T* __restrict__ bb, const T* __restrict__ cbb,
+             const SidePath* __restrict__ pside, const int32_t* __restrict__ feat,
+             const float* __restrict__ lo, const float* __restrict__ hi,
+             const T* __restrict__ bb, const T* __restrict__ cbb,
              int32_t np, int32_t chunk, const double* __restrict__ leaf_val,
              const float* __restrict__ X, int64_t M, int64_t ldx, int32_t F, int32_t r0,
              int32_t r1, int32_t with_phi, double* __restrict__ tri64,
@@ -131,12 +143,21 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
       bv[j] = bb[e];
       cbv[j] = cbb[e];
     }
-    const double val0 = leaf_val[leaf];
+    // MERGE: the class may hold merged rows (capacity <= kPairMergeMax)
+    SidePath sp{};
+    if (MERGE) sp = pside[pc];
+    const bool merged = MERGE && valid && sp.leaf_b >= 0;
+    const double va = leaf_val[leaf];
+    const double vb = MERGE ? leaf_val[merged ? sp.leaf_b : leaf] : 0.0;
     const int d = valid ? d0 : 0;
-    T val = valid ? (T)val0 : T(0);
+    T val = valid ? (merged ? T(1) : (T)va) : T(0);
+    // combined slot-0 factor of a merged row, in FP64, then rounded
+    const T bm = MERGE ? (T)(va * sp.b_a + vb * sp.b_b) : T(0);
+    const T cAm = MERGE ? (T)(va * sp.cb_a - vb * sp.b_b) : T(0);
+    const T cBm = MERGE ? (T)(vb * sp.cb_b - va * sp.b_a) : T(0);
     // feature, row offset of its pairs in this launch's triangle rows, and
     // whether those rows are in range; then the slot's c = o - b and b (a
-    // slot with b = 0 and o = 0 zeroes the path: its b is replaced by 1)
+    // slot j >= 1 with b = 0 and o = 0 zeroes the path: its b is replaced by 1)
     int f[C], rb[C];
     bool inr[C];
     T cj[C], bj[C];
@@ -151,65 +172,180 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
       const bool lower = miss ? !(x < lov[j]) : (x >= lov[j]);
       const bool upper = !(x >= hiv[j]);
       const T b = bv[j];
-      const T c = (lower & upper) ? cbv[j] : -b;
-      const bool z = (b == T(0)) & (c == T(0));
-      dead |= z;
-      cj[j] = c;
-      bj[j] = z ? T(1) : b;
+      T c = (lower & upper) ? cbv[j] : -b;
+      if (j == 0) {
+        if (MERGE) {
+          const bool lowerB = sp.mok_b ? !(x < sp.lo_b) : (x >= sp.lo_b);
+          const bool upperB = !(x >= sp.hi_b);
+          const T cm = (lower & upper) ? cAm : ((lowerB & upperB) ? cBm : -bm);
+          cj[0] = merged ? cm : c;
+          bj[0] = merged ? bm : b;
+        } else {
+          const bool z = (b == T(0)) & (c == T(0));
+          dead |= z;
+          cj[0] = c;
+          bj[0] = z ? T(1) : b;
+        }
+      } else {
+        const bool z = (b == T(0)) & (c == T(0));
+        dead |= z;
+        cj[j] = c;
+        bj[j] = z ? T(1) : b;
+      }
     }
     if (dead) val = T(0);
+    const bool live = val != T(0);
 
+    if constexpr (!MERGE) {
+      // every slot sorted by feature and divided by: H = prod_j F_j,
+      // g_i = w val H r_i
+#pragma unroll
+      for (int pass = 0; pass < kNodes / NH; ++pass) {
+        const int m0 = pass * NH;
+        T H[NH];
+#pragma unroll
+        for (int m = 0; m < NH; ++m) H[m] = T(1);
+        T r[C][NH];
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+#pragma unroll
+          for (int m = 0; m < NH; ++m) {
+            const T Fv = fmaP(nc.t[m0 + m], cj[j], bj[j]);
+            H[m] *= Fv;
+            r[j][m] = cj[j] * rcpP(Fv);
+          }
+        }
+        T G[NH];
+#pragma unroll
+        for (int m = 0; m < NH; ++m) G[m] = nc.w[m0 + m] * val * H[m];
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+          if (i < d && live) {
+            T g[NH];
+            T ph = T(0);
+#pragma unroll
+            for (int m = 0; m < NH; ++m) {
+              g[m] = G[m] * r[i][m];
+              ph += g[m];
+            }
+            const int fi = f[i];
+            if (with_phi) lds_add(&phis[fi], (double)ph);
+            // pairs (i, k > i) in groups of four: the four values are
+            // computed into separate registers before their atomics issue, so
+            // the LDS queue sees back-to-back atomics instead of one per
+            // dependency chain (inert slots k >= d are not stored)
+#pragma unroll
+            for (int kb = i + 1; kb < C; kb += 4) {
+              T pr[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int k = kb + u < C ? kb + u : 0;
+                pr[u] = g[0] * r[k][0];
+#pragma unroll
+                for (int m = 1; m < NH; ++m) pr[u] = fmaP(g[m], r[k][m], pr[u]);
+              }
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int k = kb + u < C ? kb + u : 0;
+                if (kb + u < C && inr[k]) lds_add(&tris[rb[k] + fi], (double)pr[u]);
+              }
+            }
+          }
+        }
+      }
+      continue;
+    }
 #pragma unroll
     for (int pass = 0; pass < kNodes / NH; ++pass) {
       const int m0 = pass * NH;
-      T H[NH];
+      T H0[NH];
 #pragma unroll
-      for (int m = 0; m < NH; ++m) H[m] = T(1);
+      for (int m = 0; m < NH; ++m) H0[m] = T(1);
       T r[C][NH];
 #pragma unroll
-      for (int j = 0; j < C; ++j) {
+      for (int j = 1; j < C; ++j) {
 #pragma unroll
         for (int m = 0; m < NH; ++m) {
           const T Fv = fmaP(nc.t[m0 + m], cj[j], bj[j]);
-          H[m] *= Fv;
+          H0[m] *= Fv;
           r[j][m] = cj[j] * rcpP(Fv);
         }
       }
-      T G[NH];
+      // G = w val H0; slot 0: g_0 = G c_0; slots i >= 1: g_i = (G F_0) r_i
+      T G[NH], GF[NH];
 #pragma unroll
-      for (int m = 0; m < NH; ++m) G[m] = nc.w[m0 + m] * val * H[m];
-      const bool live = val != T(0);
+      for (int m = 0; m < NH; ++m) {
+        G[m] = nc.w[m0 + m] * val * H0[m];
+        GF[m] = G[m] * fmaP(nc.t[m0 + m], cj[0], bj[0]);
+      }
 
-#pragma unroll
-      for (int i = 0; i < C; ++i) {
-        if (i < d && live) {
+      if (live) {
+        // slot 0 and its pairs (0, k): the pair's larger feature gives the row
+        {
           T g[NH];
           T ph = T(0);
 #pragma unroll
           for (int m = 0; m < NH; ++m) {
-            g[m] = G[m] * r[i][m];
+            g[m] = G[m] * cj[0];
             ph += g[m];
           }
-          const int fi = f[i];
-          if (with_phi) lds_add(&phis[fi], (double)ph);
-          // pairs (i, k > i) in groups of four: the four values are computed
-          // into separate registers before their atomics issue, so the LDS
-          // queue sees back-to-back atomics instead of one per dependency
-          // chain (inert slots k >= d have r = 0 and are not stored)
+          const int f0 = f[0];
+          const int rb0 = rb[0];
+          if (with_phi) lds_add(&phis[f0], (double)ph);
 #pragma unroll
-          for (int kb = i + 1; kb < C; kb += 4) {
+          for (int kb = 1; kb < C; kb += 4) {
             T pr[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-              const int k = kb + u < C ? kb + u : 0;
+              const int k = kb + u < C ? kb + u : 1;
               pr[u] = g[0] * r[k][0];
 #pragma unroll
               for (int m = 1; m < NH; ++m) pr[u] = fmaP(g[m], r[k][m], pr[u]);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-              const int k = kb + u < C ? kb + u : 0;
-              if (kb + u < C && inr[k]) lds_add(&tris[rb[k] + fi], (double)pr[u]);
+              const int k = kb + u < C ? kb + u : 1;
+              // without merged rows every slot is sorted: f0 < f[k]
+              const bool lo0 = MERGE ? f0 < f[k] : true;
+              const int idx = lo0 ? rb[k] + f0 : rb0 + f[k];
+              const bool ok = MERGE ? (((lo0 ? f[k] : f0) >= r0) & ((lo0 ? f[k] : f0) < r1) &
+                                       (k < d))
+                                    : inr[k];
+              if (kb + u < C && ok) lds_add(&tris[idx], (double)pr[u]);
+            }
+          }
+        }
+#pragma unroll
+        for (int i = 1; i < C; ++i) {
+          if (i < d) {
+            T g[NH];
+            T ph = T(0);
+#pragma unroll
+            for (int m = 0; m < NH; ++m) {
+              g[m] = GF[m] * r[i][m];
+              ph += g[m];
+            }
+            const int fi = f[i];
+            if (with_phi) lds_add(&phis[fi], (double)ph);
+            // pairs (i, k > i) in groups of four: the four values are
+            // computed into separate registers before their atomics issue, so
+            // the LDS queue sees back-to-back atomics instead of one per
+            // dependency chain (inert slots k >= d are not stored)
+#pragma unroll
+            for (int kb = i + 1; kb < C; kb += 4) {
+              T pr[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int k = kb + u < C ? kb + u : 1;
+                pr[u] = g[0] * r[k][0];
+#pragma unroll
+                for (int m = 1; m < NH; ++m) pr[u] = fmaP(g[m], r[k][m], pr[u]);
+              }
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int k = kb + u < C ? kb + u : 1;
+                if (kb + u < C && inr[k]) lds_add(&tris[rb[k] + fi], (double)pr[u]);
+              }
             }
           }
         }
@@ -433,7 +569,7 @@ NodeConsts<T> node_consts(const DeviceTable& d) {
   if constexpr (std::is_same<T, float>::value) return d.n32; else return d.n64;
 }
 
-template <typename T, int C, int NH>
+template <typename T, int C, int NH, bool MERGE>
 void launch_pairs_fast(const HostTable& h, const DeviceTable& d, const PairClass& pc,
                        const float* X, int64_t M, int64_t ldx, const double* leaf_val,
                        double* tri64, double* phi64, const PairShape& shape, hipStream_t s) {
@@ -443,15 +579,16 @@ void launch_pairs_fast(const HostTable& h, const DeviceTable& d, const PairClass
   const int64_t grid = M * n_chunks;
   if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "interactions grid too large");
   static size_t cache = 0;
-  const void* fn = (const void*)pairs_kernel<T, C, NH>;
+  const void* fn = (const void*)pairs_kernel<T, C, NH, MERGE>;
   const size_t limit = lds_limit_of(fn, &cache);
   const size_t fixed = pairs_fixed_lds(F, sizeof(T), false);
   if (fixed >= limit) fail(QTS_E_UNSUPPORTED, "n_features too large for the interactions kernel");
   bool first = true;
   for (const auto& rg : row_ranges(F, limit - fixed)) {
     const size_t lds = fixed + (size_t)(tri_row_h(rg.second) - tri_row_h(rg.first)) * 8;
-    hipLaunchKernelGGL((pairs_kernel<T, C, NH>), dim3((unsigned)grid), dim3(512), lds, s,
-                       d.pr_d + pc.pbase, d.pr_leaf + pc.pbase, d.pr_feat + pc.base,
+    hipLaunchKernelGGL((pairs_kernel<T, C, NH, MERGE>), dim3((unsigned)grid), dim3(512), lds, s,
+                       d.pr_d + pc.pbase, d.pr_leaf + pc.pbase, d.pr_side + pc.pbase,
+                       d.pr_feat + pc.base,
                        d.pr_lo + pc.base, d.pr_hi + pc.base, table_b<T>(d) + pc.base,
                        table_cb<T>(d) + pc.base, pc.np, chunk, leaf_val, X, M, ldx, F, rg.first,
                        rg.second, (int)first, tri64, phi64, node_consts<T>(d));
@@ -495,21 +632,21 @@ void launch_pairs(const HostTable& h, const DeviceTable& d, const PairClass& pc,
   // register-resident lane-per-path instances exist where they do not spill
   if (!fp64) {
     switch (pc.cap) {
-      case 4: return launch_pairs_fast<float, 4, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
-      case 8: return launch_pairs_fast<float, 8, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
-      case 12: return launch_pairs_fast<float, 12, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
-      case 16: return launch_pairs_fast<float, 16, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
-      case 20: return launch_pairs_fast<float, 20, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
-      case 24: return launch_pairs_fast<float, 24, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+      case 4: return launch_pairs_fast<float, 4, 8, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+      case 8: return launch_pairs_fast<float, 8, 8, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+      case 12: return launch_pairs_fast<float, 12, 8, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+      case 16: return launch_pairs_fast<float, 16, 8, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+      case 20: return launch_pairs_fast<float, 20, 8, false>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+      case 24: return launch_pairs_fast<float, 24, 4, false>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
       default: return launch_pairs_generic<float>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     }
   }
   switch (pc.cap) {
-    case 4: return launch_pairs_fast<double, 4, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
-    case 8: return launch_pairs_fast<double, 8, 8>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
-    case 12: return launch_pairs_fast<double, 12, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
-    case 16: return launch_pairs_fast<double, 16, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
-    case 20: return launch_pairs_fast<double, 20, 2>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+    case 4: return launch_pairs_fast<double, 4, 8, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+    case 8: return launch_pairs_fast<double, 8, 8, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+    case 12: return launch_pairs_fast<double, 12, 4, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+    case 16: return launch_pairs_fast<double, 16, 4, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+    case 20: return launch_pairs_fast<double, 20, 2, false>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     default: return launch_pairs_generic<double>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
   }
 }

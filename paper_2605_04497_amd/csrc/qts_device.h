@@ -29,6 +29,7 @@ struct DeviceTable {
   // slot-major pair table (interactions)
   int32_t* pr_d = nullptr;
   int32_t* pr_leaf = nullptr;
+  SidePath* pr_side = nullptr;  // per row; leaf_b = -1 for a single path
   int32_t* pr_feat = nullptr;
   float* pr_lo = nullptr;
   float* pr_hi = nullptr;

@@ -83,13 +83,16 @@ struct HostTable {
 
 HostTable build_host_table(const qts_tree_arrays& t, int32_t n_features, double base_score);
 
-// Path table for the interactions kernel: paths grouped by capacity class
+// Path table for the interactions kernel: rows grouped by capacity class
 // (4, 8, ..., 40, 48, 64 slots: the kernel instances), sorted by length
-// inside a class with neighbouring paths taken from different trees,
-// features sorted ascending inside a path, stored slot-major
-// ([slot][path] within a class) so one lane per path reads coalesced.  Slots
-// past a path's end are inert (feature 0, no bounds, missing_ok, b = 1,
-// 1-b = 0).
+// inside a class with neighbouring rows taken from different trees, stored
+// slot-major ([slot][row] within a class) so one lane per row reads
+// coalesced.  A row is a path, or a merged pair of sibling leaves of at most
+// kPairMergeMax features (SidePath in `side`, the combined split feature in
+// slot 0); the remaining slots are sorted by feature (a single path: all of
+// them).  Slots past a row's end are inert (feature 0, no bounds,
+// missing_ok, b = 1, 1-b = 0).
+constexpr int kPairMergeMax = 16;
 struct PairClass {
   int32_t cap;    // slots per path
   int32_t np;     // paths in the class
@@ -99,7 +102,8 @@ struct PairClass {
 
 struct PairTable {
   std::vector<PairClass> classes;
-  std::vector<int32_t> d, leaf;          // per path
+  std::vector<int32_t> d, leaf;          // per row
+  std::vector<SidePath> side;            // per row (leaf_b = -1: a single path)
   std::vector<int32_t> feat;             // packed: feature | missing_ok bit
   std::vector<float> lo, hi;
   std::vector<double> b, cb;

@@ -128,3 +128,32 @@ def test_interactions_split_triangle(q, oracle_mod, F):
         Phi, phi, _ = _run(q, ens, X, precision)
         check(Phi, Phi_o, precision, "F=%d Phi" % F)
         check(phi, phi_o, precision, "F=%d phi" % F)
+
+
+def test_merged_sibling_rows_cancellation(q, oracle_mod):
+    """Rows that merge two sibling leaves carry a combined factor that can
+    vanish at a node (equal and opposite leaf values, zero covers); pairs and
+    phi must still match the oracle, via the model's values and an override."""
+    from tests.test_gpu_values import _sibling_leaf_pairs
+    for seed in range(3):
+        rng = np.random.default_rng(800 + seed)
+        ens = synth.random_small_ensemble(rng, 8, 9, 7, zero_cover=(seed == 1))
+        v = ens.leaf_values().copy()
+        pairs = _sibling_leaf_pairs(ens)
+        assert pairs
+        for n, (a, b) in enumerate(pairs):
+            if n % 3 == 0:
+                v[b] = -v[a]
+            elif n % 3 == 1:
+                v[b] = v[a]
+            else:
+                v[a] = 0.0
+        X = (np.round(rng.standard_normal((61, 9)) * 2) / 2).astype(np.float32)
+        X[::4, 2] = np.nan
+        phi_o, Phi_o = oracle_mod.shap_interactions(ens.with_leaf_values(v), X, n=8)
+        for precision in ("fp32", "fp64"):
+            Phi, phi, _ = _run(q, ens.with_leaf_values(v), X, precision)
+            check(Phi, Phi_o, precision, "sibling values Phi")
+            check(phi, phi_o, precision, "sibling values phi")
+            Phi, phi, _ = _run(q, ens, X, precision, leaf_values=v)
+            check(Phi, Phi_o, precision, "override Phi")
