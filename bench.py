@@ -66,9 +66,10 @@ FLOPS_PER_ELEMENT = 51  # per (sample, path, unique feature): 8 nodes x 6 + 3
 
 
 def pair_flops(d):
-    """Algorithmic flops of one (sample, path) in the interactions kernel: per
-    node, d factors (FMA), d-1 products, d reciprocals, d scalings into r and
-    g, d additions into phi, and d(d-1)/2 pair FMAs."""
+    """Algorithmic flops of one (sample, row) of d features in the
+    interactions kernel: per node, d factors (FMA), d-1 products, d
+    reciprocals, d scalings into r and g, d additions into phi, and d(d-1)/2
+    pair FMAs; 8 (d^2 + 6 d - 1) in all."""
     d = np.asarray(d, np.float64)
     return 8.0 * (2 * d + (d - 1) + 4 * d + d * (d - 1))
 
@@ -91,6 +92,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the interactions and adjoint measurements")
     ap.add_argument("--pair-samples", type=int, default=1024)
+    ap.add_argument("--full-interactions", action="store_true",
+                    help="also time one interactions call on all 50k samples (8 GB output)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes")
     ap.add_argument("--no-merge", action="store_true",
@@ -168,9 +171,12 @@ def measure_interactions(args, torch, q, synth, oracle, dev):
     X = torch.from_numpy(wl.X).to(dev)
     M = X.shape[0]
     tab = e.export_paths()
-    d = tab["path_len"].astype(np.float64)
-    flops = float(M) * float(pair_flops(d).sum())
-    pairs = float(M) * float((d * (d - 1) / 2).sum())
+    # work of the rows the kernels walk (a row merges two sibling leaves of up
+    # to 16 features, or is one path): sum over rows of pair_flops(d), from
+    # the row counts: sum d^2 = 2 U + E
+    N, E, U = (float(e.info[k]) for k in ("n_pair_rows", "n_pair_elements", "n_pair_updates"))
+    flops = float(M) * 8.0 * (2.0 * U + 7.0 * E - N)
+    pairs = float(M) * U
     F = e.n_features
     res = {}
     for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
@@ -191,6 +197,7 @@ def measure_interactions(args, torch, q, synth, oracle, dev):
     out = {"workload": "c3_interactions: 500 grown trees, depths 3..20, leaf cap 4096, 200 "
                        "features; first %d of the 50k explained samples" % M,
            "samples": M, "leaves": e.n_leaves, "mean_unique": float(tab["path_len"].mean()),
+           "kernel_rows": int(N), "pair_updates_per_sample": int(U),
            "value": M * e.n_leaves / (res["fp32"]["ms_per_step"] * 1e-3), "unit": "paths/s",
            "ms_per_step": res["fp32"]["ms_per_step"], "kernel_ms": res["fp32"]["kernel_ms"],
            "fp64_ms_per_step": res["fp64"]["ms_per_step"],
@@ -239,6 +246,106 @@ def measure_adjoint(args, torch, q, synth, oracle, dev):
            "alu_tflops": ach, "frac_of_valu_peak": ach / PEAK_VALU_TFLOPS}
     e.close()
     return out
+
+
+def measure_deep(args, torch, q, synth, oracle, dev):
+    """Deep trees (100 grown trees of depth 32, leaf cap 512, 64 features, 10k
+    samples): values and interactions, FP32 error against the 8-node FP64
+    oracle and the 8-node rule's own gap to the exact rule (Theorem 2: exact
+    for d <= 16 first order, d <= 17 pairs)."""
+    wl = synth.make_workload("c5_deep")
+    ens = wl.ensemble
+    e = q.Ensemble(ens, device=dev)
+    X = torch.from_numpy(wl.X).to(dev)
+    M, F = X.shape[0], e.n_features
+    out = {"workload": "c5_deep: 100 grown trees depth 32, leaf cap 512, 64 features, 10k "
+                       "explained samples", "samples": M, "leaves": e.n_leaves,
+           "max_unique": e.info["max_unique"]}
+    for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+        if not args.no_autotune:
+            e.autotune(M, prec)
+        e.set_graph_replay(not args.eager)
+        phi = torch.empty((M, F), dtype=dt, device=dev)
+        r = time_steps(lambda: e.shap_values(X, prec, out=phi), 5, 1, torch)
+        Phi = torch.empty((M, F, F), dtype=dt, device=dev)
+        ri = time_steps(lambda: e.shap_interactions(X, prec, out=Phi), 2, 1, torch, "interactions")
+        e.set_graph_replay(False)
+        out["values_" + prec] = {"value": M * e.n_leaves / (r["ms_per_step"] * 1e-3),
+                                 "ms_per_step": r["ms_per_step"]}
+        out["interactions_" + prec] = {"value": M * e.n_leaves / (ri["ms_per_step"] * 1e-3),
+                                       "ms_per_step": ri["ms_per_step"]}
+        if prec == "fp32":
+            rows = np.arange(0, M, M // 8)[:8]
+            phi_o = oracle.shap_values(ens, wl.X[rows], n=8)
+            phi_x = oracle.shap_values(ens, wl.X[rows], n=32)
+            _, Phi_o = oracle.shap_interactions(ens, wl.X[rows[:1]], n=8)
+            _, Phi_x = oracle.shap_interactions(ens, wl.X[rows[:1]], n=32)
+            g = phi[torch.from_numpy(rows).to(dev)].double().cpu().numpy()
+            G = Phi[torch.from_numpy(rows[:1]).to(dev)].double().cpu().numpy()
+
+            def rel(a, b):
+                a, b = a.reshape(a.shape[0], -1), b.reshape(b.shape[0], -1)
+                return float((np.abs(a - b).max(1) / np.maximum(np.abs(b).max(1), 1e-30)).max())
+            out["max_rel_err_fp32"] = {"phi": rel(g, phi_o), "Phi": rel(G, Phi_o),
+                                       "rows_checked": [int(len(rows)), 1]}
+            out["gap_8_nodes_vs_exact"] = {"phi": rel(phi_o, phi_x), "Phi": rel(Phi_o, Phi_x),
+                                           "measure": "row-normwise, FP64 oracle n=8 vs n=32"}
+        del phi, Phi
+    e.close()
+    return out
+
+
+def measure_small(args, torch, q, synth, oracle, dev):
+    """The small plain-FP64 case (10 trees of depth 4, 8 features, 1000
+    samples): per-call latency, eager launches vs HIP graph replay."""
+    wl = synth.make_workload("c1_small")
+    ens = wl.ensemble
+    e = q.Ensemble(ens, device=dev)
+    X = torch.from_numpy(wl.X).to(dev)
+    M = X.shape[0]
+    phi = torch.empty((M, e.n_features), dtype=torch.float64, device=dev)
+    res = {}
+    for mode in ("eager", "graph"):
+        e.set_graph_replay(mode == "graph")
+        res[mode] = time_steps(lambda: e.shap_values(X, "fp64", out=phi), 200, 20, torch)
+    e.set_graph_replay(False)
+    from oracle import brute
+    want = oracle.shap_values(ens, wl.X, n=8)
+    got = phi.cpu().numpy()
+    err = float((np.abs(got - want).max(1) / np.maximum(np.abs(want).max(1), 1e-30)).max())
+    err_b = float(np.abs(brute.shap_values(ens, wl.X[:20]) - got[:20]).max()
+                  / np.abs(got[:20]).max())
+    e.close()
+    return {"workload": "c1_small: 10 random trees depth 4, 8 features, 1000 samples, FP64",
+            "eager_us_per_call": res["eager"]["ms_per_step"] * 1e3,
+            "graph_us_per_call": res["graph"]["ms_per_step"] * 1e3,
+            "value": M * e.n_leaves / (res["graph"]["ms_per_step"] * 1e-3), "unit": "paths/s",
+            "max_rel_err_fp64": err, "max_rel_err_vs_enumeration_20_rows": err_b}
+
+
+def measure_interactions_full(args, torch, q, synth, oracle, dev):
+    """All 50k explained samples of the interactions workload, FP32: one
+    warm-up call and one timed call (Phi is 8.0 GB)."""
+    wl = synth.make_workload("c3_interactions")
+    e = q.Ensemble(wl.ensemble, device=dev)
+    X = torch.from_numpy(wl.X).to(dev)
+    M, F = X.shape[0], e.n_features
+    if not args.no_autotune:
+        e.autotune(1024, "fp32")
+    e.set_graph_replay(not args.eager)
+    Phi = torch.empty((M, F, F), dtype=torch.float32, device=dev)
+    r = time_steps(lambda: e.shap_interactions(X, "fp32", out=Phi), 1, 1, torch, "interactions")
+    rows = np.array([0, M // 2, M - 1])
+    _, Phi_o = oracle.shap_interactions(wl.ensemble, wl.X[rows], n=8)
+    G = Phi[torch.from_numpy(rows).to(dev)].double().cpu().numpy()
+    err = float((np.abs(G - Phi_o).reshape(3, -1).max(1)
+                 / np.abs(Phi_o).reshape(3, -1).max(1)).max())
+    e.set_graph_replay(False)
+    del Phi
+    e.close()
+    return {"workload": "c3_interactions, all 50k samples, FP32", "samples": M,
+            "ms_per_call": r["ms_per_step"], "value": M * e.n_leaves / (r["ms_per_step"] * 1e-3),
+            "unit": "paths/s", "max_rel_err_fp32": err, "rows_checked": 3}
 
 
 def main():
@@ -377,12 +484,14 @@ def main():
                      "frac_of_packed_peak": achieved / PEAK_FP32_PACKED_TFLOPS},
     }
     if not args.no_extras:
-        for key, fn in (("interactions", measure_interactions), ("adjoint", measure_adjoint)):
+        legs = [("interactions", measure_interactions), ("adjoint", measure_adjoint),
+                ("deep", measure_deep), ("small", measure_small)]
+        if args.full_interactions:
+            legs.append(("interactions_full", measure_interactions_full))
+        for key, fn in legs:
             try:
                 result[key] = fn(args, torch, q, synth, oracle, dev)
-                log("%s: %.3e paths/s, kernel %.2f ms, err %.2e" % (
-                    key, result[key]["value"], result[key]["kernel_ms"],
-                    result[key]["max_rel_err_fp32"]))
+                log("%s: %s" % (key, json.dumps(result[key])[:300]))
             except Exception as exc:  # report, keep the headline line
                 result[key] = {"error": repr(exc)}
                 log("%s failed: %r" % (key, exc))

@@ -117,6 +117,9 @@ typedef struct {
   int64_t n_merged;        /* sibling-leaf pairs merged in the first-order table */
   int64_t n_value_paths;   /* rows of the first-order table (n_paths - n_merged) */
   int64_t n_value_elements;  /* sum of d over those rows */
+  int64_t n_pair_rows;       /* rows of the interactions table (0: host-only ensemble) */
+  int64_t n_pair_elements;   /* sum of d over them */
+  int64_t n_pair_updates;    /* sum of d(d-1)/2 over them: pair updates per sample */
 } qts_info;
 
 int qts_get_info(const qts_ensemble* ens, qts_info* out);

@@ -40,7 +40,9 @@ class Info(ctypes.Structure):
                 ("max_unique", ctypes.c_int32), ("n_buckets", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("n_pair_classes", ctypes.c_int32),
                 ("n_graphs", ctypes.c_int32), ("n_merged", ctypes.c_int64),
-                ("n_value_paths", ctypes.c_int64), ("n_value_elements", ctypes.c_int64)]
+                ("n_value_paths", ctypes.c_int64), ("n_value_elements", ctypes.c_int64),
+                ("n_pair_rows", ctypes.c_int64), ("n_pair_elements", ctypes.c_int64),
+                ("n_pair_updates", ctypes.c_int64)]
 
 
 # exported symbol -> (restype, argtypes)

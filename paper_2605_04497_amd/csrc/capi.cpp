@@ -66,6 +66,7 @@ struct qts_ensemble {
   qts::ValuesShape vshape[2][4];
   std::vector<qts::PairShape> pshape[2];
   bool merge_siblings = true;  // first-order calls walk the merged table
+  int64_t pair_rows = 0, pair_elements = 0, pair_updates = 0;  // interactions table
   qts::GraphCache graphs;
 };
 
@@ -500,6 +501,11 @@ int qts_load_ensemble(const qts_tree_arrays* trees, int32_t n_features, double b
       {
         PairTable pt = build_pair_table(h);
         e->pair_classes = pt.classes;
+        e->pair_rows = (int64_t)pt.d.size();
+        for (int32_t dr : pt.d) {
+          e->pair_elements += dr;
+          e->pair_updates += (int64_t)dr * (dr - 1) / 2;
+        }
         d.pr_d = upload(pt.d, s);
         d.pr_leaf = upload(pt.leaf, s);
         d.pr_side = upload(pt.side, s);
@@ -569,6 +575,9 @@ int qts_get_info(const qts_ensemble* ens, qts_info* out) {
     out->n_merged = (int64_t)h.side.size();
     out->n_value_paths = (int64_t)h.mhdr.size();
     out->n_value_elements = (int64_t)h.mfeat.size();
+    out->n_pair_rows = ens->pair_rows;
+    out->n_pair_elements = ens->pair_elements;
+    out->n_pair_updates = ens->pair_updates;
   });
 }
 
