@@ -202,6 +202,18 @@ int qts_get_launch_shape(const qts_ensemble* ens, int32_t kind, qts_precision pr
  * setting drops the ensemble's cached graphs. */
 int qts_set_sibling_merge(qts_ensemble* ens, int32_t enable);
 
+/* Node count of the first-order and adjoint calls.
+ *   QTS_NODES_FIXED8 (default): the 8-node Gauss-Legendre rule for every path
+ *     (section 5).
+ *   QTS_NODES_EXACT: the paths of at most 8 unique features use the 4-node
+ *     rule.  Their leave-one-out products have degree <= 7 in p and an
+ *     n-node rule integrates degree 2n - 1 exactly (Theorem 2), so this gives
+ *     the same values as 8 nodes up to rounding with half the node work; longer
+ *     paths keep 8 nodes.  The interactions call always uses 8 nodes.
+ * Changing the policy drops the ensemble's cached graphs. */
+enum { QTS_NODES_FIXED8 = 0, QTS_NODES_EXACT = 1 };
+int qts_set_node_policy(qts_ensemble* ens, int32_t policy);
+
 /* HIP graph replay.  While enabled, each compute call on this ensemble is
  * captured once (on an internal stream, with its per-bucket or per-class
  * launches as parallel branches) into a graph keyed by (call kind, precision,

@@ -191,6 +191,12 @@ class Ensemble:
         (default) or every path (exact same values up to rounding)."""
         L.check(L.lib().qts_set_sibling_merge(self._h, int(bool(enable))))
 
+    def set_node_policy(self, policy: str = "fixed8"):
+        """'fixed8': the 8-node rule everywhere (default); 'exact': paths of at
+        most 8 features use 4 nodes (exact there, Theorem 2) in the
+        first-order and adjoint calls."""
+        L.check(L.lib().qts_set_node_policy(self._h, {"fixed8": 0, "exact": 1}[policy]))
+
     def refresh_info(self) -> dict:
         info = L.Info()
         L.check(L.lib().qts_get_info(self._h, ctypes.byref(info)))

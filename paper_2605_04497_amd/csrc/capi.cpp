@@ -66,6 +66,7 @@ struct qts_ensemble {
   qts::ValuesShape vshape[2][4];
   std::vector<qts::PairShape> pshape[2];
   bool merge_siblings = true;  // first-order calls walk the merged table
+  int node_policy = QTS_NODES_FIXED8;
   int64_t pair_rows = 0, pair_elements = 0, pair_updates = 0;  // interactions table
   qts::GraphCache graphs;
 };
@@ -194,6 +195,13 @@ void build_nodes(DeviceTable& d) {
     d.n64.t[m] = t[m];
     d.n64.w[m] = w[m];
   }
+  gauss_legendre(4, t, s, w);
+  for (int m = 0; m < kNodes; ++m) {
+    d.n32_4.t[m] = m < 4 ? (float)t[m] : 0.f;
+    d.n32_4.w[m] = m < 4 ? (float)w[m] : 0.f;
+    d.n64_4.t[m] = m < 4 ? t[m] : 0.0;
+    d.n64_4.w[m] = m < 4 ? w[m] : 0.0;
+  }
 }
 
 void require_device(const qts_ensemble* ens) {
@@ -300,6 +308,8 @@ struct Lanes {
   }
 };
 
+int nodes_of(const qts_ensemble* ens) { return ens->node_policy == QTS_NODES_EXACT ? 4 : 8; }
+
 const PairShape& pair_shape(const qts_ensemble* ens, bool fp64, size_t i) {
   static const PairShape kDefault{};
   const auto& v = ens->pshape[fp64 ? 1 : 0];
@@ -321,7 +331,7 @@ void issue_values(const qts_ensemble* ens, const float* X, int64_t M, int64_t ld
   for (size_t i = 0; i < bks.size(); ++i) {
     const Bucket& bk = bks[i];
     launch_values(h, ens->dev, arr, bk, fp64, X, M, ldx, leaf, a,
-                  ens->vshape[fp64 ? 1 : 0][cap_index(bk.dmax)], ln.pick((int)i));
+                  ens->vshape[fp64 ? 1 : 0][cap_index(bk.dmax)], nodes_of(ens), ln.pick((int)i));
   }
   ln.join();
   ts.done();
@@ -357,7 +367,7 @@ void issue_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_t 
   for (size_t i = 0; i < h.buckets.size(); ++i) {
     const Bucket& bk = h.buckets[i];
     launch_adjoint(h, ens->dev, bk, fp64, X, grad_phi, M, ldx, grad_leaf,
-                   ens->vshape[fp64 ? 1 : 0][cap_index(bk.dmax)], ln.pick((int)i));
+                   ens->vshape[fp64 ? 1 : 0][cap_index(bk.dmax)], nodes_of(ens), ln.pick((int)i));
   }
   ln.join();
   ts.done();
@@ -738,6 +748,17 @@ int qts_set_sibling_merge(qts_ensemble* ens, int32_t enable) {
   });
 }
 
+int qts_set_node_policy(qts_ensemble* ens, int32_t policy) {
+  return guarded([&] {
+    if (!ens) fail(QTS_E_INVALID_ARG, "null ensemble");
+    if (policy != QTS_NODES_FIXED8 && policy != QTS_NODES_EXACT)
+      fail(QTS_E_INVALID_ARG, "unknown node policy");
+    std::lock_guard<std::mutex> lock(ens->graphs.mu);
+    if (ens->node_policy != policy) clear_graphs(ens->graphs);
+    ens->node_policy = policy;
+  });
+}
+
 int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, void* stream) {
   return guarded([&] {
     if (!ens) fail(QTS_E_INVALID_ARG, "null ensemble");
@@ -793,7 +814,7 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
             const ValuesShape cand{waves, items};
             const float ms = time_ms(3, [&] {
               launch_values(h, d, arr, bk, fp64, X, Mt, F, d.leaf_val, (double*)acc.p, cand,
-                            s);
+                            nodes_of(ens), s);
             });
             if (ms < best_ms) {
               best_ms = ms;

@@ -58,7 +58,7 @@ __device__ __forceinline__ double to_vgpr(double v) {
 // d val = c_j LOO_j; instead of scattering val c_j LOO_j into the phi tile,
 // each lane gathers g[s, f_j] c_j LOO_j from the upstream-gradient tile gs,
 // the wave sums its 64 samples in FP64 and adds the result to grad_leaf.
-template <typename T, int DMAX, int NH, bool STORE_G, bool NANS, bool ADJ>
+template <typename T, int DMAX, int NH, bool STORE_G, bool NANS, bool ADJ, int NN>
 __device__ __forceinline__ void values_paths(
     const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
     const float* __restrict__ lo, const float* __restrict__ hi, const T* __restrict__ bb,
@@ -145,7 +145,7 @@ __device__ __forceinline__ void values_paths(
     }
 
 #pragma unroll
-    for (int pass = 0; pass < kNodes / NH; ++pass) {
+    for (int pass = 0; pass < NN / NH; ++pass) {
       const int m0 = pass * NH;
       // checkpoints: ck[b][m] = w_m prod_{k < 8b} F_k(m)
       T ck[NB][NH];
@@ -227,7 +227,7 @@ __device__ __forceinline__ void values_paths(
   }
 }
 
-template <typename T, int DMAX, int NH, bool STORE_G>
+template <typename T, int DMAX, int NH, bool STORE_G, int NN>
 __global__ void __launch_bounds__(512)
 values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
               const float* __restrict__ lo, const float* __restrict__ hi,
@@ -271,16 +271,16 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
 
   // nodes pinned in VGPRs: a VALU op may read only one SGPR on gfx9-class
   // hardware, and b_j arrives in an SGPR
-  T tv[kNodes];
+  T tv[NN];
 #pragma unroll
-  for (int m = 0; m < kNodes; ++m) tv[m] = to_vgpr(nc.t[m]);
+  for (int m = 0; m < NN; ++m) tv[m] = to_vgpr(nc.t[m]);
 
   if (any_nan)
-    values_paths<T, DMAX, NH, STORE_G, true, false>(hdr, feat, lo, hi, bb, cbb, side, leaf_val, xs,
+    values_paths<T, DMAX, NH, STORE_G, true, false, NN>(hdr, feat, lo, hi, bb, cbb, side, leaf_val, xs,
                                                     as, nullptr, nullptr, pb, pe, wave, nw, lane,
                                                     tv, nc);
   else
-    values_paths<T, DMAX, NH, STORE_G, false, false>(hdr, feat, lo, hi, bb, cbb, side, leaf_val, xs,
+    values_paths<T, DMAX, NH, STORE_G, false, false, NN>(hdr, feat, lo, hi, bb, cbb, side, leaf_val, xs,
                                                      as, nullptr, nullptr, pb, pe, wave, nw, lane,
                                                      tv, nc);
   __syncthreads();
@@ -299,7 +299,7 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
 
 // Adjoint to the leaf values (same tiling as values_kernel): the tile holds
 // the samples' rows and their upstream gradient rows g[s, :].
-template <typename T, int DMAX, int NH, bool STORE_G>
+template <typename T, int DMAX, int NH, bool STORE_G, int NN>
 __global__ void __launch_bounds__(512)
 adjoint_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
                const float* __restrict__ lo, const float* __restrict__ hi,
@@ -339,15 +339,15 @@ adjoint_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat
   const int nw = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
   const int pb = __builtin_amdgcn_readfirstlane(p0);
   const int pe = __builtin_amdgcn_readfirstlane(p1);
-  T tv[kNodes];
+  T tv[NN];
 #pragma unroll
-  for (int m = 0; m < kNodes; ++m) tv[m] = to_vgpr(nc.t[m]);
+  for (int m = 0; m < NN; ++m) tv[m] = to_vgpr(nc.t[m]);
   if (any_nan)
-    values_paths<T, DMAX, NH, STORE_G, true, true>(hdr, feat, lo, hi, bb, cbb, nullptr, nullptr, xs,
+    values_paths<T, DMAX, NH, STORE_G, true, true, NN>(hdr, feat, lo, hi, bb, cbb, nullptr, nullptr, xs,
                                                    nullptr, gs, grad_leaf, pb, pe, wave, nw,
                                                    lane, tv, nc);
   else
-    values_paths<T, DMAX, NH, STORE_G, false, true>(hdr, feat, lo, hi, bb, cbb, nullptr, nullptr, xs,
+    values_paths<T, DMAX, NH, STORE_G, false, true, NN>(hdr, feat, lo, hi, bb, cbb, nullptr, nullptr, xs,
                                                     nullptr, gs, grad_leaf, pb, pe, wave, nw,
                                                     lane, tv, nc);
 }
@@ -377,7 +377,7 @@ size_t values_lds_limit(const void* fn, size_t* cache) {
   return *cache;
 }
 
-template <typename T, int DMAX, int NH, bool STORE_G>
+template <typename T, int DMAX, int NH, bool STORE_G, int NN>
 void launch_one(const HostTable& h, const DeviceTable& d, const PathArrays& a, const Bucket& bk,
                 const float* X, int64_t M, int64_t ldx, const double* leaf_val, double* acc,
                 const ValuesShape& shape, hipStream_t s) {
@@ -393,17 +393,18 @@ void launch_one(const HostTable& h, const DeviceTable& d, const PathArrays& a, c
   const T* b = std::is_same<T, float>::value ? (const T*)a.b32 : (const T*)a.b64;
   const T* cb = std::is_same<T, float>::value ? (const T*)a.cb32 : (const T*)a.cb64;
   NodeConsts<T> nc;
-  if constexpr (std::is_same<T, float>::value) nc = d.n32; else nc = d.n64;
+  if constexpr (std::is_same<T, float>::value) nc = NN == 8 ? d.n32 : d.n32_4;
+  else nc = NN == 8 ? d.n64 : d.n64_4;
   static size_t cache = 0;
-  if (lds > values_lds_limit((const void*)values_kernel<T, DMAX, NH, STORE_G>, &cache))
+  if (lds > values_lds_limit((const void*)values_kernel<T, DMAX, NH, STORE_G, NN>, &cache))
     fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
-  hipLaunchKernelGGL((values_kernel<T, DMAX, NH, STORE_G>), dim3((unsigned)grid),
+  hipLaunchKernelGGL((values_kernel<T, DMAX, NH, STORE_G, NN>), dim3((unsigned)grid),
                      dim3(threads), lds, s, a.hdr, a.feat, a.lo, a.hi, b, cb, a.side, leaf_val, X,
                      M, ldx, F, bk.path_begin, bk.path_end, chunk, nsb, acc, nc);
   check_hip(hipGetLastError(), "values_kernel launch");
 }
 
-template <typename T, int DMAX, int NH, bool STORE_G>
+template <typename T, int DMAX, int NH, bool STORE_G, int NN>
 void launch_adj_one(const HostTable& h, const DeviceTable& d, const Bucket& bk, const float* X,
                     const void* G, int64_t M, int64_t ldx, double* grad_leaf,
                     const ValuesShape& shape, hipStream_t s) {
@@ -420,11 +421,12 @@ void launch_adj_one(const HostTable& h, const DeviceTable& d, const Bucket& bk, 
   const T* b = std::is_same<T, float>::value ? (const T*)d.b32 : (const T*)d.b64;
   const T* cb = std::is_same<T, float>::value ? (const T*)d.cb32 : (const T*)d.cb64;
   NodeConsts<T> nc;
-  if constexpr (std::is_same<T, float>::value) nc = d.n32; else nc = d.n64;
+  if constexpr (std::is_same<T, float>::value) nc = NN == 8 ? d.n32 : d.n32_4;
+  else nc = NN == 8 ? d.n64 : d.n64_4;
   static size_t cache = 0;
-  if (lds > values_lds_limit((const void*)adjoint_kernel<T, DMAX, NH, STORE_G>, &cache))
+  if (lds > values_lds_limit((const void*)adjoint_kernel<T, DMAX, NH, STORE_G, NN>, &cache))
     fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
-  hipLaunchKernelGGL((adjoint_kernel<T, DMAX, NH, STORE_G>), dim3((unsigned)grid),
+  hipLaunchKernelGGL((adjoint_kernel<T, DMAX, NH, STORE_G, NN>), dim3((unsigned)grid),
                      dim3(threads), lds, s, d.hdr, d.feat, d.lo, d.hi, b, cb, X, (const T*)G, M,
                      ldx, F, bk.path_begin, bk.path_end, chunk, nsb, grad_leaf, nc);
   check_hip(hipGetLastError(), "adjoint_kernel launch");
@@ -434,42 +436,53 @@ void launch_adj_one(const HostTable& h, const DeviceTable& d, const Bucket& bk, 
 
 void launch_adjoint(const HostTable& h, const DeviceTable& d, const Bucket& bk, bool fp64,
                     const float* X, const void* G, int64_t M, int64_t ldx, double* grad_leaf,
-                    const ValuesShape& shape, hipStream_t s) {
+                    const ValuesShape& shape, int nodes, hipStream_t s) {
+  if (nodes == 4 && bk.dmax == 8) {
+    if (!fp64) launch_adj_one<float, 8, 4, true, 4>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s);
+    else launch_adj_one<double, 8, 4, false, 4>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s);
+    return;
+  }
   if (!fp64) {
     switch (bk.dmax) {
-      case 8: launch_adj_one<float, 8, 8, true>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
-      case 16: launch_adj_one<float, 16, 8, true>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
-      case 32: launch_adj_one<float, 32, 8, false>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
-      default: launch_adj_one<float, 64, 4, false>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      case 8: launch_adj_one<float, 8, 8, true, 8>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      case 16: launch_adj_one<float, 16, 8, true, 8>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      case 32: launch_adj_one<float, 32, 8, false, 8>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      default: launch_adj_one<float, 64, 4, false, 8>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
     }
   } else {
     switch (bk.dmax) {
-      case 8: launch_adj_one<double, 8, 8, false>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
-      case 16: launch_adj_one<double, 16, 4, false>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
-      case 32: launch_adj_one<double, 32, 4, false>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
-      default: launch_adj_one<double, 64, 2, false>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      case 8: launch_adj_one<double, 8, 8, false, 8>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      case 16: launch_adj_one<double, 16, 4, false, 8>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      case 32: launch_adj_one<double, 32, 4, false, 8>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      default: launch_adj_one<double, 64, 2, false, 8>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
     }
   }
 }
 
 void launch_values(const HostTable& h, const DeviceTable& d, const PathArrays& a,
                    const Bucket& bk, bool fp64, const float* X, int64_t M, int64_t ldx,
-                   const double* leaf_val, double* acc, const ValuesShape& shape, hipStream_t s) {
+                   const double* leaf_val, double* acc, const ValuesShape& shape, int nodes,
+                   hipStream_t s) {
   if (values_lds_bytes(h.F) > (size_t)kMaxLdsBytes)
     fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
+  if (nodes == 4 && bk.dmax == 8) {
+    if (!fp64) launch_one<float, 8, 4, true, 4>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s);
+    else launch_one<double, 8, 4, false, 4>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s);
+    return;
+  }
   if (!fp64) {
     switch (bk.dmax) {
-      case 8: launch_one<float, 8, 8, true>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      case 16: launch_one<float, 16, 8, true>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      case 32: launch_one<float, 32, 8, false>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      default: launch_one<float, 64, 4, false>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 8: launch_one<float, 8, 8, true, 8>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 16: launch_one<float, 16, 8, true, 8>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 32: launch_one<float, 32, 8, false, 8>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      default: launch_one<float, 64, 4, false, 8>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
     }
   } else {
     switch (bk.dmax) {
-      case 8: launch_one<double, 8, 8, false>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      case 16: launch_one<double, 16, 4, false>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      case 32: launch_one<double, 32, 4, false>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      default: launch_one<double, 64, 2, false>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 8: launch_one<double, 8, 8, false, 8>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 16: launch_one<double, 16, 4, false, 8>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 32: launch_one<double, 32, 4, false, 8>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      default: launch_one<double, 64, 2, false, 8>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
     }
   }
 }

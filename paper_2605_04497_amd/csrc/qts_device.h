@@ -47,8 +47,10 @@ struct DeviceTable {
   double* mb64 = nullptr;
   double* mcb64 = nullptr;
   SidePath* side = nullptr;
-  NodeConsts<float> n32;
+  NodeConsts<float> n32;     // the 8-node rule
   NodeConsts<double> n64;
+  NodeConsts<float> n32_4;   // the 4-node rule (first 4 entries)
+  NodeConsts<double> n64_4;
 };
 
 // The arrays one first-order (or adjoint) launch walks.
@@ -111,15 +113,18 @@ void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s
 
 // Accumulate phi (FP64, [M,F], pre-zeroed) over the paths of one bucket.
 // `a` is plain_arrays() or, with `bk` from HostTable::mbuckets, merged_arrays().
+// nodes = 4 runs the d <= 8 bucket with the 4-node rule (exact there for
+// first order, Theorem 2); every other bucket, and nodes = 8, use 8 nodes.
 void launch_values(const HostTable& h, const DeviceTable& d, const PathArrays& a,
                    const Bucket& bk, bool fp64, const float* X, int64_t M, int64_t ldx,
-                   const double* leaf_val, double* acc, const ValuesShape& shape, hipStream_t s);
+                   const double* leaf_val, double* acc, const ValuesShape& shape, int nodes,
+                   hipStream_t s);
 
 // Adjoint: add J^T G over the paths of one bucket into grad_leaf (pre-zeroed).
 // G is [M, F] float (fp64 = false) or double.
 void launch_adjoint(const HostTable& h, const DeviceTable& d, const Bucket& bk, bool fp64,
                     const float* X, const void* G, int64_t M, int64_t ldx, double* grad_leaf,
-                    const ValuesShape& shape, hipStream_t s);
+                    const ValuesShape& shape, int nodes, hipStream_t s);
 
 // Interactions: accumulate the FP64 pair triangle [M][F(F-1)/2] and phi [M][F]
 // (both pre-zeroed) over the paths of one capacity class.

@@ -222,3 +222,32 @@ def test_sibling_merge_cancellation_and_overrides(q, oracle_mod):
             check(got, want, precision, "sibling values")
             got, _ = _run(q, ens, X, precision, leaf_values=v)
             check(got, want, precision, "sibling values via override")
+
+
+@pytest.mark.parametrize("name,over", [
+    ("c2_values", dict(T=40, M=333, n_train=20000)),      # every path d <= 8: 4 nodes
+    ("c5_deep", dict(T=4, M=70, n_train=30000)),          # longer buckets keep 8 nodes
+    ("c4_adjoint", dict(T=20, M=200, n_train=20000)),
+])
+def test_exact_node_policy(q, oracle_mod, name, over):
+    """With the 'exact' node policy, paths of at most 8 features use 4 nodes;
+    their integrands have degree <= 7, so the values equal the 8-node ones
+    (and the 4-node oracle's) up to rounding, and so does the adjoint."""
+    print("case", name, over, flush=True)
+    wl = synth.make_workload(name, **over)
+    e = q.Ensemble(wl.ensemble)
+    e.set_node_policy("exact")
+    X = torch.from_numpy(wl.X).cuda()
+    want = oracle_mod.shap_values(wl.ensemble, wl.X, n=8)
+    G = np.random.default_rng(3).normal(size=want.shape)
+    want_g = oracle_mod.leaf_grad(wl.ensemble, wl.X, G)
+    for precision in ("fp32", "fp64"):
+        got = e.shap_values(X, precision).double().cpu().numpy()
+        check(got, want, precision, name + " exact nodes")
+        Gp = G.astype(np.float32).astype(np.float64) if precision == "fp32" else G
+        g = e.shap_backward(X, torch.from_numpy(Gp).cuda(), precision).cpu().numpy()
+        wg = oracle_mod.leaf_grad(wl.ensemble, wl.X, Gp) if precision == "fp32" else want_g
+        err = np.abs(g - wg).max() / np.abs(wg).max()
+        assert err <= (1e-5 if precision == "fp32" else 1e-10), err
+    if e.info["max_unique"] <= 8:
+        check(got, oracle_mod.shap_values(wl.ensemble, wl.X, n=4), "fp64", "4-node oracle")
