@@ -157,9 +157,17 @@ def cpu_baseline(ens, X, seconds, oracle):
                     break
     except OSError:
         pass
+    # one core, on a smaller sample sized for about a fifth of the time
+    per_row_1core = dt / rows * threads
+    rows1 = max(1, min(rows, int(seconds / 5.0 / max(per_row_1core, 1e-9))))
+    t1 = time.perf_counter()
+    oracle.shap_values(ens, X[:rows1], n=8, threads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": rows * n_leaves / dt, "unit": "paths/s", "cores": threads, "kind": "oracle",
             "sample": "%d of the workload's explained rows, all 1000 trees, FP64 8-node path "
-                      "quadrature, %.1f s, %s" % (rows, dt, cpu)}
+                      "quadrature, %.1f s, %s" % (rows, dt, cpu),
+            "single_core": {"value": rows1 * n_leaves / dt1, "unit": "paths/s", "cores": 1,
+                            "sample": "%d rows, %.1f s" % (rows1, dt1)}}
 
 
 def measure_interactions(args, torch, q, synth, oracle, dev):
@@ -418,6 +426,7 @@ def main():
         return float((np.abs(g - want).max(1) / np.maximum(np.abs(want).max(1), 1e-30)).max())
 
     err32, err64 = rel(got32), rel(got64)
+    abs32, abs64 = float(np.abs(got32 - want).max()), float(np.abs(got64 - want).max())
     log("row-normwise rel err vs oracle: fp32 %.2e fp64 %.2e" % (err32, err64))
 
     flops = FLOPS_PER_ELEMENT * float(M) * n_vel
@@ -433,6 +442,20 @@ def main():
                  "alu_tflops": FLOPS_PER_ELEMENT * float(M) * n_el / (rp["kernel_ms"] * 1e-3)
                  / 1e12}
         log("fp32 without sibling merging: %.3f ms/step" % rp["ms_per_step"])
+    exact = None
+    if not args.no_extras:
+        # the optional node policy: 4 nodes for paths of at most 8 features
+        # (exact there, Theorem 2), same launch shapes
+        e.set_node_policy("exact")
+        rx = time_steps(lambda: e.shap_values(X, "fp32", out=out32), max(2, args.steps // 2),
+                        1, torch)
+        e.set_node_policy("fixed8")
+        gx = out32[torch.from_numpy(rows).to(dev)].double().cpu().numpy()
+        exact = {"value": units / (rx["ms_per_step"] * 1e-3), "ms_per_step": rx["ms_per_step"],
+                 "dtype": "f32", "max_rel_err": rel(gx),
+                 "note": "4-node rule for paths of at most 8 unique features (all of this "
+                         "workload): exact for first order, same values up to rounding"}
+        log("fp32 with the exact node policy: %.3f ms/step" % rx["ms_per_step"])
     achieved = flops / (r32["kernel_ms"] * 1e-3) / 1e12
     result = {
         "metric": METRIC,
@@ -456,7 +479,8 @@ def main():
                    else e.info["n_paths"],
                    "kernel_elements": n_vel,
                    "max_unique": e.info["max_unique"]},
-        "max_rel_err": {"fp32": err32, "fp64": err64, "rows_checked": int(len(rows)),
+        "max_rel_err": {"fp32": err32, "fp64": err64, "max_abs_fp32": abs32,
+                        "max_abs_fp64": abs64, "rows_checked": int(len(rows)),
                         "measure": "row-normwise vs FP64 oracle (8 nodes)"},
         "launch": {"mode": "hipGraph replay" if not args.eager else "eager",
                    "autotuned": not args.no_autotune, "autotune_s": tune_s,
@@ -465,6 +489,7 @@ def main():
                    "step_ms_median": r32["step_ms_median"], "step_ms_min": r32["step_ms_min"],
                    "step_ms_max": r32["step_ms_max"]},
         "fp32_without_sibling_merge": plain,
+        "fp32_exact_node_policy": exact,
         "fp64": {"value": units / (r64["ms_per_step"] * 1e-3), "ms_per_step": r64["ms_per_step"],
                  "kernel_ms": r64["kernel_ms"], "dtype": "f64",
                  "speedup_fp32_over_fp64": r64["ms_per_step"] / r32["ms_per_step"]},
