@@ -363,10 +363,12 @@ void issue_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_t 
   launch_fill_zero(grad_leaf, (int64_t)h.leaf_value.size(), ln.main);
   if (M == 0) return;
   TimedScope ts(2, timed ? ln.main : nullptr, timed);
-  ln.fork((int)h.buckets.size());
-  for (size_t i = 0; i < h.buckets.size(); ++i) {
-    const Bucket& bk = h.buckets[i];
-    launch_adjoint(h, ens->dev, bk, fp64, X, grad_phi, M, ldx, grad_leaf,
+  const std::vector<Bucket>& bks = ens->merge_siblings ? h.mbuckets : h.buckets;
+  const PathArrays arr = ens->merge_siblings ? merged_arrays(ens->dev) : plain_arrays(ens->dev);
+  ln.fork((int)bks.size());
+  for (size_t i = 0; i < bks.size(); ++i) {
+    const Bucket& bk = bks[i];
+    launch_adjoint(h, ens->dev, arr, bk, fp64, X, grad_phi, M, ldx, grad_leaf,
                    ens->vshape[fp64 ? 1 : 0][cap_index(bk.dmax)], nodes_of(ens), ln.pick((int)i));
   }
   ln.join();

@@ -72,33 +72,52 @@ __device__ __forceinline__ void values_paths(
     const int off = ldu(&hdr[p].off);
     const int leaf = ldu(&hdr[p].leaf);
     T val = ADJ ? T(1) : (T)ldu(leaf_val + leaf);
-    // A merged sibling pair (first order only): slot 0 is the parent's split
-    // feature L with factor vA F_A + vB F_B = bm + t c, where c is cA when
-    // the sample follows A's interval, cB when it follows B's, else -bm;
+    // A merged sibling pair: slot 0 is the parent's split feature L.
+    // First order: L's factor is vA F_A + vB F_B = bm + t c, where c is cA
+    // when the sample follows A's interval, cB when it follows B's, else -bm;
     // the path's leaf value is then 1.  Built here in FP64 from the leaf
     // values (which a call may override), then rounded to T.
-    const int sidx = (ADJ || side == nullptr) ? -1 : ldu(&hdr[p].tree);
+    // Adjoint: slot 0 is made inert in the products (b = 1, c = 0), so the
+    // sweep yields w Q_j(m) = w prod_{k >= 1, k != j} F_k(m); then
+    //   d/dvA = sum_m F_A(m) R(m) + g_L c_A sum_m w Q_0(m),
+    //   R(m) = sum_{j >= 1} g_j c_j w Q_j(m)   (shared by A and B),
+    // and likewise for B with F_B and c_B.
+    const int sidx = side == nullptr ? -1 : ldu(&hdr[p].tree);
     const bool merged = sidx >= 0;
     T bm = T(0), cA = T(0), cB = T(0);
+    T ba = T(0), cba = T(0), bb2 = T(0), cbb2 = T(0);
     float loB = 0.f, hiB = 0.f;
     bool mokB = false;
+    int leafB = 0;
     if (merged) {
       const SidePath* sp = side + sidx;
-      const double va = ldu(leaf_val + leaf);
-      const double vb = ldu(leaf_val + ldu(&sp->leaf_b));
-      const double ba = ldu(&sp->b_a), cba = ldu(&sp->cb_a);
-      const double bb2 = ldu(&sp->b_b), cbb2 = ldu(&sp->cb_b);
-      bm = (T)(va * ba + vb * bb2);
-      cA = (T)(va * cba - vb * bb2);
-      cB = (T)(vb * cbb2 - va * ba);
+      leafB = ldu(&sp->leaf_b);
       loB = ldu(&sp->lo_b);
       hiB = ldu(&sp->hi_b);
       mokB = ldu(&sp->mok_b) != 0;
-      val = T(1);
+      if (ADJ) {
+        ba = (T)ldu(&sp->b_a);
+        cba = (T)ldu(&sp->cb_a);
+        bb2 = (T)ldu(&sp->b_b);
+        cbb2 = (T)ldu(&sp->cb_b);
+        bm = T(1);
+      } else {
+        const double va = ldu(leaf_val + leaf);
+        const double vb = ldu(leaf_val + leafB);
+        const double dba = ldu(&sp->b_a), dcba = ldu(&sp->cb_a);
+        const double dbb = ldu(&sp->b_b), dcbb = ldu(&sp->cb_b);
+        bm = (T)(va * dba + vb * dbb);
+        cA = (T)(va * dcba - vb * dbb);
+        cB = (T)(vb * dcbb - va * dba);
+        val = T(1);
+      }
     }
     // b_j of slot j (slot 0 of a merged path: bm)
     auto bload = [&](int j) -> T { return (j == 0 && merged) ? bm : ldu(bb + off + j); };
     double gacc = 0.0;
+    double gaccB = 0.0;          // adjoint of a merged path: B's gradient
+    T oc0A = T(0), oc0B = T(0);  // adjoint of a merged path: c_A and c_B
+    T q0 = T(0);                 // adjoint of a merged path: sum_m w Q_0(m)
     const int nb = (d + 7) >> 3;  // batches in use; slots [d, 8 nb) are inert
 
     // c_j per slot, eight slots per batch
@@ -138,7 +157,13 @@ __device__ __forceinline__ void values_paths(
             if (NANS) lowerB = mokB ? !(x[0] < loB) : (x[0] >= loB);
             else lowerB = x[0] >= loB;
             const bool upperB = !(x[0] >= hiB);
-            cf[0] = (lower & upper) ? cA : ((lowerB & upperB) ? cB : -bm);
+            if (ADJ) {
+              oc0A = (lower & upper) ? cba : -ba;
+              oc0B = (lowerB & upperB) ? cbb2 : -bb2;
+              cf[0] = T(0);
+            } else {
+              cf[0] = (lower & upper) ? cA : ((lowerB & upperB) ? cB : -bm);
+            }
           }
         }
       }
@@ -170,6 +195,9 @@ __device__ __forceinline__ void values_paths(
       T S[NH];
 #pragma unroll
       for (int m = 0; m < NH; ++m) S[m] = T(1);
+      T R[ADJ ? NH : 1];
+#pragma unroll
+      for (int m = 0; m < (ADJ ? NH : 1); ++m) R[m] = T(0);
 #pragma unroll
       for (int b = NB - 1; b >= 0; --b) {
         if (b < nb) {
@@ -196,16 +224,28 @@ __device__ __forceinline__ void values_paths(
           for (int k = 7; k >= 0; --k) {
             const int j = jb + k;
             if (j < d) {
-              T dot = Pb[k][0] * S[0];
-#pragma unroll
-              for (int m = 1; m < NH; ++m) dot = fmaT(Pb[k][m], S[m], dot);
               const int f = ldu(feat + off + j) & kFeatureMask;
-              if (ADJ) {
-                gacc += (double)(gs[f * kTileStride + lane] * cf[j] * dot);
+              if (ADJ && merged) {
+                if (j > 0) {
+                  const T gc = gs[f * kTileStride + lane] * cf[j];
+#pragma unroll
+                  for (int m = 0; m < NH; ++m)
+                    R[ADJ ? m : 0] = fmaT(gc, Pb[k][m] * S[m], R[ADJ ? m : 0]);
+                } else {
+#pragma unroll
+                  for (int m = 0; m < NH; ++m) q0 = fmaT(Pb[k][m], S[m], q0);
+                }
               } else {
-                const double c = (double)(val * cf[j] * dot);
-                __hip_atomic_fetch_add(&as[f * kTileStride + lane], c, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                T dot = Pb[k][0] * S[0];
+#pragma unroll
+                for (int m = 1; m < NH; ++m) dot = fmaT(Pb[k][m], S[m], dot);
+                if (ADJ) {
+                  gacc += (double)(gs[f * kTileStride + lane] * cf[j] * dot);
+                } else {
+                  const double c = (double)(val * cf[j] * dot);
+                  __hip_atomic_fetch_add(&as[f * kTileStride + lane], c, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
               }
             }
             if (j > 0) {
@@ -218,8 +258,26 @@ __device__ __forceinline__ void values_paths(
           }
         }
       }
+      if (ADJ && merged) {
+        T sa = T(0), sb = T(0);
+#pragma unroll
+        for (int m = 0; m < NH; ++m) {
+          sa = fmaT(fmaT(tv[m0 + m], oc0A, ba), R[ADJ ? m : 0], sa);
+          sb = fmaT(fmaT(tv[m0 + m], oc0B, bb2), R[ADJ ? m : 0], sb);
+        }
+        gacc += (double)sa;
+        gaccB += (double)sb;
+      }
     }
     if (ADJ) {
+      if (merged) {
+        const T gL = gs[(ldu(feat + off) & kFeatureMask) * kTileStride + lane];
+        gacc += (double)(gL * oc0A * q0);
+        gaccB += (double)(gL * oc0B * q0);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) gaccB += __shfl_xor(gaccB, o, 64);
+        if (lane == 0 && gaccB != 0.0) unsafeAtomicAdd(&grad_leaf[leafB], gaccB);
+      }
 #pragma unroll
       for (int o = 32; o >= 1; o >>= 1) gacc += __shfl_xor(gacc, o, 64);
       if (lane == 0 && gacc != 0.0) unsafeAtomicAdd(&grad_leaf[leaf], gacc);
@@ -303,7 +361,8 @@ template <typename T, int DMAX, int NH, bool STORE_G, int NN>
 __global__ void __launch_bounds__(512)
 adjoint_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
                const float* __restrict__ lo, const float* __restrict__ hi,
-               const T* __restrict__ bb, const T* __restrict__ cbb, const float* __restrict__ X,
+               const T* __restrict__ bb, const T* __restrict__ cbb,
+               const SidePath* __restrict__ side, const float* __restrict__ X,
                const T* __restrict__ G, int64_t M, int64_t ldx, int32_t F, int32_t path_begin,
                int32_t path_end, int32_t chunk, int32_t nsb, double* __restrict__ grad_leaf,
                NodeConsts<T> nc) {
@@ -343,11 +402,11 @@ adjoint_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat
 #pragma unroll
   for (int m = 0; m < NN; ++m) tv[m] = to_vgpr(nc.t[m]);
   if (any_nan)
-    values_paths<T, DMAX, NH, STORE_G, true, true, NN>(hdr, feat, lo, hi, bb, cbb, nullptr, nullptr, xs,
+    values_paths<T, DMAX, NH, STORE_G, true, true, NN>(hdr, feat, lo, hi, bb, cbb, side, nullptr, xs,
                                                    nullptr, gs, grad_leaf, pb, pe, wave, nw,
                                                    lane, tv, nc);
   else
-    values_paths<T, DMAX, NH, STORE_G, false, true, NN>(hdr, feat, lo, hi, bb, cbb, nullptr, nullptr, xs,
+    values_paths<T, DMAX, NH, STORE_G, false, true, NN>(hdr, feat, lo, hi, bb, cbb, side, nullptr, xs,
                                                     nullptr, gs, grad_leaf, pb, pe, wave, nw,
                                                     lane, tv, nc);
 }
@@ -405,9 +464,9 @@ void launch_one(const HostTable& h, const DeviceTable& d, const PathArrays& a, c
 }
 
 template <typename T, int DMAX, int NH, bool STORE_G, int NN>
-void launch_adj_one(const HostTable& h, const DeviceTable& d, const Bucket& bk, const float* X,
-                    const void* G, int64_t M, int64_t ldx, double* grad_leaf,
-                    const ValuesShape& shape, hipStream_t s) {
+void launch_adj_one(const HostTable& h, const DeviceTable& d, const PathArrays& a,
+                    const Bucket& bk, const float* X, const void* G, int64_t M, int64_t ldx,
+                    double* grad_leaf, const ValuesShape& shape, hipStream_t s) {
   const int F = h.F;
   const int nsb = (int)((M + kSamplesPerBlock - 1) / kSamplesPerBlock);
   const int n_paths = bk.path_end - bk.path_begin;
@@ -418,8 +477,8 @@ void launch_adj_one(const HostTable& h, const DeviceTable& d, const Bucket& bk, 
   size_t xs = ((size_t)F * kTileStride * sizeof(float) + 15) & ~(size_t)15;
   const size_t lds = xs + (size_t)F * kTileStride * sizeof(T);
   const int threads = 64 * shape.waves_per_block;
-  const T* b = std::is_same<T, float>::value ? (const T*)d.b32 : (const T*)d.b64;
-  const T* cb = std::is_same<T, float>::value ? (const T*)d.cb32 : (const T*)d.cb64;
+  const T* b = std::is_same<T, float>::value ? (const T*)a.b32 : (const T*)a.b64;
+  const T* cb = std::is_same<T, float>::value ? (const T*)a.cb32 : (const T*)a.cb64;
   NodeConsts<T> nc;
   if constexpr (std::is_same<T, float>::value) nc = NN == 8 ? d.n32 : d.n32_4;
   else nc = NN == 8 ? d.n64 : d.n64_4;
@@ -427,34 +486,35 @@ void launch_adj_one(const HostTable& h, const DeviceTable& d, const Bucket& bk, 
   if (lds > values_lds_limit((const void*)adjoint_kernel<T, DMAX, NH, STORE_G, NN>, &cache))
     fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
   hipLaunchKernelGGL((adjoint_kernel<T, DMAX, NH, STORE_G, NN>), dim3((unsigned)grid),
-                     dim3(threads), lds, s, d.hdr, d.feat, d.lo, d.hi, b, cb, X, (const T*)G, M,
+                     dim3(threads), lds, s, a.hdr, a.feat, a.lo, a.hi, b, cb, a.side, X, (const T*)G, M,
                      ldx, F, bk.path_begin, bk.path_end, chunk, nsb, grad_leaf, nc);
   check_hip(hipGetLastError(), "adjoint_kernel launch");
 }
 
 }  // namespace
 
-void launch_adjoint(const HostTable& h, const DeviceTable& d, const Bucket& bk, bool fp64,
-                    const float* X, const void* G, int64_t M, int64_t ldx, double* grad_leaf,
-                    const ValuesShape& shape, int nodes, hipStream_t s) {
+void launch_adjoint(const HostTable& h, const DeviceTable& d, const PathArrays& a,
+                    const Bucket& bk, bool fp64, const float* X, const void* G, int64_t M,
+                    int64_t ldx, double* grad_leaf, const ValuesShape& shape, int nodes,
+                    hipStream_t s) {
   if (nodes == 4 && bk.dmax == 8) {
-    if (!fp64) launch_adj_one<float, 8, 4, true, 4>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s);
-    else launch_adj_one<double, 8, 4, false, 4>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s);
+    if (!fp64) launch_adj_one<float, 8, 4, true, 4>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s);
+    else launch_adj_one<double, 8, 4, false, 4>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s);
     return;
   }
   if (!fp64) {
     switch (bk.dmax) {
-      case 8: launch_adj_one<float, 8, 8, true, 8>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
-      case 16: launch_adj_one<float, 16, 8, true, 8>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
-      case 32: launch_adj_one<float, 32, 8, false, 8>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
-      default: launch_adj_one<float, 64, 4, false, 8>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      case 8: launch_adj_one<float, 8, 8, true, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      case 16: launch_adj_one<float, 16, 8, true, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      case 32: launch_adj_one<float, 32, 8, false, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      default: launch_adj_one<float, 64, 4, false, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s); break;
     }
   } else {
     switch (bk.dmax) {
-      case 8: launch_adj_one<double, 8, 8, false, 8>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
-      case 16: launch_adj_one<double, 16, 4, false, 8>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
-      case 32: launch_adj_one<double, 32, 4, false, 8>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
-      default: launch_adj_one<double, 64, 2, false, 8>(h, d, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      case 8: launch_adj_one<double, 8, 4, false, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      case 16: launch_adj_one<double, 16, 4, false, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      case 32: launch_adj_one<double, 32, 4, false, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      default: launch_adj_one<double, 64, 1, false, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s); break;
     }
   }
 }

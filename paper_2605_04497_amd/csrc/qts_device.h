@@ -120,11 +120,13 @@ void launch_values(const HostTable& h, const DeviceTable& d, const PathArrays& a
                    const double* leaf_val, double* acc, const ValuesShape& shape, int nodes,
                    hipStream_t s);
 
-// Adjoint: add J^T G over the paths of one bucket into grad_leaf (pre-zeroed).
+// Adjoint: add J^T G over the rows of one bucket into grad_leaf (pre-zeroed);
+// a merged row adds to both of its leaves.
 // G is [M, F] float (fp64 = false) or double.
-void launch_adjoint(const HostTable& h, const DeviceTable& d, const Bucket& bk, bool fp64,
-                    const float* X, const void* G, int64_t M, int64_t ldx, double* grad_leaf,
-                    const ValuesShape& shape, int nodes, hipStream_t s);
+void launch_adjoint(const HostTable& h, const DeviceTable& d, const PathArrays& a,
+                    const Bucket& bk, bool fp64, const float* X, const void* G, int64_t M,
+                    int64_t ldx, double* grad_leaf, const ValuesShape& shape, int nodes,
+                    hipStream_t s);
 
 // Interactions: accumulate the FP64 pair triangle [M][F(F-1)/2] and phi [M][F]
 // (both pre-zeroed) over the paths of one capacity class.

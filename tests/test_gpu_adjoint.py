@@ -142,3 +142,21 @@ def test_adjoint_edge_cases(q, oracle_mod):
     F = wl.ensemble.n_features
     g = e.shap_backward(torch.zeros((0, F), device="cuda"), torch.zeros((0, F), device="cuda"))
     assert g.shape == (wl.ensemble.n_leaves(),) and float(g.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("name,over", CASES, ids=[c[0] for c in CASES])
+def test_adjoint_merged_rows_match_plain(q, oracle_mod, name, over):
+    """A merged row gives both of its leaves' gradients from one pass (a
+    per-node vector shared by the two leaves); with merging off every leaf
+    has its own path.  Both equal the oracle's J^T G."""
+    wl = synth.make_workload(name, **over)
+    rng = np.random.default_rng(21)
+    G = rng.normal(size=wl.X.shape[:1] + (wl.ensemble.n_features,))
+    e = q.Ensemble(wl.ensemble)
+    assert e.info["n_merged"] > 0
+    X = torch.from_numpy(wl.X).cuda()
+    want = oracle_mod.leaf_grad(wl.ensemble, wl.X, G)
+    for merge in (True, False):
+        e.set_sibling_merge(merge)
+        g = e.shap_backward(X, torch.from_numpy(G).cuda(), "fp64").cpu().numpy()
+        assert normwise(g, want) <= 1e-10, (merge, normwise(g, want))
