@@ -33,9 +33,11 @@
  *
  * Streams: `stream` is a hipStream_t (NULL = the default stream).  Compute
  * calls are asynchronous on that stream; the caller synchronises before
- * reading outputs.  An ensemble is read-only after loading and may be used
- * from several streams concurrently.  qts_free_ensemble requires that no work
- * on the ensemble is still in flight.
+ * reading outputs.  Compute calls on one ensemble may run from several
+ * streams concurrently; the settings calls (qts_autotune,
+ * qts_set_graph_replay, qts_set_sibling_merge, qts_set_node_policy) must not
+ * overlap compute calls on the same ensemble.  qts_free_ensemble requires that
+ * no work on the ensemble is still in flight.
  *
  * Errors: every call returns QTS_OK (0) or a negative code below; the text of
  * the last error on the calling thread is available from qts_last_error().

@@ -1,7 +1,7 @@
 """Error measures shared by the GPU parity tests.
 
-Tolerances (derived in the design doc): the FP32 path must reach a row-normwise
-relative error of 1e-5 against the FP64 oracle, the FP64 path 1e-10:
+Tolerances: the FP32 path must reach a row-normwise relative error of 1e-5
+against the FP64 oracle, the FP64 path 1e-10:
     rel = max over rows r of  max_i |gpu[r,i] - oracle[r,i]| / max_i |oracle[r,i]|
 (for Phi the row is one sample's F x F matrix).  A per-element relative
 criterion is not reachable even by exact FP32 arithmetic: entries far below a
