@@ -357,8 +357,43 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
 
 // Generic form for long paths (any capacity up to 64): one wavefront per
 // path.  Lane j owns slot j (o_j, c_j, F_j(m), r_j(m) = c_j / F_j(m)); the
-// node products H(m) are reduced across lanes; then the wave's lanes take the
-// d(d-1)/2 pairs of the path in turn, reading r from a per-wave LDS area.
+// node products H(m) are reduced across lanes; each lane then leaves
+// g_j(m) = w val H(m) r_j(m), r_j(m), its feature and its triangle row offset
+// in the wave's LDS area, and the wave's lanes take the d(d-1)/2 pairs of the
+// path in turn: pair q -> (i, k) from a table built once per workgroup, then
+// SII_ik += sum_m g_i(m) r_k(m) from two 8-wide vector reads.
+constexpr int kPairTable = kMaxUnique * (kMaxUnique - 1) / 2;  // 2016 pairs of <= 64 slots
+
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<float> { using type = float4; static constexpr int n = 4; };
+template <>
+struct Vec2<double> { using type = double2; static constexpr int n = 2; };
+
+// Eight consecutive values from 16-byte aligned LDS.
+template <typename T>
+__device__ __forceinline__ void lds_load8(const T* p, T* out) {
+  using V = typename Vec2<T>::type;
+  constexpr int n = Vec2<T>::n;
+  const V* v = reinterpret_cast<const V*>(p);
+#pragma unroll
+  for (int q = 0; q < 8 / n; ++q) {
+    const V w = v[q];
+    if constexpr (n == 4) {
+      out[4 * q + 0] = w.x; out[4 * q + 1] = w.y; out[4 * q + 2] = w.z; out[4 * q + 3] = w.w;
+    } else {
+      out[2 * q + 0] = w.x; out[2 * q + 1] = w.y;
+    }
+  }
+}
+
+// LDS bytes of the generic kernel between the triangle and the sample row
+// (pair table, padding to 16 bytes, per-wave slot areas), for nw waves.
+__host__ __device__ constexpr size_t generic_mid_lds(int nw, size_t tsize) {
+  return (size_t)kPairTable * 2 + 16 + (size_t)nw * 64 * (2 * kNodes * tsize + 2 * sizeof(int));
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 pairs_generic_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
@@ -374,33 +409,52 @@ pairs_generic_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__
   const int64_t base0 = tri_row(r0);
   const int64_t ntri_r = tri_row(r1) - base0;
   const int nw = blockDim.x >> 6;
-  double* phis = reinterpret_cast<double*>(smem);           // [F]
-  double* tris = phis + F;                                  // [ntri_r]
-  T* rall = reinterpret_cast<T*>(tris + ntri_r);            // [nw][64][8]
-  int* fall = reinterpret_cast<int*>(rall + (size_t)nw * 64 * kNodes);  // [nw][64]
-  float* xrow = reinterpret_cast<float*>(fall + nw * 64);   // [F]
+  double* phis = reinterpret_cast<double*>(smem);  // [F]
+  double* tris = phis + F;                         // [ntri_r]
+  size_t off = (size_t)(F + ntri_r) * sizeof(double);
+  uint16_t* ptab = reinterpret_cast<uint16_t*>(smem + off);  // [kPairTable]: k << 8 | i
+  off = (off + (size_t)kPairTable * 2 + 15) & ~(size_t)15;
+  T* gall = reinterpret_cast<T*>(smem + off);      // [nw][64][8]
+  off += (size_t)nw * 64 * kNodes * sizeof(T);
+  T* rall = reinterpret_cast<T*>(smem + off);      // [nw][64][8]
+  off += (size_t)nw * 64 * kNodes * sizeof(T);
+  int* fall = reinterpret_cast<int*>(smem + off);  // [nw][64] feature
+  off += (size_t)nw * 64 * sizeof(int);
+  int* rball = reinterpret_cast<int*>(smem + off); // [nw][64] row offset, -1: out of range
+  off += (size_t)nw * 64 * sizeof(int);
+  float* xrow = reinterpret_cast<float*>(smem + off);  // [F]
 
   const int64_t s = (int64_t)blockIdx.x % M;
   const int ch = (int)((int64_t)blockIdx.x / M);
   const int p0 = ch * chunk;
   const int p1 = min(np, p0 + chunk);
-  pairs_prologue(phis, tris, ntri_r, xrow, X, s, ldx, F);
+  // pair q -> (i < k) with k(k-1)/2 <= q < k(k+1)/2
+  for (int q = threadIdx.x; q < kPairTable; q += blockDim.x) {
+    int k = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)q)) * 0.5f);
+    while (k * (k - 1) / 2 > q) --k;
+    while ((k + 1) * k / 2 <= q) ++k;
+    ptab[q] = (uint16_t)((k << 8) | (q - k * (k - 1) / 2));
+  }
+  pairs_prologue(phis, tris, ntri_r, xrow, X, s, ldx, F);  // ends with a barrier
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  T* gw = gall + (size_t)wave * 64 * kNodes;
   T* rw = rall + (size_t)wave * 64 * kNodes;
   int* fw = fall + wave * 64;
+  int* rbw = rball + wave * 64;
   for (int p = p0 + wave; p < p1; p += nw) {
     const int d = pd[p];
     const T val = (T)leaf_val[pleaf[p]];
-    T Fv[kNodes];
+    T Fv[kNodes], r[kNodes];
     bool z = false;
+    int f = 0;
     if (lane < d) {
       const int64_t e = (int64_t)lane * np + p;
       const int fm = feat[e];
       const float lov = lo[e], hiv = hi[e];
       const T b = bb[e], cb = cbb[e];
-      const int f = fm & kFeatureMask;
+      f = fm & kFeatureMask;
       const float x = xrow[f];
       const bool miss = (fm & kMissingOkBit) != 0;
       const bool lower = miss ? !(x < lov) : (x >= lov);
@@ -411,48 +465,53 @@ pairs_generic_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__
 #pragma unroll
       for (int m = 0; m < kNodes; ++m) {
         Fv[m] = fmaP(nc.t[m], c, bz);
-        rw[lane * kNodes + m] = c * rcpP(Fv[m]);
+        r[m] = c * rcpP(Fv[m]);
       }
-      fw[lane] = f;
     } else {
 #pragma unroll
-      for (int m = 0; m < kNodes; ++m) Fv[m] = T(1);
+      for (int m = 0; m < kNodes; ++m) {
+        Fv[m] = T(1);
+        r[m] = T(0);
+      }
     }
     // a factor that vanishes at every node zeroes the whole path
     if (__any(z) || val == T(0)) continue;
     // H(m) = prod over the lanes' factors (butterfly product)
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1)
+    for (int o = 32; o >= 1; o >>= 1)
 #pragma unroll
-      for (int m = 0; m < kNodes; ++m) Fv[m] *= __shfl_xor(Fv[m], off, 64);
-    T G[kNodes];
+      for (int m = 0; m < kNodes; ++m) Fv[m] *= __shfl_xor(Fv[m], o, 64);
+    T ph = T(0);
+    if (lane < d) {
 #pragma unroll
-    for (int m = 0; m < kNodes; ++m) G[m] = nc.w[m] * val * Fv[m];
+      for (int m = 0; m < kNodes; ++m) {
+        const T g = nc.w[m] * val * Fv[m] * r[m];
+        ph += g;
+        gw[lane * kNodes + m] = g;
+        rw[lane * kNodes + m] = r[m];
+      }
+      fw[lane] = f;
+      rbw[lane] = (f >= r0 && f < r1) ? (int)(tri_row(f) - base0) : -1;
+      if (with_phi) lds_add(&phis[f], (double)ph);
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (lane < d && with_phi) {
-      T ph = T(0);
-#pragma unroll
-      for (int m = 0; m < kNodes; ++m) ph = fmaP(G[m], rw[lane * kNodes + m], ph);
-      lds_add(&phis[fw[lane]], (double)ph);
-    }
     const int npair = d * (d - 1) / 2;
     for (int q = lane; q < npair; q += 64) {
-      // pair q -> (i < k): k(k-1)/2 <= q < k(k+1)/2
-      int k = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)q)) * 0.5f);
-      while (k * (k - 1) / 2 > q) --k;
-      while ((k + 1) * k / 2 <= q) ++k;
-      const int i = q - k * (k - 1) / 2;
-      const int fi = fw[i], fk = fw[k];
-      if (fk < r0 || fk >= r1) continue;
-      T pr = T(0);
+      const int e = ptab[q];
+      const int i = e & 0xFF, k = e >> 8;
+      const int rbk = rbw[k];
+      if (rbk < 0) continue;
+      T gi[kNodes], rk[kNodes];
+      lds_load8(gw + i * kNodes, gi);
+      lds_load8(rw + k * kNodes, rk);
+      T pr = gi[0] * rk[0];
 #pragma unroll
-      for (int m = 0; m < kNodes; ++m)
-        pr = fmaP(G[m] * rw[i * kNodes + m], rw[k * kNodes + m], pr);
-      lds_add(&tris[tri_row(fk) - base0 + fi], (double)pr);
+      for (int m = 1; m < kNodes; ++m) pr = fmaP(gi[m], rk[m], pr);
+      lds_add(&tris[rbk + fw[i]], (double)pr);
     }
-    // the next path overwrites this wave's r and feature slots
+    // the next path overwrites this wave's slot areas
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -503,13 +562,10 @@ namespace {
 constexpr int kGenericThreads = 256;
 
 // LDS bytes besides the triangle rows: the FP64 phi row, the sample row and,
-// for the generic kernel, each wave's r and feature slots.
+// for the generic kernel, the pair table and each wave's slot areas.
 size_t pairs_fixed_lds(int F, size_t tsize, bool generic) {
   size_t b = (size_t)F * sizeof(double) + (size_t)F * sizeof(float);
-  if (generic) {
-    const int nw = kGenericThreads / 64;
-    b += (size_t)nw * 64 * kNodes * tsize + (size_t)nw * 64 * sizeof(int);
-  }
+  if (generic) b += generic_mid_lds(kGenericThreads / 64, tsize);
   return b;
 }
 

@@ -157,3 +157,19 @@ def test_merged_sibling_rows_cancellation(q, oracle_mod):
             check(phi, phi_o, precision, "sibling values phi")
             Phi, phi, _ = _run(q, ens, X, precision, leaf_values=v)
             check(Phi, Phi_o, precision, "override Phi")
+
+
+def test_long_paths_with_split_triangle(q, oracle_mod):
+    """Paths longer than the register-resident instances take (the
+    wave-per-path kernel and its pair table) together with more features
+    than one LDS triangle holds (row ranges), in both precisions."""
+    rng = np.random.default_rng(900)
+    ens = synth.random_small_ensemble(rng, 3, 260, 34, n_train=4000, p_leaf=0.0)
+    X = rng.standard_normal((23, 260)).astype(np.float32)
+    X[::6, ::11] = np.nan
+    phi_o, Phi_o = oracle_mod.shap_interactions(ens, X, n=8)
+    for precision in ("fp32", "fp64"):
+        Phi, phi, e = _run(q, ens, X, precision)
+        assert e.info["max_unique"] > 24
+        check(Phi, Phi_o, precision, "long paths Phi")
+        check(phi, phi_o, precision, "long paths phi")
