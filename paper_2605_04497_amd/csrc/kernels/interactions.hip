@@ -388,46 +388,6 @@ __device__ __forceinline__ void lds_load8(const T* p, T* out) {
   }
 }
 
-// Product of v over the 64 lanes of the wavefront, returned to every lane.
-// DPP steps inside each row of 16 lanes (row_shr 1, 2, 4, 8; lanes with no
-// source take 1), then across rows (row_bcast 15 into rows 1 and 3,
-// row_bcast 31 into rows 2 and 3): lane 63 then holds the product of all
-// lanes, read back with readlane.
-__device__ __forceinline__ int dpp_step(int old, int v, int ctrl_sel, int rmask) {
-  switch (ctrl_sel) {
-    case 0: return __builtin_amdgcn_update_dpp(old, v, 0x111, 0xf, 0xf, false);
-    case 1: return __builtin_amdgcn_update_dpp(old, v, 0x112, 0xf, 0xf, false);
-    case 2: return __builtin_amdgcn_update_dpp(old, v, 0x114, 0xf, 0xf, false);
-    case 3: return __builtin_amdgcn_update_dpp(old, v, 0x118, 0xf, 0xf, false);
-    case 4: return __builtin_amdgcn_update_dpp(old, v, 0x142, 0xa, 0xf, false);
-    default: return __builtin_amdgcn_update_dpp(old, v, 0x143, 0xc, 0xf, false);
-  }
-  (void)rmask;
-}
-
-__device__ __forceinline__ float wave_prod(float v) {
-#pragma unroll
-  for (int st = 0; st < 6; ++st)
-    v *= __int_as_float(dpp_step(__float_as_int(1.0f), __float_as_int(v), st, 0));
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
-}
-
-__device__ __forceinline__ double wave_prod(double v) {
-  const long long one = __double_as_longlong(1.0);
-  const int one_lo = (int)(one & 0xffffffffLL), one_hi = (int)(one >> 32);
-#pragma unroll
-  for (int st = 0; st < 6; ++st) {
-    const long long bits = __double_as_longlong(v);
-    const int lo = dpp_step(one_lo, (int)(bits & 0xffffffffLL), st, 0);
-    const int hi = dpp_step(one_hi, (int)(bits >> 32), st, 0);
-    v *= __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-  }
-  const long long bits = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), 63);
-  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), 63);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
 // LDS bytes of the generic kernel between the triangle and the sample row
 // (pair table, padding to 16 bytes, per-wave slot areas), for nw waves.
 __host__ __device__ constexpr size_t generic_mid_lds(int nw, size_t tsize) {

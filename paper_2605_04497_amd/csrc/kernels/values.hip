@@ -57,7 +57,8 @@ __device__ __forceinline__ double to_vgpr(double v) {
 // ADJ: adjoint mode.  phi is linear in the leaf value, so d phi[s, f_j] /
 // d val = c_j LOO_j; instead of scattering val c_j LOO_j into the phi tile,
 // each lane gathers g[s, f_j] c_j LOO_j from the upstream-gradient tile gs,
-// the wave sums its 64 samples in FP64 and adds the result to grad_leaf.
+// the wave sums its 64 samples in FP64 (DPP reduction into lane 63) and adds
+// the result to grad_leaf.
 template <typename T, int DMAX, int NH, bool STORE_G, bool NANS, bool ADJ, int NN>
 __device__ __forceinline__ void values_paths(
     const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
@@ -274,13 +275,11 @@ __device__ __forceinline__ void values_paths(
         const T gL = gs[(ldu(feat + off) & kFeatureMask) * kTileStride + lane];
         gacc += (double)(gL * oc0A * q0);
         gaccB += (double)(gL * oc0B * q0);
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) gaccB += __shfl_xor(gaccB, o, 64);
-        if (lane == 0 && gaccB != 0.0) unsafeAtomicAdd(&grad_leaf[leafB], gaccB);
+        gaccB = wave_sum_last(gaccB);
+        if (lane == 63 && gaccB != 0.0) unsafeAtomicAdd(&grad_leaf[leafB], gaccB);
       }
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) gacc += __shfl_xor(gacc, o, 64);
-      if (lane == 0 && gacc != 0.0) unsafeAtomicAdd(&grad_leaf[leaf], gacc);
+      gacc = wave_sum_last(gacc);
+      if (lane == 63 && gacc != 0.0) unsafeAtomicAdd(&grad_leaf[leaf], gacc);
     }
   }
 }

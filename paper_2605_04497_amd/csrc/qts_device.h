@@ -106,6 +106,58 @@ __device__ __forceinline__ T ldu(const T* p) {
           (const __attribute__((address_space(4))) void*)p));
 }
 
+// Wavefront reductions with DPP (no LDS): inclusive steps inside each row of
+// 16 lanes (row_shr 1, 2, 4, 8; a lane with no source takes `old`, the
+// identity), then across rows (row_bcast 15 into rows 1 and 3, row_bcast 31
+// into rows 2 and 3).  Lane 63 then holds the reduction of all 64 lanes.
+// Every lane of the wavefront must be active.
+__device__ __forceinline__ int dpp_step(int old, int v, int st) {
+  switch (st) {
+    case 0: return __builtin_amdgcn_update_dpp(old, v, 0x111, 0xf, 0xf, false);
+    case 1: return __builtin_amdgcn_update_dpp(old, v, 0x112, 0xf, 0xf, false);
+    case 2: return __builtin_amdgcn_update_dpp(old, v, 0x114, 0xf, 0xf, false);
+    case 3: return __builtin_amdgcn_update_dpp(old, v, 0x118, 0xf, 0xf, false);
+    case 4: return __builtin_amdgcn_update_dpp(old, v, 0x142, 0xa, 0xf, false);
+    default: return __builtin_amdgcn_update_dpp(old, v, 0x143, 0xc, 0xf, false);
+  }
+}
+
+__device__ __forceinline__ double dpp_step(double old, double v, int st) {
+  const long long o = __double_as_longlong(old), b = __double_as_longlong(v);
+  const int lo = dpp_step((int)(o & 0xffffffffLL), (int)(b & 0xffffffffLL), st);
+  const int hi = dpp_step((int)(o >> 32), (int)(b >> 32), st);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ float dpp_step(float old, float v, int st) {
+  return __int_as_float(dpp_step(__float_as_int(old), __float_as_int(v), st));
+}
+
+__device__ __forceinline__ float read_lane63(float v) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ __forceinline__ double read_lane63(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Product over the wavefront, returned to every lane.
+template <typename T>
+__device__ __forceinline__ T wave_prod(T v) {
+#pragma unroll
+  for (int st = 0; st < 6; ++st) v *= dpp_step(T(1), v, st);
+  return read_lane63(v);
+}
+
+// Sum over the wavefront, valid in lane 63 only.
+__device__ __forceinline__ double wave_sum_last(double v) {
+#pragma unroll
+  for (int st = 0; st < 6; ++st) v += dpp_step(0.0, v, st);
+  return v;
+}
+
 void launch_fill_zero(double* p, int64_t n, hipStream_t s);
 // Seeded uniform values in [-3, 3) (inputs for timing launch shapes).
 void launch_fill_uniform(float* p, int64_t n, uint32_t seed, hipStream_t s);
