@@ -500,7 +500,7 @@ def main():
                      "lane_ops_per_launch": LANE_OPS_PER_ELEMENT * float(M) * n_vel,
                      "lane_op_frac": LANE_OPS_PER_ELEMENT * float(M) * n_vel
                      / (r32["kernel_ms"] * 1e-3) / PEAK_LANE_OPS,
-                     "kernel": "values_kernel<float, 8, 8, true>", "kernel_ms": r32["kernel_ms"],
+                     "kernel": "values_kernel<float, 8, 8, true, 8>", "kernel_ms": r32["kernel_ms"],
                      "kernel_ms_scope": "event pair around each graph replay (zero-fill, "
                                         "values kernel, cast)" if not args.eager else
                                         "event pair around the values kernel launches",
