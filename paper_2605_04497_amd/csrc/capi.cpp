@@ -317,20 +317,34 @@ const PairShape& pair_shape(const qts_ensemble* ens, bool fp64, size_t i) {
 }
 
 // The launches of one call, on `ln` (acc: the FP64 accumulators of the call).
+// Rows of the first-order table in use and the call's scratch: the Slot0
+// records first, then (FP32) the FP64 accumulator at a 256-byte boundary.
+int32_t value_rows(const qts_ensemble* ens) {
+  return (int32_t)(ens->merge_siblings ? ens->host.mhdr.size() : ens->host.hdr.size());
+}
+size_t slot0_region(const qts_ensemble* ens, bool fp64) {
+  return (slot0_bytes(value_rows(ens), fp64) + 255) & ~(size_t)255;
+}
+size_t values_scratch_bytes(const qts_ensemble* ens, int64_t M, bool fp64) {
+  return slot0_region(ens, fp64) + (fp64 ? 0 : sizeof(double) * (size_t)(M * ens->host.F));
+}
+
 void issue_values(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
-                  const double* leaf, void* phi, bool fp64, double* acc, Lanes& ln,
+                  const double* leaf, void* phi, bool fp64, void* scratch, Lanes& ln,
                   bool timed) {
   const HostTable& h = ens->host;
   const int64_t n = M * h.F;
-  double* a = fp64 ? (double*)phi : acc;
+  void* slot0 = scratch;
+  double* a = fp64 ? (double*)phi : (double*)((char*)scratch + slot0_region(ens, fp64));
+  const PathArrays arr = ens->merge_siblings ? merged_arrays(ens->dev) : plain_arrays(ens->dev);
   launch_fill_zero(a, n, ln.main);
+  launch_slot0(arr, value_rows(ens), leaf, fp64, slot0, ln.main);
   TimedScope ts(0, timed ? ln.main : nullptr, timed);
   const std::vector<Bucket>& bks = ens->merge_siblings ? h.mbuckets : h.buckets;
-  const PathArrays arr = ens->merge_siblings ? merged_arrays(ens->dev) : plain_arrays(ens->dev);
   ln.fork((int)bks.size());
   for (size_t i = 0; i < bks.size(); ++i) {
     const Bucket& bk = bks[i];
-    launch_values(h, ens->dev, arr, bk, fp64, X, M, ldx, leaf, a,
+    launch_values(h, ens->dev, arr, bk, fp64, X, M, ldx, slot0, a,
                   ens->vshape[fp64 ? 1 : 0][cap_index(bk.dmax)], nodes_of(ens), ln.pick((int)i));
   }
   ln.join();
@@ -636,22 +650,18 @@ int qts_shap_values(const qts_ensemble* ens, const float* X, int64_t M, int64_t 
     hipStream_t s = (hipStream_t)stream;
     const bool fp64 = precision == QTS_FP64;
     const double* leaf = leaf_values ? leaf_values : ens->dev.leaf_val;
-    const size_t acc_bytes = fp64 ? 0 : sizeof(double) * (size_t)(M * ens->host.F);
+    const size_t scratch_bytes = values_scratch_bytes(ens, M, fp64);
     qts_ensemble* me = const_cast<qts_ensemble*>(ens);  // the graph cache only
     if (ens->graphs.on) {
       GraphKey key{0, fp64, X, M, ldx, leaf, phi, nullptr, s};
-      run_graph(me, key, acc_bytes, 0, [&](Lanes& ln, double* acc) {
-        issue_values(ens, X, M, ldx, leaf, phi, fp64, acc, ln, false);
+      run_graph(me, key, scratch_bytes, 0, [&](Lanes& ln, double* scratch) {
+        issue_values(ens, X, M, ldx, leaf, phi, fp64, scratch, ln, false);
       });
       return;
     }
     Lanes ln{s, nullptr};
-    if (fp64) {
-      issue_values(ens, X, M, ldx, leaf, phi, true, nullptr, ln, true);
-    } else {
-      Scratch acc(acc_bytes, s);
-      issue_values(ens, X, M, ldx, leaf, phi, false, (double*)acc.p, ln, true);
-    }
+    Scratch scratch(scratch_bytes, s);
+    issue_values(ens, X, M, ldx, leaf, phi, fp64, scratch.p, ln, true);
   });
 }
 
@@ -808,6 +818,8 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
       launch_fill_zero((double*)acc.p, Mt * F, s);
       const std::vector<Bucket>& bks = ens->merge_siblings ? h.mbuckets : h.buckets;
       const PathArrays arr = ens->merge_siblings ? merged_arrays(d) : plain_arrays(d);
+      Scratch slot0(slot0_bytes(value_rows(ens), fp64), s);
+      launch_slot0(arr, value_rows(ens), d.leaf_val, fp64, slot0.p, s);
       for (const Bucket& bk : bks) {
         ValuesShape best;
         float best_ms = 1e30f;
@@ -815,7 +827,7 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
           for (int items : {4096, 8192, 16384, 32768, 65536}) {
             const ValuesShape cand{waves, items};
             const float ms = time_ms(3, [&] {
-              launch_values(h, d, arr, bk, fp64, X, Mt, F, d.leaf_val, (double*)acc.p, cand,
+              launch_values(h, d, arr, bk, fp64, X, Mt, F, slot0.p, (double*)acc.p, cand,
                             nodes_of(ens), s);
             });
             if (ms < best_ms) {

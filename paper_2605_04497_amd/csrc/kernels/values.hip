@@ -20,6 +20,9 @@
 //   F_j(m) = b_j (1 - t_m) + o_j t_m = b_j + t_m c_j      (one FMA per node)
 //   LOO_j  = sum_m w_m prod_{k != j} F_k(m)    by prefix x suffix products
 //   phi[s, f_j] += val c_j LOO_j
+// The leaf value is folded into slot 0 (Slot0: F_0 scaled by val, built per
+// call in FP64), so a row needs no multiply by val; a merged sibling pair is
+// the same form with a combined slot-0 factor.
 // Slots past the end of a path get c = 0 and b = 1, a factor of exactly 1, so
 // whole batches of eight features run without branches.  The prefix products
 // are kept only at batch checkpoints and rebuilt batch by batch in the
@@ -64,7 +67,7 @@ __device__ __forceinline__ void values_paths(
     const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
     const float* __restrict__ lo, const float* __restrict__ hi, const T* __restrict__ bb,
     const T* __restrict__ cbb, const SidePath* __restrict__ side,
-    const double* __restrict__ leaf_val, const float* xs, double* as, const T* gs,
+    const Slot0<T>* __restrict__ z0, const float* xs, double* as, const T* gs,
     double* __restrict__ grad_leaf, int pb, int pe, int wave, int nw, int lane, const T* tv,
     const NodeConsts<T>& nc) {
   constexpr int NB = DMAX / 8;  // feature batches
@@ -72,49 +75,44 @@ __device__ __forceinline__ void values_paths(
     const int d = ldu(&hdr[p].d);
     const int off = ldu(&hdr[p].off);
     const int leaf = ldu(&hdr[p].leaf);
-    T val = ADJ ? T(1) : (T)ldu(leaf_val + leaf);
-    // A merged sibling pair: slot 0 is the parent's split feature L.
-    // First order: L's factor is vA F_A + vB F_B = bm + t c, where c is cA
-    // when the sample follows A's interval, cB when it follows B's, else -bm;
-    // the path's leaf value is then 1.  Built here in FP64 from the leaf
-    // values (which a call may override), then rounded to T.
-    // Adjoint: slot 0 is made inert in the products (b = 1, c = 0), so the
-    // sweep yields w Q_j(m) = w prod_{k >= 1, k != j} F_k(m); then
+    // First order: slot 0 comes from Slot0 (leaf value folded in; the row's
+    // own b_0, 1 - b_0 are not read).  Adjoint of a merged sibling pair:
+    // slot 0 is the parent's split feature L, made inert in the products
+    // (b = 1, c = 0), so the sweep yields w Q_j(m) = w prod_{k >= 1, k != j} F_k(m);
+    // then
     //   d/dvA = sum_m F_A(m) R(m) + g_L c_A sum_m w Q_0(m),
     //   R(m) = sum_{j >= 1} g_j c_j w Q_j(m)   (shared by A and B),
     // and likewise for B with F_B and c_B.
-    const int sidx = side == nullptr ? -1 : ldu(&hdr[p].tree);
-    const bool merged = sidx >= 0;
+    const int sidx = (!ADJ || side == nullptr) ? -1 : ldu(&hdr[p].tree);
+    const bool merged = sidx >= 0;  // adjoint only
+    const bool own0 = !ADJ || merged;  // slot 0 not taken from the row's elements
     T bm = T(0), cA = T(0), cB = T(0);
     T ba = T(0), cba = T(0), bb2 = T(0), cbb2 = T(0);
     float loB = 0.f, hiB = 0.f;
     bool mokB = false;
     int leafB = 0;
-    if (merged) {
+    if (!ADJ) {
+      const Slot0<T>* z = z0 + p;
+      bm = ldu(&z->bm);
+      cA = ldu(&z->ca);
+      cB = ldu(&z->cb);
+      loB = ldu(&z->lo_b);
+      hiB = ldu(&z->hi_b);
+      mokB = ldu(&z->mok_b) != 0;
+    } else if (merged) {
       const SidePath* sp = side + sidx;
       leafB = ldu(&sp->leaf_b);
       loB = ldu(&sp->lo_b);
       hiB = ldu(&sp->hi_b);
       mokB = ldu(&sp->mok_b) != 0;
-      if (ADJ) {
-        ba = (T)ldu(&sp->b_a);
-        cba = (T)ldu(&sp->cb_a);
-        bb2 = (T)ldu(&sp->b_b);
-        cbb2 = (T)ldu(&sp->cb_b);
-        bm = T(1);
-      } else {
-        const double va = ldu(leaf_val + leaf);
-        const double vb = ldu(leaf_val + leafB);
-        const double dba = ldu(&sp->b_a), dcba = ldu(&sp->cb_a);
-        const double dbb = ldu(&sp->b_b), dcbb = ldu(&sp->cb_b);
-        bm = (T)(va * dba + vb * dbb);
-        cA = (T)(va * dcba - vb * dbb);
-        cB = (T)(vb * dcbb - va * dba);
-        val = T(1);
-      }
+      ba = (T)ldu(&sp->b_a);
+      cba = (T)ldu(&sp->cb_a);
+      bb2 = (T)ldu(&sp->b_b);
+      cbb2 = (T)ldu(&sp->cb_b);
+      bm = T(1);
     }
     // b_j of slot j (slot 0 of a merged path: bm)
-    auto bload = [&](int j) -> T { return (j == 0 && merged) ? bm : ldu(bb + off + j); };
+    auto bload = [&](int j) -> T { return (j == 0 && own0) ? bm : ldu(bb + off + j); };
     double gacc = 0.0;
     double gaccB = 0.0;          // adjoint of a merged path: B's gradient
     T oc0A = T(0), oc0B = T(0);  // adjoint of a merged path: c_A and c_B
@@ -153,7 +151,7 @@ __device__ __forceinline__ void values_paths(
           }
           const bool upper = !(x[k] >= u[k]);
           cf[jb + k] = (lower & upper) ? cbl[k] : -bl[k];
-          if (b == 0 && k == 0 && merged) {
+          if (b == 0 && k == 0 && own0) {
             bool lowerB;
             if (NANS) lowerB = mokB ? !(x[0] < loB) : (x[0] >= loB);
             else lowerB = x[0] >= loB;
@@ -243,7 +241,7 @@ __device__ __forceinline__ void values_paths(
                 if (ADJ) {
                   gacc += (double)(gs[f * kTileStride + lane] * cf[j] * dot);
                 } else {
-                  const double c = (double)(val * cf[j] * dot);
+                  const double c = (double)(cf[j] * dot);
                   __hip_atomic_fetch_add(&as[f * kTileStride + lane], c, __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
@@ -289,8 +287,7 @@ __global__ void __launch_bounds__(512)
 values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
               const float* __restrict__ lo, const float* __restrict__ hi,
               const T* __restrict__ bb, const T* __restrict__ cbb,
-              const SidePath* __restrict__ side,
-              const double* __restrict__ leaf_val, const float* __restrict__ X, int64_t M,
+              const Slot0<T>* __restrict__ z0, const float* __restrict__ X, int64_t M,
               int64_t ldx, int32_t F, int32_t path_begin, int32_t path_end, int32_t chunk,
               int32_t nsb, double* __restrict__ acc, NodeConsts<T> nc) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -333,13 +330,13 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
   for (int m = 0; m < NN; ++m) tv[m] = to_vgpr(nc.t[m]);
 
   if (any_nan)
-    values_paths<T, DMAX, NH, STORE_G, true, false, NN>(hdr, feat, lo, hi, bb, cbb, side, leaf_val, xs,
-                                                    as, nullptr, nullptr, pb, pe, wave, nw, lane,
-                                                    tv, nc);
+    values_paths<T, DMAX, NH, STORE_G, true, false, NN>(hdr, feat, lo, hi, bb, cbb, nullptr,
+                                                        z0, xs, as, nullptr, nullptr, pb,
+                                                        pe, wave, nw, lane, tv, nc);
   else
-    values_paths<T, DMAX, NH, STORE_G, false, false, NN>(hdr, feat, lo, hi, bb, cbb, side, leaf_val, xs,
-                                                     as, nullptr, nullptr, pb, pe, wave, nw, lane,
-                                                     tv, nc);
+    values_paths<T, DMAX, NH, STORE_G, false, false, NN>(hdr, feat, lo, hi, bb, cbb, nullptr,
+                                                         z0, xs, as, nullptr, nullptr, pb,
+                                                         pe, wave, nw, lane, tv, nc);
   __syncthreads();
 
   // flush: consecutive threads take consecutive features of one sample
@@ -401,13 +398,13 @@ adjoint_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat
 #pragma unroll
   for (int m = 0; m < NN; ++m) tv[m] = to_vgpr(nc.t[m]);
   if (any_nan)
-    values_paths<T, DMAX, NH, STORE_G, true, true, NN>(hdr, feat, lo, hi, bb, cbb, side, nullptr, xs,
-                                                   nullptr, gs, grad_leaf, pb, pe, wave, nw,
-                                                   lane, tv, nc);
+    values_paths<T, DMAX, NH, STORE_G, true, true, NN>(hdr, feat, lo, hi, bb, cbb, side, nullptr,
+                                                       xs, nullptr, gs, grad_leaf, pb, pe,
+                                                       wave, nw, lane, tv, nc);
   else
-    values_paths<T, DMAX, NH, STORE_G, false, true, NN>(hdr, feat, lo, hi, bb, cbb, side, nullptr, xs,
-                                                    nullptr, gs, grad_leaf, pb, pe, wave, nw,
-                                                    lane, tv, nc);
+    values_paths<T, DMAX, NH, STORE_G, false, true, NN>(hdr, feat, lo, hi, bb, cbb, side, nullptr,
+                                                        xs, nullptr, gs, grad_leaf, pb, pe,
+                                                        wave, nw, lane, tv, nc);
 }
 
 namespace {
@@ -437,7 +434,7 @@ size_t values_lds_limit(const void* fn, size_t* cache) {
 
 template <typename T, int DMAX, int NH, bool STORE_G, int NN>
 void launch_one(const HostTable& h, const DeviceTable& d, const PathArrays& a, const Bucket& bk,
-                const float* X, int64_t M, int64_t ldx, const double* leaf_val, double* acc,
+                const float* X, int64_t M, int64_t ldx, const void* slot0, double* acc,
                 const ValuesShape& shape, hipStream_t s) {
   const int F = h.F;
   const int nsb = (int)((M + kSamplesPerBlock - 1) / kSamplesPerBlock);
@@ -457,7 +454,8 @@ void launch_one(const HostTable& h, const DeviceTable& d, const PathArrays& a, c
   if (lds > values_lds_limit((const void*)values_kernel<T, DMAX, NH, STORE_G, NN>, &cache))
     fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
   hipLaunchKernelGGL((values_kernel<T, DMAX, NH, STORE_G, NN>), dim3((unsigned)grid),
-                     dim3(threads), lds, s, a.hdr, a.feat, a.lo, a.hi, b, cb, a.side, leaf_val, X,
+                     dim3(threads), lds, s, a.hdr, a.feat, a.lo, a.hi, b, cb,
+                     (const Slot0<T>*)slot0, X,
                      M, ldx, F, bk.path_begin, bk.path_end, chunk, nsb, acc, nc);
   check_hip(hipGetLastError(), "values_kernel launch");
 }
@@ -518,30 +516,83 @@ void launch_adjoint(const HostTable& h, const DeviceTable& d, const PathArrays& 
   }
 }
 
+// Slot 0 of every first-order row with the current leaf values folded in.
+template <typename T>
+__global__ void __launch_bounds__(256)
+slot0_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
+             const float* __restrict__ lo, const float* __restrict__ hi,
+             const double* __restrict__ b64, const double* __restrict__ cb64,
+             const SidePath* __restrict__ side, const double* __restrict__ leaf_val, int32_t n,
+             Slot0<T>* __restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const PathHdr h = hdr[r];
+  Slot0<T> z{T(0), T(0), T(0), 0.f, 0.f, 0};
+  const int sidx = side == nullptr ? -1 : h.tree;
+  if (h.d > 0 && sidx >= 0) {
+    const SidePath sp = side[sidx];
+    const double va = leaf_val[h.leaf];
+    const double vb = leaf_val[sp.leaf_b];
+    z.bm = (T)(va * sp.b_a + vb * sp.b_b);
+    z.ca = (T)(va * sp.cb_a - vb * sp.b_b);
+    z.cb = (T)(vb * sp.cb_b - va * sp.b_a);
+    z.lo_b = sp.lo_b;
+    z.hi_b = sp.hi_b;
+    z.mok_b = sp.mok_b;
+  } else if (h.d > 0) {
+    const double v = leaf_val[h.leaf];
+    const double bm = v * b64[h.off];
+    z.bm = (T)bm;
+    z.ca = (T)(v * cb64[h.off]);
+    z.cb = (T)(-bm);
+    z.lo_b = lo[h.off];
+    z.hi_b = hi[h.off];
+    z.mok_b = (feat[h.off] & kMissingOkBit) != 0 ? 1 : 0;
+  }
+  out[r] = z;
+}
+
+size_t slot0_bytes(int32_t n_rows, bool fp64) {
+  return (size_t)n_rows * (fp64 ? sizeof(Slot0<double>) : sizeof(Slot0<float>));
+}
+
+void launch_slot0(const PathArrays& a, int32_t n_rows, const double* leaf_val, bool fp64,
+                  void* out, hipStream_t s) {
+  if (n_rows <= 0) return;
+  const unsigned grid = (unsigned)((n_rows + 255) / 256);
+  if (fp64)
+    hipLaunchKernelGGL(slot0_kernel<double>, dim3(grid), dim3(256), 0, s, a.hdr, a.feat, a.lo,
+                       a.hi, a.b64, a.cb64, a.side, leaf_val, n_rows, (Slot0<double>*)out);
+  else
+    hipLaunchKernelGGL(slot0_kernel<float>, dim3(grid), dim3(256), 0, s, a.hdr, a.feat, a.lo,
+                       a.hi, a.b64, a.cb64, a.side, leaf_val, n_rows, (Slot0<float>*)out);
+  check_hip(hipGetLastError(), "slot0_kernel launch");
+}
+
 void launch_values(const HostTable& h, const DeviceTable& d, const PathArrays& a,
                    const Bucket& bk, bool fp64, const float* X, int64_t M, int64_t ldx,
-                   const double* leaf_val, double* acc, const ValuesShape& shape, int nodes,
+                   const void* slot0, double* acc, const ValuesShape& shape, int nodes,
                    hipStream_t s) {
   if (values_lds_bytes(h.F) > (size_t)kMaxLdsBytes)
     fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
   if (nodes == 4 && bk.dmax == 8) {
-    if (!fp64) launch_one<float, 8, 4, true, 4>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s);
-    else launch_one<double, 8, 4, false, 4>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s);
+    if (!fp64) launch_one<float, 8, 4, true, 4>(h, d, a, bk, X, M, ldx, slot0, acc, shape, s);
+    else launch_one<double, 8, 4, false, 4>(h, d, a, bk, X, M, ldx, slot0, acc, shape, s);
     return;
   }
   if (!fp64) {
     switch (bk.dmax) {
-      case 8: launch_one<float, 8, 8, true, 8>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      case 16: launch_one<float, 16, 8, true, 8>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      case 32: launch_one<float, 32, 8, false, 8>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      default: launch_one<float, 64, 4, false, 8>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 8: launch_one<float, 8, 8, true, 8>(h, d, a, bk, X, M, ldx, slot0, acc, shape, s); break;
+      case 16: launch_one<float, 16, 8, true, 8>(h, d, a, bk, X, M, ldx, slot0, acc, shape, s); break;
+      case 32: launch_one<float, 32, 8, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, shape, s); break;
+      default: launch_one<float, 64, 4, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, shape, s); break;
     }
   } else {
     switch (bk.dmax) {
-      case 8: launch_one<double, 8, 8, false, 8>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      case 16: launch_one<double, 16, 4, false, 8>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      case 32: launch_one<double, 32, 4, false, 8>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
-      default: launch_one<double, 64, 2, false, 8>(h, d, a, bk, X, M, ldx, leaf_val, acc, shape, s); break;
+      case 8: launch_one<double, 8, 8, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, shape, s); break;
+      case 16: launch_one<double, 16, 4, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, shape, s); break;
+      case 32: launch_one<double, 32, 4, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, shape, s); break;
+      default: launch_one<double, 64, 2, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, shape, s); break;
     }
   }
 }

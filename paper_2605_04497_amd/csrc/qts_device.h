@@ -73,6 +73,21 @@ inline PathArrays merged_arrays(const DeviceTable& d) {
   return PathArrays{d.mhdr, d.mfeat, d.mlo, d.mhi, d.mb32, d.mcb32, d.mb64, d.mcb64, d.side};
 }
 
+// Slot 0 of a first-order row with its leaf value folded in, built per call
+// from the current leaf values (launch_slot0).  The row's polynomial is
+//   F_0(t) prod_{j >= 1} F_j(t),  F_0(t) = bm + t c,
+// c = ca when the sample is in A's interval on slot 0's feature, else cb when
+// it is in B's, else -bm.  A merged sibling pair: bm = vA b_A + vB b_B,
+// ca = vA (1 - b_A) - vB b_B, cb = vB (1 - b_B) - vA b_A.  A single path with
+// value v: bm = v b_0, ca = v (1 - b_0), cb = -bm (B's interval is A's).  The
+// products are taken in FP64 and rounded once to T.
+template <typename T>
+struct Slot0 {
+  T bm, ca, cb;
+  float lo_b, hi_b;  // B's interval on slot 0's feature (hi = NaN: no bound)
+  int32_t mok_b;     // 1: a NaN follows B's splits there
+};
+
 // Launch shape of the first-order (and adjoint) kernel for one bucket.
 struct ValuesShape {
   int waves_per_block = 8;  // wavefronts sharing one 64-sample tile
@@ -163,13 +178,20 @@ void launch_fill_zero(double* p, int64_t n, hipStream_t s);
 void launch_fill_uniform(float* p, int64_t n, uint32_t seed, hipStream_t s);
 void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 
+// Fill Slot0<float> (fp64 = false) or Slot0<double> for the n_rows rows of `a`
+// from leaf_val; `out` holds n_rows records.
+void launch_slot0(const PathArrays& a, int32_t n_rows, const double* leaf_val, bool fp64,
+                  void* out, hipStream_t s);
+size_t slot0_bytes(int32_t n_rows, bool fp64);
+
 // Accumulate phi (FP64, [M,F], pre-zeroed) over the paths of one bucket.
-// `a` is plain_arrays() or, with `bk` from HostTable::mbuckets, merged_arrays().
+// `a` is plain_arrays() or, with `bk` from HostTable::mbuckets, merged_arrays();
+// slot0 is launch_slot0's output for the same arrays and precision.
 // nodes = 4 runs the d <= 8 bucket with the 4-node rule (exact there for
 // first order, Theorem 2); every other bucket, and nodes = 8, use 8 nodes.
 void launch_values(const HostTable& h, const DeviceTable& d, const PathArrays& a,
                    const Bucket& bk, bool fp64, const float* X, int64_t M, int64_t ldx,
-                   const double* leaf_val, double* acc, const ValuesShape& shape, int nodes,
+                   const void* slot0, double* acc, const ValuesShape& shape, int nodes,
                    hipStream_t s);
 
 // Adjoint: add J^T G over the rows of one bucket into grad_leaf (pre-zeroed);
