@@ -174,7 +174,7 @@ int qts_shap_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_
  * [64, 32768]; interactions on at most 256 of them) and keeps the fastest for
  * this ensemble and precision:
  *   first-order and adjoint kernels, per length bucket: wavefronts per
- *     workgroup {4, 8} x target work items {4096 .. 65536};
+ *     workgroup {4, 6, 8} x target work items {4096 .. 65536};
  *   interactions, per capacity class: largest path chunk {8192, 32768,
  *     131072} x least work items {1024, 4096}.
  * Synchronises `stream`; drops the ensemble's cached graphs.  Optional:

@@ -180,7 +180,7 @@ void free_device(DeviceTable& d) {
                   d.b64,    d.cb64,    d.leaf_val, d.pr_d,   d.pr_leaf, d.pr_feat,
                   d.pr_lo,  d.pr_hi,   d.pr_b32,  d.pr_cb32, d.pr_b64,  d.pr_cb64,
                   d.mhdr,   d.mfeat,   d.mlo,     d.mhi,     d.mb32,    d.mcb32,
-                  d.mb64,   d.mcb64,   d.side,    d.pr_side};
+                  d.mb64,   d.mcb64,   d.side,    d.pr_side, d.share,   d.mshare};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   d = DeviceTable{};
@@ -523,6 +523,8 @@ int qts_load_ensemble(const qts_tree_arrays* trees, int32_t n_features, double b
       upload_paths(h.mhdr, h.mfeat, h.mlo, h.mhi, h.mb, h.mcb, s, &d.mhdr, &d.mfeat, &d.mlo,
                    &d.mhi, &d.mb32, &d.mcb32, &d.mb64, &d.mcb64);
       d.side = upload(h.side, s);
+      d.share = upload(h.share, s);
+      d.mshare = upload(h.mshare, s);
       d.leaf_val = upload(h.leaf_value, s);
       {
         PairTable pt = build_pair_table(h);
@@ -823,7 +825,7 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
       for (const Bucket& bk : bks) {
         ValuesShape best;
         float best_ms = 1e30f;
-        for (int waves : {4, 8})
+        for (int waves : {4, 6, 8})
           for (int items : {4096, 8192, 16384, 32768, 65536}) {
             const ValuesShape cand{waves, items};
             const float ms = time_ms(3, [&] {

@@ -22,6 +22,7 @@
 // value of 1.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <limits>
 
 #include "../qts_internal.h"
@@ -180,6 +181,35 @@ class Builder {
 
 }  // namespace
 
+// Per row of a table: the number s of leading slots 1..s whose elements
+// (feature, missing_ok, interval, b) are identical to the previous row's,
+// for consecutive rows of at most 8 features (0 otherwise).  Rows are in tree
+// order with leaves left to right, so neighbours share the root side of
+// their paths; slot 0 is each row's own factor and is never shared.
+static std::vector<int32_t> prefix_share(const std::vector<PathHdr>& hdr,
+                                         const std::vector<int32_t>& feat,
+                                         const std::vector<float>& lo,
+                                         const std::vector<float>& hi,
+                                         const std::vector<double>& b) {
+  auto same_bits = [](auto x, auto y) { return std::memcmp(&x, &y, sizeof(x)) == 0; };
+  std::vector<int32_t> share(hdr.size(), 0);
+  for (size_t r = 1; r < hdr.size(); ++r) {
+    const PathHdr& a = hdr[r];
+    const PathHdr& q = hdr[r - 1];
+    if (a.d > 8 || q.d > 8) continue;
+    const int n = std::min(a.d, q.d);
+    int k = 1;
+    for (; k < n; ++k) {
+      const size_t i = (size_t)a.off + (size_t)k, j = (size_t)q.off + (size_t)k;
+      if (feat[i] != feat[j] || !same_bits(lo[i], lo[j]) || !same_bits(hi[i], hi[j]) ||
+          !same_bits(b[i], b[j]))
+        break;
+    }
+    share[r] = k - 1;
+  }
+  return share;
+}
+
 HostTable build_host_table(const qts_tree_arrays& t, int32_t F, double base_score) {
   if (F < 1) fail(QTS_E_INVALID_ARG, "n_features must be >= 1");
   if (t.n_trees < 0) fail(QTS_E_INVALID_ARG, "n_trees must be >= 0");
@@ -274,8 +304,10 @@ HostTable build_host_table(const qts_tree_arrays& t, int32_t F, double base_scor
         continue;
       }
     }
+    // a single path: its deepest feature takes slot 0, so slots 1.. keep the
+    // root-first order that merged neighbours have there
     units.push_back(Unit{i, -1});
-    slot0.push_back(0);
+    slot0.push_back(bld.paths[i].feat.empty() ? 0 : bld.paths[i].feat.size() - 1);
   }
   std::vector<size_t> morder(units.size());
   for (size_t i = 0; i < morder.size(); ++i) morder[i] = i;
@@ -293,7 +325,8 @@ HostTable build_host_table(const qts_tree_arrays& t, int32_t F, double base_scor
     h.mbuckets.back().path_end = pi + 1;
     h.mbuckets.back().elems += d;
     h.mhdr.push_back(PathHdr{(int32_t)h.mfeat.size(), d, p.leaf, units[ui].side});
-    // element order: the merged slot first, the others in path order
+    // element order: the merged (or a single path's deepest) slot first, the
+    // others in path order
     const size_t kL = slot0[ui];
     for (int r = 0; r < d; ++r) {
       const size_t k = r == 0 ? kL : ((size_t)r <= kL ? (size_t)r - 1 : (size_t)r);
@@ -304,6 +337,8 @@ HostTable build_host_table(const qts_tree_arrays& t, int32_t F, double base_scor
       h.mcb.push_back(1.0 - p.b[k]);
     }
   }
+  h.share = prefix_share(h.hdr, h.feat, h.lo, h.hi, h.b);
+  h.mshare = prefix_share(h.mhdr, h.mfeat, h.mlo, h.mhi, h.mb);
   return h;
 }
 

@@ -282,14 +282,139 @@ __device__ __forceinline__ void values_paths(
   }
 }
 
+
+// First order over rows of at most 8 features with all NH nodes in one pass,
+// reusing work between consecutive rows.  Each wave walks a contiguous run of
+// rows.  The products are taken over the slots in the order 1, 2, ..., 7, 0,
+// so the prefix products and the factors F_j(m) of slots 1..s depend only on
+// those slots; when slots 1..s of a row equal the previous row's (share[p] =
+// s, from the host), their c_j and F_j(m) are still in registers and only
+// their suffix products and dot products are formed again.  Slot 0 (the
+// row's own factor, from Slot0) and slots past s are evaluated as usual;
+// inert padding slots (b = 1, c = 0) give a factor of exactly 1.
+template <typename T, int NH, bool NANS>
+__device__ __forceinline__ void values_rows_shared(
+    const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
+    const float* __restrict__ lo, const float* __restrict__ hi, const T* __restrict__ bb,
+    const T* __restrict__ cbb, const Slot0<T>* __restrict__ z0,
+    const int32_t* __restrict__ share, const float* xs, double* as, int pb, int pe, int wave,
+    int nw, int lane, const T* tv, const NodeConsts<T>& nc) {
+  constexpr bool kScalarT = NH == 8;
+  const int run = (pe - pb + nw - 1) / nw;
+  const int p_first = pb + wave * run;
+  const int p_last = min(pe, p_first + run);
+  T cf[8];       // c_j of the current row
+  T G[8][NH];    // F_j(m) of the current row
+  for (int p = p_first; p < p_last; ++p) {
+    const int d = ldu(&hdr[p].d);
+    if (d == 0) continue;
+    const int off = ldu(&hdr[p].off);
+    const int s = p == p_first ? 0 : ldu(share + p);
+    const Slot0<T>* z = z0 + p;
+    const T bm = ldu(&z->bm);
+    const T cA = ldu(&z->ca);
+    const T cB = ldu(&z->cb);
+    const float loB = ldu(&z->lo_b);
+    const float hiB = ldu(&z->hi_b);
+    const bool mokB = ldu(&z->mok_b) != 0;
+    int fm[8];
+    float l[8], u[8], x[8];
+    T bl[8], cbl[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      fm[k] = ldu(feat + off + k);
+      l[k] = ldu(lo + off + k);
+      u[k] = ldu(hi + off + k);
+      bl[k] = ldu(bb + off + k);
+      cbl[k] = ldu(cbb + off + k);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = xs[(fm[k] & kFeatureMask) * kTileStride + lane];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (k == 0 || k > s) {
+        bool lower;
+        if (NANS) {
+          const bool miss = (fm[k] & kMissingOkBit) != 0;
+          lower = miss ? !(x[k] < l[k]) : (x[k] >= l[k]);
+        } else {
+          lower = x[k] >= l[k];
+        }
+        const bool in = lower & !(x[k] >= u[k]);
+        T c, b;
+        if (k == 0) {
+          bool lowerB;
+          if (NANS) lowerB = mokB ? !(x[0] < loB) : (x[0] >= loB);
+          else lowerB = x[0] >= loB;
+          const bool inB = lowerB & !(x[0] >= hiB);
+          c = in ? cA : (inB ? cB : -bm);
+          b = bm;
+        } else {
+          c = in ? cbl[k] : -bl[k];
+          b = bl[k];
+        }
+        cf[k] = c;
+        if (kScalarT) {
+          // t from SGPRs, b copied to a VGPR (one SGPR operand per VALU op)
+          const T bv = to_vgpr(b);
+#pragma unroll
+          for (int m = 0; m < NH; ++m) G[k][m] = fmaT(nc.t[m], c, bv);
+        } else {
+#pragma unroll
+          for (int m = 0; m < NH; ++m) G[k][m] = fmaT(tv[m], c, b);
+        }
+      }
+    }
+    // prefix products in the order 1..7, 0: P[q] = w prod over the first q
+    // slots of that order (slot q + 1 at position q)
+    T P[7][NH];
+#pragma unroll
+    for (int m = 0; m < NH; ++m) P[0][m] = nc.w[m];
+#pragma unroll
+    for (int q = 1; q < 7; ++q)
+#pragma unroll
+      for (int m = 0; m < NH; ++m) P[q][m] = P[q - 1][m] * G[q][m];
+    // slot 0, last in the order: its leave-one-out product is P[6] F_7
+    {
+      T dot = P[6][0] * G[7][0];
+#pragma unroll
+      for (int m = 1; m < NH; ++m) dot = fmaT(P[6][m], G[7][m], dot);
+      __hip_atomic_fetch_add(&as[(fm[0] & kFeatureMask) * kTileStride + lane],
+                             (double)(cf[0] * dot), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    // slots 7..1: suffix products, starting from slot 0's factor
+    T S[NH];
+#pragma unroll
+    for (int m = 0; m < NH; ++m) S[m] = G[0][m];
+#pragma unroll
+    for (int q = 6; q >= 0; --q) {
+      const int j = q + 1;
+      if (j < d) {
+        T dot = P[q][0] * S[0];
+#pragma unroll
+        for (int m = 1; m < NH; ++m) dot = fmaT(P[q][m], S[m], dot);
+        const double c = (double)(cf[j] * dot);
+        __hip_atomic_fetch_add(&as[(fm[j] & kFeatureMask) * kTileStride + lane], c,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      if (q > 0) {
+#pragma unroll
+        for (int m = 0; m < NH; ++m) S[m] *= G[j][m];
+      }
+    }
+  }
+}
+
 template <typename T, int DMAX, int NH, bool STORE_G, int NN>
 __global__ void __launch_bounds__(512)
 values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
               const float* __restrict__ lo, const float* __restrict__ hi,
               const T* __restrict__ bb, const T* __restrict__ cbb,
-              const Slot0<T>* __restrict__ z0, const float* __restrict__ X, int64_t M,
-              int64_t ldx, int32_t F, int32_t path_begin, int32_t path_end, int32_t chunk,
-              int32_t nsb, double* __restrict__ acc, NodeConsts<T> nc) {
+              const Slot0<T>* __restrict__ z0, const int32_t* __restrict__ share,
+              const float* __restrict__ X, int64_t M, int64_t ldx, int32_t F, int32_t path_begin,
+              int32_t path_end, int32_t chunk, int32_t nsb, double* __restrict__ acc,
+              NodeConsts<T> nc) {
   extern __shared__ __align__(16) unsigned char smem[];
   float* xs = reinterpret_cast<float*>(smem);
   size_t xs_bytes = ((size_t)F * kTileStride * sizeof(float) + 15) & ~(size_t)15;
@@ -329,7 +454,16 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
 #pragma unroll
   for (int m = 0; m < NN; ++m) tv[m] = to_vgpr(nc.t[m]);
 
-  if (any_nan)
+  // the shared-prefix walk keeps c_j and F_j(m) of all eight slots live
+  // across rows (FP32: within 128 VGPRs, four waves per SIMD)
+  constexpr bool kShared = DMAX == 8 && STORE_G && NH == NN;
+  if (kShared && any_nan)
+    values_rows_shared<T, NH, true>(hdr, feat, lo, hi, bb, cbb, z0, share, xs, as, pb, pe, wave,
+                                    nw, lane, tv, nc);
+  else if (kShared)
+    values_rows_shared<T, NH, false>(hdr, feat, lo, hi, bb, cbb, z0, share, xs, as, pb, pe, wave,
+                                     nw, lane, tv, nc);
+  else if (any_nan)
     values_paths<T, DMAX, NH, STORE_G, true, false, NN>(hdr, feat, lo, hi, bb, cbb, nullptr,
                                                         z0, xs, as, nullptr, nullptr, pb,
                                                         pe, wave, nw, lane, tv, nc);
@@ -455,7 +589,7 @@ void launch_one(const HostTable& h, const DeviceTable& d, const PathArrays& a, c
     fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
   hipLaunchKernelGGL((values_kernel<T, DMAX, NH, STORE_G, NN>), dim3((unsigned)grid),
                      dim3(threads), lds, s, a.hdr, a.feat, a.lo, a.hi, b, cb,
-                     (const Slot0<T>*)slot0, X,
+                     (const Slot0<T>*)slot0, a.share, X,
                      M, ldx, F, bk.path_begin, bk.path_end, chunk, nsb, acc, nc);
   check_hip(hipGetLastError(), "values_kernel launch");
 }

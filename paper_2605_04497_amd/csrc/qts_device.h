@@ -26,6 +26,7 @@ struct DeviceTable {
   double* b64 = nullptr;
   double* cb64 = nullptr;
   double* leaf_val = nullptr;  // the model's own leaf values
+  int32_t* share = nullptr;    // HostTable::share
   // slot-major pair table (interactions)
   int32_t* pr_d = nullptr;
   int32_t* pr_leaf = nullptr;
@@ -47,6 +48,7 @@ struct DeviceTable {
   double* mb64 = nullptr;
   double* mcb64 = nullptr;
   SidePath* side = nullptr;
+  int32_t* mshare = nullptr;
   NodeConsts<float> n32;     // the 8-node rule
   NodeConsts<double> n64;
   NodeConsts<float> n32_4;   // the 4-node rule (first 4 entries)
@@ -64,13 +66,15 @@ struct PathArrays {
   const double* b64;
   const double* cb64;
   const SidePath* side;  // null: no merged paths (hdr.tree is then ignored)
+  const int32_t* share;  // per row: slots 1..share equal to the previous row's
 };
 
 inline PathArrays plain_arrays(const DeviceTable& d) {
-  return PathArrays{d.hdr, d.feat, d.lo, d.hi, d.b32, d.cb32, d.b64, d.cb64, nullptr};
+  return PathArrays{d.hdr, d.feat, d.lo, d.hi, d.b32, d.cb32, d.b64, d.cb64, nullptr, d.share};
 }
 inline PathArrays merged_arrays(const DeviceTable& d) {
-  return PathArrays{d.mhdr, d.mfeat, d.mlo, d.mhi, d.mb32, d.mcb32, d.mb64, d.mcb64, d.side};
+  return PathArrays{d.mhdr, d.mfeat, d.mlo, d.mhi, d.mb32, d.mcb32, d.mb64, d.mcb64, d.side,
+                    d.mshare};
 }
 
 // Slot 0 of a first-order row with its leaf value folded in, built per call

@@ -71,6 +71,9 @@ struct HostTable {
   std::vector<double> b, cb;  // b_j and 1 - b_j, FP64
   std::vector<double> leaf_value;
   std::vector<Bucket> buckets;
+  // per row of a table with at most 8 features: the number s of slots
+  // 1..s equal to the previous row's (0 for other rows); see prefix_share
+  std::vector<int32_t> share;
   // The first-order table with sibling leaves merged: same layout; a merged
   // path has hdr.tree = its SidePath index (-1 for an unmerged path).
   std::vector<PathHdr> mhdr;
@@ -79,6 +82,7 @@ struct HostTable {
   std::vector<double> mb, mcb;
   std::vector<Bucket> mbuckets;
   std::vector<SidePath> side;
+  std::vector<int32_t> mshare;
 };
 
 HostTable build_host_table(const qts_tree_arrays& t, int32_t n_features, double base_score);

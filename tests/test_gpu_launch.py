@@ -21,7 +21,7 @@ def q():
     return q
 
 
-VALUES_WAVES = {4, 8}
+VALUES_WAVES = {4, 6, 8}
 VALUES_ITEMS = {4096, 8192, 16384, 32768, 65536}
 PAIR_CHUNKS = {8192, 32768, 131072}
 PAIR_FILL = {1024, 4096}
