@@ -122,6 +122,10 @@ typedef struct {
   int64_t n_pair_rows;       /* rows of the interactions table (0: host-only ensemble) */
   int64_t n_pair_elements;   /* sum of d over them */
   int64_t n_pair_updates;    /* sum of d(d-1)/2 over them: pair updates per sample */
+  int64_t n_value_shared;    /* first-order rows with at most 8 features: leading
+                                slots after slot 0 equal to the previous row's,
+                                summed (their factors are reused, not re-evaluated) */
+  int64_t n_path_shared;     /* the same for the unmerged table */
 } qts_info;
 
 int qts_get_info(const qts_ensemble* ens, qts_info* out);

@@ -42,7 +42,8 @@ class Info(ctypes.Structure):
                 ("n_graphs", ctypes.c_int32), ("n_merged", ctypes.c_int64),
                 ("n_value_paths", ctypes.c_int64), ("n_value_elements", ctypes.c_int64),
                 ("n_pair_rows", ctypes.c_int64), ("n_pair_elements", ctypes.c_int64),
-                ("n_pair_updates", ctypes.c_int64)]
+                ("n_pair_updates", ctypes.c_int64), ("n_value_shared", ctypes.c_int64),
+                ("n_path_shared", ctypes.c_int64)]
 
 
 # exported symbol -> (restype, argtypes)

@@ -606,6 +606,10 @@ int qts_get_info(const qts_ensemble* ens, qts_info* out) {
     out->n_pair_rows = ens->pair_rows;
     out->n_pair_elements = ens->pair_elements;
     out->n_pair_updates = ens->pair_updates;
+    out->n_value_shared = 0;
+    for (int32_t v : h.mshare) out->n_value_shared += v;
+    out->n_path_shared = 0;
+    for (int32_t v : h.share) out->n_path_shared += v;
   });
 }
 

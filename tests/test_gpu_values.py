@@ -251,3 +251,34 @@ def test_exact_node_policy(q, oracle_mod, name, over):
         assert err <= (1e-5 if precision == "fp32" else 1e-10), err
     if e.info["max_unique"] <= 8:
         check(got, oracle_mod.shap_values(wl.ensemble, wl.X, n=4), "fp64", "4-node oracle")
+
+
+@pytest.mark.parametrize("M", [1, 63, 300, 2000])
+def test_shared_prefix_walk(q, oracle_mod, M):
+    """Rows of at most 8 features (FP32) reuse the factors of the leading slots
+    they share with the previous row; each wave's run of rows starts afresh.
+    The sample count moves the chunk boundaries (and so where runs start);
+    NaN inputs take the missing-value path; both tables and both node rules;
+    a leaf-value override changes the folded slot-0 factor only."""
+    print("case shared prefix M =", M, flush=True)
+    wl = synth.make_workload("c2_values", T=25, M=M, n_train=20000)
+    ens = wl.ensemble
+    X = wl.X.copy()
+    rng = np.random.default_rng(M)
+    X[rng.random(X.shape) < 0.05] = np.nan
+    lv = rng.normal(size=ens.n_leaves())
+    want = oracle_mod.shap_values(ens, X, n=8)
+    want_lv = oracle_mod.shap_values(ens.with_leaf_values(lv), X, n=8)
+    e = q.Ensemble(ens)
+    assert e.info["n_value_shared"] > 0
+    Xd = torch.from_numpy(X).cuda()
+    lvd = torch.from_numpy(lv).cuda()
+    for merge in (True, False):
+        e.set_sibling_merge(merge)
+        for policy in ("fixed8", "exact"):
+            e.set_node_policy(policy)
+            tag = "merge=%s %s" % (merge, policy)
+            got = e.shap_values(Xd, "fp32").double().cpu().numpy()
+            check(got, want, "fp32", "shared prefix " + tag)
+            got = e.shap_values(Xd, "fp32", leaf_values=lvd).double().cpu().numpy()
+            check(got, want_lv, "fp32", "shared prefix, leaf override " + tag)

@@ -225,3 +225,117 @@ def test_sibling_merge_counts(q, name, over):
     assert info["n_value_elements"] <= info["n_elements"]
     assert info["n_elements"] - info["n_value_elements"] >= want   # each pair drops >= 1 element
     assert d.min() >= 1
+
+
+def _first_order_rows(ens, merged):
+    """Rows of the first-order table rebuilt from the trees (independently of
+    the library): per leaf with at least one split, its unique features in
+    order of first appearance with (feature, missing_ok, lo, hi, b); two leaf
+    children of one node with the same feature count form one merged row with
+    the parent's split feature in slot 0; a single path puts its deepest
+    feature in slot 0 (merged table) or keeps path order (unmerged table).
+    Rows are in tree and left-to-right leaf order, stably grouped by length
+    capacity 8, 16, 32, 64."""
+    left, right = np.asarray(ens.left), np.asarray(ens.right)
+    feat, thr = np.asarray(ens.feature), np.asarray(ens.threshold, dtype=np.float32)
+    dleft, cover = np.asarray(ens.default_left), np.asarray(ens.cover, dtype=np.float64)
+    offs = np.asarray(ens.tree_offsets)
+    paths = []   # (elements dict in first-appearance order, parent node, is_left, tree)
+    for t in range(ens.n_trees):
+        a = int(offs[t])
+
+        def walk(node, edges):
+            g = a + node
+            if left[g] < 0:
+                el = {}
+                for (f, is_left, th, dl, w, _) in edges:
+                    lo, hi, mok, b = el.get(f, (-np.inf, None, True, 1.0))
+                    b = b * w
+                    if is_left:
+                        hi = th if hi is None else min(hi, th)
+                        mok = mok and bool(dl)
+                    else:
+                        lo = max(lo, th)
+                        mok = mok and not bool(dl)
+                    el[f] = (lo, hi, mok, b)
+                if el:
+                    parent = edges[-1][5] if edges else -1
+                    paths.append(([(f,) + v for f, v in el.items()], parent, edges[-1][1], t))
+                return
+            cp = cover[g]
+            for child, is_left in ((int(left[g]), True), (int(right[g]), False)):
+                w = 0.0 if cp == 0.0 else cover[a + child] / cp
+                walk(child, edges + [(int(feat[g]), is_left, thr[g], dleft[g], w, node)])
+
+        walk(0, [])
+    rows = []
+    i = 0
+    while i < len(paths):
+        A = paths[i]
+        if merged and i + 1 < len(paths):
+            B = paths[i + 1]
+            if (A[1] >= 0 and A[1] == B[1] and A[3] == B[3] and A[2] and not B[2]
+                    and len(A[0]) == len(B[0])):
+                L = int(feat[int(offs[A[3]]) + A[1]])
+                kL = [e[0] for e in A[0]].index(L)
+                rows.append([A[0][kL]] + A[0][:kL] + A[0][kL + 1:])
+                i += 2
+                continue
+        rows.append(A[0][-1:] + A[0][:-1] if merged else A[0])
+        i += 1
+    cap = lambda d: min(c for c in (8, 16, 32, 64) if d <= c)
+    return sorted(rows, key=lambda r: cap(len(r)))
+
+
+def _shared_slots(rows):
+    total = 0
+    for prev, row in zip(rows, rows[1:]):
+        if len(prev) > 8 or len(row) > 8:
+            continue
+        k = 1
+        while k < min(len(prev), len(row)) and prev[k] == row[k]:
+            k += 1
+        total += k - 1
+    return total
+
+
+@pytest.mark.parametrize("name,over", [
+    ("c1_small", dict(M=4)),
+    ("c2_values", dict(T=12, M=4, n_train=20000)),
+    ("c3_interactions", dict(T=6, M=4, n_train=20000)),
+    ("c5_deep", dict(T=2, M=4, n_train=30000)),
+])
+def test_shared_prefix_counts(q, name, over):
+    """The first-order kernel for rows of at most 8 features reuses the factors
+    of the leading slots (after slot 0) that equal the previous row's; the
+    library's per-table totals must equal those of the rows rebuilt here."""
+    wl = synth.make_workload(name, **over)
+    e = q.Ensemble(wl.ensemble, host_only=True)
+    want_m = _shared_slots(_first_order_rows(wl.ensemble, merged=True))
+    want_p = _shared_slots(_first_order_rows(wl.ensemble, merged=False))
+    assert e.info["n_value_shared"] == want_m
+    assert e.info["n_path_shared"] == want_p
+    if name == "c2_values":
+        assert want_m > 0 and want_p > 0
+
+
+def test_shared_prefix_stops_at_first_difference(q):
+    """Hand-made tree: the root splits on f0; its left child on f1, whose left
+    child splits on f2 and whose right child splits on f0 again."""
+    tree = ("split", 0, 0.0, 100.0,
+            ("split", 1, 1.0, 60.0,
+             ("split", 2, 2.0, 30.0, ("leaf", 1.0, 10.0), ("leaf", 2.0, 20.0)),
+             ("split", 0, -1.0, 30.0, ("leaf", 3.0, 15.0), ("leaf", 4.0, 15.0))),
+            ("leaf", 5.0, 40.0))
+    ens = synth.from_nested([tree], n_features=3)
+    e = q.Ensemble(ens, host_only=True)
+    rows = _first_order_rows(ens, merged=True)
+    assert len(rows) == 3 and e.info["n_merged"] == 2
+    # merged rows: [f2 | f0, f1], [f0 narrowed to x < -1 | f1 right], [f0
+    # right]: slot 1 holds f0 then f1, nothing is shared
+    assert e.info["n_value_shared"] == _shared_slots(rows) == 0
+    # unmerged rows: [f0, f1 left, f2 left], [f0, f1 left, f2 right] share
+    # slot 1; [f0 narrowed, f1 right] differs from it in slot 1; [f0 in
+    # [-1, 0), f1 right] shares slot 1 with it; the root's right leaf has
+    # no slot after 0
+    assert e.info["n_path_shared"] == _shared_slots(_first_order_rows(ens, merged=False)) == 2
