@@ -455,8 +455,9 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
   for (int m = 0; m < NN; ++m) tv[m] = to_vgpr(nc.t[m]);
 
   // the shared-prefix walk keeps c_j and F_j(m) of all eight slots live
-  // across rows (FP32: within 128 VGPRs, four waves per SIMD)
-  constexpr bool kShared = DMAX == 8 && STORE_G && NH == NN;
+  // across rows: FP32 within 128 VGPRs (four waves per SIMD); FP64 only with
+  // the 4-node rule (the 8-node FP64 instance has no registers to spare)
+  constexpr bool kShared = DMAX == 8 && NH == NN && (STORE_G || NN == 4);
   if (kShared && any_nan)
     values_rows_shared<T, NH, true>(hdr, feat, lo, hi, bb, cbb, z0, share, xs, as, pb, pe, wave,
                                     nw, lane, tv, nc);
