@@ -36,10 +36,6 @@ PEAK_HBM_GBS = 8000.0
 # LDS FP64 atomic add, measured on MI355X: 2.45 lanes per clock per CU, random
 # addresses in an 80 KB table (the interactions kernel's accumulator)
 LDS_F64_ATOMIC_RATE = 2.45 * 256 * 2.4e9
-# VALU lane operations of the method per (sample, element) unit: 4 per node
-# (factor FMA, prefix product, suffix product, FMA into the node sum) + 3
-LANE_OPS_PER_ELEMENT = 35
-PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
 # HBM bytes per launch of the first-order kernel on this workload in its timed
 # launch shape, from two rocprofv3 --pmc runs (FETCH_SIZE x 2 and WRITE_SIZE x 1,
@@ -47,8 +43,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # profiles/values_kernel_c2_values.md.  Valid only for the kernel source they
 # were measured on (its SHA-256 prefix); otherwise traffic is reported as null.
 TRAFFIC = {"kernel_source": "paper_2605_04497_amd/csrc/kernels/values.hip",
-           "sha256_16": "5c3afb528382b148", "fetch_bytes": 1.3261e+09, "write_bytes": 1.6800e+09,
-           "shape": [8, 32768]}
+           "sha256_16": "f0acd046a81b5e7a", "fetch_bytes": 2.6378e+09, "write_bytes": 4.8000e+08,
+           "shape": [8, 8192]}
 
 
 def measured_traffic(shape):
@@ -63,6 +59,18 @@ def measured_traffic(shape):
         return None
     return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
 FLOPS_PER_ELEMENT = 51  # per (sample, path, unique feature): 8 nodes x 6 + 3
+
+
+def shared_kernel_flops(rows, elements, shared):
+    """FP32 flops (FMA = 2) per sample of the first-order kernel for rows of at
+    most 8 features at 8 nodes: a row of d features whose first s slots after
+    slot 0 are reused from the previous row costs
+      16 (8 - s)   factor FMAs of the slots it evaluates (padding included)
+      48           prefix products over slots 1..6
+      16 d         a 15-flop node sum and a scale per feature
+      48           suffix products over slots 7..2
+    = 112 + 16 d + 16 (8 - s); summed over the table: 224 R + 16 E - 16 S."""
+    return 224.0 * rows + 16.0 * elements - 16.0 * shared
 
 
 def pair_flops(d):
@@ -439,8 +447,9 @@ def main():
         e.set_sibling_merge(True)
         plain = {"value": units / (rp["ms_per_step"] * 1e-3), "ms_per_step": rp["ms_per_step"],
                  "kernel_ms": rp["kernel_ms"], "dtype": "f32",
-                 "alu_tflops": FLOPS_PER_ELEMENT * float(M) * n_el / (rp["kernel_ms"] * 1e-3)
-                 / 1e12}
+                 "alu_tflops": float(M) * shared_kernel_flops(
+                     float(e.info["n_paths"]), n_el, float(e.info["n_path_shared"]))
+                 / (rp["kernel_ms"] * 1e-3) / 1e12}
         log("fp32 without sibling merging: %.3f ms/step" % rp["ms_per_step"])
     exact = None
     if not args.no_extras:
@@ -456,7 +465,14 @@ def main():
                  "note": "4-node rule for paths of at most 8 unique features (all of this "
                          "workload): exact for first order, same values up to rounding"}
         log("fp32 with the exact node policy: %.3f ms/step" % rx["ms_per_step"])
-    achieved = flops / (r32["kernel_ms"] * 1e-3) / 1e12
+    # the arithmetic the kernel runs (every row of this workload has at most 8
+    # features: one bucket, the shared-prefix walk); flops above is the
+    # per-element count of the method without merging or reuse
+    n_shared = float(e.info["n_value_shared"] if not args.no_merge else e.info["n_path_shared"])
+    n_rows = float(e.info["n_value_paths"] if not args.no_merge else e.info["n_paths"])
+    assert e.info["max_unique"] <= 8
+    kernel_flops = float(M) * shared_kernel_flops(n_rows, n_vel, n_shared)
+    achieved = kernel_flops / (r32["kernel_ms"] * 1e-3) / 1e12
     result = {
         "metric": METRIC,
         "value": units / (r32["ms_per_step"] * 1e-3),
@@ -497,14 +513,19 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
                      "traffic": measured_traffic(e.launch_shape("values", "fp32", 0)),
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
-                     "lane_ops_per_launch": LANE_OPS_PER_ELEMENT * float(M) * n_vel,
-                     "lane_op_frac": LANE_OPS_PER_ELEMENT * float(M) * n_vel
-                     / (r32["kernel_ms"] * 1e-3) / PEAK_LANE_OPS,
+                     "flops_per_launch": kernel_flops,
+                     "flops_model": "per (sample, row) of d features with s reused slots: "
+                                    "224 + 16 d - 16 s (8 nodes, FMA = 2 flops)",
+                     "rows": n_rows, "elements_per_sample": n_vel,
+                     "shared_slots_per_sample": n_shared,
+                     "method_flops_per_launch": flops,
+                     "method_flops_model": "51 per (sample, element): the per-path method "
+                                          "without reuse",
+                     "method_frac": flops / (r32["kernel_ms"] * 1e-3) / 1e12 / PEAK_VALU_TFLOPS,
                      "kernel": "values_kernel<float, 8, 8, true, 8>", "kernel_ms": r32["kernel_ms"],
                      "kernel_ms_scope": "event pair around each graph replay (zero-fill, "
                                         "values kernel, cast)" if not args.eager else
                                         "event pair around the values kernel launches",
-                     "flops_per_launch": flops,
                      "peak_fp32_packed": PEAK_FP32_PACKED_TFLOPS,
                      "frac_of_packed_peak": achieved / PEAK_FP32_PACKED_TFLOPS},
     }
