@@ -177,7 +177,8 @@ int qts_shap_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_
  * launch shapes on M_hint synthetic rows (uniform in [-3, 3), M_hint capped to
  * [64, 32768]; interactions on at most 256 of them) and keeps the fastest for
  * this ensemble and precision:
- *   first-order and adjoint kernels, per length bucket: wavefronts per
+ *   first-order kernel, and separately the adjoint kernel (upstream
+ *     gradient uniform in [-3, 3)), per length bucket: wavefronts per
  *     workgroup {4, 6, 8} x target work items {4096 .. 65536};
  *   interactions, per capacity class: largest path chunk {8192, 32768,
  *     131072} x least work items {1024, 4096}.
@@ -186,10 +187,11 @@ int qts_shap_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_
  * compute calls on the same ensemble. */
 int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, void* stream);
 
-/* The launch shape in use: kind 0 = first-order/adjoint bucket `index`
- * (0..3 for lengths <= 8, 16, 32, 64) -> (*a, *b) = (wavefronts per
- * workgroup, target work items); kind 1 = interactions capacity class `index`
- * (0 .. n_pair_classes-1) -> (largest path chunk, least work items). */
+/* The launch shape in use: kind 0 = first-order bucket `index`, kind 2 =
+ * adjoint bucket `index` (0..3 for lengths <= 8, 16, 32, 64) -> (*a, *b) =
+ * (wavefronts per workgroup, target work items); kind 1 = interactions
+ * capacity class `index` (0 .. n_pair_classes-1) -> (largest path chunk,
+ * least work items). */
 int qts_get_launch_shape(const qts_ensemble* ens, int32_t kind, qts_precision precision,
                          int32_t index, int32_t* a, int32_t* b);
 

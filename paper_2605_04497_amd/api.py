@@ -172,10 +172,11 @@ class Ensemble:
 
     def launch_shape(self, kind: str, precision: str = "fp32", index: int = 0):
         """(waves per workgroup, target work items) of first-order bucket `index`
-        (kind 'values'), or (largest path chunk, least work items) of
-        interactions class `index` (kind 'interactions')."""
+        (kind 'values') or adjoint bucket `index` (kind 'adjoint'), or (largest
+        path chunk, least work items) of interactions class `index` (kind
+        'interactions')."""
         a, b = ctypes.c_int32(), ctypes.c_int32()
-        L.check(L.lib().qts_get_launch_shape(self._h, {"values": 0, "interactions": 1}[kind],
+        L.check(L.lib().qts_get_launch_shape(self._h, {"values": 0, "interactions": 1, "adjoint": 2}[kind],
                                              _PREC[precision], int(index), ctypes.byref(a),
                                              ctypes.byref(b)))
         return a.value, b.value

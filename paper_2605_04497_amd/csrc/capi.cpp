@@ -64,6 +64,7 @@ struct qts_ensemble {
   // launch shapes per bucket capacity index (8, 16, 32, 64) and precision,
   // and per pair capacity class and precision (defaults until autotuned)
   qts::ValuesShape vshape[2][4];
+  qts::ValuesShape ashape[2][4];  // the adjoint kernel's, tuned separately
   std::vector<qts::PairShape> pshape[2];
   bool merge_siblings = true;  // first-order calls walk the merged table
   int node_policy = QTS_NODES_FIXED8;
@@ -383,7 +384,7 @@ void issue_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_t 
   for (size_t i = 0; i < bks.size(); ++i) {
     const Bucket& bk = bks[i];
     launch_adjoint(h, ens->dev, arr, bk, fp64, X, grad_phi, M, ldx, grad_leaf,
-                   ens->vshape[fp64 ? 1 : 0][cap_index(bk.dmax)], nodes_of(ens), ln.pick((int)i));
+                   ens->ashape[fp64 ? 1 : 0][cap_index(bk.dmax)], nodes_of(ens), ln.pick((int)i));
   }
   ln.join();
   ts.done();
@@ -844,6 +845,35 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
         ens->vshape[pi][cap_index(bk.dmax)] = best;
       }
     }
+    // adjoint kernel, per bucket, with a synthetic upstream gradient
+    {
+      Scratch gl(sizeof(double) * (size_t)std::max<size_t>(1, h.leaf_value.size()), s);
+      Scratch g32(sizeof(float) * (size_t)(Mt * F), s);
+      launch_fill_uniform((float*)g32.p, Mt * F, 0x4a11u, s);
+      Scratch g64(fp64 ? sizeof(double) * (size_t)(Mt * F) : 8, s);
+      if (fp64) launch_widen_f32_f64((const float*)g32.p, (double*)g64.p, Mt * F, s);
+      const void* G = fp64 ? g64.p : g32.p;
+      launch_fill_zero((double*)gl.p, (int64_t)h.leaf_value.size(), s);
+      const std::vector<Bucket>& bks = ens->merge_siblings ? h.mbuckets : h.buckets;
+      const PathArrays arr = ens->merge_siblings ? merged_arrays(d) : plain_arrays(d);
+      for (const Bucket& bk : bks) {
+        ValuesShape best;
+        float best_ms = 1e30f;
+        for (int waves : {4, 6, 8})
+          for (int items : {4096, 8192, 16384, 32768, 65536}) {
+            const ValuesShape cand{waves, items};
+            const float ms = time_ms(3, [&] {
+              launch_adjoint(h, d, arr, bk, fp64, X, G, Mt, F, (double*)gl.p, cand,
+                             nodes_of(ens), s);
+            });
+            if (ms < best_ms) {
+              best_ms = ms;
+              best = cand;
+            }
+          }
+        ens->ashape[pi][cap_index(bk.dmax)] = best;
+      }
+    }
     // interactions, per capacity class, on at most 256 of the rows (and an
     // accumulator of at most 512 MiB)
     if (!ens->pair_classes.empty() && F >= 2) {
@@ -888,9 +918,9 @@ int qts_get_launch_shape(const qts_ensemble* ens, int32_t kind, qts_precision pr
     if (precision != QTS_FP32 && precision != QTS_FP64)
       fail(QTS_E_INVALID_ARG, "unknown precision");
     const bool fp64 = precision == QTS_FP64;
-    if (kind == 0) {
+    if (kind == 0 || kind == 2) {
       if (index < 0 || index > 3) fail(QTS_E_INVALID_ARG, "bucket index out of range");
-      const ValuesShape& v = ens->vshape[fp64 ? 1 : 0][index];
+      const ValuesShape& v = (kind == 0 ? ens->vshape : ens->ashape)[fp64 ? 1 : 0][index];
       *a = v.waves_per_block;
       *b = v.items;
     } else if (kind == 1) {

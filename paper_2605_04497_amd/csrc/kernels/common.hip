@@ -29,6 +29,13 @@ __global__ void __launch_bounds__(256) fill_uniform_kernel(float* __restrict__ p
   }
 }
 
+__global__ void __launch_bounds__(256) widen_kernel(const float* __restrict__ src,
+                                                    double* __restrict__ dst, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    dst[i] = (double)src[i];
+}
+
 static unsigned grid_for(int64_t n) {
   int64_t g = (n + 255) / 256;
   if (g > 8192) g = 8192;
@@ -46,6 +53,12 @@ void launch_fill_uniform(float* p, int64_t n, uint32_t seed, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(fill_uniform_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n, seed);
   check_hip(hipGetLastError(), "fill_uniform launch");
+}
+
+void launch_widen_f32_f64(const float* src, double* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(widen_kernel, dim3(grid_for(n)), dim3(256), 0, s, src, dst, n);
+  check_hip(hipGetLastError(), "widen launch");
 }
 
 void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s) {

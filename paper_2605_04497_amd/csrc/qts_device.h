@@ -181,6 +181,7 @@ void launch_fill_zero(double* p, int64_t n, hipStream_t s);
 // Seeded uniform values in [-3, 3) (inputs for timing launch shapes).
 void launch_fill_uniform(float* p, int64_t n, uint32_t seed, hipStream_t s);
 void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+void launch_widen_f32_f64(const float* src, double* dst, int64_t n, hipStream_t s);
 
 // Fill Slot0<float> (fp64 = false) or Slot0<double> for the n_rows rows of `a`
 // from leaf_val; `out` holds n_rows records.

@@ -32,6 +32,7 @@ def test_default_shapes(q):
     e = q.Ensemble(wl.ensemble)
     assert e.launch_shape("values", "fp32", 0) == (8, 16384)
     assert e.launch_shape("interactions", "fp32", 0) == (65536, 2048)
+    assert e.launch_shape("adjoint", "fp32", 0) == (8, 16384)
     with pytest.raises(q.QtsError):
         e.launch_shape("values", "fp32", 4)
 
@@ -51,8 +52,9 @@ def test_autotune_keeps_parity(q, oracle_mod, name, over):
     for precision in ("fp32", "fp64"):
         e.autotune(wl.X.shape[0], precision)
         for i in range(4):
-            w, items = e.launch_shape("values", precision, i)
-            assert w in VALUES_WAVES and items in VALUES_ITEMS, (w, items)
+            for kind in ("values", "adjoint"):
+                w, items = e.launch_shape(kind, precision, i)
+                assert w in VALUES_WAVES and items in VALUES_ITEMS, (kind, w, items)
         for i in range(e.info["n_pair_classes"]):
             mc, fill = e.launch_shape("interactions", precision, i)
             assert mc in PAIR_CHUNKS and fill in PAIR_FILL, (mc, fill)
