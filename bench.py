@@ -259,7 +259,10 @@ def measure_adjoint(args, torch, q, synth, oracle, dev):
            "ms_per_step": res["fp32"]["ms_per_step"], "kernel_ms": res["fp32"]["kernel_ms"],
            "fp64_ms_per_step": res["fp64"]["ms_per_step"],
            "max_rel_err_fp32": err, "rows_checked": int(len(rows)),
-           "alu_tflops": ach, "frac_of_valu_peak": ach / PEAK_VALU_TFLOPS}
+           "method_tflops": ach, "method_frac_of_valu_peak": ach / PEAK_VALU_TFLOPS,
+           "method_note": "51 flops per (sample, element) of the unmerged table: the "
+                          "per-path method's count; the kernel merges siblings and reuses "
+                          "shared slots, so it runs fewer"}
     e.close()
     return out
 

@@ -486,6 +486,142 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
   }
 }
 
+
+// Adjoint over rows of at most 8 features with all NH nodes in one pass,
+// with the reuse of values_rows_shared (contiguous runs, slots 1..s of the
+// previous row kept in registers: c_j, F_j(m) and g_j c_j).  Slot 0 (a merged
+// pair's split feature, or any one feature of a single path) stays out of the
+// products; with Q_j(m) = prod_{k >= 1, k != j} F_k(m), Q_0 = prod_{k >= 1} F_k,
+//   R(m) = sum_{j >= 1} g_j c_j w_m Q_j(m),
+//   d phi . g / d v_A = sum_m F_A(m) R(m) + g_0 c_A sum_m w_m Q_0(m),
+// where F_A = b_A + t c_A is slot 0's factor of leaf A (a single path: its
+// own), and likewise for leaf B of a merged pair.  The sum over m of
+// F_A(m) R(m) is b_A sum_m R(m) + c_A sum_m t_m R(m).
+template <typename T, int NH, bool NANS>
+__device__ __forceinline__ void adjoint_rows_shared(
+    const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
+    const float* __restrict__ lo, const float* __restrict__ hi, const T* __restrict__ bb,
+    const T* __restrict__ cbb, const SidePath* __restrict__ side,
+    const int32_t* __restrict__ share, const float* xs, const T* gs,
+    double* __restrict__ grad_leaf, int pb, int pe, int wave, int nw, int lane, const T* tv,
+    const NodeConsts<T>& nc) {
+  constexpr bool kScalarT = NH == 8;
+  const int run = (pe - pb + nw - 1) / nw;
+  const int p_first = pb + wave * run;
+  const int p_last = min(pe, p_first + run);
+  T cf[8], gc[8];  // slots 1..7: c_j and g_j c_j of the current row
+  T G[8][NH];      // slots 1..7: F_j(m)
+  for (int p = p_first; p < p_last; ++p) {
+    const int d = ldu(&hdr[p].d);
+    if (d == 0) continue;
+    const int off = ldu(&hdr[p].off);
+    const int leaf = ldu(&hdr[p].leaf);
+    const int sidx = side == nullptr ? -1 : ldu(&hdr[p].tree);
+    const bool merged = sidx >= 0;
+    const int s = p == p_first ? 0 : ldu(share + p);
+    int fm[8];
+    float l[8], u[8], x[8];
+    T bl[8], cbl[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      fm[k] = ldu(feat + off + k);
+      l[k] = ldu(lo + off + k);
+      u[k] = ldu(hi + off + k);
+      bl[k] = ldu(bb + off + k);
+      cbl[k] = ldu(cbb + off + k);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = xs[(fm[k] & kFeatureMask) * kTileStride + lane];
+    auto follows = [&](float xv, float lv, float uv, bool miss) -> bool {
+      bool lower;
+      if (NANS) lower = miss ? !(xv < lv) : (xv >= lv);
+      else lower = xv >= lv;
+      return lower & !(xv >= uv);
+    };
+    // slot 0: leaf A's factor (and B's for a merged pair)
+    T bA = bl[0], cbA = cbl[0], bB = T(0), cbB = T(0);
+    float loB = 0.f, hiB = 0.f;
+    bool mokB = false;
+    int leafB = 0;
+    if (merged) {
+      const SidePath* sp = side + sidx;
+      leafB = ldu(&sp->leaf_b);
+      loB = ldu(&sp->lo_b);
+      hiB = ldu(&sp->hi_b);
+      mokB = ldu(&sp->mok_b) != 0;
+      bA = (T)ldu(&sp->b_a);
+      cbA = (T)ldu(&sp->cb_a);
+      bB = (T)ldu(&sp->b_b);
+      cbB = (T)ldu(&sp->cb_b);
+    }
+    const T cA = follows(x[0], l[0], u[0], (fm[0] & kMissingOkBit) != 0) ? cbA : -bA;
+    const T cB = follows(x[0], loB, hiB, mokB) ? cbB : -bB;
+    const T g0 = gs[(fm[0] & kFeatureMask) * kTileStride + lane];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+      if (k > s) {
+        const T c = follows(x[k], l[k], u[k], (fm[k] & kMissingOkBit) != 0) ? cbl[k] : -bl[k];
+        cf[k] = c;
+        gc[k] = gs[(fm[k] & kFeatureMask) * kTileStride + lane] * c;
+        if (kScalarT) {
+          const T bv = to_vgpr(bl[k]);
+#pragma unroll
+          for (int m = 0; m < NH; ++m) G[k][m] = fmaT(nc.t[m], c, bv);
+        } else {
+#pragma unroll
+          for (int m = 0; m < NH; ++m) G[k][m] = fmaT(tv[m], c, bl[k]);
+        }
+      }
+    }
+    // prefix products over slots 1..q (P[q], q = 0..6; w folded in)
+    T P[7][NH];
+#pragma unroll
+    for (int m = 0; m < NH; ++m) P[0][m] = nc.w[m];
+#pragma unroll
+    for (int q = 1; q < 7; ++q)
+#pragma unroll
+      for (int m = 0; m < NH; ++m) P[q][m] = P[q - 1][m] * G[q][m];
+    // sum_m w_m Q_0(m)
+    T q0 = P[6][0] * G[7][0];
+#pragma unroll
+    for (int m = 1; m < NH; ++m) q0 = fmaT(P[6][m], G[7][m], q0);
+    // R(m), slots 7..1
+    T S[NH], R[NH];
+#pragma unroll
+    for (int m = 0; m < NH; ++m) {
+      S[m] = T(1);
+      R[m] = T(0);
+    }
+#pragma unroll
+    for (int q = 6; q >= 0; --q) {
+      const int j = q + 1;
+      if (j < d) {
+#pragma unroll
+        for (int m = 0; m < NH; ++m) R[m] = fmaT(gc[j], P[q][m] * S[m], R[m]);
+      }
+      if (q > 0) {
+#pragma unroll
+        for (int m = 0; m < NH; ++m) S[m] *= G[j][m];
+      }
+    }
+    T sR = R[0], stR = (kScalarT ? nc.t[0] : tv[0]) * R[0];
+#pragma unroll
+    for (int m = 1; m < NH; ++m) {
+      sR += R[m];
+      stR = fmaT(kScalarT ? nc.t[m] : tv[m], R[m], stR);
+    }
+    const T gq = g0 * q0;
+    double gA = (double)fmaT(bA, sR, cA * (stR + gq));
+    gA = wave_sum_last(gA);
+    if (lane == 63 && gA != 0.0) unsafeAtomicAdd(&grad_leaf[leaf], gA);
+    if (merged) {
+      double gB = (double)fmaT(bB, sR, cB * (stR + gq));
+      gB = wave_sum_last(gB);
+      if (lane == 63 && gB != 0.0) unsafeAtomicAdd(&grad_leaf[leafB], gB);
+    }
+  }
+}
+
 // Adjoint to the leaf values (same tiling as values_kernel): the tile holds
 // the samples' rows and their upstream gradient rows g[s, :].
 template <typename T, int DMAX, int NH, bool STORE_G, int NN>
@@ -493,8 +629,9 @@ __global__ void __launch_bounds__(512)
 adjoint_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
                const float* __restrict__ lo, const float* __restrict__ hi,
                const T* __restrict__ bb, const T* __restrict__ cbb,
-               const SidePath* __restrict__ side, const float* __restrict__ X,
-               const T* __restrict__ G, int64_t M, int64_t ldx, int32_t F, int32_t path_begin,
+               const SidePath* __restrict__ side, const int32_t* __restrict__ share,
+               const float* __restrict__ X, const T* __restrict__ G, int64_t M, int64_t ldx,
+               int32_t F, int32_t path_begin,
                int32_t path_end, int32_t chunk, int32_t nsb, double* __restrict__ grad_leaf,
                NodeConsts<T> nc) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -532,7 +669,14 @@ adjoint_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat
   T tv[NN];
 #pragma unroll
   for (int m = 0; m < NN; ++m) tv[m] = to_vgpr(nc.t[m]);
-  if (any_nan)
+  constexpr bool kShared = DMAX == 8 && NH == NN && (STORE_G || NN == 4);
+  if (kShared && any_nan)
+    adjoint_rows_shared<T, NH, true>(hdr, feat, lo, hi, bb, cbb, side, share, xs, gs, grad_leaf,
+                                     pb, pe, wave, nw, lane, tv, nc);
+  else if (kShared)
+    adjoint_rows_shared<T, NH, false>(hdr, feat, lo, hi, bb, cbb, side, share, xs, gs, grad_leaf,
+                                      pb, pe, wave, nw, lane, tv, nc);
+  else if (any_nan)
     values_paths<T, DMAX, NH, STORE_G, true, true, NN>(hdr, feat, lo, hi, bb, cbb, side, nullptr,
                                                        xs, nullptr, gs, grad_leaf, pb, pe,
                                                        wave, nw, lane, tv, nc);
@@ -618,7 +762,8 @@ void launch_adj_one(const HostTable& h, const DeviceTable& d, const PathArrays& 
   if (lds > values_lds_limit((const void*)adjoint_kernel<T, DMAX, NH, STORE_G, NN>, &cache))
     fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
   hipLaunchKernelGGL((adjoint_kernel<T, DMAX, NH, STORE_G, NN>), dim3((unsigned)grid),
-                     dim3(threads), lds, s, a.hdr, a.feat, a.lo, a.hi, b, cb, a.side, X, (const T*)G, M,
+                     dim3(threads), lds, s, a.hdr, a.feat, a.lo, a.hi, b, cb, a.side, a.share, X,
+                     (const T*)G, M,
                      ldx, F, bk.path_begin, bk.path_end, chunk, nsb, grad_leaf, nc);
   check_hip(hipGetLastError(), "adjoint_kernel launch");
 }

@@ -160,3 +160,35 @@ def test_adjoint_merged_rows_match_plain(q, oracle_mod, name, over):
         e.set_sibling_merge(merge)
         g = e.shap_backward(X, torch.from_numpy(G).cuda(), "fp64").cpu().numpy()
         assert normwise(g, want) <= 1e-10, (merge, normwise(g, want))
+
+
+@pytest.mark.parametrize("M", [1, 77, 700])
+def test_adjoint_shared_prefix_walk(q, oracle_mod, M):
+    """Rows of at most 8 features reuse the factors (and g_j c_j) of the slots
+    they share with the previous row; runs start afresh at chunk boundaries,
+    which move with M.  NaN inputs, both tables, both node rules, FP32 and
+    FP64 (FP64 with 8 nodes takes the unshared path), against the oracle's
+    transposed map."""
+    print("case adjoint shared prefix M =", M, flush=True)
+    wl = synth.make_workload("c2_values", T=25, M=M, n_train=20000)
+    ens = wl.ensemble
+    X = wl.X.copy()
+    rng = np.random.default_rng(100 + M)
+    X[rng.random(X.shape) < 0.05] = np.nan
+    G = rng.normal(size=(M, ens.n_features))
+    e = q.Ensemble(ens)
+    assert e.info["n_value_shared"] > 0
+    Xd = torch.from_numpy(X).cuda()
+    for precision in ("fp32", "fp64"):
+        Gp = G.astype(np.float32).astype(np.float64) if precision == "fp32" else G
+        want = oracle_mod.leaf_grad(ens, X, Gp)
+        Gd = torch.from_numpy(Gp).cuda()
+        if precision == "fp32":
+            Gd = Gd.float()
+        for merge in (True, False):
+            e.set_sibling_merge(merge)
+            for policy in ("fixed8", "exact"):
+                e.set_node_policy(policy)
+                got = e.shap_backward(Xd, Gd, precision).cpu().numpy()
+                err = normwise(got, want)
+                assert err <= TOL[precision], (precision, merge, policy, err)
