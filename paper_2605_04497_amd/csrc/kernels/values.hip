@@ -1,12 +1,14 @@
 // First-order Shapley values: phi[s, f] accumulated over every root-to-leaf
-// path of the ensemble (Theorem 1 with |S| = 1, Eq. 9-10, 8 nodes).
+// path of the ensemble (Theorem 1 with |S| = 1, Eq. 9-10, 8 nodes), and the
+// adjoint of phi with respect to the leaf values.
 //
 // Work mapping (gfx950, wave64):
 //   * a workgroup owns a tile of 64 explained samples (one per lane) and a
-//     contiguous chunk of paths from one bucket; its wavefronts split the
-//     chunk path by path;
-//   * a wavefront processes one path at a time for all 64 samples, so every
-//     path quantity (features, bounds, b_j, 1-b_j, leaf value) is uniform
+//     contiguous chunk of rows from one bucket; its wavefronts split the
+//     chunk (rows of at most 8 features: one contiguous run per wavefront;
+//     longer rows: row by row in turn);
+//   * a wavefront processes one row at a time for all 64 samples, so every
+//     row quantity (features, bounds, b_j, 1-b_j, slot-0 factor) is uniform
 //     across the wave and is fetched with scalar loads;
 //   * the sample tile is staged transposed in LDS ([F][65] floats), so the
 //     per-lane gather x[s, f_j] is a conflict-free LDS read;
@@ -14,7 +16,7 @@
 //     shared by the workgroup's waves) and flushed to the FP64 global
 //     accumulator with one atomic per (sample, feature) at the end.
 //
-// Per (sample, path) with unique features j = 0..d-1 and nodes m:
+// Per (sample, row) with unique features j = 0..d-1 and nodes m:
 //   o_j    = x in [lo_j, hi_j) ? 1 : 0   (NaN: missing_ok_j)            (Eq. 2)
 //   c_j    = o_j - b_j, taken as the stored FP64-derived 1 - b_j or as -b_j
 //   F_j(m) = b_j (1 - t_m) + o_j t_m = b_j + t_m c_j      (one FMA per node)
@@ -23,11 +25,13 @@
 // The leaf value is folded into slot 0 (Slot0: F_0 scaled by val, built per
 // call in FP64), so a row needs no multiply by val; a merged sibling pair is
 // the same form with a combined slot-0 factor.
-// Slots past the end of a path get c = 0 and b = 1, a factor of exactly 1, so
-// whole batches of eight features run without branches.  The prefix products
-// are kept only at batch checkpoints and rebuilt batch by batch in the
-// backward sweep, which bounds the registers for long paths; NH < 8 splits the
-// nodes over several passes (the node sum is additive).
+// Rows of at most 8 features reuse the factors of the slots they share with
+// the previous row (values_rows_shared, adjoint_rows_shared).  Longer rows
+// (values_paths) run in batches of eight slots: slots past the end of a row
+// get c = 0 and b = 1, a factor of exactly 1, so whole batches run without
+// branches; the prefix products are kept only at batch checkpoints and
+// rebuilt batch by batch in the backward sweep, which bounds the registers;
+// NH < NN splits the nodes over several passes (the node sum is additive).
 #include <hip/hip_runtime.h>
 
 #include "../qts_device.h"
