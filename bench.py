@@ -457,8 +457,10 @@ def main():
     exact = None
     if not args.no_extras:
         # the optional node policy: 4 nodes for paths of at most 8 features
-        # (exact there, Theorem 2), same launch shapes
+        # (exact there, Theorem 2), with launch shapes tuned for it
         e.set_node_policy("exact")
+        if not args.no_autotune:
+            e.autotune(M, "fp32")
         rx = time_steps(lambda: e.shap_values(X, "fp32", out=out32), max(2, args.steps // 2),
                         1, torch)
         e.set_node_policy("fixed8")

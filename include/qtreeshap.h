@@ -182,12 +182,15 @@ int qts_shap_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_
  *     workgroup {4, 6, 8} x target work items {4096 .. 65536};
  *   interactions, per capacity class: largest path chunk {8192, 32768,
  *     131072} x least work items {1024, 4096}.
+ * First-order and adjoint shapes are kept per node policy and tuned for the
+ * policy in effect (qts_set_node_policy).
  * Synchronises `stream`; drops the ensemble's cached graphs.  Optional:
  * untuned ensembles use fixed defaults.  Not thread-safe against concurrent
  * compute calls on the same ensemble. */
 int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, void* stream);
 
-/* The launch shape in use: kind 0 = first-order bucket `index`, kind 2 =
+/* The launch shape in use (first order and adjoint: for the node policy in
+ * effect): kind 0 = first-order bucket `index`, kind 2 =
  * adjoint bucket `index` (0..3 for lengths <= 8, 16, 32, 64) -> (*a, *b) =
  * (wavefronts per workgroup, target work items); kind 1 = interactions
  * capacity class `index` (0 .. n_pair_classes-1) -> (largest path chunk,

@@ -63,8 +63,9 @@ struct qts_ensemble {
   bool on_device = false;
   // launch shapes per bucket capacity index (8, 16, 32, 64) and precision,
   // and per pair capacity class and precision (defaults until autotuned)
-  qts::ValuesShape vshape[2][4];
-  qts::ValuesShape ashape[2][4];  // the adjoint kernel's, tuned separately
+  // [node policy][precision][length bucket]; the adjoint's tuned separately
+  qts::ValuesShape vshape[2][2][4];
+  qts::ValuesShape ashape[2][2][4];
   std::vector<qts::PairShape> pshape[2];
   bool merge_siblings = true;  // first-order calls walk the merged table
   int node_policy = QTS_NODES_FIXED8;
@@ -310,6 +311,7 @@ struct Lanes {
 };
 
 int nodes_of(const qts_ensemble* ens) { return ens->node_policy == QTS_NODES_EXACT ? 4 : 8; }
+int pol_index(const qts_ensemble* ens) { return ens->node_policy == QTS_NODES_EXACT ? 1 : 0; }
 
 const PairShape& pair_shape(const qts_ensemble* ens, bool fp64, size_t i) {
   static const PairShape kDefault{};
@@ -346,7 +348,8 @@ void issue_values(const qts_ensemble* ens, const float* X, int64_t M, int64_t ld
   for (size_t i = 0; i < bks.size(); ++i) {
     const Bucket& bk = bks[i];
     launch_values(h, ens->dev, arr, bk, fp64, X, M, ldx, slot0, a,
-                  ens->vshape[fp64 ? 1 : 0][cap_index(bk.dmax)], nodes_of(ens), ln.pick((int)i));
+                  ens->vshape[pol_index(ens)][fp64 ? 1 : 0][cap_index(bk.dmax)], nodes_of(ens),
+                  ln.pick((int)i));
   }
   ln.join();
   ts.done();
@@ -384,7 +387,8 @@ void issue_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_t 
   for (size_t i = 0; i < bks.size(); ++i) {
     const Bucket& bk = bks[i];
     launch_adjoint(h, ens->dev, arr, bk, fp64, X, grad_phi, M, ldx, grad_leaf,
-                   ens->ashape[fp64 ? 1 : 0][cap_index(bk.dmax)], nodes_of(ens), ln.pick((int)i));
+                   ens->ashape[pol_index(ens)][fp64 ? 1 : 0][cap_index(bk.dmax)], nodes_of(ens),
+                   ln.pick((int)i));
   }
   ln.join();
   ts.done();
@@ -842,7 +846,7 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
               best = cand;
             }
           }
-        ens->vshape[pi][cap_index(bk.dmax)] = best;
+        ens->vshape[pol_index(ens)][pi][cap_index(bk.dmax)] = best;
       }
     }
     // adjoint kernel, per bucket, with a synthetic upstream gradient
@@ -871,7 +875,7 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
               best = cand;
             }
           }
-        ens->ashape[pi][cap_index(bk.dmax)] = best;
+        ens->ashape[pol_index(ens)][pi][cap_index(bk.dmax)] = best;
       }
     }
     // interactions, per capacity class, on at most 256 of the rows (and an
@@ -920,7 +924,8 @@ int qts_get_launch_shape(const qts_ensemble* ens, int32_t kind, qts_precision pr
     const bool fp64 = precision == QTS_FP64;
     if (kind == 0 || kind == 2) {
       if (index < 0 || index > 3) fail(QTS_E_INVALID_ARG, "bucket index out of range");
-      const ValuesShape& v = (kind == 0 ? ens->vshape : ens->ashape)[fp64 ? 1 : 0][index];
+      const ValuesShape& v =
+          (kind == 0 ? ens->vshape : ens->ashape)[pol_index(ens)][fp64 ? 1 : 0][index];
       *a = v.waves_per_block;
       *b = v.items;
     } else if (kind == 1) {

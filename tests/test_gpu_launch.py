@@ -153,3 +153,21 @@ def test_graph_cache_eviction(q, oracle_mod):
         torch.cuda.synchronize()
         assert row_normwise(out.cpu().numpy(), want[:m]) <= 1e-10
     assert e.refresh_info()["n_graphs"] == 16
+
+
+def test_shapes_kept_per_node_policy(q):
+    """First-order and adjoint launch shapes are tuned and kept per node
+    policy: tuning under one policy leaves the other's shapes alone."""
+    wl = synth.make_workload("c2_values", T=10, M=500, n_train=20000)
+    e = q.Ensemble(wl.ensemble)
+    kinds = ("values", "adjoint")
+    e.autotune(500, "fp32")
+    tuned8 = [e.launch_shape(k, "fp32", 0) for k in kinds]
+    e.set_node_policy("exact")
+    assert [e.launch_shape(k, "fp32", 0) for k in kinds] == [(8, 16384)] * 2  # untuned
+    e.autotune(500, "fp32")
+    for k in kinds:
+        w, items = e.launch_shape(k, "fp32", 0)
+        assert w in VALUES_WAVES and items in VALUES_ITEMS
+    e.set_node_policy("fixed8")
+    assert [e.launch_shape(k, "fp32", 0) for k in kinds] == tuned8
