@@ -328,8 +328,18 @@ int32_t value_rows(const qts_ensemble* ens) {
 size_t slot0_region(const qts_ensemble* ens, bool fp64) {
   return (slot0_bytes(value_rows(ens), fp64) + 255) & ~(size_t)255;
 }
+// A call whose rows form one bucket walked as one chunk writes phi from its
+// workgroups directly (no FP64 accumulator, zero fill or cast).
+bool direct_call(const qts_ensemble* ens, int64_t M, bool fp64) {
+  const HostTable& h = ens->host;
+  const std::vector<Bucket>& bks = ens->merge_siblings ? h.mbuckets : h.buckets;
+  if (bks.size() != 1) return false;
+  return values_direct(bks, M,
+                       ens->vshape[pol_index(ens)][fp64 ? 1 : 0][cap_index(bks[0].dmax)]);
+}
 size_t values_scratch_bytes(const qts_ensemble* ens, int64_t M, bool fp64) {
-  return slot0_region(ens, fp64) + (fp64 ? 0 : sizeof(double) * (size_t)(M * ens->host.F));
+  const bool acc = !fp64 && !direct_call(ens, M, fp64);
+  return slot0_region(ens, fp64) + (acc ? sizeof(double) * (size_t)(M * ens->host.F) : 0);
 }
 
 void issue_values(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
@@ -338,16 +348,24 @@ void issue_values(const qts_ensemble* ens, const float* X, int64_t M, int64_t ld
   const HostTable& h = ens->host;
   const int64_t n = M * h.F;
   void* slot0 = scratch;
-  double* a = fp64 ? (double*)phi : (double*)((char*)scratch + slot0_region(ens, fp64));
   const PathArrays arr = ens->merge_siblings ? merged_arrays(ens->dev) : plain_arrays(ens->dev);
-  launch_fill_zero(a, n, ln.main);
-  launch_slot0(arr, value_rows(ens), leaf, fp64, slot0, ln.main);
-  TimedScope ts(0, timed ? ln.main : nullptr, timed);
   const std::vector<Bucket>& bks = ens->merge_siblings ? h.mbuckets : h.buckets;
+  launch_slot0(arr, value_rows(ens), leaf, fp64, slot0, ln.main);
+  if (direct_call(ens, M, fp64)) {
+    TimedScope ts(0, timed ? ln.main : nullptr, timed);
+    launch_values(h, ens->dev, arr, bks[0], fp64, X, M, ldx, slot0, nullptr, phi,
+                  ens->vshape[pol_index(ens)][fp64 ? 1 : 0][cap_index(bks[0].dmax)],
+                  nodes_of(ens), ln.main);
+    ts.done();
+    return;
+  }
+  double* a = fp64 ? (double*)phi : (double*)((char*)scratch + slot0_region(ens, fp64));
+  launch_fill_zero(a, n, ln.main);
+  TimedScope ts(0, timed ? ln.main : nullptr, timed);
   ln.fork((int)bks.size());
   for (size_t i = 0; i < bks.size(); ++i) {
     const Bucket& bk = bks[i];
-    launch_values(h, ens->dev, arr, bk, fp64, X, M, ldx, slot0, a,
+    launch_values(h, ens->dev, arr, bk, fp64, X, M, ldx, slot0, a, nullptr,
                   ens->vshape[pol_index(ens)][fp64 ? 1 : 0][cap_index(bk.dmax)], nodes_of(ens),
                   ln.pick((int)i));
   }
@@ -838,7 +856,7 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
           for (int items : {4096, 8192, 16384, 32768, 65536}) {
             const ValuesShape cand{waves, items};
             const float ms = time_ms(3, [&] {
-              launch_values(h, d, arr, bk, fp64, X, Mt, F, slot0.p, (double*)acc.p, cand,
+              launch_values(h, d, arr, bk, fp64, X, Mt, F, slot0.p, (double*)acc.p, nullptr, cand,
                             nodes_of(ens), s);
             });
             if (ms < best_ms) {

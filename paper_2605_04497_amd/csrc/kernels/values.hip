@@ -418,7 +418,7 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
               const Slot0<T>* __restrict__ z0, const int32_t* __restrict__ share,
               const float* __restrict__ X, int64_t M, int64_t ldx, int32_t F, int32_t path_begin,
               int32_t path_end, int32_t chunk, int32_t nsb, double* __restrict__ acc,
-              NodeConsts<T> nc) {
+              void* __restrict__ direct, int32_t direct_fp64, NodeConsts<T> nc) {
   extern __shared__ __align__(16) unsigned char smem[];
   float* xs = reinterpret_cast<float*>(smem);
   size_t xs_bytes = ((size_t)F * kTileStride * sizeof(float) + 15) & ~(size_t)15;
@@ -478,14 +478,21 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
                                                          pe, wave, nw, lane, tv, nc);
   __syncthreads();
 
-  // flush: consecutive threads take consecutive features of one sample
+  // flush: consecutive threads take consecutive features of one sample.
+  // direct: this workgroup is the only one of its sample block (one bucket,
+  // one chunk), so it writes phi rows outright, in the output precision.
   for (int i = threadIdx.x; i < tile; i += blockDim.x) {
     const int r = i / F;
     const int f = i - r * F;
     const int64_t s = s0 + r;
     if (s < M) {
       const double v = as[f * kTileStride + r];
-      if (v != 0.0) unsafeAtomicAdd(&acc[s * F + f], v);
+      if (direct != nullptr) {
+        if (direct_fp64) static_cast<double*>(direct)[s * F + f] = v;
+        else static_cast<float*>(direct)[s * F + f] = (float)v;
+      } else if (v != 0.0) {
+        unsafeAtomicAdd(&acc[s * F + f], v);
+      }
     }
   }
 }
@@ -702,6 +709,17 @@ int values_chunk(int n_paths, int nsb, int items) {
   return (int)((n_paths + n_chunks - 1) / n_chunks);
 }
 
+}  // namespace
+
+bool values_direct(const std::vector<Bucket>& bks, int64_t M, const ValuesShape& shape) {
+  if (bks.size() != 1 || M <= 0) return false;
+  const int nsb = (int)((M + kSamplesPerBlock - 1) / kSamplesPerBlock);
+  const int n_paths = bks[0].path_end - bks[0].path_begin;
+  return values_chunk(n_paths, nsb, shape.items) >= n_paths;
+}
+
+namespace {
+
 // Raise a kernel's dynamic-LDS limit once; returns the usable bytes.
 size_t values_lds_limit(const void* fn, size_t* cache) {
   if (*cache == 0) {
@@ -718,7 +736,7 @@ size_t values_lds_limit(const void* fn, size_t* cache) {
 template <typename T, int DMAX, int NH, bool STORE_G, int NN>
 void launch_one(const HostTable& h, const DeviceTable& d, const PathArrays& a, const Bucket& bk,
                 const float* X, int64_t M, int64_t ldx, const void* slot0, double* acc,
-                const ValuesShape& shape, hipStream_t s) {
+                void* direct, const ValuesShape& shape, hipStream_t s) {
   const int F = h.F;
   const int nsb = (int)((M + kSamplesPerBlock - 1) / kSamplesPerBlock);
   const int n_paths = bk.path_end - bk.path_begin;
@@ -739,7 +757,8 @@ void launch_one(const HostTable& h, const DeviceTable& d, const PathArrays& a, c
   hipLaunchKernelGGL((values_kernel<T, DMAX, NH, STORE_G, NN>), dim3((unsigned)grid),
                      dim3(threads), lds, s, a.hdr, a.feat, a.lo, a.hi, b, cb,
                      (const Slot0<T>*)slot0, a.share, X,
-                     M, ldx, F, bk.path_begin, bk.path_end, chunk, nsb, acc, nc);
+                     M, ldx, F, bk.path_begin, bk.path_end, chunk, nsb, acc, direct,
+                     (int32_t)(std::is_same<T, double>::value ? 1 : 0), nc);
   check_hip(hipGetLastError(), "values_kernel launch");
 }
 
@@ -855,28 +874,28 @@ void launch_slot0(const PathArrays& a, int32_t n_rows, const double* leaf_val, b
 
 void launch_values(const HostTable& h, const DeviceTable& d, const PathArrays& a,
                    const Bucket& bk, bool fp64, const float* X, int64_t M, int64_t ldx,
-                   const void* slot0, double* acc, const ValuesShape& shape, int nodes,
-                   hipStream_t s) {
+                   const void* slot0, double* acc, void* direct, const ValuesShape& shape,
+                   int nodes, hipStream_t s) {
   if (values_lds_bytes(h.F) > (size_t)kMaxLdsBytes)
     fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
   if (nodes == 4 && bk.dmax == 8) {
-    if (!fp64) launch_one<float, 8, 4, true, 4>(h, d, a, bk, X, M, ldx, slot0, acc, shape, s);
-    else launch_one<double, 8, 4, false, 4>(h, d, a, bk, X, M, ldx, slot0, acc, shape, s);
+    if (!fp64) launch_one<float, 8, 4, true, 4>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s);
+    else launch_one<double, 8, 4, false, 4>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s);
     return;
   }
   if (!fp64) {
     switch (bk.dmax) {
-      case 8: launch_one<float, 8, 8, true, 8>(h, d, a, bk, X, M, ldx, slot0, acc, shape, s); break;
-      case 16: launch_one<float, 16, 8, true, 8>(h, d, a, bk, X, M, ldx, slot0, acc, shape, s); break;
-      case 32: launch_one<float, 32, 8, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, shape, s); break;
-      default: launch_one<float, 64, 4, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, shape, s); break;
+      case 8: launch_one<float, 8, 8, true, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s); break;
+      case 16: launch_one<float, 16, 8, true, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s); break;
+      case 32: launch_one<float, 32, 8, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s); break;
+      default: launch_one<float, 64, 4, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s); break;
     }
   } else {
     switch (bk.dmax) {
-      case 8: launch_one<double, 8, 8, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, shape, s); break;
-      case 16: launch_one<double, 16, 4, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, shape, s); break;
-      case 32: launch_one<double, 32, 4, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, shape, s); break;
-      default: launch_one<double, 64, 2, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, shape, s); break;
+      case 8: launch_one<double, 8, 8, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s); break;
+      case 16: launch_one<double, 16, 4, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s); break;
+      case 32: launch_one<double, 32, 4, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s); break;
+      default: launch_one<double, 64, 2, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s); break;
     }
   }
 }

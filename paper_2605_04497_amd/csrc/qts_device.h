@@ -191,13 +191,20 @@ size_t slot0_bytes(int32_t n_rows, bool fp64);
 
 // Accumulate phi (FP64, [M,F], pre-zeroed) over the paths of one bucket.
 // `a` is plain_arrays() or, with `bk` from HostTable::mbuckets, merged_arrays();
-// slot0 is launch_slot0's output for the same arrays and precision.
+// slot0 is launch_slot0's output for the same arrays and precision.  With
+// `direct` non-null (see values_direct) phi is written there instead.
 // nodes = 4 runs the d <= 8 bucket with the 4-node rule (exact there for
 // first order, Theorem 2); every other bucket, and nodes = 8, use 8 nodes.
 void launch_values(const HostTable& h, const DeviceTable& d, const PathArrays& a,
                    const Bucket& bk, bool fp64, const float* X, int64_t M, int64_t ldx,
-                   const void* slot0, double* acc, const ValuesShape& shape, int nodes,
-                   hipStream_t s);
+                   const void* slot0, double* acc, void* direct, const ValuesShape& shape,
+                   int nodes, hipStream_t s);
+// True when a first-order call over `bks` (the table in use) with M samples
+// and this launch shape is one bucket walked as one chunk: each sample block
+// has a single workgroup, which may then write phi itself (launch_values with
+// `direct` = phi, float or double by precision; acc unused, no zero fill and
+// no cast).
+bool values_direct(const std::vector<Bucket>& bks, int64_t M, const ValuesShape& shape);
 
 // Adjoint: add J^T G over the rows of one bucket into grad_leaf (pre-zeroed);
 // a merged row adds to both of its leaves.

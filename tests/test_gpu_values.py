@@ -282,3 +282,22 @@ def test_shared_prefix_walk(q, oracle_mod, M):
             check(got, want, "fp32", "shared prefix " + tag)
             got = e.shap_values(Xd, "fp32", leaf_values=lvd).double().cpu().numpy()
             check(got, want_lv, "fp32", "shared prefix, leaf override " + tag)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_output_fully_overwritten(q, oracle_mod, precision):
+    """Calls that write phi directly from the workgroups (one bucket walked
+    as one chunk: a small table) and calls that accumulate and cast must both
+    overwrite every entry of an `out=` buffer that holds garbage."""
+    for name, over in (("c1_small", dict(M=333)), ("c5_deep", dict(T=2, M=70, n_train=30000))):
+        print("case", name, precision, flush=True)
+        wl = synth.make_workload(name, **over)
+        e = q.Ensemble(wl.ensemble)
+        X = torch.from_numpy(wl.X).cuda()
+        dt = torch.float32 if precision == "fp32" else torch.float64
+        out = torch.full((X.shape[0], e.n_features), float("nan"), dtype=dt, device="cuda")
+        e.shap_values(X, precision, out=out)
+        torch.cuda.synchronize()
+        got = out.double().cpu().numpy()
+        assert np.isfinite(got).all(), name
+        check(got, oracle_mod.shap_values(wl.ensemble, wl.X, n=8), precision, name + " out=")
