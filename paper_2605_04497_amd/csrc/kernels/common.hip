@@ -2,9 +2,31 @@
 // the call sequence stays safe to capture in a HIP graph) and FP64 -> FP32.
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "../qts_device.h"
 
 namespace qts {
+
+size_t raise_lds_limit(const void* fn) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, size_t> done;
+  int dev = 0;
+  check_hip(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lock(mu);
+  const auto key = std::make_pair(fn, dev);
+  const auto it = done.find(key);
+  if (it != done.end()) return it->second;
+  hipFuncAttributes fa;
+  check_hip(hipFuncGetAttributes(&fa, fn), "hipFuncGetAttributes");
+  const size_t limit = (size_t)kMaxLdsBytes - fa.sharedSizeBytes;
+  check_hip(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)limit),
+            "hipFuncSetAttribute");
+  done.emplace(key, limit);
+  return limit;
+}
 
 __global__ void __launch_bounds__(256) fill_zero_kernel(double* __restrict__ p, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;

@@ -597,18 +597,6 @@ int pair_chunk(int np, int64_t M, const PairShape& shape, int64_t* n_chunks_out)
   return (int)((np + n_chunks - 1) / n_chunks);
 }
 
-// Raise a kernel's dynamic-LDS limit once; returns the usable bytes.
-size_t lds_limit_of(const void* fn, size_t* cache) {
-  if (*cache == 0) {
-    hipFuncAttributes fa;
-    check_hip(hipFuncGetAttributes(&fa, fn), "hipFuncGetAttributes");
-    const size_t limit = (size_t)kMaxLdsBytes - fa.sharedSizeBytes;
-    check_hip(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)limit),
-              "hipFuncSetAttribute");
-    *cache = limit;
-  }
-  return *cache;
-}
 
 template <typename T>
 const T* table_b(const DeviceTable& d) {
@@ -632,9 +620,8 @@ void launch_pairs_fast(const HostTable& h, const DeviceTable& d, const PairClass
   const int chunk = pair_chunk(pc.np, M, shape, &n_chunks);
   const int64_t grid = M * n_chunks;
   if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "interactions grid too large");
-  static size_t cache = 0;
   const void* fn = (const void*)pairs_kernel<T, C, NH, MERGE>;
-  const size_t limit = lds_limit_of(fn, &cache);
+  const size_t limit = raise_lds_limit(fn);
   const size_t fixed = pairs_fixed_lds(F, sizeof(T), false);
   if (fixed >= limit) fail(QTS_E_UNSUPPORTED, "n_features too large for the interactions kernel");
   bool first = true;
@@ -660,9 +647,8 @@ void launch_pairs_generic(const HostTable& h, const DeviceTable& d, const PairCl
   const int chunk = pair_chunk(pc.np, M, shape, &n_chunks);
   const int64_t grid = M * n_chunks;
   if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "interactions grid too large");
-  static size_t cache = 0;
   const void* fn = (const void*)pairs_generic_kernel<T>;
-  const size_t limit = lds_limit_of(fn, &cache);
+  const size_t limit = raise_lds_limit(fn);
   const size_t fixed = pairs_fixed_lds(F, sizeof(T), true);
   if (fixed >= limit) fail(QTS_E_UNSUPPORTED, "n_features too large for the interactions kernel");
   bool first = true;

@@ -720,18 +720,6 @@ bool values_direct(const std::vector<Bucket>& bks, int64_t M, const ValuesShape&
 
 namespace {
 
-// Raise a kernel's dynamic-LDS limit once; returns the usable bytes.
-size_t values_lds_limit(const void* fn, size_t* cache) {
-  if (*cache == 0) {
-    hipFuncAttributes fa;
-    check_hip(hipFuncGetAttributes(&fa, fn), "hipFuncGetAttributes");
-    const size_t limit = (size_t)kMaxLdsBytes - fa.sharedSizeBytes;
-    check_hip(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)limit),
-              "hipFuncSetAttribute");
-    *cache = limit;
-  }
-  return *cache;
-}
 
 template <typename T, int DMAX, int NH, bool STORE_G, int NN>
 void launch_one(const HostTable& h, const DeviceTable& d, const PathArrays& a, const Bucket& bk,
@@ -751,8 +739,7 @@ void launch_one(const HostTable& h, const DeviceTable& d, const PathArrays& a, c
   NodeConsts<T> nc;
   if constexpr (std::is_same<T, float>::value) nc = NN == 8 ? d.n32 : d.n32_4;
   else nc = NN == 8 ? d.n64 : d.n64_4;
-  static size_t cache = 0;
-  if (lds > values_lds_limit((const void*)values_kernel<T, DMAX, NH, STORE_G, NN>, &cache))
+  if (lds > raise_lds_limit((const void*)values_kernel<T, DMAX, NH, STORE_G, NN>))
     fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
   hipLaunchKernelGGL((values_kernel<T, DMAX, NH, STORE_G, NN>), dim3((unsigned)grid),
                      dim3(threads), lds, s, a.hdr, a.feat, a.lo, a.hi, b, cb,
@@ -781,8 +768,7 @@ void launch_adj_one(const HostTable& h, const DeviceTable& d, const PathArrays& 
   NodeConsts<T> nc;
   if constexpr (std::is_same<T, float>::value) nc = NN == 8 ? d.n32 : d.n32_4;
   else nc = NN == 8 ? d.n64 : d.n64_4;
-  static size_t cache = 0;
-  if (lds > values_lds_limit((const void*)adjoint_kernel<T, DMAX, NH, STORE_G, NN>, &cache))
+  if (lds > raise_lds_limit((const void*)adjoint_kernel<T, DMAX, NH, STORE_G, NN>))
     fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
   hipLaunchKernelGGL((adjoint_kernel<T, DMAX, NH, STORE_G, NN>), dim3((unsigned)grid),
                      dim3(threads), lds, s, a.hdr, a.feat, a.lo, a.hi, b, cb, a.side, a.share, X,

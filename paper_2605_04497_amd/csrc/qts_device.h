@@ -177,6 +177,10 @@ __device__ __forceinline__ double wave_sum_last(double v) {
   return v;
 }
 
+// Raise a kernel's dynamic-LDS limit on the current device (once per kernel
+// and device; thread-safe); returns the usable dynamic LDS bytes.
+size_t raise_lds_limit(const void* fn);
+
 void launch_fill_zero(double* p, int64_t n, hipStream_t s);
 // Seeded uniform values in [-3, 3) (inputs for timing launch shapes).
 void launch_fill_uniform(float* p, int64_t n, uint32_t seed, hipStream_t s);
