@@ -213,15 +213,18 @@ int qts_get_launch_shape(const qts_ensemble* ens, int32_t kind, qts_precision pr
  * setting drops the ensemble's cached graphs. */
 int qts_set_sibling_merge(qts_ensemble* ens, int32_t enable);
 
-/* Node count of the first-order and adjoint calls.
+/* Node count of every call.
  *   QTS_NODES_FIXED8 (default): the 8-node Gauss-Legendre rule for every path
  *     (section 5).
- *   QTS_NODES_EXACT: the paths of at most 8 unique features use the 4-node
- *     rule.  Their leave-one-out products have degree <= 7 in p and an
- *     n-node rule integrates degree 2n - 1 exactly (Theorem 2), so this gives
- *     the same values as 8 nodes up to rounding with half the node work; longer
- *     paths keep 8 nodes.  The interactions call always uses 8 nodes.
- * Changing the policy drops the ensemble's cached graphs. */
+ *   QTS_NODES_EXACT: the fewest nodes that are exact where that is fewer than
+ *     8.  An n-node rule integrates degree 2n - 1 exactly (Theorem 2); the
+ *     order-s integrand of a path of d unique features has degree d - s.
+ *     First order and adjoint: paths of at most 8 features use 4 nodes.
+ *     Interactions: capacity classes 4, 8 and 12 use 2, 4 and 6 nodes (their
+ *     first-order sums too).  Longer paths keep 8 nodes.  Results equal the
+ *     8-node ones up to rounding.
+ * Launch shapes are kept per policy.  Changing the policy drops the
+ * ensemble's cached graphs. */
 enum { QTS_NODES_FIXED8 = 0, QTS_NODES_EXACT = 1 };
 int qts_set_node_policy(qts_ensemble* ens, int32_t policy);
 

@@ -193,9 +193,10 @@ class Ensemble:
         L.check(L.lib().qts_set_sibling_merge(self._h, int(bool(enable))))
 
     def set_node_policy(self, policy: str = "fixed8"):
-        """'fixed8': the 8-node rule everywhere (default); 'exact': paths of at
-        most 8 features use 4 nodes (exact there, Theorem 2) in the
-        first-order and adjoint calls."""
+        """'fixed8': the 8-node rule everywhere (default); 'exact': the fewest
+        nodes exact by Theorem 2 where that is fewer than 8 (first order and
+        adjoint: 4 for paths of at most 8 features; interactions: 2, 4, 6 for
+        capacity classes 4, 8, 12)."""
         L.check(L.lib().qts_set_node_policy(self._h, {"fixed8": 0, "exact": 1}[policy]))
 
     def refresh_info(self) -> dict:

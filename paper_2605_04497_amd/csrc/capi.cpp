@@ -66,7 +66,7 @@ struct qts_ensemble {
   // [node policy][precision][length bucket]; the adjoint's tuned separately
   qts::ValuesShape vshape[2][2][4];
   qts::ValuesShape ashape[2][2][4];
-  std::vector<qts::PairShape> pshape[2];
+  std::vector<qts::PairShape> pshape[2][2];  // [node policy][precision]
   bool merge_siblings = true;  // first-order calls walk the merged table
   int node_policy = QTS_NODES_FIXED8;
   int64_t pair_rows = 0, pair_elements = 0, pair_updates = 0;  // interactions table
@@ -197,13 +197,19 @@ void build_nodes(DeviceTable& d) {
     d.n64.t[m] = t[m];
     d.n64.w[m] = w[m];
   }
-  gauss_legendre(4, t, s, w);
-  for (int m = 0; m < kNodes; ++m) {
-    d.n32_4.t[m] = m < 4 ? (float)t[m] : 0.f;
-    d.n32_4.w[m] = m < 4 ? (float)w[m] : 0.f;
-    d.n64_4.t[m] = m < 4 ? t[m] : 0.0;
-    d.n64_4.w[m] = m < 4 ? w[m] : 0.0;
-  }
+  // fewer-node rules, padded with zero nodes and weights
+  auto rule = [&](int n, NodeConsts<float>& f32, NodeConsts<double>& f64) {
+    gauss_legendre(n, t, s, w);
+    for (int m = 0; m < kNodes; ++m) {
+      f32.t[m] = m < n ? (float)t[m] : 0.f;
+      f32.w[m] = m < n ? (float)w[m] : 0.f;
+      f64.t[m] = m < n ? t[m] : 0.0;
+      f64.w[m] = m < n ? w[m] : 0.0;
+    }
+  };
+  rule(4, d.n32_4, d.n64_4);
+  rule(2, d.n32_2, d.n64_2);
+  rule(6, d.n32_6, d.n64_6);
 }
 
 void require_device(const qts_ensemble* ens) {
@@ -315,7 +321,7 @@ int pol_index(const qts_ensemble* ens) { return ens->node_policy == QTS_NODES_EX
 
 const PairShape& pair_shape(const qts_ensemble* ens, bool fp64, size_t i) {
   static const PairShape kDefault{};
-  const auto& v = ens->pshape[fp64 ? 1 : 0];
+  const auto& v = ens->pshape[ens->node_policy == QTS_NODES_EXACT ? 1 : 0][fp64 ? 1 : 0];
   return i < v.size() ? v[i] : kDefault;
 }
 
@@ -387,7 +393,8 @@ void issue_interactions(const qts_ensemble* ens, const float* X, int64_t M, int6
   ln.fork((int)ens->pair_classes.size());
   for (size_t i = 0; i < ens->pair_classes.size(); ++i)
     launch_pairs(h, ens->dev, ens->pair_classes[i], fp64, X, M, ldx, leaf, tri64, phi64,
-                 pair_shape(ens, fp64, i), ln.pick((int)i));
+                 pair_shape(ens, fp64, i), ens->node_policy == QTS_NODES_EXACT,
+                 ln.pick((int)i));
   ln.join();
   ts.done();
   launch_pairs_finalize(tri64, phi64, M, (int)F, fp64, Phi, phi, ln.main);
@@ -906,7 +913,7 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
       double* tri64 = (double*)acc.p;
       double* phi64 = tri64 + Mp * (F * (F - 1) / 2);
       launch_fill_zero(tri64, Mp * per_row, s);
-      std::vector<PairShape>& out = ens->pshape[pi];
+      std::vector<PairShape>& out = ens->pshape[pol_index(ens)][pi];
       out.assign(ens->pair_classes.size(), PairShape{});
       for (size_t i = 0; i < ens->pair_classes.size(); ++i) {
         const PairClass& pc = ens->pair_classes[i];
@@ -916,7 +923,8 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
           for (int fill : {1024, 4096}) {
             const PairShape cand{max_chunk, fill};
             const float ms = time_ms(1, [&] {
-              launch_pairs(h, d, pc, fp64, X, Mp, F, d.leaf_val, tri64, phi64, cand, s);
+              launch_pairs(h, d, pc, fp64, X, Mp, F, d.leaf_val, tri64, phi64, cand,
+                           ens->node_policy == QTS_NODES_EXACT, s);
             });
             if (ms < best_ms) {
               best_ms = ms;

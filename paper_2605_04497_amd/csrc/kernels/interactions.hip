@@ -93,9 +93,10 @@ __device__ __forceinline__ void pairs_epilogue(const double* phis, const double*
 
 // Lane-per-path form for short paths (capacity C, register resident).  Each
 // lane takes one path of the class (the table is slot-major, so a wave's 64
-// paths load coalesced).  NH < 8 splits the nodes over passes to bound the
-// registers held by r (the node sum is additive).
-template <typename T, int C, int NH, bool MERGE>
+// paths load coalesced).  NN nodes (the rule's size, 8 or fewer where fewer
+// are exact); NH < NN splits them over passes to bound the registers held by
+// r (the node sum is additive).
+template <typename T, int C, int NH, bool MERGE, int NN>
 __global__ void __launch_bounds__(512)
 pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
              const SidePath* __restrict__ pside, const int32_t* __restrict__ feat,
@@ -200,7 +201,7 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
       // every slot sorted by feature and divided by: H = prod_j F_j,
       // g_i = w val H r_i
 #pragma unroll
-      for (int pass = 0; pass < kNodes / NH; ++pass) {
+      for (int pass = 0; pass < NN / NH; ++pass) {
         const int m0 = pass * NH;
         T H[NH];
 #pragma unroll
@@ -256,7 +257,7 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
       continue;
     }
 #pragma unroll
-    for (int pass = 0; pass < kNodes / NH; ++pass) {
+    for (int pass = 0; pass < NN / NH; ++pass) {
       const int m0 = pass * NH;
       T H0[NH];
 #pragma unroll
@@ -607,11 +608,14 @@ const T* table_cb(const DeviceTable& d) {
   return std::is_same<T, float>::value ? (const T*)d.pr_cb32 : (const T*)d.pr_cb64;
 }
 template <typename T>
-NodeConsts<T> node_consts(const DeviceTable& d) {
-  if constexpr (std::is_same<T, float>::value) return d.n32; else return d.n64;
+NodeConsts<T> node_consts(const DeviceTable& d, int n = 8) {
+  if constexpr (std::is_same<T, float>::value)
+    return n == 2 ? d.n32_2 : n == 4 ? d.n32_4 : n == 6 ? d.n32_6 : d.n32;
+  else
+    return n == 2 ? d.n64_2 : n == 4 ? d.n64_4 : n == 6 ? d.n64_6 : d.n64;
 }
 
-template <typename T, int C, int NH, bool MERGE>
+template <typename T, int C, int NH, bool MERGE, int NN = 8>
 void launch_pairs_fast(const HostTable& h, const DeviceTable& d, const PairClass& pc,
                        const float* X, int64_t M, int64_t ldx, const double* leaf_val,
                        double* tri64, double* phi64, const PairShape& shape, hipStream_t s) {
@@ -620,19 +624,19 @@ void launch_pairs_fast(const HostTable& h, const DeviceTable& d, const PairClass
   const int chunk = pair_chunk(pc.np, M, shape, &n_chunks);
   const int64_t grid = M * n_chunks;
   if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "interactions grid too large");
-  const void* fn = (const void*)pairs_kernel<T, C, NH, MERGE>;
+  const void* fn = (const void*)pairs_kernel<T, C, NH, MERGE, NN>;
   const size_t limit = raise_lds_limit(fn);
   const size_t fixed = pairs_fixed_lds(F, sizeof(T), false);
   if (fixed >= limit) fail(QTS_E_UNSUPPORTED, "n_features too large for the interactions kernel");
   bool first = true;
   for (const auto& rg : row_ranges(F, limit - fixed)) {
     const size_t lds = fixed + (size_t)(tri_row_h(rg.second) - tri_row_h(rg.first)) * 8;
-    hipLaunchKernelGGL((pairs_kernel<T, C, NH, MERGE>), dim3((unsigned)grid), dim3(512), lds, s,
+    hipLaunchKernelGGL((pairs_kernel<T, C, NH, MERGE, NN>), dim3((unsigned)grid), dim3(512), lds, s,
                        d.pr_d + pc.pbase, d.pr_leaf + pc.pbase, d.pr_side + pc.pbase,
                        d.pr_feat + pc.base,
                        d.pr_lo + pc.base, d.pr_hi + pc.base, table_b<T>(d) + pc.base,
                        table_cb<T>(d) + pc.base, pc.np, chunk, leaf_val, X, M, ldx, F, rg.first,
-                       rg.second, (int)first, tri64, phi64, node_consts<T>(d));
+                       rg.second, (int)first, tri64, phi64, node_consts<T>(d, NN));
     check_hip(hipGetLastError(), "pairs_kernel launch");
     first = false;
   }
@@ -668,7 +672,23 @@ void launch_pairs_generic(const HostTable& h, const DeviceTable& d, const PairCl
 
 void launch_pairs(const HostTable& h, const DeviceTable& d, const PairClass& pc, bool fp64,
                   const float* X, int64_t M, int64_t ldx, const double* lv, double* tri64,
-                  double* phi64, const PairShape& sh, hipStream_t s) {
+                  double* phi64, const PairShape& sh, bool nodes_exact, hipStream_t s) {
+  // the fewest nodes exact for the class (pair integrands of degree <= C - 2,
+  // first-order ones of degree <= C - 1: n = C / 2)
+  if (nodes_exact && pc.cap <= 12) {
+    if (!fp64) {
+      switch (pc.cap) {
+        case 4: return launch_pairs_fast<float, 4, 2, true, 2>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+        case 8: return launch_pairs_fast<float, 8, 4, true, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+        default: return launch_pairs_fast<float, 12, 6, true, 6>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+      }
+    }
+    switch (pc.cap) {
+      case 4: return launch_pairs_fast<double, 4, 2, true, 2>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+      case 8: return launch_pairs_fast<double, 8, 4, true, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+      default: return launch_pairs_fast<double, 12, 3, true, 6>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+    }
+  }
   // register-resident lane-per-path instances exist where they do not spill
   if (!fp64) {
     switch (pc.cap) {

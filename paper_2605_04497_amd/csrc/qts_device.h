@@ -53,6 +53,8 @@ struct DeviceTable {
   NodeConsts<double> n64;
   NodeConsts<float> n32_4;   // the 4-node rule (first 4 entries)
   NodeConsts<double> n64_4;
+  NodeConsts<float> n32_2, n32_6;   // the 2- and 6-node rules (interactions)
+  NodeConsts<double> n64_2, n64_6;
 };
 
 // The arrays one first-order (or adjoint) launch walks.
@@ -220,9 +222,12 @@ void launch_adjoint(const HostTable& h, const DeviceTable& d, const PathArrays& 
 
 // Interactions: accumulate the FP64 pair triangle [M][F(F-1)/2] and phi [M][F]
 // (both pre-zeroed) over the paths of one capacity class.
+// nodes_exact: the class uses the fewest nodes exact for its capacity C
+// (pair integrands have degree <= C - 2: 2 nodes for C <= 4, 4 for C <= 8,
+// 6 for C <= 12, else 8), instead of the 8-node rule.
 void launch_pairs(const HostTable& h, const DeviceTable& d, const PairClass& pc, bool fp64,
                   const float* X, int64_t M, int64_t ldx, const double* leaf_val, double* tri64,
-                  double* phi64, const PairShape& shape, hipStream_t s);
+                  double* phi64, const PairShape& shape, bool nodes_exact, hipStream_t s);
 // Phi[M][F][F] (and phi[M][F] when non-null) in FP32 or FP64 from the accumulators.
 void launch_pairs_finalize(const double* tri64, const double* phi64, int64_t M, int F, bool fp64,
                            void* Phi, void* phi, hipStream_t s);

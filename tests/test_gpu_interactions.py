@@ -173,3 +173,28 @@ def test_long_paths_with_split_triangle(q, oracle_mod):
         assert e.info["max_unique"] > 24
         check(Phi, Phi_o, precision, "long paths Phi")
         check(phi, phi_o, precision, "long paths phi")
+
+
+@pytest.mark.parametrize("name,over", [
+    ("c1_small", dict(M=40)),                                  # classes 4 and 8
+    ("c3_interactions", dict(T=6, M=24, n_train=20000)),       # classes 4..20
+])
+def test_interactions_exact_node_policy(q, oracle_mod, name, over):
+    """With the 'exact' node policy, capacity classes 4, 8 and 12 use the
+    2-, 4- and 6-node rules; their pair integrands have degree <= C - 2 (and
+    first-order ones <= C - 1), so Phi and phi equal the 8-node oracle's up to
+    rounding.  Longer classes keep 8 nodes."""
+    print("case", name, over, flush=True)
+    wl = synth.make_workload(name, **over)
+    e = q.Ensemble(wl.ensemble)
+    e.set_node_policy("exact")
+    X = torch.from_numpy(wl.X).cuda()
+    phi_o, Phi_o = oracle_mod.shap_interactions(wl.ensemble, wl.X, n=8)
+    for precision in ("fp32", "fp64"):
+        dt = torch.float32 if precision == "fp32" else torch.float64
+        Phi = torch.empty((X.shape[0], e.n_features, e.n_features), dtype=dt, device="cuda")
+        phi = torch.empty((X.shape[0], e.n_features), dtype=dt, device="cuda")
+        e.shap_interactions(X, precision, with_phi=True, out=Phi, out_phi=phi)
+        torch.cuda.synchronize()
+        check(Phi.double().cpu().numpy(), Phi_o, precision, name + " exact Phi")
+        check(phi.double().cpu().numpy(), phi_o, precision, name + " exact phi")
