@@ -175,7 +175,7 @@ int qts_shap_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_
 
 /* Launch-shape autotuner.  Times, with HIP events on `stream`, candidate
  * launch shapes on M_hint synthetic rows (uniform in [-3, 3), M_hint capped to
- * [64, 32768]; interactions on at most 256 of them) and keeps the fastest for
+ * [64, 262144]; interactions on at most 256 of them) and keeps the fastest for
  * this ensemble and precision:
  *   first-order kernel, and separately the adjoint kernel (upstream
  *     gradient uniform in [-3, 3)), per length bucket: wavefronts per

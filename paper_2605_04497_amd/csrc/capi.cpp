@@ -819,9 +819,11 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
     const bool fp64 = precision == QTS_FP64;
     const int pi = fp64 ? 1 : 0;
     const int64_t F = h.F;
-    // synthetic rows: uniform in [-3, 3), M_hint rows capped to [64, 32768]
+    // synthetic rows: uniform in [-3, 3), M_hint rows capped to [64, 262144]
+    // (the chunking a shape gives depends on the row count, so tuning at the
+    // real count matters)
     const int64_t Mt = std::max<int64_t>(64, std::min<int64_t>(M_hint > 0 ? M_hint : 16384,
-                                                               32768));
+                                                               262144));
     Scratch xs(sizeof(float) * (size_t)(Mt * F), s);
     const float* X = (const float*)xs.p;
     launch_fill_uniform((float*)xs.p, Mt * F, 0x2605u, s);
