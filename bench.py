@@ -289,10 +289,25 @@ def measure_deep(args, torch, q, synth, oracle, dev):
         Phi = torch.empty((M, F, F), dtype=dt, device=dev)
         ri = time_steps(lambda: e.shap_interactions(X, prec, out=Phi), 2, 1, torch, "interactions")
         e.set_graph_replay(False)
+        # method flops: 51 per (sample, element) of the first-order table (the
+        # batched kernels of rows over 8 features run about that many; the
+        # <= 8 bucket, 0.5% of this workload's elements, runs fewer), and the
+        # pair count of the interactions table as in the interactions leg
+        vflops = FLOPS_PER_ELEMENT * float(M) * float(e.info["n_value_elements"])
+        N, E, U = (float(e.info[k]) for k in ("n_pair_rows", "n_pair_elements",
+                                              "n_pair_updates"))
+        pflops = float(M) * 8.0 * (2.0 * U + 7.0 * E - N)
+        vt = r["kernel_ms"] * 1e-3
+        pt = ri["kernel_ms"] * 1e-3
+        peak = PEAK_VALU_TFLOPS
         out["values_" + prec] = {"value": M * e.n_leaves / (r["ms_per_step"] * 1e-3),
-                                 "ms_per_step": r["ms_per_step"]}
+                                 "ms_per_step": r["ms_per_step"],
+                                 "method_tflops": vflops / vt / 1e12,
+                                 "method_frac_of_valu_peak": vflops / vt / 1e12 / peak}
         out["interactions_" + prec] = {"value": M * e.n_leaves / (ri["ms_per_step"] * 1e-3),
-                                       "ms_per_step": ri["ms_per_step"]}
+                                       "ms_per_step": ri["ms_per_step"],
+                                       "alu_tflops": pflops / pt / 1e12,
+                                       "frac_of_valu_peak": pflops / pt / 1e12 / peak}
         if prec == "fp32":
             rows = np.arange(0, M, M // 8)[:8]
             phi_o = oracle.shap_values(ens, wl.X[rows], n=8)
