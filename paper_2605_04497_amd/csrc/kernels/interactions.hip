@@ -60,6 +60,74 @@ __device__ __forceinline__ void lds_add(double* p, double v) {
 
 __device__ __forceinline__ int64_t tri_row(int64_t k) { return k * (k - 1) / 2; }
 
+// Lane exchanges inside a quad of lanes (DPP quad_perm): partner lane ^ 1 and ^ 2.
+constexpr int kQuadXor1 = 0xB1;  // [1, 0, 3, 2]
+constexpr int kQuadXor2 = 0x4E;  // [2, 3, 0, 1]
+
+template <int CTRL>
+__device__ __forceinline__ float quad_swap(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double quad_swap(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+  const unsigned hi =
+      (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Sum over the LS lanes that share a path (LS = 1, 2 or 4 consecutive lanes,
+// all active together).
+template <int LS, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+  if constexpr (LS >= 4) v += quad_swap<kQuadXor2>(v);
+  if constexpr (LS >= 2) v += quad_swap<kQuadXor1>(v);
+  return v;
+}
+
+// Add four pair values to the triangle with one atomic per pair.  With LS
+// lanes per path each lane holds its nodes' part of the four sums; a
+// reduce-scatter over the group leaves lane q with the totals of pairs
+// u = q, q + LS, ..., which it adds.  idx/ok give each pair's triangle entry
+// and whether it is stored.  The lane's choices are selects between scalars
+// (a select between array elements can become a lane-dependent index, which
+// puts the array in scratch memory).
+template <int LS, typename T>
+__device__ __forceinline__ void group_add(double* tris, const T (&pr)[4], const int (&idx)[4],
+                                          const bool (&ok)[4], int q) {
+  if constexpr (LS == 1) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (ok[u]) lds_add(&tris[idx[u]], (double)pr[u]);
+  } else if constexpr (LS == 2) {
+    const bool h1 = (q & 1) != 0;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const T a = pr[2 * t], b = pr[2 * t + 1];
+      const int ea = idx[2 * t], eb = idx[2 * t + 1];
+      const bool oa = ok[2 * t], ob = ok[2 * t + 1];
+      const T sum = (h1 ? b : a) + quad_swap<kQuadXor1>(h1 ? a : b);
+      if (h1 ? ob : oa) lds_add(&tris[h1 ? eb : ea], (double)sum);
+    }
+  } else {
+    static_assert(LS == 4, "1, 2 or 4 lanes per path");
+    const bool h2 = (q & 2) != 0, h1 = (q & 1) != 0;
+    const T a0 = pr[0], a1 = pr[1], a2 = pr[2], a3 = pr[3];
+    // lanes q and q ^ 2: keep pairs {2 h2, 2 h2 + 1}
+    const T s0 = (h2 ? a2 : a0) + quad_swap<kQuadXor2>(h2 ? a0 : a2);
+    const T s1 = (h2 ? a3 : a1) + quad_swap<kQuadXor2>(h2 ? a1 : a3);
+    // lanes q and q ^ 1: keep pair 2 h2 + h1 = q
+    const T sum = (h1 ? s1 : s0) + quad_swap<kQuadXor1>(h1 ? s0 : s1);
+    const int e0 = idx[0], e1 = idx[1], e2 = idx[2], e3 = idx[3];
+    const bool o0 = ok[0], o1 = ok[1], o2 = ok[2], o3 = ok[3];
+    const int e = h2 ? (h1 ? e3 : e2) : (h1 ? e1 : e0);
+    const bool o = h2 ? (h1 ? o3 : o2) : (h1 ? o1 : o0);
+    if (o) lds_add(&tris[e], (double)sum);
+  }
+}
+
 // Zero the LDS accumulators and stage the sample row.
 __device__ __forceinline__ void pairs_prologue(double* phis, double* tris, int64_t ntri_r,
                                                float* xrow, const float* X, int64_t s,
@@ -92,11 +160,15 @@ __device__ __forceinline__ void pairs_epilogue(const double* phis, const double*
 }  // namespace
 
 // Lane-per-path form for short paths (capacity C, register resident).  Each
-// lane takes one path of the class (the table is slot-major, so a wave's 64
-// paths load coalesced).  NN nodes (the rule's size, 8 or fewer where fewer
-// are exact); NH < NN splits them over passes to bound the registers held by
-// r (the node sum is additive).
-template <typename T, int C, int NH, bool MERGE, int NN>
+// path of the class is taken by LS consecutive lanes (the table is slot-major,
+// so a wave's 64 / LS paths load coalesced).  NN nodes (the rule's size, 8 or
+// fewer where fewer are exact), NH at a time, to bound the registers held by r
+// (the node sum is additive):
+//   LS = 1: one lane per path, NN / NH passes over the nodes, each adding its
+//           partial sums with its own atomics;
+//   LS > 1: NH = NN / LS nodes per lane in one pass; the lanes' partial sums
+//           are added across the group (DPP) before one atomic per pair.
+template <typename T, int C, int NH, bool MERGE, int NN, int LS>
 __global__ void __launch_bounds__(512)
 pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
              const SidePath* __restrict__ pside, const int32_t* __restrict__ feat,
@@ -120,11 +192,26 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
   const int p1 = min(np, p0 + chunk);
   pairs_prologue(phis, tris, ntri_r, xrow, X, s, ldx, F);
 
+  static_assert(LS == 1 || NH * LS == NN, "a lane group takes the nodes in one pass");
+  constexpr int PW = 64 / LS;  // paths per wave
   const int lane = threadIdx.x & 63;
+  const int q = lane % LS;     // LS > 1: the lane takes nodes q NH .. q NH + NH - 1
   const int wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
-  for (int base = p0 + wave * 64; base < p1; base += nw * 64) {
-    const int p = base + lane;
+  // LS > 1: the lane's nodes and weights, selected with static indices
+  T tq[NH], wq[NH];
+#pragma unroll
+  for (int m = 0; m < NH; ++m) {
+    tq[m] = nc.t[m];
+    wq[m] = nc.w[m];
+#pragma unroll
+    for (int g = 1; g < LS; ++g) {
+      tq[m] = q == g ? nc.t[g * NH + m] : tq[m];
+      wq[m] = q == g ? nc.w[g * NH + m] : wq[m];
+    }
+  }
+  for (int base = p0 + wave * PW; base < p1; base += nw * PW) {
+    const int p = base + lane / LS;
     const bool valid = p < p1;
     const int pc = valid ? p : p1 - 1;  // clamped index for the loads
     // every table load of the path issues before the first use, and none is
@@ -201,7 +288,7 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
       // every slot sorted by feature and divided by: H = prod_j F_j,
       // g_i = w val H r_i
 #pragma unroll
-      for (int pass = 0; pass < NN / NH; ++pass) {
+      for (int pass = 0; pass < NN / (NH * LS); ++pass) {
         const int m0 = pass * NH;
         T H[NH];
 #pragma unroll
@@ -211,14 +298,14 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
         for (int j = 0; j < C; ++j) {
 #pragma unroll
           for (int m = 0; m < NH; ++m) {
-            const T Fv = fmaP(nc.t[m0 + m], cj[j], bj[j]);
+            const T Fv = fmaP(LS == 1 ? nc.t[m0 + m] : tq[m], cj[j], bj[j]);
             H[m] *= Fv;
             r[j][m] = cj[j] * rcpP(Fv);
           }
         }
         T G[NH];
 #pragma unroll
-        for (int m = 0; m < NH; ++m) G[m] = nc.w[m0 + m] * val * H[m];
+        for (int m = 0; m < NH; ++m) G[m] = (LS == 1 ? nc.w[m0 + m] : wq[m]) * val * H[m];
 #pragma unroll
         for (int i = 0; i < C; ++i) {
           if (i < d && live) {
@@ -230,7 +317,8 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
               ph += g[m];
             }
             const int fi = f[i];
-            if (with_phi) lds_add(&phis[fi], (double)ph);
+            ph = group_sum<LS>(ph);
+            if (with_phi && q == 0) lds_add(&phis[fi], (double)ph);
             // pairs (i, k > i) in groups of four: the four values are
             // computed into separate registers before their atomics issue, so
             // the LDS queue sees back-to-back atomics instead of one per
@@ -245,10 +333,22 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
 #pragma unroll
                 for (int m = 1; m < NH; ++m) pr[u] = fmaP(g[m], r[k][m], pr[u]);
               }
+              if constexpr (LS == 1) {
 #pragma unroll
-              for (int u = 0; u < 4; ++u) {
-                const int k = kb + u < C ? kb + u : 0;
-                if (kb + u < C && inr[k]) lds_add(&tris[rb[k] + fi], (double)pr[u]);
+                for (int u = 0; u < 4; ++u) {
+                  const int k = kb + u < C ? kb + u : 0;
+                  if (kb + u < C && inr[k]) lds_add(&tris[rb[k] + fi], (double)pr[u]);
+                }
+              } else {
+                int idx[4];
+                bool ok[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                  const int k = kb + u < C ? kb + u : 0;
+                  idx[u] = rb[k] + fi;
+                  ok[u] = kb + u < C && inr[k];
+                }
+                group_add<LS>(tris, pr, idx, ok, q);
               }
             }
           }
@@ -257,7 +357,7 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
       continue;
     }
 #pragma unroll
-    for (int pass = 0; pass < NN / NH; ++pass) {
+    for (int pass = 0; pass < NN / (NH * LS); ++pass) {
       const int m0 = pass * NH;
       T H0[NH];
 #pragma unroll
@@ -267,7 +367,7 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
       for (int j = 1; j < C; ++j) {
 #pragma unroll
         for (int m = 0; m < NH; ++m) {
-          const T Fv = fmaP(nc.t[m0 + m], cj[j], bj[j]);
+          const T Fv = fmaP(LS == 1 ? nc.t[m0 + m] : tq[m], cj[j], bj[j]);
           H0[m] *= Fv;
           r[j][m] = cj[j] * rcpP(Fv);
         }
@@ -276,8 +376,8 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
       T G[NH], GF[NH];
 #pragma unroll
       for (int m = 0; m < NH; ++m) {
-        G[m] = nc.w[m0 + m] * val * H0[m];
-        GF[m] = G[m] * fmaP(nc.t[m0 + m], cj[0], bj[0]);
+        G[m] = (LS == 1 ? nc.w[m0 + m] : wq[m]) * val * H0[m];
+        GF[m] = G[m] * fmaP(LS == 1 ? nc.t[m0 + m] : tq[m], cj[0], bj[0]);
       }
 
       if (live) {
@@ -292,7 +392,8 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
           }
           const int f0 = f[0];
           const int rb0 = rb[0];
-          if (with_phi) lds_add(&phis[f0], (double)ph);
+          ph = group_sum<LS>(ph);
+          if (with_phi && q == 0) lds_add(&phis[f0], (double)ph);
 #pragma unroll
           for (int kb = 1; kb < C; kb += 4) {
             T pr[4];
@@ -303,17 +404,20 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
 #pragma unroll
               for (int m = 1; m < NH; ++m) pr[u] = fmaP(g[m], r[k][m], pr[u]);
             }
+            int idx[4];
+            bool ok[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               const int k = kb + u < C ? kb + u : 1;
               // without merged rows every slot is sorted: f0 < f[k]
               const bool lo0 = MERGE ? f0 < f[k] : true;
-              const int idx = lo0 ? rb[k] + f0 : rb0 + f[k];
-              const bool ok = MERGE ? (((lo0 ? f[k] : f0) >= r0) & ((lo0 ? f[k] : f0) < r1) &
+              idx[u] = lo0 ? rb[k] + f0 : rb0 + f[k];
+              const bool in = MERGE ? (((lo0 ? f[k] : f0) >= r0) & ((lo0 ? f[k] : f0) < r1) &
                                        (k < d))
                                     : inr[k];
-              if (kb + u < C && ok) lds_add(&tris[idx], (double)pr[u]);
+              ok[u] = kb + u < C && in;
             }
+            group_add<LS>(tris, pr, idx, ok, q);
           }
         }
 #pragma unroll
@@ -327,7 +431,8 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
               ph += g[m];
             }
             const int fi = f[i];
-            if (with_phi) lds_add(&phis[fi], (double)ph);
+            ph = group_sum<LS>(ph);
+            if (with_phi && q == 0) lds_add(&phis[fi], (double)ph);
             // pairs (i, k > i) in groups of four: the four values are
             // computed into separate registers before their atomics issue, so
             // the LDS queue sees back-to-back atomics instead of one per
@@ -342,10 +447,22 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
 #pragma unroll
                 for (int m = 1; m < NH; ++m) pr[u] = fmaP(g[m], r[k][m], pr[u]);
               }
+              if constexpr (LS == 1) {
 #pragma unroll
-              for (int u = 0; u < 4; ++u) {
-                const int k = kb + u < C ? kb + u : 1;
-                if (kb + u < C && inr[k]) lds_add(&tris[rb[k] + fi], (double)pr[u]);
+                for (int u = 0; u < 4; ++u) {
+                  const int k = kb + u < C ? kb + u : 1;
+                  if (kb + u < C && inr[k]) lds_add(&tris[rb[k] + fi], (double)pr[u]);
+                }
+              } else {
+                int idx[4];
+                bool ok[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                  const int k = kb + u < C ? kb + u : 1;
+                  idx[u] = rb[k] + fi;
+                  ok[u] = kb + u < C && inr[k];
+                }
+                group_add<LS>(tris, pr, idx, ok, q);
               }
             }
           }
@@ -615,7 +732,7 @@ NodeConsts<T> node_consts(const DeviceTable& d, int n = 8) {
     return n == 2 ? d.n64_2 : n == 4 ? d.n64_4 : n == 6 ? d.n64_6 : d.n64;
 }
 
-template <typename T, int C, int NH, bool MERGE, int NN = 8>
+template <typename T, int C, int NH, bool MERGE, int NN = 8, int LS = 1>
 void launch_pairs_fast(const HostTable& h, const DeviceTable& d, const PairClass& pc,
                        const float* X, int64_t M, int64_t ldx, const double* leaf_val,
                        double* tri64, double* phi64, const PairShape& shape, hipStream_t s) {
@@ -624,14 +741,14 @@ void launch_pairs_fast(const HostTable& h, const DeviceTable& d, const PairClass
   const int chunk = pair_chunk(pc.np, M, shape, &n_chunks);
   const int64_t grid = M * n_chunks;
   if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "interactions grid too large");
-  const void* fn = (const void*)pairs_kernel<T, C, NH, MERGE, NN>;
+  const void* fn = (const void*)pairs_kernel<T, C, NH, MERGE, NN, LS>;
   const size_t limit = raise_lds_limit(fn);
   const size_t fixed = pairs_fixed_lds(F, sizeof(T), false);
   if (fixed >= limit) fail(QTS_E_UNSUPPORTED, "n_features too large for the interactions kernel");
   bool first = true;
   for (const auto& rg : row_ranges(F, limit - fixed)) {
     const size_t lds = fixed + (size_t)(tri_row_h(rg.second) - tri_row_h(rg.first)) * 8;
-    hipLaunchKernelGGL((pairs_kernel<T, C, NH, MERGE, NN>), dim3((unsigned)grid), dim3(512), lds, s,
+    hipLaunchKernelGGL((pairs_kernel<T, C, NH, MERGE, NN, LS>), dim3((unsigned)grid), dim3(512), lds, s,
                        d.pr_d + pc.pbase, d.pr_leaf + pc.pbase, d.pr_side + pc.pbase,
                        d.pr_feat + pc.base,
                        d.pr_lo + pc.base, d.pr_hi + pc.base, table_b<T>(d) + pc.base,
@@ -689,7 +806,8 @@ void launch_pairs(const HostTable& h, const DeviceTable& d, const PairClass& pc,
       default: return launch_pairs_fast<double, 12, 3, true, 6>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     }
   }
-  // register-resident lane-per-path instances exist where they do not spill
+  // register-resident instances exist where they do not spill; FP32 C = 24
+  // takes two lanes per path (four nodes each) instead of two node passes
   if (!fp64) {
     switch (pc.cap) {
       case 4: return launch_pairs_fast<float, 4, 8, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
@@ -697,7 +815,7 @@ void launch_pairs(const HostTable& h, const DeviceTable& d, const PairClass& pc,
       case 12: return launch_pairs_fast<float, 12, 8, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
       case 16: return launch_pairs_fast<float, 16, 8, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
       case 20: return launch_pairs_fast<float, 20, 8, false>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
-      case 24: return launch_pairs_fast<float, 24, 4, false>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+      case 24: return launch_pairs_fast<float, 24, 4, false, 8, 2>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
       default: return launch_pairs_generic<float>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     }
   }
