@@ -806,8 +806,12 @@ void launch_pairs(const HostTable& h, const DeviceTable& d, const PairClass& pc,
       default: return launch_pairs_fast<double, 12, 3, true, 6>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     }
   }
-  // register-resident instances exist where they do not spill; FP32 C = 24
-  // takes two lanes per path (four nodes each) instead of two node passes
+  // register-resident instances exist where they do not spill.  Up to FP32
+  // C = 20 and FP64 C = 8 a lane holds all eight nodes; FP64 C = 12..20 take
+  // node passes (the lane split measured no faster there: the FP64 selects and
+  // swaps cost as much VALU time as the atomics they save); longer classes
+  // take two or four lanes per path, which beats the wave-per-path generic
+  // kernel; the longest run the generic kernel
   if (!fp64) {
     switch (pc.cap) {
       case 4: return launch_pairs_fast<float, 4, 8, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
@@ -816,6 +820,10 @@ void launch_pairs(const HostTable& h, const DeviceTable& d, const PairClass& pc,
       case 16: return launch_pairs_fast<float, 16, 8, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
       case 20: return launch_pairs_fast<float, 20, 8, false>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
       case 24: return launch_pairs_fast<float, 24, 4, false, 8, 2>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+      case 28: return launch_pairs_fast<float, 28, 4, false, 8, 2>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+      case 32: return launch_pairs_fast<float, 32, 2, false, 8, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+      case 36: return launch_pairs_fast<float, 36, 2, false, 8, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+      case 40: return launch_pairs_fast<float, 40, 2, false, 8, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
       default: return launch_pairs_generic<float>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     }
   }
@@ -825,6 +833,8 @@ void launch_pairs(const HostTable& h, const DeviceTable& d, const PairClass& pc,
     case 12: return launch_pairs_fast<double, 12, 4, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     case 16: return launch_pairs_fast<double, 16, 4, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     case 20: return launch_pairs_fast<double, 20, 2, false>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+    case 24: return launch_pairs_fast<double, 24, 2, false, 8, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+    case 28: return launch_pairs_fast<double, 28, 2, false, 8, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     default: return launch_pairs_generic<double>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
   }
 }

@@ -102,10 +102,11 @@ def test_interactions_edge_cases(q, oracle_mod):
     assert out.shape == (0, wl.ensemble.n_features, wl.ensemble.n_features)
 
 
-@pytest.mark.parametrize("d", [3, 12, 13, 24, 25, 40, 41, 48, 64])
+@pytest.mark.parametrize("d", [3, 12, 13, 20, 21, 24, 25, 28, 29, 32, 33, 36, 37, 40, 41, 48, 64])
 def test_interaction_capacity_classes(q, oracle_mod, d):
-    """A chain of d features covers each capacity class boundary, including the
-    long-path (generic) classes."""
+    """A chain of d features covers each capacity class boundary: the one-lane
+    classes, the classes whose paths take two or four lanes (FP32 24..40,
+    FP64 24..28) and the long-path (generic) classes."""
     from tests.test_gpu_values import chain_model, chain_rows
     ens, X = chain_model(d), chain_rows(d)
     phi_o, Phi_o = oracle_mod.shap_interactions(ens, X, n=8)
