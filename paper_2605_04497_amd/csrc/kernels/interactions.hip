@@ -162,12 +162,11 @@ __device__ __forceinline__ void pairs_epilogue(const double* phis, const double*
 // Lane-per-path form for short paths (capacity C, register resident).  Each
 // path of the class is taken by LS consecutive lanes (the table is slot-major,
 // so a wave's 64 / LS paths load coalesced).  NN nodes (the rule's size, 8 or
-// fewer where fewer are exact), NH at a time, to bound the registers held by r
-// (the node sum is additive):
-//   LS = 1: one lane per path, NN / NH passes over the nodes, each adding its
-//           partial sums with its own atomics;
-//   LS > 1: NH = NN / LS nodes per lane in one pass; the lanes' partial sums
-//           are added across the group (DPP) before one atomic per pair.
+// fewer where fewer are exact), NH per lane at a time, to bound the registers
+// held by r (the node sum is additive): NN / (NH LS) passes, each adding its
+// partial sums with its own atomics; with LS > 1 the group's lanes take
+// different nodes in a pass and their partial sums are added across the group
+// (DPP) before one atomic per pair and pass.
 template <typename T, int C, int NH, bool MERGE, int NN, int LS>
 __global__ void __launch_bounds__(512)
 pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
@@ -192,22 +191,24 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
   const int p1 = min(np, p0 + chunk);
   pairs_prologue(phis, tris, ntri_r, xrow, X, s, ldx, F);
 
-  static_assert(LS == 1 || NH * LS == NN, "a lane group takes the nodes in one pass");
+  constexpr int NP = NN / (NH * LS);  // node passes
+  static_assert(NP * NH * LS == NN, "passes of NH nodes on each of LS lanes");
   constexpr int PW = 64 / LS;  // paths per wave
   const int lane = threadIdx.x & 63;
-  const int q = lane % LS;     // LS > 1: the lane takes nodes q NH .. q NH + NH - 1
+  const int q = lane % LS;     // pass P: the lane takes nodes P NH LS + q NH + [0, NH)
   const int wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
-  // LS > 1: the lane's nodes and weights, selected with static indices
-  T tq[NH], wq[NH];
+  // LS > 1: the lane's nodes and weights per pass, selected with static indices
+  T tq[NP * NH], wq[NP * NH];
 #pragma unroll
-  for (int m = 0; m < NH; ++m) {
-    tq[m] = nc.t[m];
-    wq[m] = nc.w[m];
+  for (int e = 0; e < NP * NH; ++e) {
+    const int n0 = (e / NH) * NH * LS + e % NH;
+    tq[e] = nc.t[n0];
+    wq[e] = nc.w[n0];
 #pragma unroll
     for (int g = 1; g < LS; ++g) {
-      tq[m] = q == g ? nc.t[g * NH + m] : tq[m];
-      wq[m] = q == g ? nc.w[g * NH + m] : wq[m];
+      tq[e] = q == g ? nc.t[n0 + g * NH] : tq[e];
+      wq[e] = q == g ? nc.w[n0 + g * NH] : wq[e];
     }
   }
   for (int base = p0 + wave * PW; base < p1; base += nw * PW) {
@@ -288,7 +289,7 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
       // every slot sorted by feature and divided by: H = prod_j F_j,
       // g_i = w val H r_i
 #pragma unroll
-      for (int pass = 0; pass < NN / (NH * LS); ++pass) {
+      for (int pass = 0; pass < NP; ++pass) {
         const int m0 = pass * NH;
         T H[NH];
 #pragma unroll
@@ -298,14 +299,14 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
         for (int j = 0; j < C; ++j) {
 #pragma unroll
           for (int m = 0; m < NH; ++m) {
-            const T Fv = fmaP(LS == 1 ? nc.t[m0 + m] : tq[m], cj[j], bj[j]);
+            const T Fv = fmaP(LS == 1 ? nc.t[m0 + m] : tq[m0 + m], cj[j], bj[j]);
             H[m] *= Fv;
             r[j][m] = cj[j] * rcpP(Fv);
           }
         }
         T G[NH];
 #pragma unroll
-        for (int m = 0; m < NH; ++m) G[m] = (LS == 1 ? nc.w[m0 + m] : wq[m]) * val * H[m];
+        for (int m = 0; m < NH; ++m) G[m] = (LS == 1 ? nc.w[m0 + m] : wq[m0 + m]) * val * H[m];
 #pragma unroll
         for (int i = 0; i < C; ++i) {
           if (i < d && live) {
@@ -357,7 +358,7 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
       continue;
     }
 #pragma unroll
-    for (int pass = 0; pass < NN / (NH * LS); ++pass) {
+    for (int pass = 0; pass < NP; ++pass) {
       const int m0 = pass * NH;
       T H0[NH];
 #pragma unroll
@@ -367,7 +368,7 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
       for (int j = 1; j < C; ++j) {
 #pragma unroll
         for (int m = 0; m < NH; ++m) {
-          const T Fv = fmaP(LS == 1 ? nc.t[m0 + m] : tq[m], cj[j], bj[j]);
+          const T Fv = fmaP(LS == 1 ? nc.t[m0 + m] : tq[m0 + m], cj[j], bj[j]);
           H0[m] *= Fv;
           r[j][m] = cj[j] * rcpP(Fv);
         }
@@ -376,8 +377,8 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
       T G[NH], GF[NH];
 #pragma unroll
       for (int m = 0; m < NH; ++m) {
-        G[m] = (LS == 1 ? nc.w[m0 + m] : wq[m]) * val * H0[m];
-        GF[m] = G[m] * fmaP(LS == 1 ? nc.t[m0 + m] : tq[m], cj[0], bj[0]);
+        G[m] = (LS == 1 ? nc.w[m0 + m] : wq[m0 + m]) * val * H0[m];
+        GF[m] = G[m] * fmaP(LS == 1 ? nc.t[m0 + m] : tq[m0 + m], cj[0], bj[0]);
       }
 
       if (live) {
@@ -807,11 +808,12 @@ void launch_pairs(const HostTable& h, const DeviceTable& d, const PairClass& pc,
     }
   }
   // register-resident instances exist where they do not spill.  Up to FP32
-  // C = 20 and FP64 C = 8 a lane holds all eight nodes; FP64 C = 12..20 take
-  // node passes (the lane split measured no faster there: the FP64 selects and
-  // swaps cost as much VALU time as the atomics they save); longer classes
-  // take two or four lanes per path, which beats the wave-per-path generic
-  // kernel; the longest run the generic kernel
+  // C = 20 and FP64 C = 8 a lane holds all eight nodes.  FP64 C = 12 and 16
+  // take two node passes (one pass on two lanes measured slower: the FP64
+  // selects and swaps cost more VALU time than the atomics they save), FP64
+  // C = 20 two lanes and two passes (half the atomics of four passes on one
+  // lane).  Longer classes take two or four lanes per path, which beats the
+  // wave-per-path generic kernel; the longest run the generic kernel
   if (!fp64) {
     switch (pc.cap) {
       case 4: return launch_pairs_fast<float, 4, 8, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
@@ -832,7 +834,7 @@ void launch_pairs(const HostTable& h, const DeviceTable& d, const PairClass& pc,
     case 8: return launch_pairs_fast<double, 8, 8, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     case 12: return launch_pairs_fast<double, 12, 4, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     case 16: return launch_pairs_fast<double, 16, 4, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
-    case 20: return launch_pairs_fast<double, 20, 2, false>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+    case 20: return launch_pairs_fast<double, 20, 2, false, 8, 2>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     case 24: return launch_pairs_fast<double, 24, 2, false, 8, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     case 28: return launch_pairs_fast<double, 28, 2, false, 8, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     default: return launch_pairs_generic<double>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
