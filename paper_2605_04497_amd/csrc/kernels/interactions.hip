@@ -128,6 +128,34 @@ __device__ __forceinline__ void group_add(double* tris, const T (&pr)[4], const 
   }
 }
 
+// group_add for rows whose pair (i, k) sits at row offset of k + fi for
+// every k (no merged slot 0): lane q's offsets were chosen per path (rbs[j]:
+// slot j + q's offset, -1 if not stored), so only the values need selects.
+template <int LS, int C, typename T>
+__device__ __forceinline__ void group_add_own(double* tris, const T (&pr)[4], const int (&rbs)[C],
+                                              int kb, int fi, int q) {
+  if constexpr (LS == 2) {
+    const bool h1 = (q & 1) != 0;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      if (kb + 2 * t < C) {
+        const T a = pr[2 * t], b = pr[2 * t + 1];
+        const T sum = (h1 ? b : a) + quad_swap<kQuadXor1>(h1 ? a : b);
+        const int e = rbs[kb + 2 * t];
+        if (e >= 0) lds_add(&tris[e + fi], (double)sum);
+      }
+    }
+  } else {
+    static_assert(LS == 4, "2 or 4 lanes per path");
+    const bool h2 = (q & 2) != 0, h1 = (q & 1) != 0;
+    const T a0 = pr[0], a1 = pr[1], a2 = pr[2], a3 = pr[3];
+    const T s0 = (h2 ? a2 : a0) + quad_swap<kQuadXor2>(h2 ? a0 : a2);
+    const T s1 = (h2 ? a3 : a1) + quad_swap<kQuadXor2>(h2 ? a1 : a3);
+    const T sum = (h1 ? s1 : s0) + quad_swap<kQuadXor1>(h1 ? s0 : s1);
+    if (rbs[kb] >= 0) lds_add(&tris[rbs[kb] + fi], (double)sum);
+  }
+}
+
 // Zero the LDS accumulators and stage the sample row.
 __device__ __forceinline__ void pairs_prologue(double* phis, double* tris, int64_t ntri_r,
                                                float* xrow, const float* X, int64_t s,
@@ -283,6 +311,20 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
       }
     }
     if (dead) val = T(0);
+    // LS > 1: the triangle row offset of slot j + q (-1: its pairs are not
+    // stored), where q is the lane's place in its group, chosen once per path
+    // so that each lane reads its own pairs' entries with static indices
+    // (lane q adds the pairs k = kb + q + LS v of each group of four)
+    int rbs[C];
+    if constexpr (LS > 1) {
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        rbs[j] = inr[j] ? rb[j] : -1;
+#pragma unroll
+        for (int g = 1; g < LS; ++g)
+          rbs[j] = q == g ? (j + g < C && inr[j + g] ? rb[j + g] : -1) : rbs[j];
+      }
+    }
     const bool live = val != T(0);
 
     if constexpr (!MERGE) {
@@ -341,15 +383,7 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
                   if (kb + u < C && inr[k]) lds_add(&tris[rb[k] + fi], (double)pr[u]);
                 }
               } else {
-                int idx[4];
-                bool ok[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                  const int k = kb + u < C ? kb + u : 0;
-                  idx[u] = rb[k] + fi;
-                  ok[u] = kb + u < C && inr[k];
-                }
-                group_add<LS>(tris, pr, idx, ok, q);
+                group_add_own<LS, C>(tris, pr, rbs, kb, fi, q);
               }
             }
           }
@@ -813,7 +847,8 @@ void launch_pairs(const HostTable& h, const DeviceTable& d, const PairClass& pc,
   // selects and swaps cost more VALU time than the atomics they save), FP64
   // C = 20 two lanes and two passes (half the atomics of four passes on one
   // lane).  Longer classes take two or four lanes per path, which beats the
-  // wave-per-path generic kernel; the longest run the generic kernel
+  // wave-per-path generic kernel; the longest (FP32 64, FP64 36 and up, which
+  // would spill) run the generic kernel
   if (!fp64) {
     switch (pc.cap) {
       case 4: return launch_pairs_fast<float, 4, 8, true>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
@@ -826,6 +861,7 @@ void launch_pairs(const HostTable& h, const DeviceTable& d, const PairClass& pc,
       case 32: return launch_pairs_fast<float, 32, 2, false, 8, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
       case 36: return launch_pairs_fast<float, 36, 2, false, 8, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
       case 40: return launch_pairs_fast<float, 40, 2, false, 8, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+      case 48: return launch_pairs_fast<float, 48, 2, false, 8, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
       default: return launch_pairs_generic<float>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     }
   }
@@ -837,6 +873,7 @@ void launch_pairs(const HostTable& h, const DeviceTable& d, const PairClass& pc,
     case 20: return launch_pairs_fast<double, 20, 2, false, 8, 2>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     case 24: return launch_pairs_fast<double, 24, 2, false, 8, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     case 28: return launch_pairs_fast<double, 28, 2, false, 8, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
+    case 32: return launch_pairs_fast<double, 32, 2, false, 8, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     default: return launch_pairs_generic<double>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
   }
 }
