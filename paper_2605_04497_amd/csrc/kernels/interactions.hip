@@ -128,9 +128,11 @@ __device__ __forceinline__ void group_add(double* tris, const T (&pr)[4], const 
   }
 }
 
-// group_add for rows whose pair (i, k) sits at row offset of k + fi for
-// every k (no merged slot 0): lane q's offsets were chosen per path (rbs[j]:
-// slot j + q's offset, -1 if not stored), so only the values need selects.
+// group_add for LS > 1 where pair (i, k) sits at tris[rb[k] + f_i] (every
+// pair but a merged slot 0's): lane q's offsets were chosen once per path
+// (rbs[j] = rb[j + q], or -1 if not stored), so only the values need selects.
+// The merged slot-0 pairs, whose entry depends on which feature is larger,
+// take group_add.
 template <int LS, int C, typename T>
 __device__ __forceinline__ void group_add_own(double* tris, const T (&pr)[4], const int (&rbs)[C],
                                               int kb, int fi, int q) {
