@@ -33,7 +33,7 @@ CASES = [
     ("c1_small", dict(M=70)),
     ("c3_interactions", dict(T=4, M=20, n_train=20000)),   # F=200, depths 3..20
     ("c4_adjoint", dict(T=10, M=70, n_train=20000)),
-    ("c5_deep", dict(T=3, M=12, n_train=30000)),           # long paths: generic kernel
+    ("c5_deep", dict(T=3, M=12, n_train=30000)),           # long paths: lane groups
 ]
 
 
@@ -161,9 +161,9 @@ def test_merged_sibling_rows_cancellation(q, oracle_mod):
 
 
 def test_long_paths_with_split_triangle(q, oracle_mod):
-    """Paths longer than the register-resident instances take (the
-    wave-per-path kernel and its pair table) together with more features
-    than one LDS triangle holds (row ranges), in both precisions."""
+    """Paths of more than 24 features (two or four lanes per path) together
+    with more features than one LDS triangle holds (row ranges), in both
+    precisions."""
     rng = np.random.default_rng(900)
     ens = synth.random_small_ensemble(rng, 3, 260, 34, n_train=4000, p_leaf=0.0)
     X = rng.standard_normal((23, 260)).astype(np.float32)
@@ -199,3 +199,43 @@ def test_interactions_exact_node_policy(q, oracle_mod, name, over):
         torch.cuda.synchronize()
         check(Phi.double().cpu().numpy(), Phi_o, precision, name + " exact Phi")
         check(phi.double().cpu().numpy(), phi_o, precision, name + " exact phi")
+
+
+def _random_chains(rng, n_chains, F, D):
+    """Chains of D distinct features drawn from F: at each split a random side
+    continues and the other is a leaf, with random thresholds, missing-value
+    directions and cover ratios, so the rows of one chain have 1..D unique
+    features and fill every capacity class up to D."""
+    trees = []
+    for _ in range(n_chains):
+        feats = rng.permutation(F)[:D]
+        b = rng.uniform(0.55, 0.95, D)
+        cov = np.cumprod(np.concatenate([[1.0], b]))
+        node = ("leaf", float(rng.standard_normal()), float(cov[D]))
+        for j in reversed(range(D)):
+            leaf = ("leaf", float(rng.standard_normal()), float(cov[j] * (1 - b[j])))
+            thr = float(np.round(rng.standard_normal() * 0.8, 2))
+            dl = int(rng.integers(2))
+            if rng.random() < 0.5:
+                node = ("split", int(feats[j]), thr, float(cov[j]), node, leaf, dl)
+            else:
+                node = ("split", int(feats[j]), thr, float(cov[j]), leaf, node, dl)
+        trees.append(node)
+    return synth.from_nested(trees, n_features=F)
+
+
+def test_every_class_with_many_rows(q, oracle_mod):
+    """Several rows in every capacity class from 4 to 64: one-lane instances
+    with node passes, two- and four-lane groups (ragged in the last group of
+    a wave) and the wave-per-path kernel, over a triangle split into row
+    ranges (F = 260), with missing values, in both precisions."""
+    rng = np.random.default_rng(4242)
+    ens = _random_chains(rng, 5, 260, 64)
+    X = rng.standard_normal((29, 260)).astype(np.float32) * 0.6
+    X[::5, ::9] = np.nan
+    phi_o, Phi_o = oracle_mod.shap_interactions(ens, X, n=8)
+    for precision in ("fp32", "fp64"):
+        Phi, phi, e = _run(q, ens, X, precision)
+        assert e.info["max_unique"] == 64
+        check(Phi, Phi_o, precision, "chains Phi")
+        check(phi, phi_o, precision, "chains phi")
