@@ -171,3 +171,39 @@ def test_shapes_kept_per_node_policy(q):
         assert w in VALUES_WAVES and items in VALUES_ITEMS
     e.set_node_policy("fixed8")
     assert [e.launch_shape(k, "fp32", 0) for k in kinds] == tuned8
+
+
+def test_calls_on_side_streams(q, oracle_mod):
+    """Calls made under a non-default torch stream (default priority) run on
+    that stream, eager and under graph replay: two ensembles alternate
+    between two streams, with new X contents between rounds, and every
+    result matches the oracle."""
+    wl = synth.make_workload("c1_small", M=300)
+    X2 = wl.X[::-1].copy()
+    want = [oracle_mod.shap_values(wl.ensemble, x, n=8) for x in (wl.X, X2)]
+    _, want_pairs = oracle_mod.shap_interactions(wl.ensemble, wl.X[:8], n=8)
+    e1, e2 = q.Ensemble(wl.ensemble), q.Ensemble(wl.ensemble)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    X = torch.from_numpy(wl.X).cuda()
+    torch.cuda.synchronize()
+    for replay in (False, True):
+        e1.set_graph_replay(replay)
+        e2.set_graph_replay(replay)
+        for it in range(4):
+            k = it % 2
+            X.copy_(torch.from_numpy(wl.X if k == 0 else X2))
+            torch.cuda.synchronize()
+            with torch.cuda.stream(s1):
+                a = e1.shap_values(X, "fp64")
+            with torch.cuda.stream(s2):
+                b = e2.shap_values(X, "fp32")
+                P = e2.shap_interactions(X[:8], "fp64")
+            s1.synchronize()
+            s2.synchronize()
+            check(a.cpu().numpy(), want[k], "fp64", "stream 1, replay %s, round %d" % (replay, it))
+            check(b.double().cpu().numpy(), want[k], "fp32",
+                  "stream 2, replay %s, round %d" % (replay, it))
+            if k == 0:
+                check(P.cpu().numpy(), want_pairs, "fp64", "stream 2 pairs, replay %s" % replay)
+    e1.close()
+    e2.close()
