@@ -122,6 +122,20 @@ def shap_sii(ens, X):
     return sii
 
 
+def shap_sii3(ens, X):
+    """sii3[M,F,F,F] for ordered triples of distinct features by enumeration."""
+    X = np.asarray(X, np.float32)
+    F = ens.n_features
+    sii3 = np.zeros((X.shape[0], F, F, F))
+    for r in range(X.shape[0]):
+        for t in range(ens.n_trees):
+            feats, v = tree_game(ens, t, X[r])
+            for S, val in _sii_of_game(feats, v, 3).items():
+                for a, b, c in itertools.permutations(S):
+                    sii3[r, a, b, c] += val
+    return sii3
+
+
 def game_value(ens, x, S):
     """Ensemble game v_x(S) (sum over trees)."""
     return sum(tree_game(ens, t, x)[1](frozenset(S)) for t in range(ens.n_trees))

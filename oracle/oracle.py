@@ -155,6 +155,22 @@ def shap_interactions(m, X, n=N_METHOD, threads=None):
     return phi, interaction_matrix(phi, sii)
 
 
+def shap_sii3(m, X, n=N_METHOD, threads=None) -> np.ndarray:
+    """sii3[M,F,F,F]: third-order Shapley interaction indices (Theorem 1 with
+    |S| = 3, Eq. 9-10) of every ordered triple of distinct features; entries
+    with a repeated index are 0."""
+    m = _model(m)
+    X, M, ld = _X(X)
+    sii3 = np.zeros((M, m.F, m.F, m.F))
+    rc = lib().orc_shap_sii3(m.ref(), ctypes.c_void_p(X.ctypes.data), ctypes.c_int64(M),
+                             ctypes.c_int64(ld), ctypes.c_int(n),
+                             ctypes.c_void_p(sii3.ctypes.data),
+                             ctypes.c_int(threads or default_threads()))
+    if rc != 0:
+        raise RuntimeError("orc_shap_sii3 failed")
+    return sii3
+
+
 def leaf_grad(m, X, G, n=N_METHOD, threads=None) -> np.ndarray:
     """grad_leaf = J^T G with J[s,i,leaf] = d phi[s,i] / d val(leaf); leaves in
     tree-major node-id order."""

@@ -272,3 +272,44 @@ def test_leaf_gradient_is_transposed_jacobian(oracle_mod, layout):
         want[leaf] = np.sum(G * brute.shap_values(ens.with_leaf_values(e), X))
     for n in (8, 32):
         np.testing.assert_allclose(oracle_mod.leaf_grad(ens, X, G, n=n), want, atol=1e-13)
+
+
+def test_third_order_closed_form(oracle_mod):
+    """A chain of three features, cover ratio 1/2 at every split, and a row
+    that goes left everywhere.  Only the two leaves below the third split
+    carry all three features, so (Theorem 1 with |S| = 3; the integrand of an
+    empty product is 1, exact for every rule)
+      SII_012 = 1.0 (1/2)^3 + 0.3 (1/2)(1/2)(0 - 1/2) = 0.0875,
+    the same for every ordering, and 0 for any triple with feature 3."""
+    node = ("split", 2, 0.0, 0.25, ("leaf", 1.0, 0.125), ("leaf", 0.3, 0.125))
+    node = ("split", 1, 0.0, 0.5, node, ("leaf", -0.7, 0.25))
+    node = ("split", 0, 0.0, 1.0, node, ("leaf", 0.4, 0.5))
+    ens = synth.from_nested([node], n_features=4)
+    X = np.full((1, 4), -1.0, np.float32)
+    want = np.zeros((1, 4, 4, 4))
+    for a, b, c in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+        want[0, a, b, c] = 0.0875
+    for n in (1, 2, 8):
+        np.testing.assert_allclose(oracle_mod.shap_sii3(ens, X, n=n), want, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(brute.shap_sii3(ens, X), want, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_third_order_equals_enumeration(oracle_mod, seed):
+    """Third-order indices by 8-node path quadrature (exact for paths of up to
+    18 features, Theorem 2) against subset enumeration of the path-dependent
+    game (Theorem 3's definition), with missing values, on small irregular
+    ensembles; zero covers in one of the seeds."""
+    rng = np.random.default_rng(70 + seed)
+    ens = synth.random_small_ensemble(rng, 3, 6, 5, zero_cover=(seed == 2))
+    X = rng.standard_normal((4, 6)).astype(np.float32)
+    X[1, ::2] = np.nan
+    got = oracle_mod.shap_sii3(ens, X, n=8)
+    want = brute.shap_sii3(ens, X)
+    assert np.abs(want).max() > 1e-3
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())
+    # symmetric in its three indices, zero wherever two coincide
+    for perm in ((0, 2, 1, 3), (0, 3, 2, 1), (0, 2, 3, 1)):
+        np.testing.assert_array_equal(got, np.transpose(got, perm))
+    i = np.arange(6)
+    assert not got[:, i, i, :].any() and not got[:, :, i, i].any()

@@ -35,6 +35,10 @@ MUTATIONS = {
     "nan_wrong_direction": ("return m->default_left[g] != 0;", "return m->default_left[g] == 0;"),
     "edge_weight_of_parent": ("return m->cover[child] / cp;", "return m->cover[child] / (cp + 1.0);"),
     "leaf_ordinal_in_visit_order": ("leaf_ordinal(m, base, node));", "(*leaf_ord)++);"),
+    "triple_drops_k": ("if (l != i && l != j && l != k) prod *=", "if (l != i && l != j) prod *="),
+    "triple_uses_j_twice": ("(o[i] - b[i]) * (o[j] - b[j]) * (o[k] - b[k]) * integral",
+                            "(o[i] - b[i]) * (o[j] - b[j]) * (o[j] - b[j]) * integral"),
+    "triple_ordering_missing": ("        c->sii3[(z * F + y) * F + x] += v;\n", ""),
 }
 
 
@@ -64,6 +68,8 @@ def _pins_pass() -> bool:
             if not np.allclose(phi_q, brute.shap_values(ens, X), atol=1e-12):
                 return False
             if not np.allclose(sii_q, brute.shap_sii(ens, X), atol=1e-12):
+                return False
+            if not np.allclose(O.shap_sii3(ens, X, n=8), brute.shap_sii3(ens, X), atol=1e-12):
                 return False
             G = rng.normal(size=(5, 6))
             J = np.zeros(ens.n_leaves())
@@ -105,7 +111,8 @@ def test_planted_mistake_is_caught(tmp_path, monkeypatch, name):
                            "-pthread", "-o", str(so), str(bad), "-lm"])
     L = ctypes.CDLL(str(so))
     for fn in ("orc_gauss_legendre", "orc_shap_values", "orc_shap_interactions",
-               "orc_leaf_grad", "orc_expected_value", "orc_predict", "orc_treeshap"):
+               "orc_leaf_grad", "orc_expected_value", "orc_predict", "orc_treeshap",
+               "orc_shap_sii3"):
         getattr(L, fn).restype = ctypes.c_int
     monkeypatch.setattr(O, "_lib", L)
     with np.errstate(all="ignore"):
