@@ -163,6 +163,26 @@ int qts_shap_interactions(const qts_ensemble* ens, const float* X, int64_t M, in
                           const double* leaf_values, void* phi, void* Phi,
                           qts_precision precision, void* stream);
 
+/* Third-order Shapley interaction indices: Theorem 1 with |S| = 3 and Eq. 9,
+ * integrated with the 8-node rule of Eq. 10,
+ *   SII_ijk = sum over paths with i, j, k among their unique features of
+ *             val (o_i - b_i)(o_j - b_j)(o_k - b_k)
+ *             * sum_m w_m prod_{l != i,j,k} (b_l (1 - t_m) + o_l t_m).
+ *   out  [M, F(F-1)(F-2)/6] device array, float32 for QTS_FP32, double for
+ *        QTS_FP64, packed: the triple of features i < j < k at
+ *        k(k-1)(k-2)/6 + j(j-1)/2 + i (the index is symmetric in its three
+ *        features; triples with a repeated feature are not stored).
+ *        Overwritten.  With F < 3 there is nothing to write (out may be NULL).
+ *   leaf_values, X, M, ldx, precision, stream as for qts_shap_values.
+ * Accumulation is in FP64 throughout; the FP32 form allocates an FP64
+ * accumulator of M * F(F-1)(F-2)/6 doubles on `stream` for the call.  Calls
+ * run eagerly (graph replay does not apply).  Errors: QTS_E_UNSUPPORTED when
+ * one feature's triples (k(k-1)/2 of them) do not fit in LDS (F above about
+ * 170). */
+int qts_shap_interactions3(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
+                           const double* leaf_values, void* out, qts_precision precision,
+                           void* stream);
+
 /* Adjoint of qts_shap_values with respect to the leaf values: phi is linear
  * in val(v) (Eq. 1, Eq. 10), so
  *   grad_leaf[v] = sum_s sum_{j on path(v)} grad_phi[s, f_j] (o_j - b_j)

@@ -62,6 +62,8 @@ SIGNATURES = {
                                        ctypes.c_int, P]),
     "qts_shap_interactions": (ctypes.c_int, [P, P, ctypes.c_int64, ctypes.c_int64, P, P, P,
                                              ctypes.c_int, P]),
+    "qts_shap_interactions3": (ctypes.c_int, [P, P, ctypes.c_int64, ctypes.c_int64, P, P,
+                                              ctypes.c_int, P]),
     "qts_shap_backward": (ctypes.c_int, [P, P, ctypes.c_int64, ctypes.c_int64, P, P,
                                          ctypes.c_int, P]),
     "qts_autotune": (ctypes.c_int, [P, ctypes.c_int64, ctypes.c_int, P]),

@@ -152,6 +152,37 @@ class Ensemble:
                                               _stream_ptr(X.device)))
         return (Phi, phi) if with_phi else Phi
 
+    def shap_interactions3(self, X: torch.Tensor, precision: str = "fp32",
+                           leaf_values: torch.Tensor | None = None, out=None) -> torch.Tensor:
+        """Third-order Shapley interaction indices, packed [M, F(F-1)(F-2)/6]:
+        the triple of features i < j < k at k(k-1)(k-2)/6 + j(j-1)/2 + i."""
+        X, M, ldx = self._rows(X)
+        F = self.n_features
+        T3 = F * (F - 1) * (F - 2) // 6
+        dt = _DTYPE[precision]
+        if out is None:
+            out = torch.empty((M, T3), dtype=dt, device=X.device)
+        elif out.dtype != dt or tuple(out.shape) != (M, T3) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous [M, F(F-1)(F-2)/6] tensor of the output type")
+        lv = self._leaf(leaf_values)
+        L.check(L.lib().qts_shap_interactions3(self._h, _ptr(X), M, ldx, _ptr(lv), _ptr(out),
+                                               _PREC[precision], _stream_ptr(X.device)))
+        return out
+
+    @staticmethod
+    def triples_dense(packed: torch.Tensor, n_features: int) -> torch.Tensor:
+        """Expand a packed [M, F(F-1)(F-2)/6] tensor to the symmetric [M, F, F, F]
+        one (zero where two indices coincide)."""
+        F = n_features
+        idx = torch.combinations(torch.arange(F, device=packed.device), 3)  # i < j < k
+        i, j, k = idx[:, 0], idx[:, 1], idx[:, 2]
+        pos = k * (k - 1) * (k - 2) // 6 + j * (j - 1) // 2 + i
+        dense = torch.zeros((packed.shape[0], F, F, F), dtype=packed.dtype, device=packed.device)
+        v = packed[:, pos]
+        for a, b, c in ((i, j, k), (i, k, j), (j, i, k), (j, k, i), (k, i, j), (k, j, i)):
+            dense[:, a, b, c] = v
+        return dense
+
     def shap_backward(self, X: torch.Tensor, grad_phi: torch.Tensor,
                       precision: str = "fp32", out=None) -> torch.Tensor:
         """grad_leaf[n_leaves] (float64) = J^T grad_phi."""

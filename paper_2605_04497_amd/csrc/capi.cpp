@@ -731,6 +731,37 @@ int qts_shap_interactions(const qts_ensemble* ens, const float* X, int64_t M, in
   });
 }
 
+int qts_shap_interactions3(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
+                           const double* leaf_values, void* out, qts_precision precision,
+                           void* stream) {
+  return guarded([&] {
+    if (!ens) fail(QTS_E_INVALID_ARG, "null ensemble");
+    if (precision != QTS_FP32 && precision != QTS_FP64)
+      fail(QTS_E_INVALID_ARG, "unknown precision");
+    check_rows(ens, X, M, ldx);
+    const int64_t F = ens->host.F;
+    const int64_t T3 = F * (F - 1) * (F - 2) / 6;
+    if (M > 0 && T3 > 0 && !out) fail(QTS_E_INVALID_ARG, "null out");
+    require_device(ens);
+    if (M == 0 || T3 == 0) return;
+    hipStream_t s = (hipStream_t)stream;
+    const bool fp64 = precision == QTS_FP64;
+    const double* leaf = leaf_values ? leaf_values : ens->dev.leaf_val;
+    auto run = [&](double* acc) {
+      launch_fill_zero(acc, M * T3, s);
+      for (const PairClass& pc : ens->pair_classes)
+        launch_triples(ens->host, ens->dev, pc, fp64, X, M, ldx, leaf, acc, s);
+    };
+    if (fp64) {
+      run(static_cast<double*>(out));
+      return;
+    }
+    Scratch acc(sizeof(double) * (size_t)(M * T3), s);
+    run((double*)acc.p);
+    launch_narrow_f64_f32((const double*)acc.p, M * T3, static_cast<float*>(out), s);
+  });
+}
+
 int qts_shap_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
                       const void* grad_phi, double* grad_leaf, qts_precision precision,
                       void* stream) {

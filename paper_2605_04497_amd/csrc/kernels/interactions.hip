@@ -682,6 +682,201 @@ pairs_generic_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__
   pairs_epilogue(phis, tris, ntri_r, base0, ntri, with_phi != 0, s, F, tri64, phi64);
 }
 
+// Third-order Shapley interaction indices (Theorem 1 with |S| = 3, Eq. 9-10,
+// 8 nodes), per sample, into a packed tensor: the triple of features
+// x < y < z sits at z(z-1)(z-2)/6 + y(y-1)/2 + x.
+//
+// A row of the pair table (slot 0 possibly the combined factor of a merged
+// pair of sibling leaves, as above) with factors F_j(m) = b_j + t_m c_j and
+// H0(m) = prod_{j >= 1} F_j(m), G(m) = w_m val H0(m):
+//   g_0(m) = G(m) c_0,   g_j(m) = G(m) F_0(m) r_j(m),   r_j = c_j / F_j  (j >= 1)
+//   SII_{abc} += sum_m g_a(m) r_b(m) r_c(m)   for slots a < b < c,
+// so slot 0 is never divided by.  A slot j >= 1 with b_j = o_j = 0 zeroes the
+// row, which is skipped.  One wavefront per row, lane j on slot j; for each
+// largest slot c (uniform over the wave) the lanes take the pairs a < b < c
+// from the pair table in LDS.  The sample's triples whose largest feature
+// lies in [r0, r1) accumulate in LDS in FP64 and are flushed with FP64
+// atomics into acc[M][F(F-1)(F-2)/6].
+__host__ __device__ __forceinline__ int64_t tet_row(int64_t z) { return z * (z - 1) * (z - 2) / 6; }
+
+template <typename T>
+__device__ __forceinline__ T read_lane0(T v);
+template <>
+__device__ __forceinline__ float read_lane0<float>(float v) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+}
+template <>
+__device__ __forceinline__ double read_lane0<double>(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), 0);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 0);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// LDS bytes of the triples kernel besides the tensor range, for nw waves.
+__host__ __device__ constexpr size_t triples_fixed_lds(int nw, size_t tsize, int F) {
+  return (((size_t)kPairTable * 2 + 15) & ~(size_t)15) +
+         (size_t)nw * 64 * (2 * kNodes * tsize + sizeof(int)) + (size_t)F * sizeof(float);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+triples_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
+               const SidePath* __restrict__ pside, const int32_t* __restrict__ feat,
+               const float* __restrict__ lo, const float* __restrict__ hi,
+               const T* __restrict__ bb, const T* __restrict__ cbb, int32_t np, int32_t chunk,
+               const double* __restrict__ leaf_val, const float* __restrict__ X, int64_t M,
+               int64_t ldx, int32_t F, int32_t r0, int32_t r1, double* __restrict__ acc,
+               NodeConsts<T> nc) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nw = blockDim.x >> 6;
+  const int64_t nt = tet_row(F);
+  const int64_t base0 = tet_row(r0);
+  const int64_t nt_r = tet_row(r1) - base0;
+  double* tets = reinterpret_cast<double*>(smem);  // [nt_r]
+  size_t off = ((size_t)nt_r * sizeof(double) + 15) & ~(size_t)15;  // 16-byte areas follow
+  uint16_t* ptab = reinterpret_cast<uint16_t*>(smem + off);  // [kPairTable]: b << 8 | a
+  off += ((size_t)kPairTable * 2 + 15) & ~(size_t)15;
+  T* gall = reinterpret_cast<T*>(smem + off);  // [nw][64][8]
+  off += (size_t)nw * 64 * kNodes * sizeof(T);
+  T* rall = reinterpret_cast<T*>(smem + off);  // [nw][64][8]
+  off += (size_t)nw * 64 * kNodes * sizeof(T);
+  int* fall = reinterpret_cast<int*>(smem + off);  // [nw][64] feature
+  off += (size_t)nw * 64 * sizeof(int);
+  float* xrow = reinterpret_cast<float*>(smem + off);  // [F]
+
+  const int64_t s = (int64_t)blockIdx.x % M;
+  const int ch = (int)((int64_t)blockIdx.x / M);
+  const int p0 = ch * chunk;
+  const int p1 = min(np, p0 + chunk);
+  // pair q -> (a < b) with b(b-1)/2 <= q < b(b+1)/2
+  for (int q = threadIdx.x; q < kPairTable; q += blockDim.x) {
+    int b = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)q)) * 0.5f);
+    while (b * (b - 1) / 2 > q) --b;
+    while ((b + 1) * b / 2 <= q) ++b;
+    ptab[q] = (uint16_t)((b << 8) | (q - b * (b - 1) / 2));
+  }
+  for (int i = threadIdx.x; i < F; i += blockDim.x) xrow[i] = X[s * ldx + i];
+  for (int64_t e = threadIdx.x; e < nt_r; e += blockDim.x) tets[e] = 0.0;
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  T* gw = gall + (size_t)wave * 64 * kNodes;
+  T* rw = rall + (size_t)wave * 64 * kNodes;
+  int* fw = fall + wave * 64;
+  for (int p = p0 + wave; p < p1; p += nw) {
+    const int d = pd[p];
+    if (d < 3) continue;
+    const SidePath sp = pside[p];
+    const bool merged = sp.leaf_b >= 0;
+    const double va = leaf_val[pleaf[p]];
+    const double vb = merged ? leaf_val[sp.leaf_b] : 0.0;
+    const T val = merged ? T(1) : (T)va;
+    T Fv[kNodes], r[kNodes];
+    T c = T(0);
+    bool z = false;
+    int f = 0;
+    if (lane < d) {
+      const int64_t e = (int64_t)lane * np + p;
+      const int fm = feat[e];
+      const float lov = lo[e], hiv = hi[e];
+      const T b = bb[e], cb = cbb[e];
+      f = fm & kFeatureMask;
+      const float x = xrow[f];
+      const bool miss = (fm & kMissingOkBit) != 0;
+      const bool lower = miss ? !(x < lov) : (x >= lov);
+      const bool upper = !(x >= hiv);
+      c = (lower & upper) ? cb : -b;
+      T bz;
+      if (lane == 0 && merged) {
+        // combined slot-0 factor of the merged pair, in FP64, then rounded
+        const T bm = (T)(va * sp.b_a + vb * sp.b_b);
+        const T cAm = (T)(va * sp.cb_a - vb * sp.b_b);
+        const T cBm = (T)(vb * sp.cb_b - va * sp.b_a);
+        const bool lowerB = sp.mok_b ? !(x < sp.lo_b) : (x >= sp.lo_b);
+        const bool upperB = !(x >= sp.hi_b);
+        c = (lower & upper) ? cAm : ((lowerB & upperB) ? cBm : -bm);
+        bz = bm;
+      } else {
+        z = (b == T(0)) & (c == T(0));
+        bz = z ? T(1) : b;
+      }
+#pragma unroll
+      for (int m = 0; m < kNodes; ++m) {
+        Fv[m] = fmaP(nc.t[m], c, bz);
+        r[m] = lane == 0 ? T(0) : c * rcpP(Fv[m]);
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < kNodes; ++m) {
+        Fv[m] = T(1);
+        r[m] = T(0);
+      }
+    }
+    // a factor that vanishes at every node zeroes the whole row
+    if (__any(z) || val == T(0)) continue;
+    T H0[kNodes], F0[kNodes];
+#pragma unroll
+    for (int m = 0; m < kNodes; ++m) {
+      F0[m] = read_lane0(Fv[m]);
+      H0[m] = wave_prod(lane == 0 ? T(1) : Fv[m]);
+    }
+    if (lane < d) {
+#pragma unroll
+      for (int m = 0; m < kNodes; ++m) {
+        const T G = nc.w[m] * val * H0[m];
+        gw[lane * kNodes + m] = lane == 0 ? G * c : G * F0[m] * r[m];
+        rw[lane * kNodes + m] = r[m];
+      }
+      fw[lane] = f;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int cc = 2; cc < d; ++cc) {
+      T rc[kNodes];
+      lds_load8(rw + cc * kNodes, rc);
+      const int fc = fw[cc];
+      const int npair = cc * (cc - 1) / 2;
+      for (int q = lane; q < npair; q += 64) {
+        const int e = ptab[q];
+        const int a = e & 0xFF, b = e >> 8;
+        T ga[kNodes], rb[kNodes];
+        lds_load8(gw + a * kNodes, ga);
+        lds_load8(rw + b * kNodes, rb);
+        T v = ga[0] * rb[0] * rc[0];
+#pragma unroll
+        for (int m = 1; m < kNodes; ++m) v = fmaP(ga[m] * rb[m], rc[m], v);
+        // the three features in increasing order (slot 0 of a merged row can
+        // hold any feature; the other slots are sorted)
+        const int fa = fw[a], fb = fw[b];
+        const int x0 = min(fa, fb), x1 = max(fa, fb);
+        const int zf = max(x1, fc), y = max(x0, min(x1, fc)), x = min(x0, fc);
+        if (x < y && y < zf && zf >= r0 && zf < r1)
+          lds_add(&tets[tet_row(zf) - base0 + (int64_t)y * (y - 1) / 2 + x], (double)v);
+      }
+    }
+    // the next row overwrites this wave's slot areas
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  __syncthreads();
+  for (int64_t e = threadIdx.x; e < nt_r; e += blockDim.x) {
+    const double v = tets[e];
+    if (v != 0.0) unsafeAtomicAdd(&acc[s * nt + base0 + e], v);
+  }
+}
+
+// out[i] = (float)acc[i]
+__global__ void __launch_bounds__(256)
+narrow_kernel(const double* __restrict__ acc, int64_t n, float* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (float)acc[i];
+}
+
 // Phi[s] from the FP64 accumulators: off-diagonal SII/2, diagonal
 // phi_i - sum_{k != i} Phi[i][k] (rows sum to phi).
 template <typename TO>
@@ -832,6 +1027,44 @@ void launch_pairs_generic(const HostTable& h, const DeviceTable& d, const PairCl
   }
 }
 
+template <typename T>
+void launch_triples_t(const HostTable& h, const DeviceTable& d, const PairClass& pc,
+                      const float* X, int64_t M, int64_t ldx, const double* leaf_val,
+                      double* acc, hipStream_t s) {
+  constexpr int kThreads = 256;
+  const int F = h.F;
+  if (pc.np == 0) return;
+  // enough work items for the chip when there are few samples; chunks of no
+  // fewer than 64 rows
+  const int64_t want = (2048 + M - 1) / M;
+  const int64_t n_chunks = std::max<int64_t>(1, std::min<int64_t>(want, (pc.np + 63) / 64));
+  const int chunk = (int)((pc.np + n_chunks - 1) / n_chunks);
+  const int64_t grid = M * ((pc.np + chunk - 1) / chunk);
+  if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "third-order grid too large");
+  const void* fn = (const void*)triples_kernel<T>;
+  const size_t limit = raise_lds_limit(fn);
+  const size_t fixed = triples_fixed_lds(kThreads / 64, sizeof(T), F);
+  if (fixed >= limit) fail(QTS_E_UNSUPPORTED, "n_features too large for the third-order kernel");
+  const int64_t cap = (int64_t)((limit - fixed) / sizeof(double)) - 1;  // less the alignment pad
+  // ranges of the largest feature z; z holds z(z-1)/2 triples
+  int r0 = 0;
+  while (r0 < F) {
+    int r1 = r0 + 1;
+    if (tet_row(r1) - tet_row(r0) > cap)
+      fail(QTS_E_UNSUPPORTED, "n_features too large for the third-order kernel");
+    while (r1 < F && tet_row(r1 + 1) - tet_row(r0) <= cap) ++r1;
+    const size_t lds =
+        fixed + (((size_t)(tet_row(r1) - tet_row(r0)) * sizeof(double) + 15) & ~(size_t)15);
+    hipLaunchKernelGGL((triples_kernel<T>), dim3((unsigned)grid), dim3(kThreads), lds, s,
+                       d.pr_d + pc.pbase, d.pr_leaf + pc.pbase, d.pr_side + pc.pbase,
+                       d.pr_feat + pc.base, d.pr_lo + pc.base, d.pr_hi + pc.base,
+                       table_b<T>(d) + pc.base, table_cb<T>(d) + pc.base, pc.np, chunk, leaf_val,
+                       X, M, ldx, F, r0, r1, acc, node_consts<T>(d));
+    check_hip(hipGetLastError(), "triples_kernel launch");
+    r0 = r1;
+  }
+}
+
 }  // namespace
 
 void launch_pairs(const HostTable& h, const DeviceTable& d, const PairClass& pc, bool fp64,
@@ -888,6 +1121,20 @@ void launch_pairs(const HostTable& h, const DeviceTable& d, const PairClass& pc,
     case 32: return launch_pairs_fast<double, 32, 2, false, 8, 4>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
     default: return launch_pairs_generic<double>(h, d, pc, X, M, ldx, lv, tri64, phi64, sh, s);
   }
+}
+
+void launch_triples(const HostTable& h, const DeviceTable& d, const PairClass& pc, bool fp64,
+                    const float* X, int64_t M, int64_t ldx, const double* lv, double* acc,
+                    hipStream_t s) {
+  if (fp64) launch_triples_t<double>(h, d, pc, X, M, ldx, lv, acc, s);
+  else launch_triples_t<float>(h, d, pc, X, M, ldx, lv, acc, s);
+}
+
+void launch_narrow_f64_f32(const double* acc, int64_t n, float* out, hipStream_t s) {
+  if (n <= 0) return;
+  const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(narrow_kernel, dim3(grid), dim3(256), 0, s, acc, n, out);
+  check_hip(hipGetLastError(), "narrow_kernel launch");
 }
 
 void launch_pairs_finalize(const double* tri64, const double* phi64, int64_t M, int F, bool fp64,

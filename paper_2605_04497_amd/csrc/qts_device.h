@@ -229,6 +229,12 @@ void launch_pairs(const HostTable& h, const DeviceTable& d, const PairClass& pc,
                   const float* X, int64_t M, int64_t ldx, const double* leaf_val, double* tri64,
                   double* phi64, const PairShape& shape, bool nodes_exact, hipStream_t s);
 // Phi[M][F][F] (and phi[M][F] when non-null) in FP32 or FP64 from the accumulators.
+// Third-order indices of one capacity class added into acc[M][F(F-1)(F-2)/6]
+// (FP64, zeroed by the caller); acc cast to float32.
+void launch_triples(const HostTable& h, const DeviceTable& d, const PairClass& pc, bool fp64,
+                    const float* X, int64_t M, int64_t ldx, const double* lv, double* acc,
+                    hipStream_t s);
+void launch_narrow_f64_f32(const double* acc, int64_t n, float* out, hipStream_t s);
 void launch_pairs_finalize(const double* tri64, const double* phi64, int64_t M, int F, bool fp64,
                            void* Phi, void* phi, hipStream_t s);
 
