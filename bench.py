@@ -267,6 +267,62 @@ def measure_adjoint(args, torch, q, synth, oracle, dev):
     return out
 
 
+def path_unique_counts(ens):
+    """Unique features of every root-to-leaf path of a synthetic ensemble."""
+    out = []
+    for t in range(ens.n_trees):
+        a = int(ens.tree_offsets[t])
+        stack = [(0, frozenset())]
+        while stack:
+            node, fs = stack.pop()
+            g = a + node
+            if ens.left[g] < 0:
+                out.append(len(fs))
+                continue
+            fs = fs | {int(ens.feature[g])}
+            stack.append((int(ens.left[g]), fs))
+            stack.append((int(ens.right[g]), fs))
+    return out
+
+
+def measure_third_order(args, torch, q, synth, oracle, dev):
+    """Third-order Shapley interaction indices (Theorem 1 with |S| = 3) on the
+    adjoint workload's ensemble (200 full depth-6 trees, 50 features: 19,600
+    feature triples per sample), 2000 samples, FP32 and FP64."""
+    import math
+    wl = synth.make_workload("c4_adjoint")
+    ens = wl.ensemble
+    e = q.Ensemble(ens, device=dev)
+    M = 2000
+    X = torch.from_numpy(wl.X[:M]).to(dev)
+    F = e.n_features
+    T3 = F * (F - 1) * (F - 2) // 6
+    triples = sum(math.comb(d, 3) for d in path_unique_counts(ens))
+    res = {}
+    for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+        out = torch.empty((M, T3), dtype=dt, device=dev)
+        res[prec] = time_steps(lambda: e.shap_interactions3(X, prec, out=out), 5, 1, torch)
+        del out
+    rows = np.array([0, M - 1])
+    want = oracle.shap_sii3(ens, wl.X[rows], n=8)
+    got = e.triples_dense(e.shap_interactions3(X[torch.from_numpy(rows).to(dev)], "fp32"),
+                          F).double().cpu().numpy()
+    err = float((np.abs(got - want).reshape(2, -1).max(1)
+                 / np.abs(want).reshape(2, -1).max(1)).max())
+    t32 = res["fp32"]["ms_per_step"] * 1e-3
+    out = {"workload": "third order on the c4_adjoint ensemble: 200 full depth-6 trees (12,800 "
+                       "leaves), 50 features, first 2000 samples; packed [M, 19600] output",
+           "samples": M, "triples_per_sample": triples,
+           "value": M * e.n_leaves / t32, "unit": "paths/s",
+           "ms_per_step": res["fp32"]["ms_per_step"],
+           "fp64_ms_per_step": res["fp64"]["ms_per_step"],
+           "triple_updates_per_s": M * triples / t32,
+           "max_rel_err_fp32": err, "rows_checked": 2,
+           "launch": "eager (one launch per capacity class)"}
+    e.close()
+    return out
+
+
 def measure_deep(args, torch, q, synth, oracle, dev):
     """Deep trees (100 grown trees of depth 32, leaf cap 512, 64 features, 10k
     samples): values and interactions, FP32 error against the 8-node FP64
@@ -551,7 +607,8 @@ def main():
     }
     if not args.no_extras:
         legs = [("interactions", measure_interactions), ("adjoint", measure_adjoint),
-                ("deep", measure_deep), ("small", measure_small)]
+                ("deep", measure_deep), ("small", measure_small),
+                ("third_order", measure_third_order)]
         if args.full_interactions:
             legs.append(("interactions_full", measure_interactions_full))
         for key, fn in legs:

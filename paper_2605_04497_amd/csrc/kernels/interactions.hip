@@ -713,18 +713,20 @@ __device__ __forceinline__ double read_lane0<double>(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// LDS bytes of the triples kernel besides the tensor range, for nw waves.
-__host__ __device__ constexpr size_t triples_fixed_lds(int nw, size_t tsize, int F) {
+// LDS bytes of the triples kernel besides the tensor range, for nw waves
+// whose slot areas hold `cap` slots (the class capacity).
+__host__ __device__ constexpr size_t triples_fixed_lds(int nw, int cap, size_t tsize, int F) {
   return (((size_t)kPairTable * 2 + 15) & ~(size_t)15) +
-         (size_t)nw * 64 * (2 * kNodes * tsize + sizeof(int)) + (size_t)F * sizeof(float);
+         (size_t)nw * cap * (2 * kNodes * tsize + sizeof(int)) + (size_t)F * sizeof(float);
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 triples_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
                const SidePath* __restrict__ pside, const int32_t* __restrict__ feat,
                const float* __restrict__ lo, const float* __restrict__ hi,
-               const T* __restrict__ bb, const T* __restrict__ cbb, int32_t np, int32_t chunk,
+               const T* __restrict__ bb, const T* __restrict__ cbb, int32_t np, int32_t cap,
+               int32_t chunk,
                const double* __restrict__ leaf_val, const float* __restrict__ X, int64_t M,
                int64_t ldx, int32_t F, int32_t r0, int32_t r1, double* __restrict__ acc,
                NodeConsts<T> nc) {
@@ -737,12 +739,12 @@ triples_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf
   size_t off = ((size_t)nt_r * sizeof(double) + 15) & ~(size_t)15;  // 16-byte areas follow
   uint16_t* ptab = reinterpret_cast<uint16_t*>(smem + off);  // [kPairTable]: b << 8 | a
   off += ((size_t)kPairTable * 2 + 15) & ~(size_t)15;
-  T* gall = reinterpret_cast<T*>(smem + off);  // [nw][64][8]
-  off += (size_t)nw * 64 * kNodes * sizeof(T);
-  T* rall = reinterpret_cast<T*>(smem + off);  // [nw][64][8]
-  off += (size_t)nw * 64 * kNodes * sizeof(T);
-  int* fall = reinterpret_cast<int*>(smem + off);  // [nw][64] feature
-  off += (size_t)nw * 64 * sizeof(int);
+  T* gall = reinterpret_cast<T*>(smem + off);  // [nw][cap][8]
+  off += (size_t)nw * cap * kNodes * sizeof(T);
+  T* rall = reinterpret_cast<T*>(smem + off);  // [nw][cap][8]
+  off += (size_t)nw * cap * kNodes * sizeof(T);
+  int* fall = reinterpret_cast<int*>(smem + off);  // [nw][cap] feature
+  off += (size_t)nw * cap * sizeof(int);
   float* xrow = reinterpret_cast<float*>(smem + off);  // [F]
 
   const int64_t s = (int64_t)blockIdx.x % M;
@@ -762,11 +764,11 @@ triples_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  T* gw = gall + (size_t)wave * 64 * kNodes;
-  T* rw = rall + (size_t)wave * 64 * kNodes;
-  int* fw = fall + wave * 64;
+  T* gw = gall + (size_t)wave * cap * kNodes;
+  T* rw = rall + (size_t)wave * cap * kNodes;
+  int* fw = fall + wave * cap;
   for (int p = p0 + wave; p < p1; p += nw) {
-    const int d = pd[p];
+    const int d = pd[p];  // <= cap
     if (d < 3) continue;
     const SidePath sp = pside[p];
     const bool merged = sp.leaf_b >= 0;
@@ -1031,9 +1033,10 @@ template <typename T>
 void launch_triples_t(const HostTable& h, const DeviceTable& d, const PairClass& pc,
                       const float* X, int64_t M, int64_t ldx, const double* leaf_val,
                       double* acc, hipStream_t s) {
-  constexpr int kThreads = 256;
   const int F = h.F;
   if (pc.np == 0) return;
+  // slot areas sized by the class capacity: short classes take more waves
+  const int threads = pc.cap <= 16 ? 1024 : pc.cap <= 32 ? 512 : 256;
   // enough work items for the chip when there are few samples; chunks of no
   // fewer than 64 rows
   const int64_t want = (2048 + M - 1) / M;
@@ -1043,7 +1046,7 @@ void launch_triples_t(const HostTable& h, const DeviceTable& d, const PairClass&
   if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "third-order grid too large");
   const void* fn = (const void*)triples_kernel<T>;
   const size_t limit = raise_lds_limit(fn);
-  const size_t fixed = triples_fixed_lds(kThreads / 64, sizeof(T), F);
+  const size_t fixed = triples_fixed_lds(threads / 64, pc.cap, sizeof(T), F);
   if (fixed >= limit) fail(QTS_E_UNSUPPORTED, "n_features too large for the third-order kernel");
   const int64_t cap = (int64_t)((limit - fixed) / sizeof(double)) - 1;  // less the alignment pad
   // ranges of the largest feature z; z holds z(z-1)/2 triples
@@ -1055,10 +1058,11 @@ void launch_triples_t(const HostTable& h, const DeviceTable& d, const PairClass&
     while (r1 < F && tet_row(r1 + 1) - tet_row(r0) <= cap) ++r1;
     const size_t lds =
         fixed + (((size_t)(tet_row(r1) - tet_row(r0)) * sizeof(double) + 15) & ~(size_t)15);
-    hipLaunchKernelGGL((triples_kernel<T>), dim3((unsigned)grid), dim3(kThreads), lds, s,
+    hipLaunchKernelGGL((triples_kernel<T>), dim3((unsigned)grid), dim3(threads), lds, s,
                        d.pr_d + pc.pbase, d.pr_leaf + pc.pbase, d.pr_side + pc.pbase,
                        d.pr_feat + pc.base, d.pr_lo + pc.base, d.pr_hi + pc.base,
-                       table_b<T>(d) + pc.base, table_cb<T>(d) + pc.base, pc.np, chunk, leaf_val,
+                       table_b<T>(d) + pc.base, table_cb<T>(d) + pc.base, pc.np, pc.cap, chunk,
+                       leaf_val,
                        X, M, ldx, F, r0, r1, acc, node_consts<T>(d));
     check_hip(hipGetLastError(), "triples_kernel launch");
     r0 = r1;
