@@ -716,7 +716,7 @@ __device__ __forceinline__ double read_lane0<double>(double v) {
 // LDS bytes of the triples kernel besides the tensor range, for nw waves
 // whose slot areas hold `cap` slots (the class capacity).
 __host__ __device__ constexpr size_t triples_fixed_lds(int nw, int cap, size_t tsize, int F) {
-  return (((size_t)kPairTable * 2 + 15) & ~(size_t)15) +
+  return (((size_t)cap * (cap - 1) + 15) & ~(size_t)15) +
          (size_t)nw * cap * (2 * kNodes * tsize + sizeof(int)) + (size_t)F * sizeof(float);
 }
 
@@ -737,8 +737,10 @@ triples_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf
   const int64_t nt_r = tet_row(r1) - base0;
   double* tets = reinterpret_cast<double*>(smem);  // [nt_r]
   size_t off = ((size_t)nt_r * sizeof(double) + 15) & ~(size_t)15;  // 16-byte areas follow
-  uint16_t* ptab = reinterpret_cast<uint16_t*>(smem + off);  // [kPairTable]: b << 8 | a
-  off += ((size_t)kPairTable * 2 + 15) & ~(size_t)15;
+  // pairs of slots below the class capacity: cap(cap-1)/2 of them
+  const int npt = cap * (cap - 1) / 2;
+  uint16_t* ptab = reinterpret_cast<uint16_t*>(smem + off);  // [npt]: b << 8 | a
+  off += ((size_t)npt * 2 + 15) & ~(size_t)15;
   T* gall = reinterpret_cast<T*>(smem + off);  // [nw][cap][8]
   off += (size_t)nw * cap * kNodes * sizeof(T);
   T* rall = reinterpret_cast<T*>(smem + off);  // [nw][cap][8]
@@ -752,7 +754,7 @@ triples_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf
   const int p0 = ch * chunk;
   const int p1 = min(np, p0 + chunk);
   // pair q -> (a < b) with b(b-1)/2 <= q < b(b+1)/2
-  for (int q = threadIdx.x; q < kPairTable; q += blockDim.x) {
+  for (int q = threadIdx.x; q < npt; q += blockDim.x) {
     int b = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)q)) * 0.5f);
     while (b * (b - 1) / 2 > q) --b;
     while ((b + 1) * b / 2 <= q) ++b;
@@ -1035,8 +1037,19 @@ void launch_triples_t(const HostTable& h, const DeviceTable& d, const PairClass&
                       double* acc, hipStream_t s) {
   const int F = h.F;
   if (pc.np == 0) return;
-  // slot areas sized by the class capacity: short classes take more waves
-  const int threads = pc.cap <= 16 ? 1024 : pc.cap <= 32 ? 512 : 256;
+  // slot areas sized by the class capacity: short classes take more waves,
+  // but eight rather than sixteen where that lets the whole tensor fit in one
+  // range (each range walks every row again; four waves measured slower than
+  // two ranges)
+  const size_t limit0 = raise_lds_limit((const void*)triples_kernel<T>);
+  int threads = pc.cap <= 16 ? 1024 : pc.cap <= 32 ? 512 : 256;
+  for (int t = threads; t >= 512; t /= 2) {
+    const size_t fx = triples_fixed_lds(t / 64, pc.cap, sizeof(T), F);
+    if (fx < limit0 && tet_row(F) <= (int64_t)((limit0 - fx) / sizeof(double)) - 1) {
+      threads = t;
+      break;
+    }
+  }
   // enough work items for the chip when there are few samples; chunks of no
   // fewer than 64 rows
   const int64_t want = (2048 + M - 1) / M;
