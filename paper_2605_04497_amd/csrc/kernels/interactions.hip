@@ -873,6 +873,120 @@ triples_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf
   }
 }
 
+// Lane-per-row form of triples_kernel for the short classes (capacity C <= 8):
+// lane = row (slot-major table: a wave's 64 rows load coalesced), the row's
+// factors and ratios in registers, its C(C,3) triples unrolled, with the same
+// H0 form and the same LDS tensor range and flush.
+template <typename T, int C>
+__global__ void __launch_bounds__(512)
+triples_lane_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
+                    const SidePath* __restrict__ pside, const int32_t* __restrict__ feat,
+                    const float* __restrict__ lo, const float* __restrict__ hi,
+                    const T* __restrict__ bb, const T* __restrict__ cbb, int32_t np,
+                    int32_t chunk, const double* __restrict__ leaf_val, const float* __restrict__ X,
+                    int64_t M, int64_t ldx, int32_t F, int32_t r0, int32_t r1,
+                    double* __restrict__ acc, NodeConsts<T> nc) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t nt = tet_row(F);
+  const int64_t base0 = tet_row(r0);
+  const int64_t nt_r = tet_row(r1) - base0;
+  double* tets = reinterpret_cast<double*>(smem);  // [nt_r]
+  float* xrow = reinterpret_cast<float*>(smem + (((size_t)nt_r * sizeof(double) + 15) & ~(size_t)15));
+
+  const int64_t s = (int64_t)blockIdx.x % M;
+  const int ch = (int)((int64_t)blockIdx.x / M);
+  const int p0 = ch * chunk;
+  const int p1 = min(np, p0 + chunk);
+  for (int i = threadIdx.x; i < F; i += blockDim.x) xrow[i] = X[s * ldx + i];
+  for (int64_t e = threadIdx.x; e < nt_r; e += blockDim.x) tets[e] = 0.0;
+  __syncthreads();
+
+  for (int p = p0 + (int)threadIdx.x; p < p1; p += blockDim.x) {
+    const int d = pd[p];
+    if (d < 3) continue;
+    const SidePath sp = pside[p];
+    const bool merged = sp.leaf_b >= 0;
+    const double va = leaf_val[pleaf[p]];
+    const double vb = merged ? leaf_val[sp.leaf_b] : 0.0;
+    const T val = merged ? T(1) : (T)va;
+    int f[C];
+    T cj[C], bj[C];
+    bool dead = false;
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int64_t e = (int64_t)j * np + p;
+      const int fm = feat[e];
+      const T b = bb[e];
+      f[j] = fm & kFeatureMask;
+      const float x = xrow[f[j]];
+      const bool miss = (fm & kMissingOkBit) != 0;
+      const bool lower = miss ? !(x < lo[e]) : (x >= lo[e]);
+      const bool upper = !(x >= hi[e]);
+      T c = (lower & upper) ? cbb[e] : -b;
+      if (j == 0 && merged) {
+        const T bm = (T)(va * sp.b_a + vb * sp.b_b);
+        const T cAm = (T)(va * sp.cb_a - vb * sp.b_b);
+        const T cBm = (T)(vb * sp.cb_b - va * sp.b_a);
+        const bool lowerB = sp.mok_b ? !(x < sp.lo_b) : (x >= sp.lo_b);
+        const bool upperB = !(x >= sp.hi_b);
+        cj[0] = (lower & upper) ? cAm : ((lowerB & upperB) ? cBm : -bm);
+        bj[0] = bm;
+      } else {
+        // inert slots (j >= d) hold b = 1, c = 0: a factor of 1
+        const bool z = (b == T(0)) & (c == T(0));
+        dead |= z;
+        cj[j] = c;
+        bj[j] = z ? T(1) : b;
+      }
+    }
+    if (dead || val == T(0)) continue;
+    T GF[kNodes], G[kNodes], r[C][kNodes];
+#pragma unroll
+    for (int m = 0; m < kNodes; ++m) {
+      T h = T(1);
+#pragma unroll
+      for (int j = 1; j < C; ++j) {
+        const T Fv = fmaP(nc.t[m], cj[j], bj[j]);
+        h *= Fv;
+        r[j][m] = cj[j] * rcpP(Fv);
+      }
+      G[m] = nc.w[m] * val * h;
+      GF[m] = G[m] * fmaP(nc.t[m], cj[0], bj[0]);
+    }
+#pragma unroll
+    for (int c = 2; c < C; ++c) {
+      if (c < d) {
+#pragma unroll
+        for (int b = 1; b < c; ++b) {
+#pragma unroll
+          for (int a = 0; a < b; ++a) {
+            T v;
+            if (a == 0) {
+              T t = G[0] * r[b][0] * r[c][0];
+#pragma unroll
+              for (int m = 1; m < kNodes; ++m) t = fmaP(G[m] * r[b][m], r[c][m], t);
+              v = cj[0] * t;
+            } else {
+              v = GF[0] * r[a][0] * r[b][0] * r[c][0];
+#pragma unroll
+              for (int m = 1; m < kNodes; ++m) v = fmaP(GF[m] * r[a][m] * r[b][m], r[c][m], v);
+            }
+            const int x0 = min(f[a], f[b]), x1 = max(f[a], f[b]);
+            const int zf = max(x1, f[c]), y = max(x0, min(x1, f[c])), x = min(x0, f[c]);
+            if (x < y && y < zf && zf >= r0 && zf < r1)
+              lds_add(&tets[tet_row(zf) - base0 + (int64_t)y * (y - 1) / 2 + x], (double)v);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int64_t e = threadIdx.x; e < nt_r; e += blockDim.x) {
+    const double v = tets[e];
+    if (v != 0.0) unsafeAtomicAdd(&acc[s * nt + base0 + e], v);
+  }
+}
+
 // out[i] = (float)acc[i]
 __global__ void __launch_bounds__(256)
 narrow_kernel(const double* __restrict__ acc, int64_t n, float* __restrict__ out) {
@@ -1031,12 +1145,49 @@ void launch_pairs_generic(const HostTable& h, const DeviceTable& d, const PairCl
   }
 }
 
+template <typename T, int C>
+void launch_triples_lane(const HostTable& h, const DeviceTable& d, const PairClass& pc,
+                         const float* X, int64_t M, int64_t ldx, const double* leaf_val,
+                         double* acc, hipStream_t s) {
+  constexpr int kThreads = 512;
+  const int F = h.F;
+  const int64_t want = (2048 + M - 1) / M;
+  const int64_t n_chunks = std::max<int64_t>(1, std::min<int64_t>(want, (pc.np + 511) / 512));
+  const int chunk = (int)((pc.np + n_chunks - 1) / n_chunks);
+  const int64_t grid = M * ((pc.np + chunk - 1) / chunk);
+  if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "third-order grid too large");
+  const void* fn = (const void*)triples_lane_kernel<T, C>;
+  const size_t limit = raise_lds_limit(fn);
+  const size_t fixed = (size_t)F * sizeof(float) + 16;  // the sample row and the alignment pad
+  if (fixed >= limit) fail(QTS_E_UNSUPPORTED, "n_features too large for the third-order kernel");
+  const int64_t cap = (int64_t)((limit - fixed) / sizeof(double));
+  int r0 = 0;
+  while (r0 < F) {
+    int r1 = r0 + 1;
+    if (tet_row(r1) - tet_row(r0) > cap)
+      fail(QTS_E_UNSUPPORTED, "n_features too large for the third-order kernel");
+    while (r1 < F && tet_row(r1 + 1) - tet_row(r0) <= cap) ++r1;
+    const size_t lds =
+        fixed + (((size_t)(tet_row(r1) - tet_row(r0)) * sizeof(double) + 15) & ~(size_t)15);
+    hipLaunchKernelGGL((triples_lane_kernel<T, C>), dim3((unsigned)grid), dim3(kThreads), lds, s,
+                       d.pr_d + pc.pbase, d.pr_leaf + pc.pbase, d.pr_side + pc.pbase,
+                       d.pr_feat + pc.base, d.pr_lo + pc.base, d.pr_hi + pc.base,
+                       table_b<T>(d) + pc.base, table_cb<T>(d) + pc.base, pc.np, chunk, leaf_val,
+                       X, M, ldx, F, r0, r1, acc, node_consts<T>(d));
+    check_hip(hipGetLastError(), "triples_lane_kernel launch");
+    r0 = r1;
+  }
+}
+
 template <typename T>
 void launch_triples_t(const HostTable& h, const DeviceTable& d, const PairClass& pc,
                       const float* X, int64_t M, int64_t ldx, const double* leaf_val,
                       double* acc, hipStream_t s) {
   const int F = h.F;
   if (pc.np == 0) return;
+  // short classes: one lane per row
+  if (pc.cap == 4) return launch_triples_lane<T, 4>(h, d, pc, X, M, ldx, leaf_val, acc, s);
+  if (pc.cap == 8) return launch_triples_lane<T, 8>(h, d, pc, X, M, ldx, leaf_val, acc, s);
   // slot areas sized by the class capacity: short classes take more waves,
   // but eight rather than sixteen where that lets the whole tensor fit in one
   // range (each range walks every row again; four waves measured slower than
