@@ -43,7 +43,7 @@ LDS_F64_ATOMIC_RATE = 2.45 * 256 * 2.4e9
 # profiles/values_kernel_c2_values.md.  Valid only for the kernel source they
 # were measured on (its SHA-256 prefix); otherwise traffic is reported as null.
 TRAFFIC = {"kernel_source": "paper_2605_04497_amd/csrc/kernels/values.hip",
-           "sha256_16": "10bd085e780ca08e", "fetch_bytes": 1.2559e+09, "write_bytes": 1.6800e+09,
+           "sha256_16": "10bd085e780ca08e", "fetch_bytes": 1.2566e+09, "write_bytes": 1.6800e+09,
            "shape": [8, 32768]}
 
 
