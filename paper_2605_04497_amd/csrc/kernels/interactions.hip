@@ -1,5 +1,6 @@
 // Pairwise Shapley interaction indices (Theorem 1 with |S| = 2, Eq. 9-10,
-// 8 nodes) and first-order values, per sample.
+// 8 nodes) and first-order values, per sample; third-order indices (|S| = 3)
+// on the same row table further below (triples_lane_kernel, triples_kernel).
 //
 // For a path P with unique features j, factors F_j(m) = b_j + t_m c_j
 // (c_j = o_j - b_j), H(m) = prod_j F_j(m):
