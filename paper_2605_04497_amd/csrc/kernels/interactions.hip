@@ -840,9 +840,12 @@ triples_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (int cc = 2; cc < d; ++cc) {
+      const int fc = fw[cc];
+      // slots of an unmerged row are sorted by feature: the triples below
+      // slot cc all have fc as their largest feature
+      if (!merged && (fc < r0 || fc >= r1)) continue;
       T rc[kNodes];
       lds_load8(rw + cc * kNodes, rc);
-      const int fc = fw[cc];
       const int npair = cc * (cc - 1) / 2;
       for (int q = lane; q < npair; q += 64) {
         const int e = ptab[q];
@@ -956,7 +959,9 @@ triples_lane_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ 
     }
 #pragma unroll
     for (int c = 2; c < C; ++c) {
-      if (c < d) {
+      // an unmerged row's slots are sorted: f[c] is the largest feature of
+      // every triple below slot c
+      if (c < d && (merged || (f[c] >= r0 && f[c] < r1))) {
 #pragma unroll
         for (int b = 1; b < c; ++b) {
 #pragma unroll
