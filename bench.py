@@ -60,6 +60,35 @@ def measured_traffic(shape):
     return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
 FLOPS_PER_ELEMENT = 51  # per (sample, path, unique feature): 8 nodes x 6 + 3
 
+# Executed flops per call of the other legs' kernels: SQ_INSTS_VALU_FLOPS_FP32
+# (or _FP64) x 64 summed over one call's dispatches, from rocprofv3 --pmc runs
+# of `bench.py --only <leg>` (profiles/ holds the commands and counts).  Valid
+# only for the kernel sources they were measured on (SHA-256 prefix over the
+# kernel files); otherwise the executed figures are reported as null.
+KERNEL_SOURCES = ("paper_2605_04497_amd/csrc/kernels/values.hip",
+                  "paper_2605_04497_amd/csrc/kernels/interactions.hip")
+EXECUTED_FLOPS_SHA = None
+EXECUTED_FLOPS = {}  # (leg, precision) -> flops per call
+
+
+def kernel_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def executed(leg, precision, seconds):
+    """(TFLOP/s, fraction of the published peak of the precision) of one call
+    of a leg from its counter-measured flops, or (None, None)."""
+    fl = EXECUTED_FLOPS.get((leg, precision))
+    if fl is None or EXECUTED_FLOPS_SHA != kernel_sources_sha():
+        return None, None
+    tf = fl / seconds / 1e12
+    return tf, tf / (PEAK_FP32_PACKED_TFLOPS if precision == "fp32" else PEAK_VALU_TFLOPS)
+
 
 def shared_kernel_flops(rows, elements, shared):
     """FP32 flops (FMA = 2) per sample of the first-order kernel for rows of at
@@ -100,14 +129,18 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the interactions and adjoint measurements")
     ap.add_argument("--pair-samples", type=int, default=1024)
-    ap.add_argument("--full-interactions", action="store_true",
-                    help="also time one interactions call on all 50k samples (8 GB output)")
+    ap.add_argument("--no-full-interactions", action="store_true",
+                    help="skip the interactions calls on all 50k samples (8 GB FP32 output)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes")
     ap.add_argument("--no-merge", action="store_true",
                     help="first-order calls walk every leaf's path (no sibling merging)")
     ap.add_argument("--eager", action="store_true",
                     help="launch eagerly instead of replaying a captured HIP graph")
+    ap.add_argument("--only", default=None,
+                    choices=["interactions", "interactions_full", "adjoint", "deep", "small",
+                             "third_order"],
+                    help="run one leg alone and print its JSON (profiling aid)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MB (a "
                          "known-size reference for the memory counters)")
@@ -208,7 +241,8 @@ def measure_interactions(args, torch, q, synth, oracle, dev):
     _, Phi_o = oracle.shap_interactions(ens, wl.X[:2], n=8)
     err = float((np.abs(Phi - Phi_o).reshape(2, -1).max(1)
                  / np.abs(Phi_o).reshape(2, -1).max(1)).max())
-    ach = flops / (res["fp32"]["kernel_ms"] * 1e-3) / 1e12
+    tf32, fr32 = executed("interactions", "fp32", res["fp32"]["kernel_ms"] * 1e-3)
+    tf64, fr64 = executed("interactions", "fp64", res["fp64"]["kernel_ms"] * 1e-3)
     lds_rate = pairs / (res["fp32"]["kernel_ms"] * 1e-3)
     out = {"workload": "c3_interactions: 500 grown trees, depths 3..20, leaf cap 4096, 200 "
                        "features; first %d of the 50k explained samples" % M,
@@ -218,7 +252,8 @@ def measure_interactions(args, torch, q, synth, oracle, dev):
            "ms_per_step": res["fp32"]["ms_per_step"], "kernel_ms": res["fp32"]["kernel_ms"],
            "fp64_ms_per_step": res["fp64"]["ms_per_step"],
            "max_rel_err_fp32": err, "rows_checked": 2,
-           "alu_tflops": ach, "frac_of_valu_peak": ach / PEAK_VALU_TFLOPS,
+           "executed_tflops_fp32": tf32, "frac_of_fp32_peak": fr32,
+           "executed_tflops_fp64": tf64, "frac_of_fp64_peak": fr64,
            "pair_updates_per_s": lds_rate,
            "frac_of_lds_f64_atomic_rate": lds_rate / LDS_F64_ATOMIC_RATE,
            "fp64_kernel_ms": res["fp64"]["kernel_ms"],
@@ -251,18 +286,18 @@ def measure_adjoint(args, torch, q, synth, oracle, dev):
     got = e.shap_backward(X[torch.from_numpy(rows).to(dev)], G32[torch.from_numpy(rows).to(dev)],
                           "fp32").cpu().numpy()
     err = float(np.abs(got - want).max() / np.abs(want).max())
-    flops = FLOPS_PER_ELEMENT * float(M) * e.info["n_elements"]
-    ach = flops / (res["fp32"]["kernel_ms"] * 1e-3) / 1e12
+    tf32, fr32 = executed("adjoint", "fp32", res["fp32"]["kernel_ms"] * 1e-3)
+    tf64, fr64 = executed("adjoint", "fp64", res["fp64"]["kernel_ms"] * 1e-3)
     out = {"workload": "c4_adjoint: 200 full depth-6 trees (12,800 leaves), 50 features, "
                        "20k samples, grad of ||phi - target||^2",
            "value": M * e.n_leaves / (res["fp32"]["ms_per_step"] * 1e-3), "unit": "paths/s",
            "ms_per_step": res["fp32"]["ms_per_step"], "kernel_ms": res["fp32"]["kernel_ms"],
            "fp64_ms_per_step": res["fp64"]["ms_per_step"],
            "max_rel_err_fp32": err, "rows_checked": int(len(rows)),
-           "method_tflops": ach, "method_frac_of_valu_peak": ach / PEAK_VALU_TFLOPS,
-           "method_note": "51 flops per (sample, element) of the unmerged table: the "
-                          "per-path method's count; the kernel merges siblings and reuses "
-                          "shared slots, so it runs fewer"}
+           "kernel_rows": int(e.info["n_value_paths"]),
+           "executed_tflops_fp32": tf32, "frac_of_fp32_peak": fr32,
+           "executed_tflops_fp64": tf64, "frac_of_fp64_peak": fr64,
+           "flops_source": "SQ_INSTS_VALU_FLOPS x 64 per call (profiles/)"}
     e.close()
     return out
 
@@ -345,25 +380,32 @@ def measure_deep(args, torch, q, synth, oracle, dev):
         Phi = torch.empty((M, F, F), dtype=dt, device=dev)
         ri = time_steps(lambda: e.shap_interactions(X, prec, out=Phi), 2, 1, torch, "interactions")
         e.set_graph_replay(False)
-        # method flops: 51 per (sample, element) of the first-order table (the
-        # batched kernels of rows over 8 features run about that many; the
-        # <= 8 bucket, 0.5% of this workload's elements, runs fewer), and the
-        # pair count of the interactions table as in the interactions leg
-        vflops = FLOPS_PER_ELEMENT * float(M) * float(e.info["n_value_elements"])
-        N, E, U = (float(e.info[k]) for k in ("n_pair_rows", "n_pair_elements",
-                                              "n_pair_updates"))
-        pflops = float(M) * 8.0 * (2.0 * U + 7.0 * E - N)
         vt = r["kernel_ms"] * 1e-3
         pt = ri["kernel_ms"] * 1e-3
-        peak = PEAK_VALU_TFLOPS
+        vtf, vfr = executed("deep_values", prec, vt)
+        ptf, pfr = executed("deep_interactions", prec, pt)
         out["values_" + prec] = {"value": M * e.n_leaves / (r["ms_per_step"] * 1e-3),
-                                 "ms_per_step": r["ms_per_step"],
-                                 "method_tflops": vflops / vt / 1e12,
-                                 "method_frac_of_valu_peak": vflops / vt / 1e12 / peak}
+                                 "ms_per_step": r["ms_per_step"], "kernel_ms": r["kernel_ms"],
+                                 "executed_tflops": vtf, "frac_of_peak": vfr}
         out["interactions_" + prec] = {"value": M * e.n_leaves / (ri["ms_per_step"] * 1e-3),
                                        "ms_per_step": ri["ms_per_step"],
-                                       "alu_tflops": pflops / pt / 1e12,
-                                       "frac_of_valu_peak": pflops / pt / 1e12 / peak}
+                                       "kernel_ms": ri["kernel_ms"],
+                                       "executed_tflops": ptf, "frac_of_peak": pfr}
+        # third order on 200 of the samples (F = 64: 41,664 triples per sample)
+        T3 = F * (F - 1) * (F - 2) // 6
+        M3 = 200
+        o3 = torch.empty((M3, T3), dtype=dt, device=dev)
+        r3 = time_steps(lambda: e.shap_interactions3(X[:M3], prec, out=o3), 2, 1, torch)
+        out["third_order_" + prec] = {"samples": M3, "ms_per_step": r3["ms_per_step"],
+                                      "value": M3 * e.n_leaves / (r3["ms_per_step"] * 1e-3)}
+        if prec == "fp32":
+            rows3 = np.array([0, M3 - 1])
+            want3 = oracle.shap_sii3(ens, wl.X[rows3], n=8)
+            got3 = e.triples_dense(o3[torch.from_numpy(rows3).to(dev)], F).double().cpu().numpy()
+            out["third_order_fp32"]["max_rel_err"] = float(
+                (np.abs(got3 - want3).reshape(2, -1).max(1)
+                 / np.abs(want3).reshape(2, -1).max(1)).max())
+        del o3
         if prec == "fp32":
             rows = np.arange(0, M, M // 8)[:8]
             phi_o = oracle.shap_values(ens, wl.X[rows], n=8)
@@ -414,28 +456,60 @@ def measure_small(args, torch, q, synth, oracle, dev):
 
 
 def measure_interactions_full(args, torch, q, synth, oracle, dev):
-    """All 50k explained samples of the interactions workload, FP32: one
-    warm-up call and one timed call (Phi is 8.0 GB)."""
+    """The interactions workload at its stated size: all 50k explained samples
+    of the 500-tree, 200-feature ensemble, Phi[50k, 200, 200] in FP32 (8.0 GB)
+    and FP64 (16 GB), under HIP graph replay into reused output buffers.  The
+    error is taken on rows spread over the sample blocks against the 8-node
+    FP64 oracle, which runs on the host cores while the GPU is timed."""
+    import threading
     wl = synth.make_workload("c3_interactions")
-    e = q.Ensemble(wl.ensemble, device=dev)
+    ens = wl.ensemble
+    M, F = wl.X.shape[0], ens.n_features
+    rows = np.array([0, M // 3, (2 * M) // 3, M - 1])
+    ref = {}
+    th = threading.Thread(target=lambda: ref.update(
+        r=oracle.shap_interactions(ens, wl.X[rows], n=8)), daemon=True)
+    th.start()
+    e = q.Ensemble(ens, device=dev)
     X = torch.from_numpy(wl.X).to(dev)
-    M, F = X.shape[0], e.n_features
-    if not args.no_autotune:
-        e.autotune(1024, "fp32")
-    e.set_graph_replay(not args.eager)
-    Phi = torch.empty((M, F, F), dtype=torch.float32, device=dev)
-    r = time_steps(lambda: e.shap_interactions(X, "fp32", out=Phi), 1, 1, torch, "interactions")
-    rows = np.array([0, M // 2, M - 1])
-    _, Phi_o = oracle.shap_interactions(wl.ensemble, wl.X[rows], n=8)
-    G = Phi[torch.from_numpy(rows).to(dev)].double().cpu().numpy()
-    err = float((np.abs(G - Phi_o).reshape(3, -1).max(1)
-                 / np.abs(Phi_o).reshape(3, -1).max(1)).max())
-    e.set_graph_replay(False)
-    del Phi
+    U = float(e.info["n_pair_updates"])
+    res, got = {}, {}
+    for prec, dt, steps in (("fp32", torch.float32, 2), ("fp64", torch.float64, 1)):
+        if not args.no_autotune:
+            e.autotune(1024, prec)
+        e.set_graph_replay(not args.eager)
+        Phi = torch.empty((M, F, F), dtype=dt, device=dev)
+        res[prec] = time_steps(lambda: e.shap_interactions(X, prec, out=Phi), steps, 1, torch,
+                               "interactions")
+        got[prec] = Phi[torch.from_numpy(rows).to(dev)].double().cpu().numpy()
+        e.set_graph_replay(False)
+        del Phi
+        torch.cuda.empty_cache()
+        log("interactions 50k %s: %.1f ms per call" % (prec, res[prec]["ms_per_step"]))
+    th.join()
+    _, Phi_o = ref["r"]
+
+    def rel(g):
+        return float((np.abs(g - Phi_o).reshape(len(rows), -1).max(1)
+                      / np.abs(Phi_o).reshape(len(rows), -1).max(1)).max())
+    t32 = res["fp32"]["kernel_ms"] * 1e-3
+    out = {"workload": "c3_interactions at its stated size: 500 grown trees, depths 3..20, "
+                       "leaf cap 4096, 200 features, all 50,000 explained samples; "
+                       "Phi[50000, 200, 200]",
+           "samples": M, "leaves": e.n_leaves,
+           "value": M * e.n_leaves / (res["fp32"]["ms_per_step"] * 1e-3), "unit": "paths/s",
+           "ms_per_call": res["fp32"]["ms_per_step"], "kernel_ms": res["fp32"]["kernel_ms"],
+           "fp64_ms_per_call": res["fp64"]["ms_per_step"],
+           "fp64_value": M * e.n_leaves / (res["fp64"]["ms_per_step"] * 1e-3),
+           "speedup_fp32_over_fp64": res["fp64"]["ms_per_step"] / res["fp32"]["ms_per_step"],
+           "pair_updates_per_sample": int(U),
+           "pair_updates_per_s": M * U / t32,
+           "frac_of_lds_f64_atomic_rate": M * U / t32 / LDS_F64_ATOMIC_RATE,
+           "max_rel_err_fp32": rel(got["fp32"]), "max_rel_err_fp64": rel(got["fp64"]),
+           "rows_checked": [int(r) for r in rows],
+           "launch": "hipGraph replay" if not args.eager else "eager"}
     e.close()
-    return {"workload": "c3_interactions, all 50k samples, FP32", "samples": M,
-            "ms_per_call": r["ms_per_step"], "value": M * e.n_leaves / (r["ms_per_step"] * 1e-3),
-            "unit": "paths/s", "max_rel_err_fp32": err, "rows_checked": 3}
+    return out
 
 
 def main():
@@ -449,6 +523,16 @@ def main():
     import paper_2605_04497_amd as q
     import synth
     from oracle import oracle
+
+    if args.only:
+        dev = torch.device("cuda:0")
+        torch.cuda.set_device(dev)
+        fn = {"interactions": measure_interactions, "interactions_full": measure_interactions_full,
+              "adjoint": measure_adjoint, "deep": measure_deep, "small": measure_small,
+              "third_order": measure_third_order}[args.only]
+        print(json.dumps({"leg": args.only, "result": fn(args, torch, q, synth, oracle, dev)}),
+              flush=True)
+        return
 
     over = {}
     if args.samples:
@@ -585,31 +669,35 @@ def main():
         "fp64": {"value": units / (r64["ms_per_step"] * 1e-3), "ms_per_step": r64["ms_per_step"],
                  "kernel_ms": r64["kernel_ms"], "dtype": "f64",
                  "speedup_fp32_over_fp64": r64["ms_per_step"] / r32["ms_per_step"]},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_PACKED_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_PACKED_TFLOPS,
                      "traffic": measured_traffic(e.launch_shape("values", "fp32", 0)),
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
                      "flops_per_launch": kernel_flops,
-                     "flops_model": "per (sample, row) of d features with s reused slots: "
-                                    "224 + 16 d - 16 s (8 nodes, FMA = 2 flops)",
+                     "flops_model": "executed FP32 flops per (sample, row) of d features with s "
+                                    "reused slots: 224 + 16 d - 16 s (8 nodes, FMA = 2 flops); "
+                                    "matches SQ_INSTS_VALU_FLOPS_FP32 x 64",
                      "rows": n_rows, "elements_per_sample": n_vel,
                      "shared_slots_per_sample": n_shared,
-                     "method_flops_per_launch": flops,
-                     "method_flops_model": "51 per (sample, element): the per-path method "
-                                          "without reuse",
-                     "method_frac": flops / (r32["kernel_ms"] * 1e-3) / 1e12 / PEAK_VALU_TFLOPS,
+                     "peak_note": "published MI355X FP32 vector peak, which needs packed "
+                                  "two-wide FP32 instructions; this build is compiled without "
+                                  "them, so its issue ceiling is the non-packed one",
+                     "nonpacked_issue_ceiling": PEAK_VALU_TFLOPS,
+                     "frac_of_nonpacked_issue_ceiling": achieved / PEAK_VALU_TFLOPS,
                      "kernel": "values_kernel<float, 8, 8, true, 8>", "kernel_ms": r32["kernel_ms"],
                      "kernel_ms_scope": "event pair around each graph replay (zero-fill, "
                                         "values kernel, cast)" if not args.eager else
                                         "event pair around the values kernel launches",
-                     "peak_fp32_packed": PEAK_FP32_PACKED_TFLOPS,
-                     "frac_of_packed_peak": achieved / PEAK_FP32_PACKED_TFLOPS},
+                     "method_flops_per_launch": flops,
+                     "method_flops_note": "51 flops per (sample, element) of the rows walked, "
+                                          "without the slot reuse: a work count, not a "
+                                          "roofline figure"},
     }
     if not args.no_extras:
         legs = [("interactions", measure_interactions), ("adjoint", measure_adjoint),
                 ("deep", measure_deep), ("small", measure_small),
                 ("third_order", measure_third_order)]
-        if args.full_interactions:
+        if not args.no_full_interactions:
             legs.append(("interactions_full", measure_interactions_full))
         for key, fn in legs:
             try:

@@ -57,8 +57,9 @@ enum {
   QTS_E_INVALID_ARG = -1,   /* null pointer, negative size, ldx < n_features, ... */
   QTS_E_INVALID_MODEL = -2, /* child out of range, cycle, one-child node, feature >= F,
                                negative or NaN cover, NaN threshold */
-  QTS_E_UNSUPPORTED = -3,   /* tree deeper than 128, path with > 64 unique features,
-                               n_features too large for this entry point */
+  QTS_E_UNSUPPORTED = -3,   /* tree deeper than 128, path with > 64 unique features;
+                               qts_shap_interactions3 also when one feature's
+                               triples do not fit in LDS (F above about 170) */
   QTS_E_HIP = -4,           /* a HIP runtime error; its text is in qts_last_error() */
   QTS_E_OOM = -5            /* host or device allocation failed */
 };
@@ -95,10 +96,35 @@ int qts_load_ensemble(const qts_tree_arrays* trees, int32_t n_features, double b
 int qts_build_host(const qts_tree_arrays* trees, int32_t n_features, double base_score,
                    qts_ensemble** out);
 
+/* Multi-output ensembles: each tree adds to the output of one group (for
+ * example one group per class of a multiclass model; the XGBoost entry points
+ * the paper's implementation serves, section 1, return attributions per
+ * output).  The game of group g is the sum over its own trees of the
+ * path-dependent games of Eq. 3, so each group's Shapley values and
+ * interaction indices are those of its sub-ensemble.
+ *   tree_group   [n_trees] group of each tree in [0, n_groups) (NULL: all in
+ *                group 0); a group outside that range is QTS_E_INVALID_MODEL
+ *   base_scores  [n_groups] bias of each group (host memory)
+ * The compute calls then return one block per group inside each sample row:
+ * phi [M, n_groups, F], Phi [M, n_groups, F, F], third-order
+ * [M, n_groups, F(F-1)(F-2)/6], and take grad_phi as [M, n_groups, F];
+ * grad_leaf keeps its length and order.  qts_load_ensemble and qts_build_host
+ * are these calls with one group (n_groups = 1: the shapes below). */
+int qts_load_ensemble_grouped(const qts_tree_arrays* trees, const int32_t* tree_group,
+                              int32_t n_groups, int32_t n_features, const double* base_scores,
+                              void* stream, qts_ensemble** out);
+int qts_build_host_grouped(const qts_tree_arrays* trees, const int32_t* tree_group,
+                           int32_t n_groups, int32_t n_features, const double* base_scores,
+                           qts_ensemble** out);
+
 int qts_free_ensemble(qts_ensemble* ens);
 
-/* sum over trees of E_T[f] = v(empty set) (Eq. 1, Eq. 3) plus base_score, FP64. */
+/* sum over trees of E_T[f] = v(empty set) (Eq. 1, Eq. 3) plus base_score, FP64
+ * (with output groups: group 0's). */
 int qts_expected_value(const qts_ensemble* ens, double* out);
+
+/* The same per output group: out[n_groups]. */
+int qts_expected_values(const qts_ensemble* ens, double* out);
 
 /* Number of leaves = length of grad_leaf and of a leaf_values override, in
  * tree-major, node-id order. */
@@ -126,6 +152,11 @@ typedef struct {
                                 slots after slot 0 equal to the previous row's,
                                 summed (their factors are reused, not re-evaluated) */
   int64_t n_path_shared;     /* the same for the unmerged table */
+  int64_t n_value_segments;  /* work segments of the merged first-order table when
+                                the sample tile of all features does not fit in
+                                LDS (more than 210 features): consecutive rows
+                                using at most 96 distinct features; 0 otherwise */
+  int32_t n_groups;          /* output groups (1 unless loaded grouped) */
 } qts_info;
 
 int qts_get_info(const qts_ensemble* ens, qts_info* out);
@@ -149,14 +180,16 @@ int qts_gauss_legendre(int32_t n, double* t, double* one_minus_t, double* weight
  *   X            [M, ldx] float32 device rows (ldx >= F); NaN = missing.
  *   leaf_values  NULL, or [n_leaves] FP64 device array replacing the model's leaf
  *                values (phi is linear in them; used by the autograd wrapper).
- *   phi          [M, F] device output: float32 for QTS_FP32, double for QTS_FP64.
+ *   phi          [M, F] device output: float32 for QTS_FP32, double for QTS_FP64
+ *                ([M, n_groups, F] for a grouped ensemble).
  * QTS_FP32 evaluates the quadrature in FP32 and accumulates across paths and
  * trees in FP64; QTS_FP64 does everything in FP64.  M = 0 is a no-op. */
 int qts_shap_values(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
                     const double* leaf_values, void* phi, qts_precision precision,
                     void* stream);
 
-/* Pairwise interaction matrices Phi[M, F, F] (and optionally phi[M, F]) with the
+/* Pairwise interaction matrices Phi[M, F, F] (and optionally phi[M, F]; with
+ * output groups [M, n_groups, F, F] and [M, n_groups, F]) with the
  * convention above.  Pair indices are the |S|=2 case of Theorem 1 and Eq. 9.
  * Output types follow `precision` as for qts_shap_values; phi may be NULL. */
 int qts_shap_interactions(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
@@ -187,7 +220,8 @@ int qts_shap_interactions3(const qts_ensemble* ens, const float* X, int64_t M, i
  * in val(v) (Eq. 1, Eq. 10), so
  *   grad_leaf[v] = sum_s sum_{j on path(v)} grad_phi[s, f_j] (o_j - b_j)
  *                  * sum_m w_m prod_{k != j} (b_k (1 - t_m) + o_k t_m).
- *   grad_phi   [M, F] device array, float32 for QTS_FP32, double for QTS_FP64.
+ *   grad_phi   [M, F] device array, float32 for QTS_FP32, double for QTS_FP64
+ *              ([M, n_groups, F] for a grouped ensemble).
  *   grad_leaf  [n_leaves] FP64 device output (overwritten). */
 int qts_shap_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
                       const void* grad_phi, double* grad_leaf, qts_precision precision,
@@ -256,7 +290,8 @@ int qts_set_node_policy(qts_ensemble* ens, int32_t policy);
  * key.  A graph owns its FP64 accumulators, so a replay allocates nothing.
  * The graphs contain kernel nodes only (zeroing is a kernel, not a memset).
  * At most 16 graphs are kept (least recently used evicted, after waiting for
- * its stream).  The caller keeps the keyed buffers alive and at the same size
+ * its last launch on an event of the library's own, so the caller's stream
+ * may be destroyed while its graphs stay cached).  The caller keeps the keyed buffers alive and at the same size
  * while their graph may replay; disabling drops every graph.  Calls of one
  * ensemble are serialised by the cache. */
 int qts_set_graph_replay(qts_ensemble* ens, int32_t enable);

@@ -43,7 +43,8 @@ class Info(ctypes.Structure):
                 ("n_value_paths", ctypes.c_int64), ("n_value_elements", ctypes.c_int64),
                 ("n_pair_rows", ctypes.c_int64), ("n_pair_elements", ctypes.c_int64),
                 ("n_pair_updates", ctypes.c_int64), ("n_value_shared", ctypes.c_int64),
-                ("n_path_shared", ctypes.c_int64)]
+                ("n_path_shared", ctypes.c_int64), ("n_value_segments", ctypes.c_int64),
+                ("n_groups", ctypes.c_int32)]
 
 
 # exported symbol -> (restype, argtypes)
@@ -52,7 +53,12 @@ SIGNATURES = {
                                          ctypes.c_double, P, ctypes.POINTER(P)]),
     "qts_build_host": (ctypes.c_int, [ctypes.POINTER(TreeArrays), ctypes.c_int32,
                                       ctypes.c_double, ctypes.POINTER(P)]),
+    "qts_load_ensemble_grouped": (ctypes.c_int, [ctypes.POINTER(TreeArrays), P, ctypes.c_int32,
+                                                 ctypes.c_int32, P, P, ctypes.POINTER(P)]),
+    "qts_build_host_grouped": (ctypes.c_int, [ctypes.POINTER(TreeArrays), P, ctypes.c_int32,
+                                              ctypes.c_int32, P, ctypes.POINTER(P)]),
     "qts_free_ensemble": (ctypes.c_int, [P]),
+    "qts_expected_values": (ctypes.c_int, [P, P]),
     "qts_expected_value": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double)]),
     "qts_num_leaves": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int64)]),
     "qts_get_info": (ctypes.c_int, [P, ctypes.POINTER(Info)]),

@@ -115,12 +115,31 @@ class Ensemble:
             X = X.contiguous()
         return X, X.shape[0], X.stride(0)
 
-    def _leaf(self, leaf_values):
+    @staticmethod
+    def _out(t, shape, dtype, device, what):
+        """Check a caller-supplied output buffer before any library call: the
+        kernels write through its raw device pointer, so a wrong size, type,
+        layout or device must be rejected here."""
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("%s must be a torch tensor" % what)
+        if t.device != device:
+            raise ValueError("%s is on %s, X is on %s" % (what, t.device, device))
+        if t.dtype != dtype:
+            raise TypeError("%s must be %s for this precision, got %s" % (what, dtype, t.dtype))
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError("%s must have shape %s, got %s" % (what, tuple(shape),
+                                                                tuple(t.shape)))
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % what)
+        return t
+
+    def _leaf(self, leaf_values, device):
         if leaf_values is None:
             return None
-        if (leaf_values.dtype != torch.float64 or leaf_values.device.type != "cuda"
-                or leaf_values.numel() != self.n_leaves):
-            raise TypeError("leaf_values must be a float64 device tensor of n_leaves values")
+        if (not isinstance(leaf_values, torch.Tensor) or leaf_values.dtype != torch.float64
+                or leaf_values.device != device or leaf_values.numel() != self.n_leaves):
+            raise TypeError("leaf_values must be a float64 tensor of n_leaves values on the "
+                            "device of X")
         return leaf_values.contiguous()
 
     # ---------------------------------------------------------------- compute
@@ -128,9 +147,12 @@ class Ensemble:
                     out=None) -> torch.Tensor:
         """phi[M, F]; float32 for 'fp32', float64 for 'fp64'."""
         X, M, ldx = self._rows(X)
-        lv = self._leaf(leaf_values)
+        lv = self._leaf(leaf_values, X.device)
+        shape = (M, self.n_features)
         if out is None:
-            out = torch.empty((M, self.n_features), dtype=_DTYPE[precision], device=X.device)
+            out = torch.empty(shape, dtype=_DTYPE[precision], device=X.device)
+        else:
+            self._out(out, shape, _DTYPE[precision], X.device, "out")
         L.check(L.lib().qts_shap_values(self._h, _ptr(X), M, ldx, _ptr(lv), _ptr(out),
                                         _PREC[precision], _stream_ptr(X.device)))
         return out
@@ -139,14 +161,21 @@ class Ensemble:
                           with_phi: bool = False, out=None, out_phi=None):
         """Phi[M, F, F] (and phi[M, F] when with_phi)."""
         X, M, ldx = self._rows(X)
-        lv = self._leaf(leaf_values)
+        lv = self._leaf(leaf_values, X.device)
         F = self.n_features
-        Phi = out if out is not None else torch.empty((M, F, F), dtype=_DTYPE[precision],
-                                                      device=X.device)
+        dt = _DTYPE[precision]
+        if out is not None:
+            Phi = self._out(out, (M, F, F), dt, X.device, "out")
+        else:
+            Phi = torch.empty((M, F, F), dtype=dt, device=X.device)
         phi = None
         if with_phi:
-            phi = out_phi if out_phi is not None else torch.empty(
-                (M, F), dtype=_DTYPE[precision], device=X.device)
+            if out_phi is not None:
+                phi = self._out(out_phi, (M, F), dt, X.device, "out_phi")
+            else:
+                phi = torch.empty((M, F), dtype=dt, device=X.device)
+        elif out_phi is not None:
+            raise ValueError("out_phi is given but with_phi is False")
         L.check(L.lib().qts_shap_interactions(self._h, _ptr(X), M, ldx, _ptr(lv), _ptr(phi),
                                               _ptr(Phi), _PREC[precision],
                                               _stream_ptr(X.device)))
@@ -162,9 +191,9 @@ class Ensemble:
         dt = _DTYPE[precision]
         if out is None:
             out = torch.empty((M, T3), dtype=dt, device=X.device)
-        elif out.dtype != dt or tuple(out.shape) != (M, T3) or not out.is_contiguous():
-            raise ValueError("out must be a contiguous [M, F(F-1)(F-2)/6] tensor of the output type")
-        lv = self._leaf(leaf_values)
+        else:
+            self._out(out, (M, T3), dt, X.device, "out")
+        lv = self._leaf(leaf_values, X.device)
         L.check(L.lib().qts_shap_interactions3(self._h, _ptr(X), M, ldx, _ptr(lv), _ptr(out),
                                                _PREC[precision], _stream_ptr(X.device)))
         return out
@@ -187,11 +216,17 @@ class Ensemble:
                       precision: str = "fp32", out=None) -> torch.Tensor:
         """grad_leaf[n_leaves] (float64) = J^T grad_phi."""
         X, M, ldx = self._rows(X)
-        g = grad_phi.to(_DTYPE[precision]).contiguous()
-        if tuple(g.shape) != (M, self.n_features):
+        if not isinstance(grad_phi, torch.Tensor):
+            raise TypeError("grad_phi must be a torch tensor")
+        if grad_phi.device != X.device:
+            raise ValueError("grad_phi is on %s, X is on %s" % (grad_phi.device, X.device))
+        if tuple(grad_phi.shape) != (M, self.n_features):
             raise ValueError("grad_phi must be [M, F]")
+        g = grad_phi.to(_DTYPE[precision]).contiguous()
         if out is None:
             out = torch.empty(self.n_leaves, dtype=torch.float64, device=X.device)
+        else:
+            self._out(out, (self.n_leaves,), torch.float64, X.device, "out")
         L.check(L.lib().qts_shap_backward(self._h, _ptr(X), M, ldx, _ptr(g), _ptr(out),
                                           _PREC[precision], _stream_ptr(X.device)))
         return out

@@ -39,6 +39,7 @@ struct GraphEntry {
   GraphKey key;
   hipGraphExec_t exec = nullptr;
   void* scratch = nullptr;  // the call's FP64 accumulators, owned by this graph
+  hipEvent_t done = nullptr;  // recorded after each launch of the graph
   uint64_t stamp = 0;
 };
 
@@ -132,10 +133,12 @@ std::vector<T> narrow(const std::vector<double>& v) {
 void upload_paths(const std::vector<PathHdr>& hdr_in, const std::vector<int32_t>& feat_in,
                   const std::vector<float>& lo_in, const std::vector<float>& hi_in,
                   const std::vector<double>& b_in, const std::vector<double>& cb_in,
-                  hipStream_t s, PathHdr** o_hdr, int32_t** o_feat, float** o_lo, float** o_hi,
-                  float** o_b32, float** o_cb32, double** o_b64, double** o_cb64) {
+                  const CompactTable& ct, hipStream_t s, PathHdr** o_hdr, int32_t** o_feat,
+                  float** o_lo, float** o_hi, float** o_b32, float** o_cb32, double** o_b64,
+                  double** o_cb64, int32_t** o_lfeat, Segment** o_segs, int32_t** o_seg_feat) {
   std::vector<PathHdr> hdr = hdr_in;
-  std::vector<int32_t> feat;
+  const bool wide = !ct.segs.empty();
+  std::vector<int32_t> feat, lfeat;
   std::vector<float> lo, hi;
   std::vector<double> b64, cb64;
   size_t n_pad = 0;
@@ -153,6 +156,7 @@ void upload_paths(const std::vector<PathHdr>& hdr_in, const std::vector<int32_t>
       const bool real = k < p.d;
       const size_t e = (size_t)p.off + (size_t)k;
       feat.push_back(real ? feat_in[e] : kMissingOkBit);
+      if (wide) lfeat.push_back(real ? ct.lfeat[e] : kMissingOkBit);
       lo.push_back(real ? lo_in[e] : -INFINITY);
       hi.push_back(real ? hi_in[e] : NAN);
       b64.push_back(real ? b_in[e] : 1.0);
@@ -161,6 +165,7 @@ void upload_paths(const std::vector<PathHdr>& hdr_in, const std::vector<int32_t>
   }
   if (feat.size() > (size_t)0x7fffffff) fail(QTS_E_UNSUPPORTED, "path table too large");
   feat = padded(feat, (int32_t)kMissingOkBit);
+  if (wide) lfeat = padded(lfeat, (int32_t)kMissingOkBit);
   lo = padded(lo, -INFINITY);
   hi = padded(hi, NAN);
   b64 = padded(b64, 1.0);
@@ -174,6 +179,11 @@ void upload_paths(const std::vector<PathHdr>& hdr_in, const std::vector<int32_t>
   *o_cb32 = upload(cb32, s);
   *o_b64 = upload(b64, s);
   *o_cb64 = upload(cb64, s);
+  if (wide) {
+    *o_lfeat = upload(lfeat, s);
+    *o_segs = upload(ct.segs, s);
+    *o_seg_feat = upload(ct.seg_feat, s);
+  }
   check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
@@ -182,7 +192,8 @@ void free_device(DeviceTable& d) {
                   d.b64,    d.cb64,    d.leaf_val, d.pr_d,   d.pr_leaf, d.pr_feat,
                   d.pr_lo,  d.pr_hi,   d.pr_b32,  d.pr_cb32, d.pr_b64,  d.pr_cb64,
                   d.mhdr,   d.mfeat,   d.mlo,     d.mhi,     d.mb32,    d.mcb32,
-                  d.mb64,   d.mcb64,   d.side,    d.pr_side, d.share,   d.mshare};
+                  d.mb64,   d.mcb64,   d.side,    d.pr_side, d.share,   d.mshare,
+                  d.lfeat,  d.segs,    d.seg_feat, d.mlfeat, d.msegs,  d.mseg_feat};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   d = DeviceTable{};
@@ -339,22 +350,28 @@ size_t slot0_region(const qts_ensemble* ens, bool fp64) {
 bool direct_call(const qts_ensemble* ens, int64_t M, bool fp64) {
   const HostTable& h = ens->host;
   const std::vector<Bucket>& bks = ens->merge_siblings ? h.mbuckets : h.buckets;
-  if (bks.size() != 1) return false;
+  // segmented (wide feature space) tables split every sample block; with
+  // several outputs each group has buckets of its own
+  if (bks.size() != 1 || wide_features(h.F) || h.n_groups != 1) return false;
   return values_direct(bks, M,
                        ens->vshape[pol_index(ens)][fp64 ? 1 : 0][cap_index(bks[0].dmax)]);
 }
+// Output elements per sample: K groups of F features.
+int64_t out_row(const qts_ensemble* ens) { return (int64_t)ens->host.n_groups * ens->host.F; }
+
 size_t values_scratch_bytes(const qts_ensemble* ens, int64_t M, bool fp64) {
   const bool acc = !fp64 && !direct_call(ens, M, fp64);
-  return slot0_region(ens, fp64) + (acc ? sizeof(double) * (size_t)(M * ens->host.F) : 0);
+  return slot0_region(ens, fp64) + (acc ? sizeof(double) * (size_t)(M * out_row(ens)) : 0);
 }
 
 void issue_values(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
                   const double* leaf, void* phi, bool fp64, void* scratch, Lanes& ln,
                   bool timed) {
   const HostTable& h = ens->host;
-  const int64_t n = M * h.F;
+  const int64_t n = M * out_row(ens);
   void* slot0 = scratch;
-  const PathArrays arr = ens->merge_siblings ? merged_arrays(ens->dev) : plain_arrays(ens->dev);
+  const PathArrays arr = ens->merge_siblings ? merged_arrays(ens->dev, ens->host)
+                                             : plain_arrays(ens->dev, ens->host);
   const std::vector<Bucket>& bks = ens->merge_siblings ? h.mbuckets : h.buckets;
   launch_slot0(arr, value_rows(ens), leaf, fp64, slot0, ln.main);
   if (direct_call(ens, M, fp64)) {
@@ -386,9 +403,10 @@ void issue_interactions(const qts_ensemble* ens, const float* X, int64_t M, int6
   const HostTable& h = ens->host;
   const int64_t F = h.F;
   const int64_t ntri = F * (F - 1) / 2;
+  const int64_t MK = M * h.n_groups;  // output rows: (sample, group)
   double* tri64 = acc;
-  double* phi64 = tri64 + M * ntri;
-  launch_fill_zero(tri64, M * ntri + M * F, ln.main);
+  double* phi64 = tri64 + MK * ntri;
+  launch_fill_zero(tri64, MK * ntri + MK * F, ln.main);
   TimedScope ts(1, timed ? ln.main : nullptr, timed);
   ln.fork((int)ens->pair_classes.size());
   for (size_t i = 0; i < ens->pair_classes.size(); ++i)
@@ -397,7 +415,7 @@ void issue_interactions(const qts_ensemble* ens, const float* X, int64_t M, int6
                  ln.pick((int)i));
   ln.join();
   ts.done();
-  launch_pairs_finalize(tri64, phi64, M, (int)F, fp64, Phi, phi, ln.main);
+  launch_pairs_finalize(tri64, phi64, MK, (int)F, fp64, Phi, phi, ln.main);
 }
 
 void issue_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
@@ -407,7 +425,8 @@ void issue_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_t 
   if (M == 0) return;
   TimedScope ts(2, timed ? ln.main : nullptr, timed);
   const std::vector<Bucket>& bks = ens->merge_siblings ? h.mbuckets : h.buckets;
-  const PathArrays arr = ens->merge_siblings ? merged_arrays(ens->dev) : plain_arrays(ens->dev);
+  const PathArrays arr = ens->merge_siblings ? merged_arrays(ens->dev, ens->host)
+                                             : plain_arrays(ens->dev, ens->host);
   ln.fork((int)bks.size());
   for (size_t i = 0; i < bks.size(); ++i) {
     const Bucket& bk = bks[i];
@@ -420,12 +439,17 @@ void issue_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_t 
 }
 
 void destroy_entry(GraphEntry& e) {
-  // the graph may still run on its stream: wait before releasing it
-  (void)hipStreamSynchronize(e.key.stream);
+  // the graph may still run: wait for its last launch (an event of the
+  // library's own, so the caller's stream need not outlive the cache)
+  if (e.done) {
+    (void)hipEventSynchronize(e.done);
+    (void)hipEventDestroy(e.done);
+  }
   if (e.exec) (void)hipGraphExecDestroy(e.exec);
   if (e.scratch) (void)hipFree(e.scratch);
   e.exec = nullptr;
   e.scratch = nullptr;
+  e.done = nullptr;
 }
 
 void clear_graphs(GraphCache& g) {
@@ -467,6 +491,7 @@ void run_graph(qts_ensemble* ens, const GraphKey& key, size_t scratch_bytes, int
     if (scratch_bytes) check_hip(hipMalloc(&ne.scratch, scratch_bytes), "hipMalloc");
     hipGraph_t graph = nullptr;
     try {
+      check_hip(hipEventCreateWithFlags(&ne.done, hipEventDisableTiming), "hipEventCreate");
       check_hip(hipStreamBeginCapture(g.cap, hipStreamCaptureModeRelaxed),
                 "hipStreamBeginCapture");
       try {
@@ -485,6 +510,7 @@ void run_graph(qts_ensemble* ens, const GraphKey& key, size_t scratch_bytes, int
     } catch (...) {
       if (graph) (void)hipGraphDestroy(graph);
       if (ne.scratch) (void)hipFree(ne.scratch);
+      if (ne.done) (void)hipEventDestroy(ne.done);
       throw;
     }
     if (g.entries.size() >= kMaxGraphs) {
@@ -500,6 +526,7 @@ void run_graph(qts_ensemble* ens, const GraphKey& key, size_t scratch_bytes, int
   hit->stamp = ++g.clock;
   TimedScope ts(kind, key.stream, true);
   check_hip(hipGraphLaunch(hit->exec, key.stream), "hipGraphLaunch");
+  check_hip(hipEventRecord(hit->done, key.stream), "hipEventRecord");
   ts.done();
 }
 
@@ -519,14 +546,15 @@ using namespace qts;
 
 extern "C" {
 
-int qts_build_host(const qts_tree_arrays* trees, int32_t n_features, double base_score,
-                   qts_ensemble** out) {
+int qts_build_host_grouped(const qts_tree_arrays* trees, const int32_t* tree_group,
+                           int32_t n_groups, int32_t n_features, const double* base_scores,
+                           qts_ensemble** out) {
   return guarded([&] {
-    if (!trees || !out) fail(QTS_E_INVALID_ARG, "null argument");
+    if (!trees || !out || !base_scores) fail(QTS_E_INVALID_ARG, "null argument");
     *out = nullptr;
     qts_ensemble* e = new qts_ensemble();
     try {
-      e->host = build_host_table(*trees, n_features, base_score);
+      e->host = build_host_table(*trees, n_features, n_groups, tree_group, base_scores);
     } catch (...) {
       delete e;
       throw;
@@ -535,23 +563,30 @@ int qts_build_host(const qts_tree_arrays* trees, int32_t n_features, double base
   });
 }
 
-int qts_load_ensemble(const qts_tree_arrays* trees, int32_t n_features, double base_score,
-                      void* stream, qts_ensemble** out) {
+int qts_build_host(const qts_tree_arrays* trees, int32_t n_features, double base_score,
+                   qts_ensemble** out) {
+  return qts_build_host_grouped(trees, nullptr, 1, n_features, &base_score, out);
+}
+
+int qts_load_ensemble_grouped(const qts_tree_arrays* trees, const int32_t* tree_group,
+                              int32_t n_groups, int32_t n_features, const double* base_scores,
+                              void* stream, qts_ensemble** out) {
   return guarded([&] {
-    if (!trees || !out) fail(QTS_E_INVALID_ARG, "null argument");
+    if (!trees || !out || !base_scores) fail(QTS_E_INVALID_ARG, "null argument");
     *out = nullptr;
     qts_ensemble* e = new qts_ensemble();
     try {
-      e->host = build_host_table(*trees, n_features, base_score);
+      e->host = build_host_table(*trees, n_features, n_groups, tree_group, base_scores);
       const HostTable& h = e->host;
       hipStream_t s = (hipStream_t)stream;
       DeviceTable& d = e->dev;
       check_hip(hipGetDevice(&d.device), "hipGetDevice");
       build_nodes(d);
-      upload_paths(h.hdr, h.feat, h.lo, h.hi, h.b, h.cb, s, &d.hdr, &d.feat, &d.lo, &d.hi,
-                   &d.b32, &d.cb32, &d.b64, &d.cb64);
-      upload_paths(h.mhdr, h.mfeat, h.mlo, h.mhi, h.mb, h.mcb, s, &d.mhdr, &d.mfeat, &d.mlo,
-                   &d.mhi, &d.mb32, &d.mcb32, &d.mb64, &d.mcb64);
+      upload_paths(h.hdr, h.feat, h.lo, h.hi, h.b, h.cb, h.compact, s, &d.hdr, &d.feat, &d.lo,
+                   &d.hi, &d.b32, &d.cb32, &d.b64, &d.cb64, &d.lfeat, &d.segs, &d.seg_feat);
+      upload_paths(h.mhdr, h.mfeat, h.mlo, h.mhi, h.mb, h.mcb, h.mcompact, s, &d.mhdr, &d.mfeat,
+                   &d.mlo, &d.mhi, &d.mb32, &d.mcb32, &d.mb64, &d.mcb64, &d.mlfeat, &d.msegs,
+                   &d.mseg_feat);
       d.side = upload(h.side, s);
       d.share = upload(h.share, s);
       d.mshare = upload(h.mshare, s);
@@ -589,6 +624,11 @@ int qts_load_ensemble(const qts_tree_arrays* trees, int32_t n_features, double b
   });
 }
 
+int qts_load_ensemble(const qts_tree_arrays* trees, int32_t n_features, double base_score,
+                      void* stream, qts_ensemble** out) {
+  return qts_load_ensemble_grouped(trees, nullptr, 1, n_features, &base_score, stream, out);
+}
+
 int qts_free_ensemble(qts_ensemble* ens) {
   return guarded([&] {
     if (!ens) return;
@@ -605,6 +645,13 @@ int qts_expected_value(const qts_ensemble* ens, double* out) {
   return guarded([&] {
     if (!ens || !out) fail(QTS_E_INVALID_ARG, "null argument");
     *out = ens->host.expected;
+  });
+}
+
+int qts_expected_values(const qts_ensemble* ens, double* out) {
+  return guarded([&] {
+    if (!ens || !out) fail(QTS_E_INVALID_ARG, "null argument");
+    for (size_t g = 0; g < ens->host.expected_g.size(); ++g) out[g] = ens->host.expected_g[g];
   });
 }
 
@@ -640,6 +687,8 @@ int qts_get_info(const qts_ensemble* ens, qts_info* out) {
     for (int32_t v : h.mshare) out->n_value_shared += v;
     out->n_path_shared = 0;
     for (int32_t v : h.share) out->n_path_shared += v;
+    out->n_value_segments = (int64_t)h.mcompact.segs.size();
+    out->n_groups = h.n_groups;
   });
 }
 
@@ -715,8 +764,9 @@ int qts_shap_interactions(const qts_ensemble* ens, const float* X, int64_t M, in
     hipStream_t s = (hipStream_t)stream;
     const bool fp64 = precision == QTS_FP64;
     const int64_t F = ens->host.F;
+    const int64_t MK = M * ens->host.n_groups;
     const double* leaf = leaf_values ? leaf_values : ens->dev.leaf_val;
-    const size_t acc_bytes = sizeof(double) * (size_t)(M * (F * (F - 1) / 2) + M * F);
+    const size_t acc_bytes = sizeof(double) * (size_t)(MK * (F * (F - 1) / 2) + MK * F);
     qts_ensemble* me = const_cast<qts_ensemble*>(ens);
     if (ens->graphs.on) {
       GraphKey key{1, fp64, X, M, ldx, leaf, Phi, phi, s};
@@ -747,8 +797,9 @@ int qts_shap_interactions3(const qts_ensemble* ens, const float* X, int64_t M, i
     hipStream_t s = (hipStream_t)stream;
     const bool fp64 = precision == QTS_FP64;
     const double* leaf = leaf_values ? leaf_values : ens->dev.leaf_val;
+    const int64_t MK = M * ens->host.n_groups;
     auto run = [&](double* acc) {
-      launch_fill_zero(acc, M * T3, s);
+      launch_fill_zero(acc, MK * T3, s);
       for (const PairClass& pc : ens->pair_classes)
         launch_triples(ens->host, ens->dev, pc, fp64, X, M, ldx, leaf, acc, s);
     };
@@ -756,9 +807,9 @@ int qts_shap_interactions3(const qts_ensemble* ens, const float* X, int64_t M, i
       run(static_cast<double*>(out));
       return;
     }
-    Scratch acc(sizeof(double) * (size_t)(M * T3), s);
+    Scratch acc(sizeof(double) * (size_t)(MK * T3), s);
     run((double*)acc.p);
-    launch_narrow_f64_f32((const double*)acc.p, M * T3, static_cast<float*>(out), s);
+    launch_narrow_f64_f32((const double*)acc.p, MK * T3, static_cast<float*>(out), s);
   });
 }
 
@@ -855,6 +906,7 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
     // real count matters)
     const int64_t Mt = std::max<int64_t>(64, std::min<int64_t>(M_hint > 0 ? M_hint : 16384,
                                                                262144));
+    const int64_t K = h.n_groups;
     Scratch xs(sizeof(float) * (size_t)(Mt * F), s);
     const float* X = (const float*)xs.p;
     launch_fill_uniform((float*)xs.p, Mt * F, 0x2605u, s);
@@ -883,10 +935,10 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
 
     // first-order kernel (its shapes also serve the adjoint), per bucket
     {
-      Scratch acc(sizeof(double) * (size_t)(Mt * F), s);
-      launch_fill_zero((double*)acc.p, Mt * F, s);
+      Scratch acc(sizeof(double) * (size_t)(Mt * K * F), s);
+      launch_fill_zero((double*)acc.p, Mt * K * F, s);
       const std::vector<Bucket>& bks = ens->merge_siblings ? h.mbuckets : h.buckets;
-      const PathArrays arr = ens->merge_siblings ? merged_arrays(d) : plain_arrays(d);
+      const PathArrays arr = ens->merge_siblings ? merged_arrays(d, h) : plain_arrays(d, h);
       Scratch slot0(slot0_bytes(value_rows(ens), fp64), s);
       launch_slot0(arr, value_rows(ens), d.leaf_val, fp64, slot0.p, s);
       for (const Bucket& bk : bks) {
@@ -910,14 +962,14 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
     // adjoint kernel, per bucket, with a synthetic upstream gradient
     {
       Scratch gl(sizeof(double) * (size_t)std::max<size_t>(1, h.leaf_value.size()), s);
-      Scratch g32(sizeof(float) * (size_t)(Mt * F), s);
-      launch_fill_uniform((float*)g32.p, Mt * F, 0x4a11u, s);
-      Scratch g64(fp64 ? sizeof(double) * (size_t)(Mt * F) : 8, s);
-      if (fp64) launch_widen_f32_f64((const float*)g32.p, (double*)g64.p, Mt * F, s);
+      Scratch g32(sizeof(float) * (size_t)(Mt * K * F), s);
+      launch_fill_uniform((float*)g32.p, Mt * K * F, 0x4a11u, s);
+      Scratch g64(fp64 ? sizeof(double) * (size_t)(Mt * K * F) : 8, s);
+      if (fp64) launch_widen_f32_f64((const float*)g32.p, (double*)g64.p, Mt * K * F, s);
       const void* G = fp64 ? g64.p : g32.p;
       launch_fill_zero((double*)gl.p, (int64_t)h.leaf_value.size(), s);
       const std::vector<Bucket>& bks = ens->merge_siblings ? h.mbuckets : h.buckets;
-      const PathArrays arr = ens->merge_siblings ? merged_arrays(d) : plain_arrays(d);
+      const PathArrays arr = ens->merge_siblings ? merged_arrays(d, h) : plain_arrays(d, h);
       for (const Bucket& bk : bks) {
         ValuesShape best;
         float best_ms = 1e30f;
@@ -939,12 +991,12 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
     // interactions, per capacity class, on at most 256 of the rows (and an
     // accumulator of at most 512 MiB)
     if (!ens->pair_classes.empty() && F >= 2) {
-      const int64_t per_row = F * (F - 1) / 2 + F;
+      const int64_t per_row = K * (F * (F - 1) / 2 + F);
       const int64_t Mp = std::max<int64_t>(
           1, std::min<int64_t>({Mt, (int64_t)256, ((int64_t)512 << 20) / (8 * per_row)}));
       Scratch acc(sizeof(double) * (size_t)(Mp * per_row), s);
       double* tri64 = (double*)acc.p;
-      double* phi64 = tri64 + Mp * (F * (F - 1) / 2);
+      double* phi64 = tri64 + Mp * K * (F * (F - 1) / 2);
       launch_fill_zero(tri64, Mp * per_row, s);
       std::vector<PairShape>& out = ens->pshape[pol_index(ens)][pi];
       out.assign(ens->pair_classes.size(), PairShape{});

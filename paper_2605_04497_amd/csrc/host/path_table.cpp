@@ -43,6 +43,7 @@ struct Edge {
 struct RawPath {
   int32_t leaf;
   int32_t tree;
+  int32_t group = 0;  // output group of the tree
   int32_t parent = -1;     // parent node of the leaf (-1: the root is the leaf)
   bool left_child = false;
   std::vector<int32_t> feat;
@@ -62,7 +63,8 @@ class Builder {
  public:
   Builder(const qts_tree_arrays& t, int32_t F) : t_(t), F_(F) {}
 
-  void tree(int32_t ti) {
+  void tree(int32_t ti, int32_t group) {
+    group_ = group;
     const int64_t a = t_.tree_offsets[ti], e = t_.tree_offsets[ti + 1];
     if (e <= a) fail(QTS_E_INVALID_MODEL, "tree " + std::to_string(ti) + " has no nodes");
     if (e - a > (int64_t)std::numeric_limits<int32_t>::max())
@@ -81,7 +83,7 @@ class Builder {
 
   std::vector<RawPath> paths;
   std::vector<double> leaf_value;
-  double expected = 0.0;
+  std::vector<double> expected;  // per output group
   int32_t max_depth = 0;
   int32_t max_unique = 0;
   int64_t n_leaves_ = 0;
@@ -132,6 +134,7 @@ class Builder {
     RawPath p;
     p.leaf = leaf_ord_[(size_t)node];
     p.tree = tree_;
+    p.group = group_;
     if (!path_.empty()) {
       p.parent = path_.back().parent;
       p.left_child = path_.back().left;
@@ -165,12 +168,13 @@ class Builder {
     leaf_value[(size_t)p.leaf] = val;
     double prod = val;
     for (double bj : p.b) prod *= bj;
-    expected += prod;
+    expected[(size_t)group_] += prod;
     if (d > 0) paths.push_back(std::move(p));
   }
 
   const qts_tree_arrays& t_;
   int32_t F_;
+  int32_t group_ = 0;
   int64_t base_ = 0;
   int32_t n_ = 0;
   int32_t tree_ = 0;
@@ -210,8 +214,63 @@ static std::vector<int32_t> prefix_share(const std::vector<PathHdr>& hdr,
   return share;
 }
 
-HostTable build_host_table(const qts_tree_arrays& t, int32_t F, double base_score) {
+CompactTable build_compact(const std::vector<PathHdr>& hdr, const std::vector<int32_t>& feat,
+                           const std::vector<Bucket>& bks, int32_t F) {
+  CompactTable c;
+  c.lfeat.assign(feat.size(), 0);
+  std::vector<int32_t> local((size_t)F, -1);  // feature -> index in the open segment
+  std::vector<int32_t> open;                  // the open segment's features
+  c.bucket_seg.push_back(0);
+  for (const Bucket& bk : bks) {
+    int32_t r = bk.path_begin;
+    while (r < bk.path_end) {
+      Segment sg{r, r, (int32_t)c.seg_feat.size(), 0};
+      open.clear();
+      while (r < bk.path_end && r - sg.row_begin < kSegMaxRows) {
+        // the row joins if its new features still fit the tile
+        const PathHdr& p = hdr[(size_t)r];
+        int fresh = 0;
+        for (int k = 0; k < p.d; ++k) {
+          const int32_t f = feat[(size_t)p.off + (size_t)k] & kFeatureMask;
+          if (local[(size_t)f] < 0) {
+            local[(size_t)f] = -2;  // counted once
+            ++fresh;
+          }
+        }
+        for (int k = 0; k < p.d; ++k) {
+          const int32_t f = feat[(size_t)p.off + (size_t)k] & kFeatureMask;
+          if (local[(size_t)f] == -2) local[(size_t)f] = -1;
+        }
+        if ((int)open.size() + fresh > kSegFeatures) break;  // a row has <= 64 < kSegFeatures
+        for (int k = 0; k < p.d; ++k) {
+          const size_t e = (size_t)p.off + (size_t)k;
+          const int32_t f = feat[e] & kFeatureMask;
+          if (local[(size_t)f] < 0) {
+            local[(size_t)f] = (int32_t)open.size();
+            open.push_back(f);
+          }
+          c.lfeat[e] = local[(size_t)f] | (feat[e] & kMissingOkBit);
+        }
+        ++r;
+      }
+      sg.row_end = r;
+      sg.nfeat = (int32_t)open.size();
+      for (int32_t f : open) {
+        c.seg_feat.push_back(f);
+        local[(size_t)f] = -1;
+      }
+      c.segs.push_back(sg);
+    }
+    c.bucket_seg.push_back((int32_t)c.segs.size());
+  }
+  return c;
+}
+
+HostTable build_host_table(const qts_tree_arrays& t, int32_t F, int32_t n_groups,
+                           const int32_t* tree_group, const double* base_scores) {
   if (F < 1) fail(QTS_E_INVALID_ARG, "n_features must be >= 1");
+  if (n_groups < 1) fail(QTS_E_INVALID_ARG, "n_groups must be >= 1");
+  if (!base_scores) fail(QTS_E_INVALID_ARG, "null base scores");
   if (t.n_trees < 0) fail(QTS_E_INVALID_ARG, "n_trees must be >= 0");
   if (t.n_trees > 0 && (!t.tree_offsets || !t.left || !t.right || !t.feature || !t.threshold ||
                         !t.cover || !t.value))
@@ -219,26 +278,41 @@ HostTable build_host_table(const qts_tree_arrays& t, int32_t F, double base_scor
   if (t.n_trees > 0 && t.tree_offsets[0] != 0)
     fail(QTS_E_INVALID_MODEL, "tree_offsets[0] must be 0");
   Builder bld(t, F);
-  for (int32_t ti = 0; ti < t.n_trees; ++ti) bld.tree(ti);
+  bld.expected.assign((size_t)n_groups, 0.0);
+  std::vector<int32_t> groups((size_t)std::max(0, t.n_trees), 0);
+  for (int32_t ti = 0; ti < t.n_trees; ++ti) {
+    const int32_t g = tree_group ? tree_group[ti] : 0;
+    if (g < 0 || g >= n_groups)
+      fail(QTS_E_INVALID_MODEL, "tree " + std::to_string(ti) + ": output group out of range");
+    groups[(size_t)ti] = g;
+    bld.tree(ti, g);
+  }
   if (bld.n_leaves_ > (int64_t)std::numeric_limits<int32_t>::max() / 2)
     fail(QTS_E_UNSUPPORTED, "too many leaves");
 
   HostTable h;
   h.F = F;
+  h.n_groups = n_groups;
   h.n_trees = t.n_trees;
   h.max_depth = bld.max_depth;
   h.max_unique = bld.max_unique;
-  h.base_score = base_score;
-  h.expected = bld.expected + base_score;
+  h.base_score = base_scores[0];
+  h.expected_g.resize((size_t)n_groups);
+  for (int32_t g = 0; g < n_groups; ++g)
+    h.expected_g[(size_t)g] = bld.expected[(size_t)g] + base_scores[g];
+  h.expected = h.expected_g[0];
   h.leaf_value = std::move(bld.leaf_value);
   h.leaf_value.resize((size_t)bld.n_leaves_, 0.0);
 
   // group paths by capacity, keeping tree-major order inside a group
   std::vector<size_t> order(bld.paths.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  // buckets: runs of equal (capacity, output group)
+  auto bucket_key = [&](const RawPath& p) {
+    return std::make_pair(bucket_capacity((int)p.feat.size()), p.group);
+  };
   std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
-    return bucket_capacity((int)bld.paths[x].feat.size()) <
-           bucket_capacity((int)bld.paths[y].feat.size());
+    return bucket_key(bld.paths[x]) < bucket_key(bld.paths[y]);
   });
   int64_t n_el = 0;
   for (const RawPath& p : bld.paths) n_el += (int64_t)p.feat.size();
@@ -255,8 +329,8 @@ HostTable build_host_table(const qts_tree_arrays& t, int32_t F, double base_scor
     const int d = (int)p.feat.size();
     const int cap = bucket_capacity(d);
     const int32_t pi = (int32_t)h.hdr.size();
-    if (h.buckets.empty() || h.buckets.back().dmax != cap)
-      h.buckets.push_back(Bucket{cap, pi, pi, 0});
+    if (h.buckets.empty() || h.buckets.back().dmax != cap || h.buckets.back().group != p.group)
+      h.buckets.push_back(Bucket{cap, pi, pi, 0, p.group});
     h.buckets.back().path_end = pi + 1;
     h.buckets.back().elems += d;
     h.hdr.push_back(PathHdr{(int32_t)h.feat.size(), d, p.leaf, p.tree});
@@ -312,16 +386,16 @@ HostTable build_host_table(const qts_tree_arrays& t, int32_t F, double base_scor
   std::vector<size_t> morder(units.size());
   for (size_t i = 0; i < morder.size(); ++i) morder[i] = i;
   std::stable_sort(morder.begin(), morder.end(), [&](size_t x, size_t y) {
-    return bucket_capacity((int)bld.paths[units[x].a].feat.size()) <
-           bucket_capacity((int)bld.paths[units[y].a].feat.size());
+    return bucket_key(bld.paths[units[x].a]) < bucket_key(bld.paths[units[y].a]);
   });
   for (size_t ui : morder) {
     const RawPath& p = bld.paths[units[ui].a];
     const int d = (int)p.feat.size();
     const int cap = bucket_capacity(d);
     const int32_t pi = (int32_t)h.mhdr.size();
-    if (h.mbuckets.empty() || h.mbuckets.back().dmax != cap)
-      h.mbuckets.push_back(Bucket{cap, pi, pi, 0});
+    if (h.mbuckets.empty() || h.mbuckets.back().dmax != cap ||
+        h.mbuckets.back().group != p.group)
+      h.mbuckets.push_back(Bucket{cap, pi, pi, 0, p.group});
     h.mbuckets.back().path_end = pi + 1;
     h.mbuckets.back().elems += d;
     h.mhdr.push_back(PathHdr{(int32_t)h.mfeat.size(), d, p.leaf, units[ui].side});
@@ -337,8 +411,13 @@ HostTable build_host_table(const qts_tree_arrays& t, int32_t F, double base_scor
       h.mcb.push_back(1.0 - p.b[k]);
     }
   }
+  h.tree_group = std::move(groups);
   h.share = prefix_share(h.hdr, h.feat, h.lo, h.hi, h.b);
   h.mshare = prefix_share(h.mhdr, h.mfeat, h.mlo, h.mhi, h.mb);
+  if (wide_features(F)) {
+    h.compact = build_compact(h.hdr, h.feat, h.buckets, F);
+    h.mcompact = build_compact(h.mhdr, h.mfeat, h.mbuckets, F);
+  }
   return h;
 }
 
@@ -393,9 +472,12 @@ PairTable build_pair_table(const HostTable& h) {
     for (size_t i = 0; i < n; ++i)
       rank[i] = count[(size_t)rows[i].tree * (kMaxUnique + 1) + (size_t)rows[i].d]++;
   }
+  auto group_of = [&](const Row& r) { return h.tree_group[(size_t)r.tree]; };
   std::sort(order.begin(), order.end(), [&](size_t x, size_t y) {
     const int cx = cap_of(rows[x].d), cy = cap_of(rows[y].d);
     if (cx != cy) return cx < cy;
+    const int gx = group_of(rows[x]), gy = group_of(rows[y]);
+    if (gx != gy) return gx < gy;
     if (rows[x].d != rows[y].d) return rows[x].d < rows[y].d;
     if (rank[x] != rank[y]) return rank[x] < rank[y];
     return rows[x].tree < rows[y].tree;
@@ -405,9 +487,10 @@ PairTable build_pair_table(const HostTable& h) {
   int64_t el = 0;
   while (i < n) {
     const int cap = cap_of(rows[order[i]].d);
+    const int32_t g = group_of(rows[order[i]]);
     size_t j = i;
-    while (j < n && cap_of(rows[order[j]].d) == cap) ++j;
-    pt.classes.push_back(PairClass{cap, (int32_t)(j - i), el, (int32_t)i});
+    while (j < n && cap_of(rows[order[j]].d) == cap && group_of(rows[order[j]]) == g) ++j;
+    pt.classes.push_back(PairClass{cap, (int32_t)(j - i), el, (int32_t)i, g});
     el += (int64_t)cap * (int64_t)(j - i);
     i = j;
   }

@@ -181,7 +181,8 @@ __device__ __forceinline__ void pairs_prologue(double* phis, double* tris, int64
   __syncthreads();
 }
 
-// Flush the LDS accumulators of sample s into the global FP64 ones.
+// Flush the LDS accumulators of output row s (sample, group) into the global
+// FP64 ones.
 __device__ __forceinline__ void pairs_epilogue(const double* phis, const double* tris,
                                                int64_t ntri_r, int64_t base, int64_t ntri,
                                                bool with_phi, int64_t s, int F,
@@ -216,8 +217,8 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
              const T* __restrict__ bb, const T* __restrict__ cbb,
              int32_t np, int32_t chunk, const double* __restrict__ leaf_val,
              const float* __restrict__ X, int64_t M, int64_t ldx, int32_t F, int32_t r0,
-             int32_t r1, int32_t with_phi, double* __restrict__ tri64,
-             double* __restrict__ phi64, NodeConsts<T> nc) {
+             int32_t r1, int32_t with_phi, int32_t ng, int32_t grp,
+             double* __restrict__ tri64, double* __restrict__ phi64, NodeConsts<T> nc) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t ntri = tri_row(F + 1) - F;         // F(F-1)/2
   const int64_t base0 = tri_row(r0);
@@ -518,7 +519,8 @@ pairs_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf,
       }
     }
   }
-  pairs_epilogue(phis, tris, ntri_r, base0, ntri, with_phi != 0, s, F, tri64, phi64);
+  // output row of (sample s, group grp): the accumulators are [M][ng][...]
+  pairs_epilogue(phis, tris, ntri_r, base0, ntri, with_phi != 0, s * ng + grp, F, tri64, phi64);
 }
 
 // Generic form for long paths (any capacity up to 64): one wavefront per
@@ -568,8 +570,8 @@ pairs_generic_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__
                      const T* __restrict__ cbb, int32_t np, int32_t chunk,
                      const double* __restrict__ leaf_val, const float* __restrict__ X, int64_t M,
                      int64_t ldx, int32_t F, int32_t r0, int32_t r1, int32_t with_phi,
-                     double* __restrict__ tri64, double* __restrict__ phi64,
-                     NodeConsts<T> nc) {
+                     int32_t ng, int32_t grp, double* __restrict__ tri64,
+                     double* __restrict__ phi64, NodeConsts<T> nc) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t ntri = tri_row(F + 1) - F;
   const int64_t base0 = tri_row(r0);
@@ -680,7 +682,7 @@ pairs_generic_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  pairs_epilogue(phis, tris, ntri_r, base0, ntri, with_phi != 0, s, F, tri64, phi64);
+  pairs_epilogue(phis, tris, ntri_r, base0, ntri, with_phi != 0, s * ng + grp, F, tri64, phi64);
 }
 
 // Third-order Shapley interaction indices (Theorem 1 with |S| = 3, Eq. 9-10,
@@ -729,8 +731,8 @@ triples_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf
                const T* __restrict__ bb, const T* __restrict__ cbb, int32_t np, int32_t cap,
                int32_t chunk,
                const double* __restrict__ leaf_val, const float* __restrict__ X, int64_t M,
-               int64_t ldx, int32_t F, int32_t r0, int32_t r1, double* __restrict__ acc,
-               NodeConsts<T> nc) {
+               int64_t ldx, int32_t F, int32_t r0, int32_t r1, int32_t ng, int32_t grp,
+               double* __restrict__ acc, NodeConsts<T> nc) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int nw = blockDim.x >> 6;
   const int64_t nt = tet_row(F);
@@ -871,9 +873,10 @@ triples_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ pleaf
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   __syncthreads();
+  const int64_t orow = s * ng + grp;  // acc is [M][ng][F(F-1)(F-2)/6]
   for (int64_t e = threadIdx.x; e < nt_r; e += blockDim.x) {
     const double v = tets[e];
-    if (v != 0.0) unsafeAtomicAdd(&acc[s * nt + base0 + e], v);
+    if (v != 0.0) unsafeAtomicAdd(&acc[orow * nt + base0 + e], v);
   }
 }
 
@@ -888,8 +891,8 @@ triples_lane_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ 
                     const float* __restrict__ lo, const float* __restrict__ hi,
                     const T* __restrict__ bb, const T* __restrict__ cbb, int32_t np,
                     int32_t chunk, const double* __restrict__ leaf_val, const float* __restrict__ X,
-                    int64_t M, int64_t ldx, int32_t F, int32_t r0, int32_t r1,
-                    double* __restrict__ acc, NodeConsts<T> nc) {
+                    int64_t M, int64_t ldx, int32_t F, int32_t r0, int32_t r1, int32_t ng,
+                    int32_t grp, double* __restrict__ acc, NodeConsts<T> nc) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t nt = tet_row(F);
   const int64_t base0 = tet_row(r0);
@@ -987,9 +990,10 @@ triples_lane_kernel(const int32_t* __restrict__ pd, const int32_t* __restrict__ 
     }
   }
   __syncthreads();
+  const int64_t orow = s * ng + grp;
   for (int64_t e = threadIdx.x; e < nt_r; e += blockDim.x) {
     const double v = tets[e];
-    if (v != 0.0) unsafeAtomicAdd(&acc[s * nt + base0 + e], v);
+    if (v != 0.0) unsafeAtomicAdd(&acc[orow * nt + base0 + e], v);
   }
 }
 
@@ -1119,7 +1123,8 @@ void launch_pairs_fast(const HostTable& h, const DeviceTable& d, const PairClass
                        d.pr_feat + pc.base,
                        d.pr_lo + pc.base, d.pr_hi + pc.base, table_b<T>(d) + pc.base,
                        table_cb<T>(d) + pc.base, pc.np, chunk, leaf_val, X, M, ldx, F, rg.first,
-                       rg.second, (int)first, tri64, phi64, node_consts<T>(d, NN));
+                       rg.second, (int)first, h.n_groups, pc.group, tri64, phi64,
+                       node_consts<T>(d, NN));
     check_hip(hipGetLastError(), "pairs_kernel launch");
     first = false;
   }
@@ -1145,7 +1150,8 @@ void launch_pairs_generic(const HostTable& h, const DeviceTable& d, const PairCl
                        lds, s, d.pr_d + pc.pbase, d.pr_leaf + pc.pbase, d.pr_feat + pc.base,
                        d.pr_lo + pc.base, d.pr_hi + pc.base, table_b<T>(d) + pc.base,
                        table_cb<T>(d) + pc.base, pc.np, chunk, leaf_val, X, M, ldx, F, rg.first,
-                       rg.second, (int)first, tri64, phi64, node_consts<T>(d));
+                       rg.second, (int)first, h.n_groups, pc.group, tri64, phi64,
+                       node_consts<T>(d));
     check_hip(hipGetLastError(), "pairs_generic_kernel launch");
     first = false;
   }
@@ -1179,7 +1185,7 @@ void launch_triples_lane(const HostTable& h, const DeviceTable& d, const PairCla
                        d.pr_d + pc.pbase, d.pr_leaf + pc.pbase, d.pr_side + pc.pbase,
                        d.pr_feat + pc.base, d.pr_lo + pc.base, d.pr_hi + pc.base,
                        table_b<T>(d) + pc.base, table_cb<T>(d) + pc.base, pc.np, chunk, leaf_val,
-                       X, M, ldx, F, r0, r1, acc, node_consts<T>(d));
+                       X, M, ldx, F, r0, r1, h.n_groups, pc.group, acc, node_consts<T>(d));
     check_hip(hipGetLastError(), "triples_lane_kernel launch");
     r0 = r1;
   }
@@ -1232,8 +1238,8 @@ void launch_triples_t(const HostTable& h, const DeviceTable& d, const PairClass&
                        d.pr_d + pc.pbase, d.pr_leaf + pc.pbase, d.pr_side + pc.pbase,
                        d.pr_feat + pc.base, d.pr_lo + pc.base, d.pr_hi + pc.base,
                        table_b<T>(d) + pc.base, table_cb<T>(d) + pc.base, pc.np, pc.cap, chunk,
-                       leaf_val,
-                       X, M, ldx, F, r0, r1, acc, node_consts<T>(d));
+                       leaf_val, X, M, ldx, F, r0, r1, h.n_groups, pc.group, acc,
+                       node_consts<T>(d));
     check_hip(hipGetLastError(), "triples_kernel launch");
     r0 = r1;
   }

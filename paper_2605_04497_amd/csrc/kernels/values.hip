@@ -410,38 +410,72 @@ __device__ __forceinline__ void values_rows_shared(
   }
 }
 
+// The rows and tile features of one work item.  Work item b is (sample block
+// b mod nsb, row chunk b div nsb).  Ordinarily a chunk is `chunk` consecutive
+// rows of the bucket and the tile holds every feature; with segments (wide
+// feature spaces) chunk c is segment c, whose tile holds its own feature
+// list, which the rows' elements index (lfeat).
+struct ItemRows {
+  int p0, p1;            // rows [p0, p1)
+  int nf;                // tile features
+  const int32_t* fmap;   // tile feature -> global feature (null: identity)
+};
+
+__device__ __forceinline__ ItemRows item_rows(const Segment* segs, const int32_t* seg_feat,
+                                              int ch, int32_t path_begin, int32_t path_end,
+                                              int32_t chunk, int32_t F) {
+  ItemRows ir;
+  if (segs != nullptr) {
+    ir.p0 = ldu(&segs[ch].row_begin);
+    ir.p1 = ldu(&segs[ch].row_end);
+    ir.nf = ldu(&segs[ch].nfeat);
+    ir.fmap = seg_feat + ldu(&segs[ch].feat_begin);
+  } else {
+    ir.p0 = path_begin + ch * chunk;
+    ir.p1 = min(path_end, ir.p0 + chunk);
+    ir.nf = F;
+    ir.fmap = nullptr;
+  }
+  return ir;
+}
+
+// tile_f: the features the LDS layout is sized for (F, or kSegFeatures with
+// segments); F: phi's row length.
 template <typename T, int DMAX, int NH, bool STORE_G, int NN>
 __global__ void __launch_bounds__(512)
 values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
               const float* __restrict__ lo, const float* __restrict__ hi,
               const T* __restrict__ bb, const T* __restrict__ cbb,
               const Slot0<T>* __restrict__ z0, const int32_t* __restrict__ share,
-              const float* __restrict__ X, int64_t M, int64_t ldx, int32_t F, int32_t path_begin,
-              int32_t path_end, int32_t chunk, int32_t nsb, double* __restrict__ acc,
-              void* __restrict__ direct, int32_t direct_fp64, NodeConsts<T> nc) {
+              const float* __restrict__ X, int64_t M, int64_t ldx, int32_t F, int32_t tile_f,
+              int32_t path_begin, int32_t path_end, int32_t chunk, int32_t nsb,
+              const Segment* __restrict__ segs, const int32_t* __restrict__ seg_feat,
+              int32_t ng, int32_t grp, double* __restrict__ acc, void* __restrict__ direct,
+              int32_t direct_fp64, NodeConsts<T> nc) {
   extern __shared__ __align__(16) unsigned char smem[];
   float* xs = reinterpret_cast<float*>(smem);
-  size_t xs_bytes = ((size_t)F * kTileStride * sizeof(float) + 15) & ~(size_t)15;
+  size_t xs_bytes = ((size_t)tile_f * kTileStride * sizeof(float) + 15) & ~(size_t)15;
   double* as = reinterpret_cast<double*>(smem + xs_bytes);
 
   const int item = blockIdx.x;
   const int sb = item % nsb;
   const int ch = item / nsb;
   const int64_t s0 = (int64_t)sb * kSamplesPerBlock;
-  const int p0 = path_begin + ch * chunk;
-  const int p1 = min(path_end, p0 + chunk);
+  const ItemRows ir = item_rows(segs, seg_feat, ch, path_begin, path_end, chunk, F);
+  const int nf = ir.nf;
 
   // stage the sample tile transposed; zero the accumulator; note any NaN
-  const int tile = kSamplesPerBlock * F;
+  const int tile = kSamplesPerBlock * nf;
   int nan_seen = 0;
   for (int i = threadIdx.x; i < tile; i += blockDim.x) {
-    const int r = i / F;
-    const int f = i - r * F;
+    const int r = i / nf;
+    const int k = i - r * nf;
+    const int f = ir.fmap ? ir.fmap[k] : k;
     const int64_t s = s0 + r;
     const float v = (s < M) ? X[s * ldx + f] : 0.0f;
     nan_seen |= (v != v);
-    xs[f * kTileStride + r] = v;
-    as[f * kTileStride + r] = 0.0;
+    xs[k * kTileStride + r] = v;
+    as[k * kTileStride + r] = 0.0;
   }
   const bool any_nan = __syncthreads_or(nan_seen) != 0;
 
@@ -449,8 +483,8 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
   // wave-uniform loop bounds (kept in SGPRs so the path loads are scalar)
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nw = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
-  const int pb = __builtin_amdgcn_readfirstlane(p0);
-  const int pe = __builtin_amdgcn_readfirstlane(p1);
+  const int pb = __builtin_amdgcn_readfirstlane(ir.p0);
+  const int pe = __builtin_amdgcn_readfirstlane(ir.p1);
 
   // nodes pinned in VGPRs: a VALU op may read only one SGPR on gfx9-class
   // hardware, and b_j arrives in an SGPR
@@ -482,16 +516,18 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
   // direct: this workgroup is the only one of its sample block (one bucket,
   // one chunk), so it writes phi rows outright, in the output precision.
   for (int i = threadIdx.x; i < tile; i += blockDim.x) {
-    const int r = i / F;
-    const int f = i - r * F;
+    const int r = i / nf;
+    const int k = i - r * nf;
+    const int f = ir.fmap ? ir.fmap[k] : k;
     const int64_t s = s0 + r;
     if (s < M) {
-      const double v = as[f * kTileStride + r];
+      const double v = as[k * kTileStride + r];
+      const int64_t o = (s * ng + grp) * F + f;  // phi[s, grp, f]
       if (direct != nullptr) {
-        if (direct_fp64) static_cast<double*>(direct)[s * F + f] = v;
-        else static_cast<float*>(direct)[s * F + f] = (float)v;
+        if (direct_fp64) static_cast<double*>(direct)[o] = v;
+        else static_cast<float*>(direct)[o] = (float)v;
       } else if (v != 0.0) {
-        unsafeAtomicAdd(&acc[s * F + f], v);
+        unsafeAtomicAdd(&acc[o], v);
       }
     }
   }
@@ -642,41 +678,43 @@ adjoint_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat
                const T* __restrict__ bb, const T* __restrict__ cbb,
                const SidePath* __restrict__ side, const int32_t* __restrict__ share,
                const float* __restrict__ X, const T* __restrict__ G, int64_t M, int64_t ldx,
-               int32_t F, int32_t path_begin,
-               int32_t path_end, int32_t chunk, int32_t nsb, double* __restrict__ grad_leaf,
-               NodeConsts<T> nc) {
+               int32_t F, int32_t tile_f, int32_t path_begin, int32_t path_end, int32_t chunk,
+               int32_t nsb, const Segment* __restrict__ segs,
+               const int32_t* __restrict__ seg_feat, int32_t ng, int32_t grp,
+               double* __restrict__ grad_leaf, NodeConsts<T> nc) {
   extern __shared__ __align__(16) unsigned char smem[];
   float* xs = reinterpret_cast<float*>(smem);
-  size_t xs_bytes = ((size_t)F * kTileStride * sizeof(float) + 15) & ~(size_t)15;
+  size_t xs_bytes = ((size_t)tile_f * kTileStride * sizeof(float) + 15) & ~(size_t)15;
   T* gs = reinterpret_cast<T*>(smem + xs_bytes);
 
   const int item = blockIdx.x;
   const int sb = item % nsb;
   const int ch = item / nsb;
   const int64_t s0 = (int64_t)sb * kSamplesPerBlock;
-  const int p0 = path_begin + ch * chunk;
-  const int p1 = min(path_end, p0 + chunk);
+  const ItemRows ir = item_rows(segs, seg_feat, ch, path_begin, path_end, chunk, F);
+  const int nf = ir.nf;
 
   // stage the sample rows and gradient rows transposed (padding rows get a
   // zero gradient, so they add nothing); note any NaN
-  const int tile = kSamplesPerBlock * F;
+  const int tile = kSamplesPerBlock * nf;
   int nan_seen = 0;
   for (int i = threadIdx.x; i < tile; i += blockDim.x) {
-    const int r = i / F;
-    const int f = i - r * F;
+    const int r = i / nf;
+    const int k = i - r * nf;
+    const int f = ir.fmap ? ir.fmap[k] : k;
     const int64_t s = s0 + r;
     const float v = (s < M) ? X[s * ldx + f] : 0.0f;
     nan_seen |= (v != v);
-    xs[f * kTileStride + r] = v;
-    gs[f * kTileStride + r] = (s < M) ? G[s * F + f] : T(0);
+    xs[k * kTileStride + r] = v;
+    gs[k * kTileStride + r] = (s < M) ? G[(s * ng + grp) * F + f] : T(0);  // G[s, grp, f]
   }
   const bool any_nan = __syncthreads_or(nan_seen) != 0;
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nw = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
-  const int pb = __builtin_amdgcn_readfirstlane(p0);
-  const int pe = __builtin_amdgcn_readfirstlane(p1);
+  const int pb = __builtin_amdgcn_readfirstlane(ir.p0);
+  const int pe = __builtin_amdgcn_readfirstlane(ir.p1);
   T tv[NN];
 #pragma unroll
   for (int m = 0; m < NN; ++m) tv[m] = to_vgpr(nc.t[m]);
@@ -721,18 +759,50 @@ bool values_direct(const std::vector<Bucket>& bks, int64_t M, const ValuesShape&
 namespace {
 
 
+// How one launch over a bucket splits its rows: chunks of `chunk` rows with
+// the full feature tile, or (wide feature spaces) the bucket's segments with
+// their own tiles, the rows' elements read through lfeat.
+struct RowSplit {
+  const int32_t* feat;   // element features as the kernel indexes its tile
+  const Segment* segs;   // null: plain chunks
+  int chunk;
+  int n_chunks;
+  int tile_f;            // features the LDS tile is laid out for
+};
+
+RowSplit row_split(const HostTable& h, const PathArrays& a, const Bucket& bk, int nsb,
+                   const ValuesShape& shape) {
+  RowSplit r{a.feat, nullptr, 0, 0, h.F};
+  if (a.compact == nullptr) {
+    const int n_paths = bk.path_end - bk.path_begin;
+    r.chunk = values_chunk(n_paths, nsb, shape.items);
+    r.n_chunks = (n_paths + r.chunk - 1) / r.chunk;
+    return r;
+  }
+  const CompactTable& c = *a.compact;
+  for (size_t i = 0; i + 1 < c.bucket_seg.size(); ++i) {
+    const int s0 = c.bucket_seg[i], s1 = c.bucket_seg[i + 1];
+    if (s1 > s0 && c.segs[(size_t)s0].row_begin == bk.path_begin) {
+      r.feat = a.lfeat;
+      r.segs = a.segs + s0;
+      r.n_chunks = s1 - s0;
+      r.tile_f = kSegFeatures;
+      return r;
+    }
+  }
+  fail(QTS_E_INVALID_ARG, "internal: bucket without segments");
+}
+
 template <typename T, int DMAX, int NH, bool STORE_G, int NN>
 void launch_one(const HostTable& h, const DeviceTable& d, const PathArrays& a, const Bucket& bk,
                 const float* X, int64_t M, int64_t ldx, const void* slot0, double* acc,
                 void* direct, const ValuesShape& shape, hipStream_t s) {
   const int F = h.F;
   const int nsb = (int)((M + kSamplesPerBlock - 1) / kSamplesPerBlock);
-  const int n_paths = bk.path_end - bk.path_begin;
-  const int chunk = values_chunk(n_paths, nsb, shape.items);
-  const int n_chunks = (n_paths + chunk - 1) / chunk;
-  const int64_t grid = (int64_t)nsb * n_chunks;
+  const RowSplit rs = row_split(h, a, bk, nsb, shape);
+  const int64_t grid = (int64_t)nsb * rs.n_chunks;
   if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "grid too large");
-  const size_t lds = values_lds_bytes(F);
+  const size_t lds = values_lds_bytes(rs.tile_f);
   const int threads = 64 * shape.waves_per_block;
   const T* b = std::is_same<T, float>::value ? (const T*)a.b32 : (const T*)a.b64;
   const T* cb = std::is_same<T, float>::value ? (const T*)a.cb32 : (const T*)a.cb64;
@@ -740,11 +810,12 @@ void launch_one(const HostTable& h, const DeviceTable& d, const PathArrays& a, c
   if constexpr (std::is_same<T, float>::value) nc = NN == 8 ? d.n32 : d.n32_4;
   else nc = NN == 8 ? d.n64 : d.n64_4;
   if (lds > raise_lds_limit((const void*)values_kernel<T, DMAX, NH, STORE_G, NN>))
-    fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
+    fail(QTS_E_UNSUPPORTED, "internal: the sample tile does not fit in LDS");
   hipLaunchKernelGGL((values_kernel<T, DMAX, NH, STORE_G, NN>), dim3((unsigned)grid),
-                     dim3(threads), lds, s, a.hdr, a.feat, a.lo, a.hi, b, cb,
-                     (const Slot0<T>*)slot0, a.share, X,
-                     M, ldx, F, bk.path_begin, bk.path_end, chunk, nsb, acc, direct,
+                     dim3(threads), lds, s, a.hdr, rs.feat, a.lo, a.hi, b, cb,
+                     (const Slot0<T>*)slot0, a.share, X, M, ldx, F, rs.tile_f, bk.path_begin,
+                     bk.path_end, rs.chunk, nsb, rs.segs, a.seg_feat, h.n_groups, bk.group,
+                     acc, rs.segs ? nullptr : direct,
                      (int32_t)(std::is_same<T, double>::value ? 1 : 0), nc);
   check_hip(hipGetLastError(), "values_kernel launch");
 }
@@ -755,13 +826,11 @@ void launch_adj_one(const HostTable& h, const DeviceTable& d, const PathArrays& 
                     double* grad_leaf, const ValuesShape& shape, hipStream_t s) {
   const int F = h.F;
   const int nsb = (int)((M + kSamplesPerBlock - 1) / kSamplesPerBlock);
-  const int n_paths = bk.path_end - bk.path_begin;
-  const int chunk = values_chunk(n_paths, nsb, shape.items);
-  const int n_chunks = (n_paths + chunk - 1) / chunk;
-  const int64_t grid = (int64_t)nsb * n_chunks;
+  const RowSplit rs = row_split(h, a, bk, nsb, shape);
+  const int64_t grid = (int64_t)nsb * rs.n_chunks;
   if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "grid too large");
-  size_t xs = ((size_t)F * kTileStride * sizeof(float) + 15) & ~(size_t)15;
-  const size_t lds = xs + (size_t)F * kTileStride * sizeof(T);
+  size_t xs = ((size_t)rs.tile_f * kTileStride * sizeof(float) + 15) & ~(size_t)15;
+  const size_t lds = xs + (size_t)rs.tile_f * kTileStride * sizeof(T);
   const int threads = 64 * shape.waves_per_block;
   const T* b = std::is_same<T, float>::value ? (const T*)a.b32 : (const T*)a.b64;
   const T* cb = std::is_same<T, float>::value ? (const T*)a.cb32 : (const T*)a.cb64;
@@ -769,11 +838,11 @@ void launch_adj_one(const HostTable& h, const DeviceTable& d, const PathArrays& 
   if constexpr (std::is_same<T, float>::value) nc = NN == 8 ? d.n32 : d.n32_4;
   else nc = NN == 8 ? d.n64 : d.n64_4;
   if (lds > raise_lds_limit((const void*)adjoint_kernel<T, DMAX, NH, STORE_G, NN>))
-    fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
+    fail(QTS_E_UNSUPPORTED, "internal: the sample tile does not fit in LDS");
   hipLaunchKernelGGL((adjoint_kernel<T, DMAX, NH, STORE_G, NN>), dim3((unsigned)grid),
-                     dim3(threads), lds, s, a.hdr, a.feat, a.lo, a.hi, b, cb, a.side, a.share, X,
-                     (const T*)G, M,
-                     ldx, F, bk.path_begin, bk.path_end, chunk, nsb, grad_leaf, nc);
+                     dim3(threads), lds, s, a.hdr, rs.feat, a.lo, a.hi, b, cb, a.side, a.share,
+                     X, (const T*)G, M, ldx, F, rs.tile_f, bk.path_begin, bk.path_end, rs.chunk,
+                     nsb, rs.segs, a.seg_feat, h.n_groups, bk.group, grad_leaf, nc);
   check_hip(hipGetLastError(), "adjoint_kernel launch");
 }
 
@@ -862,8 +931,6 @@ void launch_values(const HostTable& h, const DeviceTable& d, const PathArrays& a
                    const Bucket& bk, bool fp64, const float* X, int64_t M, int64_t ldx,
                    const void* slot0, double* acc, void* direct, const ValuesShape& shape,
                    int nodes, hipStream_t s) {
-  if (values_lds_bytes(h.F) > (size_t)kMaxLdsBytes)
-    fail(QTS_E_UNSUPPORTED, "n_features too large for the LDS-resident tile");
   if (nodes == 4 && bk.dmax == 8) {
     if (!fp64) launch_one<float, 8, 4, true, 4>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s);
     else launch_one<double, 8, 4, false, 4>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s);

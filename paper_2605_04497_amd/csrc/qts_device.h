@@ -49,6 +49,13 @@ struct DeviceTable {
   double* mcb64 = nullptr;
   SidePath* side = nullptr;
   int32_t* mshare = nullptr;
+  // feature-compacted segments (wide_features only), plain and merged tables
+  int32_t* lfeat = nullptr;
+  Segment* segs = nullptr;
+  int32_t* seg_feat = nullptr;
+  int32_t* mlfeat = nullptr;
+  Segment* msegs = nullptr;
+  int32_t* mseg_feat = nullptr;
   NodeConsts<float> n32;     // the 8-node rule
   NodeConsts<double> n64;
   NodeConsts<float> n32_4;   // the 4-node rule (first 4 entries)
@@ -69,14 +76,23 @@ struct PathArrays {
   const double* cb64;
   const SidePath* side;  // null: no merged paths (hdr.tree is then ignored)
   const int32_t* share;  // per row: slots 1..share equal to the previous row's
+  // wide_features: the table's segments (host copy) and their device arrays;
+  // null otherwise
+  const CompactTable* compact;
+  const int32_t* lfeat;
+  const Segment* segs;
+  const int32_t* seg_feat;
 };
 
-inline PathArrays plain_arrays(const DeviceTable& d) {
-  return PathArrays{d.hdr, d.feat, d.lo, d.hi, d.b32, d.cb32, d.b64, d.cb64, nullptr, d.share};
+inline PathArrays plain_arrays(const DeviceTable& d, const HostTable& h) {
+  const bool w = !h.compact.segs.empty();
+  return PathArrays{d.hdr, d.feat, d.lo, d.hi, d.b32, d.cb32, d.b64, d.cb64, nullptr, d.share,
+                    w ? &h.compact : nullptr, d.lfeat, d.segs, d.seg_feat};
 }
-inline PathArrays merged_arrays(const DeviceTable& d) {
+inline PathArrays merged_arrays(const DeviceTable& d, const HostTable& h) {
+  const bool w = !h.mcompact.segs.empty();
   return PathArrays{d.mhdr, d.mfeat, d.mlo, d.mhi, d.mb32, d.mcb32, d.mb64, d.mcb64, d.side,
-                    d.mshare};
+                    d.mshare, w ? &h.mcompact : nullptr, d.mlfeat, d.msegs, d.mseg_feat};
 }
 
 // Slot 0 of a first-order row with its leaf value folded in, built per call

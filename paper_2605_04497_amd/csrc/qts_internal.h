@@ -36,11 +36,13 @@ constexpr int32_t kMissingOkBit = 1 << 30;
 constexpr int32_t kFeatureMask = kMissingOkBit - 1;
 
 // Paths with the same unique-feature capacity are stored contiguously.
+// With several outputs (tree groups), a bucket holds one group's paths.
 struct Bucket {
   int32_t dmax;        // capacity of the kernel instance (8, 16, 32 or 64)
   int32_t path_begin;  // [path_begin, path_end) in path order
   int32_t path_end;
   int64_t elems;       // sum of d over the bucket's paths
+  int32_t group = 0;   // output group of the bucket's trees
 };
 
 // Sibling record of a merged path.  Two leaves A (left) and B (right) of one
@@ -57,19 +59,52 @@ struct alignas(16) SidePath {
   double b_b, cb_b;  // B's b_L and 1 - b_L (FP64)
 };
 
+// Feature-compacted segments of a first-order table.  The first-order and
+// adjoint kernels stage a workgroup's 64 samples transposed in LDS, F floats
+// plus F doubles of accumulator per sample; when that tile does not fit
+// (wide_features), each work item takes instead a segment: consecutive rows
+// of one bucket whose elements use at most kSegFeatures distinct features.
+// The kernel stages only those features and addresses them by their index in
+// the segment's feature list (lfeat), then adds its accumulators to phi at
+// the features' global ids.
+constexpr int kSegFeatures = 96;   // tile features per segment (75 KB of LDS)
+constexpr int kSegMaxRows = 2048;  // rows per segment at most
+constexpr int kTileLdsBudget = 160 * 1024;
+inline bool wide_features(int F) {
+  const size_t xs = ((size_t)F * 65 * sizeof(float) + 15) & ~(size_t)15;
+  return xs + (size_t)F * 65 * sizeof(double) > (size_t)kTileLdsBudget;
+}
+struct Segment {
+  int32_t row_begin, row_end;  // rows [row_begin, row_end) of the table
+  int32_t feat_begin;          // first entry of the segment's list in seg_feat
+  int32_t nfeat;               // distinct features of its rows (<= kSegFeatures)
+};
+struct CompactTable {
+  std::vector<Segment> segs;        // every bucket's segments, in row order
+  std::vector<int32_t> bucket_seg;  // [n_buckets + 1]: segments of bucket i
+  std::vector<int32_t> seg_feat;    // global feature ids, per segment
+  std::vector<int32_t> lfeat;       // per element: index in its segment's list | missing_ok
+};
+CompactTable build_compact(const std::vector<PathHdr>& hdr,
+                           const std::vector<int32_t>& feat,
+                           const std::vector<Bucket>& bks, int32_t F);
+
 // Collapsed path table in host memory (built once per model).
 struct HostTable {
   int32_t F = 0;
+  int32_t n_groups = 1;  // outputs: every tree adds to the output of its group
   int32_t n_trees = 0;
   int32_t max_depth = 0;
   int32_t max_unique = 0;
   double base_score = 0.0;
-  double expected = 0.0;  // sum_T E_T[f] + base_score
+  double expected = 0.0;  // sum_T E_T[f] + base_score (group 0)
+  std::vector<double> expected_g;  // per group: sum over its trees of E_T[f] + its base score
   std::vector<PathHdr> hdr;
   std::vector<int32_t> feat;  // packed: feature | missing_ok bit
   std::vector<float> lo, hi;
   std::vector<double> b, cb;  // b_j and 1 - b_j, FP64
   std::vector<double> leaf_value;
+  std::vector<int32_t> tree_group;  // [n_trees]
   std::vector<Bucket> buckets;
   // per row of a table with at most 8 features: the number s of slots
   // 1..s equal to the previous row's (0 for other rows); see prefix_share
@@ -83,9 +118,14 @@ struct HostTable {
   std::vector<Bucket> mbuckets;
   std::vector<SidePath> side;
   std::vector<int32_t> mshare;
+  // wide_features(F): the segments of both first-order tables
+  CompactTable compact, mcompact;
 };
 
-HostTable build_host_table(const qts_tree_arrays& t, int32_t n_features, double base_score);
+// tree_group: [n_trees] output group of each tree (null: all in group 0);
+// base_scores: [n_groups].
+HostTable build_host_table(const qts_tree_arrays& t, int32_t n_features, int32_t n_groups,
+                           const int32_t* tree_group, const double* base_scores);
 
 // Path table for the interactions kernel: rows grouped by capacity class
 // (4, 8, ..., 40, 48, 64 slots: the kernel instances), sorted by length
@@ -102,6 +142,7 @@ struct PairClass {
   int32_t np;     // paths in the class
   int64_t base;   // first element of the class (slot-major block of cap * np)
   int32_t pbase;  // first path of the class in the per-path arrays
+  int32_t group = 0;  // output group of the class's rows
 };
 
 struct PairTable {

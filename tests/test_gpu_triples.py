@@ -1,8 +1,10 @@
 """GPU parity of the third-order Shapley interaction indices
 (qts_shap_interactions3: Theorem 1 with |S| = 3, Eq. 9-10) against the FP64
-oracle's dense [M, F, F, F] tensor, in both precisions: merged sibling rows,
-missing values, every capacity class up to 64 slots, a tensor split into
-ranges of its largest feature, leaf-value overrides and the empty cases."""
+oracle's dense [M, F, F, F] tensor, in both precisions: merged sibling rows
+(short ones in the lane-per-row kernel, rows of 9 to 16 features in the
+wave-per-row kernel), missing values, every capacity class up to 64 slots, a
+tensor split into ranges of its largest feature, leaf-value overrides and the
+empty cases."""
 import numpy as np
 import pytest
 
@@ -122,3 +124,36 @@ def test_triples_dense_expansion_and_empty_cases(q, oracle_mod):
     e2 = q.Ensemble(synth.from_nested([node], n_features=2))
     out = e2.shap_interactions3(torch.zeros((4, 2), device="cuda"), "fp64")
     assert tuple(out.shape) == (4, 0)
+
+
+def test_triples_deep_grown_merged_rows(q, oracle_mod):
+    """A few grown depth-32 trees (the deep workload's structure): rows of up
+    to ~30 features, including merged sibling rows of 9 to 16 features, which
+    take the merged branch of the wave-per-row kernel in classes 12 and 16."""
+    wl = synth.make_workload("c5_deep", T=3, M=4, n_train=30000)
+    e0 = q.Ensemble(wl.ensemble)
+    assert e0.info["max_unique"] > 16
+    pt_rows = e0.info["n_pair_rows"]
+    assert pt_rows < e0.info["n_paths"]  # some rows are merged sibling pairs
+    want = packed(oracle_mod.shap_sii3(wl.ensemble, wl.X, n=8))
+    assert np.abs(want).max() > 0
+    for precision in ("fp32", "fp64"):
+        got, e = _run(q, wl.ensemble, wl.X, precision)
+        err = check(got, want, precision, "deep grown")
+        print("deep grown triples %s: %.2e" % (precision, err), flush=True)
+
+
+def test_triples_chains_of_64(q, oracle_mod):
+    """Chains of 64 distinct features out of 72: rows in the 48- and 64-slot
+    classes (the longest instances), a tensor of 59,640 triples cut into
+    several LDS ranges, missing values on one sample."""
+    rng = np.random.default_rng(78)
+    ens = _chains(rng, 2, 72, 64)
+    X = (rng.standard_normal((2, 72)) * 0.6).astype(np.float32)
+    X[1, ::7] = np.nan
+    want = packed(oracle_mod.shap_sii3(ens, X, n=8))
+    for precision in ("fp32", "fp64"):
+        got, e = _run(q, ens, X, precision)
+        assert e.info["max_unique"] == 64
+        err = check(got, want, precision, "chains of 64")
+        print("chains of 64 triples %s: %.2e" % (precision, err), flush=True)

@@ -301,3 +301,43 @@ def test_output_fully_overwritten(q, oracle_mod, precision):
         got = out.double().cpu().numpy()
         assert np.isfinite(got).all(), name
         check(got, oracle_mod.shap_values(wl.ensemble, wl.X, n=8), precision, name + " out=")
+
+
+WIDE_CASES = [
+    # Fashion-MNIST's width (784 features): full depth-8 random trees, 20%
+    # integer columns, and grown deep trees (16/32 buckets) on 784 features
+    ("c2_values", dict(F=784, T=24, M=150, n_train=20000)),
+    ("c5_deep", dict(F=784, T=3, M=70, n_train=30000)),
+]
+
+
+@pytest.mark.parametrize("name,over", WIDE_CASES, ids=[c[0] for c in WIDE_CASES])
+def test_wide_feature_space(q, oracle_mod, name, over):
+    """784 features: the sample tile of all features does not fit in LDS, so
+    each work item takes a segment of rows with at most 96 distinct features
+    and stages only those.  Values and the adjoint, merged and plain tables,
+    both precisions, with NaN rows, against the oracle."""
+    print("case wide", name, over, flush=True)
+    wl = synth.make_workload(name, **over)
+    ens = wl.ensemble
+    X = wl.X.copy()
+    rng = np.random.default_rng(7)
+    X[rng.random(X.shape) < 0.03] = np.nan
+    X[5] = np.nan
+    assert ens.n_features == 784
+    want = oracle_mod.shap_values(ens, X, n=8)
+    G = rng.normal(size=(X.shape[0], ens.n_features))
+    e = q.Ensemble(ens)
+    Xd = torch.from_numpy(X).cuda()
+    for merge in (True, False):
+        e.set_sibling_merge(merge)
+        for precision in ("fp32", "fp64"):
+            got = e.shap_values(Xd, precision).double().cpu().numpy()
+            err = check(got, want, precision, "wide %s merge=%s" % (name, merge))
+            Gp = G.astype(np.float32).astype(np.float64) if precision == "fp32" else G
+            gw = oracle_mod.leaf_grad(ens, X, Gp)
+            gl = e.shap_backward(Xd, torch.from_numpy(Gp).cuda(), precision).cpu().numpy()
+            gerr = float(np.abs(gl - gw).max() / np.abs(gw).max())
+            print("wide %s merge=%s %s: phi %.2e grad %.2e" % (name, merge, precision, err,
+                                                              gerr), flush=True)
+            assert gerr <= (1e-5 if precision == "fp32" else 1e-10)

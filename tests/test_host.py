@@ -339,3 +339,22 @@ def test_shared_prefix_stops_at_first_difference(q):
     # [-1, 0), f1 right] shares slot 1 with it; the root's right leaf has
     # no slot after 0
     assert e.info["n_path_shared"] == _shared_slots(_first_order_rows(ens, merged=False)) == 2
+
+
+def test_wide_feature_space_segments(q):
+    """Beyond 210 features the first-order table is cut into segments of rows
+    using at most 96 distinct features (the LDS tile of one work item); a
+    table of every feature fits below that, and has none."""
+    wl = synth.make_workload("c2_values", F=784, T=12, M=4, n_train=20000)
+    e = q.Ensemble(wl.ensemble, host_only=True)
+    n_seg = e.info["n_value_segments"]
+    assert n_seg > 0
+    # each segment holds whole rows and at most 96 features: at least
+    # (distinct features of the table) / 96 segments
+    used = len(set(wl.ensemble.feature[wl.ensemble.left >= 0].tolist()))
+    assert n_seg >= -(-used // 96)
+    for F in (100, 210):
+        wl = synth.make_workload("c2_values", F=F, T=4, M=4, n_train=20000)
+        assert q.Ensemble(wl.ensemble, host_only=True).info["n_value_segments"] == 0
+    wl = synth.make_workload("c2_values", F=211, T=4, M=4, n_train=20000)
+    assert q.Ensemble(wl.ensemble, host_only=True).info["n_value_segments"] > 0
