@@ -111,6 +111,9 @@ def pair_flops(d):
     return 8.0 * (2 * d + (d - 1) + 4 * d + d * (d - 1))
 
 
+TUNE_CACHE = os.path.join(ROOT, "paper_2605_04497_amd", "tune_cache_mi355x.txt")
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -133,13 +136,17 @@ def parse():
                     help="skip the interactions calls on all 50k samples (8 GB FP32 output)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="autotune cache file (shapes measured on MI355X ship with the "
+                         "package; keys include the kernel sources, so edited kernels "
+                         "tune afresh); '' turns the cache off")
     ap.add_argument("--no-merge", action="store_true",
                     help="first-order calls walk every leaf's path (no sibling merging)")
     ap.add_argument("--eager", action="store_true",
                     help="launch eagerly instead of replaying a captured HIP graph")
     ap.add_argument("--only", default=None,
                     choices=["interactions", "interactions_full", "adjoint", "deep", "small",
-                             "third_order"],
+                             "third_order", "wide", "groups"],
                     help="run one leg alone and print its JSON (profiling aid)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MB (a "
@@ -455,6 +462,81 @@ def measure_small(args, torch, q, synth, oracle, dev):
             "max_rel_err_fp64": err, "max_rel_err_vs_enumeration_20_rows": err_b}
 
 
+def measure_wide(args, torch, q, synth, oracle, dev):
+    """Fashion-MNIST's width: 784 features (the sample tile of every feature
+    does not fit in LDS, so work items take segments of rows with at most 96
+    distinct features).  200 random trees of depth 8 (20% integer columns),
+    20k samples: values in FP32 and FP64 and the adjoint, with the error on
+    sampled rows."""
+    wl = synth.make_workload("c2_values", F=784, T=200, M=20000)
+    ens = wl.ensemble
+    e = q.Ensemble(ens, device=dev)
+    X = torch.from_numpy(wl.X).to(dev)
+    M, F = X.shape[0], e.n_features
+    res = {}
+    for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+        if not args.no_autotune:
+            e.autotune(M, prec)
+        e.set_graph_replay(not args.eager)
+        phi = torch.empty((M, F), dtype=dt, device=dev)
+        res[prec] = time_steps(lambda: e.shap_values(X, prec, out=phi), 5, 1, torch)
+        G = torch.ones((M, F), dtype=dt, device=dev)
+        gl = torch.empty(e.n_leaves, dtype=torch.float64, device=dev)
+        res["adj_" + prec] = time_steps(lambda: e.shap_backward(X, G, prec, out=gl), 5, 1, torch,
+                                        "backward")
+        e.set_graph_replay(False)
+        if prec == "fp32":
+            rows = np.array([0, M // 2, M - 1])
+            want = oracle.shap_values(ens, wl.X[rows], n=8)
+            got = phi[torch.from_numpy(rows).to(dev)].double().cpu().numpy()
+            res["err"] = float((np.abs(got - want).max(1) / np.abs(want).max(1)).max())
+        del phi, G
+    out = {"workload": "784 features (Fashion-MNIST's width): 200 random trees depth 8, "
+                       "20%% integer columns, %d leaves, 20k samples" % e.n_leaves,
+           "segments": int(e.info["n_value_segments"]),
+           "value": M * e.n_leaves / (res["fp32"]["ms_per_step"] * 1e-3), "unit": "paths/s",
+           "ms_per_step": res["fp32"]["ms_per_step"],
+           "fp64_ms_per_step": res["fp64"]["ms_per_step"],
+           "adjoint_ms_per_step": res["adj_fp32"]["ms_per_step"],
+           "adjoint_fp64_ms_per_step": res["adj_fp64"]["ms_per_step"],
+           "max_rel_err_fp32": res["err"], "rows_checked": 3}
+    e.close()
+    return out
+
+
+def measure_groups(args, torch, q, synth, oracle, dev):
+    """A three-output model (tree t adds to output t mod 3, as the rounds of
+    a multiclass booster): the headline's tree recipe with 300 trees, 20k
+    samples; phi[M, 3, 100] in FP32 and FP64."""
+    wl = synth.make_workload("c2_values", T=300, M=20000, groups=3)
+    ens = wl.ensemble
+    e = q.Ensemble(ens, device=dev)
+    X = torch.from_numpy(wl.X).to(dev)
+    M, F, K = X.shape[0], e.n_features, e.n_groups
+    res = {}
+    for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+        if not args.no_autotune:
+            e.autotune(M, prec)
+        e.set_graph_replay(not args.eager)
+        phi = torch.empty((M, K, F), dtype=dt, device=dev)
+        res[prec] = time_steps(lambda: e.shap_values(X, prec, out=phi), 5, 1, torch)
+        e.set_graph_replay(False)
+        if prec == "fp32":
+            rows = np.array([0, M - 1])
+            want = oracle.shap_values_grouped(ens, wl.X[rows], n=8).reshape(2 * K, F)
+            got = phi[torch.from_numpy(rows).to(dev)].double().cpu().numpy().reshape(2 * K, F)
+            res["err"] = float((np.abs(got - want).max(1) / np.abs(want).max(1)).max())
+        del phi
+    out = {"workload": "3 outputs: 300 random trees depth 8 (100 per output), 100 features, "
+                       "20k samples, phi[M, 3, F]",
+           "value": M * e.n_leaves / (res["fp32"]["ms_per_step"] * 1e-3), "unit": "paths/s",
+           "ms_per_step": res["fp32"]["ms_per_step"],
+           "fp64_ms_per_step": res["fp64"]["ms_per_step"],
+           "max_rel_err_fp32": res["err"], "rows_checked": 2}
+    e.close()
+    return out
+
+
 def measure_interactions_full(args, torch, q, synth, oracle, dev):
     """The interactions workload at its stated size: all 50k explained samples
     of the 500-tree, 200-feature ensemble, Phi[50k, 200, 200] in FP32 (8.0 GB)
@@ -524,12 +606,14 @@ def main():
     import synth
     from oracle import oracle
 
+    q.set_tune_cache(args.tune_cache or None)
     if args.only:
         dev = torch.device("cuda:0")
         torch.cuda.set_device(dev)
         fn = {"interactions": measure_interactions, "interactions_full": measure_interactions_full,
               "adjoint": measure_adjoint, "deep": measure_deep, "small": measure_small,
-              "third_order": measure_third_order}[args.only]
+              "third_order": measure_third_order, "wide": measure_wide,
+              "groups": measure_groups}[args.only]
         print(json.dumps({"leg": args.only, "result": fn(args, torch, q, synth, oracle, dev)}),
               flush=True)
         return
@@ -565,13 +649,16 @@ def main():
     n_vel = e.info["n_value_elements"] if not args.no_merge else n_el
     e.set_sibling_merge(not args.no_merge)
     tune_s = 0.0
+    tune_hits = tune_misses = 0
     if not args.no_autotune:
         t0 = time.perf_counter()
         for prec in ("fp32", "fp64"):
             e.autotune(M, prec)
         tune_s = time.perf_counter() - t0
-        log("autotune: %.1f s; fp32 shape %s, fp64 shape %s" % (
-            tune_s, e.launch_shape("values", "fp32", 0), e.launch_shape("values", "fp64", 0)))
+        tune_hits, tune_misses = q.tune_cache_stats()
+        log("autotune: %.1f s (cache hits %d, misses %d); fp32 shape %s, fp64 shape %s" % (
+            tune_s, tune_hits, tune_misses, e.launch_shape("values", "fp32", 0),
+            e.launch_shape("values", "fp64", 0)))
     e.set_graph_replay(not args.eager)
 
     out32 = torch.empty((M, e.n_features), dtype=torch.float32, device=dev)
@@ -660,6 +747,9 @@ def main():
                         "measure": "row-normwise vs FP64 oracle (8 nodes)"},
         "launch": {"mode": "hipGraph replay" if not args.eager else "eager",
                    "autotuned": not args.no_autotune, "autotune_s": tune_s,
+                   "tune_cache": {"path": os.path.relpath(args.tune_cache, ROOT)
+                                  if args.tune_cache else None,
+                                  "hits": tune_hits, "misses": tune_misses},
                    "values_shape_fp32": list(e.launch_shape("values", "fp32", 0)),
                    "values_shape_fp64": list(e.launch_shape("values", "fp64", 0)),
                    "step_ms_median": r32["step_ms_median"], "step_ms_min": r32["step_ms_min"],
@@ -696,7 +786,8 @@ def main():
     if not args.no_extras:
         legs = [("interactions", measure_interactions), ("adjoint", measure_adjoint),
                 ("deep", measure_deep), ("small", measure_small),
-                ("third_order", measure_third_order)]
+                ("third_order", measure_third_order), ("wide", measure_wide),
+                ("groups", measure_groups)]
         if not args.no_full_interactions:
             legs.append(("interactions_full", measure_interactions_full))
         for key, fn in legs:

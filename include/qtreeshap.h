@@ -243,6 +243,19 @@ int qts_shap_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_
  * compute calls on the same ensemble. */
 int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, void* stream);
 
+/* Persistent autotune cache (process-wide; NULL or "" turns it off, the
+ * default).  While set, qts_autotune looks up each bucket's and class's launch
+ * shape in the text file at `path` before timing candidates, and appends the
+ * shapes it times.  A key names everything the timing depends on: the
+ * library's kernel sources, the device (architecture and compute units), the
+ * kernel kind, precision and node policy, the feature and output counts, the
+ * bucket or class (capacity, output group, rows) and the size class of
+ * M_hint; a file that cannot be written still serves hits.  Lines are
+ * "<key> -> a b"; later lines win. */
+int qts_set_tune_cache(const char* path);
+/* Cache lookups since the last qts_set_tune_cache: hits and misses. */
+int qts_tune_cache_stats(int64_t* hits, int64_t* misses);
+
 /* The launch shape in use (first order and adjoint: for the node policy in
  * effect): kind 0 = first-order bucket `index`, kind 2 =
  * adjoint bucket `index` (0..3 for lengths <= 8, 16, 32, 64) -> (*a, *b) =
@@ -266,6 +279,22 @@ int qts_get_launch_shape(const qts_ensemble* ens, int32_t kind, qts_precision pr
  * interactions and adjoint calls always walk every path.  Changing the
  * setting drops the ensemble's cached graphs. */
 int qts_set_sibling_merge(qts_ensemble* ens, int32_t enable);
+
+/* Deterministic first-order and adjoint results (off by default).  phi and
+ * grad_leaf are sums over paths and trees in FP64; with atomics their order,
+ * and so their last bits, depend on scheduling.  While enabled:
+ *   qts_shap_values runs one wavefront per
+ *     workgroup and one launch per row chunk, in order, on the call's stream,
+ *     each adding its tiles without atomics: every (sample, feature) has one
+ *     writer per launch;
+ *   qts_shap_backward stores each 64-sample block's leaf sums in a row of its
+ *     own (every leaf belongs to one row of the table) and adds the rows in
+ *     order (scratch of ceil(M / 64) * n_leaves doubles).
+ * Results are then identical bit for bit from run to run on one device and
+ * build, and equal the default mode's up to rounding.  The first-order call
+ * runs several times slower (one wavefront per workgroup).  Interactions and
+ * third-order calls are not affected.  Changing it drops the cached graphs. */
+int qts_set_deterministic(qts_ensemble* ens, int32_t enable);
 
 /* Node count of every call.
  *   QTS_NODES_FIXED8 (default): the 8-node Gauss-Legendre rule for every path

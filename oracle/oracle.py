@@ -10,6 +10,8 @@ Output conventions (readings of the paper, listed with the tests):
   Phi[M,F,F]  interaction matrix: Phi[i,k] = SII_ik / 2 for i != k and
               Phi[i,i] = phi_i - sum_{k != i} Phi[i,k], so each row sums to phi
   expected    E[f] = v(empty set) summed over trees, plus the base score
+Multi-output models (a group per tree) are computed per group on the group's
+sub-ensemble; the *_grouped functions stack the results as [M, K, ...].
 """
 from __future__ import annotations
 
@@ -216,3 +218,80 @@ def treeshap(m, X, threads=None) -> np.ndarray:
                           ctypes.c_int(threads or default_threads())) != 0:
         raise RuntimeError("orc_treeshap failed")
     return phi
+
+
+# ---------------------------------------------------------------------------
+# Multi-output ensembles.  Each tree adds to the output of its group, so the
+# game of output g is the sum of the path-dependent games (Eq. 3) of group g's
+# trees, and every quantity above is computed per group on that group's
+# sub-ensemble: a plain composition of the single-output oracle.
+# ---------------------------------------------------------------------------
+
+def _groups(ens):
+    K = int(getattr(ens, "n_groups", 1) or 1)
+    return K, [ens.group_trees(g) if K > 1 else list(range(ens.n_trees)) for g in range(K)]
+
+
+def _base(ens, g):
+    b = np.asarray(ens.base_score, np.float64).reshape(-1)
+    return float(b[g] if b.shape[0] > 1 else b[0])
+
+
+def _sub(ens, trees):
+    sub = ens.subset_trees(trees)
+    sub.base_score = 0.0
+    return sub
+
+
+def shap_values_grouped(ens, X, n=N_METHOD, threads=None) -> np.ndarray:
+    """phi[M, K, F]: Shapley values of each output's game."""
+    K, tg = _groups(ens)
+    return np.stack([shap_values(_sub(ens, t), X, n, threads) for t in tg], axis=1)
+
+
+def shap_interactions_grouped(ens, X, n=N_METHOD, threads=None):
+    """(phi[M, K, F], Phi[M, K, F, F]) of each output's game."""
+    K, tg = _groups(ens)
+    parts = [shap_interactions(_sub(ens, t), X, n, threads) for t in tg]
+    return (np.stack([p[0] for p in parts], axis=1), np.stack([p[1] for p in parts], axis=1))
+
+
+def shap_sii3_grouped(ens, X, n=N_METHOD, threads=None) -> np.ndarray:
+    """sii3[M, K, F, F, F] of each output's game."""
+    K, tg = _groups(ens)
+    return np.stack([shap_sii3(_sub(ens, t), X, n, threads) for t in tg], axis=1)
+
+
+def expected_values_grouped(ens) -> np.ndarray:
+    """E_g[f] + base score of each output."""
+    K, tg = _groups(ens)
+    return np.array([expected_value(_sub(ens, t)) + _base(ens, g) for g, t in enumerate(tg)])
+
+
+def predict_grouped(ens, X) -> np.ndarray:
+    """f_g(x) + base score of each output: [M, K]."""
+    K, tg = _groups(ens)
+    return np.stack([predict(_sub(ens, t), X) + _base(ens, g) for g, t in enumerate(tg)], axis=1)
+
+
+def leaf_grad_grouped(ens, X, G, n=N_METHOD, threads=None) -> np.ndarray:
+    """grad_leaf = sum_g J_g^T G[:, g, :] with each leaf's gradient taken in
+    the game of its own tree's output; leaves in tree-major node-id order of
+    the whole ensemble."""
+    K, tg = _groups(ens)
+    G = np.asarray(G, np.float64)
+    assert G.shape[1] == K
+    leaves_per_tree = np.array([int((ens.left[ens.tree_offsets[t]:ens.tree_offsets[t + 1]]
+                                     < 0).sum()) for t in range(ens.n_trees)])
+    first = np.concatenate([[0], np.cumsum(leaves_per_tree)])
+    out = np.zeros(int(first[-1]))
+    for g, trees in enumerate(tg):
+        if not trees:
+            continue
+        part = leaf_grad(_sub(ens, trees), X, G[:, g, :], n, threads)
+        pos = 0
+        for t in trees:
+            k = int(leaves_per_tree[t])
+            out[first[t]:first[t] + k] = part[pos:pos + k]
+            pos += k
+    return out

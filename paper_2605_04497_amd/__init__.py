@@ -6,9 +6,10 @@ include/qtreeshap.h.  Importing the package loads the in-tree library and
 fails if it has not been built.
 """
 from ._lib import QtsError, lib
-from .api import Ensemble, ShapValues, gauss_legendre, read_kernel_timing, set_kernel_timing
+from .api import (Ensemble, ShapValues, gauss_legendre, read_kernel_timing, set_kernel_timing,
+                  set_tune_cache, tune_cache_stats)
 
 lib()
 
 __all__ = ["Ensemble", "ShapValues", "gauss_legendre", "QtsError", "lib", "set_kernel_timing",
-           "read_kernel_timing"]
+           "read_kernel_timing", "set_tune_cache", "tune_cache_stats"]

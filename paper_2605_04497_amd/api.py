@@ -32,6 +32,18 @@ def gauss_legendre(n: int = 8):
     return t, s, w
 
 
+def set_tune_cache(path) -> None:
+    """Keep autotuned launch shapes in the text file `path` (None: off)."""
+    L.check(L.lib().qts_set_tune_cache(None if path is None else str(path).encode()))
+
+
+def tune_cache_stats():
+    """(hits, misses) of the autotune cache since it was set."""
+    h, m = ctypes.c_int64(), ctypes.c_int64()
+    L.check(L.lib().qts_tune_cache_stats(ctypes.byref(h), ctypes.byref(m)))
+    return int(h.value), int(m.value)
+
+
 KERNEL_KINDS = {"values": 0, "interactions": 1, "backward": 2}
 
 
@@ -63,30 +75,40 @@ class Ensemble:
             ("feature", np.int32), ("threshold", np.float32), ("default_left", np.uint8),
             ("cover", np.float64), ("value", np.float64))}
         self.n_features = int(model.n_features)
-        self.base_score = float(getattr(model, "base_score", 0.0))
-        ta = L.TreeArrays(int(a["tree_offsets"].shape[0] - 1),
+        n_trees = int(a["tree_offsets"].shape[0] - 1)
+        # multi-output models: tree_group [T] and n_groups (base_score then
+        # holds one value per group)
+        tg = getattr(model, "tree_group", None)
+        self.n_groups = int(getattr(model, "n_groups", 1) or 1) if tg is not None else 1
+        bs = np.ascontiguousarray(np.broadcast_to(
+            np.asarray(getattr(model, "base_score", 0.0), np.float64).reshape(-1),
+            (self.n_groups,)))
+        tg = np.ascontiguousarray(tg if tg is not None else np.zeros(n_trees), np.int32)
+        ta = L.TreeArrays(n_trees,
                           *[a[k].ctypes.data for k in ("tree_offsets", "left", "right", "feature",
                                                        "threshold", "default_left", "cover",
                                                        "value")])
         h = ctypes.c_void_p()
         if host_only:
             self.device = None
-            L.check(L.lib().qts_build_host(ctypes.byref(ta), self.n_features, self.base_score,
-                                           ctypes.byref(h)))
+            L.check(L.lib().qts_build_host_grouped(ctypes.byref(ta), tg.ctypes.data,
+                                                   self.n_groups, self.n_features,
+                                                   bs.ctypes.data, ctypes.byref(h)))
         else:
             self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
                 else torch.device(device)
             with torch.cuda.device(self.device):
-                L.check(L.lib().qts_load_ensemble(ctypes.byref(ta), self.n_features,
-                                                  self.base_score, _stream_ptr(self.device),
-                                                  ctypes.byref(h)))
+                L.check(L.lib().qts_load_ensemble_grouped(
+                    ctypes.byref(ta), tg.ctypes.data, self.n_groups, self.n_features,
+                    bs.ctypes.data, _stream_ptr(self.device), ctypes.byref(h)))
         self._h = h
         info = L.Info()
         L.check(L.lib().qts_get_info(self._h, ctypes.byref(info)))
         self.info = {k: getattr(info, k) for k, _ in L.Info._fields_}
-        ev = ctypes.c_double()
-        L.check(L.lib().qts_expected_value(self._h, ctypes.byref(ev)))
-        self.expected_value = ev.value
+        ev = np.zeros(self.n_groups)
+        L.check(L.lib().qts_expected_values(self._h, ev.ctypes.data))
+        # one output: a float; several: one value per output group
+        self.expected_value = float(ev[0]) if self.n_groups == 1 else ev
         self.n_leaves = int(info.n_leaves)
 
     def close(self):
@@ -143,12 +165,17 @@ class Ensemble:
         return leaf_values.contiguous()
 
     # ---------------------------------------------------------------- compute
+    def _per_sample(self, M, *rest):
+        """Output shape: [M, *rest], or [M, n_groups, *rest] for several outputs."""
+        return (M,) + ((self.n_groups,) if self.n_groups > 1 else ()) + tuple(rest)
+
     def shap_values(self, X: torch.Tensor, precision: str = "fp32", leaf_values=None,
                     out=None) -> torch.Tensor:
-        """phi[M, F]; float32 for 'fp32', float64 for 'fp64'."""
+        """phi[M, F] ([M, n_groups, F] for a multi-output model); float32 for
+        'fp32', float64 for 'fp64'."""
         X, M, ldx = self._rows(X)
         lv = self._leaf(leaf_values, X.device)
-        shape = (M, self.n_features)
+        shape = self._per_sample(M, self.n_features)
         if out is None:
             out = torch.empty(shape, dtype=_DTYPE[precision], device=X.device)
         else:
@@ -159,21 +186,22 @@ class Ensemble:
 
     def shap_interactions(self, X: torch.Tensor, precision: str = "fp32", leaf_values=None,
                           with_phi: bool = False, out=None, out_phi=None):
-        """Phi[M, F, F] (and phi[M, F] when with_phi)."""
+        """Phi[M, F, F] (and phi[M, F] when with_phi); with several outputs
+        [M, n_groups, F, F] and [M, n_groups, F]."""
         X, M, ldx = self._rows(X)
         lv = self._leaf(leaf_values, X.device)
         F = self.n_features
         dt = _DTYPE[precision]
         if out is not None:
-            Phi = self._out(out, (M, F, F), dt, X.device, "out")
+            Phi = self._out(out, self._per_sample(M, F, F), dt, X.device, "out")
         else:
-            Phi = torch.empty((M, F, F), dtype=dt, device=X.device)
+            Phi = torch.empty(self._per_sample(M, F, F), dtype=dt, device=X.device)
         phi = None
         if with_phi:
             if out_phi is not None:
-                phi = self._out(out_phi, (M, F), dt, X.device, "out_phi")
+                phi = self._out(out_phi, self._per_sample(M, F), dt, X.device, "out_phi")
             else:
-                phi = torch.empty((M, F), dtype=dt, device=X.device)
+                phi = torch.empty(self._per_sample(M, F), dtype=dt, device=X.device)
         elif out_phi is not None:
             raise ValueError("out_phi is given but with_phi is False")
         L.check(L.lib().qts_shap_interactions(self._h, _ptr(X), M, ldx, _ptr(lv), _ptr(phi),
@@ -183,16 +211,17 @@ class Ensemble:
 
     def shap_interactions3(self, X: torch.Tensor, precision: str = "fp32",
                            leaf_values: torch.Tensor | None = None, out=None) -> torch.Tensor:
-        """Third-order Shapley interaction indices, packed [M, F(F-1)(F-2)/6]:
-        the triple of features i < j < k at k(k-1)(k-2)/6 + j(j-1)/2 + i."""
+        """Third-order Shapley interaction indices, packed [M, F(F-1)(F-2)/6]
+        ([M, n_groups, ...] with several outputs): the triple of features
+        i < j < k at k(k-1)(k-2)/6 + j(j-1)/2 + i."""
         X, M, ldx = self._rows(X)
         F = self.n_features
         T3 = F * (F - 1) * (F - 2) // 6
         dt = _DTYPE[precision]
         if out is None:
-            out = torch.empty((M, T3), dtype=dt, device=X.device)
+            out = torch.empty(self._per_sample(M, T3), dtype=dt, device=X.device)
         else:
-            self._out(out, (M, T3), dt, X.device, "out")
+            self._out(out, self._per_sample(M, T3), dt, X.device, "out")
         lv = self._leaf(leaf_values, X.device)
         L.check(L.lib().qts_shap_interactions3(self._h, _ptr(X), M, ldx, _ptr(lv), _ptr(out),
                                                _PREC[precision], _stream_ptr(X.device)))
@@ -200,9 +229,11 @@ class Ensemble:
 
     @staticmethod
     def triples_dense(packed: torch.Tensor, n_features: int) -> torch.Tensor:
-        """Expand a packed [M, F(F-1)(F-2)/6] tensor to the symmetric [M, F, F, F]
-        one (zero where two indices coincide)."""
+        """Expand a packed [..., F(F-1)(F-2)/6] tensor to the symmetric
+        [..., F, F, F] one (zero where two indices coincide)."""
         F = n_features
+        lead = tuple(packed.shape[:-1])
+        packed = packed.reshape(-1, packed.shape[-1])
         idx = torch.combinations(torch.arange(F, device=packed.device), 3)  # i < j < k
         i, j, k = idx[:, 0], idx[:, 1], idx[:, 2]
         pos = k * (k - 1) * (k - 2) // 6 + j * (j - 1) // 2 + i
@@ -210,7 +241,7 @@ class Ensemble:
         v = packed[:, pos]
         for a, b, c in ((i, j, k), (i, k, j), (j, i, k), (j, k, i), (k, i, j), (k, j, i)):
             dense[:, a, b, c] = v
-        return dense
+        return dense.reshape(lead + (F, F, F))
 
     def shap_backward(self, X: torch.Tensor, grad_phi: torch.Tensor,
                       precision: str = "fp32", out=None) -> torch.Tensor:
@@ -220,8 +251,8 @@ class Ensemble:
             raise TypeError("grad_phi must be a torch tensor")
         if grad_phi.device != X.device:
             raise ValueError("grad_phi is on %s, X is on %s" % (grad_phi.device, X.device))
-        if tuple(grad_phi.shape) != (M, self.n_features):
-            raise ValueError("grad_phi must be [M, F]")
+        if tuple(grad_phi.shape) != self._per_sample(M, self.n_features):
+            raise ValueError("grad_phi must be [M, F] ([M, n_groups, F] with several outputs)")
         g = grad_phi.to(_DTYPE[precision]).contiguous()
         if out is None:
             out = torch.empty(self.n_leaves, dtype=torch.float64, device=X.device)
@@ -257,6 +288,11 @@ class Ensemble:
         """First-order calls walk one merged path per pair of sibling leaves
         (default) or every path (exact same values up to rounding)."""
         L.check(L.lib().qts_set_sibling_merge(self._h, int(bool(enable))))
+
+    def set_deterministic(self, enable: bool = True):
+        """First-order values and the adjoint identical bit for bit from run to
+        run (ordered sums without atomics; the values call runs slower)."""
+        L.check(L.lib().qts_set_deterministic(self._h, int(bool(enable))))
 
     def set_node_policy(self, policy: str = "fixed8"):
         """'fixed8': the 8-node rule everywhere (default); 'exact': the fewest

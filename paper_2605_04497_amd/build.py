@@ -51,9 +51,24 @@ def _compile(src, extra=()):
     return obj, r.stderr
 
 
+def kernels_sha() -> str:
+    """SHA-256 prefix of the kernel sources and device header: part of every
+    autotune cache key, so a kernel change invalidates cached shapes."""
+    import hashlib
+    h = hashlib.sha256()
+    for sub in ("kernels", ""):
+        d = os.path.join(CSRC, sub)
+        for f in sorted(os.listdir(d)):
+            if f.endswith((".hip", ".h")):
+                with open(os.path.join(d, f), "rb") as fh:
+                    h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False, extra=()) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
+    extra = list(extra) + ['-DQTS_KERNELS_SHA="%s"' % kernels_sha()]
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         results = list(ex.map(lambda s: _compile(s, extra), srcs))
     if verbose:

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -69,6 +70,7 @@ struct qts_ensemble {
   qts::ValuesShape ashape[2][2][4];
   std::vector<qts::PairShape> pshape[2][2];  // [node policy][precision]
   bool merge_siblings = true;  // first-order calls walk the merged table
+  bool deterministic = false;  // first-order and adjoint results independent of scheduling
   int node_policy = QTS_NODES_FIXED8;
   int64_t pair_rows = 0, pair_elements = 0, pair_updates = 0;  // interactions table
   qts::GraphCache graphs;
@@ -80,6 +82,22 @@ namespace {
 thread_local std::string g_last_error;
 
 int cap_index(int dmax) { return dmax <= 8 ? 0 : dmax <= 16 ? 1 : dmax <= 32 ? 2 : 3; }
+
+// The bucket with the most rows of each capacity (launch shapes are kept per
+// capacity; with output groups several buckets share one).
+std::vector<Bucket> largest_per_capacity(const std::vector<Bucket>& bks) {
+  std::vector<Bucket> out;
+  for (const Bucket& bk : bks) {
+    bool done = false;
+    for (Bucket& o : out)
+      if (o.dmax == bk.dmax) {
+        if (bk.path_end - bk.path_begin > o.path_end - o.path_begin) o = bk;
+        done = true;
+      }
+    if (!done) out.push_back(bk);
+  }
+  return out;
+}
 
 template <class Fn>
 int guarded(Fn&& fn) {
@@ -299,6 +317,84 @@ class TimedScope {
   bool active_ = false;
 };
 
+// Persistent autotune cache (qts_set_tune_cache): one line per tuned launch,
+//   <key> -> a b
+// where the key names everything the timing depended on: the build's kernel
+// sources, the device (architecture and compute units), the kernel kind,
+// precision and node policy, the features and outputs, the bucket or class
+// (capacity, group, rows) and the size class of the tuning row count.
+#ifndef QTS_KERNELS_SHA
+#define QTS_KERNELS_SHA "unversioned"
+#endif
+struct TuneCache {
+  std::mutex mu;
+  std::string path;
+  bool loaded = false;
+  std::vector<std::pair<std::string, std::pair<int, int>>> entries;
+  int64_t hits = 0, misses = 0;
+};
+TuneCache& tune_cache() {
+  static TuneCache c;
+  return c;
+}
+
+// Under the cache's lock.
+void tune_cache_load(TuneCache& c) {
+  if (c.loaded) return;
+  c.loaded = true;
+  c.entries.clear();
+  FILE* f = std::fopen(c.path.c_str(), "r");
+  if (!f) return;
+  char line[1024];
+  while (std::fgets(line, sizeof line, f)) {
+    std::string ln(line);
+    const size_t arrow = ln.find(" -> ");
+    if (arrow == std::string::npos) continue;
+    int a = 0, b = 0;
+    if (std::sscanf(ln.c_str() + arrow + 4, "%d %d", &a, &b) != 2) continue;
+    c.entries.emplace_back(ln.substr(0, arrow), std::make_pair(a, b));
+  }
+  std::fclose(f);
+}
+
+bool tune_cache_get(const std::string& key, int* a, int* b) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  if (c.path.empty()) return false;
+  tune_cache_load(c);
+  for (auto it = c.entries.rbegin(); it != c.entries.rend(); ++it)
+    if (it->first == key) {
+      *a = it->second.first;
+      *b = it->second.second;
+      ++c.hits;
+      return true;
+    }
+  ++c.misses;
+  return false;
+}
+
+void tune_cache_put(const std::string& key, int a, int b) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  if (c.path.empty()) return;
+  c.entries.emplace_back(key, std::make_pair(a, b));
+  FILE* f = std::fopen(c.path.c_str(), "a");
+  if (!f) return;  // a read-only cache still serves hits
+  std::fprintf(f, "%s -> %d %d\n", key.c_str(), a, b);
+  std::fclose(f);
+}
+
+std::string tune_key(const std::string& device, const char* kind, bool fp64, int policy,
+                     const HostTable& h, int cap, int group, int64_t rows, int64_t m_class) {
+  char buf[512];
+  std::snprintf(buf, sizeof buf,
+                "v1 kernels=%s device=%s kind=%s prec=%s policy=%d F=%d groups=%d cap=%d "
+                "group=%d rows=%lld mclass=%lld",
+                QTS_KERNELS_SHA, device.c_str(), kind, fp64 ? "fp64" : "fp32", policy, h.F,
+                h.n_groups, cap, group, (long long)rows, (long long)m_class);
+  return buf;
+}
+
 // The streams one call's launches go to: the call's own stream, plus, while
 // a graph is captured, side streams forked from it so that the per-bucket
 // (per-class) launches become parallel branches of the graph.  Buckets add
@@ -360,7 +456,7 @@ bool direct_call(const qts_ensemble* ens, int64_t M, bool fp64) {
 int64_t out_row(const qts_ensemble* ens) { return (int64_t)ens->host.n_groups * ens->host.F; }
 
 size_t values_scratch_bytes(const qts_ensemble* ens, int64_t M, bool fp64) {
-  const bool acc = !fp64 && !direct_call(ens, M, fp64);
+  const bool acc = !fp64 && (ens->deterministic || !direct_call(ens, M, fp64));
   return slot0_region(ens, fp64) + (acc ? sizeof(double) * (size_t)(M * out_row(ens)) : 0);
 }
 
@@ -374,6 +470,19 @@ void issue_values(const qts_ensemble* ens, const float* X, int64_t M, int64_t ld
                                              : plain_arrays(ens->dev, ens->host);
   const std::vector<Bucket>& bks = ens->merge_siblings ? h.mbuckets : h.buckets;
   launch_slot0(arr, value_rows(ens), leaf, fp64, slot0, ln.main);
+  if (ens->deterministic) {
+    // one stream, buckets and chunks in order, adds without atomics
+    double* a = fp64 ? (double*)phi : (double*)((char*)scratch + slot0_region(ens, fp64));
+    launch_fill_zero(a, n, ln.main);
+    TimedScope ts(0, timed ? ln.main : nullptr, timed);
+    for (const Bucket& bk : bks)
+      launch_values(h, ens->dev, arr, bk, fp64, X, M, ldx, slot0, a, nullptr,
+                    ens->vshape[pol_index(ens)][fp64 ? 1 : 0][cap_index(bk.dmax)],
+                    nodes_of(ens), ln.main, true);
+    ts.done();
+    if (!fp64) launch_cast_f64_f32(a, (float*)phi, n, ln.main);
+    return;
+  }
   if (direct_call(ens, M, fp64)) {
     TimedScope ts(0, timed ? ln.main : nullptr, timed);
     launch_values(h, ens->dev, arr, bks[0], fp64, X, M, ldx, slot0, nullptr, phi,
@@ -418,10 +527,35 @@ void issue_interactions(const qts_ensemble* ens, const float* X, int64_t M, int6
   launch_pairs_finalize(tri64, phi64, MK, (int)F, fp64, Phi, phi, ln.main);
 }
 
+// Scratch of a backward call: deterministic calls keep one row of leaf
+// partial sums per 64-sample block.
+size_t backward_scratch_bytes(const qts_ensemble* ens, int64_t M) {
+  if (!ens->deterministic || M == 0) return 0;
+  const int64_t nsb = (M + kSamplesPerBlock - 1) / kSamplesPerBlock;
+  return sizeof(double) * (size_t)(nsb * (int64_t)ens->host.leaf_value.size());
+}
+
 void issue_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
-                    const void* grad_phi, double* grad_leaf, bool fp64, Lanes& ln, bool timed) {
+                    const void* grad_phi, double* grad_leaf, bool fp64, double* scratch,
+                    Lanes& ln, bool timed) {
   const HostTable& h = ens->host;
-  launch_fill_zero(grad_leaf, (int64_t)h.leaf_value.size(), ln.main);
+  const int64_t L = (int64_t)h.leaf_value.size();
+  if (ens->deterministic && M > 0) {
+    const int64_t nsb = (M + kSamplesPerBlock - 1) / kSamplesPerBlock;
+    launch_fill_zero(scratch, nsb * L, ln.main);
+    const std::vector<Bucket>& bks = ens->merge_siblings ? h.mbuckets : h.buckets;
+    const PathArrays arr = ens->merge_siblings ? merged_arrays(ens->dev, ens->host)
+                                               : plain_arrays(ens->dev, ens->host);
+    TimedScope ts(2, timed ? ln.main : nullptr, timed);
+    for (const Bucket& bk : bks)
+      launch_adjoint(h, ens->dev, arr, bk, fp64, X, grad_phi, M, ldx, scratch,
+                     ens->ashape[pol_index(ens)][fp64 ? 1 : 0][cap_index(bk.dmax)],
+                     nodes_of(ens), ln.main, L);
+    ts.done();
+    launch_sum_rows(scratch, nsb, L, grad_leaf, ln.main);
+    return;
+  }
+  launch_fill_zero(grad_leaf, L, ln.main);
   if (M == 0) return;
   TimedScope ts(2, timed ? ln.main : nullptr, timed);
   const std::vector<Bucket>& bks = ens->merge_siblings ? h.mbuckets : h.buckets;
@@ -827,15 +961,21 @@ int qts_shap_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_
     hipStream_t s = (hipStream_t)stream;
     const bool fp64 = precision == QTS_FP64;
     qts_ensemble* me = const_cast<qts_ensemble*>(ens);
+    const size_t scratch_bytes = backward_scratch_bytes(ens, M);
     if (ens->graphs.on && M > 0) {
       GraphKey key{2, fp64, X, M, ldx, grad_phi, grad_leaf, nullptr, s};
-      run_graph(me, key, 0, 2, [&](Lanes& ln, double*) {
-        issue_backward(ens, X, M, ldx, grad_phi, grad_leaf, fp64, ln, false);
+      run_graph(me, key, scratch_bytes, 2, [&](Lanes& ln, double* scratch) {
+        issue_backward(ens, X, M, ldx, grad_phi, grad_leaf, fp64, scratch, ln, false);
       });
       return;
     }
     Lanes ln{s, nullptr};
-    issue_backward(ens, X, M, ldx, grad_phi, grad_leaf, fp64, ln, true);
+    if (scratch_bytes == 0) {
+      issue_backward(ens, X, M, ldx, grad_phi, grad_leaf, fp64, nullptr, ln, true);
+      return;
+    }
+    Scratch scratch(scratch_bytes, s);
+    issue_backward(ens, X, M, ldx, grad_phi, grad_leaf, fp64, (double*)scratch.p, ln, true);
   });
 }
 
@@ -878,6 +1018,15 @@ int qts_set_sibling_merge(qts_ensemble* ens, int32_t enable) {
   });
 }
 
+int qts_set_deterministic(qts_ensemble* ens, int32_t enable) {
+  return guarded([&] {
+    if (!ens) fail(QTS_E_INVALID_ARG, "null ensemble");
+    std::lock_guard<std::mutex> lock(ens->graphs.mu);
+    if (ens->deterministic != (enable != 0)) clear_graphs(ens->graphs);
+    ens->deterministic = enable != 0;
+  });
+}
+
 int qts_set_node_policy(qts_ensemble* ens, int32_t policy) {
   return guarded([&] {
     if (!ens) fail(QTS_E_INVALID_ARG, "null ensemble");
@@ -906,6 +1055,20 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
     // real count matters)
     const int64_t Mt = std::max<int64_t>(64, std::min<int64_t>(M_hint > 0 ? M_hint : 16384,
                                                                262144));
+    // tuning cache key parts: the device, and the row count's size class
+    std::string device;
+    {
+      int dev = -1;
+      check_hip(hipGetDevice(&dev), "hipGetDevice");
+      hipDeviceProp_t prop;
+      check_hip(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+      device = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount);
+      for (char& ch : device)
+        if (ch == ' ') ch = '_';
+    }
+    int64_t m_class = 0;
+    while (((int64_t)1 << m_class) < Mt) ++m_class;
+    const int pol = pol_index(ens);
     const int64_t K = h.n_groups;
     Scratch xs(sizeof(float) * (size_t)(Mt * F), s);
     const float* X = (const float*)xs.p;
@@ -941,22 +1104,27 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
       const PathArrays arr = ens->merge_siblings ? merged_arrays(d, h) : plain_arrays(d, h);
       Scratch slot0(slot0_bytes(value_rows(ens), fp64), s);
       launch_slot0(arr, value_rows(ens), d.leaf_val, fp64, slot0.p, s);
-      for (const Bucket& bk : bks) {
+      for (const Bucket& bk : largest_per_capacity(bks)) {
+        const std::string key = tune_key(device, "values", fp64, pol, h, bk.dmax, bk.group,
+                                         bk.path_end - bk.path_begin, m_class);
         ValuesShape best;
-        float best_ms = 1e30f;
-        for (int waves : {4, 6, 8})
-          for (int items : {4096, 8192, 16384, 32768, 65536}) {
-            const ValuesShape cand{waves, items};
-            const float ms = time_ms(3, [&] {
-              launch_values(h, d, arr, bk, fp64, X, Mt, F, slot0.p, (double*)acc.p, nullptr, cand,
-                            nodes_of(ens), s);
-            });
-            if (ms < best_ms) {
-              best_ms = ms;
-              best = cand;
+        if (!tune_cache_get(key, &best.waves_per_block, &best.items)) {
+          float best_ms = 1e30f;
+          for (int waves : {4, 6, 8})
+            for (int items : {4096, 8192, 16384, 32768, 65536}) {
+              const ValuesShape cand{waves, items};
+              const float ms = time_ms(3, [&] {
+                launch_values(h, d, arr, bk, fp64, X, Mt, F, slot0.p, (double*)acc.p, nullptr,
+                              cand, nodes_of(ens), s);
+              });
+              if (ms < best_ms) {
+                best_ms = ms;
+                best = cand;
+              }
             }
-          }
-        ens->vshape[pol_index(ens)][pi][cap_index(bk.dmax)] = best;
+          tune_cache_put(key, best.waves_per_block, best.items);
+        }
+        ens->vshape[pol][pi][cap_index(bk.dmax)] = best;
       }
     }
     // adjoint kernel, per bucket, with a synthetic upstream gradient
@@ -970,22 +1138,27 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
       launch_fill_zero((double*)gl.p, (int64_t)h.leaf_value.size(), s);
       const std::vector<Bucket>& bks = ens->merge_siblings ? h.mbuckets : h.buckets;
       const PathArrays arr = ens->merge_siblings ? merged_arrays(d, h) : plain_arrays(d, h);
-      for (const Bucket& bk : bks) {
+      for (const Bucket& bk : largest_per_capacity(bks)) {
+        const std::string key = tune_key(device, "adjoint", fp64, pol, h, bk.dmax, bk.group,
+                                         bk.path_end - bk.path_begin, m_class);
         ValuesShape best;
-        float best_ms = 1e30f;
-        for (int waves : {4, 6, 8})
-          for (int items : {4096, 8192, 16384, 32768, 65536}) {
-            const ValuesShape cand{waves, items};
-            const float ms = time_ms(3, [&] {
-              launch_adjoint(h, d, arr, bk, fp64, X, G, Mt, F, (double*)gl.p, cand,
-                             nodes_of(ens), s);
-            });
-            if (ms < best_ms) {
-              best_ms = ms;
-              best = cand;
+        if (!tune_cache_get(key, &best.waves_per_block, &best.items)) {
+          float best_ms = 1e30f;
+          for (int waves : {4, 6, 8})
+            for (int items : {4096, 8192, 16384, 32768, 65536}) {
+              const ValuesShape cand{waves, items};
+              const float ms = time_ms(3, [&] {
+                launch_adjoint(h, d, arr, bk, fp64, X, G, Mt, F, (double*)gl.p, cand,
+                               nodes_of(ens), s);
+              });
+              if (ms < best_ms) {
+                best_ms = ms;
+                best = cand;
+              }
             }
-          }
-        ens->ashape[pol_index(ens)][pi][cap_index(bk.dmax)] = best;
+          tune_cache_put(key, best.waves_per_block, best.items);
+        }
+        ens->ashape[pol][pi][cap_index(bk.dmax)] = best;
       }
     }
     // interactions, per capacity class, on at most 256 of the rows (and an
@@ -1002,20 +1175,25 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
       out.assign(ens->pair_classes.size(), PairShape{});
       for (size_t i = 0; i < ens->pair_classes.size(); ++i) {
         const PairClass& pc = ens->pair_classes[i];
+        const std::string key = tune_key(device, "pairs", fp64, pol, h, pc.cap, pc.group, pc.np,
+                                         m_class);
         PairShape best;
-        float best_ms = 1e30f;
-        for (int max_chunk : {8192, 32768, 131072})
-          for (int fill : {1024, 4096}) {
-            const PairShape cand{max_chunk, fill};
-            const float ms = time_ms(1, [&] {
-              launch_pairs(h, d, pc, fp64, X, Mp, F, d.leaf_val, tri64, phi64, cand,
-                           ens->node_policy == QTS_NODES_EXACT, s);
-            });
-            if (ms < best_ms) {
-              best_ms = ms;
-              best = cand;
+        if (!tune_cache_get(key, &best.max_chunk, &best.fill)) {
+          float best_ms = 1e30f;
+          for (int max_chunk : {8192, 32768, 131072})
+            for (int fill : {1024, 4096}) {
+              const PairShape cand{max_chunk, fill};
+              const float ms = time_ms(1, [&] {
+                launch_pairs(h, d, pc, fp64, X, Mp, F, d.leaf_val, tri64, phi64, cand,
+                             ens->node_policy == QTS_NODES_EXACT, s);
+              });
+              if (ms < best_ms) {
+                best_ms = ms;
+                best = cand;
+              }
             }
-          }
+          tune_cache_put(key, best.max_chunk, best.fill);
+        }
         out[i] = best;
       }
     }
@@ -1048,6 +1226,27 @@ int qts_get_launch_shape(const qts_ensemble* ens, int32_t kind, qts_precision pr
     } else {
       fail(QTS_E_INVALID_ARG, "unknown kind");
     }
+  });
+}
+
+int qts_set_tune_cache(const char* path) {
+  return guarded([&] {
+    TuneCache& c = tune_cache();
+    std::lock_guard<std::mutex> g(c.mu);
+    c.path = path ? path : "";
+    c.loaded = false;
+    c.entries.clear();
+    c.hits = c.misses = 0;
+  });
+}
+
+int qts_tune_cache_stats(int64_t* hits, int64_t* misses) {
+  return guarded([&] {
+    if (!hits || !misses) fail(QTS_E_INVALID_ARG, "null argument");
+    TuneCache& c = tune_cache();
+    std::lock_guard<std::mutex> g(c.mu);
+    *hits = c.hits;
+    *misses = c.misses;
   });
 }
 

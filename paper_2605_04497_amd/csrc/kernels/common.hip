@@ -58,6 +58,19 @@ __global__ void __launch_bounds__(256) widen_kernel(const float* __restrict__ sr
     dst[i] = (double)src[i];
 }
 
+// out[i] = sum over r = 0, 1, ..., nrows - 1 of part[r * n + i], added in that
+// order (a reduction whose result does not depend on scheduling).
+__global__ void __launch_bounds__(256) sum_rows_kernel(const double* __restrict__ part,
+                                                       int64_t nrows, int64_t n,
+                                                       double* __restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double acc = 0.0;
+    for (int64_t r = 0; r < nrows; ++r) acc += part[r * n + i];
+    out[i] = acc;
+  }
+}
+
 static unsigned grid_for(int64_t n) {
   int64_t g = (n + 255) / 256;
   if (g > 8192) g = 8192;
@@ -81,6 +94,12 @@ void launch_widen_f32_f64(const float* src, double* dst, int64_t n, hipStream_t 
   if (n <= 0) return;
   hipLaunchKernelGGL(widen_kernel, dim3(grid_for(n)), dim3(256), 0, s, src, dst, n);
   check_hip(hipGetLastError(), "widen launch");
+}
+
+void launch_sum_rows(const double* part, int64_t nrows, int64_t n, double* out, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(sum_rows_kernel, dim3(grid_for(n)), dim3(256), 0, s, part, nrows, n, out);
+  check_hip(hipGetLastError(), "sum_rows launch");
 }
 
 void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s) {

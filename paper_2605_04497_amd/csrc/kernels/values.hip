@@ -59,6 +59,15 @@ __device__ __forceinline__ double to_vgpr(double v) {
   return r;
 }
 
+// Add a row's leaf-value gradient, summed over the wave's 64 samples.  det:
+// grad_leaf is this sample block's own row of partial sums, and every leaf
+// belongs to one row, so a plain store suffices (and keeps the result
+// independent of scheduling).
+__device__ __forceinline__ void leaf_add(double* grad_leaf, int leaf, double v, bool det) {
+  if (det) grad_leaf[leaf] = v;
+  else if (v != 0.0) unsafeAtomicAdd(&grad_leaf[leaf], v);
+}
+
 // The path loop of one workgroup.  NANS: the tile holds a NaN, so the
 // missing-value rule is evaluated; otherwise plain interval tests suffice.
 // ADJ: adjoint mode.  phi is linear in the leaf value, so d phi[s, f_j] /
@@ -73,7 +82,7 @@ __device__ __forceinline__ void values_paths(
     const T* __restrict__ cbb, const SidePath* __restrict__ side,
     const Slot0<T>* __restrict__ z0, const float* xs, double* as, const T* gs,
     double* __restrict__ grad_leaf, int pb, int pe, int wave, int nw, int lane, const T* tv,
-    const NodeConsts<T>& nc) {
+    const NodeConsts<T>& nc, bool det = false) {
   constexpr int NB = DMAX / 8;  // feature batches
   for (int p = pb + wave; p < pe; p += nw) {
     const int d = ldu(&hdr[p].d);
@@ -278,10 +287,10 @@ __device__ __forceinline__ void values_paths(
         gacc += (double)(gL * oc0A * q0);
         gaccB += (double)(gL * oc0B * q0);
         gaccB = wave_sum_last(gaccB);
-        if (lane == 63 && gaccB != 0.0) unsafeAtomicAdd(&grad_leaf[leafB], gaccB);
+        if (lane == 63) leaf_add(grad_leaf, leafB, gaccB, det);
       }
       gacc = wave_sum_last(gacc);
-      if (lane == 63 && gacc != 0.0) unsafeAtomicAdd(&grad_leaf[leaf], gacc);
+      if (lane == 63) leaf_add(grad_leaf, leaf, gacc, det);
     }
   }
 }
@@ -451,7 +460,7 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
               int32_t path_begin, int32_t path_end, int32_t chunk, int32_t nsb,
               const Segment* __restrict__ segs, const int32_t* __restrict__ seg_feat,
               int32_t ng, int32_t grp, double* __restrict__ acc, void* __restrict__ direct,
-              int32_t direct_fp64, NodeConsts<T> nc) {
+              int32_t direct_fp64, int32_t plain_add, NodeConsts<T> nc) {
   extern __shared__ __align__(16) unsigned char smem[];
   float* xs = reinterpret_cast<float*>(smem);
   size_t xs_bytes = ((size_t)tile_f * kTileStride * sizeof(float) + 15) & ~(size_t)15;
@@ -527,7 +536,9 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
         if (direct_fp64) static_cast<double*>(direct)[o] = v;
         else static_cast<float*>(direct)[o] = (float)v;
       } else if (v != 0.0) {
-        unsafeAtomicAdd(&acc[o], v);
+        // plain_add: the only workgroup of this launch that holds (s, f)
+        if (plain_add) acc[o] += v;
+        else unsafeAtomicAdd(&acc[o], v);
       }
     }
   }
@@ -551,7 +562,7 @@ __device__ __forceinline__ void adjoint_rows_shared(
     const T* __restrict__ cbb, const SidePath* __restrict__ side,
     const int32_t* __restrict__ share, const float* xs, const T* gs,
     double* __restrict__ grad_leaf, int pb, int pe, int wave, int nw, int lane, const T* tv,
-    const NodeConsts<T>& nc) {
+    const NodeConsts<T>& nc, bool det) {
   constexpr bool kScalarT = NH == 8;
   const int run = (pe - pb + nw - 1) / nw;
   const int p_first = pb + wave * run;
@@ -660,11 +671,11 @@ __device__ __forceinline__ void adjoint_rows_shared(
     const T gq = g0 * q0;
     double gA = (double)fmaT(bA, sR, cA * (stR + gq));
     gA = wave_sum_last(gA);
-    if (lane == 63 && gA != 0.0) unsafeAtomicAdd(&grad_leaf[leaf], gA);
+    if (lane == 63) leaf_add(grad_leaf, leaf, gA, det);
     if (merged) {
       double gB = (double)fmaT(bB, sR, cB * (stR + gq));
       gB = wave_sum_last(gB);
-      if (lane == 63 && gB != 0.0) unsafeAtomicAdd(&grad_leaf[leafB], gB);
+      if (lane == 63) leaf_add(grad_leaf, leafB, gB, det);
     }
   }
 }
@@ -681,7 +692,7 @@ adjoint_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat
                int32_t F, int32_t tile_f, int32_t path_begin, int32_t path_end, int32_t chunk,
                int32_t nsb, const Segment* __restrict__ segs,
                const int32_t* __restrict__ seg_feat, int32_t ng, int32_t grp,
-               double* __restrict__ grad_leaf, NodeConsts<T> nc) {
+               double* __restrict__ grad_leaf, int64_t part_stride, NodeConsts<T> nc) {
   extern __shared__ __align__(16) unsigned char smem[];
   float* xs = reinterpret_cast<float*>(smem);
   size_t xs_bytes = ((size_t)tile_f * kTileStride * sizeof(float) + 15) & ~(size_t)15;
@@ -718,21 +729,24 @@ adjoint_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat
   T tv[NN];
 #pragma unroll
   for (int m = 0; m < NN; ++m) tv[m] = to_vgpr(nc.t[m]);
+  // deterministic: this sample block's own row of partial sums
+  const bool det = part_stride > 0;
+  double* gl = det ? grad_leaf + (int64_t)sb * part_stride : grad_leaf;
   constexpr bool kShared = DMAX == 8 && NH == NN && (STORE_G || NN == 4);
   if (kShared && any_nan)
-    adjoint_rows_shared<T, NH, true>(hdr, feat, lo, hi, bb, cbb, side, share, xs, gs, grad_leaf,
-                                     pb, pe, wave, nw, lane, tv, nc);
+    adjoint_rows_shared<T, NH, true>(hdr, feat, lo, hi, bb, cbb, side, share, xs, gs, gl, pb,
+                                     pe, wave, nw, lane, tv, nc, det);
   else if (kShared)
-    adjoint_rows_shared<T, NH, false>(hdr, feat, lo, hi, bb, cbb, side, share, xs, gs, grad_leaf,
-                                      pb, pe, wave, nw, lane, tv, nc);
+    adjoint_rows_shared<T, NH, false>(hdr, feat, lo, hi, bb, cbb, side, share, xs, gs, gl, pb,
+                                      pe, wave, nw, lane, tv, nc, det);
   else if (any_nan)
     values_paths<T, DMAX, NH, STORE_G, true, true, NN>(hdr, feat, lo, hi, bb, cbb, side, nullptr,
-                                                       xs, nullptr, gs, grad_leaf, pb, pe,
-                                                       wave, nw, lane, tv, nc);
+                                                       xs, nullptr, gs, gl, pb, pe, wave, nw,
+                                                       lane, tv, nc, det);
   else
     values_paths<T, DMAX, NH, STORE_G, false, true, NN>(hdr, feat, lo, hi, bb, cbb, side, nullptr,
-                                                        xs, nullptr, gs, grad_leaf, pb, pe,
-                                                        wave, nw, lane, tv, nc);
+                                                        xs, nullptr, gs, gl, pb, pe, wave, nw,
+                                                        lane, tv, nc, det);
 }
 
 namespace {
@@ -796,14 +810,16 @@ RowSplit row_split(const HostTable& h, const PathArrays& a, const Bucket& bk, in
 template <typename T, int DMAX, int NH, bool STORE_G, int NN>
 void launch_one(const HostTable& h, const DeviceTable& d, const PathArrays& a, const Bucket& bk,
                 const float* X, int64_t M, int64_t ldx, const void* slot0, double* acc,
-                void* direct, const ValuesShape& shape, hipStream_t s) {
+                void* direct, const ValuesShape& shape, hipStream_t s, bool det) {
   const int F = h.F;
   const int nsb = (int)((M + kSamplesPerBlock - 1) / kSamplesPerBlock);
   const RowSplit rs = row_split(h, a, bk, nsb, shape);
   const int64_t grid = (int64_t)nsb * rs.n_chunks;
   if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "grid too large");
   const size_t lds = values_lds_bytes(rs.tile_f);
-  const int threads = 64 * shape.waves_per_block;
+  // deterministic: one wave per workgroup (no LDS atomics between waves), and
+  // one launch per chunk, so each launch has one workgroup per (sample, feature)
+  const int threads = det ? 64 : 64 * shape.waves_per_block;
   const T* b = std::is_same<T, float>::value ? (const T*)a.b32 : (const T*)a.b64;
   const T* cb = std::is_same<T, float>::value ? (const T*)a.cb32 : (const T*)a.cb64;
   NodeConsts<T> nc;
@@ -811,19 +827,34 @@ void launch_one(const HostTable& h, const DeviceTable& d, const PathArrays& a, c
   else nc = NN == 8 ? d.n64 : d.n64_4;
   if (lds > raise_lds_limit((const void*)values_kernel<T, DMAX, NH, STORE_G, NN>))
     fail(QTS_E_UNSUPPORTED, "internal: the sample tile does not fit in LDS");
-  hipLaunchKernelGGL((values_kernel<T, DMAX, NH, STORE_G, NN>), dim3((unsigned)grid),
-                     dim3(threads), lds, s, a.hdr, rs.feat, a.lo, a.hi, b, cb,
-                     (const Slot0<T>*)slot0, a.share, X, M, ldx, F, rs.tile_f, bk.path_begin,
-                     bk.path_end, rs.chunk, nsb, rs.segs, a.seg_feat, h.n_groups, bk.group,
-                     acc, rs.segs ? nullptr : direct,
-                     (int32_t)(std::is_same<T, double>::value ? 1 : 0), nc);
-  check_hip(hipGetLastError(), "values_kernel launch");
+  if (!det) {
+    hipLaunchKernelGGL((values_kernel<T, DMAX, NH, STORE_G, NN>), dim3((unsigned)grid),
+                       dim3(threads), lds, s, a.hdr, rs.feat, a.lo, a.hi, b, cb,
+                       (const Slot0<T>*)slot0, a.share, X, M, ldx, F, rs.tile_f, bk.path_begin,
+                       bk.path_end, rs.chunk, nsb, rs.segs, a.seg_feat, h.n_groups, bk.group,
+                       acc, rs.segs ? nullptr : direct,
+                       (int32_t)(std::is_same<T, double>::value ? 1 : 0), 0, nc);
+    check_hip(hipGetLastError(), "values_kernel launch");
+    return;
+  }
+  for (int c = 0; c < rs.n_chunks; ++c) {
+    const int p0 = rs.segs ? bk.path_begin : bk.path_begin + c * rs.chunk;
+    const int p1 = rs.segs ? bk.path_end : std::min(bk.path_end, p0 + rs.chunk);
+    hipLaunchKernelGGL((values_kernel<T, DMAX, NH, STORE_G, NN>), dim3((unsigned)nsb),
+                       dim3(threads), lds, s, a.hdr, rs.feat, a.lo, a.hi, b, cb,
+                       (const Slot0<T>*)slot0, a.share, X, M, ldx, F, rs.tile_f, p0, p1,
+                       rs.chunk, nsb, rs.segs ? rs.segs + c : nullptr, a.seg_feat, h.n_groups,
+                       bk.group, acc, nullptr, (int32_t)(std::is_same<T, double>::value ? 1 : 0),
+                       1, nc);
+    check_hip(hipGetLastError(), "values_kernel launch");
+  }
 }
 
 template <typename T, int DMAX, int NH, bool STORE_G, int NN>
 void launch_adj_one(const HostTable& h, const DeviceTable& d, const PathArrays& a,
                     const Bucket& bk, const float* X, const void* G, int64_t M, int64_t ldx,
-                    double* grad_leaf, const ValuesShape& shape, hipStream_t s) {
+                    double* grad_leaf, const ValuesShape& shape, hipStream_t s,
+                    int64_t part_stride) {
   const int F = h.F;
   const int nsb = (int)((M + kSamplesPerBlock - 1) / kSamplesPerBlock);
   const RowSplit rs = row_split(h, a, bk, nsb, shape);
@@ -842,7 +873,8 @@ void launch_adj_one(const HostTable& h, const DeviceTable& d, const PathArrays& 
   hipLaunchKernelGGL((adjoint_kernel<T, DMAX, NH, STORE_G, NN>), dim3((unsigned)grid),
                      dim3(threads), lds, s, a.hdr, rs.feat, a.lo, a.hi, b, cb, a.side, a.share,
                      X, (const T*)G, M, ldx, F, rs.tile_f, bk.path_begin, bk.path_end, rs.chunk,
-                     nsb, rs.segs, a.seg_feat, h.n_groups, bk.group, grad_leaf, nc);
+                     nsb, rs.segs, a.seg_feat, h.n_groups, bk.group, grad_leaf, part_stride,
+                     nc);
   check_hip(hipGetLastError(), "adjoint_kernel launch");
 }
 
@@ -851,25 +883,25 @@ void launch_adj_one(const HostTable& h, const DeviceTable& d, const PathArrays& 
 void launch_adjoint(const HostTable& h, const DeviceTable& d, const PathArrays& a,
                     const Bucket& bk, bool fp64, const float* X, const void* G, int64_t M,
                     int64_t ldx, double* grad_leaf, const ValuesShape& shape, int nodes,
-                    hipStream_t s) {
+                    hipStream_t s, int64_t part_stride) {
   if (nodes == 4 && bk.dmax == 8) {
-    if (!fp64) launch_adj_one<float, 8, 4, true, 4>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s);
-    else launch_adj_one<double, 8, 4, false, 4>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s);
+    if (!fp64) launch_adj_one<float, 8, 4, true, 4>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s, part_stride);
+    else launch_adj_one<double, 8, 4, false, 4>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s, part_stride);
     return;
   }
   if (!fp64) {
     switch (bk.dmax) {
-      case 8: launch_adj_one<float, 8, 8, true, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s); break;
-      case 16: launch_adj_one<float, 16, 8, true, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s); break;
-      case 32: launch_adj_one<float, 32, 8, false, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s); break;
-      default: launch_adj_one<float, 64, 4, false, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      case 8: launch_adj_one<float, 8, 8, true, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s, part_stride); break;
+      case 16: launch_adj_one<float, 16, 8, true, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s, part_stride); break;
+      case 32: launch_adj_one<float, 32, 8, false, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s, part_stride); break;
+      default: launch_adj_one<float, 64, 4, false, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s, part_stride); break;
     }
   } else {
     switch (bk.dmax) {
-      case 8: launch_adj_one<double, 8, 4, false, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s); break;
-      case 16: launch_adj_one<double, 16, 4, false, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s); break;
-      case 32: launch_adj_one<double, 32, 4, false, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s); break;
-      default: launch_adj_one<double, 64, 1, false, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s); break;
+      case 8: launch_adj_one<double, 8, 4, false, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s, part_stride); break;
+      case 16: launch_adj_one<double, 16, 4, false, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s, part_stride); break;
+      case 32: launch_adj_one<double, 32, 4, false, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s, part_stride); break;
+      default: launch_adj_one<double, 64, 1, false, 8>(h, d, a, bk, X, G, M, ldx, grad_leaf, shape, s, part_stride); break;
     }
   }
 }
@@ -930,25 +962,25 @@ void launch_slot0(const PathArrays& a, int32_t n_rows, const double* leaf_val, b
 void launch_values(const HostTable& h, const DeviceTable& d, const PathArrays& a,
                    const Bucket& bk, bool fp64, const float* X, int64_t M, int64_t ldx,
                    const void* slot0, double* acc, void* direct, const ValuesShape& shape,
-                   int nodes, hipStream_t s) {
+                   int nodes, hipStream_t s, bool deterministic) {
   if (nodes == 4 && bk.dmax == 8) {
-    if (!fp64) launch_one<float, 8, 4, true, 4>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s);
-    else launch_one<double, 8, 4, false, 4>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s);
+    if (!fp64) launch_one<float, 8, 4, true, 4>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s, deterministic);
+    else launch_one<double, 8, 4, false, 4>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s, deterministic);
     return;
   }
   if (!fp64) {
     switch (bk.dmax) {
-      case 8: launch_one<float, 8, 8, true, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s); break;
-      case 16: launch_one<float, 16, 8, true, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s); break;
-      case 32: launch_one<float, 32, 8, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s); break;
-      default: launch_one<float, 64, 4, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s); break;
+      case 8: launch_one<float, 8, 8, true, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s, deterministic); break;
+      case 16: launch_one<float, 16, 8, true, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s, deterministic); break;
+      case 32: launch_one<float, 32, 8, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s, deterministic); break;
+      default: launch_one<float, 64, 4, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s, deterministic); break;
     }
   } else {
     switch (bk.dmax) {
-      case 8: launch_one<double, 8, 8, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s); break;
-      case 16: launch_one<double, 16, 4, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s); break;
-      case 32: launch_one<double, 32, 4, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s); break;
-      default: launch_one<double, 64, 2, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s); break;
+      case 8: launch_one<double, 8, 8, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s, deterministic); break;
+      case 16: launch_one<double, 16, 4, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s, deterministic); break;
+      case 32: launch_one<double, 32, 4, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s, deterministic); break;
+      default: launch_one<double, 64, 2, false, 8>(h, d, a, bk, X, M, ldx, slot0, acc, direct, shape, s, deterministic); break;
     }
   }
 }

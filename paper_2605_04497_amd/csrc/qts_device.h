@@ -204,6 +204,8 @@ void launch_fill_zero(double* p, int64_t n, hipStream_t s);
 void launch_fill_uniform(float* p, int64_t n, uint32_t seed, hipStream_t s);
 void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 void launch_widen_f32_f64(const float* src, double* dst, int64_t n, hipStream_t s);
+// out[i] = sum_r part[r * n + i] over r = 0 .. nrows-1, in that order.
+void launch_sum_rows(const double* part, int64_t nrows, int64_t n, double* out, hipStream_t s);
 
 // Fill Slot0<float> (fp64 = false) or Slot0<double> for the n_rows rows of `a`
 // from leaf_val; `out` holds n_rows records.
@@ -217,10 +219,13 @@ size_t slot0_bytes(int32_t n_rows, bool fp64);
 // `direct` non-null (see values_direct) phi is written there instead.
 // nodes = 4 runs the d <= 8 bucket with the 4-node rule (exact there for
 // first order, Theorem 2); every other bucket, and nodes = 8, use 8 nodes.
+// deterministic: one wavefront per workgroup and one launch per row chunk,
+// in chunk order, each adding its tiles to acc without atomics (each (sample,
+// feature) has one owner per launch), so phi does not depend on scheduling.
 void launch_values(const HostTable& h, const DeviceTable& d, const PathArrays& a,
                    const Bucket& bk, bool fp64, const float* X, int64_t M, int64_t ldx,
                    const void* slot0, double* acc, void* direct, const ValuesShape& shape,
-                   int nodes, hipStream_t s);
+                   int nodes, hipStream_t s, bool deterministic = false);
 // True when a first-order call over `bks` (the table in use) with M samples
 // and this launch shape is one bucket walked as one chunk: each sample block
 // has a single workgroup, which may then write phi itself (launch_values with
@@ -231,10 +236,14 @@ bool values_direct(const std::vector<Bucket>& bks, int64_t M, const ValuesShape&
 // Adjoint: add J^T G over the rows of one bucket into grad_leaf (pre-zeroed);
 // a merged row adds to both of its leaves.
 // G is [M, F] float (fp64 = false) or double.
+// part_stride > 0 (deterministic): grad_leaf is [sample blocks][part_stride],
+// zeroed by the caller; each sample block stores its rows' leaf sums there
+// without atomics (every leaf belongs to one row), and the caller adds the
+// blocks in order (launch_sum_rows).
 void launch_adjoint(const HostTable& h, const DeviceTable& d, const PathArrays& a,
                     const Bucket& bk, bool fp64, const float* X, const void* G, int64_t M,
                     int64_t ldx, double* grad_leaf, const ValuesShape& shape, int nodes,
-                    hipStream_t s);
+                    hipStream_t s, int64_t part_stride = 0);
 
 // Interactions: accumulate the FP64 pair triangle [M][F(F-1)/2] and phi [M][F]
 // (both pre-zeroed) over the paths of one capacity class.

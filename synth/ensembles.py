@@ -57,6 +57,10 @@ class Ensemble:
     n_features: int
     base_score: float = 0.0
     meta: dict = field(default_factory=dict)
+    # multi-output models: output group of every tree and the number of
+    # groups (None: one output); base_score is then one value per group
+    tree_group: np.ndarray | None = None
+    n_groups: int = 1
 
     @property
     def n_trees(self) -> int:
@@ -81,7 +85,25 @@ class Ensemble:
         v[self.leaf_mask()] = np.asarray(vals, dtype=np.float64)
         return Ensemble(self.tree_offsets, self.left, self.right, self.feature,
                         self.threshold, self.default_left, self.cover, v,
-                        self.n_features, self.base_score, dict(self.meta))
+                        self.n_features, self.base_score, dict(self.meta),
+                        self.tree_group, self.n_groups)
+
+    def with_groups(self, tree_group, n_groups: int, base_scores=None) -> "Ensemble":
+        """The same trees as a multi-output model: tree t adds to output
+        tree_group[t]; base_scores[g] is output g's bias (default 0)."""
+        tg = np.ascontiguousarray(tree_group, np.int32)
+        assert tg.shape == (self.n_trees,)
+        bs = (np.zeros(n_groups) if base_scores is None
+              else np.asarray(base_scores, np.float64).reshape(n_groups))
+        return Ensemble(self.tree_offsets, self.left, self.right, self.feature,
+                        self.threshold, self.default_left, self.cover, self.value,
+                        self.n_features, bs, dict(self.meta), tg, int(n_groups))
+
+    def group_trees(self, g: int) -> list:
+        """Indices of the trees of output group g (all trees when ungrouped)."""
+        if self.tree_group is None:
+            return list(range(self.n_trees))
+        return [int(t) for t in np.flatnonzero(self.tree_group == g)]
 
     def subset_trees(self, trees) -> "Ensemble":
         trees = list(trees)
@@ -261,7 +283,8 @@ class Workload:
 def make_workload(name: str, **over) -> Workload:
     """Build a seeded workload.  Overrides (T, M, n_train, depth, F, ...) give
     scaled-down copies; the seed depends only on the config index and the
-    optional 'seed_offset' override."""
+    optional 'seed_offset' override.  groups=K makes a K-output model of the
+    same trees (tree t adds to output t mod K)."""
     cfg = dict(CONFIGS[name])
     cfg.update(over)
     seed = SEED_BASE + cfg["index"] + 1000 * int(cfg.get("seed_offset", 0))
@@ -294,6 +317,11 @@ def make_workload(name: str, **over) -> Workload:
         else:
             raise ValueError(kind)
     ens = _concat_trees(trees, F, 0.0, {"config": name, "int_cols": list(int_cols)})
+    if cfg.get("groups", 1) > 1:
+        # a multi-output model: boosting rounds add one tree per output in turn
+        K = int(cfg["groups"])
+        ens = ens.with_groups(np.arange(ens.n_trees) % K, K,
+                              base_scores=0.5 - 0.25 * np.arange(K))
     X = normal_rows(rng, cfg["M"], F, int_cols)
     target = None
     if "target_sigma" in cfg:

@@ -207,3 +207,75 @@ def test_calls_on_side_streams(q, oracle_mod):
                 check(P.cpu().numpy(), want_pairs, "fp64", "stream 2 pairs, replay %s" % replay)
     e1.close()
     e2.close()
+
+
+def test_autotune_cache_round_trip(q, oracle_mod, tmp_path):
+    """A tuned shape is written to the cache file and served from it to the
+    next ensemble of the same table without timing; a cache hit keeps
+    parity."""
+    path = tmp_path / "tune.txt"
+    wl = synth.make_workload("c2_values", T=12, M=300, n_train=20000)
+    try:
+        q.set_tune_cache(str(path))
+        e1 = q.Ensemble(wl.ensemble)
+        e1.autotune(300, "fp32")
+        h1, m1 = q.tune_cache_stats()
+        assert h1 == 0 and m1 > 0
+        lines = path.read_text().splitlines()
+        assert len(lines) == m1 and all(" -> " in ln for ln in lines)
+        assert any("kind=values" in ln for ln in lines) and any("kind=pairs" in ln
+                                                                 for ln in lines)
+        e2 = q.Ensemble(wl.ensemble)
+        e2.autotune(300, "fp32")
+        h2, m2 = q.tune_cache_stats()
+        assert h2 == m1 and m2 == m1          # every lookup of the second tuning hit
+        assert len(path.read_text().splitlines()) == m1
+        for kind, n in (("values", 1), ("adjoint", 1), ("interactions", e1.info["n_pair_classes"])):
+            for i in range(n):
+                assert e1.launch_shape(kind, "fp32", i) == e2.launch_shape(kind, "fp32", i)
+        X = torch.from_numpy(wl.X).cuda()
+        check(e2.shap_values(X, "fp32").double().cpu().numpy(),
+              oracle_mod.shap_values(wl.ensemble, wl.X, n=8), "fp32", "cached shapes")
+    finally:
+        q.set_tune_cache(None)
+
+
+@pytest.mark.parametrize("name,over", [
+    ("c2_values", dict(T=40, M=900, n_train=20000)),          # one bucket, many chunks
+    ("c5_deep", dict(T=3, M=300, n_train=30000)),             # several buckets
+    ("c2_values", dict(F=784, T=8, M=200, n_train=20000)),    # feature segments
+])
+def test_deterministic_mode_bitwise(q, oracle_mod, name, over):
+    """With the deterministic setting, phi and grad_leaf are identical bit for
+    bit across repeated calls (eager and replayed, with other launches in
+    between), and still match the oracle."""
+    print("case deterministic", name, over, flush=True)
+    wl = synth.make_workload(name, **over)
+    e = q.Ensemble(wl.ensemble)
+    e.autotune(wl.X.shape[0], "fp64")
+    e.set_deterministic(True)
+    X = torch.from_numpy(wl.X).cuda()
+    G = torch.from_numpy(np.random.default_rng(8).standard_normal(
+        (wl.X.shape[0], e.n_features))).cuda()
+    want = oracle_mod.shap_values(wl.ensemble, wl.X, n=8)
+    gwant = oracle_mod.leaf_grad(wl.ensemble, wl.X, G.cpu().numpy())
+    for precision in ("fp64", "fp32"):
+        Gp = G if precision == "fp64" else G.float()
+        runs, gruns = [], []
+        for i in range(4):
+            e.set_graph_replay(i >= 2)
+            runs.append(e.shap_values(X, precision).cpu())
+            gruns.append(e.shap_backward(X, Gp, precision).cpu())
+            torch.cuda.synchronize()
+            e.shap_values(X[: 1 + i], precision)  # other work in between
+        for r in runs[1:]:
+            assert torch.equal(r, runs[0]), precision
+        for g in gruns[1:]:
+            assert torch.equal(g, gruns[0]), precision
+        check(runs[0].double().numpy(), want, precision, "deterministic phi")
+        gw = gwant if precision == "fp64" else oracle_mod.leaf_grad(
+            wl.ensemble, wl.X, Gp.double().cpu().numpy())
+        err = float(np.abs(gruns[0].numpy() - gw).max() / np.abs(gw).max())
+        assert err <= (1e-5 if precision == "fp32" else 1e-10), err
+        e.set_graph_replay(False)
+    e.close()
