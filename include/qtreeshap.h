@@ -188,6 +188,23 @@ int qts_shap_values(const qts_ensemble* ens, const float* X, int64_t M, int64_t 
                     const double* leaf_values, void* phi, qts_precision precision,
                     void* stream);
 
+/* qts_shap_values for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same arguments, kernels and results, but the call's scratch (the
+ * per-row slot-0 records and, for QTS_FP32 calls that need it, the FP64
+ * accumulator of M * n_groups * F doubles) lives in a fixed 64 MiB device
+ * array of the library instead of a per-call allocation.  Each GPU holds its
+ * own copy of that array until the process ends.  A call whose scratch would
+ * exceed it returns QTS_E_UNSUPPORTED without launching anything: split the
+ * samples (the FP32 form of a 100-feature model takes up to about 80k samples
+ * per call).  The call runs eagerly on `stream` (graph replay does not apply)
+ * and allocates nothing.  Every call on one GPU shares that GPU's array:
+ * calls that overlap in time on one GPU (different streams or threads) race
+ * and must be serialised by the caller. */
+int qts_shap_values_noalloc(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
+                            const double* leaf_values, void* phi, qts_precision precision,
+                            void* stream);
+
 /* Pairwise interaction matrices Phi[M, F, F] (and optionally phi[M, F]; with
  * output groups [M, n_groups, F, F] and [M, n_groups, F]) with the
  * convention above.  Pair indices are the |S|=2 case of Theorem 1 and Eq. 9.
@@ -283,7 +300,7 @@ int qts_set_sibling_merge(qts_ensemble* ens, int32_t enable);
 /* Deterministic first-order and adjoint results (off by default).  phi and
  * grad_leaf are sums over paths and trees in FP64; with atomics their order,
  * and so their last bits, depend on scheduling.  While enabled:
- *   qts_shap_values runs one wavefront per
+ *   qts_shap_values (and qts_shap_values_noalloc) run one wavefront per
  *     workgroup and one launch per row chunk, in order, on the call's stream,
  *     each adding its tiles without atomics: every (sample, feature) has one
  *     writer per launch;

@@ -66,6 +66,8 @@ SIGNATURES = {
     "qts_gauss_legendre": (ctypes.c_int, [ctypes.c_int32, P, P, P]),
     "qts_shap_values": (ctypes.c_int, [P, P, ctypes.c_int64, ctypes.c_int64, P, P,
                                        ctypes.c_int, P]),
+    "qts_shap_values_noalloc": (ctypes.c_int, [P, P, ctypes.c_int64, ctypes.c_int64, P, P,
+                                               ctypes.c_int, P]),
     "qts_shap_interactions": (ctypes.c_int, [P, P, ctypes.c_int64, ctypes.c_int64, P, P, P,
                                              ctypes.c_int, P]),
     "qts_shap_interactions3": (ctypes.c_int, [P, P, ctypes.c_int64, ctypes.c_int64, P, P,

@@ -666,6 +666,34 @@ void run_graph(qts_ensemble* ens, const GraphKey& key, size_t scratch_bytes, int
 
 }  // namespace
 
+// Scratch of qts_shap_values_noalloc: a file-scope device array, so the call
+// needs no allocation.  Every GPU the library runs on holds its own copy for
+// the life of the process.  On the host the array's name is not a device
+// address: the per-device address comes from hipGetSymbolAddress.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;  // 64 MiB
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per
+// device, with that device current).
+void* noalloc_scratch() {
+  int dev = -1;
+  check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) fail(QTS_E_UNSUPPORTED, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
 [[noreturn]] void fail(int code, const std::string& msg) { throw Error{code, msg}; }
 
 void check_hip(hipError_t e, const char* what) {
@@ -881,6 +909,31 @@ int qts_shap_values(const qts_ensemble* ens, const float* X, int64_t M, int64_t 
     Lanes ln{s, nullptr};
     Scratch scratch(scratch_bytes, s);
     issue_values(ens, X, M, ldx, leaf, phi, fp64, scratch.p, ln, true);
+  });
+}
+
+int qts_shap_values_noalloc(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
+                            const double* leaf_values, void* phi, qts_precision precision,
+                            void* stream) {
+  return guarded([&] {
+    if (!ens) fail(QTS_E_INVALID_ARG, "null ensemble");
+    if (precision != QTS_FP32 && precision != QTS_FP64)
+      fail(QTS_E_INVALID_ARG, "unknown precision");
+    check_rows(ens, X, M, ldx);
+    if (M > 0 && !phi) fail(QTS_E_INVALID_ARG, "null phi");
+    require_device(ens);
+    if (M == 0) return;
+    const bool fp64 = precision == QTS_FP64;
+    const size_t need = values_scratch_bytes(ens, M, fp64);
+    if (need > kNoAllocScratchBytes)
+      fail(QTS_E_UNSUPPORTED,
+           "qts_shap_values_noalloc: this call needs " + std::to_string(need) +
+               " bytes of scratch, more than its fixed " +
+               std::to_string(kNoAllocScratchBytes) + "; use fewer samples per call");
+    void* buf = noalloc_scratch();
+    const double* leaf = leaf_values ? leaf_values : ens->dev.leaf_val;
+    Lanes ln{(hipStream_t)stream, nullptr};
+    issue_values(ens, X, M, ldx, leaf, phi, fp64, buf, ln, false);
   });
 }
 
