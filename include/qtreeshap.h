@@ -157,6 +157,12 @@ typedef struct {
                                 LDS (more than 210 features): consecutive rows
                                 using at most 96 distinct features; 0 otherwise */
   int32_t n_groups;          /* output groups (1 unless loaded grouped) */
+  int32_t pairs_dfs;         /* bit 0 (FP32), bit 1 (FP64): qts_shap_interactions takes
+                                the depth-first form */
+  int64_t n_dfs_nodes;       /* internal nodes of the depth-first interactions form
+                                (0 until qts_set_pair_traversal selects it) */
+  int64_t n_dfs_updates;     /* its pair updates per sample: the features split above
+                                each internal node, summed */
 } qts_info;
 
 int qts_get_info(const qts_ensemble* ens, qts_info* out);
@@ -327,6 +333,31 @@ int qts_set_deterministic(qts_ensemble* ens, int32_t enable);
  * ensemble's cached graphs. */
 enum { QTS_NODES_FIXED8 = 0, QTS_NODES_EXACT = 1 };
 int qts_set_node_policy(qts_ensemble* ens, int32_t policy);
+
+/* Traversal of qts_shap_interactions.
+ *   QTS_PAIRS_PATHS (default): every root-to-leaf path (or merged pair of
+ *     sibling leaves) collapsed to its unique features; each adds its
+ *     d(d-1)/2 pair terms (Theorem 1 with |S| = 2).
+ *   QTS_PAIRS_DFS: Algorithm 1 at order 2 (section 5).  A depth-first walk of
+ *     each tree carries, per sample and node t_m, the product of the factors
+ *     of the features split above the current node and returns each
+ *     subtree's summed polynomial H_u; at each internal node v on feature f
+ *     the change of f's ratio r_f = (o_f - b_f) / F_f across each child edge
+ *     (the telescoping update of Eq. 11) gives
+ *       y_v(t_m) = w_m sum_u H_u(t_m) (r_f^u - r_f^v)(t_m),
+ *     and the pair pass adds phi_f += sum_m y_v and, for every feature j
+ *     split above v, SII_fj += sum_m y_v r_j^v: one update per (internal
+ *     node, feature above it) instead of per pair of a path's features.  The
+ *     samples go in batches whose y_v values fit 4 GiB of scratch.  Same
+ *     results up to rounding, always with the 8-node rule.
+ * Selecting QTS_PAIRS_DFS builds its tables on the current device (from the
+ * tree arrays kept at load) the first time; QTS_E_UNSUPPORTED if its walk's
+ * per-level stacks do not fit in LDS.  Changing it drops the cached graphs. */
+/*   QTS_PAIRS_AUTO: the form qts_autotune finds faster on the ensemble, per
+ *     precision (timed on one batch of its synthetic rows; kept in the
+ *     autotune cache); the path form until the ensemble is tuned. */
+enum { QTS_PAIRS_PATHS = 0, QTS_PAIRS_DFS = 1, QTS_PAIRS_AUTO = 2 };
+int qts_set_pair_traversal(qts_ensemble* ens, int32_t traversal);
 
 /* HIP graph replay.  While enabled, each compute call on this ensemble is
  * captured once (on an internal stream, with its per-bucket or per-class

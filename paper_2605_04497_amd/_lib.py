@@ -44,7 +44,9 @@ class Info(ctypes.Structure):
                 ("n_pair_rows", ctypes.c_int64), ("n_pair_elements", ctypes.c_int64),
                 ("n_pair_updates", ctypes.c_int64), ("n_value_shared", ctypes.c_int64),
                 ("n_path_shared", ctypes.c_int64), ("n_value_segments", ctypes.c_int64),
-                ("n_groups", ctypes.c_int32)]
+                ("n_groups", ctypes.c_int32), ("pairs_dfs", ctypes.c_int32),
+                ("n_dfs_nodes", ctypes.c_int64),
+                ("n_dfs_updates", ctypes.c_int64)]
 
 
 # exported symbol -> (restype, argtypes)
@@ -82,6 +84,7 @@ SIGNATURES = {
     "qts_set_sibling_merge": (ctypes.c_int, [P, ctypes.c_int32]),
     "qts_set_node_policy": (ctypes.c_int, [P, ctypes.c_int32]),
     "qts_set_deterministic": (ctypes.c_int, [P, ctypes.c_int32]),
+    "qts_set_pair_traversal": (ctypes.c_int, [P, ctypes.c_int32]),
     "qts_set_tune_cache": (ctypes.c_int, [ctypes.c_char_p]),
     "qts_tune_cache_stats": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64),
                                             ctypes.POINTER(ctypes.c_int64)]),

@@ -289,6 +289,16 @@ class Ensemble:
         (default) or every path (exact same values up to rounding)."""
         L.check(L.lib().qts_set_sibling_merge(self._h, int(bool(enable))))
 
+    def set_pair_traversal(self, traversal: str = "paths"):
+        """'paths' (default): the interactions call walks collapsed paths;
+        'dfs': Algorithm 1's depth-first form (one pair update per internal
+        node and feature split above it); 'auto': the faster of the two, as
+        found by the next autotune of each precision."""
+        with torch.cuda.device(self.device):
+            L.check(L.lib().qts_set_pair_traversal(
+                self._h, {"paths": 0, "dfs": 1, "auto": 2}[traversal]))
+        self.refresh_info()
+
     def set_deterministic(self, enable: bool = True):
         """First-order values and the adjoint identical bit for bit from run to
         run (ordered sums without atomics; the values call runs slower)."""

@@ -73,6 +73,18 @@ struct qts_ensemble {
   bool deterministic = false;  // first-order and adjoint results independent of scheduling
   int node_policy = QTS_NODES_FIXED8;
   int64_t pair_rows = 0, pair_elements = 0, pair_updates = 0;  // interactions table
+  // depth-first form of the interactions (qts_set_pair_traversal): the tree
+  // arrays are kept to build its tables on first use
+  int pair_traversal = QTS_PAIRS_PATHS;
+  bool dfs_faster[2] = {false, false};  // QTS_PAIRS_AUTO: qts_autotune's choice per precision
+  struct Trees {
+    std::vector<int64_t> off;
+    std::vector<int32_t> left, right, feature;
+    std::vector<float> threshold;
+    std::vector<uint8_t> default_left;
+    std::vector<double> cover, value;
+  } trees;
+  qts::DeviceDfs dfs;
   qts::GraphCache graphs;
 };
 
@@ -203,6 +215,72 @@ void upload_paths(const std::vector<PathHdr>& hdr_in, const std::vector<int32_t>
     *o_seg_feat = upload(ct.seg_feat, s);
   }
   check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+void keep_trees(const qts_tree_arrays& t, qts_ensemble::Trees& k) {
+  const int64_t n = t.n_trees > 0 ? t.tree_offsets[t.n_trees] : 0;
+  k.off.assign(t.tree_offsets, t.tree_offsets + (t.n_trees + 1));
+  k.left.assign(t.left, t.left + n);
+  k.right.assign(t.right, t.right + n);
+  k.feature.assign(t.feature, t.feature + n);
+  k.threshold.assign(t.threshold, t.threshold + n);
+  if (t.default_left) k.default_left.assign(t.default_left, t.default_left + n);
+  else k.default_left.assign((size_t)n, 0);
+  k.cover.assign(t.cover, t.cover + n);
+  k.value.assign(t.value, t.value + n);
+}
+
+void free_dfs(DeviceDfs& d) {
+  void* ptrs[] = {d.nodes, d.coef32, d.coef64, d.events, d.tree_first, d.tree_nodes, d.row_f,
+                  d.row_d, d.tile_base, d.tile_d, d.feat, d.lo, d.hi, d.b32, d.cb32, d.b64,
+                  d.cb64};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  d = DeviceDfs{};
+}
+
+void build_dfs(qts_ensemble* e) {
+  if (e->dfs.built) return;
+  const qts_ensemble::Trees& k = e->trees;
+  qts_tree_arrays ta{(int32_t)(k.off.size() - 1), k.off.data(), k.left.data(), k.right.data(),
+                     k.feature.data(), k.threshold.data(), k.default_left.data(),
+                     k.cover.data(), k.value.data()};
+  const DfsTable t = build_dfs_table(ta, e->host);
+  DeviceDfs& d = e->dfs;
+  hipStream_t s = nullptr;
+  try {
+    d.nodes = upload(t.nodes, s);
+    const std::vector<float> c32 = narrow<float>(t.coef);
+    d.coef32 = upload(c32, s);
+    d.coef64 = upload(t.coef, s);
+    d.events = upload(t.events, s);
+    d.tree_first = upload(t.tree_first, s);
+    d.tree_nodes = upload(t.tree_nodes, s);
+    d.n_trees = (int32_t)t.tree_first.size();
+    d.max_level = t.max_level;
+    d.n_rows = t.n_rows;
+    d.row_f = upload(t.row_f, s);
+    d.row_d = upload(t.row_d, s);
+    d.tile_base = upload(t.tile_base, s);
+    d.tile_d = upload(t.tile_d, s);
+    d.feat = upload(t.feat, s);
+    d.lo = upload(t.lo, s);
+    d.hi = upload(t.hi, s);
+    const std::vector<float> b32 = narrow<float>(t.b), cb32 = narrow<float>(t.cb);
+    d.b32 = upload(b32, s);
+    d.cb32 = upload(cb32, s);
+    d.b64 = upload(t.b, s);
+    d.cb64 = upload(t.cb, s);
+    d.group_tile = t.group_tile;
+    d.n_updates = t.n_updates;
+    d.n_nodes = (int64_t)t.nodes.size();
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    d.built = true;
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    free_dfs(d);
+    throw;
+  }
 }
 
 void free_device(DeviceTable& d) {
@@ -506,6 +584,43 @@ void issue_values(const qts_ensemble* ens, const float* X, int64_t M, int64_t ld
   if (!fp64) launch_cast_f64_f32(a, (float*)phi, n, ln.main);
 }
 
+// Whether an interactions call of this precision takes the depth-first form.
+bool use_dfs(const qts_ensemble* ens, bool fp64) {
+  return ens->pair_traversal == QTS_PAIRS_DFS ||
+         (ens->pair_traversal == QTS_PAIRS_AUTO && ens->dfs_faster[fp64 ? 1 : 0]);
+}
+
+// The depth-first form takes the samples in batches whose y_v values (8 per
+// sample and internal node) fit this much scratch.
+constexpr size_t kDfsScratchBytes = (size_t)4 << 30;
+
+int32_t dfs_batch(const qts_ensemble* ens, int64_t M, bool fp64) {
+  const size_t per = (size_t)ens->dfs.n_rows * kNodes * (fp64 ? sizeof(double) : sizeof(float));
+  int64_t mb = per == 0 ? M : (int64_t)(kDfsScratchBytes / per);
+  mb = std::max<int64_t>(8, mb / 8 * 8);
+  return (int32_t)std::min<int64_t>(mb, std::max<int64_t>(M, 1));
+}
+
+// Bytes of an interactions call's scratch: the FP64 accumulators, and for the
+// depth-first form the y_v values of one batch after them.
+size_t pairs_acc_bytes(const qts_ensemble* ens, int64_t M) {
+  const int64_t F = ens->host.F;
+  const int64_t MK = M * ens->host.n_groups;
+  return sizeof(double) * (size_t)(MK * (F * (F - 1) / 2) + MK * F);
+}
+// Layout: accumulators | y values of one batch | the walk's leaf values.
+size_t dfs_y_bytes(const qts_ensemble* ens, int64_t M, bool fp64) {
+  return ((size_t)dfs_batch(ens, M, fp64) * (size_t)ens->dfs.n_rows * kNodes *
+              (fp64 ? sizeof(double) : sizeof(float)) + 255) & ~(size_t)255;
+}
+size_t interactions_scratch_bytes(const qts_ensemble* ens, int64_t M, bool fp64) {
+  size_t b = (pairs_acc_bytes(ens, M) + 255) & ~(size_t)255;
+  if (use_dfs(ens, fp64))
+    b += dfs_y_bytes(ens, M, fp64) +
+         2 * (size_t)ens->dfs.n_nodes * (fp64 ? sizeof(double) : sizeof(float));
+  return b;
+}
+
 void issue_interactions(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
                         const double* leaf, void* phi, void* Phi, bool fp64, double* acc,
                         Lanes& ln, bool timed) {
@@ -516,6 +631,29 @@ void issue_interactions(const qts_ensemble* ens, const float* X, int64_t M, int6
   double* tri64 = acc;
   double* phi64 = tri64 + MK * ntri;
   launch_fill_zero(tri64, MK * ntri + MK * F, ln.main);
+  if (use_dfs(ens, fp64)) {
+    // Algorithm 1's order-2 form: per batch, the tree walk writes y_v, then
+    // the pair pass adds its updates (the next walk reuses the y buffer)
+    void* Y = (char*)acc + ((pairs_acc_bytes(ens, M) + 255) & ~(size_t)255);
+    void* lvals = (char*)Y + dfs_y_bytes(ens, M, fp64);
+    const int32_t mb = dfs_batch(ens, M, fp64);
+    const int64_t tiles = (int64_t)ens->dfs.n_rows / 64;
+    TimedScope ts(1, timed ? ln.main : nullptr, timed);
+    for (int64_t s0 = 0; s0 < M; s0 += mb) {
+      const int32_t n = (int32_t)std::min<int64_t>(mb, M - s0);
+      // pair-pass chunks of 128 tiles (8192 rows): their elements, about 2 MB
+      // on the interactions workload, stay in each XCD's L2 while the
+      // batch's samples walk them (the next samples' workgroups follow)
+      (void)tiles;
+      const int32_t tpc = 128;
+      launch_dfs_walk(h, ens->dfs, ens->dev, fp64, leaf, X, s0, n, ldx, Y, lvals, ln.main);
+      launch_dfs_pairs(h, ens->dfs, ens->dev, fp64, X, s0, n, ldx, Y, tri64, phi64, tpc,
+                       ln.main);
+    }
+    ts.done();
+    launch_pairs_finalize(tri64, phi64, MK, (int)F, fp64, Phi, phi, ln.main);
+    return;
+  }
   TimedScope ts(1, timed ? ln.main : nullptr, timed);
   ln.fork((int)ens->pair_classes.size());
   for (size_t i = 0; i < ens->pair_classes.size(); ++i)
@@ -739,6 +877,7 @@ int qts_load_ensemble_grouped(const qts_tree_arrays* trees, const int32_t* tree_
     qts_ensemble* e = new qts_ensemble();
     try {
       e->host = build_host_table(*trees, n_features, n_groups, tree_group, base_scores);
+      keep_trees(*trees, e->trees);
       const HostTable& h = e->host;
       hipStream_t s = (hipStream_t)stream;
       DeviceTable& d = e->dev;
@@ -798,7 +937,10 @@ int qts_free_ensemble(qts_ensemble* ens) {
       std::lock_guard<std::mutex> lock(ens->graphs.mu);
       release_graph_cache(ens->graphs);
     }
-    if (ens->on_device) free_device(ens->dev);
+    if (ens->on_device) {
+      free_dfs(ens->dfs);
+      free_device(ens->dev);
+    }
     delete ens;
   });
 }
@@ -851,6 +993,9 @@ int qts_get_info(const qts_ensemble* ens, qts_info* out) {
     for (int32_t v : h.share) out->n_path_shared += v;
     out->n_value_segments = (int64_t)h.mcompact.segs.size();
     out->n_groups = h.n_groups;
+    out->pairs_dfs = (use_dfs(ens, false) ? 1 : 0) | (use_dfs(ens, true) ? 2 : 0);
+    out->n_dfs_nodes = ens->dfs.n_nodes;
+    out->n_dfs_updates = ens->dfs.n_updates;
   });
 }
 
@@ -950,10 +1095,8 @@ int qts_shap_interactions(const qts_ensemble* ens, const float* X, int64_t M, in
     if (M == 0) return;
     hipStream_t s = (hipStream_t)stream;
     const bool fp64 = precision == QTS_FP64;
-    const int64_t F = ens->host.F;
-    const int64_t MK = M * ens->host.n_groups;
     const double* leaf = leaf_values ? leaf_values : ens->dev.leaf_val;
-    const size_t acc_bytes = sizeof(double) * (size_t)(MK * (F * (F - 1) / 2) + MK * F);
+    const size_t acc_bytes = interactions_scratch_bytes(ens, M, fp64);
     qts_ensemble* me = const_cast<qts_ensemble*>(ens);
     if (ens->graphs.on) {
       GraphKey key{1, fp64, X, M, ldx, leaf, Phi, phi, s};
@@ -1068,6 +1211,24 @@ int qts_set_sibling_merge(qts_ensemble* ens, int32_t enable) {
     std::lock_guard<std::mutex> lock(ens->graphs.mu);
     if (ens->merge_siblings != (enable != 0)) clear_graphs(ens->graphs);
     ens->merge_siblings = enable != 0;
+  });
+}
+
+int qts_set_pair_traversal(qts_ensemble* ens, int32_t traversal) {
+  return guarded([&] {
+    if (!ens) fail(QTS_E_INVALID_ARG, "null ensemble");
+    if (traversal != QTS_PAIRS_PATHS && traversal != QTS_PAIRS_DFS &&
+        traversal != QTS_PAIRS_AUTO)
+      fail(QTS_E_INVALID_ARG, "unknown pair traversal");
+    std::lock_guard<std::mutex> lock(ens->graphs.mu);
+    if (traversal != QTS_PAIRS_PATHS) {
+      require_device(ens);
+      if (dfs_walk_lds_bytes(ens->host.F, ens->host.max_depth, true) > (size_t)kMaxLdsBytes)
+        fail(QTS_E_UNSUPPORTED, "the depth-first walk's stacks do not fit in LDS");
+      build_dfs(ens);
+    }
+    if (ens->pair_traversal != traversal) clear_graphs(ens->graphs);
+    ens->pair_traversal = traversal;
   });
 }
 
@@ -1248,6 +1409,32 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
           tune_cache_put(key, best.max_chunk, best.fill);
         }
         out[i] = best;
+      }
+      // QTS_PAIRS_AUTO: time a whole interactions pass both ways on the same
+      // rows (at most one depth-first batch) and keep the faster form
+      if (ens->pair_traversal == QTS_PAIRS_AUTO && ens->dfs.built) {
+        const std::string key = tune_key(device, "traversal", fp64, pol, h, 0, 0,
+                                         ens->dfs.n_nodes, m_class);
+        int choice = -1, unused = 0;
+        if (!tune_cache_get(key, &choice, &unused)) {
+          const int32_t md = (int32_t)std::min<int64_t>(Mp, dfs_batch(ens, Mp, fp64));
+          Scratch y((size_t)md * (size_t)ens->dfs.n_rows * kNodes *
+                        (fp64 ? sizeof(double) : sizeof(float)) + 256, s);
+          Scratch lv(2 * (size_t)std::max<int64_t>(1, ens->dfs.n_nodes) *
+                         (fp64 ? sizeof(double) : sizeof(float)), s);
+          const float t_paths = time_ms(1, [&] {
+            for (size_t i = 0; i < ens->pair_classes.size(); ++i)
+              launch_pairs(h, d, ens->pair_classes[i], fp64, X, md, F, d.leaf_val, tri64, phi64,
+                           out[i], ens->node_policy == QTS_NODES_EXACT, s);
+          });
+          const float t_dfs = time_ms(1, [&] {
+            launch_dfs_walk(h, ens->dfs, d, fp64, d.leaf_val, X, 0, md, F, y.p, lv.p, s);
+            launch_dfs_pairs(h, ens->dfs, d, fp64, X, 0, md, F, y.p, tri64, phi64, 128, s);
+          });
+          choice = t_dfs < t_paths ? 1 : 0;
+          tune_cache_put(key, choice, 0);
+        }
+        ens->dfs_faster[pi] = choice == 1;
       }
     }
     check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");

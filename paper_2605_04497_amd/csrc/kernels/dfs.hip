@@ -1,0 +1,402 @@
+// Depth-first form of the pairwise interactions (section 5, Algorithm 1 at
+// order 2, with Eq. 11's telescoping update for repeated features); the
+// notation and the formulas are those of DfsTable (qts_internal.h).
+//
+// dfs_walk_kernel: the tree walk.  A wavefront walks one tree for 8 samples,
+// lane = (sample, node m), so the walk is uniform across the wave and every
+// node record is read with scalar loads.  Each lane carries the product C of
+// the factors of the features split above the current node at t_m, kept on
+// a per-level stack in LDS while a subtree is walked, and returns up the tree
+// H_u(t_m), the sum of val * C over the leaves below u.  At each internal
+// node it stores y_v(t_m) = w_m sum_u H_u (r_f^u - r_f^v)(t_m) for the pair
+// pass.  Entering child u multiplies C by F_f^u / F_f^v (a division only when
+// f was split above); a factor that vanishes identically (b = o = 0) makes
+// the subtree's polynomials zero, and the guards keep its terms exactly zero.
+//
+// dfs_pairs_kernel: the pair pass.  A workgroup owns one sample (its pair
+// triangle and phi row in LDS, FP64, as in the path form); lane = internal
+// node (rows sorted by length in tiles of 64, slot-major inside a tile).  A
+// row adds phi_f += sum_m y_v(m) and, for every feature j split above v,
+// SII_fj += c_j sum_m y_v(m) / F_j(t_m): one update per (node, feature).
+#include <hip/hip_runtime.h>
+
+#include "../qts_device.h"
+
+namespace qts {
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ T fmaD(T a, T b, T c) {
+  return __builtin_fma(a, b, c);
+}
+template <>
+__device__ __forceinline__ float fmaD<float>(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+
+__device__ __forceinline__ float rcpD(float x) { return __builtin_amdgcn_rcpf(x); }
+// FP64: the hardware estimate and two Newton steps (see the pairs kernel).
+__device__ __forceinline__ double rcpD(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+// x follows the splits of an interval [lo, hi) (hi NaN: no upper bound); a
+// NaN x follows them iff mok.
+__device__ __forceinline__ bool follows(float x, float lo, float hi, bool mok) {
+  const bool lower = mok ? !(x < lo) : (x >= lo);
+  return lower & !(x >= hi);
+}
+
+}  // namespace
+
+constexpr int kDfsSamples = 8;  // samples per wavefront of the walk (8 lanes each)
+
+// LDS of the walk: the sample rows of the workgroup's 8 samples (stride F+1),
+// then per wave the two stacks [level][64] of C and of the left subtree's H.
+__host__ __device__ inline size_t dfs_walk_lds(int F, int levels, int waves, size_t tsize) {
+  const size_t xs = (((size_t)kDfsSamples * (F + 1) * sizeof(float)) + 15) & ~(size_t)15;
+  return xs + (size_t)waves * 2 * levels * 64 * tsize;
+}
+
+// Lane k's value, wave-uniform.
+__device__ __forceinline__ int bcast(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
+__device__ __forceinline__ float bcast(float v, int k) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+__device__ __forceinline__ double bcast(double v, int k) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), k);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024)
+dfs_walk_kernel(const DfsNode* __restrict__ nodes, const T* __restrict__ coef,
+                const T* __restrict__ lvals, const int32_t* __restrict__ events,
+                const int32_t* __restrict__ tree_first, const int32_t* __restrict__ tree_nodes,
+                int32_t n_trees, const float* __restrict__ X, int64_t s0, int32_t mb,
+                int64_t ldx, int32_t F, int32_t levels, int32_t nsg, int32_t n_rows,
+                T* __restrict__ Y, NodeConsts<T> nc) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int waves = blockDim.x >> 6;
+  const int sg = blockIdx.x % nsg;            // group of 8 samples
+  const int tb = blockIdx.x / nsg;            // block of `waves` trees
+  float* xs = reinterpret_cast<float*>(smem);
+  const int xstride = F + 1;
+  for (int i = threadIdx.x; i < kDfsSamples * F; i += blockDim.x) {
+    const int q = i / F, f = i - q * F;
+    const int sl = sg * kDfsSamples + q;
+    xs[q * xstride + f] = sl < mb ? X[(s0 + sl) * ldx + f] : 0.0f;
+  }
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int ti = tb * waves + wave;
+  if (ti >= n_trees) return;
+  const int lane = threadIdx.x & 63;
+  const int q = lane >> 3, m = lane & 7;
+  const int sl = sg * kDfsSamples + q;         // sample within the batch
+  const bool valid = sl < mb;
+  const size_t xs_bytes = (((size_t)kDfsSamples * xstride * sizeof(float)) + 15) & ~(size_t)15;
+  T* cst = reinterpret_cast<T*>(smem + xs_bytes) + (size_t)wave * 2 * levels * 64;
+  T* hst = cst + (size_t)levels * 64;
+  const float* xrow = xs + q * xstride;
+  T tm = nc.t[0], wm = nc.w[0];
+#pragma unroll
+  for (int k = 1; k < kNodes; ++k) {
+    tm = m == k ? nc.t[k] : tm;
+    wm = m == k ? nc.w[k] : wm;
+  }
+
+  const int first = __builtin_amdgcn_readfirstlane(tree_first[ti]);
+  const int n_ev = 3 * __builtin_amdgcn_readfirstlane(tree_nodes[ti]);
+  const int32_t* ev = events + 3 * (size_t)first;
+  T C = T(1), H = T(0);
+  // Windows of 64 events: lane i loads event i of the window and its node
+  // data with one coalesced load per field, and the walk reads them back
+  // with lane broadcasts, so its sequential steps wait on no memory.
+  for (int w0 = 0; w0 < n_ev; w0 += 64) {
+    const int nwin = min(64, n_ev - w0);
+    const int e = ev[w0 + min(lane, nwin - 1)];
+    const int r = e >> 2;
+    const int4* p4 = reinterpret_cast<const int4*>(nodes + r);
+    const int4 ra = p4[0], rc = p4[2], rd = p4[3];
+    T cf[kDfsCoef];
+#pragma unroll
+    for (int k = 0; k < kDfsCoef; ++k) cf[k] = coef[(size_t)r * kDfsCoef + k];
+    const T lv0 = lvals[2 * (size_t)r], lv1 = lvals[2 * (size_t)r + 1];
+    // pass 1: whether this lane's sample follows f's splits above each
+    // event's node (ov), and on the left (ol) and right (or) edges; the steps
+    // are independent, so their LDS reads overlap
+    uint64_t bov = 0, bol = 0, bor = 0;
+    for (int k = 0; k < nwin; ++k) {
+      const int f = bcast(ra.x, k);
+      const int flags = bcast(ra.w, k);
+      const float x = xrow[f];
+      const uint64_t bit = (uint64_t)1 << k;
+      if (follows(x, bcast(__int_as_float(rc.y), k), bcast(__int_as_float(rc.z), k),
+                  (flags & kDfsMokV) != 0)) bov |= bit;
+      if (follows(x, bcast(__int_as_float(rc.w), k), bcast(__int_as_float(rd.x), k),
+                  (flags & kDfsMokL) != 0)) bol |= bit;
+      if (follows(x, bcast(__int_as_float(rd.y), k), bcast(__int_as_float(rd.z), k),
+                  (flags & kDfsMokR) != 0)) bor |= bit;
+    }
+    // pass 2: the walk's steps in order
+    for (int k = 0; k < nwin; ++k) {
+      const int kind = bcast(e, k) & 3;
+      const int level = bcast(ra.y, k);
+      const int flags = bcast(ra.w, k);
+      const bool ov = (bov >> k) & 1;
+      const T bv = bcast(cf[0], k), cbv = bcast(cf[1], k);
+      const T Fv = fmaD(tm, ov ? cbv : -bv, bv);
+      const bool fresh = (flags & kDfsFresh) != 0;
+      if (kind == kDfsEnter) {
+        const T bl = bcast(cf[2], k), cbl = bcast(cf[3], k);
+        const T Fl = fmaD(tm, ((bol >> k) & 1) ? cbl : -bl, bl);
+        cst[level * 64 + lane] = C;
+        // C times F_f^u / F_f^v; F_f^v = 1 when f is not split above v, and a
+        // vanishing F_f^v leaves the whole subtree at zero
+        C = fresh ? C * Fl : (Fv == T(0) ? T(0) : C * Fl * rcpD(Fv));
+        H = bcast(lv0, k) * C;  // used only when the left child is a leaf
+      } else if (kind == kDfsMiddle) {
+        const T br = bcast(cf[4], k), cbr = bcast(cf[5], k);
+        const T Fr = fmaD(tm, ((bor >> k) & 1) ? cbr : -br, br);
+        hst[level * 64 + lane] = H;
+        const T Cv = cst[level * 64 + lane];
+        C = fresh ? Cv * Fr : (Fv == T(0) ? T(0) : Cv * Fr * rcpD(Fv));
+        H = bcast(lv1, k) * C;
+      } else {
+        // both subtrees done: H holds H_R, the stack H_L
+        const bool ol = (bol >> k) & 1, orr = (bor >> k) & 1;
+        const T bl = bcast(cf[2], k), cbl = bcast(cf[3], k);
+        const T br = bcast(cf[4], k), cbr = bcast(cf[5], k);
+        const T Fl = fmaD(tm, ol ? cbl : -bl, bl);
+        const T Fr = fmaD(tm, orr ? cbr : -br, br);
+        const T HL = hst[level * 64 + lane];
+        const T nl = ol ? bcast(cf[6], k) : (ov ? -bl : T(0));
+        const T nr = orr ? bcast(cf[7], k) : (ov ? -br : T(0));
+        const T tl = (Fl == T(0) || Fv == T(0)) ? T(0) : HL * nl * rcpD(Fl * Fv);
+        const T tr = (Fr == T(0) || Fv == T(0)) ? T(0) : H * nr * rcpD(Fr * Fv);
+        if (valid) Y[((int64_t)sl * n_rows + bcast(rc.x, k)) * kNodes + m] = wm * (tl + tr);
+        H = HL + H;
+      }
+    }
+  }
+}
+
+// Per-call values of each record's leaf children (0 for an internal child),
+// from the current leaf values, in the walk's precision.
+template <typename T>
+__global__ void __launch_bounds__(256)
+dfs_leaf_values_kernel(const DfsNode* __restrict__ nodes, int32_t n,
+                       const double* __restrict__ leaf_val, T* __restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int l = nodes[r].leaf_l, rr = nodes[r].leaf_r;
+  out[2 * (size_t)r] = l >= 0 ? (T)leaf_val[l] : T(0);
+  out[2 * (size_t)r + 1] = rr >= 0 ? (T)leaf_val[rr] : T(0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512)
+dfs_pairs_kernel(const int32_t* __restrict__ row_f, const int32_t* __restrict__ row_d,
+                 const int32_t* __restrict__ tile_base, const int32_t* __restrict__ tile_d,
+                 const int32_t* __restrict__ feat, const float* __restrict__ lo,
+                 const float* __restrict__ hi, const T* __restrict__ bb,
+                 const T* __restrict__ cbb, int32_t t0, int32_t t1, int32_t chunk,
+                 const T* __restrict__ Y, int32_t n_rows, const float* __restrict__ X,
+                 int64_t s0, int32_t mb, int64_t ldx, int32_t F, int32_t r0, int32_t r1,
+                 int32_t with_phi, int32_t ng, int32_t grp, double* __restrict__ tri64,
+                 double* __restrict__ phi64, NodeConsts<T> nc) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t ntri = (int64_t)F * (F - 1) / 2;
+  const int64_t base0 = (int64_t)r0 * (r0 - 1) / 2;
+  const int64_t ntri_r = (int64_t)r1 * (r1 - 1) / 2 - base0;
+  double* phis = reinterpret_cast<double*>(smem);  // [F]
+  double* tris = phis + F;                         // [ntri_r]
+  float* xrow = reinterpret_cast<float*>(tris + ntri_r);  // [F]
+  const int sl = (int)(blockIdx.x % (unsigned)mb);
+  const int ch = (int)(blockIdx.x / (unsigned)mb);
+  const int64_t s = s0 + sl;
+  for (int i = threadIdx.x; i < F; i += blockDim.x) {
+    xrow[i] = X[s * ldx + i];
+    phis[i] = 0.0;
+  }
+  for (int64_t e = threadIdx.x; e < ntri_r; e += blockDim.x) tris[e] = 0.0;
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int tb0 = t0 + ch * chunk;
+  const int tb1 = min(t1, tb0 + chunk);
+  for (int tile = tb0 + wave; tile < tb1; tile += nw) {
+    const int row = tile * 64 + lane;
+    const int f = row_f[row];
+    const int d = row_d[row];
+    T y[kNodes];
+    T ysum = T(0);
+    const T* yp = Y + ((int64_t)sl * n_rows + row) * kNodes;
+#pragma unroll
+    for (int k = 0; k < kNodes; ++k) {
+      y[k] = f >= 0 ? yp[k] : T(0);
+      ysum += y[k];
+    }
+    if (with_phi && f >= 0 && ysum != T(0))
+      __hip_atomic_fetch_add(&phis[f], (double)ysum, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+    const int eb = __builtin_amdgcn_readfirstlane(tile_base[tile]);
+    const int td = __builtin_amdgcn_readfirstlane(tile_d[tile]);
+    // slots in groups of four: every load of a group issues before its first
+    // use, so the wave waits for memory once per group, not once per slot
+    for (int k0 = 0; k0 < td; k0 += 4) {
+      int fm[4];
+      float l[4], u[4], xv[4];
+      T bq[4], cq[4];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int e = eb + 64 * min(k0 + w, td - 1) + lane;
+        fm[w] = feat[e];
+        l[w] = lo[e];
+        u[w] = hi[e];
+        bq[w] = bb[e];
+        cq[w] = cbb[e];
+      }
+#pragma unroll
+      for (int w = 0; w < 4; ++w) xv[w] = xrow[fm[w] & kFeatureMask];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int k = k0 + w;
+        const T b = bq[w];
+        const bool o = follows(xv[w], l[w], u[w], (fm[w] & kMissingOkBit) != 0);
+        const T c = o ? cq[w] : -b;
+        // a factor that vanishes identically zeroes every leaf below (y = 0)
+        if (k < d && f >= 0 && !(b == T(0) && c == T(0))) {
+          T acc = y[0] * rcpD(fmaD(nc.t[0], c, b));
+#pragma unroll
+          for (int m = 1; m < kNodes; ++m) acc = fmaD(y[m], rcpD(fmaD(nc.t[m], c, b)), acc);
+          const T v = c * acc;
+          const int j = fm[w] & kFeatureMask;
+          const int a = min(f, j), zf = max(f, j);
+          if (zf >= r0 && zf < r1 && v != T(0))
+            __hip_atomic_fetch_add(&tris[(int64_t)zf * (zf - 1) / 2 + a - base0], (double)v,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int64_t orow = s * ng + grp;
+  if (with_phi)
+    for (int i = threadIdx.x; i < F; i += blockDim.x) {
+      const double v = phis[i];
+      if (v != 0.0) unsafeAtomicAdd(&phi64[orow * F + i], v);
+    }
+  for (int64_t e = threadIdx.x; e < ntri_r; e += blockDim.x) {
+    const double v = tris[e];
+    if (v != 0.0) unsafeAtomicAdd(&tri64[orow * ntri + base0 + e], v);
+  }
+}
+
+namespace {
+
+int64_t tri_h(int64_t k) { return k * (k - 1) / 2; }
+
+template <typename T>
+void walk_t(const HostTable& h, const DeviceDfs& d, const NodeConsts<T>& nc,
+            const double* leaf_val, const float* X, int64_t s0, int32_t mb, int64_t ldx, T* Y,
+            T* lvals, hipStream_t s) {
+  const int F = h.F;
+  const int levels = d.max_level + 1;
+  if (s0 == 0 && d.n_nodes > 0) {
+    hipLaunchKernelGGL((dfs_leaf_values_kernel<T>), dim3((unsigned)((d.n_nodes + 255) / 256)),
+                       dim3(256), 0, s, d.nodes, (int32_t)d.n_nodes, leaf_val, lvals);
+    check_hip(hipGetLastError(), "dfs_leaf_values_kernel launch");
+  }
+  const size_t limit = raise_lds_limit((const void*)dfs_walk_kernel<T>);
+  // as many waves (trees) per workgroup as the stacks allow, up to 16: the
+  // walk is bound by the latency of its sequential steps, which more waves hide
+  int waves = 16;
+  while (waves > 1 && dfs_walk_lds(F, levels, waves, sizeof(T)) > limit) --waves;
+  const size_t lds = dfs_walk_lds(F, levels, waves, sizeof(T));
+  if (lds > limit) fail(QTS_E_UNSUPPORTED, "internal: tree too deep for the depth-first walk");
+  const int nsg = (mb + kDfsSamples - 1) / kDfsSamples;
+  const int n_tb = (d.n_trees + waves - 1) / waves;
+  const int64_t grid = (int64_t)nsg * n_tb;
+  if (grid <= 0) return;
+  if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "depth-first walk grid too large");
+  const T* coef = std::is_same<T, float>::value ? (const T*)d.coef32 : (const T*)d.coef64;
+  hipLaunchKernelGGL((dfs_walk_kernel<T>), dim3((unsigned)grid), dim3(64 * waves), lds, s,
+                     d.nodes, coef, (const T*)lvals, d.events, d.tree_first, d.tree_nodes,
+                     d.n_trees, X, s0, mb, ldx, F, levels, nsg, d.n_rows, Y, nc);
+  check_hip(hipGetLastError(), "dfs_walk_kernel launch");
+}
+
+template <typename T>
+void pairs_t(const HostTable& h, const DeviceDfs& d, const NodeConsts<T>& nc, const float* X,
+             int64_t s0, int32_t mb, int64_t ldx, const T* Y, double* tri64, double* phi64,
+             int32_t tiles_per_chunk, hipStream_t s) {
+  const int F = h.F;
+  const void* fn = (const void*)dfs_pairs_kernel<T>;
+  const size_t limit = raise_lds_limit(fn);
+  const size_t fixed = (size_t)F * sizeof(double) + (size_t)F * sizeof(float);
+  if (fixed >= limit) fail(QTS_E_UNSUPPORTED, "n_features too large for the interactions kernel");
+  // triangle rows [r0, r1) whose FP64 entries fit beside the fixed part
+  const int64_t cap = (int64_t)((limit - fixed) / sizeof(double));
+  if (cap < F) fail(QTS_E_UNSUPPORTED, "n_features too large for the interactions kernel");
+  for (int g = 0; g < h.n_groups; ++g) {
+    const int t0 = d.group_tile[g], t1 = d.group_tile[g + 1];
+    if (t1 <= t0) continue;
+    const int chunk = std::max(1, tiles_per_chunk);
+    const int64_t n_chunks = (t1 - t0 + chunk - 1) / chunk;
+    const int64_t grid = (int64_t)mb * n_chunks;
+    if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "depth-first pair grid too large");
+    const T* b = std::is_same<T, float>::value ? (const T*)d.b32 : (const T*)d.b64;
+    const T* cb = std::is_same<T, float>::value ? (const T*)d.cb32 : (const T*)d.cb64;
+    bool first = true;
+    int r0 = 0;
+    while (r0 < F) {
+      int r1 = r0 + 1;
+      while (r1 < F && tri_h(r1 + 1) - tri_h(r0) <= cap) ++r1;
+      const size_t lds = fixed + (size_t)(tri_h(r1) - tri_h(r0)) * sizeof(double);
+      hipLaunchKernelGGL((dfs_pairs_kernel<T>), dim3((unsigned)grid), dim3(512), lds, s,
+                         d.row_f, d.row_d, d.tile_base, d.tile_d, d.feat, d.lo, d.hi, b, cb, t0,
+                         t1, chunk, Y, d.n_rows, X, s0, mb, ldx, F, r0, r1, (int)first,
+                         h.n_groups, g, tri64, phi64, nc);
+      check_hip(hipGetLastError(), "dfs_pairs_kernel launch");
+      first = false;
+      r0 = r1;
+    }
+  }
+}
+
+}  // namespace
+
+size_t dfs_walk_lds_bytes(int F, int max_level, bool fp64) {
+  return dfs_walk_lds(F, max_level + 1, 1, fp64 ? sizeof(double) : sizeof(float));
+}
+
+void launch_dfs_walk(const HostTable& h, const DeviceDfs& d, const DeviceTable& dt, bool fp64,
+                     const double* leaf_val, const float* X, int64_t s0, int32_t mb,
+                     int64_t ldx, void* Y, void* lvals, hipStream_t s) {
+  if (fp64) walk_t<double>(h, d, dt.n64, leaf_val, X, s0, mb, ldx, (double*)Y, (double*)lvals, s);
+  else walk_t<float>(h, d, dt.n32, leaf_val, X, s0, mb, ldx, (float*)Y, (float*)lvals, s);
+}
+
+void launch_dfs_pairs(const HostTable& h, const DeviceDfs& d, const DeviceTable& dt, bool fp64,
+                      const float* X, int64_t s0, int32_t mb, int64_t ldx, const void* Y,
+                      double* tri64, double* phi64, int32_t tiles_per_chunk, hipStream_t s) {
+  if (fp64)
+    pairs_t<double>(h, d, dt.n64, X, s0, mb, ldx, (const double*)Y, tri64, phi64,
+                    tiles_per_chunk, s);
+  else
+    pairs_t<float>(h, d, dt.n32, X, s0, mb, ldx, (const float*)Y, tri64, phi64,
+                   tiles_per_chunk, s);
+}
+
+}  // namespace qts

@@ -64,6 +64,34 @@ struct DeviceTable {
   NodeConsts<double> n64_2, n64_6;
 };
 
+// Device copy of the depth-first tables (DfsTable).
+struct DeviceDfs {
+  bool built = false;
+  DfsNode* nodes = nullptr;
+  float* coef32 = nullptr;
+  double* coef64 = nullptr;
+  int32_t* events = nullptr;       // DfsTable::events
+  int32_t* tree_first = nullptr;
+  int32_t* tree_nodes = nullptr;
+  int32_t n_trees = 0;
+  int32_t max_level = 0;
+  int32_t n_rows = 0;
+  int32_t* row_f = nullptr;
+  int32_t* row_d = nullptr;
+  int32_t* tile_base = nullptr;
+  int32_t* tile_d = nullptr;
+  int32_t* feat = nullptr;
+  float* lo = nullptr;
+  float* hi = nullptr;
+  float* b32 = nullptr;
+  float* cb32 = nullptr;
+  double* b64 = nullptr;
+  double* cb64 = nullptr;
+  std::vector<int32_t> group_tile;  // host copy: tiles of each output group
+  int64_t n_updates = 0;            // pair updates per sample
+  int64_t n_nodes = 0;              // internal nodes
+};
+
 // The arrays one first-order (or adjoint) launch walks.
 struct PathArrays {
   const PathHdr* hdr;
@@ -260,6 +288,18 @@ void launch_triples(const HostTable& h, const DeviceTable& d, const PairClass& p
                     const float* X, int64_t M, int64_t ldx, const double* lv, double* acc,
                     hipStream_t s);
 void launch_narrow_f64_f32(const double* acc, int64_t n, float* out, hipStream_t s);
+
+// Depth-first interactions (DfsTable): the walk writes y_v(t_m) of samples
+// [s0, s0 + mb) to Y[mb][n_rows][8] (T by precision); the pair pass adds their
+// pair and first-order updates into the FP64 accumulators of those samples.
+size_t dfs_walk_lds_bytes(int F, int max_level, bool fp64);
+// lvals: 2 values per record (T), filled from leaf_val by the launch with s0 = 0.
+void launch_dfs_walk(const HostTable& h, const DeviceDfs& d, const DeviceTable& dt, bool fp64,
+                     const double* leaf_val, const float* X, int64_t s0, int32_t mb,
+                     int64_t ldx, void* Y, void* lvals, hipStream_t s);
+void launch_dfs_pairs(const HostTable& h, const DeviceDfs& d, const DeviceTable& dt, bool fp64,
+                      const float* X, int64_t s0, int32_t mb, int64_t ldx, const void* Y,
+                      double* tri64, double* phi64, int32_t tiles_per_chunk, hipStream_t s);
 void launch_pairs_finalize(const double* tri64, const double* phi64, int64_t M, int F, bool fp64,
                            void* Phi, void* phi, hipStream_t s);
 

@@ -156,6 +156,73 @@ struct PairTable {
 
 PairTable build_pair_table(const HostTable& h);
 
+// Tables of the depth-first form of the interactions (section 5, Algorithm 1
+// at order 2, with the telescoping update of Eq. 11).  For an internal node v
+// with split feature f and children u, let (b_j, o_j) be feature j's cover
+// product and follow indicator over the splits on j above v (b = o = 1 when
+// j is not split there), F_j = b_j + t (o_j - b_j), r_j = (o_j - b_j) / F_j,
+// and H_u(t) the sum over the leaves below u of val * prod F (the leaf's own
+// factors).  Summing the change of r_f across the edge v -> u over the
+// subtree, with every other feature at its value at v, gives
+//   y_v(t_m) = w_m sum_u H_u(t_m) (r_f^u - r_f^v)(t_m),
+//   phi_f   += sum_m y_v(t_m),
+//   SII_fj  += sum_m y_v(t_m) r_j^v(t_m)   for the features j != f split above v,
+// and the telescoping sum over a path's edges reproduces Theorem 1's
+// products.  The change of r is taken without cancellation as
+//   r_f^u - r_f^v = (o^u b^v - o^v b^u) / (F^u F^v),
+// and o^u b^v - o^v b^u is b^v - b^u (FP64 from the covers), -b^u or 0.
+// The tree walk (one wavefront per tree and group of samples) forms y_v for
+// every internal node; the pair pass (lane per node) adds the updates.
+struct alignas(16) DfsNode {
+  int32_t f;        // split feature
+  int32_t level;    // depth of the node (root 0)
+  int32_t parent;   // record of the parent node, -1 at the root
+  int32_t flags;    // kDfs* bits
+  int32_t left, right;      // records of internal children, -1 for a leaf
+  int32_t leaf_l, leaf_r;   // leaf ordinals of leaf children, -1 otherwise
+  int32_t row;      // the node's row of the pair pass (where y_v is stored)
+  float lo_v, hi_v;         // the interval of f's splits above v (no bound: -inf / NaN)
+  float lo_l, hi_l, lo_r, hi_r;  // the same including the edge to each child
+  int32_t pad;
+};
+constexpr int32_t kDfsLeftChild = 1;  // the node is its parent's left child
+constexpr int32_t kDfsFresh = 2;      // f is not split above the node
+constexpr int32_t kDfsMokV = 4;       // a NaN follows every split on f above the node
+constexpr int32_t kDfsMokL = 8;       // ... and the edge to the left child
+constexpr int32_t kDfsMokR = 16;      // ... and the edge to the right child
+// Per node, FP64: b^v, 1 - b^v, b^L, 1 - b^L, b^R, 1 - b^R, b^v - b^L, b^v - b^R.
+constexpr int kDfsCoef = 8;
+
+// The walk of a tree as a linear stream of events, in the order a depth-first
+// walk meets them: per internal node, enter (go down the left edge), middle
+// (left subtree done, go down the right edge) and exit (both done).  An event
+// is record << 2 | kind, so the walk reads its control in order instead of
+// following child and parent links.
+constexpr int32_t kDfsEnter = 0, kDfsMiddle = 1, kDfsExit = 2;
+
+struct DfsTable {
+  std::vector<DfsNode> nodes;    // per tree, internal nodes in preorder
+  std::vector<double> coef;      // kDfsCoef per node
+  std::vector<int32_t> events;   // per tree, 3 per internal node
+  std::vector<int32_t> tree_first, tree_nodes;  // trees with a split, largest first
+                                               // (first record; events start at 3 x it)
+  int32_t max_level = 0;
+  // pair pass: one row per internal node, rows of a group sorted by length
+  // and padded to whole tiles of 64 rows; element (slot k, lane i) of tile t
+  // at tile_base[t] + 64 k + i (slot-major inside the tile)
+  int32_t n_rows = 0;
+  std::vector<int32_t> row_f;    // split feature (-1: padding row)
+  std::vector<int32_t> row_d;    // features split above the node, other than f
+  std::vector<int32_t> tile_base, tile_d;
+  std::vector<int32_t> group_tile;  // [n_groups + 1]: tiles of each group
+  std::vector<int32_t> feat;     // feature | missing_ok
+  std::vector<float> lo, hi;
+  std::vector<double> b, cb;
+  int64_t n_updates = 0;         // sum of row_d: pair updates per sample
+};
+
+DfsTable build_dfs_table(const qts_tree_arrays& t, const HostTable& h);
+
 // Golub-Welsch: n-node Gauss-Legendre rule on [0,1] in FP64.
 void gauss_legendre(int n, double* t, double* one_minus_t, double* w);
 

@@ -63,10 +63,13 @@ int main(int argc, char** argv) {
     }
     int64_t pair_updates = 0;
     for (int32_t d : pt.d) pair_updates += (int64_t)d * (d - 1) / 2;
+    const qts::DfsTable dt = qts::build_dfs_table(ta, h);
     std::printf("ok paths=%zu elements=%zu merged_rows=%zu pair_rows=%zu pair_updates=%lld "
-                "segments=%zu expected=%.17g wsum=%.17g\n",
+                "segments=%zu dfs_nodes=%zu dfs_updates=%lld dfs_rows=%d expected=%.17g "
+                "wsum=%.17g\n",
                 h.hdr.size(), h.feat.size(), h.mhdr.size(), pt.d.size(),
-                (long long)pair_updates, h.mcompact.segs.size(), h.expected, wsum);
+                (long long)pair_updates, h.mcompact.segs.size(), dt.nodes.size(),
+                (long long)dt.n_updates, dt.n_rows, h.expected, wsum);
   } catch (const qts::Error& e) {
     std::printf("error %d %s\n", e.code, e.msg.c_str());
   }

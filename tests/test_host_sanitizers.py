@@ -27,6 +27,7 @@ def driver(tmp_path_factory):
            "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            os.path.join(HERE, "sanitize", "host_driver.cpp"),
            os.path.join(CSRC, "host", "path_table.cpp"),
+           os.path.join(CSRC, "host", "dfs_table.cpp"),
            os.path.join(CSRC, "host", "gauss_legendre.cpp"), "-o", out]
     subprocess.check_call(cmd)
     return out
@@ -80,6 +81,25 @@ def test_host_tables_under_sanitizers(driver, tmp_path, name, over):
     assert int(kv["elements"]) == info["n_elements"]
     assert int(kv["merged_rows"]) == info["n_value_paths"]
     assert int(kv["segments"]) == info["n_value_segments"]
+    # depth-first form: one row per internal node; updates = features split
+    # above each internal node other than its own split feature
+    ens = wl.ensemble
+    n_int, upd = 0, 0
+    for t in range(ens.n_trees):
+        a = int(ens.tree_offsets[t])
+        stack = [(0, frozenset())]
+        while stack:
+            node, fs = stack.pop()
+            g = a + node
+            if ens.left[g] < 0:
+                continue
+            f = int(ens.feature[g])
+            n_int += 1
+            upd += len(fs - {f})
+            stack.append((int(ens.left[g]), fs | {f}))
+            stack.append((int(ens.right[g]), fs | {f}))
+    assert int(kv["dfs_nodes"]) == n_int and int(kv["dfs_updates"]) == upd
+    assert int(kv["dfs_rows"]) % 64 == 0 and int(kv["dfs_rows"]) >= n_int
     assert abs(float(kv["wsum"]) - 7.0) < 1e-13   # each rule's weights sum to 1
 
 
