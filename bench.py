@@ -248,6 +248,7 @@ def measure_interactions(args, torch, q, synth, oracle, dev):
     _, Phi_o = oracle.shap_interactions(ens, wl.X[:2], n=8)
     err = float((np.abs(Phi - Phi_o).reshape(2, -1).max(1)
                  / np.abs(Phi_o).reshape(2, -1).max(1)).max())
+    dfs = measure_dfs_form(args, torch, e, X, Phi_o, res)
     tf32, fr32 = executed("interactions", "fp32", res["fp32"]["kernel_ms"] * 1e-3)
     tf64, fr64 = executed("interactions", "fp64", res["fp64"]["kernel_ms"] * 1e-3)
     lds_rate = pairs / (res["fp32"]["kernel_ms"] * 1e-3)
@@ -264,8 +265,41 @@ def measure_interactions(args, torch, q, synth, oracle, dev):
            "pair_updates_per_s": lds_rate,
            "frac_of_lds_f64_atomic_rate": lds_rate / LDS_F64_ATOMIC_RATE,
            "fp64_kernel_ms": res["fp64"]["kernel_ms"],
-           "launch": "hipGraph replay" if not args.eager else "eager"}
+           "launch": "hipGraph replay" if not args.eager else "eager",
+           "depth_first_form": dfs}
     e.close()
+    return out
+
+
+def measure_dfs_form(args, torch, e, X, Phi_o, res_paths, steps=3):
+    """The depth-first form of the same interactions call (Algorithm 1 at order
+    2): step times in both precisions beside the path form's, its error on the
+    first rows, and the form the autotuner keeps ('auto')."""
+    M, F = X.shape[0], e.n_features
+    e.set_pair_traversal("dfs")
+    out = {"pair_updates_per_sample": int(e.info["n_dfs_updates"]),
+           "internal_nodes": int(e.info["n_dfs_nodes"])}
+    for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+        e.set_graph_replay(not args.eager)
+        Phi = torch.empty((M, F, F), dtype=dt, device=X.device)
+        r = time_steps(lambda: e.shap_interactions(X, prec, out=Phi), steps, 1, torch,
+                       "interactions")
+        out[prec + "_ms_per_step"] = r["ms_per_step"]
+        out[prec + "_speedup_over_paths"] = res_paths[prec]["ms_per_step"] / r["ms_per_step"]
+        if prec == "fp32":
+            n = Phi_o.shape[0]
+            G = Phi[:n].double().cpu().numpy()
+            out["max_rel_err_fp32"] = float((np.abs(G - Phi_o).reshape(n, -1).max(1)
+                                             / np.abs(Phi_o).reshape(n, -1).max(1)).max())
+        del Phi
+        e.set_graph_replay(False)
+    e.set_pair_traversal("auto")
+    for prec in ("fp32", "fp64"):
+        if not args.no_autotune:
+            e.autotune(M, prec)
+    out["auto_keeps"] = {p: ("dfs" if e.refresh_info()["pairs_dfs"] & b else "paths")
+                         for p, b in (("fp32", 1), ("fp64", 2))}
+    e.set_pair_traversal("paths")
     return out
 
 
@@ -378,6 +412,7 @@ def measure_deep(args, torch, q, synth, oracle, dev):
     out = {"workload": "c5_deep: 100 grown trees depth 32, leaf cap 512, 64 features, 10k "
                        "explained samples", "samples": M, "leaves": e.n_leaves,
            "max_unique": e.info["max_unique"]}
+    res_deep = {}
     for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
         if not args.no_autotune:
             e.autotune(M, prec)
@@ -427,9 +462,14 @@ def measure_deep(args, torch, q, synth, oracle, dev):
                 return float((np.abs(a - b).max(1) / np.maximum(np.abs(b).max(1), 1e-30)).max())
             out["max_rel_err_fp32"] = {"phi": rel(g, phi_o), "Phi": rel(G, Phi_o),
                                        "rows_checked": [int(len(rows)), 1]}
+            assert rows[0] == 0  # Phi_o is sample 0's
             out["gap_8_nodes_vs_exact"] = {"phi": rel(phi_o, phi_x), "Phi": rel(Phi_o, Phi_x),
                                            "measure": "row-normwise, FP64 oracle n=8 vs n=32"}
+        res_deep[prec] = ri
         del phi, Phi
+    # the depth-first form of the interactions call (sample 0 against the oracle)
+    out["interactions_depth_first_form"] = measure_dfs_form(args, torch, e, X, Phi_o, res_deep,
+                                                            steps=2)
     e.close()
     return out
 
