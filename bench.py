@@ -66,9 +66,27 @@ FLOPS_PER_ELEMENT = 51  # per (sample, path, unique feature): 8 nodes x 6 + 3
 # only for the kernel sources they were measured on (SHA-256 prefix over the
 # kernel files); otherwise the executed figures are reported as null.
 KERNEL_SOURCES = ("paper_2605_04497_amd/csrc/kernels/values.hip",
-                  "paper_2605_04497_amd/csrc/kernels/interactions.hip")
+                  "paper_2605_04497_amd/csrc/kernels/interactions.hip",
+                  "paper_2605_04497_amd/csrc/kernels/dfs.hip",
+                  "paper_2605_04497_amd/csrc/kernels/common.hip")
 EXECUTED_FLOPS_SHA = None
-EXECUTED_FLOPS = {}  # (leg, precision) -> flops per call
+EXECUTED_FLOPS = {}  # (leg, precision) -> (FP32 flops, FP64 flops) per call
+
+# One call of each leg for the counter runs (`--flop-call LEG:PREC` under
+# rocprofv3 --pmc): workload, samples ("pairs": --pair-samples, else all), the
+# call, and the interactions traversal.
+FLOP_CALLS = {
+    "values": ("c2_values", None, "values", None),
+    "interactions": ("c3_interactions", "pairs", "interactions", "paths"),
+    "interactions_dfs": ("c3_interactions", "pairs", "interactions", "dfs"),
+    "adjoint": ("c4_adjoint", None, "backward", None),
+    "deep_values": ("c5_deep", None, "values", None),
+    "deep_interactions": ("c5_deep", None, "interactions", "paths"),
+    "deep_interactions_dfs": ("c5_deep", None, "interactions", "dfs"),
+}
+# kernels that only the autotuner launches (synthetic inputs), left out of a
+# call's counts
+TUNER_KERNELS = ("fill_uniform_kernel", "widen_kernel")
 
 
 def kernel_sources_sha():
@@ -81,13 +99,87 @@ def kernel_sources_sha():
 
 
 def executed(leg, precision, seconds):
-    """(TFLOP/s, fraction of the published peak of the precision) of one call
-    of a leg from its counter-measured flops, or (None, None)."""
+    """Executed flops of one call of a leg from its counters (FP32 and FP64
+    vector flops together), as TFLOP/s over `seconds`, with the fraction of
+    the published peak of the precision and of the non-packed issue ceiling;
+    None where the table does not hold the leg or the kernels have changed."""
     fl = EXECUTED_FLOPS.get((leg, precision))
     if fl is None or EXECUTED_FLOPS_SHA != kernel_sources_sha():
-        return None, None
-    tf = fl / seconds / 1e12
-    return tf, tf / (PEAK_FP32_PACKED_TFLOPS if precision == "fp32" else PEAK_VALU_TFLOPS)
+        return None
+    tf = (fl[0] + fl[1]) / seconds / 1e12
+    peak = PEAK_FP32_PACKED_TFLOPS if precision == "fp32" else PEAK_VALU_TFLOPS
+    return {"executed_tflops": tf, "frac_of_peak": tf / peak, "peak_tflops": peak,
+            "frac_of_nonpacked_issue_ceiling": tf / PEAK_VALU_TFLOPS,
+            "flops_per_call": {"fp32": fl[0], "fp64": fl[1]},
+            "source": "SQ_INSTS_VALU_FLOPS_FP32/_FP64 x 64 over one call's dispatches, "
+                      "rocprofv3 --pmc of bench.py --flop-call %s:%s" % (leg, precision)}
+
+
+def flop_call(args, torch, q, synth, dev):
+    """One eager call of a leg, launch shapes from the tune cache (a miss would
+    add the tuner's launches to the counts, so it is an error)."""
+    leg, prec = args.flop_call.split(":")
+    name, samples, call, trav = FLOP_CALLS[leg]
+    over = {"M": args.pair_samples} if samples == "pairs" else {}
+    wl = synth.make_workload(name, **over)
+    e = q.Ensemble(wl.ensemble, device=dev)
+    X = torch.from_numpy(wl.X).to(dev)
+    M = X.shape[0]
+    if trav:
+        e.set_pair_traversal(trav)
+    G = None
+    if call == "backward":
+        g = 2.0 * (0.0 - wl.target.astype(np.float64))
+        G = torch.from_numpy(g.astype(np.float32) if prec == "fp32" else g).to(dev)
+    _, m0 = q.tune_cache_stats()
+    if not args.no_autotune:
+        e.autotune(M, prec)
+    _, m1 = q.tune_cache_stats()
+    if m1 > m0:
+        raise SystemExit("tune cache miss (%d): the counts would include the tuner's launches"
+                         % (m1 - m0))
+    torch.cuda.synchronize()
+    if call == "values":
+        e.shap_values(X, prec)
+    elif call == "interactions":
+        e.shap_interactions(X, prec)
+    else:
+        e.shap_backward(X, G, prec)
+    torch.cuda.synchronize()
+    print(json.dumps({"flop_call": leg, "precision": prec, "workload": name, "samples": M,
+                      "kernel_sources_sha": kernel_sources_sha()}), flush=True)
+    e.close()
+
+
+def pmc_summary(paths):
+    """Per kernel, dispatch count and the sum over its dispatches (and over a
+    counter's instances within each) of every counter in rocprofv3 result
+    databases; FP32/FP64 executed flops of all kernels but the tuner's."""
+    import sqlite3
+    for path in paths:
+        con = sqlite3.connect(path)
+        rows = con.execute(
+            "select k.name, p.counter_name, p.dispatch_id, sum(p.counter_value), k.duration "
+            "from pmc_events p join kernels k on p.dispatch_id = k.dispatch_id "
+            "group by p.dispatch_id, p.counter_name").fetchall()
+        per = {}
+        for name, counter, disp, val, dur in rows:
+            kn = name.split("(")[0].split("<")[0].split()[-1]
+            d = per.setdefault(kn, {"dispatches": set(), "ns": {}, "counters": {}})
+            d["dispatches"].add(disp)
+            d["ns"][disp] = dur
+            d["counters"][counter] = d["counters"].get(counter, 0.0) + val
+        print("# %s" % path)
+        flops = [0.0, 0.0]
+        for kn, d in sorted(per.items()):
+            ms = sum(d["ns"].values()) / 1e6
+            print("%-28s dispatches %4d  %.3f ms  %s" % (
+                kn, len(d["dispatches"]), ms,
+                "  ".join("%s=%.4e" % kv for kv in sorted(d["counters"].items()))))
+            if kn not in TUNER_KERNELS:
+                flops[0] += 64.0 * d["counters"].get("SQ_INSTS_VALU_FLOPS_FP32", 0.0)
+                flops[1] += 64.0 * d["counters"].get("SQ_INSTS_VALU_FLOPS_FP64", 0.0)
+        print("executed flops (x64, tuner kernels excluded): fp32 %.4e fp64 %.4e" % tuple(flops))
 
 
 def shared_kernel_flops(rows, elements, shared):
@@ -144,6 +236,10 @@ def parse():
                     help="first-order calls walk every leaf's path (no sibling merging)")
     ap.add_argument("--eager", action="store_true",
                     help="launch eagerly instead of replaying a captured HIP graph")
+    ap.add_argument("--flop-call", default=None, metavar="LEG:PREC",
+                    help="one call of a leg (%s) for counter runs" % ", ".join(FLOP_CALLS))
+    ap.add_argument("--pmc-summary", nargs="+", default=None, metavar="DB",
+                    help="summarise rocprofv3 --pmc result databases and exit (no GPU)")
     ap.add_argument("--only", default=None,
                     choices=["interactions", "interactions_full", "adjoint", "deep", "small",
                              "third_order", "wide", "groups"],
@@ -248,9 +344,7 @@ def measure_interactions(args, torch, q, synth, oracle, dev):
     _, Phi_o = oracle.shap_interactions(ens, wl.X[:2], n=8)
     err = float((np.abs(Phi - Phi_o).reshape(2, -1).max(1)
                  / np.abs(Phi_o).reshape(2, -1).max(1)).max())
-    dfs = measure_dfs_form(args, torch, e, X, Phi_o, res)
-    tf32, fr32 = executed("interactions", "fp32", res["fp32"]["kernel_ms"] * 1e-3)
-    tf64, fr64 = executed("interactions", "fp64", res["fp64"]["kernel_ms"] * 1e-3)
+    dfs = measure_dfs_form(args, torch, e, X, Phi_o, res, "interactions_dfs")
     lds_rate = pairs / (res["fp32"]["kernel_ms"] * 1e-3)
     out = {"workload": "c3_interactions: 500 grown trees, depths 3..20, leaf cap 4096, 200 "
                        "features; first %d of the 50k explained samples" % M,
@@ -260,8 +354,8 @@ def measure_interactions(args, torch, q, synth, oracle, dev):
            "ms_per_step": res["fp32"]["ms_per_step"], "kernel_ms": res["fp32"]["kernel_ms"],
            "fp64_ms_per_step": res["fp64"]["ms_per_step"],
            "max_rel_err_fp32": err, "rows_checked": 2,
-           "executed_tflops_fp32": tf32, "frac_of_fp32_peak": fr32,
-           "executed_tflops_fp64": tf64, "frac_of_fp64_peak": fr64,
+           "executed_fp32": executed("interactions", "fp32", res["fp32"]["kernel_ms"] * 1e-3),
+           "executed_fp64": executed("interactions", "fp64", res["fp64"]["kernel_ms"] * 1e-3),
            "pair_updates_per_s": lds_rate,
            "frac_of_lds_f64_atomic_rate": lds_rate / LDS_F64_ATOMIC_RATE,
            "fp64_kernel_ms": res["fp64"]["kernel_ms"],
@@ -271,7 +365,7 @@ def measure_interactions(args, torch, q, synth, oracle, dev):
     return out
 
 
-def measure_dfs_form(args, torch, e, X, Phi_o, res_paths, steps=3):
+def measure_dfs_form(args, torch, e, X, Phi_o, res_paths, leg, steps=3):
     """The depth-first form of the same interactions call (Algorithm 1 at order
     2): step times in both precisions beside the path form's, its error on the
     first rows, and the form the autotuner keeps ('auto')."""
@@ -286,6 +380,8 @@ def measure_dfs_form(args, torch, e, X, Phi_o, res_paths, steps=3):
                        "interactions")
         out[prec + "_ms_per_step"] = r["ms_per_step"]
         out[prec + "_speedup_over_paths"] = res_paths[prec]["ms_per_step"] / r["ms_per_step"]
+        out[prec + "_kernel_ms"] = r["kernel_ms"]
+        out["executed_" + prec] = executed(leg, prec, r["kernel_ms"] * 1e-3)
         if prec == "fp32":
             n = Phi_o.shape[0]
             G = Phi[:n].double().cpu().numpy()
@@ -327,8 +423,6 @@ def measure_adjoint(args, torch, q, synth, oracle, dev):
     got = e.shap_backward(X[torch.from_numpy(rows).to(dev)], G32[torch.from_numpy(rows).to(dev)],
                           "fp32").cpu().numpy()
     err = float(np.abs(got - want).max() / np.abs(want).max())
-    tf32, fr32 = executed("adjoint", "fp32", res["fp32"]["kernel_ms"] * 1e-3)
-    tf64, fr64 = executed("adjoint", "fp64", res["fp64"]["kernel_ms"] * 1e-3)
     out = {"workload": "c4_adjoint: 200 full depth-6 trees (12,800 leaves), 50 features, "
                        "20k samples, grad of ||phi - target||^2",
            "value": M * e.n_leaves / (res["fp32"]["ms_per_step"] * 1e-3), "unit": "paths/s",
@@ -336,9 +430,8 @@ def measure_adjoint(args, torch, q, synth, oracle, dev):
            "fp64_ms_per_step": res["fp64"]["ms_per_step"],
            "max_rel_err_fp32": err, "rows_checked": int(len(rows)),
            "kernel_rows": int(e.info["n_value_paths"]),
-           "executed_tflops_fp32": tf32, "frac_of_fp32_peak": fr32,
-           "executed_tflops_fp64": tf64, "frac_of_fp64_peak": fr64,
-           "flops_source": "SQ_INSTS_VALU_FLOPS x 64 per call (profiles/)"}
+           "executed_fp32": executed("adjoint", "fp32", res["fp32"]["kernel_ms"] * 1e-3),
+           "executed_fp64": executed("adjoint", "fp64", res["fp64"]["kernel_ms"] * 1e-3)}
     e.close()
     return out
 
@@ -424,15 +517,13 @@ def measure_deep(args, torch, q, synth, oracle, dev):
         e.set_graph_replay(False)
         vt = r["kernel_ms"] * 1e-3
         pt = ri["kernel_ms"] * 1e-3
-        vtf, vfr = executed("deep_values", prec, vt)
-        ptf, pfr = executed("deep_interactions", prec, pt)
         out["values_" + prec] = {"value": M * e.n_leaves / (r["ms_per_step"] * 1e-3),
                                  "ms_per_step": r["ms_per_step"], "kernel_ms": r["kernel_ms"],
-                                 "executed_tflops": vtf, "frac_of_peak": vfr}
+                                 "executed": executed("deep_values", prec, vt)}
         out["interactions_" + prec] = {"value": M * e.n_leaves / (ri["ms_per_step"] * 1e-3),
                                        "ms_per_step": ri["ms_per_step"],
                                        "kernel_ms": ri["kernel_ms"],
-                                       "executed_tflops": ptf, "frac_of_peak": pfr}
+                                       "executed": executed("deep_interactions", prec, pt)}
         # third order on 200 of the samples (F = 64: 41,664 triples per sample)
         T3 = F * (F - 1) * (F - 2) // 6
         M3 = 200
@@ -469,7 +560,7 @@ def measure_deep(args, torch, q, synth, oracle, dev):
         del phi, Phi
     # the depth-first form of the interactions call (sample 0 against the oracle)
     out["interactions_depth_first_form"] = measure_dfs_form(args, torch, e, X, Phi_o, res_deep,
-                                                            steps=2)
+                                                            "deep_interactions_dfs", steps=2)
     e.close()
     return out
 
@@ -636,6 +727,9 @@ def measure_interactions_full(args, torch, q, synth, oracle, dev):
 
 def main():
     args = parse()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -647,6 +741,11 @@ def main():
     from oracle import oracle
 
     q.set_tune_cache(args.tune_cache or None)
+    if args.flop_call:
+        dev = torch.device("cuda:0")
+        torch.cuda.set_device(dev)
+        flop_call(args, torch, q, synth, dev)
+        return
     if args.only:
         dev = torch.device("cuda:0")
         torch.cuda.set_device(dev)

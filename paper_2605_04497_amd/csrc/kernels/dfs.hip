@@ -3,8 +3,9 @@
 // notation and the formulas are those of DfsTable (qts_internal.h).
 //
 // dfs_walk_kernel: the tree walk.  A wavefront walks one tree for 8 samples,
-// lane = (sample, node m), so the walk is uniform across the wave and every
-// node record is read with scalar loads.  Each lane carries the product C of
+// lane = (sample, node m), so the walk is uniform across the wave; the node
+// records of each window of 64 events are staged in LDS by one coalesced load
+// and read back by broadcast.  Each lane carries the product C of
 // the factors of the features split above the current node at t_m, kept on
 // a per-level stack in LDS while a subtree is walked, and returns up the tree
 // H_u(t_m), the sum of val * C over the leaves below u.  At each internal
@@ -57,10 +58,17 @@ __device__ __forceinline__ bool follows(float x, float lo, float hi, bool mok) {
 constexpr int kDfsSamples = 8;  // samples per wavefront of the walk (8 lanes each)
 
 // LDS of the walk: the sample rows of the workgroup's 8 samples (stride F+1),
-// then per wave the two stacks [level][64] of C and of the left subtree's H.
+// then per wave the two stacks [level][64] of C and of the left subtree's H
+// and the stage of 64 events' node data.
+__host__ __device__ inline size_t staged_event_bytes(size_t tsize) {
+  return ((4 * sizeof(int32_t) + (kDfsCoef + 2) * tsize) + 15) & ~(size_t)15;
+}
+__host__ __device__ inline size_t dfs_wave_lds(int levels, size_t tsize) {
+  return (((size_t)2 * levels * 64 * tsize + 15) & ~(size_t)15) + 64 * staged_event_bytes(tsize);
+}
 __host__ __device__ inline size_t dfs_walk_lds(int F, int levels, int waves, size_t tsize) {
   const size_t xs = (((size_t)kDfsSamples * (F + 1) * sizeof(float)) + 15) & ~(size_t)15;
-  return xs + (size_t)waves * 2 * levels * 64 * tsize;
+  return xs + (size_t)waves * dfs_wave_lds(levels, tsize);
 }
 
 // Lane k's value, wave-uniform.
@@ -74,6 +82,15 @@ __device__ __forceinline__ double bcast(double v, int k) {
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+
+// One event's node data as the walk reads it back from LDS (wave-uniform
+// address: a broadcast), 16-byte aligned.
+template <typename T>
+struct alignas(16) StagedEvent {
+  int32_t kind, level, flags, row;
+  T coef[kDfsCoef];  // b^v, 1 - b^v, b^L, 1 - b^L, b^R, 1 - b^R, b^v - b^L, b^v - b^R
+  T lv[2];           // values of leaf children (0 for internal ones)
+};
 
 template <typename T>
 __global__ void __launch_bounds__(1024)
@@ -103,9 +120,10 @@ dfs_walk_kernel(const DfsNode* __restrict__ nodes, const T* __restrict__ coef,
   const int sl = sg * kDfsSamples + q;         // sample within the batch
   const bool valid = sl < mb;
   const size_t xs_bytes = (((size_t)kDfsSamples * xstride * sizeof(float)) + 15) & ~(size_t)15;
-  T* cst = reinterpret_cast<T*>(smem + xs_bytes) + (size_t)wave * 2 * levels * 64;
+  unsigned char* wbase = smem + xs_bytes + (size_t)wave * dfs_wave_lds(levels, sizeof(T));
+  T* cst = reinterpret_cast<T*>(wbase);
   T* hst = cst + (size_t)levels * 64;
-  const float* xrow = xs + q * xstride;
+  StagedEvent<T>* stage = reinterpret_cast<StagedEvent<T>*>(hst + (size_t)levels * 64);
   T tm = nc.t[0], wm = nc.w[0];
 #pragma unroll
   for (int k = 1; k < kNodes; ++k) {
@@ -117,74 +135,86 @@ dfs_walk_kernel(const DfsNode* __restrict__ nodes, const T* __restrict__ coef,
   const int n_ev = 3 * __builtin_amdgcn_readfirstlane(tree_nodes[ti]);
   const int32_t* ev = events + 3 * (size_t)first;
   T C = T(1), H = T(0);
-  // Windows of 64 events: lane i loads event i of the window and its node
-  // data with one coalesced load per field, and the walk reads them back
-  // with lane broadcasts, so its sequential steps wait on no memory.
+  // Windows of 64 events.  Pass 1, lane i on event i of the window: load its
+  // node data (coalesced) into the wave's LDS stage, and test the follow
+  // conditions of its split feature for all 8 samples at once (3 bits per
+  // sample: above the node, left edge, right edge).  Pass 2 walks the
+  // window's events in order, reading each event's data back from the stage
+  // (a broadcast) and its sample's bits from the event's lane.
   for (int w0 = 0; w0 < n_ev; w0 += 64) {
     const int nwin = min(64, n_ev - w0);
-    const int e = ev[w0 + min(lane, nwin - 1)];
-    const int r = e >> 2;
-    const int4* p4 = reinterpret_cast<const int4*>(nodes + r);
-    const int4 ra = p4[0], rc = p4[2], rd = p4[3];
-    T cf[kDfsCoef];
+    {
+      const int e = ev[w0 + min(lane, nwin - 1)];
+      const int r = e >> 2;
+      const DfsNode nd = nodes[r];
+      StagedEvent<T> se;
+      se.kind = e & 3;
+      se.level = nd.level;
+      se.flags = nd.flags;
+      se.row = nd.row;
 #pragma unroll
-    for (int k = 0; k < kDfsCoef; ++k) cf[k] = coef[(size_t)r * kDfsCoef + k];
-    const T lv0 = lvals[2 * (size_t)r], lv1 = lvals[2 * (size_t)r + 1];
-    // pass 1: whether this lane's sample follows f's splits above each
-    // event's node (ov), and on the left (ol) and right (or) edges; the steps
-    // are independent, so their LDS reads overlap
-    uint64_t bov = 0, bol = 0, bor = 0;
-    for (int k = 0; k < nwin; ++k) {
-      const int f = bcast(ra.x, k);
-      const int flags = bcast(ra.w, k);
-      const float x = xrow[f];
-      const uint64_t bit = (uint64_t)1 << k;
-      if (follows(x, bcast(__int_as_float(rc.y), k), bcast(__int_as_float(rc.z), k),
-                  (flags & kDfsMokV) != 0)) bov |= bit;
-      if (follows(x, bcast(__int_as_float(rc.w), k), bcast(__int_as_float(rd.x), k),
-                  (flags & kDfsMokL) != 0)) bol |= bit;
-      if (follows(x, bcast(__int_as_float(rd.y), k), bcast(__int_as_float(rd.z), k),
-                  (flags & kDfsMokR) != 0)) bor |= bit;
-    }
-    // pass 2: the walk's steps in order
-    for (int k = 0; k < nwin; ++k) {
-      const int kind = bcast(e, k) & 3;
-      const int level = bcast(ra.y, k);
-      const int flags = bcast(ra.w, k);
-      const bool ov = (bov >> k) & 1;
-      const T bv = bcast(cf[0], k), cbv = bcast(cf[1], k);
-      const T Fv = fmaD(tm, ov ? cbv : -bv, bv);
-      const bool fresh = (flags & kDfsFresh) != 0;
-      if (kind == kDfsEnter) {
-        const T bl = bcast(cf[2], k), cbl = bcast(cf[3], k);
-        const T Fl = fmaD(tm, ((bol >> k) & 1) ? cbl : -bl, bl);
-        cst[level * 64 + lane] = C;
-        // C times F_f^u / F_f^v; F_f^v = 1 when f is not split above v, and a
-        // vanishing F_f^v leaves the whole subtree at zero
-        C = fresh ? C * Fl : (Fv == T(0) ? T(0) : C * Fl * rcpD(Fv));
-        H = bcast(lv0, k) * C;  // used only when the left child is a leaf
-      } else if (kind == kDfsMiddle) {
-        const T br = bcast(cf[4], k), cbr = bcast(cf[5], k);
-        const T Fr = fmaD(tm, ((bor >> k) & 1) ? cbr : -br, br);
-        hst[level * 64 + lane] = H;
-        const T Cv = cst[level * 64 + lane];
-        C = fresh ? Cv * Fr : (Fv == T(0) ? T(0) : Cv * Fr * rcpD(Fv));
-        H = bcast(lv1, k) * C;
-      } else {
-        // both subtrees done: H holds H_R, the stack H_L
-        const bool ol = (bol >> k) & 1, orr = (bor >> k) & 1;
-        const T bl = bcast(cf[2], k), cbl = bcast(cf[3], k);
-        const T br = bcast(cf[4], k), cbr = bcast(cf[5], k);
-        const T Fl = fmaD(tm, ol ? cbl : -bl, bl);
-        const T Fr = fmaD(tm, orr ? cbr : -br, br);
-        const T HL = hst[level * 64 + lane];
-        const T nl = ol ? bcast(cf[6], k) : (ov ? -bl : T(0));
-        const T nr = orr ? bcast(cf[7], k) : (ov ? -br : T(0));
-        const T tl = (Fl == T(0) || Fv == T(0)) ? T(0) : HL * nl * rcpD(Fl * Fv);
-        const T tr = (Fr == T(0) || Fv == T(0)) ? T(0) : H * nr * rcpD(Fr * Fv);
-        if (valid) Y[((int64_t)sl * n_rows + bcast(rc.x, k)) * kNodes + m] = wm * (tl + tr);
-        H = HL + H;
+      for (int k = 0; k < kDfsCoef; ++k) se.coef[k] = coef[(size_t)r * kDfsCoef + k];
+      se.lv[0] = lvals[2 * (size_t)r];
+      se.lv[1] = lvals[2 * (size_t)r + 1];
+      stage[lane] = se;
+      uint32_t bits = 0;
+#pragma unroll
+      for (int qq = 0; qq < kDfsSamples; ++qq) {
+        const float x = xs[qq * xstride + nd.f];
+        const uint32_t b3 =
+            (follows(x, nd.lo_v, nd.hi_v, (nd.flags & kDfsMokV) != 0) ? 1u : 0u) |
+            (follows(x, nd.lo_l, nd.hi_l, (nd.flags & kDfsMokL) != 0) ? 2u : 0u) |
+            (follows(x, nd.lo_r, nd.hi_r, (nd.flags & kDfsMokR) != 0) ? 4u : 0u);
+        bits |= b3 << (3 * qq);
       }
+      // the stage is written by this wave only and read back by it below
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int k = 0; k < nwin; ++k) {
+        const StagedEvent<T>& w = stage[k];
+        const int kind = __builtin_amdgcn_readfirstlane(w.kind);
+        const int level = __builtin_amdgcn_readfirstlane(w.level);
+        const int flags = __builtin_amdgcn_readfirstlane(w.flags);
+        const uint32_t mine = ((uint32_t)__builtin_amdgcn_readlane((int)bits, k) >> (3 * q)) & 7u;
+        const bool ov = (mine & 1u) != 0;
+        const T bv = w.coef[0], cbv = w.coef[1];
+        const T Fv = fmaD(tm, ov ? cbv : -bv, bv);
+        const bool fresh = (flags & kDfsFresh) != 0;
+        if (kind == kDfsEnter) {
+          const T bl = w.coef[2], cbl = w.coef[3];
+          const T Fl = fmaD(tm, (mine & 2u) ? cbl : -bl, bl);
+          cst[level * 64 + lane] = C;
+          // C times F_f^u / F_f^v; F_f^v = 1 when f is not split above v, and
+          // a vanishing F_f^v leaves the whole subtree at zero
+          C = fresh ? C * Fl : (Fv == T(0) ? T(0) : C * Fl * rcpD(Fv));
+          H = w.lv[0] * C;  // used only when the left child is a leaf
+        } else if (kind == kDfsMiddle) {
+          const T br = w.coef[4], cbr = w.coef[5];
+          const T Fr = fmaD(tm, (mine & 4u) ? cbr : -br, br);
+          hst[level * 64 + lane] = H;
+          const T Cv = cst[level * 64 + lane];
+          C = fresh ? Cv * Fr : (Fv == T(0) ? T(0) : Cv * Fr * rcpD(Fv));
+          H = w.lv[1] * C;
+        } else {
+          // both subtrees done: H holds H_R, the stack H_L
+          const bool ol = (mine & 2u) != 0, orr = (mine & 4u) != 0;
+          const T bl = w.coef[2], cbl = w.coef[3], br = w.coef[4], cbr = w.coef[5];
+          const T Fl = fmaD(tm, ol ? cbl : -bl, bl);
+          const T Fr = fmaD(tm, orr ? cbr : -br, br);
+          const T HL = hst[level * 64 + lane];
+          const T nl = ol ? w.coef[6] : (ov ? -bl : T(0));
+          const T nr = orr ? w.coef[7] : (ov ? -br : T(0));
+          const T tl = (Fl == T(0) || Fv == T(0)) ? T(0) : HL * nl * rcpD(Fl * Fv);
+          const T tr = (Fr == T(0) || Fv == T(0)) ? T(0) : H * nr * rcpD(Fr * Fv);
+          if (valid) Y[((int64_t)sl * n_rows + w.row) * kNodes + m] = wm * (tl + tr);
+          H = HL + H;
+        }
+      }
+      // the next window overwrites the stage
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
 }
