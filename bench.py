@@ -314,6 +314,11 @@ def cpu_baseline(ens, X, seconds, oracle):
                             "sample": "%d rows, %.1f s" % (rows1, dt1)}}
 
 
+def traversal(e, prec):
+    """The form qts_shap_interactions takes for a precision ('paths' or 'dfs')."""
+    return "dfs" if e.refresh_info()["pairs_dfs"] & (1 if prec == "fp32" else 2) else "paths"
+
+
 def measure_interactions(args, torch, q, synth, oracle, dev):
     """Pairwise interactions on the full 500-tree, 200-feature ensemble (depths
     3..20), over a slice of its explained samples; FP32 form."""
@@ -331,9 +336,11 @@ def measure_interactions(args, torch, q, synth, oracle, dev):
     pairs = float(M) * U
     F = e.n_features
     res = {}
+    trav = {}
     for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
         if not args.no_autotune:
             e.autotune(M, prec)
+        trav[prec] = traversal(e, prec)
         e.set_graph_replay(not args.eager)
         Phi = torch.empty((M, F, F), dtype=dt, device=dev)
         res[prec] = time_steps(lambda: e.shap_interactions(X, prec, out=Phi), 3, 1, torch,
@@ -344,20 +351,23 @@ def measure_interactions(args, torch, q, synth, oracle, dev):
     _, Phi_o = oracle.shap_interactions(ens, wl.X[:2], n=8)
     err = float((np.abs(Phi - Phi_o).reshape(2, -1).max(1)
                  / np.abs(Phi_o).reshape(2, -1).max(1)).max())
-    dfs = measure_dfs_form(args, torch, e, X, Phi_o, res, "interactions_dfs")
-    lds_rate = pairs / (res["fp32"]["kernel_ms"] * 1e-3)
+    dfs = measure_dfs_form(args, torch, e, X, Phi_o, "interactions_dfs")
+    # LDS FP64 atomics of the path form: one per pair update
+    lds_rate = pairs / (res["fp32"]["kernel_ms"] * 1e-3) if trav["fp32"] == "paths" else None
+    leg = {"paths": "interactions", "dfs": "interactions_dfs"}
     out = {"workload": "c3_interactions: 500 grown trees, depths 3..20, leaf cap 4096, 200 "
                        "features; first %d of the 50k explained samples" % M,
+           "traversal": trav,
            "samples": M, "leaves": e.n_leaves, "mean_unique": float(tab["path_len"].mean()),
            "kernel_rows": int(N), "pair_updates_per_sample": int(U),
            "value": M * e.n_leaves / (res["fp32"]["ms_per_step"] * 1e-3), "unit": "paths/s",
            "ms_per_step": res["fp32"]["ms_per_step"], "kernel_ms": res["fp32"]["kernel_ms"],
            "fp64_ms_per_step": res["fp64"]["ms_per_step"],
            "max_rel_err_fp32": err, "rows_checked": 2,
-           "executed_fp32": executed("interactions", "fp32", res["fp32"]["kernel_ms"] * 1e-3),
-           "executed_fp64": executed("interactions", "fp64", res["fp64"]["kernel_ms"] * 1e-3),
+           "executed_fp32": executed(leg[trav["fp32"]], "fp32", res["fp32"]["kernel_ms"] * 1e-3),
+           "executed_fp64": executed(leg[trav["fp64"]], "fp64", res["fp64"]["kernel_ms"] * 1e-3),
            "pair_updates_per_s": lds_rate,
-           "frac_of_lds_f64_atomic_rate": lds_rate / LDS_F64_ATOMIC_RATE,
+           "frac_of_lds_f64_atomic_rate": lds_rate / LDS_F64_ATOMIC_RATE if lds_rate else None,
            "fp64_kernel_ms": res["fp64"]["kernel_ms"],
            "launch": "hipGraph replay" if not args.eager else "eager",
            "depth_first_form": dfs}
@@ -365,37 +375,47 @@ def measure_interactions(args, torch, q, synth, oracle, dev):
     return out
 
 
-def measure_dfs_form(args, torch, e, X, Phi_o, res_paths, leg, steps=3):
-    """The depth-first form of the same interactions call (Algorithm 1 at order
-    2): step times in both precisions beside the path form's, its error on the
-    first rows, and the form the autotuner keeps ('auto')."""
+def measure_dfs_form(args, torch, e, X, Phi_o, leg, steps=3):
+    """The interactions call in each traversal, forced: collapsed paths and
+    the depth-first form (Algorithm 1 at order 2), step times in both
+    precisions, the depth-first form's error on the first rows, and the form
+    the autotuner keeps under the default ('auto')."""
     M, F = X.shape[0], e.n_features
-    e.set_pair_traversal("dfs")
-    out = {"pair_updates_per_sample": int(e.info["n_dfs_updates"]),
-           "internal_nodes": int(e.info["n_dfs_nodes"])}
-    for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
-        e.set_graph_replay(not args.eager)
-        Phi = torch.empty((M, F, F), dtype=dt, device=X.device)
-        r = time_steps(lambda: e.shap_interactions(X, prec, out=Phi), steps, 1, torch,
-                       "interactions")
-        out[prec + "_ms_per_step"] = r["ms_per_step"]
-        out[prec + "_speedup_over_paths"] = res_paths[prec]["ms_per_step"] / r["ms_per_step"]
-        out[prec + "_kernel_ms"] = r["kernel_ms"]
-        out["executed_" + prec] = executed(leg, prec, r["kernel_ms"] * 1e-3)
-        if prec == "fp32":
-            n = Phi_o.shape[0]
-            G = Phi[:n].double().cpu().numpy()
-            out["max_rel_err_fp32"] = float((np.abs(G - Phi_o).reshape(n, -1).max(1)
-                                             / np.abs(Phi_o).reshape(n, -1).max(1)).max())
-        del Phi
-        e.set_graph_replay(False)
+    out = {}
+    ms = {}
+    for trav in ("paths", "dfs"):
+        e.set_pair_traversal(trav)
+        if trav == "dfs":
+            out["pair_updates_per_sample"] = int(e.info["n_dfs_updates"])
+            out["internal_nodes"] = int(e.info["n_dfs_nodes"])
+        for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+            e.set_graph_replay(not args.eager)
+            Phi = torch.empty((M, F, F), dtype=dt, device=X.device)
+            r = time_steps(lambda: e.shap_interactions(X, prec, out=Phi), steps, 1, torch,
+                           "interactions")
+            ms[trav, prec] = r["ms_per_step"]
+            if trav == "dfs":
+                out[prec + "_ms_per_step"] = r["ms_per_step"]
+                out[prec + "_kernel_ms"] = r["kernel_ms"]
+                out["executed_" + prec] = executed(leg, prec, r["kernel_ms"] * 1e-3)
+                if prec == "fp32":
+                    n = Phi_o.shape[0]
+                    G = Phi[:n].double().cpu().numpy()
+                    out["max_rel_err_fp32"] = float(
+                        (np.abs(G - Phi_o).reshape(n, -1).max(1)
+                         / np.abs(Phi_o).reshape(n, -1).max(1)).max())
+            else:
+                out["paths_" + prec + "_ms_per_step"] = r["ms_per_step"]
+            del Phi
+            e.set_graph_replay(False)
+    for prec in ("fp32", "fp64"):
+        out[prec + "_speedup_over_paths"] = ms["paths", prec] / ms["dfs", prec]
     e.set_pair_traversal("auto")
     for prec in ("fp32", "fp64"):
         if not args.no_autotune:
             e.autotune(M, prec)
     out["auto_keeps"] = {p: ("dfs" if e.refresh_info()["pairs_dfs"] & b else "paths")
                          for p, b in (("fp32", 1), ("fp64", 2))}
-    e.set_pair_traversal("paths")
     return out
 
 
@@ -505,10 +525,10 @@ def measure_deep(args, torch, q, synth, oracle, dev):
     out = {"workload": "c5_deep: 100 grown trees depth 32, leaf cap 512, 64 features, 10k "
                        "explained samples", "samples": M, "leaves": e.n_leaves,
            "max_unique": e.info["max_unique"]}
-    res_deep = {}
     for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
         if not args.no_autotune:
             e.autotune(M, prec)
+        tr = traversal(e, prec)
         e.set_graph_replay(not args.eager)
         phi = torch.empty((M, F), dtype=dt, device=dev)
         r = time_steps(lambda: e.shap_values(X, prec, out=phi), 5, 1, torch)
@@ -522,8 +542,10 @@ def measure_deep(args, torch, q, synth, oracle, dev):
                                  "executed": executed("deep_values", prec, vt)}
         out["interactions_" + prec] = {"value": M * e.n_leaves / (ri["ms_per_step"] * 1e-3),
                                        "ms_per_step": ri["ms_per_step"],
-                                       "kernel_ms": ri["kernel_ms"],
-                                       "executed": executed("deep_interactions", prec, pt)}
+                                       "kernel_ms": ri["kernel_ms"], "traversal": tr,
+                                       "executed": executed(
+                                           "deep_interactions" + ("_dfs" if tr == "dfs" else ""),
+                                           prec, pt)}
         # third order on 200 of the samples (F = 64: 41,664 triples per sample)
         T3 = F * (F - 1) * (F - 2) // 6
         M3 = 200
@@ -556,10 +578,9 @@ def measure_deep(args, torch, q, synth, oracle, dev):
             assert rows[0] == 0  # Phi_o is sample 0's
             out["gap_8_nodes_vs_exact"] = {"phi": rel(phi_o, phi_x), "Phi": rel(Phi_o, Phi_x),
                                            "measure": "row-normwise, FP64 oracle n=8 vs n=32"}
-        res_deep[prec] = ri
         del phi, Phi
     # the depth-first form of the interactions call (sample 0 against the oracle)
-    out["interactions_depth_first_form"] = measure_dfs_form(args, torch, e, X, Phi_o, res_deep,
+    out["interactions_depth_first_form"] = measure_dfs_form(args, torch, e, X, Phi_o,
                                                             "deep_interactions_dfs", steps=2)
     e.close()
     return out
@@ -608,6 +629,7 @@ def measure_wide(args, torch, q, synth, oracle, dev):
     for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
         if not args.no_autotune:
             e.autotune(M, prec)
+        tr = traversal(e, prec)
         e.set_graph_replay(not args.eager)
         phi = torch.empty((M, F), dtype=dt, device=dev)
         res[prec] = time_steps(lambda: e.shap_values(X, prec, out=phi), 5, 1, torch)

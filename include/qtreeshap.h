@@ -148,9 +148,9 @@ typedef struct {
   int64_t n_pair_rows;       /* rows of the interactions table (0: host-only ensemble) */
   int64_t n_pair_elements;   /* sum of d over them */
   int64_t n_pair_updates;    /* sum of d(d-1)/2 over them: pair updates per sample */
-  int64_t n_value_shared;    /* first-order rows with at most 8 features: leading
-                                slots after slot 0 equal to the previous row's,
-                                summed (their factors are reused, not re-evaluated) */
+  int64_t n_value_shared;    /* first-order rows: leading slots after slot 0 equal
+                                to the previous row's, summed (the kernels reuse
+                                their work instead of evaluating it again) */
   int64_t n_path_shared;     /* the same for the unmerged table */
   int64_t n_value_segments;  /* work segments of the merged first-order table when
                                 the sample tile of all features does not fit in
@@ -335,7 +335,7 @@ enum { QTS_NODES_FIXED8 = 0, QTS_NODES_EXACT = 1 };
 int qts_set_node_policy(qts_ensemble* ens, int32_t policy);
 
 /* Traversal of qts_shap_interactions.
- *   QTS_PAIRS_PATHS (default): every root-to-leaf path (or merged pair of
+ *   QTS_PAIRS_PATHS: every root-to-leaf path (or merged pair of
  *     sibling leaves) collapsed to its unique features; each adds its
  *     d(d-1)/2 pair terms (Theorem 1 with |S| = 2).
  *   QTS_PAIRS_DFS: Algorithm 1 at order 2 (section 5).  A depth-first walk of
@@ -353,9 +353,11 @@ int qts_set_node_policy(qts_ensemble* ens, int32_t policy);
  * Selecting QTS_PAIRS_DFS builds its tables on the current device (from the
  * tree arrays kept at load) the first time; QTS_E_UNSUPPORTED if its walk's
  * per-level stacks do not fit in LDS.  Changing it drops the cached graphs. */
-/*   QTS_PAIRS_AUTO: the form qts_autotune finds faster on the ensemble, per
- *     precision (timed on one batch of its synthetic rows; kept in the
- *     autotune cache); the path form until the ensemble is tuned. */
+/*   QTS_PAIRS_AUTO (default): the form qts_autotune finds faster on the
+ *     ensemble, per precision (timed on one batch of its synthetic rows; kept
+ *     in the autotune cache); the path form until the ensemble is tuned, and
+ *     where the walk's stacks do not fit in LDS.  qts_autotune builds the
+ *     depth-first tables on first use. */
 enum { QTS_PAIRS_PATHS = 0, QTS_PAIRS_DFS = 1, QTS_PAIRS_AUTO = 2 };
 int qts_set_pair_traversal(qts_ensemble* ens, int32_t traversal);
 

@@ -289,11 +289,11 @@ class Ensemble:
         (default) or every path (exact same values up to rounding)."""
         L.check(L.lib().qts_set_sibling_merge(self._h, int(bool(enable))))
 
-    def set_pair_traversal(self, traversal: str = "paths"):
-        """'paths' (default): the interactions call walks collapsed paths;
-        'dfs': Algorithm 1's depth-first form (one pair update per internal
-        node and feature split above it); 'auto': the faster of the two, as
-        found by the next autotune of each precision."""
+    def set_pair_traversal(self, traversal: str = "auto"):
+        """'paths': the interactions call walks collapsed paths; 'dfs':
+        Algorithm 1's depth-first form (one pair update per internal node and
+        feature split above it); 'auto' (default): the faster of the two, as
+        found by the next autotune of each precision (paths until then)."""
         with torch.cuda.device(self.device):
             L.check(L.lib().qts_set_pair_traversal(
                 self._h, {"paths": 0, "dfs": 1, "auto": 2}[traversal]))

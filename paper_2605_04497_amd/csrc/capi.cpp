@@ -75,7 +75,7 @@ struct qts_ensemble {
   int64_t pair_rows = 0, pair_elements = 0, pair_updates = 0;  // interactions table
   // depth-first form of the interactions (qts_set_pair_traversal): the tree
   // arrays are kept to build its tables on first use
-  int pair_traversal = QTS_PAIRS_PATHS;
+  int pair_traversal = QTS_PAIRS_AUTO;
   bool dfs_faster[2] = {false, false};  // QTS_PAIRS_AUTO: qts_autotune's choice per precision
   struct Trees {
     std::vector<int64_t> off;
@@ -1412,6 +1412,11 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
       }
       // QTS_PAIRS_AUTO: time a whole interactions pass both ways on the same
       // rows (at most one depth-first batch) and keep the faster form
+      // (the depth-first tables are built here on first use, where its walk
+      // fits in LDS; otherwise the path form stays)
+      if (ens->pair_traversal == QTS_PAIRS_AUTO && !ens->dfs.built &&
+          dfs_walk_lds_bytes((int)F, h.max_depth, true) <= (size_t)kMaxLdsBytes)
+        build_dfs(ens);
       if (ens->pair_traversal == QTS_PAIRS_AUTO && ens->dfs.built) {
         const std::string key = tune_key(device, "traversal", fp64, pol, h, 0, 0,
                                          ens->dfs.n_nodes, m_class);

@@ -186,10 +186,10 @@ class Builder {
 }  // namespace
 
 // Per row of a table: the number s of leading slots 1..s whose elements
-// (feature, missing_ok, interval, b) are identical to the previous row's,
-// for consecutive rows of at most 8 features (0 otherwise).  Rows are in tree
-// order with leaves left to right, so neighbours share the root side of
-// their paths; slot 0 is each row's own factor and is never shared.
+// (feature, missing_ok, interval, b) are identical to the previous row's.
+// Rows are in tree order with leaves left to right (stably grouped by
+// length bucket), so neighbours share the root side of their paths; slot 0
+// is each row's own factor and is never shared.
 static std::vector<int32_t> prefix_share(const std::vector<PathHdr>& hdr,
                                          const std::vector<int32_t>& feat,
                                          const std::vector<float>& lo,
@@ -200,7 +200,6 @@ static std::vector<int32_t> prefix_share(const std::vector<PathHdr>& hdr,
   for (size_t r = 1; r < hdr.size(); ++r) {
     const PathHdr& a = hdr[r];
     const PathHdr& q = hdr[r - 1];
-    if (a.d > 8 || q.d > 8) continue;
     const int n = std::min(a.d, q.d);
     int k = 1;
     for (; k < n; ++k) {

@@ -171,8 +171,12 @@ dfs_walk_kernel(const DfsNode* __restrict__ nodes, const T* __restrict__ coef,
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // each step's record is read one step ahead, so the LDS latency of
+      // the broadcast overlaps the previous step's arithmetic
+      StagedEvent<T> nx = stage[0];
       for (int k = 0; k < nwin; ++k) {
-        const StagedEvent<T>& w = stage[k];
+        const StagedEvent<T> w = nx;
+        nx = stage[min(k + 1, nwin - 1)];
         const int kind = __builtin_amdgcn_readfirstlane(w.kind);
         const int level = __builtin_amdgcn_readfirstlane(w.level);
         const int flags = __builtin_amdgcn_readfirstlane(w.flags);
@@ -192,8 +196,8 @@ dfs_walk_kernel(const DfsNode* __restrict__ nodes, const T* __restrict__ coef,
         } else if (kind == kDfsMiddle) {
           const T br = w.coef[4], cbr = w.coef[5];
           const T Fr = fmaD(tm, (mine & 4u) ? cbr : -br, br);
-          hst[level * 64 + lane] = H;
           const T Cv = cst[level * 64 + lane];
+          hst[level * 64 + lane] = H;
           C = fresh ? Cv * Fr : (Fv == T(0) ? T(0) : Cv * Fr * rcpD(Fv));
           H = w.lv[1] * C;
         } else {
@@ -233,7 +237,7 @@ dfs_leaf_values_kernel(const DfsNode* __restrict__ nodes, int32_t n,
 }
 
 template <typename T>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(1024)
 dfs_pairs_kernel(const int32_t* __restrict__ row_f, const int32_t* __restrict__ row_d,
                  const int32_t* __restrict__ tile_base, const int32_t* __restrict__ tile_d,
                  const int32_t* __restrict__ feat, const float* __restrict__ lo,
@@ -394,7 +398,7 @@ void pairs_t(const HostTable& h, const DeviceDfs& d, const NodeConsts<T>& nc, co
       int r1 = r0 + 1;
       while (r1 < F && tri_h(r1 + 1) - tri_h(r0) <= cap) ++r1;
       const size_t lds = fixed + (size_t)(tri_h(r1) - tri_h(r0)) * sizeof(double);
-      hipLaunchKernelGGL((dfs_pairs_kernel<T>), dim3((unsigned)grid), dim3(512), lds, s,
+      hipLaunchKernelGGL((dfs_pairs_kernel<T>), dim3((unsigned)grid), dim3(1024), lds, s,
                          d.row_f, d.row_d, d.tile_base, d.tile_d, d.feat, d.lo, d.hi, b, cb, t0,
                          t1, chunk, Y, d.n_rows, X, s0, mb, ldx, F, r0, r1, (int)first,
                          h.n_groups, g, tri64, phi64, nc);

@@ -419,6 +419,182 @@ __device__ __forceinline__ void values_rows_shared(
   }
 }
 
+// First order over rows of more than 8 features, reusing work between
+// consecutive rows.  Each wave walks a contiguous run of rows.  The products
+// are taken over the slots in the order 1, 2, ..., d - 1, 0: slot 0 (the
+// row's own factor, from Slot0) comes last, so the prefix products over slots
+// 1..j-1 depend only on those slots.  When slots 1..s equal the previous
+// row's (share[p] = s, from the host), the c_j of the batches of 8 slots that
+// lie within them are still in registers, and so are the prefix checkpoints
+// ck[b] = w prod_{1 <= k < 8b} F_k(m) of the batches b with 8b - 1 <= s (kept
+// across rows when all nodes run in one pass).  The backward sweep is that of values_paths with the suffix
+// products started from slot 0's factor; slot 0's own leave-one-out product
+// is the full prefix over slots 1..d-1 (inert padding slots are factors 1).
+template <typename T, int DMAX, int NH, bool STORE_G, bool NANS, int NN>
+__device__ __forceinline__ void values_rows_long(
+    const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
+    const float* __restrict__ lo, const float* __restrict__ hi, const T* __restrict__ bb,
+    const T* __restrict__ cbb, const Slot0<T>* __restrict__ z0,
+    const int32_t* __restrict__ share, const float* xs, double* as, int pb, int pe, int wave,
+    int nw, int lane, const T* tv, const NodeConsts<T>& nc) {
+  constexpr int NB = DMAX / 8;
+  constexpr bool kKeep = NH == NN;
+  const int run = (pe - pb + nw - 1) / nw;
+  const int p_first = pb + wave * run;
+  const int p_last = min(pe, p_first + run);
+  T cf[DMAX];     // c_j of the current row
+  T ck[NB][NH];   // prefix checkpoints
+  int ckv = 0;    // ck[1 .. ckv - 1] are the previous row's
+  for (int p = p_first; p < p_last; ++p) {
+    const int d = ldu(&hdr[p].d);
+    if (d == 0) {
+      ckv = 0;
+      continue;
+    }
+    const int off = ldu(&hdr[p].off);
+    const int s = p == p_first ? 0 : ldu(share + p);
+    const int nb = (d + 7) >> 3;
+    const Slot0<T>* z = z0 + p;
+    const T bm = ldu(&z->bm);
+    const T cA = ldu(&z->ca);
+    const T cB = ldu(&z->cb);
+    const float loB = ldu(&z->lo_b);
+    const float hiB = ldu(&z->hi_b);
+    const bool mokB = ldu(&z->mok_b) != 0;
+
+    // c_j of every batch with a slot past s (a batch's shared slots are
+    // evaluated again with it, to the same values: one branch per batch)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if (b < nb && (b == 0 || 8 * b + 7 > s)) {
+        const int jb = 8 * b;
+        int fm[8];
+        float l[8], u[8], x[8];
+        T bl[8], cbl[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          fm[k] = ldu(feat + off + jb + k);
+          l[k] = ldu(lo + off + jb + k);
+          u[k] = ldu(hi + off + jb + k);
+          bl[k] = ldu(bb + off + jb + k);
+          cbl[k] = ldu(cbb + off + jb + k);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = xs[(fm[k] & kFeatureMask) * kTileStride + lane];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int j = jb + k;
+          bool lower;
+          if (NANS) {
+            const bool miss = (fm[k] & kMissingOkBit) != 0;
+            lower = miss ? !(x[k] < l[k]) : (x[k] >= l[k]);
+          } else {
+            lower = x[k] >= l[k];
+          }
+          const bool in = lower & !(x[k] >= u[k]);
+          if (j == 0) {
+            bool lowerB;
+            if (NANS) lowerB = mokB ? !(x[0] < loB) : (x[0] >= loB);
+            else lowerB = x[0] >= loB;
+            const bool inB = lowerB & !(x[0] >= hiB);
+            cf[0] = in ? cA : (inB ? cB : -bm);
+          } else {
+            cf[j] = in ? cbl[k] : -bl[k];
+          }
+        }
+      }
+    }
+    const int f0 = ldu(feat + off) & kFeatureMask;
+
+#pragma unroll
+    for (int pass = 0; pass < NN / NH; ++pass) {
+      const int m0 = pass * NH;
+      // checkpoints, recomputed from the first batch whose slots are not all
+      // shared with the previous row
+#pragma unroll
+      for (int m = 0; m < NH; ++m) ck[0][m] = nc.w[m0 + m];
+      bool fresh = !kKeep;
+#pragma unroll
+      for (int b = 1; b < NB; ++b) {
+        if (b < nb) {
+          fresh = fresh || b >= ckv || 8 * b - 1 > s;
+          if (fresh) {
+#pragma unroll
+            for (int m = 0; m < NH; ++m) ck[b][m] = ck[b - 1][m];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              const int j = 8 * (b - 1) + k;
+              if (j > 0) {
+                const T bj = ldu(bb + off + j);
+#pragma unroll
+                for (int m = 0; m < NH; ++m) ck[b][m] *= fmaT(tv[m0 + m], cf[j], bj);
+              }
+            }
+          }
+        }
+      }
+      // backward sweep, last batch first; S starts from slot 0's factor
+      T S[NH];
+#pragma unroll
+      for (int m = 0; m < NH; ++m) S[m] = fmaT(tv[m0 + m], cf[0], bm);
+#pragma unroll
+      for (int b = NB - 1; b >= 0; --b) {
+        if (b < nb) {
+          const int jb = 8 * b;
+          T bj[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) bj[k] = jb + k == 0 ? T(1) : ldu(bb + off + jb + k);
+          T Pb[8][NH];
+          T Gb[STORE_G ? 8 : 1][NH];
+          T run[NH];
+#pragma unroll
+          for (int m = 0; m < NH; ++m) run[m] = ck[b][m];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+#pragma unroll
+            for (int m = 0; m < NH; ++m) {
+              Pb[k][m] = run[m];
+              if (jb + k > 0) {
+                const T g = fmaT(tv[m0 + m], cf[jb + k], bj[k]);
+                if (STORE_G) Gb[STORE_G ? k : 0][m] = g;
+                run[m] *= g;
+              }
+            }
+          }
+          if (b == nb - 1) {
+            // slot 0: w prod_{k >= 1} F_k(m), the full prefix
+            T dot = run[0];
+#pragma unroll
+            for (int m = 1; m < NH; ++m) dot += run[m];
+            __hip_atomic_fetch_add(&as[f0 * kTileStride + lane], (double)(cf[0] * dot),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+#pragma unroll
+          for (int k = 7; k >= 0; --k) {
+            const int j = jb + k;
+            if (j > 0) {
+              if (j < d) {
+                const int f = ldu(feat + off + j) & kFeatureMask;
+                T dot = Pb[k][0] * S[0];
+#pragma unroll
+                for (int m = 1; m < NH; ++m) dot = fmaT(Pb[k][m], S[m], dot);
+                __hip_atomic_fetch_add(&as[f * kTileStride + lane], (double)(cf[j] * dot),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              }
+#pragma unroll
+              for (int m = 0; m < NH; ++m) {
+                const T g = STORE_G ? Gb[STORE_G ? k : 0][m] : fmaT(tv[m0 + m], cf[j], bj[k]);
+                S[m] *= g;
+              }
+            }
+          }
+        }
+      }
+    }
+    ckv = kKeep ? nb : 0;
+  }
+}
+
 // The rows and tile features of one work item.  Work item b is (sample block
 // b mod nsb, row chunk b div nsb).  Ordinarily a chunk is `chunk` consecutive
 // rows of the bucket and the tile holds every feature; with segments (wide
@@ -505,7 +681,13 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
   // across rows: FP32 within 128 VGPRs (four waves per SIMD); FP64 only with
   // the 4-node rule (the 8-node FP64 instance has no registers to spare)
   constexpr bool kShared = DMAX == 8 && NH == NN && (STORE_G || NN == 4);
-  if (kShared && any_nan)
+  if (DMAX > 8 && any_nan)
+    values_rows_long<T, DMAX, NH, STORE_G, true, NN>(hdr, feat, lo, hi, bb, cbb, z0, share, xs,
+                                                     as, pb, pe, wave, nw, lane, tv, nc);
+  else if (DMAX > 8)
+    values_rows_long<T, DMAX, NH, STORE_G, false, NN>(hdr, feat, lo, hi, bb, cbb, z0, share, xs,
+                                                      as, pb, pe, wave, nw, lane, tv, nc);
+  else if (kShared && any_nan)
     values_rows_shared<T, NH, true>(hdr, feat, lo, hi, bb, cbb, z0, share, xs, as, pb, pe, wave,
                                     nw, lane, tv, nc);
   else if (kShared)

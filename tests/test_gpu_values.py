@@ -284,6 +284,37 @@ def test_shared_prefix_walk(q, oracle_mod, M):
             check(got, want_lv, "fp32", "shared prefix, leaf override " + tag)
 
 
+@pytest.mark.parametrize("M", [1, 77, 700])
+def test_long_row_reuse(q, oracle_mod, M):
+    """Rows of more than 8 features (deep grown trees, buckets 16, 32 and 64)
+    reuse the c_j of the leading slots they share with the previous row and,
+    with all nodes in one pass, the prefix checkpoints of whole shared
+    batches; each wave's run of rows starts afresh.  The sample count moves
+    the chunk boundaries; NaN inputs, both tables, FP32 and FP64 (two node
+    passes: no checkpoint reuse), and a leaf-value override."""
+    print("case long-row reuse M =", M, flush=True)
+    wl = synth.make_workload("c5_deep", T=4, M=M, n_train=30000)
+    ens = wl.ensemble
+    X = wl.X.copy()
+    rng = np.random.default_rng(900 + M)
+    X[rng.random(X.shape) < 0.05] = np.nan
+    lv = rng.normal(size=ens.n_leaves())
+    want = oracle_mod.shap_values(ens, X, n=8)
+    want_lv = oracle_mod.shap_values(ens.with_leaf_values(lv), X, n=8)
+    e = q.Ensemble(ens)
+    assert e.info["max_unique"] > 16 and e.info["n_value_shared"] > 0
+    Xd = torch.from_numpy(X).cuda()
+    lvd = torch.from_numpy(lv).cuda()
+    for merge in (True, False):
+        e.set_sibling_merge(merge)
+        for precision in ("fp32", "fp64"):
+            tag = "merge=%s %s" % (merge, precision)
+            got = e.shap_values(Xd, precision).double().cpu().numpy()
+            check(got, want, precision, "long rows " + tag)
+            got = e.shap_values(Xd, precision, leaf_values=lvd).double().cpu().numpy()
+            check(got, want_lv, precision, "long rows, leaf override " + tag)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_output_fully_overwritten(q, oracle_mod, precision):
     """Calls that write phi directly from the workgroups (one bucket walked

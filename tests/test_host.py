@@ -290,8 +290,6 @@ def _first_order_rows(ens, merged):
 def _shared_slots(rows):
     total = 0
     for prev, row in zip(rows, rows[1:]):
-        if len(prev) > 8 or len(row) > 8:
-            continue
         k = 1
         while k < min(len(prev), len(row)) and prev[k] == row[k]:
             k += 1
@@ -306,9 +304,9 @@ def _shared_slots(rows):
     ("c5_deep", dict(T=2, M=4, n_train=30000)),
 ])
 def test_shared_prefix_counts(q, name, over):
-    """The first-order kernel for rows of at most 8 features reuses the factors
-    of the leading slots (after slot 0) that equal the previous row's; the
-    library's per-table totals must equal those of the rows rebuilt here."""
+    """The first-order kernels reuse the work of the leading slots (after slot
+    0) that equal the previous row's; the library's per-table totals must
+    equal those of the rows rebuilt here (rows of every length)."""
     wl = synth.make_workload(name, **over)
     e = q.Ensemble(wl.ensemble, host_only=True)
     want_m = _shared_slots(_first_order_rows(wl.ensemble, merged=True))
