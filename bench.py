@@ -629,7 +629,6 @@ def measure_wide(args, torch, q, synth, oracle, dev):
     for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
         if not args.no_autotune:
             e.autotune(M, prec)
-        tr = traversal(e, prec)
         e.set_graph_replay(not args.eager)
         phi = torch.empty((M, F), dtype=dt, device=dev)
         res[prec] = time_steps(lambda: e.shap_values(X, prec, out=phi), 5, 1, torch)

@@ -533,7 +533,18 @@ bool direct_call(const qts_ensemble* ens, int64_t M, bool fp64) {
 // Output elements per sample: K groups of F features.
 int64_t out_row(const qts_ensemble* ens) { return (int64_t)ens->host.n_groups * ens->host.F; }
 
+// Wide feature spaces (wide_features): the first-order and adjoint kernels
+// take X feature-major, [F][M], in the call's scratch.
+size_t xt_region(const qts_ensemble* ens, int64_t M) {
+  return (sizeof(float) * (size_t)(M * ens->host.F) + 255) & ~(size_t)255;
+}
+
+// Layout: Slot0 records | (wide: X feature-major | FP64 accumulator [K][F][M])
+// | (otherwise, FP32 output: FP64 accumulator [M][K][F]).
 size_t values_scratch_bytes(const qts_ensemble* ens, int64_t M, bool fp64) {
+  if (wide_features(ens->host.F))
+    return slot0_region(ens, fp64) + xt_region(ens, M) +
+           sizeof(double) * (size_t)(M * out_row(ens));
   const bool acc = !fp64 && (ens->deterministic || !direct_call(ens, M, fp64));
   return slot0_region(ens, fp64) + (acc ? sizeof(double) * (size_t)(M * out_row(ens)) : 0);
 }
@@ -548,17 +559,40 @@ void issue_values(const qts_ensemble* ens, const float* X, int64_t M, int64_t ld
                                              : plain_arrays(ens->dev, ens->host);
   const std::vector<Bucket>& bks = ens->merge_siblings ? h.mbuckets : h.buckets;
   launch_slot0(arr, value_rows(ens), leaf, fp64, slot0, ln.main);
+  // wide feature spaces: X transposed into the scratch, the accumulator
+  // [K][F][M], transposed into phi at the end
+  const bool fmajor = wide_features(h.F);
+  const int64_t F = h.F, K = h.n_groups;
+  const float* Xk = X;
+  int64_t ldk = ldx;
+  double* a;
+  if (fmajor) {
+    float* xt = (float*)((char*)scratch + slot0_region(ens, fp64));
+    a = (double*)((char*)xt + xt_region(ens, M));
+    launch_transpose(X, M, F, ldx, 0, xt, M, 0, 1, ln.main);
+    Xk = xt;
+    ldk = M;
+  } else {
+    a = fp64 ? (double*)phi : (double*)((char*)scratch + slot0_region(ens, fp64));
+  }
+  auto finish = [&] {
+    if (fmajor) {
+      if (fp64) launch_transpose(a, F, M, M, F * M, (double*)phi, K * F, F, (int32_t)K, ln.main);
+      else launch_transpose(a, F, M, M, F * M, (float*)phi, K * F, F, (int32_t)K, ln.main);
+    } else if (!fp64) {
+      launch_cast_f64_f32(a, (float*)phi, n, ln.main);
+    }
+  };
   if (ens->deterministic) {
     // one stream, buckets and chunks in order, adds without atomics
-    double* a = fp64 ? (double*)phi : (double*)((char*)scratch + slot0_region(ens, fp64));
     launch_fill_zero(a, n, ln.main);
     TimedScope ts(0, timed ? ln.main : nullptr, timed);
     for (const Bucket& bk : bks)
-      launch_values(h, ens->dev, arr, bk, fp64, X, M, ldx, slot0, a, nullptr,
+      launch_values(h, ens->dev, arr, bk, fp64, Xk, M, ldk, slot0, a, nullptr,
                     ens->vshape[pol_index(ens)][fp64 ? 1 : 0][cap_index(bk.dmax)],
                     nodes_of(ens), ln.main, true);
     ts.done();
-    if (!fp64) launch_cast_f64_f32(a, (float*)phi, n, ln.main);
+    finish();
     return;
   }
   if (direct_call(ens, M, fp64)) {
@@ -569,19 +603,18 @@ void issue_values(const qts_ensemble* ens, const float* X, int64_t M, int64_t ld
     ts.done();
     return;
   }
-  double* a = fp64 ? (double*)phi : (double*)((char*)scratch + slot0_region(ens, fp64));
   launch_fill_zero(a, n, ln.main);
   TimedScope ts(0, timed ? ln.main : nullptr, timed);
   ln.fork((int)bks.size());
   for (size_t i = 0; i < bks.size(); ++i) {
     const Bucket& bk = bks[i];
-    launch_values(h, ens->dev, arr, bk, fp64, X, M, ldx, slot0, a, nullptr,
+    launch_values(h, ens->dev, arr, bk, fp64, Xk, M, ldk, slot0, a, nullptr,
                   ens->vshape[pol_index(ens)][fp64 ? 1 : 0][cap_index(bk.dmax)], nodes_of(ens),
                   ln.pick((int)i));
   }
   ln.join();
   ts.done();
-  if (!fp64) launch_cast_f64_f32(a, (float*)phi, n, ln.main);
+  finish();
 }
 
 // Whether an interactions call of this precision takes the depth-first form.
@@ -667,17 +700,47 @@ void issue_interactions(const qts_ensemble* ens, const float* X, int64_t M, int6
 
 // Scratch of a backward call: deterministic calls keep one row of leaf
 // partial sums per 64-sample block.
-size_t backward_scratch_bytes(const qts_ensemble* ens, int64_t M) {
-  if (!ens->deterministic || M == 0) return 0;
-  const int64_t nsb = (M + kSamplesPerBlock - 1) / kSamplesPerBlock;
-  return sizeof(double) * (size_t)(nsb * (int64_t)ens->host.leaf_value.size());
+// Layout: (wide: X feature-major | grad_phi feature-major [K][F][M]) |
+// (deterministic: per-sample-block leaf partials).
+size_t gt_region(const qts_ensemble* ens, int64_t M, bool fp64) {
+  return ((fp64 ? sizeof(double) : sizeof(float)) * (size_t)(M * out_row(ens)) + 255) &
+         ~(size_t)255;
+}
+size_t backward_scratch_bytes(const qts_ensemble* ens, int64_t M, bool fp64) {
+  if (M == 0) return 0;
+  size_t b = 0;
+  if (wide_features(ens->host.F)) b += xt_region(ens, M) + gt_region(ens, M, fp64);
+  if (ens->deterministic) {
+    const int64_t nsb = (M + kSamplesPerBlock - 1) / kSamplesPerBlock;
+    b += sizeof(double) * (size_t)(nsb * (int64_t)ens->host.leaf_value.size());
+  }
+  return b;
 }
 
 void issue_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
-                    const void* grad_phi, double* grad_leaf, bool fp64, double* scratch,
+                    const void* grad_phi, double* grad_leaf, bool fp64, double* scratch_in,
                     Lanes& ln, bool timed) {
   const HostTable& h = ens->host;
   const int64_t L = (int64_t)h.leaf_value.size();
+  char* sp = (char*)scratch_in;
+  // wide feature spaces: X and grad_phi transposed into the scratch
+  if (wide_features(h.F) && M > 0) {
+    const int64_t F = h.F, K = h.n_groups;
+    float* xt = (float*)sp;
+    sp += xt_region(ens, M);
+    launch_transpose(X, M, F, ldx, 0, xt, M, 0, 1, ln.main);
+    if (fp64)
+      launch_transpose((const double*)grad_phi, M, F, K * F, F, (double*)sp, M, F * M,
+                       (int32_t)K, ln.main);
+    else
+      launch_transpose((const float*)grad_phi, M, F, K * F, F, (float*)sp, M, F * M,
+                       (int32_t)K, ln.main);
+    X = xt;
+    ldx = M;
+    grad_phi = sp;
+    sp += gt_region(ens, M, fp64);
+  }
+  double* scratch = (double*)sp;
   if (ens->deterministic && M > 0) {
     const int64_t nsb = (M + kSamplesPerBlock - 1) / kSamplesPerBlock;
     launch_fill_zero(scratch, nsb * L, ln.main);
@@ -1157,7 +1220,7 @@ int qts_shap_backward(const qts_ensemble* ens, const float* X, int64_t M, int64_
     hipStream_t s = (hipStream_t)stream;
     const bool fp64 = precision == QTS_FP64;
     qts_ensemble* me = const_cast<qts_ensemble*>(ens);
-    const size_t scratch_bytes = backward_scratch_bytes(ens, M);
+    const size_t scratch_bytes = backward_scratch_bytes(ens, M, fp64);
     if (ens->graphs.on && M > 0) {
       GraphKey key{2, fp64, X, M, ldx, grad_phi, grad_leaf, nullptr, s};
       run_graph(me, key, scratch_bytes, 2, [&](Lanes& ln, double* scratch) {
@@ -1286,6 +1349,8 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
     const int64_t K = h.n_groups;
     Scratch xs(sizeof(float) * (size_t)(Mt * F), s);
     const float* X = (const float*)xs.p;
+    // the first-order kernels of wide feature spaces read it feature-major
+    const int64_t ldt = wide_features((int)F) ? Mt : F;
     launch_fill_uniform((float*)xs.p, Mt * F, 0x2605u, s);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     check_hip(hipEventCreate(&e0), "hipEventCreate");
@@ -1328,7 +1393,7 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
             for (int items : {4096, 8192, 16384, 32768, 65536}) {
               const ValuesShape cand{waves, items};
               const float ms = time_ms(3, [&] {
-                launch_values(h, d, arr, bk, fp64, X, Mt, F, slot0.p, (double*)acc.p, nullptr,
+                launch_values(h, d, arr, bk, fp64, X, Mt, ldt, slot0.p, (double*)acc.p, nullptr,
                               cand, nodes_of(ens), s);
               });
               if (ms < best_ms) {
@@ -1362,7 +1427,7 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
             for (int items : {4096, 8192, 16384, 32768, 65536}) {
               const ValuesShape cand{waves, items};
               const float ms = time_ms(3, [&] {
-                launch_adjoint(h, d, arr, bk, fp64, X, G, Mt, F, (double*)gl.p, cand,
+                launch_adjoint(h, d, arr, bk, fp64, X, G, Mt, ldt, (double*)gl.p, cand,
                                nodes_of(ens), s);
               });
               if (ms < best_ms) {

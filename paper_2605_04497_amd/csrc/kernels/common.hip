@@ -1,5 +1,6 @@
 // Small element-wise kernels: zero fill (used instead of hipMemsetAsync so
-// the call sequence stays safe to capture in a HIP graph) and FP64 -> FP32.
+// the call sequence stays safe to capture in a HIP graph), FP64 -> FP32, and
+// tiled transposes (the feature-major layouts of wide feature spaces).
 #include <hip/hip_runtime.h>
 
 #include <map>
@@ -69,6 +70,55 @@ __global__ void __launch_bounds__(256) sum_rows_kernel(const double* __restrict_
     for (int64_t r = 0; r < nrows; ++r) acc += part[r * n + i];
     out[i] = acc;
   }
+}
+
+// dst[b][c][r] = src[b][r][c] for r < R, c < C (row strides lds, ldd; batch
+// strides sbs, dbs): 32 x 32 tiles through LDS, so both the reads and the
+// writes are coalesced.
+template <typename Ti, typename To>
+__global__ void __launch_bounds__(256)
+transpose_kernel(const Ti* __restrict__ src, int64_t R, int64_t C, int64_t lds, int64_t sbs,
+                 To* __restrict__ dst, int64_t ldd, int64_t dbs, int64_t tiles_c) {
+  __shared__ Ti tile[32][33];
+  const int64_t t = blockIdx.x;
+  const int64_t r0 = (t / tiles_c) * 32, c0 = (t % tiles_c) * 32;
+  const Ti* sp = src + (int64_t)blockIdx.y * sbs;
+  To* dp = dst + (int64_t)blockIdx.y * dbs;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int j = ty; j < 32; j += 8) {
+    const int64_t r = r0 + j, c = c0 + tx;
+    if (r < R && c < C) tile[j][tx] = sp[r * lds + c];
+  }
+  __syncthreads();
+  for (int j = ty; j < 32; j += 8) {
+    const int64_t c = c0 + j, r = r0 + tx;
+    if (r < R && c < C) dp[c * ldd + r] = (To)tile[tx][j];
+  }
+}
+
+template <typename Ti, typename To>
+static void transpose_t(const Ti* src, int64_t R, int64_t C, int64_t lds, int64_t sbs, To* dst,
+                        int64_t ldd, int64_t dbs, int32_t nbatch, hipStream_t s) {
+  if (R <= 0 || C <= 0 || nbatch <= 0) return;
+  const int64_t tiles_c = (C + 31) / 32;
+  const int64_t tiles = ((R + 31) / 32) * tiles_c;
+  if (tiles > 0x7fffffff || nbatch > 65535) fail(QTS_E_UNSUPPORTED, "transpose too large");
+  hipLaunchKernelGGL((transpose_kernel<Ti, To>), dim3((unsigned)tiles, (unsigned)nbatch),
+                     dim3(256), 0, s, src, R, C, lds, sbs, dst, ldd, dbs, tiles_c);
+  check_hip(hipGetLastError(), "transpose launch");
+}
+
+void launch_transpose(const float* src, int64_t R, int64_t C, int64_t lds, int64_t sbs,
+                      float* dst, int64_t ldd, int64_t dbs, int32_t nbatch, hipStream_t s) {
+  transpose_t(src, R, C, lds, sbs, dst, ldd, dbs, nbatch, s);
+}
+void launch_transpose(const double* src, int64_t R, int64_t C, int64_t lds, int64_t sbs,
+                      double* dst, int64_t ldd, int64_t dbs, int32_t nbatch, hipStream_t s) {
+  transpose_t(src, R, C, lds, sbs, dst, ldd, dbs, nbatch, s);
+}
+void launch_transpose(const double* src, int64_t R, int64_t C, int64_t lds, int64_t sbs,
+                      float* dst, int64_t ldd, int64_t dbs, int32_t nbatch, hipStream_t s) {
+  transpose_t(src, R, C, lds, sbs, dst, ldd, dbs, nbatch, s);
 }
 
 static unsigned grid_for(int64_t n) {

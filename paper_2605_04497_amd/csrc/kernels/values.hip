@@ -649,15 +649,24 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
   const ItemRows ir = item_rows(segs, seg_feat, ch, path_begin, path_end, chunk, F);
   const int nf = ir.nf;
 
-  // stage the sample tile transposed; zero the accumulator; note any NaN
+  // stage the sample tile transposed; zero the accumulator; note any NaN.
+  // With segments (wide feature spaces) X is feature-major [F][ldx] and acc
+  // [ng][F][M], so consecutive threads take consecutive samples of a feature.
+  const bool fmajor = segs != nullptr;
   const int tile = kSamplesPerBlock * nf;
   int nan_seen = 0;
   for (int i = threadIdx.x; i < tile; i += blockDim.x) {
-    const int r = i / nf;
-    const int k = i - r * nf;
+    int r, k;
+    if (fmajor) {
+      k = i >> 6;
+      r = i & 63;
+    } else {
+      r = i / nf;
+      k = i - r * nf;
+    }
     const int f = ir.fmap ? ir.fmap[k] : k;
     const int64_t s = s0 + r;
-    const float v = (s < M) ? X[s * ldx + f] : 0.0f;
+    const float v = (s < M) ? X[fmajor ? (int64_t)f * ldx + s : s * ldx + f] : 0.0f;
     nan_seen |= (v != v);
     xs[k * kTileStride + r] = v;
     as[k * kTileStride + r] = 0.0;
@@ -707,13 +716,20 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
   // direct: this workgroup is the only one of its sample block (one bucket,
   // one chunk), so it writes phi rows outright, in the output precision.
   for (int i = threadIdx.x; i < tile; i += blockDim.x) {
-    const int r = i / nf;
-    const int k = i - r * nf;
+    int r, k;
+    if (fmajor) {
+      k = i >> 6;
+      r = i & 63;
+    } else {
+      r = i / nf;
+      k = i - r * nf;
+    }
     const int f = ir.fmap ? ir.fmap[k] : k;
     const int64_t s = s0 + r;
     if (s < M) {
       const double v = as[k * kTileStride + r];
-      const int64_t o = (s * ng + grp) * F + f;  // phi[s, grp, f]
+      // phi[s, grp, f], or acc[grp, f, s] feature-major
+      const int64_t o = fmajor ? ((int64_t)grp * F + f) * M + s : (s * ng + grp) * F + f;
       if (direct != nullptr) {
         if (direct_fp64) static_cast<double*>(direct)[o] = v;
         else static_cast<float*>(direct)[o] = (float)v;
@@ -888,18 +904,28 @@ adjoint_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat
   const int nf = ir.nf;
 
   // stage the sample rows and gradient rows transposed (padding rows get a
-  // zero gradient, so they add nothing); note any NaN
+  // zero gradient, so they add nothing); note any NaN.  With segments (wide
+  // feature spaces) X is feature-major [F][ldx] and G [ng][F][M].
+  const bool fmajor = segs != nullptr;
   const int tile = kSamplesPerBlock * nf;
   int nan_seen = 0;
   for (int i = threadIdx.x; i < tile; i += blockDim.x) {
-    const int r = i / nf;
-    const int k = i - r * nf;
+    int r, k;
+    if (fmajor) {
+      k = i >> 6;
+      r = i & 63;
+    } else {
+      r = i / nf;
+      k = i - r * nf;
+    }
     const int f = ir.fmap ? ir.fmap[k] : k;
     const int64_t s = s0 + r;
-    const float v = (s < M) ? X[s * ldx + f] : 0.0f;
+    const float v = (s < M) ? X[fmajor ? (int64_t)f * ldx + s : s * ldx + f] : 0.0f;
     nan_seen |= (v != v);
     xs[k * kTileStride + r] = v;
-    gs[k * kTileStride + r] = (s < M) ? G[(s * ng + grp) * F + f] : T(0);  // G[s, grp, f]
+    // G[s, grp, f], or G[grp, f, s] feature-major
+    gs[k * kTileStride + r] =
+        (s < M) ? G[fmajor ? ((int64_t)grp * F + f) * M + s : (s * ng + grp) * F + f] : T(0);
   }
   const bool any_nan = __syncthreads_or(nan_seen) != 0;
 

@@ -232,6 +232,14 @@ void launch_fill_zero(double* p, int64_t n, hipStream_t s);
 void launch_fill_uniform(float* p, int64_t n, uint32_t seed, hipStream_t s);
 void launch_cast_f64_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 void launch_widen_f32_f64(const float* src, double* dst, int64_t n, hipStream_t s);
+// Batched transposes: dst[b][c][r] = src[b][r][c], r < R, c < C (row strides
+// lds and ldd, batch strides sbs and dbs, nbatch batches), with a cast.
+void launch_transpose(const float* src, int64_t R, int64_t C, int64_t lds, int64_t sbs,
+                      float* dst, int64_t ldd, int64_t dbs, int32_t nbatch, hipStream_t s);
+void launch_transpose(const double* src, int64_t R, int64_t C, int64_t lds, int64_t sbs,
+                      double* dst, int64_t ldd, int64_t dbs, int32_t nbatch, hipStream_t s);
+void launch_transpose(const double* src, int64_t R, int64_t C, int64_t lds, int64_t sbs,
+                      float* dst, int64_t ldd, int64_t dbs, int32_t nbatch, hipStream_t s);
 // out[i] = sum_r part[r * n + i] over r = 0 .. nrows-1, in that order.
 void launch_sum_rows(const double* part, int64_t nrows, int64_t n, double* out, hipStream_t s);
 
@@ -250,6 +258,9 @@ size_t slot0_bytes(int32_t n_rows, bool fp64);
 // deterministic: one wavefront per workgroup and one launch per row chunk,
 // in chunk order, each adding its tiles to acc without atomics (each (sample,
 // feature) has one owner per launch), so phi does not depend on scheduling.
+// Wide feature spaces (wide_features(F): the table's work items are
+// segments) take feature-major layouts: X is [F][ldx] (ldx >= M) and acc
+// [n_groups][F][M]; `direct` is not used there.
 void launch_values(const HostTable& h, const DeviceTable& d, const PathArrays& a,
                    const Bucket& bk, bool fp64, const float* X, int64_t M, int64_t ldx,
                    const void* slot0, double* acc, void* direct, const ValuesShape& shape,
@@ -263,7 +274,8 @@ bool values_direct(const std::vector<Bucket>& bks, int64_t M, const ValuesShape&
 
 // Adjoint: add J^T G over the rows of one bucket into grad_leaf (pre-zeroed);
 // a merged row adds to both of its leaves.
-// G is [M, F] float (fp64 = false) or double.
+// G is [M, F] float (fp64 = false) or double; wide feature spaces take X as
+// [F][ldx] and G as [n_groups][F][M] (feature-major, as launch_values).
 // part_stride > 0 (deterministic): grad_leaf is [sample blocks][part_stride],
 // zeroed by the caller; each sample block stores its rows' leaf sums there
 // without atomics (every leaf belongs to one row), and the caller adds the

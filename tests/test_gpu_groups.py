@@ -86,3 +86,35 @@ def test_grouped_third_order_and_replay(q, oracle_mod):
         check(out.double().cpu().numpy().reshape(33, 12), want.reshape(33, 12), "fp32",
               "grouped replay")
     e.set_graph_replay(False)
+
+
+def test_grouped_wide_feature_space(q, oracle_mod):
+    """300 features (the first-order kernels take segments, X and grad_phi
+    feature-major, an accumulator [K][F][M] transposed into phi [M][K][F]) with
+    two outputs: values and the adjoint, both precisions, eager, graph replay
+    and the deterministic mode, against the oracle's per-group composition."""
+    wl = synth.make_workload("c2_values", F=300, T=24, M=150, n_train=20000, groups=2)
+    ens, X = wl.ensemble, wl.X.copy()
+    K, F, M = ens.n_groups, ens.n_features, X.shape[0]
+    X[::7, ::5] = np.nan
+    e = q.Ensemble(ens)
+    assert e.info["n_value_segments"] > 0
+    Xd = torch.from_numpy(X).cuda()
+    want = oracle_mod.shap_values_grouped(ens, X)
+    G = np.random.default_rng(31).standard_normal((M, K, F))
+    for mode in ("eager", "replay", "deterministic"):
+        e.set_graph_replay(mode == "replay")
+        e.set_deterministic(mode == "deterministic")
+        for precision in ("fp32", "fp64"):
+            for _ in range(2 if mode == "replay" else 1):
+                phi = e.shap_values(Xd, precision)
+                check(phi.double().cpu().numpy().reshape(M * K, F), want.reshape(M * K, F),
+                      precision, "wide grouped phi %s" % mode)
+                Gp = G.astype(np.float32).astype(np.float64) if precision == "fp32" else G
+                gw = oracle_mod.leaf_grad_grouped(ens, X, Gp)
+                gl = e.shap_backward(Xd, torch.from_numpy(Gp).cuda(), precision).cpu().numpy()
+                err = float(np.abs(gl - gw).max() / np.abs(gw).max())
+                assert err <= (1e-5 if precision == "fp32" else 1e-10), (mode, precision, err)
+    e.set_graph_replay(False)
+    e.set_deterministic(False)
+
