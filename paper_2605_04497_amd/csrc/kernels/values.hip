@@ -655,21 +655,25 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
   const bool fmajor = segs != nullptr;
   const int tile = kSamplesPerBlock * nf;
   int nan_seen = 0;
-  for (int i = threadIdx.x; i < tile; i += blockDim.x) {
-    int r, k;
-    if (fmajor) {
-      k = i >> 6;
-      r = i & 63;
-    } else {
-      r = i / nf;
-      k = i - r * nf;
+  if (fmajor) {
+    for (int i = threadIdx.x; i < tile; i += blockDim.x) {
+      const int k = i >> 6, r = i & 63;
+      const int64_t s = s0 + r;
+      const float v = (s < M) ? X[(int64_t)ir.fmap[k] * ldx + s] : 0.0f;
+      nan_seen |= (v != v);
+      xs[k * kTileStride + r] = v;
+      as[k * kTileStride + r] = 0.0;
     }
-    const int f = ir.fmap ? ir.fmap[k] : k;
-    const int64_t s = s0 + r;
-    const float v = (s < M) ? X[fmajor ? (int64_t)f * ldx + s : s * ldx + f] : 0.0f;
-    nan_seen |= (v != v);
-    xs[k * kTileStride + r] = v;
-    as[k * kTileStride + r] = 0.0;
+  } else {
+    for (int i = threadIdx.x; i < tile; i += blockDim.x) {
+      const int r = i / nf;
+      const int k = i - r * nf;
+      const int64_t s = s0 + r;
+      const float v = (s < M) ? X[s * ldx + k] : 0.0f;
+      nan_seen |= (v != v);
+      xs[k * kTileStride + r] = v;
+      as[k * kTileStride + r] = 0.0;
+    }
   }
   const bool any_nan = __syncthreads_or(nan_seen) != 0;
 
@@ -715,21 +719,29 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
   // flush: consecutive threads take consecutive features of one sample.
   // direct: this workgroup is the only one of its sample block (one bucket,
   // one chunk), so it writes phi rows outright, in the output precision.
-  for (int i = threadIdx.x; i < tile; i += blockDim.x) {
-    int r, k;
-    if (fmajor) {
-      k = i >> 6;
-      r = i & 63;
-    } else {
-      r = i / nf;
-      k = i - r * nf;
+  if (fmajor) {
+    // acc[grp, f, s] (segments never write phi directly)
+    for (int i = threadIdx.x; i < tile; i += blockDim.x) {
+      const int k = i >> 6, r = i & 63;
+      const int64_t s = s0 + r;
+      if (s < M) {
+        const double v = as[k * kTileStride + r];
+        const int64_t o = ((int64_t)grp * F + ir.fmap[k]) * M + s;
+        if (v != 0.0) {
+          if (plain_add) acc[o] += v;
+          else unsafeAtomicAdd(&acc[o], v);
+        }
+      }
     }
-    const int f = ir.fmap ? ir.fmap[k] : k;
+    return;
+  }
+  for (int i = threadIdx.x; i < tile; i += blockDim.x) {
+    const int r = i / nf;
+    const int k = i - r * nf;
     const int64_t s = s0 + r;
     if (s < M) {
       const double v = as[k * kTileStride + r];
-      // phi[s, grp, f], or acc[grp, f, s] feature-major
-      const int64_t o = fmajor ? ((int64_t)grp * F + f) * M + s : (s * ng + grp) * F + f;
+      const int64_t o = (s * ng + grp) * F + k;  // phi[s, grp, f]
       if (direct != nullptr) {
         if (direct_fp64) static_cast<double*>(direct)[o] = v;
         else static_cast<float*>(direct)[o] = (float)v;
@@ -909,23 +921,26 @@ adjoint_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat
   const bool fmajor = segs != nullptr;
   const int tile = kSamplesPerBlock * nf;
   int nan_seen = 0;
-  for (int i = threadIdx.x; i < tile; i += blockDim.x) {
-    int r, k;
-    if (fmajor) {
-      k = i >> 6;
-      r = i & 63;
-    } else {
-      r = i / nf;
-      k = i - r * nf;
+  if (fmajor) {
+    for (int i = threadIdx.x; i < tile; i += blockDim.x) {
+      const int k = i >> 6, r = i & 63;
+      const int f = ir.fmap[k];
+      const int64_t s = s0 + r;
+      const float v = (s < M) ? X[(int64_t)f * ldx + s] : 0.0f;
+      nan_seen |= (v != v);
+      xs[k * kTileStride + r] = v;
+      gs[k * kTileStride + r] = (s < M) ? G[((int64_t)grp * F + f) * M + s] : T(0);  // G[grp, f, s]
     }
-    const int f = ir.fmap ? ir.fmap[k] : k;
-    const int64_t s = s0 + r;
-    const float v = (s < M) ? X[fmajor ? (int64_t)f * ldx + s : s * ldx + f] : 0.0f;
-    nan_seen |= (v != v);
-    xs[k * kTileStride + r] = v;
-    // G[s, grp, f], or G[grp, f, s] feature-major
-    gs[k * kTileStride + r] =
-        (s < M) ? G[fmajor ? ((int64_t)grp * F + f) * M + s : (s * ng + grp) * F + f] : T(0);
+  } else {
+    for (int i = threadIdx.x; i < tile; i += blockDim.x) {
+      const int r = i / nf;
+      const int k = i - r * nf;
+      const int64_t s = s0 + r;
+      const float v = (s < M) ? X[s * ldx + k] : 0.0f;
+      nan_seen |= (v != v);
+      xs[k * kTileStride + r] = v;
+      gs[k * kTileStride + r] = (s < M) ? G[(s * ng + grp) * F + k] : T(0);  // G[s, grp, f]
+    }
   }
   const bool any_nan = __syncthreads_or(nan_seen) != 0;
 
