@@ -59,7 +59,9 @@ enum {
                                negative or NaN cover, NaN threshold */
   QTS_E_UNSUPPORTED = -3,   /* tree deeper than 128, path with > 64 unique features;
                                qts_shap_interactions3 also when one feature's
-                               triples do not fit in LDS (F above about 170) */
+                               triples do not fit in LDS (F above about 170 in
+                               the path form, about 200 in the depth-first
+                               form) */
   QTS_E_HIP = -4,           /* a HIP runtime error; its text is in qts_last_error() */
   QTS_E_OOM = -5            /* host or device allocation failed */
 };
@@ -158,11 +160,14 @@ typedef struct {
                                 using at most 96 distinct features; 0 otherwise */
   int32_t n_groups;          /* output groups (1 unless loaded grouped) */
   int32_t pairs_dfs;         /* bit 0 (FP32), bit 1 (FP64): qts_shap_interactions takes
-                                the depth-first form */
+                                the depth-first form; bit 2 (FP32), bit 3 (FP64):
+                                qts_shap_interactions3 does */
   int64_t n_dfs_nodes;       /* internal nodes of the depth-first interactions form
-                                (0 until qts_set_pair_traversal selects it) */
+                                (0 until its tables are built) */
   int64_t n_dfs_updates;     /* its pair updates per sample: the features split above
                                 each internal node, summed */
+  int64_t n_dfs_updates3;    /* its third-order updates per sample: pairs of those
+                                features, summed over the internal nodes */
 } qts_info;
 
 int qts_get_info(const qts_ensemble* ens, qts_info* out);
@@ -232,9 +237,19 @@ int qts_shap_interactions(const qts_ensemble* ens, const float* X, int64_t M, in
  *   leaf_values, X, M, ldx, precision, stream as for qts_shap_values.
  * Accumulation is in FP64 throughout; the FP32 form allocates an FP64
  * accumulator of M * F(F-1)(F-2)/6 doubles on `stream` for the call.  Calls
- * run eagerly (graph replay does not apply).  Errors: QTS_E_UNSUPPORTED when
- * one feature's triples (k(k-1)/2 of them) do not fit in LDS (F above about
- * 170). */
+ * run eagerly (graph replay does not apply).
+ * The traversal follows qts_set_pair_traversal: the path form, or Algorithm 1
+ * taken to order 3 (section 5): along a path the product of three features'
+ * ratios r = (o - b) / F changes only where one of them is split, by that
+ * feature's change times the other two ratios, so with the walk's y_v of
+ * qts_shap_interactions
+ *   SII_{f j k} += sum_m y_v(t_m) r_j^v(t_m) r_k^v(t_m)
+ * at each internal node v on feature f, for every pair {j, k} of the other
+ * features split above v.  That form holds rows of at most 32 such features
+ * (trees of depth up to 33); deeper ensembles keep the path form.
+ * Errors: QTS_E_UNSUPPORTED when one feature's triples (k(k-1)/2 of them) do
+ * not fit in LDS (F above about 170 in the path form, about 200 in the
+ * depth-first form). */
 int qts_shap_interactions3(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
                            const double* leaf_values, void* out, qts_precision precision,
                            void* stream);
@@ -357,7 +372,9 @@ int qts_set_node_policy(qts_ensemble* ens, int32_t policy);
  *     ensemble, per precision (timed on one batch of its synthetic rows; kept
  *     in the autotune cache); the path form until the ensemble is tuned, and
  *     where the walk's stacks do not fit in LDS.  qts_autotune builds the
- *     depth-first tables on first use. */
+ *     depth-first tables on first use.
+ * The setting also selects the form of qts_shap_interactions3 (chosen
+ * separately by qts_autotune under QTS_PAIRS_AUTO). */
 enum { QTS_PAIRS_PATHS = 0, QTS_PAIRS_DFS = 1, QTS_PAIRS_AUTO = 2 };
 int qts_set_pair_traversal(qts_ensemble* ens, int32_t traversal);
 

@@ -77,6 +77,7 @@ struct qts_ensemble {
   // arrays are kept to build its tables on first use
   int pair_traversal = QTS_PAIRS_AUTO;
   bool dfs_faster[2] = {false, false};  // QTS_PAIRS_AUTO: qts_autotune's choice per precision
+  bool dfs3_faster[2] = {false, false};  // the same for the third-order call
   struct Trees {
     std::vector<int64_t> off;
     std::vector<int32_t> left, right, feature;
@@ -273,6 +274,8 @@ void build_dfs(qts_ensemble* e) {
     d.cb64 = upload(t.cb, s);
     d.group_tile = t.group_tile;
     d.n_updates = t.n_updates;
+    d.n_updates3 = t.n_updates3;
+    d.max_row_d = t.max_row_d;
     d.n_nodes = (int64_t)t.nodes.size();
     check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
     d.built = true;
@@ -621,6 +624,14 @@ void issue_values(const qts_ensemble* ens, const float* X, int64_t M, int64_t ld
 bool use_dfs(const qts_ensemble* ens, bool fp64) {
   return ens->pair_traversal == QTS_PAIRS_DFS ||
          (ens->pair_traversal == QTS_PAIRS_AUTO && ens->dfs_faster[fp64 ? 1 : 0]);
+}
+
+// Whether a third-order call takes the depth-first form (its pass keeps a
+// row's ratios in registers: rows of at most kDfsTriplesMaxRow features).
+bool use_dfs3(const qts_ensemble* ens, bool fp64) {
+  if (!ens->dfs.built || !dfs_triples_supported(ens->dfs)) return false;
+  return ens->pair_traversal == QTS_PAIRS_DFS ||
+         (ens->pair_traversal == QTS_PAIRS_AUTO && ens->dfs3_faster[fp64 ? 1 : 0]);
 }
 
 // The depth-first form takes the samples in batches whose y_v values (8 per
@@ -1056,9 +1067,11 @@ int qts_get_info(const qts_ensemble* ens, qts_info* out) {
     for (int32_t v : h.share) out->n_path_shared += v;
     out->n_value_segments = (int64_t)h.mcompact.segs.size();
     out->n_groups = h.n_groups;
-    out->pairs_dfs = (use_dfs(ens, false) ? 1 : 0) | (use_dfs(ens, true) ? 2 : 0);
+    out->pairs_dfs = (use_dfs(ens, false) ? 1 : 0) | (use_dfs(ens, true) ? 2 : 0) |
+                     (use_dfs3(ens, false) ? 4 : 0) | (use_dfs3(ens, true) ? 8 : 0);
     out->n_dfs_nodes = ens->dfs.n_nodes;
     out->n_dfs_updates = ens->dfs.n_updates;
+    out->n_dfs_updates3 = ens->dfs.n_updates3;
   });
 }
 
@@ -1191,6 +1204,28 @@ int qts_shap_interactions3(const qts_ensemble* ens, const float* X, int64_t M, i
     const bool fp64 = precision == QTS_FP64;
     const double* leaf = leaf_values ? leaf_values : ens->dev.leaf_val;
     const int64_t MK = M * ens->host.n_groups;
+    if (use_dfs3(ens, fp64)) {
+      // Algorithm 1 at order 3: per batch the tree walk writes y_v, then the
+      // third-order pass adds its updates.  Scratch: (FP32: the FP64
+      // accumulator) | y values of one batch | the walk's leaf values.
+      const size_t ab = fp64 ? 0 : ((sizeof(double) * (size_t)(MK * T3) + 255) & ~(size_t)255);
+      const size_t yb = dfs_y_bytes(ens, M, fp64);
+      const size_t lb = 2 * (size_t)std::max<int64_t>(1, ens->dfs.n_nodes) *
+                        (fp64 ? sizeof(double) : sizeof(float));
+      Scratch sc(ab + yb + lb, s);
+      double* acc = fp64 ? static_cast<double*>(out) : (double*)sc.p;
+      void* Y = (char*)sc.p + ab;
+      void* lvals = (char*)Y + yb;
+      launch_fill_zero(acc, MK * T3, s);
+      const int32_t mb = dfs_batch(ens, M, fp64);
+      for (int64_t s0 = 0; s0 < M; s0 += mb) {
+        const int32_t n = (int32_t)std::min<int64_t>(mb, M - s0);
+        launch_dfs_walk(ens->host, ens->dfs, ens->dev, fp64, leaf, X, s0, n, ldx, Y, lvals, s);
+        launch_dfs_triples(ens->host, ens->dfs, ens->dev, fp64, X, s0, n, ldx, Y, acc, 128, s);
+      }
+      if (!fp64) launch_narrow_f64_f32(acc, MK * T3, static_cast<float*>(out), s);
+      return;
+    }
     auto run = [&](double* acc) {
       launch_fill_zero(acc, MK * T3, s);
       for (const PairClass& pc : ens->pair_classes)
@@ -1505,6 +1540,42 @@ int qts_autotune(qts_ensemble* ens, int64_t M_hint, qts_precision precision, voi
           tune_cache_put(key, choice, 0);
         }
         ens->dfs_faster[pi] = choice == 1;
+      }
+      // the same choice for the third-order call, on fewer samples where its
+      // accumulator (F(F-1)(F-2)/6 per sample) needs it
+      if (ens->pair_traversal == QTS_PAIRS_AUTO && ens->dfs.built &&
+          dfs_triples_supported(ens->dfs) && F >= 3) {
+        const std::string key = tune_key(device, "traversal3", fp64, pol, h, 0, 0,
+                                         ens->dfs.n_nodes, m_class);
+        int choice = -1, unused = 0;
+        if (!tune_cache_get(key, &choice, &unused)) {
+          const int64_t T3 = F * (F - 1) * (F - 2) / 6;
+          const int32_t m3 = (int32_t)std::max<int64_t>(
+              1, std::min<int64_t>({Mp, (int64_t)dfs_batch(ens, Mp, fp64),
+                                    ((int64_t)512 << 20) / (8 * K * T3)}));
+          Scratch a3(sizeof(double) * (size_t)(m3 * K * T3), s);
+          launch_fill_zero((double*)a3.p, m3 * K * T3, s);
+          Scratch y((size_t)m3 * (size_t)ens->dfs.n_rows * kNodes *
+                        (fp64 ? sizeof(double) : sizeof(float)) + 256, s);
+          Scratch lv(2 * (size_t)std::max<int64_t>(1, ens->dfs.n_nodes) *
+                         (fp64 ? sizeof(double) : sizeof(float)), s);
+          float t_paths = 1e30f;
+          try {
+            t_paths = time_ms(1, [&] {
+              for (const PairClass& pc : ens->pair_classes)
+                launch_triples(h, d, pc, fp64, X, m3, F, d.leaf_val, (double*)a3.p, s);
+            });
+          } catch (const Error&) {
+            // the path form's kernels do not fit this feature count
+          }
+          const float t_dfs = time_ms(1, [&] {
+            launch_dfs_walk(h, ens->dfs, d, fp64, d.leaf_val, X, 0, m3, F, y.p, lv.p, s);
+            launch_dfs_triples(h, ens->dfs, d, fp64, X, 0, m3, F, y.p, (double*)a3.p, 128, s);
+          });
+          choice = t_dfs < t_paths ? 1 : 0;
+          tune_cache_put(key, choice, 0);
+        }
+        ens->dfs3_faster[pi] = choice == 1;
       }
     }
     check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");

@@ -122,17 +122,19 @@ class Walker {
     out_.coef.insert(out_.coef.end(), coef, coef + kDfsCoef);
     out_.max_level = std::max(out_.max_level, level);
 
-    // the pair-pass row: every feature split above the node except f
+    // the pair-pass row: every feature split above the node except f, in
+    // ascending feature order
     Row row;
     row.group = group_;
     row.node = rec;
     row.f = f;
     std::vector<int32_t> seen;
-    for (const Edge& e : path_) {
-      if (e.f == f || std::find(seen.begin(), seen.end(), e.f) != seen.end()) continue;
-      seen.push_back(e.f);
-      const Collapsed c = collapse(e.f);
-      row.feat.push_back(e.f | (c.mok ? kMissingOkBit : 0));
+    for (const Edge& e : path_)
+      if (e.f != f && std::find(seen.begin(), seen.end(), e.f) == seen.end()) seen.push_back(e.f);
+    std::sort(seen.begin(), seen.end());
+    for (const int32_t g : seen) {
+      const Collapsed c = collapse(g);
+      row.feat.push_back(g | (c.mok ? kMissingOkBit : 0));
       row.lo.push_back(c.lo);
       row.hi.push_back(c.hi);
       row.b.push_back(c.b);
@@ -257,8 +259,11 @@ DfsTable build_dfs_table(const qts_tree_arrays& t, const HostTable& h) {
     if (ri < 0) continue;
     const Row& r = rows[(size_t)ri];
     out.row_f[pos] = r.f;
-    out.row_d[pos] = (int32_t)r.feat.size();
-    out.n_updates += (int64_t)r.feat.size();
+    const int64_t rd = (int64_t)r.feat.size();
+    out.row_d[pos] = (int32_t)rd;
+    out.n_updates += rd;
+    out.n_updates3 += rd * (rd - 1) / 2;
+    out.max_row_d = std::max(out.max_row_d, (int32_t)rd);
     out.nodes[(size_t)r.node].row = (int32_t)pos;
     const size_t tt = pos / 64, lane = pos % 64;
     for (size_t k = 0; k < r.feat.size(); ++k) {

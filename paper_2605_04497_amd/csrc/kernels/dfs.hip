@@ -21,6 +21,9 @@
 // SII_fj += c_j sum_m y_v(m) / F_j(t_m): one update per (node, feature).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "../qts_device.h"
 
 namespace qts {
@@ -337,6 +340,152 @@ dfs_pairs_kernel(const int32_t* __restrict__ row_f, const int32_t* __restrict__ 
   }
 }
 
+// Lane values from within a group of 8 lanes (DPP): quad_perm swaps with lane
+// ^ 1 and ^ 2, and row_half_mirror (lane i <-> 7 - i of each 8).
+template <int CTRL>
+__device__ __forceinline__ float dpp8(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp8(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF,
+                                                            false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL,
+                                                            0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+// Sum over each group of 8 consecutive lanes (all active), in every lane.
+template <typename T>
+__device__ __forceinline__ T sum8(T v) {
+  v += dpp8<0xB1>(v);
+  v += dpp8<0x4E>(v);
+  v += dpp8<0x141>(v);
+  return v;
+}
+
+__host__ __device__ __forceinline__ int64_t tet3(int64_t z) { return z * (z - 1) * (z - 2) / 6; }
+
+// fn(integral_constant<int, 0>), ..., fn(integral_constant<int, N - 1>): an
+// unrolled loop whose index is a compile-time constant (register arrays
+// indexed by it stay in registers, whatever the unroller's limits).
+template <typename Fn, int... I>
+__device__ __forceinline__ void unroll_seq(Fn&& fn, std::integer_sequence<int, I...>) {
+  (fn(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename Fn>
+__device__ __forceinline__ void unroll(Fn&& fn) {
+  unroll_seq(fn, std::make_integer_sequence<int, N>{});
+}
+
+// The depth-first form at order 3 (Theorem 1 with |S| = 3).  Along a
+// root-to-leaf path the product of three features' ratios r = c / F changes
+// only where one of the three is split, by that feature's change times the
+// other two ratios at the node; so, as at order 2 (Eq. 11), the index is a sum
+// over internal nodes v on feature f, with the walk's y_v, of
+//   SII_{f j k} += sum_m y_v(t_m) r_j^v(t_m) r_k^v(t_m)
+// for every pair {j, k} of the other features split above v.  Lane = (row of
+// 8, node m of 8); a lane keeps the ratios of its row's features at its node
+// in registers (a row's features are sorted, so j < k means f_j < f_k); per
+// pair the 8 node lanes' terms are summed across lanes and one lane adds the
+// sum into the sample's packed tensor range in LDS (FP64): triples whose
+// largest feature lies in [r0, r1), at tet3(c) + c2(b) + a for a < b < c.
+template <typename T, int CAP>
+__global__ void __launch_bounds__(512)
+dfs_triples_kernel(const int32_t* __restrict__ row_f, const int32_t* __restrict__ row_d,
+                   const int32_t* __restrict__ tile_base, const int32_t* __restrict__ tile_d,
+                   const int32_t* __restrict__ feat, const float* __restrict__ lo,
+                   const float* __restrict__ hi, const T* __restrict__ bb,
+                   const T* __restrict__ cbb, int32_t t0, int32_t t1, int32_t chunk,
+                   const T* __restrict__ Y, int32_t n_rows, const float* __restrict__ X,
+                   int64_t s0, int32_t mb, int64_t ldx, int32_t F, int32_t r0, int32_t r1,
+                   int32_t ng, int32_t grp, double* __restrict__ acc, NodeConsts<T> nc) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t nt = tet3(F);
+  const int64_t base0 = tet3(r0);
+  const int64_t ntr = tet3(r1) - base0;
+  double* ts = reinterpret_cast<double*>(smem);       // [ntr]
+  float* xrow = reinterpret_cast<float*>(ts + ntr);  // [F]
+  const int sl = (int)(blockIdx.x % (unsigned)mb);
+  const int ch = (int)(blockIdx.x / (unsigned)mb);
+  const int64_t s = s0 + sl;
+  for (int i = threadIdx.x; i < F; i += blockDim.x) xrow[i] = X[s * ldx + i];
+  for (int64_t e = threadIdx.x; e < ntr; e += blockDim.x) ts[e] = 0.0;
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int q = lane >> 3, m = lane & 7;
+  T tm = nc.t[0];
+#pragma unroll
+  for (int k = 1; k < kNodes; ++k) tm = m == k ? nc.t[k] : tm;
+  const int tb0 = t0 + ch * chunk;
+  const int tb1 = min(t1, tb0 + chunk);
+  for (int tile = tb0 + wave; tile < tb1; tile += nw) {
+    const int eb = __builtin_amdgcn_readfirstlane(tile_base[tile]);
+    const int td = __builtin_amdgcn_readfirstlane(tile_d[tile]);
+    for (int g = 0; g < 8; ++g) {
+      const int ri = g * 8 + q;  // row within the tile
+      const int row = tile * 64 + ri;
+      const int f = row_f[row];
+      const int d = f >= 0 ? row_d[row] : 0;
+      const T y = f >= 0 ? Y[((int64_t)sl * n_rows + row) * kNodes + m] : T(0);
+      T r[CAP];
+      int fe[CAP];
+#pragma unroll
+      for (int k = 0; k < CAP; ++k) {
+        r[k] = T(0);
+        fe[k] = 0;
+        if (k < d) {
+          const int e = eb + 64 * k + ri;
+          const int fm = feat[e];
+          const T b = bb[e];
+          const bool o = follows(xrow[fm & kFeatureMask], lo[e], hi[e],
+                                 (fm & kMissingOkBit) != 0);
+          const T c = o ? cbb[e] : -b;
+          fe[k] = fm & kFeatureMask;
+          // a factor that vanishes identically zeroes every leaf below (y = 0)
+          if (!(b == T(0) && c == T(0))) r[k] = c * rcpD(fmaD(tm, c, b));
+        }
+      }
+      // indices relative to the range start fit 32 bits (the range is in LDS)
+      const int P_f = f * (f - 1) / 2;
+      unroll<CAP>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        if (k == 0 || k >= td) return;
+        const int fk = fe[k];
+        const int zc = max(f, fk);  // the largest feature of every triple (f, f_j, f_k), j < k
+        const bool in = k < d && zc >= r0 && zc < r1;
+        // no row of the wave has triples of this slot in the range
+        if (__ballot(in) == 0) return;
+        const int Tc = (int)(tet3(zc) - base0);
+        const int P_k = fk * (fk - 1) / 2;
+        const T yk = y * r[k];
+        unroll<k>([&](auto jc) {
+          constexpr int j = decltype(jc)::value;
+          const T p = sum8(yk * r[j]);
+          if (in && m == 0 && p != T(0)) {
+            const int fj = fe[j];
+            // (a, b, c) = (f_j, f_k, f), (f_j, f, f_k) or (f, f_j, f_k)
+            const int idx = f > fk ? Tc + P_k + fj
+                                   : (f > fj ? Tc + P_f + fj : Tc + fj * (fj - 1) / 2 + f);
+            __hip_atomic_fetch_add(&ts[idx], (double)p, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+        });
+      });
+    }
+  }
+  __syncthreads();
+  const int64_t orow = s * ng + grp;
+  for (int64_t e = threadIdx.x; e < ntr; e += blockDim.x) {
+    const double v = ts[e];
+    if (v != 0.0) unsafeAtomicAdd(&acc[orow * nt + base0 + e], v);
+  }
+}
+
 namespace {
 
 int64_t tri_h(int64_t k) { return k * (k - 1) / 2; }
@@ -409,7 +558,68 @@ void pairs_t(const HostTable& h, const DeviceDfs& d, const NodeConsts<T>& nc, co
   }
 }
 
+template <typename T, int CAP>
+void triples3_t(const HostTable& h, const DeviceDfs& d, const NodeConsts<T>& nc, const float* X,
+                int64_t s0, int32_t mb, int64_t ldx, const T* Y, double* acc,
+                int32_t tiles_per_chunk, hipStream_t s) {
+  const int F = h.F;
+  const void* fn = (const void*)dfs_triples_kernel<T, CAP>;
+  const size_t limit = raise_lds_limit(fn);
+  const size_t fixed = (size_t)F * sizeof(float) + 16;
+  if (fixed >= limit) fail(QTS_E_UNSUPPORTED, "n_features too large for the third-order kernel");
+  const int64_t cap = (int64_t)((limit - fixed) / sizeof(double));
+  const T* b = std::is_same<T, float>::value ? (const T*)d.b32 : (const T*)d.b64;
+  const T* cb = std::is_same<T, float>::value ? (const T*)d.cb32 : (const T*)d.cb64;
+  for (int g = 0; g < h.n_groups; ++g) {
+    const int t0 = d.group_tile[g], t1 = d.group_tile[g + 1];
+    if (t1 <= t0) continue;
+    const int chunk = std::max(1, tiles_per_chunk);
+    const int64_t grid = (int64_t)mb * ((t1 - t0 + chunk - 1) / chunk);
+    if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "depth-first third-order grid too large");
+    // ranges of the largest feature z (z holds z(z-1)/2 triples)
+    int r0 = 0;
+    while (r0 < F) {
+      int r1 = r0 + 1;
+      if (tet3(r1) - tet3(r0) > cap)
+        fail(QTS_E_UNSUPPORTED, "n_features too large for the third-order kernel");
+      while (r1 < F && tet3(r1 + 1) - tet3(r0) <= cap) ++r1;
+      const size_t lds = (((size_t)(tet3(r1) - tet3(r0)) * sizeof(double) + 15) & ~(size_t)15) +
+                         (size_t)F * sizeof(float);
+      hipLaunchKernelGGL((dfs_triples_kernel<T, CAP>), dim3((unsigned)grid), dim3(512), lds, s,
+                         d.row_f, d.row_d, d.tile_base, d.tile_d, d.feat, d.lo, d.hi, b, cb, t0,
+                         t1, chunk, Y, d.n_rows, X, s0, mb, ldx, F, r0, r1, h.n_groups, g, acc,
+                         nc);
+      check_hip(hipGetLastError(), "dfs_triples_kernel launch");
+      r0 = r1;
+    }
+  }
+}
+
 }  // namespace
+
+bool dfs_triples_supported(const DeviceDfs& d) { return d.max_row_d <= kDfsTriplesMaxRow; }
+
+void launch_dfs_triples(const HostTable& h, const DeviceDfs& d, const DeviceTable& dt, bool fp64,
+                        const float* X, int64_t s0, int32_t mb, int64_t ldx, const void* Y,
+                        double* acc, int32_t tiles_per_chunk, hipStream_t s) {
+  if (!dfs_triples_supported(d))
+    fail(QTS_E_UNSUPPORTED, "internal: rows too long for the depth-first third-order pass");
+  if (fp64) {
+    if (d.max_row_d <= 16)
+      triples3_t<double, 16>(h, d, dt.n64, X, s0, mb, ldx, (const double*)Y, acc,
+                             tiles_per_chunk, s);
+    else
+      triples3_t<double, 32>(h, d, dt.n64, X, s0, mb, ldx, (const double*)Y, acc,
+                             tiles_per_chunk, s);
+  } else {
+    if (d.max_row_d <= 16)
+      triples3_t<float, 16>(h, d, dt.n32, X, s0, mb, ldx, (const float*)Y, acc, tiles_per_chunk,
+                            s);
+    else
+      triples3_t<float, 32>(h, d, dt.n32, X, s0, mb, ldx, (const float*)Y, acc, tiles_per_chunk,
+                            s);
+  }
+}
 
 size_t dfs_walk_lds_bytes(int F, int max_level, bool fp64) {
   return dfs_walk_lds(F, max_level + 1, 1, fp64 ? sizeof(double) : sizeof(float));

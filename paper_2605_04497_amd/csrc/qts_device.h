@@ -89,8 +89,13 @@ struct DeviceDfs {
   double* cb64 = nullptr;
   std::vector<int32_t> group_tile;  // host copy: tiles of each output group
   int64_t n_updates = 0;            // pair updates per sample
+  int64_t n_updates3 = 0;           // third-order updates per sample
+  int32_t max_row_d = 0;            // most features split above one node (other than its own)
   int64_t n_nodes = 0;              // internal nodes
 };
+// The depth-first third-order pass keeps a row's ratios in registers: rows of
+// at most this many features.
+constexpr int32_t kDfsTriplesMaxRow = 32;
 
 // The arrays one first-order (or adjoint) launch walks.
 struct PathArrays {
@@ -309,6 +314,13 @@ size_t dfs_walk_lds_bytes(int F, int max_level, bool fp64);
 void launch_dfs_walk(const HostTable& h, const DeviceDfs& d, const DeviceTable& dt, bool fp64,
                      const double* leaf_val, const float* X, int64_t s0, int32_t mb,
                      int64_t ldx, void* Y, void* lvals, hipStream_t s);
+// Third order (packed tensor acc[M][n_groups][F(F-1)(F-2)/6], FP64, zeroed by
+// the caller) from the walk's y_v of samples [s0, s0 + mb); needs
+// dfs_triples_supported(d).
+bool dfs_triples_supported(const DeviceDfs& d);
+void launch_dfs_triples(const HostTable& h, const DeviceDfs& d, const DeviceTable& dt, bool fp64,
+                        const float* X, int64_t s0, int32_t mb, int64_t ldx, const void* Y,
+                        double* acc, int32_t tiles_per_chunk, hipStream_t s);
 void launch_dfs_pairs(const HostTable& h, const DeviceDfs& d, const DeviceTable& dt, bool fp64,
                       const float* X, int64_t s0, int32_t mb, int64_t ldx, const void* Y,
                       double* tri64, double* phi64, int32_t tiles_per_chunk, hipStream_t s);

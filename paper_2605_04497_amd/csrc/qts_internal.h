@@ -215,10 +215,12 @@ struct DfsTable {
   std::vector<int32_t> row_d;    // features split above the node, other than f
   std::vector<int32_t> tile_base, tile_d;
   std::vector<int32_t> group_tile;  // [n_groups + 1]: tiles of each group
-  std::vector<int32_t> feat;     // feature | missing_ok
+  std::vector<int32_t> feat;     // feature | missing_ok; a row's features ascending
   std::vector<float> lo, hi;
   std::vector<double> b, cb;
   int64_t n_updates = 0;         // sum of row_d: pair updates per sample
+  int64_t n_updates3 = 0;        // sum of row_d (row_d - 1) / 2: third-order updates
+  int32_t max_row_d = 0;
 };
 
 DfsTable build_dfs_table(const qts_tree_arrays& t, const HostTable& h);
