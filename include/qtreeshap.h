@@ -58,10 +58,9 @@ enum {
   QTS_E_INVALID_MODEL = -2, /* child out of range, cycle, one-child node, feature >= F,
                                negative or NaN cover, NaN threshold */
   QTS_E_UNSUPPORTED = -3,   /* tree deeper than 128, path with > 64 unique features;
-                               qts_shap_interactions3 also when one feature's
-                               triples do not fit in LDS (F above about 170 in
-                               the path form, about 200 in the depth-first
-                               form) */
+                               qts_shap_interactions3 in the path form also
+                               when one feature's triples do not fit in LDS
+                               (F above about 170) */
   QTS_E_HIP = -4,           /* a HIP runtime error; its text is in qts_last_error() */
   QTS_E_OOM = -5            /* host or device allocation failed */
 };
@@ -246,10 +245,12 @@ int qts_shap_interactions(const qts_ensemble* ens, const float* X, int64_t M, in
  *   SII_{f j k} += sum_m y_v(t_m) r_j^v(t_m) r_k^v(t_m)
  * at each internal node v on feature f, for every pair {j, k} of the other
  * features split above v.  That form holds rows of at most 32 such features
- * (trees of depth up to 33); deeper ensembles keep the path form.
- * Errors: QTS_E_UNSUPPORTED when one feature's triples (k(k-1)/2 of them) do
- * not fit in LDS (F above about 170 in the path form, about 200 in the
- * depth-first form). */
+ * (trees of depth up to 33); deeper ensembles keep the path form.  It adds
+ * into the sample's tensor in LDS, in ranges of the largest feature, or,
+ * where that takes more than four ranges (F above about 80), straight into
+ * the output with FP64 atomics.
+ * Errors: QTS_E_UNSUPPORTED in the path form when one feature's triples
+ * (k(k-1)/2 of them) do not fit in LDS (F above about 170). */
 int qts_shap_interactions3(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
                            const double* leaf_values, void* out, qts_precision precision,
                            void* stream);

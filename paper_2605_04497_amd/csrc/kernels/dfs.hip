@@ -23,6 +23,7 @@
 
 #include <type_traits>
 #include <utility>
+#include <vector>
 
 #include "../qts_device.h"
 
@@ -388,10 +389,10 @@ __device__ __forceinline__ void unroll(Fn&& fn) {
 // for every pair {j, k} of the other features split above v.  Lane = (row of
 // 8, node m of 8); a lane keeps the ratios of its row's features at its node
 // in registers (a row's features are sorted, so j < k means f_j < f_k); per
-// pair the 8 node lanes' terms are summed across lanes and one lane adds the
-// sum into the sample's packed tensor range in LDS (FP64): triples whose
+// pair the 8 node lanes' terms are summed across lanes, and the 8 lanes share
+// the adds into the sample's packed tensor range in LDS (FP64): triples whose
 // largest feature lies in [r0, r1), at tet3(c) + c2(b) + a for a < b < c.
-template <typename T, int CAP>
+template <typename T, int CAP, bool GLOBAL>
 __global__ void __launch_bounds__(512)
 dfs_triples_kernel(const int32_t* __restrict__ row_f, const int32_t* __restrict__ row_d,
                    const int32_t* __restrict__ tile_base, const int32_t* __restrict__ tile_d,
@@ -405,14 +406,16 @@ dfs_triples_kernel(const int32_t* __restrict__ row_f, const int32_t* __restrict_
   const int64_t nt = tet3(F);
   const int64_t base0 = tet3(r0);
   const int64_t ntr = tet3(r1) - base0;
-  double* ts = reinterpret_cast<double*>(smem);       // [ntr]
-  float* xrow = reinterpret_cast<float*>(ts + ntr);  // [F]
+  double* ts = reinterpret_cast<double*>(smem);  // [ntr] (LDS form)
+  float* xrow = GLOBAL ? reinterpret_cast<float*>(smem) : reinterpret_cast<float*>(ts + ntr);
   const int sl = (int)(blockIdx.x % (unsigned)mb);
   const int ch = (int)(blockIdx.x / (unsigned)mb);
   const int64_t s = s0 + sl;
   for (int i = threadIdx.x; i < F; i += blockDim.x) xrow[i] = X[s * ldx + i];
-  for (int64_t e = threadIdx.x; e < ntr; e += blockDim.x) ts[e] = 0.0;
+  if (!GLOBAL)
+    for (int64_t e = threadIdx.x; e < ntr; e += blockDim.x) ts[e] = 0.0;
   __syncthreads();
+  double* gacc = acc + (s * ng + grp) * nt + base0;
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -452,7 +455,7 @@ dfs_triples_kernel(const int32_t* __restrict__ row_f, const int32_t* __restrict_
       }
       // indices relative to the range start fit 32 bits (the range is in LDS)
       const int P_f = f * (f - 1) / 2;
-      unroll<CAP>([&](auto kc) {
+      unroll<CAP>([&](auto kc) __attribute__((always_inline)) {
         constexpr int k = decltype(kc)::value;
         if (k == 0 || k >= td) return;
         const int fk = fe[k];
@@ -463,26 +466,50 @@ dfs_triples_kernel(const int32_t* __restrict__ row_f, const int32_t* __restrict_
         const int Tc = (int)(tet3(zc) - base0);
         const int P_k = fk * (fk - 1) / 2;
         const T yk = y * r[k];
-        unroll<k>([&](auto jc) {
+        // the slot's cross-lane sums first (independent chains), then its
+        // updates under one branch
+        T pk[k > 0 ? k : 1];
+        unroll<k>([&](auto jc) __attribute__((always_inline)) {
           constexpr int j = decltype(jc)::value;
-          const T p = sum8(yk * r[j]);
-          if (in && m == 0 && p != T(0)) {
-            const int fj = fe[j];
+          pk[j] = sum8(yk * r[j]);
+        });
+        // every node lane of a row holds all of them: lane m adds the pairs
+        // j = 8 i + m
+        unroll<(k + 7) / 8>([&](auto ic) __attribute__((always_inline)) {
+          constexpr int i = decltype(ic)::value;
+          T v = pk[8 * i];
+          int fj = fe[8 * i];
+          unroll<7>([&](auto mc) __attribute__((always_inline)) {
+            constexpr int mm = decltype(mc)::value + 1;
+            if constexpr (8 * i + mm < k) {
+              // opaque register copies: a chain of selects between array
+              // elements would otherwise fold into one indexed load, which
+              // takes the arrays out of registers
+              T a = pk[8 * i + mm];
+              int fa = fe[8 * i + mm];
+              __asm__ volatile("" : "+v"(a), "+v"(fa));
+              v = m == mm ? a : v;
+              fj = m == mm ? fa : fj;
+            }
+          });
+          if (in && 8 * i + m < k && v != T(0)) {
             // (a, b, c) = (f_j, f_k, f), (f_j, f, f_k) or (f, f_j, f_k)
             const int idx = f > fk ? Tc + P_k + fj
                                    : (f > fj ? Tc + P_f + fj : Tc + fj * (fj - 1) / 2 + f);
-            __hip_atomic_fetch_add(&ts[idx], (double)p, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (GLOBAL) unsafeAtomicAdd(&gacc[idx], (double)v);
+            else
+              __hip_atomic_fetch_add(&ts[idx], (double)v, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
           }
         });
       });
     }
   }
+  if (GLOBAL) return;
   __syncthreads();
-  const int64_t orow = s * ng + grp;
   for (int64_t e = threadIdx.x; e < ntr; e += blockDim.x) {
     const double v = ts[e];
-    if (v != 0.0) unsafeAtomicAdd(&acc[orow * nt + base0 + e], v);
+    if (v != 0.0) unsafeAtomicAdd(&gacc[e], v);
   }
 }
 
@@ -558,40 +585,63 @@ void pairs_t(const HostTable& h, const DeviceDfs& d, const NodeConsts<T>& nc, co
   }
 }
 
+// The third-order pass adds into the sample's tensor range in LDS and
+// flushes it, one launch per range of the largest feature; where that would
+// take more than kDfs3MaxRanges ranges (every range walks all rows again), it
+// adds straight into the output with FP64 atomics instead.
+constexpr int kDfs3MaxRanges = 4;
+
+template <typename T, int CAP, bool G>
+void triples3_launch(const HostTable& h, const DeviceDfs& d, const NodeConsts<T>& nc,
+                     const float* X, int64_t s0, int32_t mb, int64_t ldx, const T* Y,
+                     double* acc, int32_t chunk, int g, int r0, int r1, hipStream_t s) {
+  const int F = h.F;
+  const int t0 = d.group_tile[g], t1 = d.group_tile[g + 1];
+  const int64_t grid = (int64_t)mb * ((t1 - t0 + chunk - 1) / chunk);
+  if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "depth-first third-order grid too large");
+  const T* b = std::is_same<T, float>::value ? (const T*)d.b32 : (const T*)d.b64;
+  const T* cb = std::is_same<T, float>::value ? (const T*)d.cb32 : (const T*)d.cb64;
+  const size_t lds = G ? (size_t)F * sizeof(float) + 16
+                       : (((size_t)(tet3(r1) - tet3(r0)) * sizeof(double) + 15) & ~(size_t)15) +
+                             (size_t)F * sizeof(float);
+  hipLaunchKernelGGL((dfs_triples_kernel<T, CAP, G>), dim3((unsigned)grid), dim3(512), lds, s,
+                     d.row_f, d.row_d, d.tile_base, d.tile_d, d.feat, d.lo, d.hi, b, cb, t0, t1,
+                     chunk, Y, d.n_rows, X, s0, mb, ldx, F, r0, r1, h.n_groups, g, acc, nc);
+  check_hip(hipGetLastError(), "dfs_triples_kernel launch");
+}
+
 template <typename T, int CAP>
 void triples3_t(const HostTable& h, const DeviceDfs& d, const NodeConsts<T>& nc, const float* X,
                 int64_t s0, int32_t mb, int64_t ldx, const T* Y, double* acc,
                 int32_t tiles_per_chunk, hipStream_t s) {
   const int F = h.F;
-  const void* fn = (const void*)dfs_triples_kernel<T, CAP>;
-  const size_t limit = raise_lds_limit(fn);
+  const size_t limit = raise_lds_limit((const void*)dfs_triples_kernel<T, CAP, false>);
+  raise_lds_limit((const void*)dfs_triples_kernel<T, CAP, true>);
   const size_t fixed = (size_t)F * sizeof(float) + 16;
   if (fixed >= limit) fail(QTS_E_UNSUPPORTED, "n_features too large for the third-order kernel");
   const int64_t cap = (int64_t)((limit - fixed) / sizeof(double));
-  const T* b = std::is_same<T, float>::value ? (const T*)d.b32 : (const T*)d.b64;
-  const T* cb = std::is_same<T, float>::value ? (const T*)d.cb32 : (const T*)d.cb64;
-  for (int g = 0; g < h.n_groups; ++g) {
-    const int t0 = d.group_tile[g], t1 = d.group_tile[g + 1];
-    if (t1 <= t0) continue;
-    const int chunk = std::max(1, tiles_per_chunk);
-    const int64_t grid = (int64_t)mb * ((t1 - t0 + chunk - 1) / chunk);
-    if (grid > 0x7fffffff) fail(QTS_E_UNSUPPORTED, "depth-first third-order grid too large");
-    // ranges of the largest feature z (z holds z(z-1)/2 triples)
-    int r0 = 0;
-    while (r0 < F) {
-      int r1 = r0 + 1;
-      if (tet3(r1) - tet3(r0) > cap)
-        fail(QTS_E_UNSUPPORTED, "n_features too large for the third-order kernel");
-      while (r1 < F && tet3(r1 + 1) - tet3(r0) <= cap) ++r1;
-      const size_t lds = (((size_t)(tet3(r1) - tet3(r0)) * sizeof(double) + 15) & ~(size_t)15) +
-                         (size_t)F * sizeof(float);
-      hipLaunchKernelGGL((dfs_triples_kernel<T, CAP>), dim3((unsigned)grid), dim3(512), lds, s,
-                         d.row_f, d.row_d, d.tile_base, d.tile_d, d.feat, d.lo, d.hi, b, cb, t0,
-                         t1, chunk, Y, d.n_rows, X, s0, mb, ldx, F, r0, r1, h.n_groups, g, acc,
-                         nc);
-      check_hip(hipGetLastError(), "dfs_triples_kernel launch");
-      r0 = r1;
+  // ranges of the largest feature z (z holds z(z-1)/2 triples)
+  std::vector<std::pair<int, int>> ranges;
+  for (int r0 = 0; r0 < F && (int)ranges.size() <= kDfs3MaxRanges;) {
+    int r1 = r0 + 1;
+    while (r1 < F && tet3(r1 + 1) - tet3(r0) <= cap) ++r1;
+    if (tet3(r1) - tet3(r0) > cap) {
+      ranges.assign(kDfs3MaxRanges + 1, {0, 0});  // one largest feature does not fit
+      break;
     }
+    ranges.emplace_back(r0, r1);
+    r0 = r1;
+  }
+  const int chunk = std::max(1, tiles_per_chunk);
+  for (int g = 0; g < h.n_groups; ++g) {
+    if (d.group_tile[g + 1] <= d.group_tile[g]) continue;
+    if ((int)ranges.size() > kDfs3MaxRanges) {
+      triples3_launch<T, CAP, true>(h, d, nc, X, s0, mb, ldx, Y, acc, chunk, g, 0, F, s);
+      continue;
+    }
+    for (const auto& rr : ranges)
+      triples3_launch<T, CAP, false>(h, d, nc, X, s0, mb, ldx, Y, acc, chunk, g, rr.first,
+                                     rr.second, s);
   }
 }
 
