@@ -319,6 +319,11 @@ def traversal(e, prec):
     return "dfs" if e.refresh_info()["pairs_dfs"] & (1 if prec == "fp32" else 2) else "paths"
 
 
+def traversal3(e, prec):
+    """The form qts_shap_interactions3 takes for a precision."""
+    return "dfs" if e.refresh_info()["pairs_dfs"] & (4 if prec == "fp32" else 8) else "paths"
+
+
 def measure_interactions(args, torch, q, synth, oracle, dev):
     """Pairwise interactions on the full 500-tree, 200-feature ensemble (depths
     3..20), over a slice of its explained samples; FP32 form."""
@@ -488,7 +493,11 @@ def measure_third_order(args, torch, q, synth, oracle, dev):
     T3 = F * (F - 1) * (F - 2) // 6
     triples = sum(math.comb(d, 3) for d in path_unique_counts(ens))
     res = {}
+    trav = {}
     for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+        if not args.no_autotune:
+            e.autotune(M, prec)
+        trav[prec] = traversal3(e, prec)
         out = torch.empty((M, T3), dtype=dt, device=dev)
         res[prec] = time_steps(lambda: e.shap_interactions3(X, prec, out=out), 5, 1, torch)
         del out
@@ -501,7 +510,7 @@ def measure_third_order(args, torch, q, synth, oracle, dev):
     t32 = res["fp32"]["ms_per_step"] * 1e-3
     out = {"workload": "third order on the c4_adjoint ensemble: 200 full depth-6 trees (12,800 "
                        "leaves), 50 features, first 2000 samples; packed [M, 19600] output",
-           "samples": M, "triples_per_sample": triples,
+           "samples": M, "triples_per_sample": triples, "traversal": trav,
            "value": M * e.n_leaves / t32, "unit": "paths/s",
            "ms_per_step": res["fp32"]["ms_per_step"],
            "fp64_ms_per_step": res["fp64"]["ms_per_step"],
@@ -550,9 +559,19 @@ def measure_deep(args, torch, q, synth, oracle, dev):
         T3 = F * (F - 1) * (F - 2) // 6
         M3 = 200
         o3 = torch.empty((M3, T3), dtype=dt, device=dev)
+        tr3 = traversal3(e, prec)
         r3 = time_steps(lambda: e.shap_interactions3(X[:M3], prec, out=o3), 2, 1, torch)
         out["third_order_" + prec] = {"samples": M3, "ms_per_step": r3["ms_per_step"],
-                                      "value": M3 * e.n_leaves / (r3["ms_per_step"] * 1e-3)}
+                                      "value": M3 * e.n_leaves / (r3["ms_per_step"] * 1e-3),
+                                      "traversal": tr3,
+                                      "updates_per_sample": int(e.info["n_dfs_updates3"])
+                                      if tr3 == "dfs" else None}
+        # the other form beside it
+        e.set_pair_traversal("paths" if tr3 == "dfs" else "dfs")
+        r3o = time_steps(lambda: e.shap_interactions3(X[:M3], prec, out=o3), 2, 1, torch)
+        out["third_order_" + prec]["other_form_ms_per_step"] = r3o["ms_per_step"]
+        e.set_pair_traversal("auto")
+        o3 = e.shap_interactions3(X[:M3], prec, out=o3)
         if prec == "fp32":
             rows3 = np.array([0, M3 - 1])
             want3 = oracle.shap_sii3(ens, wl.X[rows3], n=8)
