@@ -175,34 +175,31 @@ dfs_walk_kernel(const DfsNode* __restrict__ nodes, const T* __restrict__ coef,
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // each step's record is read one step ahead, so the LDS latency of
-      // the broadcast overlaps the previous step's arithmetic
-      StagedEvent<T> nx = stage[0];
-      for (int k = 0; k < nwin; ++k) {
-        const StagedEvent<T> w = nx;
-        nx = stage[min(k + 1, nwin - 1)];
+      // one step of the walk: event k of the window, its record w
+      auto step = [&](const StagedEvent<T>& w, int k) __attribute__((always_inline)) {
         const int kind = __builtin_amdgcn_readfirstlane(w.kind);
         const int level = __builtin_amdgcn_readfirstlane(w.level);
-        const int flags = __builtin_amdgcn_readfirstlane(w.flags);
         const uint32_t mine = ((uint32_t)__builtin_amdgcn_readlane((int)bits, k) >> (3 * q)) & 7u;
         const bool ov = (mine & 1u) != 0;
         const T bv = w.coef[0], cbv = w.coef[1];
+        // F_f^v; where f is not split above v the record has b = 1, 1 - b = 0
+        // and no bounds, so F_f^v = 1 exactly
         const T Fv = fmaD(tm, ov ? cbv : -bv, bv);
-        const bool fresh = (flags & kDfsFresh) != 0;
         if (kind == kDfsEnter) {
           const T bl = w.coef[2], cbl = w.coef[3];
           const T Fl = fmaD(tm, (mine & 2u) ? cbl : -bl, bl);
           cst[level * 64 + lane] = C;
-          // C times F_f^u / F_f^v; F_f^v = 1 when f is not split above v, and
-          // a vanishing F_f^v leaves the whole subtree at zero
-          C = fresh ? C * Fl : (Fv == T(0) ? T(0) : C * Fl * rcpD(Fv));
+          // C times F_f^u / F_f^v; a vanishing F_f^v leaves the subtree at zero
+          const T rv = rcpD(Fv);
+          C = Fv == T(0) ? T(0) : C * Fl * rv;
           H = w.lv[0] * C;  // used only when the left child is a leaf
         } else if (kind == kDfsMiddle) {
           const T br = w.coef[4], cbr = w.coef[5];
           const T Fr = fmaD(tm, (mine & 4u) ? cbr : -br, br);
           const T Cv = cst[level * 64 + lane];
           hst[level * 64 + lane] = H;
-          C = fresh ? Cv * Fr : (Fv == T(0) ? T(0) : Cv * Fr * rcpD(Fv));
+          const T rv = rcpD(Fv);
+          C = Fv == T(0) ? T(0) : Cv * Fr * rv;
           H = w.lv[1] * C;
         } else {
           // both subtrees done: H holds H_R, the stack H_L
@@ -213,10 +210,22 @@ dfs_walk_kernel(const DfsNode* __restrict__ nodes, const T* __restrict__ coef,
           const T HL = hst[level * 64 + lane];
           const T nl = ol ? w.coef[6] : (ov ? -bl : T(0));
           const T nr = orr ? w.coef[7] : (ov ? -br : T(0));
-          const T tl = (Fl == T(0) || Fv == T(0)) ? T(0) : HL * nl * rcpD(Fl * Fv);
-          const T tr = (Fr == T(0) || Fv == T(0)) ? T(0) : H * nr * rcpD(Fr * Fv);
+          const T il = rcpD(Fl * Fv), ir = rcpD(Fr * Fv);
+          const T tl = (Fl == T(0) || Fv == T(0)) ? T(0) : HL * nl * il;
+          const T tr = (Fr == T(0) || Fv == T(0)) ? T(0) : H * nr * ir;
           if (valid) Y[((int64_t)sl * n_rows + w.row) * kNodes + m] = wm * (tl + tr);
           H = HL + H;
+        }
+      };
+      // two steps per iteration, each record read one step ahead (the LDS
+      // latency of the broadcast overlaps the previous step's arithmetic)
+      StagedEvent<T> e0 = stage[0];
+      for (int k = 0; k < nwin; k += 2) {
+        const StagedEvent<T> e1 = stage[min(k + 1, nwin - 1)];
+        step(e0, k);
+        if (k + 1 < nwin) {
+          e0 = stage[min(k + 2, nwin - 1)];
+          step(e1, k + 1);
         }
       }
       // the next window overwrites the stage
