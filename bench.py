@@ -73,16 +73,19 @@ EXECUTED_FLOPS_SHA = None
 EXECUTED_FLOPS = {}  # (leg, precision) -> (FP32 flops, FP64 flops) per call
 
 # One call of each leg for the counter runs (`--flop-call LEG:PREC` under
-# rocprofv3 --pmc): workload, samples ("pairs": --pair-samples, else all), the
-# call, and the interactions traversal.
+# rocprofv3 --pmc): workload, samples ("pairs": --pair-samples, an int: the
+# first that many, None: all), the call, the interactions traversal, and the
+# sample count the leg tunes its launch shapes at (None: the call's).
 FLOP_CALLS = {
-    "values": ("c2_values", None, "values", None),
-    "interactions": ("c3_interactions", "pairs", "interactions", "paths"),
-    "interactions_dfs": ("c3_interactions", "pairs", "interactions", "dfs"),
-    "adjoint": ("c4_adjoint", None, "backward", None),
-    "deep_values": ("c5_deep", None, "values", None),
-    "deep_interactions": ("c5_deep", None, "interactions", "paths"),
-    "deep_interactions_dfs": ("c5_deep", None, "interactions", "dfs"),
+    "values": ("c2_values", None, "values", None, None),
+    "interactions": ("c3_interactions", "pairs", "interactions", "paths", None),
+    "interactions_dfs": ("c3_interactions", "pairs", "interactions", "dfs", None),
+    "adjoint": ("c4_adjoint", None, "backward", None, None),
+    "deep_values": ("c5_deep", None, "values", None, None),
+    "deep_interactions": ("c5_deep", None, "interactions", "paths", None),
+    "deep_interactions_dfs": ("c5_deep", None, "interactions", "dfs", None),
+    "deep_third_order": ("c5_deep", 200, "interactions3", "paths", 10000),
+    "deep_third_order_dfs": ("c5_deep", 200, "interactions3", "dfs", 10000),
 }
 # kernels that only the autotuner launches (synthetic inputs), left out of a
 # call's counts
@@ -119,11 +122,14 @@ def flop_call(args, torch, q, synth, dev):
     """One eager call of a leg, launch shapes from the tune cache (a miss would
     add the tuner's launches to the counts, so it is an error)."""
     leg, prec = args.flop_call.split(":")
-    name, samples, call, trav = FLOP_CALLS[leg]
+    name, samples, call, trav, tune_m = FLOP_CALLS[leg]
     over = {"M": args.pair_samples} if samples == "pairs" else {}
     wl = synth.make_workload(name, **over)
     e = q.Ensemble(wl.ensemble, device=dev)
     X = torch.from_numpy(wl.X).to(dev)
+    tune_m = tune_m or X.shape[0]
+    if isinstance(samples, int):
+        X = X[:samples].contiguous()
     M = X.shape[0]
     if trav:
         e.set_pair_traversal(trav)
@@ -133,7 +139,7 @@ def flop_call(args, torch, q, synth, dev):
         G = torch.from_numpy(g.astype(np.float32) if prec == "fp32" else g).to(dev)
     _, m0 = q.tune_cache_stats()
     if not args.no_autotune:
-        e.autotune(M, prec)
+        e.autotune(tune_m, prec)
     _, m1 = q.tune_cache_stats()
     if m1 > m0:
         raise SystemExit("tune cache miss (%d): the counts would include the tuner's launches"
@@ -143,6 +149,8 @@ def flop_call(args, torch, q, synth, dev):
         e.shap_values(X, prec)
     elif call == "interactions":
         e.shap_interactions(X, prec)
+    elif call == "interactions3":
+        e.shap_interactions3(X, prec)
     else:
         e.shap_backward(X, G, prec)
     torch.cuda.synchronize()
@@ -565,7 +573,11 @@ def measure_deep(args, torch, q, synth, oracle, dev):
                                       "value": M3 * e.n_leaves / (r3["ms_per_step"] * 1e-3),
                                       "traversal": tr3,
                                       "updates_per_sample": int(e.info["n_dfs_updates3"])
-                                      if tr3 == "dfs" else None}
+                                      if tr3 == "dfs" else None,
+                                      # the call runs eagerly: its whole step
+                                      "executed": executed(
+                                          "deep_third_order" + ("_dfs" if tr3 == "dfs" else ""),
+                                          prec, r3["ms_per_step"] * 1e-3)}
         # the other form beside it
         e.set_pair_traversal("paths" if tr3 == "dfs" else "dfs")
         r3o = time_steps(lambda: e.shap_interactions3(X[:M3], prec, out=o3), 2, 1, torch)
