@@ -43,7 +43,7 @@ LDS_F64_ATOMIC_RATE = 2.45 * 256 * 2.4e9
 # profiles/values_kernel_c2_values.md.  Valid only for the kernel source they
 # were measured on (its SHA-256 prefix); otherwise traffic is reported as null.
 TRAFFIC = {"kernel_source": "paper_2605_04497_amd/csrc/kernels/values.hip",
-           "sha256_16": "10bd085e780ca08e", "fetch_bytes": 1.2566e+09, "write_bytes": 1.6800e+09,
+           "sha256_16": "8060e3c98009c35d", "fetch_bytes": 1.2489e+09, "write_bytes": 1.6800e+09,
            "shape": [8, 32768]}
 
 
@@ -69,8 +69,28 @@ KERNEL_SOURCES = ("paper_2605_04497_amd/csrc/kernels/values.hip",
                   "paper_2605_04497_amd/csrc/kernels/interactions.hip",
                   "paper_2605_04497_amd/csrc/kernels/dfs.hip",
                   "paper_2605_04497_amd/csrc/kernels/common.hip")
-EXECUTED_FLOPS_SHA = None
-EXECUTED_FLOPS = {}  # (leg, precision) -> (FP32 flops, FP64 flops) per call
+EXECUTED_FLOPS_SHA = "e496afd4e357f086"
+# (leg, precision) -> (FP32 flops, FP64 flops) per call
+EXECUTED_FLOPS = {
+    ("values", "fp32"): (3.4361e+12, 2.3578e+06),
+    ("values", "fp64"): (9.0416e+07, 4.3635e+12),
+    ("interactions", "fp32"): (2.0299e+12, 3.7532e+09),
+    ("interactions", "fp64"): (9.3225e+07, 3.0175e+12),
+    ("interactions_dfs", "fp32"): (8.7750e+11, 1.3826e+08),
+    ("interactions_dfs", "fp64"): (3.8014e+08, 2.0795e+12),
+    ("adjoint", "fp32"): (4.1164e+10, 1.7949e+09),
+    ("adjoint", "fp64"): (1.2013e+07, 5.8223e+10),
+    ("deep_values", "fp32"): (4.5617e+11, 6.7738e+05),
+    ("deep_values", "fp64"): (4.7254e+07, 5.2107e+11),
+    ("deep_interactions", "fp32"): (2.9664e+12, 3.7794e+08),
+    ("deep_interactions", "fp64"): (1.6640e+08, 3.8921e+12),
+    ("deep_interactions_dfs", "fp32"): (5.6340e+11, 2.0386e+08),
+    ("deep_interactions_dfs", "fp64"): (2.5984e+08, 1.3728e+12),
+    ("deep_third_order", "fp32"): (8.2126e+11, 2.2150e+07),
+    ("deep_third_order", "fp64"): (1.4848e+08, 9.4479e+11),
+    ("deep_third_order_dfs", "fp32"): (1.8750e+11, 3.3869e+05),
+    ("deep_third_order_dfs", "fp64"): (7.5008e+06, 2.3076e+11),
+}
 
 # One call of each leg for the counter runs (`--flop-call LEG:PREC` under
 # rocprofv3 --pmc): workload, samples ("pairs": --pair-samples, an int: the
