@@ -335,6 +335,15 @@ int qts_set_sibling_merge(qts_ensemble* ens, int32_t enable);
  * third-order calls are not affected.  Changing it drops the cached graphs. */
 int qts_set_deterministic(qts_ensemble* ens, int32_t enable);
 
+/* Allocation-failure injection, for testing the error paths of callers and of
+ * the library.  after >= 0: the next `after` device allocations the library
+ * makes (on any ensemble and thread: table uploads, call scratch, graph
+ * scratch) succeed and every later one fails as if the device were out of
+ * memory, so the call that needed it returns QTS_E_OOM; after < 0: off (the
+ * default).  A failed call releases what it allocated, and the ensemble stays
+ * usable; a failed qts_load_ensemble returns no ensemble. */
+int qts_debug_fail_allocations(int64_t after);
+
 /* Node count of every call.
  *   QTS_NODES_FIXED8 (default): the 8-node Gauss-Legendre rule for every path
  *     (section 5).

@@ -84,6 +84,7 @@ SIGNATURES = {
     "qts_set_sibling_merge": (ctypes.c_int, [P, ctypes.c_int32]),
     "qts_set_node_policy": (ctypes.c_int, [P, ctypes.c_int32]),
     "qts_set_deterministic": (ctypes.c_int, [P, ctypes.c_int32]),
+    "qts_debug_fail_allocations": (ctypes.c_int, [ctypes.c_int64]),
     "qts_set_pair_traversal": (ctypes.c_int, [P, ctypes.c_int32]),
     "qts_set_tune_cache": (ctypes.c_int, [ctypes.c_char_p]),
     "qts_tune_cache_stats": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64),

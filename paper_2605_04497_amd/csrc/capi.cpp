@@ -1,6 +1,8 @@
 // C-ABI entry points (declared in include/qtreeshap.h).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -129,11 +131,30 @@ int guarded(Fn&& fn) {
   }
 }
 
+// Allocation-failure injection (qts_debug_fail_allocations): how many more
+// device allocations may succeed, or -1 (no injection).
+std::atomic<int64_t> g_alloc_budget{-1};
+
+// Every device allocation of the library goes through here.
+hipError_t device_alloc(void** p, size_t bytes, hipStream_t s, bool async) {
+  int64_t b = g_alloc_budget.load();
+  while (b >= 0) {
+    if (b == 0) return hipErrorOutOfMemory;
+    if (g_alloc_budget.compare_exchange_weak(b, b - 1)) break;
+  }
+  return async ? hipMallocAsync(p, bytes, s) : hipMalloc(p, bytes);
+}
+
 template <class T>
 T* upload(const std::vector<T>& v, hipStream_t s) {
   if (v.empty()) return nullptr;
   T* p = nullptr;
-  check_hip(hipMalloc(reinterpret_cast<void**>(&p), v.size() * sizeof(T)), "hipMalloc");
+  const hipError_t e = device_alloc(reinterpret_cast<void**>(&p), v.size() * sizeof(T), s, false);
+  if (e != hipSuccess) {
+    // earlier uploads may still read host vectors that the unwinding frees
+    (void)hipStreamSynchronize(s);
+    check_hip(e, "hipMalloc");
+  }
   check_hip(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s),
             "hipMemcpyAsync");
   return p;
@@ -343,7 +364,7 @@ struct Scratch {
   void* p = nullptr;
   hipStream_t s = nullptr;
   Scratch(size_t bytes, hipStream_t st) : s(st) {
-    check_hip(hipMallocAsync(&p, bytes, s), "hipMallocAsync");
+    check_hip(device_alloc(&p, bytes, s, true), "hipMallocAsync");
   }
   ~Scratch() {
     if (p) (void)hipFreeAsync(p, s);
@@ -834,7 +855,7 @@ void run_graph(qts_ensemble* ens, const GraphKey& key, size_t scratch_bytes, int
   if (!hit) {
     GraphEntry ne;
     ne.key = key;
-    if (scratch_bytes) check_hip(hipMalloc(&ne.scratch, scratch_bytes), "hipMalloc");
+    if (scratch_bytes) check_hip(device_alloc(&ne.scratch, scratch_bytes, nullptr, false), "hipMalloc");
     hipGraph_t graph = nullptr;
     try {
       check_hip(hipEventCreateWithFlags(&ne.done, hipEventDisableTiming), "hipEventCreate");
@@ -1328,6 +1349,10 @@ int qts_set_pair_traversal(qts_ensemble* ens, int32_t traversal) {
     if (ens->pair_traversal != traversal) clear_graphs(ens->graphs);
     ens->pair_traversal = traversal;
   });
+}
+
+int qts_debug_fail_allocations(int64_t after) {
+  return guarded([&] { g_alloc_budget.store(after < 0 ? -1 : after); });
 }
 
 int qts_set_deterministic(qts_ensemble* ens, int32_t enable) {
