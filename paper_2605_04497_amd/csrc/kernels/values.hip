@@ -25,10 +25,11 @@
 // The leaf value is folded into slot 0 (Slot0: F_0 scaled by val, built per
 // call in FP64), so a row needs no multiply by val; a merged sibling pair is
 // the same form with a combined slot-0 factor.
-// Rows of at most 8 features reuse the factors of the slots they share with
-// the previous row (values_rows_shared, adjoint_rows_shared).  Longer rows
-// (values_paths) run in batches of eight slots: slots past the end of a row
-// get c = 0 and b = 1, a factor of exactly 1, so whole batches run without
+// Rows of at most 8 features reuse the factors and prefix products of the
+// slots they share with the previous row (values_rows_shared,
+// adjoint_rows_shared).  Longer rows (values_rows_long, values_paths) run in
+// batches of eight slots: slots past the end of a row get c = 0 and b = 1, a
+// factor of exactly 1, so whole batches run without
 // branches; the prefix products are kept only at batch checkpoints and
 // rebuilt batch by batch in the backward sweep, which bounds the registers;
 // NH < NN splits the nodes over several passes (the node sum is additive).
@@ -301,10 +302,12 @@ __device__ __forceinline__ void values_paths(
 // rows.  The products are taken over the slots in the order 1, 2, ..., 7, 0,
 // so the prefix products and the factors F_j(m) of slots 1..s depend only on
 // those slots; when slots 1..s of a row equal the previous row's (share[p] =
-// s, from the host), their c_j and F_j(m) are still in registers and only
-// their suffix products and dot products are formed again.  Slot 0 (the
-// row's own factor, from Slot0) and slots past s are evaluated as usual;
-// inert padding slots (b = 1, c = 0) give a factor of exactly 1.
+// s, from the host), their c_j, F_j(m) and prefix products are still in
+// registers and only their suffix products and dot products are formed
+// again.  Slot 0 (the row's own factor, from Slot0) and slots past s are
+// evaluated as usual, each with the prefix product through it in the same
+// step, so the shared count picks one entry into a single straight run of
+// code; inert padding slots (b = 1, c = 0) give a factor of exactly 1.
 template <typename T, int NH, bool NANS>
 __device__ __forceinline__ void values_rows_shared(
     const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
@@ -318,6 +321,12 @@ __device__ __forceinline__ void values_rows_shared(
   const int p_last = min(pe, p_first + run);
   T cf[8];       // c_j of the current row
   T G[8][NH];    // F_j(m) of the current row
+  // prefix products in the order 1..7, 0: P[q] = w prod over the first q
+  // slots of that order (slot q + 1 at position q); P[1..s] depend only on
+  // shared slots and are kept from the previous row
+  T P[7][NH];
+#pragma unroll
+  for (int m = 0; m < NH; ++m) P[0][m] = nc.w[m];
   for (int p = p_first; p < p_last; ++p) {
     const int d = ldu(&hdr[p].d);
     if (d == 0) continue;
@@ -376,17 +385,13 @@ __device__ __forceinline__ void values_rows_shared(
 #pragma unroll
           for (int m = 0; m < NH; ++m) G[k][m] = fmaT(tv[m], c, b);
         }
+        // the prefix through this slot (every later slot is evaluated too)
+        if (k >= 1 && k <= 6) {
+#pragma unroll
+          for (int m = 0; m < NH; ++m) P[k][m] = P[k - 1][m] * G[k][m];
+        }
       }
     }
-    // prefix products in the order 1..7, 0: P[q] = w prod over the first q
-    // slots of that order (slot q + 1 at position q)
-    T P[7][NH];
-#pragma unroll
-    for (int m = 0; m < NH; ++m) P[0][m] = nc.w[m];
-#pragma unroll
-    for (int q = 1; q < 7; ++q)
-#pragma unroll
-      for (int m = 0; m < NH; ++m) P[q][m] = P[q - 1][m] * G[q][m];
     // slot 0, last in the order: its leave-one-out product is P[6] F_7
     {
       T dot = P[6][0] * G[7][0];
@@ -779,6 +784,11 @@ __device__ __forceinline__ void adjoint_rows_shared(
   const int p_last = min(pe, p_first + run);
   T cf[8], gc[8];  // slots 1..7: c_j and g_j c_j of the current row
   T G[8][NH];      // slots 1..7: F_j(m)
+  // prefix products over slots 1..q (P[q], q = 0..6; w folded in); P[1..s]
+  // depend only on shared slots and are kept from the previous row
+  T P[7][NH];
+#pragma unroll
+  for (int m = 0; m < NH; ++m) P[0][m] = nc.w[m];
   for (int p = p_first; p < p_last; ++p) {
     const int d = ldu(&hdr[p].d);
     if (d == 0) continue;
@@ -839,16 +849,13 @@ __device__ __forceinline__ void adjoint_rows_shared(
 #pragma unroll
           for (int m = 0; m < NH; ++m) G[k][m] = fmaT(tv[m], c, bl[k]);
         }
+        // the prefix through this slot (every later slot is evaluated too)
+        if (k <= 6) {
+#pragma unroll
+          for (int m = 0; m < NH; ++m) P[k][m] = P[k - 1][m] * G[k][m];
+        }
       }
     }
-    // prefix products over slots 1..q (P[q], q = 0..6; w folded in)
-    T P[7][NH];
-#pragma unroll
-    for (int m = 0; m < NH; ++m) P[0][m] = nc.w[m];
-#pragma unroll
-    for (int q = 1; q < 7; ++q)
-#pragma unroll
-      for (int m = 0; m < NH; ++m) P[q][m] = P[q - 1][m] * G[q][m];
     // sum_m w_m Q_0(m)
     T q0 = P[6][0] * G[7][0];
 #pragma unroll
