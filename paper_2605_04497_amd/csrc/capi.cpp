@@ -239,6 +239,51 @@ void upload_paths(const std::vector<PathHdr>& hdr_in, const std::vector<int32_t>
   check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
+// The short-row records (ShortRow) of a table's capacity-8 buckets, in the
+// order Bucket::srow_begin numbers them; the slots' features as the
+// first-order kernel indexes its tile (the segment-local feature for wide
+// feature spaces).
+template <typename T>
+std::vector<ShortRow<T>> short_rows(const std::vector<PathHdr>& hdr,
+                                    const std::vector<int32_t>& feat, const CompactTable& ct,
+                                    const std::vector<float>& lo, const std::vector<float>& hi,
+                                    const std::vector<double>& b, const std::vector<double>& cb,
+                                    const std::vector<int32_t>& share,
+                                    const std::vector<Bucket>& bks) {
+  const std::vector<int32_t>& tf = ct.segs.empty() ? feat : ct.lfeat;
+  std::vector<ShortRow<T>> out;
+  for (const Bucket& bk : bks) {
+    if (bk.dmax != 8) continue;
+    if ((size_t)bk.srow_begin != out.size()) fail(QTS_E_INVALID_ARG, "internal: short-row order");
+    for (int32_t p = bk.path_begin; p < bk.path_end; ++p) {
+      ShortRow<T> r{};
+      r.d = hdr[(size_t)p].d;
+      r.share = share[(size_t)p];
+      for (int k = 0; k < 8; ++k) {
+        if (k < r.d) {
+          const size_t e = (size_t)hdr[(size_t)p].off + (size_t)k;
+          const int32_t f = tf[e] & kFeatureMask;
+          r.xoff[k] = f * kTileStride * (int32_t)sizeof(float);
+          r.aoff[k] = f * kTileStride * (int32_t)sizeof(double);
+          if (tf[e] & kMissingOkBit) r.mok |= 1 << k;
+          r.lo[k] = lo[e];
+          r.hi[k] = hi[e];
+          r.b[k] = (T)b[e];
+          r.cb[k] = (T)cb[e];
+        } else {
+          r.mok |= 1 << k;
+          r.lo[k] = -INFINITY;
+          r.hi[k] = NAN;
+          r.b[k] = T(1);
+          r.cb[k] = T(0);
+        }
+      }
+      out.push_back(r);
+    }
+  }
+  return out;
+}
+
 void keep_trees(const qts_tree_arrays& t, qts_ensemble::Trees& k) {
   const int64_t n = t.n_trees > 0 ? t.tree_offsets[t.n_trees] : 0;
   k.off.assign(t.tree_offsets, t.tree_offsets + (t.n_trees + 1));
@@ -313,7 +358,8 @@ void free_device(DeviceTable& d) {
                   d.pr_lo,  d.pr_hi,   d.pr_b32,  d.pr_cb32, d.pr_b64,  d.pr_cb64,
                   d.mhdr,   d.mfeat,   d.mlo,     d.mhi,     d.mb32,    d.mcb32,
                   d.mb64,   d.mcb64,   d.side,    d.pr_side, d.share,   d.mshare,
-                  d.lfeat,  d.segs,    d.seg_feat, d.mlfeat, d.msegs,  d.mseg_feat};
+                  d.lfeat,  d.segs,    d.seg_feat, d.mlfeat, d.msegs,  d.mseg_feat,
+                  d.srow32, d.srow64,  d.msrow32, d.msrow64};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   d = DeviceTable{};
@@ -986,6 +1032,21 @@ int qts_load_ensemble_grouped(const qts_tree_arrays* trees, const int32_t* tree_
       d.side = upload(h.side, s);
       d.share = upload(h.share, s);
       d.mshare = upload(h.mshare, s);
+      {
+        const auto r32 = short_rows<float>(h.hdr, h.feat, h.compact, h.lo, h.hi, h.b, h.cb,
+                                           h.share, h.buckets);
+        const auto r64 = short_rows<double>(h.hdr, h.feat, h.compact, h.lo, h.hi, h.b, h.cb,
+                                            h.share, h.buckets);
+        const auto m32 = short_rows<float>(h.mhdr, h.mfeat, h.mcompact, h.mlo, h.mhi, h.mb,
+                                           h.mcb, h.mshare, h.mbuckets);
+        const auto m64 = short_rows<double>(h.mhdr, h.mfeat, h.mcompact, h.mlo, h.mhi, h.mb,
+                                            h.mcb, h.mshare, h.mbuckets);
+        d.srow32 = upload(r32, s);
+        d.srow64 = upload(r64, s);
+        d.msrow32 = upload(m32, s);
+        d.msrow64 = upload(m64, s);
+        check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+      }
       d.leaf_val = upload(h.leaf_value, s);
       {
         PairTable pt = build_pair_table(h);

@@ -413,6 +413,16 @@ HostTable build_host_table(const qts_tree_arrays& t, int32_t F, int32_t n_groups
   h.tree_group = std::move(groups);
   h.share = prefix_share(h.hdr, h.feat, h.lo, h.hi, h.b);
   h.mshare = prefix_share(h.mhdr, h.mfeat, h.mlo, h.mhi, h.mb);
+  // the rows of capacity-8 buckets, numbered in bucket order, index the
+  // short-row records of each table
+  for (std::vector<Bucket>* bks : {&h.buckets, &h.mbuckets}) {
+    int32_t n = 0;
+    for (Bucket& bk : *bks)
+      if (bk.dmax == 8) {
+        bk.srow_begin = n;
+        n += bk.path_end - bk.path_begin;
+      }
+  }
   if (wide_features(F)) {
     h.compact = build_compact(h.hdr, h.feat, h.buckets, F);
     h.mcompact = build_compact(h.mhdr, h.mfeat, h.mbuckets, F);

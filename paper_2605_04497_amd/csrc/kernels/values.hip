@@ -297,6 +297,14 @@ __device__ __forceinline__ void values_paths(
 }
 
 
+// Wide scalar loads of a ShortRow (dword-aligned vectors of 4 and 16 words).
+typedef int32_t row_v4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef int32_t row_v16 __attribute__((ext_vector_type(16), aligned(4)));
+static_assert(offsetof(ShortRow<float>, xoff) == 16 && offsetof(ShortRow<float>, lo) == 80 &&
+                  offsetof(ShortRow<float>, b) == 144 && offsetof(ShortRow<float>, cb) == 176 &&
+                  offsetof(ShortRow<double>, b) == 144 && offsetof(ShortRow<double>, cb) == 208,
+              "ShortRow layout");
+
 // First order over rows of at most 8 features with all NH nodes in one pass,
 // reusing work between consecutive rows.  Each wave walks a contiguous run of
 // rows.  The products are taken over the slots in the order 1, 2, ..., 7, 0,
@@ -310,11 +318,9 @@ __device__ __forceinline__ void values_paths(
 // code; inert padding slots (b = 1, c = 0) give a factor of exactly 1.
 template <typename T, int NH, bool NANS>
 __device__ __forceinline__ void values_rows_shared(
-    const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
-    const float* __restrict__ lo, const float* __restrict__ hi, const T* __restrict__ bb,
-    const T* __restrict__ cbb, const Slot0<T>* __restrict__ z0,
-    const int32_t* __restrict__ share, const float* xs, double* as, int pb, int pe, int wave,
-    int nw, int lane, const T* tv, const NodeConsts<T>& nc) {
+    const ShortRow<T>* __restrict__ rows, int row0, const Slot0<T>* __restrict__ z0,
+    const float* xs, double* as, int pb, int pe, int wave, int nw, int lane, const T* tv,
+    const NodeConsts<T>& nc) {
   constexpr bool kScalarT = NH == 8;
   const int run = (pe - pb + nw - 1) / nw;
   const int p_first = pb + wave * run;
@@ -327,11 +333,33 @@ __device__ __forceinline__ void values_rows_shared(
   T P[7][NH];
 #pragma unroll
   for (int m = 0; m < NH; ++m) P[0][m] = nc.w[m];
+  const char* xl = reinterpret_cast<const char*>(xs + lane);
+  char* al = reinterpret_cast<char*>(as + lane);
   for (int p = p_first; p < p_last; ++p) {
-    const int d = ldu(&hdr[p].d);
-    if (d == 0) continue;
-    const int off = ldu(&hdr[p].off);
-    const int s = p == p_first ? 0 : ldu(share + p);
+    // the record in four wide scalar loads and slot 0, all issued before
+    // any is used.  An empty row (d = 0) is walked too: its slots are inert
+    // and its Slot0 factor is 0, so it adds exact zeros.
+    const int32_t* rw = reinterpret_cast<const int32_t*>(rows + (p - row0));
+    const row_v4 hd = ldu(reinterpret_cast<const row_v4*>(rw));
+    const row_v16 of = ldu(reinterpret_cast<const row_v16*>(rw + 4));
+    const row_v16 bd = ldu(reinterpret_cast<const row_v16*>(rw + 20));
+    T bl[8], cbl[8];
+    if constexpr (sizeof(T) == 4) {
+      const row_v16 bc = ldu(reinterpret_cast<const row_v16*>(rw + 36));
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        bl[k] = __int_as_float(bc[k]);
+        cbl[k] = __int_as_float(bc[8 + k]);
+      }
+    } else {
+      const row_v16 b2 = ldu(reinterpret_cast<const row_v16*>(rw + 36));
+      const row_v16 c2 = ldu(reinterpret_cast<const row_v16*>(rw + 52));
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        bl[k] = __hiloint2double(b2[2 * k + 1], b2[2 * k]);
+        cbl[k] = __hiloint2double(c2[2 * k + 1], c2[2 * k]);
+      }
+    }
     const Slot0<T>* z = z0 + p;
     const T bm = ldu(&z->bm);
     const T cA = ldu(&z->ca);
@@ -339,25 +367,26 @@ __device__ __forceinline__ void values_rows_shared(
     const float loB = ldu(&z->lo_b);
     const float hiB = ldu(&z->hi_b);
     const bool mokB = ldu(&z->mok_b) != 0;
-    int fm[8];
+    const int d = hd[0];
+    const int s = p == p_first ? 0 : hd[1];
+    const int mok = hd[2];
+    int xo[8], ao[8];
     float l[8], u[8], x[8];
-    T bl[8], cbl[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      fm[k] = ldu(feat + off + k);
-      l[k] = ldu(lo + off + k);
-      u[k] = ldu(hi + off + k);
-      bl[k] = ldu(bb + off + k);
-      cbl[k] = ldu(cbb + off + k);
+      xo[k] = of[k];
+      ao[k] = of[8 + k];
+      l[k] = __int_as_float(bd[k]);
+      u[k] = __int_as_float(bd[8 + k]);
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) x[k] = xs[(fm[k] & kFeatureMask) * kTileStride + lane];
+    for (int k = 0; k < 8; ++k) x[k] = *reinterpret_cast<const float*>(xl + xo[k]);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       if (k == 0 || k > s) {
         bool lower;
         if (NANS) {
-          const bool miss = (fm[k] & kMissingOkBit) != 0;
+          const bool miss = ((mok >> k) & 1) != 0;
           lower = miss ? !(x[k] < l[k]) : (x[k] >= l[k]);
         } else {
           lower = x[k] >= l[k];
@@ -397,9 +426,8 @@ __device__ __forceinline__ void values_rows_shared(
       T dot = P[6][0] * G[7][0];
 #pragma unroll
       for (int m = 1; m < NH; ++m) dot = fmaT(P[6][m], G[7][m], dot);
-      __hip_atomic_fetch_add(&as[(fm[0] & kFeatureMask) * kTileStride + lane],
-                             (double)(cf[0] * dot), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_fetch_add(reinterpret_cast<double*>(al + ao[0]), (double)(cf[0] * dot),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     // slots 7..1: suffix products, starting from slot 0's factor
     T S[NH];
@@ -413,8 +441,8 @@ __device__ __forceinline__ void values_rows_shared(
 #pragma unroll
         for (int m = 1; m < NH; ++m) dot = fmaT(P[q][m], S[m], dot);
         const double c = (double)(cf[j] * dot);
-        __hip_atomic_fetch_add(&as[(fm[j] & kFeatureMask) * kTileStride + lane], c,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(reinterpret_cast<double*>(al + ao[j]), c, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
       }
       if (q > 0) {
 #pragma unroll
@@ -641,7 +669,8 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
               int32_t path_begin, int32_t path_end, int32_t chunk, int32_t nsb,
               const Segment* __restrict__ segs, const int32_t* __restrict__ seg_feat,
               int32_t ng, int32_t grp, double* __restrict__ acc, void* __restrict__ direct,
-              int32_t direct_fp64, int32_t plain_add, NodeConsts<T> nc) {
+              int32_t direct_fp64, int32_t plain_add, const ShortRow<T>* __restrict__ srows,
+              NodeConsts<T> nc) {
   extern __shared__ __align__(16) unsigned char smem[];
   float* xs = reinterpret_cast<float*>(smem);
   size_t xs_bytes = ((size_t)tile_f * kTileStride * sizeof(float) + 15) & ~(size_t)15;
@@ -706,11 +735,11 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
     values_rows_long<T, DMAX, NH, STORE_G, false, NN>(hdr, feat, lo, hi, bb, cbb, z0, share, xs,
                                                       as, pb, pe, wave, nw, lane, tv, nc);
   else if (kShared && any_nan)
-    values_rows_shared<T, NH, true>(hdr, feat, lo, hi, bb, cbb, z0, share, xs, as, pb, pe, wave,
-                                    nw, lane, tv, nc);
+    values_rows_shared<T, NH, true>(srows, path_begin, z0, xs, as, pb, pe, wave, nw, lane, tv,
+                                    nc);
   else if (kShared)
-    values_rows_shared<T, NH, false>(hdr, feat, lo, hi, bb, cbb, z0, share, xs, as, pb, pe, wave,
-                                     nw, lane, tv, nc);
+    values_rows_shared<T, NH, false>(srows, path_begin, z0, xs, as, pb, pe, wave, nw, lane, tv,
+                                     nc);
   else if (any_nan)
     values_paths<T, DMAX, NH, STORE_G, true, false, NN>(hdr, feat, lo, hi, bb, cbb, nullptr,
                                                         z0, xs, as, nullptr, nullptr, pb,
@@ -1057,13 +1086,21 @@ void launch_one(const HostTable& h, const DeviceTable& d, const PathArrays& a, c
   else nc = NN == 8 ? d.n64 : d.n64_4;
   if (lds > raise_lds_limit((const void*)values_kernel<T, DMAX, NH, STORE_G, NN>))
     fail(QTS_E_UNSUPPORTED, "internal: the sample tile does not fit in LDS");
+  // short-row records of a capacity-8 bucket, from the bucket's first row
+  const ShortRow<T>* srows = nullptr;
+  if (bk.dmax == 8 && bk.srow_begin >= 0) {
+    if constexpr (std::is_same<T, float>::value) srows = a.srow32;
+    else srows = a.srow64;
+    if (srows == nullptr) fail(QTS_E_INVALID_ARG, "internal: no short-row records");
+    srows += bk.srow_begin;
+  }
   if (!det) {
     hipLaunchKernelGGL((values_kernel<T, DMAX, NH, STORE_G, NN>), dim3((unsigned)grid),
                        dim3(threads), lds, s, a.hdr, rs.feat, a.lo, a.hi, b, cb,
                        (const Slot0<T>*)slot0, a.share, X, M, ldx, F, rs.tile_f, bk.path_begin,
                        bk.path_end, rs.chunk, nsb, rs.segs, a.seg_feat, h.n_groups, bk.group,
                        acc, rs.segs ? nullptr : direct,
-                       (int32_t)(std::is_same<T, double>::value ? 1 : 0), 0, nc);
+                       (int32_t)(std::is_same<T, double>::value ? 1 : 0), 0, srows, nc);
     check_hip(hipGetLastError(), "values_kernel launch");
     return;
   }
@@ -1075,7 +1112,7 @@ void launch_one(const HostTable& h, const DeviceTable& d, const PathArrays& a, c
                        (const Slot0<T>*)slot0, a.share, X, M, ldx, F, rs.tile_f, p0, p1,
                        rs.chunk, nsb, rs.segs ? rs.segs + c : nullptr, a.seg_feat, h.n_groups,
                        bk.group, acc, nullptr, (int32_t)(std::is_same<T, double>::value ? 1 : 0),
-                       1, nc);
+                       1, srows ? srows + (p0 - bk.path_begin) : nullptr, nc);
     check_hip(hipGetLastError(), "values_kernel launch");
   }
 }

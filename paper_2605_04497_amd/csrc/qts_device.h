@@ -14,6 +14,27 @@ struct NodeConsts {
   T w[kNodes];
 };
 
+constexpr int kTileStride = kSamplesPerBlock + 1;  // padded LDS row (bank spread)
+
+// A first-order row of a capacity-8 bucket as the walk over short rows reads
+// it: every field of the row in one record, so a wave fetches the row with a
+// few wide scalar loads from one address, and the LDS byte offsets of the
+// slots' features precomputed (xoff into the FP32 sample tile, aoff into the
+// FP64 accumulator tile; both tiles are [feature][kTileStride]).  Slots past
+// d are inert (offset 0, lo = -inf, hi = NaN, missing_ok, b = 1, 1 - b = 0).
+// Slot 0's factor comes from Slot0 (built per call); its lo/hi here are A's.
+template <typename T>
+struct alignas(16) ShortRow {
+  int32_t d;        // features of the row (0: an empty path)
+  int32_t share;    // slots 1..share equal to the previous row's
+  int32_t mok;      // bit k: a missing value follows slot k's splits
+  int32_t pad;
+  int32_t xoff[8];  // feature * kTileStride * 4
+  int32_t aoff[8];  // feature * kTileStride * 8
+  float lo[8], hi[8];
+  T b[8], cb[8];    // b_j and 1 - b_j (FP64-derived), rounded to T
+};
+
 // Device copy of the path table.  Element arrays are shared by all buckets.
 struct DeviceTable {
   int device = -1;
@@ -49,6 +70,12 @@ struct DeviceTable {
   double* mcb64 = nullptr;
   SidePath* side = nullptr;
   int32_t* mshare = nullptr;
+  // short-row records of the capacity-8 buckets (Bucket::srow_begin), plain
+  // and merged tables
+  ShortRow<float>* srow32 = nullptr;
+  ShortRow<double>* srow64 = nullptr;
+  ShortRow<float>* msrow32 = nullptr;
+  ShortRow<double>* msrow64 = nullptr;
   // feature-compacted segments (wide_features only), plain and merged tables
   int32_t* lfeat = nullptr;
   Segment* segs = nullptr;
@@ -115,17 +142,20 @@ struct PathArrays {
   const int32_t* lfeat;
   const Segment* segs;
   const int32_t* seg_feat;
+  const ShortRow<float>* srow32;  // capacity-8 rows (features as the kernel indexes its tile)
+  const ShortRow<double>* srow64;
 };
 
 inline PathArrays plain_arrays(const DeviceTable& d, const HostTable& h) {
   const bool w = !h.compact.segs.empty();
   return PathArrays{d.hdr, d.feat, d.lo, d.hi, d.b32, d.cb32, d.b64, d.cb64, nullptr, d.share,
-                    w ? &h.compact : nullptr, d.lfeat, d.segs, d.seg_feat};
+                    w ? &h.compact : nullptr, d.lfeat, d.segs, d.seg_feat, d.srow32, d.srow64};
 }
 inline PathArrays merged_arrays(const DeviceTable& d, const HostTable& h) {
   const bool w = !h.mcompact.segs.empty();
   return PathArrays{d.mhdr, d.mfeat, d.mlo, d.mhi, d.mb32, d.mcb32, d.mb64, d.mcb64, d.side,
-                    d.mshare, w ? &h.mcompact : nullptr, d.mlfeat, d.msegs, d.mseg_feat};
+                    d.mshare, w ? &h.mcompact : nullptr, d.mlfeat, d.msegs, d.mseg_feat,
+                    d.msrow32, d.msrow64};
 }
 
 // Slot 0 of a first-order row with its leaf value folded in, built per call
@@ -154,8 +184,6 @@ struct PairShape {
   int max_chunk = 65536;  // most paths per (sample, chunk) work item
   int fill = 2048;        // least work items when there are few samples
 };
-
-constexpr int kTileStride = kSamplesPerBlock + 1;  // padded LDS row (bank spread)
 
 inline size_t values_lds_bytes(int F) {
   size_t xs = (size_t)F * kTileStride * sizeof(float);

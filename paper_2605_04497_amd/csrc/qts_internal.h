@@ -43,6 +43,7 @@ struct Bucket {
   int32_t path_end;
   int64_t elems;       // sum of d over the bucket's paths
   int32_t group = 0;   // output group of the bucket's trees
+  int32_t srow_begin = -1;  // capacity 8: index of its first row in the short-row records
 };
 
 // Sibling record of a merged path.  Two leaves A (left) and B (right) of one

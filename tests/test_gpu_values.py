@@ -284,6 +284,63 @@ def test_shared_prefix_walk(q, oracle_mod, M):
             check(got, want_lv, "fp32", "shared prefix, leaf override " + tag)
 
 
+def _with_single_leaf_trees(ens, every, value):
+    """The ensemble with a single-leaf tree (an empty path) after every
+    `every`-th tree and before the first."""
+    trees = []
+    for t in range(ens.n_trees):
+        if t % every == 0:
+            trees.append(None)
+        trees.append(t)
+    parts = {k: [] for k in ("left", "right", "feature", "threshold", "default_left", "cover",
+                              "value")}
+    offs = [0]
+    for t in trees:
+        if t is None:
+            one = {"left": [-1], "right": [-1], "feature": [0], "threshold": [0.0],
+                   "default_left": [0], "cover": [100.0], "value": [value]}
+            for k in parts:
+                parts[k].append(np.asarray(one[k], dtype=getattr(ens, k).dtype))
+            offs.append(offs[-1] + 1)
+            continue
+        a, b = int(ens.tree_offsets[t]), int(ens.tree_offsets[t + 1])
+        for k in parts:
+            parts[k].append(getattr(ens, k)[a:b])
+        offs.append(offs[-1] + (b - a))
+    cat = {k: np.concatenate(v) for k, v in parts.items()}
+    return synth.Ensemble(np.asarray(offs, np.int64), cat["left"], cat["right"], cat["feature"],
+                          cat["threshold"], cat["default_left"], cat["cover"], cat["value"],
+                          ens.n_features, ens.base_score, dict(ens.meta))
+
+
+@pytest.mark.parametrize("M", [5, 130])
+def test_short_rows_with_empty_paths(q, oracle_mod, M):
+    """Single-leaf trees give rows without features among the rows of at most
+    8 features: the walk over short rows takes them like any row (they add
+    nothing), and the row after one starts its shared prefix afresh; both
+    tables, both node rules, both precisions, NaN inputs."""
+    print("case empty paths M =", M, flush=True)
+    wl = synth.make_workload("c2_values", T=12, M=M, n_train=20000)
+    ens = _with_single_leaf_trees(wl.ensemble, 3, 2.5)
+    X = wl.X.copy()
+    rng = np.random.default_rng(900 + M)
+    X[rng.random(X.shape) < 0.05] = np.nan
+    want = oracle_mod.shap_values(ens, X, n=8)
+    e = q.Ensemble(ens)
+    Xd = torch.from_numpy(X).cuda()
+    for merge in (True, False):
+        e.set_sibling_merge(merge)
+        for policy in ("fixed8", "exact"):
+            e.set_node_policy(policy)
+            for precision in ("fp32", "fp64"):
+                tag = "empty paths merge=%s %s %s" % (merge, policy, precision)
+                got = e.shap_values(Xd, precision).double().cpu().numpy()
+                check(got, want, precision, tag)
+    fx = oracle_mod.predict(ens, X)
+    got = e.shap_values(Xd, "fp64").cpu().numpy()
+    assert np.abs(got.sum(1) + e.expected_value - fx).max() <= 1e-10 * max(1.0, np.abs(fx).max())
+
+
 @pytest.mark.parametrize("M", [1, 77, 700])
 def test_long_row_reuse(q, oracle_mod, M):
     """Rows of more than 8 features (deep grown trees, buckets 16, 32 and 64)
