@@ -43,7 +43,7 @@ LDS_F64_ATOMIC_RATE = 2.45 * 256 * 2.4e9
 # profiles/values_kernel_c2_values.md.  Valid only for the kernel source they
 # were measured on (its SHA-256 prefix); otherwise traffic is reported as null.
 TRAFFIC = {"kernel_source": "paper_2605_04497_amd/csrc/kernels/values.hip",
-           "sha256_16": "8060e3c98009c35d", "fetch_bytes": 1.2489e+09, "write_bytes": 1.6800e+09,
+           "sha256_16": "6e4e5ebaac8fd3e9", "fetch_bytes": 1.3085e+09, "write_bytes": 1.6800e+09,
            "shape": [8, 32768]}
 
 
@@ -69,21 +69,21 @@ KERNEL_SOURCES = ("paper_2605_04497_amd/csrc/kernels/values.hip",
                   "paper_2605_04497_amd/csrc/kernels/interactions.hip",
                   "paper_2605_04497_amd/csrc/kernels/dfs.hip",
                   "paper_2605_04497_amd/csrc/kernels/common.hip")
-EXECUTED_FLOPS_SHA = "e496afd4e357f086"
+EXECUTED_FLOPS_SHA = "4bc5d059b28f3a6d"
 # (leg, precision) -> (FP32 flops, FP64 flops) per call
 EXECUTED_FLOPS = {
-    ("values", "fp32"): (3.4361e+12, 2.3578e+06),
+    ("values", "fp32"): (2.9722e+12, 2.3578e+06),
     ("values", "fp64"): (9.0416e+07, 4.3635e+12),
-    ("interactions", "fp32"): (2.0299e+12, 3.7532e+09),
-    ("interactions", "fp64"): (9.3225e+07, 3.0175e+12),
+    ("interactions", "fp32"): (2.0298e+12, 3.7527e+09),
+    ("interactions", "fp64"): (9.4274e+07, 3.0175e+12),
     ("interactions_dfs", "fp32"): (8.7750e+11, 1.3826e+08),
     ("interactions_dfs", "fp64"): (3.8014e+08, 2.0795e+12),
-    ("adjoint", "fp32"): (4.1164e+10, 1.7949e+09),
+    ("adjoint", "fp32"): (3.8300e+10, 1.7949e+09),
     ("adjoint", "fp64"): (1.2013e+07, 5.8223e+10),
-    ("deep_values", "fp32"): (4.5617e+11, 6.7738e+05),
+    ("deep_values", "fp32"): (4.5601e+11, 6.7738e+05),
     ("deep_values", "fp64"): (4.7254e+07, 5.2107e+11),
-    ("deep_interactions", "fp32"): (2.9664e+12, 3.7794e+08),
-    ("deep_interactions", "fp64"): (1.6640e+08, 3.8921e+12),
+    ("deep_interactions", "fp32"): (2.9683e+12, 3.7794e+08),
+    ("deep_interactions", "fp64"): (1.7664e+08, 3.8937e+12),
     ("deep_interactions_dfs", "fp32"): (5.6340e+11, 2.0386e+08),
     ("deep_interactions_dfs", "fp64"): (2.5984e+08, 1.3728e+12),
     ("deep_third_order", "fp32"): (8.2126e+11, 2.2150e+07),
@@ -210,16 +210,18 @@ def pmc_summary(paths):
         print("executed flops (x64, tuner kernels excluded): fp32 %.4e fp64 %.4e" % tuple(flops))
 
 
-def shared_kernel_flops(rows, elements, shared):
+def shared_kernel_flops(rows, elements, shared, kept):
     """FP32 flops (FMA = 2) per sample of the first-order kernel for rows of at
     most 8 features at 8 nodes: a row of d features whose first s slots after
     slot 0 are reused from the previous row costs
-      16 (8 - s)   factor FMAs of the slots it evaluates (padding included)
-      48           prefix products over slots 1..6
-      16 d         a 15-flop node sum and a scale per feature
-      48           suffix products over slots 7..2
-    = 112 + 16 d + 16 (8 - s); summed over the table: 224 R + 16 E - 16 S."""
-    return 224.0 * rows + 16.0 * elements - 16.0 * shared
+      16 (8 - s)          factor FMAs of the slots it evaluates (padding included)
+      8 (6 - min(s, 6))   prefix products over slots 1..6 not kept from the
+                          previous row
+      16 d                a 15-flop node sum and a scale per feature
+      48                  suffix products over slots 7..2
+    = 224 + 16 d - 16 s - 8 min(s, 6); summed over the table:
+    224 R + 16 E - 16 S - 8 K (K: min(s, 6) summed, qts_info's prefix_kept)."""
+    return 224.0 * rows + 16.0 * elements - 16.0 * shared - 8.0 * kept
 
 
 def pair_flops(d):
@@ -904,7 +906,8 @@ def main():
         plain = {"value": units / (rp["ms_per_step"] * 1e-3), "ms_per_step": rp["ms_per_step"],
                  "kernel_ms": rp["kernel_ms"], "dtype": "f32",
                  "alu_tflops": float(M) * shared_kernel_flops(
-                     float(e.info["n_paths"]), n_el, float(e.info["n_path_shared"]))
+                     float(e.info["n_paths"]), n_el, float(e.info["n_path_shared"]),
+                     float(e.info["n_path_prefix_kept"]))
                  / (rp["kernel_ms"] * 1e-3) / 1e12}
         log("fp32 without sibling merging: %.3f ms/step" % rp["ms_per_step"])
     exact = None
@@ -927,9 +930,11 @@ def main():
     # features: one bucket, the shared-prefix walk); flops above is the
     # per-element count of the method without merging or reuse
     n_shared = float(e.info["n_value_shared"] if not args.no_merge else e.info["n_path_shared"])
+    n_kept = float(e.info["n_value_prefix_kept"] if not args.no_merge
+                   else e.info["n_path_prefix_kept"])
     n_rows = float(e.info["n_value_paths"] if not args.no_merge else e.info["n_paths"])
     assert e.info["max_unique"] <= 8
-    kernel_flops = float(M) * shared_kernel_flops(n_rows, n_vel, n_shared)
+    kernel_flops = float(M) * shared_kernel_flops(n_rows, n_vel, n_shared, n_kept)
     achieved = kernel_flops / (r32["kernel_ms"] * 1e-3) / 1e12
     result = {
         "metric": METRIC,
@@ -976,10 +981,11 @@ def main():
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
                      "flops_per_launch": kernel_flops,
                      "flops_model": "executed FP32 flops per (sample, row) of d features with s "
-                                    "reused slots: 224 + 16 d - 16 s (8 nodes, FMA = 2 flops); "
-                                    "matches SQ_INSTS_VALU_FLOPS_FP32 x 64",
+                                    "reused slots: 224 + 16 d - 16 s - 8 min(s, 6) (8 nodes, "
+                                    "FMA = 2 flops); matches SQ_INSTS_VALU_FLOPS_FP32 x 64",
                      "rows": n_rows, "elements_per_sample": n_vel,
                      "shared_slots_per_sample": n_shared,
+                     "kept_prefix_levels_per_sample": n_kept,
                      "peak_note": "published MI355X FP32 vector peak, which needs packed "
                                   "two-wide FP32 instructions; this build is compiled without "
                                   "them, so its issue ceiling is the non-packed one",

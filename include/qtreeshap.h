@@ -167,6 +167,10 @@ typedef struct {
                                 each internal node, summed */
   int64_t n_dfs_updates3;    /* its third-order updates per sample: pairs of those
                                 features, summed over the internal nodes */
+  int64_t n_value_prefix_kept;  /* first-order rows of at most 8 features: min(shared
+                                   slots, 6) summed, the prefix products the walk over
+                                   them keeps from the previous row */
+  int64_t n_path_prefix_kept;   /* the same for the unmerged table */
 } qts_info;
 
 int qts_get_info(const qts_ensemble* ens, qts_info* out);

@@ -46,7 +46,8 @@ class Info(ctypes.Structure):
                 ("n_path_shared", ctypes.c_int64), ("n_value_segments", ctypes.c_int64),
                 ("n_groups", ctypes.c_int32), ("pairs_dfs", ctypes.c_int32),
                 ("n_dfs_nodes", ctypes.c_int64),
-                ("n_dfs_updates", ctypes.c_int64), ("n_dfs_updates3", ctypes.c_int64)]
+                ("n_dfs_updates", ctypes.c_int64), ("n_dfs_updates3", ctypes.c_int64),
+                ("n_value_prefix_kept", ctypes.c_int64), ("n_path_prefix_kept", ctypes.c_int64)]
 
 
 # exported symbol -> (restype, argtypes)

@@ -1147,6 +1147,16 @@ int qts_get_info(const qts_ensemble* ens, qts_info* out) {
     for (int32_t v : h.mshare) out->n_value_shared += v;
     out->n_path_shared = 0;
     for (int32_t v : h.share) out->n_path_shared += v;
+    auto prefix_kept = [](const std::vector<Bucket>& bks, const std::vector<int32_t>& share) {
+      int64_t n = 0;
+      for (const Bucket& bk : bks)
+        if (bk.dmax == 8)
+          for (int32_t p = bk.path_begin; p < bk.path_end; ++p)
+            n += std::min<int32_t>(share[(size_t)p], 6);
+      return n;
+    };
+    out->n_value_prefix_kept = prefix_kept(h.mbuckets, h.mshare);
+    out->n_path_prefix_kept = prefix_kept(h.buckets, h.share);
     out->n_value_segments = (int64_t)h.mcompact.segs.size();
     out->n_groups = h.n_groups;
     out->pairs_dfs = (use_dfs(ens, false) ? 1 : 0) | (use_dfs(ens, true) ? 2 : 0) |
