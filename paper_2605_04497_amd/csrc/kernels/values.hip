@@ -35,6 +35,8 @@
 // NH < NN splits the nodes over several passes (the node sum is additive).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "../qts_device.h"
 
 namespace qts {
@@ -305,6 +307,54 @@ static_assert(offsetof(ShortRow<float>, xoff) == 16 && offsetof(ShortRow<float>,
                   offsetof(ShortRow<double>, b) == 144 && offsetof(ShortRow<double>, cb) == 208,
               "ShortRow layout");
 
+// A short row in registers (SGPRs: every field is wave-uniform).
+template <typename T>
+struct ShortRowRegs {
+  int d, share, mok;
+  int xo[8], ao[8];
+  float l[8], u[8];
+  T bl[8], cbl[8];
+};
+
+// The record of row p in four wide scalar loads, all issued before any is
+// used.
+template <typename T>
+__device__ __forceinline__ ShortRowRegs<T> load_short_row(const ShortRow<T>* rows, int row0,
+                                                          int p) {
+  ShortRowRegs<T> r;
+  const int32_t* rw = reinterpret_cast<const int32_t*>(rows + (p - row0));
+  const row_v4 hd = ldu(reinterpret_cast<const row_v4*>(rw));
+  const row_v16 of = ldu(reinterpret_cast<const row_v16*>(rw + 4));
+  const row_v16 bd = ldu(reinterpret_cast<const row_v16*>(rw + 20));
+  if constexpr (sizeof(T) == 4) {
+    const row_v16 bc = ldu(reinterpret_cast<const row_v16*>(rw + 36));
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      r.bl[k] = __int_as_float(bc[k]);
+      r.cbl[k] = __int_as_float(bc[8 + k]);
+    }
+  } else {
+    const row_v16 b2 = ldu(reinterpret_cast<const row_v16*>(rw + 36));
+    const row_v16 c2 = ldu(reinterpret_cast<const row_v16*>(rw + 52));
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      r.bl[k] = __hiloint2double(b2[2 * k + 1], b2[2 * k]);
+      r.cbl[k] = __hiloint2double(c2[2 * k + 1], c2[2 * k]);
+    }
+  }
+  r.d = hd[0];
+  r.share = hd[1];
+  r.mok = hd[2];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    r.xo[k] = of[k];
+    r.ao[k] = of[8 + k];
+    r.l[k] = __int_as_float(bd[k]);
+    r.u[k] = __int_as_float(bd[8 + k]);
+  }
+  return r;
+}
+
 // First order over rows of at most 8 features with all NH nodes in one pass,
 // reusing work between consecutive rows.  Each wave walks a contiguous run of
 // rows.  The products are taken over the slots in the order 1, 2, ..., 7, 0,
@@ -336,30 +386,10 @@ __device__ __forceinline__ void values_rows_shared(
   const char* xl = reinterpret_cast<const char*>(xs + lane);
   char* al = reinterpret_cast<char*>(as + lane);
   for (int p = p_first; p < p_last; ++p) {
-    // the record in four wide scalar loads and slot 0, all issued before
-    // any is used.  An empty row (d = 0) is walked too: its slots are inert
-    // and its Slot0 factor is 0, so it adds exact zeros.
-    const int32_t* rw = reinterpret_cast<const int32_t*>(rows + (p - row0));
-    const row_v4 hd = ldu(reinterpret_cast<const row_v4*>(rw));
-    const row_v16 of = ldu(reinterpret_cast<const row_v16*>(rw + 4));
-    const row_v16 bd = ldu(reinterpret_cast<const row_v16*>(rw + 20));
-    T bl[8], cbl[8];
-    if constexpr (sizeof(T) == 4) {
-      const row_v16 bc = ldu(reinterpret_cast<const row_v16*>(rw + 36));
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        bl[k] = __int_as_float(bc[k]);
-        cbl[k] = __int_as_float(bc[8 + k]);
-      }
-    } else {
-      const row_v16 b2 = ldu(reinterpret_cast<const row_v16*>(rw + 36));
-      const row_v16 c2 = ldu(reinterpret_cast<const row_v16*>(rw + 52));
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        bl[k] = __hiloint2double(b2[2 * k + 1], b2[2 * k]);
-        cbl[k] = __hiloint2double(c2[2 * k + 1], c2[2 * k]);
-      }
-    }
+    // the record and slot 0, all loads issued before any is used.  An empty
+    // row (d = 0) is walked too: its slots are inert and its Slot0 factor
+    // is 0, so it adds exact zeros.
+    const ShortRowRegs<T> r = load_short_row(rows, row0, p);
     const Slot0<T>* z = z0 + p;
     const T bm = ldu(&z->bm);
     const T cA = ldu(&z->ca);
@@ -367,18 +397,16 @@ __device__ __forceinline__ void values_rows_shared(
     const float loB = ldu(&z->lo_b);
     const float hiB = ldu(&z->hi_b);
     const bool mokB = ldu(&z->mok_b) != 0;
-    const int d = hd[0];
-    const int s = p == p_first ? 0 : hd[1];
-    const int mok = hd[2];
-    int xo[8], ao[8];
-    float l[8], u[8], x[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      xo[k] = of[k];
-      ao[k] = of[8 + k];
-      l[k] = __int_as_float(bd[k]);
-      u[k] = __int_as_float(bd[8 + k]);
-    }
+    const int d = r.d;
+    const int s = p == p_first ? 0 : r.share;
+    const int mok = r.mok;
+    const int* xo = r.xo;
+    const int* ao = r.ao;
+    const float* l = r.l;
+    const float* u = r.u;
+    const T* bl = r.bl;
+    const T* cbl = r.cbl;
+    float x[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) x[k] = *reinterpret_cast<const float*>(xl + xo[k]);
 #pragma unroll
@@ -392,22 +420,23 @@ __device__ __forceinline__ void values_rows_shared(
           lower = x[k] >= l[k];
         }
         const bool in = lower & !(x[k] >= u[k]);
-        T c, b;
+        // b in a VGPR once: the select's -b and the factor FMAs read it
+        // there (a VALU op reads one SGPR, and the select's mask is one)
+        const T b = k == 0 ? bm : bl[k];
+        const T bv = kScalarT ? to_vgpr(b) : b;
+        T c;
         if (k == 0) {
           bool lowerB;
           if (NANS) lowerB = mokB ? !(x[0] < loB) : (x[0] >= loB);
           else lowerB = x[0] >= loB;
           const bool inB = lowerB & !(x[0] >= hiB);
-          c = in ? cA : (inB ? cB : -bm);
-          b = bm;
+          c = in ? cA : (inB ? cB : -bv);
         } else {
-          c = in ? cbl[k] : -bl[k];
-          b = bl[k];
+          c = in ? cbl[k] : -bv;
         }
         cf[k] = c;
         if (kScalarT) {
-          // t from SGPRs, b copied to a VGPR (one SGPR operand per VALU op)
-          const T bv = to_vgpr(b);
+          // t from SGPRs
 #pragma unroll
           for (int m = 0; m < NH; ++m) G[k][m] = fmaT(nc.t[m], c, bv);
         } else {
@@ -429,26 +458,32 @@ __device__ __forceinline__ void values_rows_shared(
       __hip_atomic_fetch_add(reinterpret_cast<double*>(al + ao[0]), (double)(cf[0] * dot),
                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
-    // slots 7..1: suffix products, starting from slot 0's factor
+    // slots 7..1: suffix products, starting from slot 0's factor.  A full
+    // row (d = 8, most rows of depth-8 trees) takes a sweep without the
+    // per-slot test of j < d.
     T S[NH];
 #pragma unroll
     for (int m = 0; m < NH; ++m) S[m] = G[0][m];
+    auto sweep = [&](auto full) __attribute__((always_inline)) {
 #pragma unroll
-    for (int q = 6; q >= 0; --q) {
-      const int j = q + 1;
-      if (j < d) {
-        T dot = P[q][0] * S[0];
+      for (int q = 6; q >= 0; --q) {
+        const int j = q + 1;
+        if (decltype(full)::value || j < d) {
+          T dot = P[q][0] * S[0];
 #pragma unroll
-        for (int m = 1; m < NH; ++m) dot = fmaT(P[q][m], S[m], dot);
-        const double c = (double)(cf[j] * dot);
-        __hip_atomic_fetch_add(reinterpret_cast<double*>(al + ao[j]), c, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP);
+          for (int m = 1; m < NH; ++m) dot = fmaT(P[q][m], S[m], dot);
+          const double c = (double)(cf[j] * dot);
+          __hip_atomic_fetch_add(reinterpret_cast<double*>(al + ao[j]), c, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        if (q > 0) {
+#pragma unroll
+          for (int m = 0; m < NH; ++m) S[m] *= G[j][m];
+        }
       }
-      if (q > 0) {
-#pragma unroll
-        for (int m = 0; m < NH; ++m) S[m] *= G[j][m];
-      }
-    }
+    };
+    if (d == 8) sweep(std::true_type{});
+    else sweep(std::false_type{});
   }
 }
 
@@ -801,10 +836,8 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
 // F_A(m) R(m) is b_A sum_m R(m) + c_A sum_m t_m R(m).
 template <typename T, int NH, bool NANS>
 __device__ __forceinline__ void adjoint_rows_shared(
-    const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
-    const float* __restrict__ lo, const float* __restrict__ hi, const T* __restrict__ bb,
-    const T* __restrict__ cbb, const SidePath* __restrict__ side,
-    const int32_t* __restrict__ share, const float* xs, const T* gs,
+    const ShortRow<T>* __restrict__ rows, int row0, const PathHdr* __restrict__ hdr,
+    const SidePath* __restrict__ side, const float* xs, const T* gs,
     double* __restrict__ grad_leaf, int pb, int pe, int wave, int nw, int lane, const T* tv,
     const NodeConsts<T>& nc, bool det) {
   constexpr bool kScalarT = NH == 8;
@@ -818,27 +851,29 @@ __device__ __forceinline__ void adjoint_rows_shared(
   T P[7][NH];
 #pragma unroll
   for (int m = 0; m < NH; ++m) P[0][m] = nc.w[m];
+  const char* xl = reinterpret_cast<const char*>(xs + lane);
+  const char* gl = reinterpret_cast<const char*>(gs + lane);
   for (int p = p_first; p < p_last; ++p) {
-    const int d = ldu(&hdr[p].d);
-    if (d == 0) continue;
-    const int off = ldu(&hdr[p].off);
+    // the record and the row's leaf and side record, all loads issued
+    // before any is used.  An empty row (d = 0) is walked too: its slots are
+    // inert, so its leaf's gradient comes out exactly 0.
+    const ShortRowRegs<T> r = load_short_row(rows, row0, p);
     const int leaf = ldu(&hdr[p].leaf);
     const int sidx = side == nullptr ? -1 : ldu(&hdr[p].tree);
     const bool merged = sidx >= 0;
-    const int s = p == p_first ? 0 : ldu(share + p);
-    int fm[8];
-    float l[8], u[8], x[8];
-    T bl[8], cbl[8];
+    const int d = r.d;
+    const int s = p == p_first ? 0 : r.share;
+    // the tile row of slot k's feature: the sample tile is FP32 and the
+    // gradient tile T
+    const int* xo = r.xo;
+    const int* go = sizeof(T) == 4 ? r.xo : r.ao;
+    const float* l = r.l;
+    const float* u = r.u;
+    const T* bl = r.bl;
+    const T* cbl = r.cbl;
+    float x[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      fm[k] = ldu(feat + off + k);
-      l[k] = ldu(lo + off + k);
-      u[k] = ldu(hi + off + k);
-      bl[k] = ldu(bb + off + k);
-      cbl[k] = ldu(cbb + off + k);
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) x[k] = xs[(fm[k] & kFeatureMask) * kTileStride + lane];
+    for (int k = 0; k < 8; ++k) x[k] = *reinterpret_cast<const float*>(xl + xo[k]);
     auto follows = [&](float xv, float lv, float uv, bool miss) -> bool {
       bool lower;
       if (NANS) lower = miss ? !(xv < lv) : (xv >= lv);
@@ -861,17 +896,18 @@ __device__ __forceinline__ void adjoint_rows_shared(
       bB = (T)ldu(&sp->b_b);
       cbB = (T)ldu(&sp->cb_b);
     }
-    const T cA = follows(x[0], l[0], u[0], (fm[0] & kMissingOkBit) != 0) ? cbA : -bA;
+    const T cA = follows(x[0], l[0], u[0], (r.mok & 1) != 0) ? cbA : -bA;
     const T cB = follows(x[0], loB, hiB, mokB) ? cbB : -bB;
-    const T g0 = gs[(fm[0] & kFeatureMask) * kTileStride + lane];
+    const T g0 = *reinterpret_cast<const T*>(gl + go[0]);
 #pragma unroll
     for (int k = 1; k < 8; ++k) {
       if (k > s) {
-        const T c = follows(x[k], l[k], u[k], (fm[k] & kMissingOkBit) != 0) ? cbl[k] : -bl[k];
+        // b in a VGPR once, for the select's -b and the factor FMAs
+        const T bv = kScalarT ? to_vgpr(bl[k]) : bl[k];
+        const T c = follows(x[k], l[k], u[k], ((r.mok >> k) & 1) != 0) ? cbl[k] : -bv;
         cf[k] = c;
-        gc[k] = gs[(fm[k] & kFeatureMask) * kTileStride + lane] * c;
+        gc[k] = *reinterpret_cast<const T*>(gl + go[k]) * c;
         if (kScalarT) {
-          const T bv = to_vgpr(bl[k]);
 #pragma unroll
           for (int m = 0; m < NH; ++m) G[k][m] = fmaT(nc.t[m], c, bv);
         } else {
@@ -938,7 +974,8 @@ adjoint_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat
                int32_t F, int32_t tile_f, int32_t path_begin, int32_t path_end, int32_t chunk,
                int32_t nsb, const Segment* __restrict__ segs,
                const int32_t* __restrict__ seg_feat, int32_t ng, int32_t grp,
-               double* __restrict__ grad_leaf, int64_t part_stride, NodeConsts<T> nc) {
+               double* __restrict__ grad_leaf, int64_t part_stride,
+               const ShortRow<T>* __restrict__ srows, NodeConsts<T> nc) {
   extern __shared__ __align__(16) unsigned char smem[];
   float* xs = reinterpret_cast<float*>(smem);
   size_t xs_bytes = ((size_t)tile_f * kTileStride * sizeof(float) + 15) & ~(size_t)15;
@@ -993,11 +1030,11 @@ adjoint_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat
   double* gl = det ? grad_leaf + (int64_t)sb * part_stride : grad_leaf;
   constexpr bool kShared = DMAX == 8 && NH == NN && (STORE_G || NN == 4);
   if (kShared && any_nan)
-    adjoint_rows_shared<T, NH, true>(hdr, feat, lo, hi, bb, cbb, side, share, xs, gs, gl, pb,
-                                     pe, wave, nw, lane, tv, nc, det);
+    adjoint_rows_shared<T, NH, true>(srows, path_begin, hdr, side, xs, gs, gl, pb, pe, wave, nw,
+                                     lane, tv, nc, det);
   else if (kShared)
-    adjoint_rows_shared<T, NH, false>(hdr, feat, lo, hi, bb, cbb, side, share, xs, gs, gl, pb,
-                                      pe, wave, nw, lane, tv, nc, det);
+    adjoint_rows_shared<T, NH, false>(srows, path_begin, hdr, side, xs, gs, gl, pb, pe, wave, nw,
+                                      lane, tv, nc, det);
   else if (any_nan)
     values_paths<T, DMAX, NH, STORE_G, true, true, NN>(hdr, feat, lo, hi, bb, cbb, side, nullptr,
                                                        xs, nullptr, gs, gl, pb, pe, wave, nw,
@@ -1031,6 +1068,18 @@ bool values_direct(const std::vector<Bucket>& bks, int64_t M, const ValuesShape&
 
 namespace {
 
+
+// The short-row records of a capacity-8 bucket from its first row (null for
+// other buckets).
+template <typename T>
+const ShortRow<T>* short_rows_of(const PathArrays& a, const Bucket& bk) {
+  if (bk.dmax != 8 || bk.srow_begin < 0) return nullptr;
+  const ShortRow<T>* r;
+  if constexpr (std::is_same<T, float>::value) r = a.srow32;
+  else r = a.srow64;
+  if (r == nullptr) fail(QTS_E_INVALID_ARG, "internal: no short-row records");
+  return r + bk.srow_begin;
+}
 
 // How one launch over a bucket splits its rows: chunks of `chunk` rows with
 // the full feature tile, or (wide feature spaces) the bucket's segments with
@@ -1086,14 +1135,7 @@ void launch_one(const HostTable& h, const DeviceTable& d, const PathArrays& a, c
   else nc = NN == 8 ? d.n64 : d.n64_4;
   if (lds > raise_lds_limit((const void*)values_kernel<T, DMAX, NH, STORE_G, NN>))
     fail(QTS_E_UNSUPPORTED, "internal: the sample tile does not fit in LDS");
-  // short-row records of a capacity-8 bucket, from the bucket's first row
-  const ShortRow<T>* srows = nullptr;
-  if (bk.dmax == 8 && bk.srow_begin >= 0) {
-    if constexpr (std::is_same<T, float>::value) srows = a.srow32;
-    else srows = a.srow64;
-    if (srows == nullptr) fail(QTS_E_INVALID_ARG, "internal: no short-row records");
-    srows += bk.srow_begin;
-  }
+  const ShortRow<T>* srows = short_rows_of<T>(a, bk);
   if (!det) {
     hipLaunchKernelGGL((values_kernel<T, DMAX, NH, STORE_G, NN>), dim3((unsigned)grid),
                        dim3(threads), lds, s, a.hdr, rs.feat, a.lo, a.hi, b, cb,
@@ -1141,7 +1183,7 @@ void launch_adj_one(const HostTable& h, const DeviceTable& d, const PathArrays& 
                      dim3(threads), lds, s, a.hdr, rs.feat, a.lo, a.hi, b, cb, a.side, a.share,
                      X, (const T*)G, M, ldx, F, rs.tile_f, bk.path_begin, bk.path_end, rs.chunk,
                      nsb, rs.segs, a.seg_feat, h.n_groups, bk.group, grad_leaf, part_stride,
-                     nc);
+                     short_rows_of<T>(a, bk), nc);
   check_hip(hipGetLastError(), "adjoint_kernel launch");
 }
 

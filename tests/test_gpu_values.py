@@ -339,6 +339,27 @@ def test_short_rows_with_empty_paths(q, oracle_mod, M):
     fx = oracle_mod.predict(ens, X)
     got = e.shap_values(Xd, "fp64").cpu().numpy()
     assert np.abs(got.sum(1) + e.expected_value - fx).max() <= 1e-10 * max(1.0, np.abs(fx).max())
+    # the adjoint walks the same rows: the single leaves' gradients are 0
+    G = rng.normal(size=(M, ens.n_features))
+    single = np.flatnonzero(np.diff(ens.tree_offsets) == 1)
+    for precision, tol in (("fp32", 1e-5), ("fp64", 1e-10)):
+        Gp = G.astype(np.float32).astype(np.float64) if precision == "fp32" else G
+        want = oracle_mod.leaf_grad(ens, X, Gp)
+        Gd = torch.from_numpy(Gp).cuda()
+        if precision == "fp32":
+            Gd = Gd.float()
+        for merge in (True, False):
+            e.set_sibling_merge(merge)
+            for policy in ("fixed8", "exact"):
+                e.set_node_policy(policy)
+                for det in (False, True):
+                    e.set_deterministic(det)
+                    g = e.shap_backward(Xd, Gd, precision).cpu().numpy()
+                    err = np.linalg.norm(g - want) / np.linalg.norm(want)
+                    assert err <= tol, (precision, merge, policy, det, err)
+                    leaf_ids = np.cumsum(ens.leaf_mask()) - 1
+                    assert np.all(g[leaf_ids[ens.tree_offsets[single]]] == 0.0)
+        e.set_deterministic(False)
 
 
 @pytest.mark.parametrize("M", [1, 77, 700])
