@@ -301,6 +301,7 @@ __device__ __forceinline__ void values_paths(
 
 // Wide scalar loads of a ShortRow (dword-aligned vectors of 4 and 16 words).
 typedef int32_t row_v4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef int32_t row_v8 __attribute__((ext_vector_type(8), aligned(4)));
 typedef int32_t row_v16 __attribute__((ext_vector_type(16), aligned(4)));
 static_assert(offsetof(ShortRow<float>, xoff) == 16 && offsetof(ShortRow<float>, lo) == 80 &&
                   offsetof(ShortRow<float>, b) == 144 && offsetof(ShortRow<float>, cb) == 176 &&
@@ -317,14 +318,25 @@ struct ShortRowRegs {
 };
 
 // The record of row p in four wide scalar loads, all issued before any is
-// used.
-template <typename T>
+// used.  AO = false leaves out the accumulator offsets (twice the sample
+// tile's: the caller derives them where it adds, which saves 8 SGPRs).
+template <typename T, bool AO = true>
 __device__ __forceinline__ ShortRowRegs<T> load_short_row(const ShortRow<T>* rows, int row0,
                                                           int p) {
   ShortRowRegs<T> r;
   const int32_t* rw = reinterpret_cast<const int32_t*>(rows + (p - row0));
   const row_v4 hd = ldu(reinterpret_cast<const row_v4*>(rw));
-  const row_v16 of = ldu(reinterpret_cast<const row_v16*>(rw + 4));
+  row_v16 of;
+  if constexpr (AO) {
+    of = ldu(reinterpret_cast<const row_v16*>(rw + 4));
+  } else {
+    const row_v8 o8 = ldu(reinterpret_cast<const row_v8*>(rw + 4));
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      of[k] = o8[k];
+      of[8 + k] = 2 * o8[k];
+    }
+  }
   const row_v16 bd = ldu(reinterpret_cast<const row_v16*>(rw + 20));
   if constexpr (sizeof(T) == 4) {
     const row_v16 bc = ldu(reinterpret_cast<const row_v16*>(rw + 36));
@@ -366,7 +378,7 @@ __device__ __forceinline__ ShortRowRegs<T> load_short_row(const ShortRow<T>* row
 // evaluated as usual, each with the prefix product through it in the same
 // step, so the shared count picks one entry into a single straight run of
 // code; inert padding slots (b = 1, c = 0) give a factor of exactly 1.
-template <typename T, int NH, bool NANS>
+template <typename T, int NH, bool NANS, bool KEEP = true>
 __device__ __forceinline__ void values_rows_shared(
     const ShortRow<T>* __restrict__ rows, int row0, const Slot0<T>* __restrict__ z0,
     const float* xs, double* as, int pb, int pe, int wave, int nw, int lane, const T* tv,
@@ -389,7 +401,8 @@ __device__ __forceinline__ void values_rows_shared(
     // the record and slot 0, all loads issued before any is used.  An empty
     // row (d = 0) is walked too: its slots are inert and its Slot0 factor
     // is 0, so it adds exact zeros.
-    const ShortRowRegs<T> r = load_short_row(rows, row0, p);
+    // the 8-node FP64 walk derives the accumulator offsets (SGPR room)
+    const ShortRowRegs<T> r = load_short_row<T, !(sizeof(T) == 8 && !KEEP)>(rows, row0, p);
     const Slot0<T>* z = z0 + p;
     const T bm = ldu(&z->bm);
     const T cA = ldu(&z->ca);
@@ -398,14 +411,14 @@ __device__ __forceinline__ void values_rows_shared(
     const float hiB = ldu(&z->hi_b);
     const bool mokB = ldu(&z->mok_b) != 0;
     const int d = r.d;
-    const int s = p == p_first ? 0 : r.share;
+    const int s = (KEEP && p != p_first) ? r.share : 0;
     const int mok = r.mok;
-    const int* xo = r.xo;
-    const int* ao = r.ao;
-    const float* l = r.l;
-    const float* u = r.u;
-    const T* bl = r.bl;
-    const T* cbl = r.cbl;
+    const auto& xo = r.xo;
+    const auto& ao = r.ao;
+    const auto& l = r.l;
+    const auto& u = r.u;
+    const auto& bl = r.bl;
+    const auto& cbl = r.cbl;
     float x[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) x[k] = *reinterpret_cast<const float*>(xl + xo[k]);
@@ -763,6 +776,9 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
   // across rows: FP32 within 128 VGPRs (four waves per SIMD); FP64 only with
   // the 4-node rule (the 8-node FP64 instance has no registers to spare)
   constexpr bool kShared = DMAX == 8 && NH == NN && (STORE_G || NN == 4);
+  // the 8-node FP64 instance walks the same records without keeping a row's
+  // factors or prefix products for the next (no registers for them)
+  constexpr bool kShortPlain = DMAX == 8 && NH == NN && !kShared;
   if (DMAX > 8 && any_nan)
     values_rows_long<T, DMAX, NH, STORE_G, true, NN>(hdr, feat, lo, hi, bb, cbb, z0, share, xs,
                                                      as, pb, pe, wave, nw, lane, tv, nc);
@@ -775,6 +791,12 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
   else if (kShared)
     values_rows_shared<T, NH, false>(srows, path_begin, z0, xs, as, pb, pe, wave, nw, lane, tv,
                                      nc);
+  else if (kShortPlain && any_nan)
+    values_rows_shared<T, NH, true, false>(srows, path_begin, z0, xs, as, pb, pe, wave, nw, lane,
+                                           tv, nc);
+  else if (kShortPlain)
+    values_rows_shared<T, NH, false, false>(srows, path_begin, z0, xs, as, pb, pe, wave, nw,
+                                            lane, tv, nc);
   else if (any_nan)
     values_paths<T, DMAX, NH, STORE_G, true, false, NN>(hdr, feat, lo, hi, bb, cbb, nullptr,
                                                         z0, xs, as, nullptr, nullptr, pb,
@@ -865,12 +887,12 @@ __device__ __forceinline__ void adjoint_rows_shared(
     const int s = p == p_first ? 0 : r.share;
     // the tile row of slot k's feature: the sample tile is FP32 and the
     // gradient tile T
-    const int* xo = r.xo;
-    const int* go = sizeof(T) == 4 ? r.xo : r.ao;
-    const float* l = r.l;
-    const float* u = r.u;
-    const T* bl = r.bl;
-    const T* cbl = r.cbl;
+    const auto& xo = r.xo;
+    const auto& go = sizeof(T) == 4 ? r.xo : r.ao;
+    const auto& l = r.l;
+    const auto& u = r.u;
+    const auto& bl = r.bl;
+    const auto& cbl = r.cbl;
     float x[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) x[k] = *reinterpret_cast<const float*>(xl + xo[k]);
