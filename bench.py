@@ -529,7 +529,10 @@ def measure_third_order(args, torch, q, synth, oracle, dev):
             e.autotune(M, prec)
         trav[prec] = traversal3(e, prec)
         out = torch.empty((M, T3), dtype=dt, device=dev)
-        res[prec] = time_steps(lambda: e.shap_interactions3(X, prec, out=out), 5, 1, torch)
+        e.set_graph_replay(not args.eager)
+        res[prec] = time_steps(lambda: e.shap_interactions3(X, prec, out=out), 5, 1, torch,
+                               "interactions3")
+        e.set_graph_replay(False)
         del out
     rows = np.array([0, M - 1])
     want = oracle.shap_sii3(ens, wl.X[rows], n=8)
@@ -542,11 +545,11 @@ def measure_third_order(args, torch, q, synth, oracle, dev):
                        "leaves), 50 features, first 2000 samples; packed [M, 19600] output",
            "samples": M, "triples_per_sample": triples, "traversal": trav,
            "value": M * e.n_leaves / t32, "unit": "paths/s",
-           "ms_per_step": res["fp32"]["ms_per_step"],
+           "ms_per_step": res["fp32"]["ms_per_step"], "kernel_ms": res["fp32"]["kernel_ms"],
            "fp64_ms_per_step": res["fp64"]["ms_per_step"],
            "triple_updates_per_s": M * triples / t32,
            "max_rel_err_fp32": err, "rows_checked": 2,
-           "launch": "eager (one launch per capacity class)"}
+           "launch": "hipGraph replay" if not args.eager else "eager"}
     e.close()
     return out
 
@@ -590,21 +593,26 @@ def measure_deep(args, torch, q, synth, oracle, dev):
         M3 = 200
         o3 = torch.empty((M3, T3), dtype=dt, device=dev)
         tr3 = traversal3(e, prec)
-        r3 = time_steps(lambda: e.shap_interactions3(X[:M3], prec, out=o3), 2, 1, torch)
+        X3 = X[:M3]
+        e.set_graph_replay(not args.eager)
+        r3 = time_steps(lambda: e.shap_interactions3(X3, prec, out=o3), 2, 1, torch,
+                        "interactions3")
         out["third_order_" + prec] = {"samples": M3, "ms_per_step": r3["ms_per_step"],
+                                      "kernel_ms": r3["kernel_ms"],
                                       "value": M3 * e.n_leaves / (r3["ms_per_step"] * 1e-3),
                                       "traversal": tr3,
                                       "updates_per_sample": int(e.info["n_dfs_updates3"])
                                       if tr3 == "dfs" else None,
-                                      # the call runs eagerly: its whole step
                                       "executed": executed(
                                           "deep_third_order" + ("_dfs" if tr3 == "dfs" else ""),
-                                          prec, r3["ms_per_step"] * 1e-3)}
+                                          prec, r3["kernel_ms"] * 1e-3)}
         # the other form beside it
         e.set_pair_traversal("paths" if tr3 == "dfs" else "dfs")
-        r3o = time_steps(lambda: e.shap_interactions3(X[:M3], prec, out=o3), 2, 1, torch)
+        r3o = time_steps(lambda: e.shap_interactions3(X3, prec, out=o3), 2, 1, torch,
+                         "interactions3")
         out["third_order_" + prec]["other_form_ms_per_step"] = r3o["ms_per_step"]
         e.set_pair_traversal("auto")
+        e.set_graph_replay(False)
         o3 = e.shap_interactions3(X[:M3], prec, out=o3)
         if prec == "fp32":
             rows3 = np.array([0, M3 - 1])

@@ -239,8 +239,9 @@ int qts_shap_interactions(const qts_ensemble* ens, const float* X, int64_t M, in
  *        Overwritten.  With F < 3 there is nothing to write (out may be NULL).
  *   leaf_values, X, M, ldx, precision, stream as for qts_shap_values.
  * Accumulation is in FP64 throughout; the FP32 form allocates an FP64
- * accumulator of M * F(F-1)(F-2)/6 doubles on `stream` for the call.  Calls
- * run eagerly (graph replay does not apply).
+ * accumulator of M * F(F-1)(F-2)/6 doubles on `stream` for the call (and the
+ * depth-first form the y values of one sample batch), or, under graph
+ * replay (qts_set_graph_replay), the call's graph owns them.
  * The traversal follows qts_set_pair_traversal: the path form, or Algorithm 1
  * taken to order 3 (section 5): along a path the product of three features'
  * ratios r = (o - b) / F changes only where one of them is split, by that
@@ -392,9 +393,11 @@ int qts_set_node_policy(qts_ensemble* ens, int32_t policy);
 enum { QTS_PAIRS_PATHS = 0, QTS_PAIRS_DFS = 1, QTS_PAIRS_AUTO = 2 };
 int qts_set_pair_traversal(qts_ensemble* ens, int32_t traversal);
 
-/* HIP graph replay.  While enabled, each compute call on this ensemble is
- * captured once (on an internal stream, with its per-bucket or per-class
- * launches as parallel branches) into a graph keyed by (call kind, precision,
+/* HIP graph replay.  While enabled, each compute call on this ensemble
+ * (qts_shap_values, qts_shap_interactions, qts_shap_interactions3,
+ * qts_shap_backward) is captured once (on an internal stream, with its
+ * per-bucket or per-class launches as parallel branches where the call has
+ * them) into a graph keyed by (call kind, precision,
  * X, M, ldx, leaf values or grad_phi, output pointers, stream), and replayed
  * with hipGraphLaunch on the caller's stream on every later call with the same
  * key.  A graph owns its FP64 accumulators, so a replay allocates nothing.
@@ -408,8 +411,9 @@ int qts_set_graph_replay(qts_ensemble* ens, int32_t enable);
 
 /* Measurement aid.  While enabled, each compute call records a HIP event pair
  * on its stream around the launches of its main kernel (kind 0: the values
- * kernel, 1: the interactions kernel, 2: the adjoint kernel), excluding the
- * zero-fill and cast kernels around them.  qts_kernel_timing_read waits for
+ * kernel, 1: the interactions kernel, 2: the adjoint kernel, 3: the
+ * third-order kernels of qts_shap_interactions3, zero-fill and narrowing
+ * included), excluding the zero-fill and cast kernels around the others.  qts_kernel_timing_read waits for
  * the recorded events of one kind, returns their summed duration in
  * milliseconds and the number of calls since the last read, and clears them.
  * With graph replay on, the pair spans the whole replay (zero-fill and cast

@@ -44,7 +44,7 @@ def tune_cache_stats():
     return int(h.value), int(m.value)
 
 
-KERNEL_KINDS = {"values": 0, "interactions": 1, "backward": 2}
+KERNEL_KINDS = {"interactions3": 3, "values": 0, "interactions": 1, "backward": 2}
 
 
 def set_kernel_timing(enable: bool) -> None:

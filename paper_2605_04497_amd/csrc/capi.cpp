@@ -24,7 +24,7 @@ constexpr size_t kMaxGraphs = 16;
 
 // One captured call: its launches depend only on these arguments.
 struct GraphKey {
-  int kind = 0;  // 0 values, 1 interactions, 2 adjoint
+  int kind = 0;  // 0 values, 1 interactions, 2 adjoint, 3 third order
   int fp64 = 0;
   const void* X = nullptr;
   int64_t M = 0, ldx = 0;
@@ -410,7 +410,7 @@ struct Scratch {
   void* p = nullptr;
   hipStream_t s = nullptr;
   Scratch(size_t bytes, hipStream_t st) : s(st) {
-    check_hip(device_alloc(&p, bytes, s, true), "hipMallocAsync");
+    if (bytes) check_hip(device_alloc(&p, bytes, s, true), "hipMallocAsync");
   }
   ~Scratch() {
     if (p) (void)hipFreeAsync(p, s);
@@ -423,7 +423,7 @@ struct Scratch {
 struct Timing {
   std::mutex mu;
   bool on = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[4];
 };
 Timing& timing() {
   static Timing t;
@@ -1279,6 +1279,63 @@ int qts_shap_interactions(const qts_ensemble* ens, const float* X, int64_t M, in
   });
 }
 
+namespace {
+
+// Scratch of one third-order call: the depth-first form's (FP32: the FP64
+// accumulator) | y values of one sample batch | the walk's leaf values; the
+// path form's FP64 accumulator (FP32 only).
+size_t interactions3_scratch_bytes(const qts_ensemble* ens, int64_t M, bool fp64) {
+  const int64_t F = ens->host.F;
+  const int64_t T3 = F * (F - 1) * (F - 2) / 6;
+  const int64_t MK = M * ens->host.n_groups;
+  if (use_dfs3(ens, fp64)) {
+    const size_t ab = fp64 ? 0 : ((sizeof(double) * (size_t)(MK * T3) + 255) & ~(size_t)255);
+    const size_t yb = dfs_y_bytes(ens, M, fp64);
+    const size_t lb = 2 * (size_t)std::max<int64_t>(1, ens->dfs.n_nodes) *
+                      (fp64 ? sizeof(double) : sizeof(float));
+    return ab + yb + lb;
+  }
+  return fp64 ? 0 : sizeof(double) * (size_t)(MK * T3);
+}
+
+// The launches of one third-order call on stream s, with `scratch` of
+// interactions3_scratch_bytes (owned by the caller or by a graph).
+void issue_interactions3(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
+                         const double* leaf, void* out, bool fp64, void* scratch,
+                         hipStream_t s, bool timed) {
+  const int64_t F = ens->host.F;
+  const int64_t T3 = F * (F - 1) * (F - 2) / 6;
+  const int64_t MK = M * ens->host.n_groups;
+  TimedScope ts(3, timed ? s : nullptr, timed);
+  if (use_dfs3(ens, fp64)) {
+    // Algorithm 1 at order 3: per batch the tree walk writes y_v, then the
+    // third-order pass adds its updates.
+    const size_t ab = fp64 ? 0 : ((sizeof(double) * (size_t)(MK * T3) + 255) & ~(size_t)255);
+    const size_t yb = dfs_y_bytes(ens, M, fp64);
+    double* acc = fp64 ? static_cast<double*>(out) : (double*)scratch;
+    void* Y = (char*)scratch + ab;
+    void* lvals = (char*)Y + yb;
+    launch_fill_zero(acc, MK * T3, s);
+    const int32_t mb = dfs_batch(ens, M, fp64);
+    for (int64_t s0 = 0; s0 < M; s0 += mb) {
+      const int32_t n = (int32_t)std::min<int64_t>(mb, M - s0);
+      launch_dfs_walk(ens->host, ens->dfs, ens->dev, fp64, leaf, X, s0, n, ldx, Y, lvals, s);
+      launch_dfs_triples(ens->host, ens->dfs, ens->dev, fp64, X, s0, n, ldx, Y, acc, 128, s);
+    }
+    if (!fp64) launch_narrow_f64_f32(acc, MK * T3, static_cast<float*>(out), s);
+    ts.done();
+    return;
+  }
+  double* acc = fp64 ? static_cast<double*>(out) : (double*)scratch;
+  launch_fill_zero(acc, MK * T3, s);
+  for (const PairClass& pc : ens->pair_classes)
+    launch_triples(ens->host, ens->dev, pc, fp64, X, M, ldx, leaf, acc, s);
+  if (!fp64) launch_narrow_f64_f32(acc, MK * T3, static_cast<float*>(out), s);
+  ts.done();
+}
+
+}  // namespace
+
 int qts_shap_interactions3(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
                            const double* leaf_values, void* out, qts_precision precision,
                            void* stream) {
@@ -1295,41 +1352,17 @@ int qts_shap_interactions3(const qts_ensemble* ens, const float* X, int64_t M, i
     hipStream_t s = (hipStream_t)stream;
     const bool fp64 = precision == QTS_FP64;
     const double* leaf = leaf_values ? leaf_values : ens->dev.leaf_val;
-    const int64_t MK = M * ens->host.n_groups;
-    if (use_dfs3(ens, fp64)) {
-      // Algorithm 1 at order 3: per batch the tree walk writes y_v, then the
-      // third-order pass adds its updates.  Scratch: (FP32: the FP64
-      // accumulator) | y values of one batch | the walk's leaf values.
-      const size_t ab = fp64 ? 0 : ((sizeof(double) * (size_t)(MK * T3) + 255) & ~(size_t)255);
-      const size_t yb = dfs_y_bytes(ens, M, fp64);
-      const size_t lb = 2 * (size_t)std::max<int64_t>(1, ens->dfs.n_nodes) *
-                        (fp64 ? sizeof(double) : sizeof(float));
-      Scratch sc(ab + yb + lb, s);
-      double* acc = fp64 ? static_cast<double*>(out) : (double*)sc.p;
-      void* Y = (char*)sc.p + ab;
-      void* lvals = (char*)Y + yb;
-      launch_fill_zero(acc, MK * T3, s);
-      const int32_t mb = dfs_batch(ens, M, fp64);
-      for (int64_t s0 = 0; s0 < M; s0 += mb) {
-        const int32_t n = (int32_t)std::min<int64_t>(mb, M - s0);
-        launch_dfs_walk(ens->host, ens->dfs, ens->dev, fp64, leaf, X, s0, n, ldx, Y, lvals, s);
-        launch_dfs_triples(ens->host, ens->dfs, ens->dev, fp64, X, s0, n, ldx, Y, acc, 128, s);
-      }
-      if (!fp64) launch_narrow_f64_f32(acc, MK * T3, static_cast<float*>(out), s);
+    const size_t scratch_bytes = interactions3_scratch_bytes(ens, M, fp64);
+    if (ens->graphs.on) {
+      GraphKey key{3, fp64, X, M, ldx, leaf, out, nullptr, s};
+      run_graph(const_cast<qts_ensemble*>(ens), key, scratch_bytes, 3,
+                [&](Lanes& ln, double* scratch) {
+                  issue_interactions3(ens, X, M, ldx, leaf, out, fp64, scratch, ln.main, false);
+                });
       return;
     }
-    auto run = [&](double* acc) {
-      launch_fill_zero(acc, MK * T3, s);
-      for (const PairClass& pc : ens->pair_classes)
-        launch_triples(ens->host, ens->dev, pc, fp64, X, M, ldx, leaf, acc, s);
-    };
-    if (fp64) {
-      run(static_cast<double*>(out));
-      return;
-    }
-    Scratch acc(sizeof(double) * (size_t)(MK * T3), s);
-    run((double*)acc.p);
-    launch_narrow_f64_f32((const double*)acc.p, MK * T3, static_cast<float*>(out), s);
+    Scratch sc(scratch_bytes, s);
+    issue_interactions3(ens, X, M, ldx, leaf, out, fp64, sc.p, s, true);
   });
 }
 
@@ -1737,7 +1770,7 @@ int qts_set_kernel_timing(int32_t enable) {
 
 int qts_kernel_timing_read(int32_t kind, double* total_ms, int64_t* calls) {
   return guarded([&] {
-    if (kind < 0 || kind > 2 || !total_ms || !calls) fail(QTS_E_INVALID_ARG, "bad argument");
+    if (kind < 0 || kind > 3 || !total_ms || !calls) fail(QTS_E_INVALID_ARG, "bad argument");
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     {
       Timing& t = timing();

@@ -139,6 +139,55 @@ def test_graph_replay_interactions_and_backward(q, oracle_mod):
     assert e.refresh_info()["n_graphs"] == 4
 
 
+def test_graph_replay_third_order(q, oracle_mod):
+    """qts_shap_interactions3 under graph replay, in both traversals and
+    precisions: each key is captured once and replayed with other eager GPU
+    work and host synchronisations in between; every replay matches the
+    oracle and the eager call (up to the order of FP64 atomic additions); a
+    leaf-value override is a key of its own."""
+    wl = synth.make_workload("c5_deep", T=3, M=9, n_train=30000)
+    ens = wl.ensemble
+    e = q.Ensemble(ens)
+    X = torch.from_numpy(wl.X).cuda()
+    F = ens.n_features
+    T3 = F * (F - 1) * (F - 2) // 6
+    dense = oracle_mod.shap_sii3(ens, wl.X, n=8)
+    idx = np.array([(i, j, k) for k in range(F) for j in range(k) for i in range(j)])
+    want = dense[:, idx[:, 0], idx[:, 1], idx[:, 2]]
+    lv = np.random.default_rng(12).normal(size=ens.n_leaves())
+    dense_lv = oracle_mod.shap_sii3(ens.with_leaf_values(lv), wl.X, n=8)
+    want_lv = dense_lv[:, idx[:, 0], idx[:, 1], idx[:, 2]]
+    lvd = torch.from_numpy(lv).cuda()
+    for trav in ("paths", "dfs"):
+        e.set_pair_traversal(trav)
+        for precision in ("fp32", "fp64"):
+            dt = torch.float32 if precision == "fp32" else torch.float64
+            eager = e.shap_interactions3(X, precision).cpu().numpy()
+            check(eager.astype(np.float64), want, precision, "eager %s" % trav)
+            out = torch.empty((X.shape[0], T3), dtype=dt, device="cuda")
+            out_lv = torch.empty_like(out)
+            e.set_graph_replay(True)
+            n0 = e.refresh_info()["n_graphs"]
+            for rep in range(3):
+                torch.randn(4096, device="cuda").sum()
+                torch.cuda.synchronize()
+                out.fill_(float("nan"))
+                e.shap_interactions3(X, precision, out=out)
+                e.shap_interactions3(X, precision, leaf_values=lvd, out=out_lv)
+                torch.cuda.synchronize()
+                # the same kernels as the eager call; FP64 atomics may add in
+                # another order, so the two agree up to rounding
+                got = out.cpu().numpy().astype(np.float64)
+                scale = np.abs(eager).max()
+                tol = 1e-6 if precision == "fp32" else 1e-12
+                assert np.abs(got - eager).max() <= tol * scale, (trav, precision, rep)
+                check(got, want, precision, "replay %s %d" % (trav, rep))
+                check(out_lv.double().cpu().numpy(), want_lv, precision,
+                      "replay leaf override %s %d" % (trav, rep))
+            assert e.refresh_info()["n_graphs"] == n0 + 2
+            e.set_graph_replay(False)
+
+
 def test_graph_cache_eviction(q, oracle_mod):
     """More keys than the cache holds: the least recently used graphs are
     dropped and every call still returns the right result."""
