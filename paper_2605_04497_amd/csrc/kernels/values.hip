@@ -705,6 +705,15 @@ __device__ __forceinline__ ItemRows item_rows(const Segment* segs, const int32_t
   return ir;
 }
 
+// Work item of workgroup b of n: the workgroups of one XCD (b mod 8) take
+// one contiguous eighth of the items (the last n mod 8 in their own order).
+__device__ __forceinline__ int xcd_item(int b, int n) {
+  constexpr int kXcds = 8;
+  const int per = n / kXcds;
+  if (b >= per * kXcds) return b;
+  return (b % kXcds) * per + b / kXcds;
+}
+
 // tile_f: the features the LDS layout is sized for (F, or kSegFeatures with
 // segments); F: phi's row length.
 template <typename T, int DMAX, int NH, bool STORE_G, int NN>
@@ -724,7 +733,10 @@ values_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat,
   size_t xs_bytes = ((size_t)tile_f * kTileStride * sizeof(float) + 15) & ~(size_t)15;
   double* as = reinterpret_cast<double*>(smem + xs_bytes);
 
-  const int item = blockIdx.x;
+  // The dispatcher deals workgroups to the 8 XCDs in turn: XCD x gets the
+  // workgroups b = x mod 8.  They take the x-th eighth of the work items in
+  // order, so each XCD's L2 holds the rows of its own chunks only.
+  const int item = xcd_item((int)blockIdx.x, (int)gridDim.x);
   const int sb = item % nsb;
   const int ch = item / nsb;
   const int64_t s0 = (int64_t)sb * kSamplesPerBlock;
@@ -1003,7 +1015,8 @@ adjoint_kernel(const PathHdr* __restrict__ hdr, const int32_t* __restrict__ feat
   size_t xs_bytes = ((size_t)tile_f * kTileStride * sizeof(float) + 15) & ~(size_t)15;
   T* gs = reinterpret_cast<T*>(smem + xs_bytes);
 
-  const int item = blockIdx.x;
+  // work items dealt to the XCDs in contiguous eighths (xcd_item)
+  const int item = xcd_item((int)blockIdx.x, (int)gridDim.x);
   const int sb = item % nsb;
   const int ch = item / nsb;
   const int64_t s0 = (int64_t)sb * kSamplesPerBlock;
