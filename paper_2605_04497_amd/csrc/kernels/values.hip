@@ -705,15 +705,6 @@ __device__ __forceinline__ ItemRows item_rows(const Segment* segs, const int32_t
   return ir;
 }
 
-// Work item of workgroup b of n: the workgroups of one XCD (b mod 8) take
-// one contiguous eighth of the items (the last n mod 8 in their own order).
-__device__ __forceinline__ int xcd_item(int b, int n) {
-  constexpr int kXcds = 8;
-  const int per = n / kXcds;
-  if (b >= per * kXcds) return b;
-  return (b % kXcds) * per + b / kXcds;
-}
-
 // tile_f: the features the LDS layout is sized for (F, or kSegFeatures with
 // segments); F: phi's row length.
 template <typename T, int DMAX, int NH, bool STORE_G, int NN>

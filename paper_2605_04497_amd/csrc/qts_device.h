@@ -194,6 +194,17 @@ inline size_t values_lds_bytes(int F) {
 // Largest F whose tile + FP64 accumulator fit in one workgroup's LDS.
 constexpr int kMaxLdsBytes = 160 * 1024;
 
+// Work item of workgroup b of n.  The dispatcher deals workgroups to the 8
+// XCDs in turn (b goes to XCD b mod 8); the workgroups of one XCD take one
+// contiguous eighth of the items, so its L2 serves the data of neighbouring
+// items (the last n mod 8 workgroups keep their own index).
+__device__ __forceinline__ int xcd_item(int b, int n) {
+  constexpr int kXcds = 8;
+  const int per = n / kXcds;
+  if (b >= per * kXcds) return b;
+  return (b % kXcds) * per + b / kXcds;
+}
+
 // Wave-uniform load through the scalar data cache: reading through the
 // constant address space lets the compiler emit s_load for an address that is
 // uniform across the wave (path data read by every lane of a wavefront).
