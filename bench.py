@@ -27,11 +27,13 @@ if ROOT not in sys.path:
 
 METRIC = "sample-tree-leaf paths/s for SHAP, FP32 vs FP64 GPU, at max rel err ≤1e-5"
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 FMA lanes/s.  Without
-# packed FP32 (not used here) FP32 and FP64 vector FMA both peak at 78.6 TFLOP/s;
-# AMD's 157.3 TFLOP/s FP32 figure needs packed (two-wide) FP32 instructions.
-PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-PEAK_FP32_PACKED_TFLOPS = 157.3
+# MI355X published vector peaks (256 CUs at 2.4 GHz).  FP64: one wave64 FMA per
+# CU per clock.  FP32: twice that.  Plain (not packed) FP32 FMAs and multiplies
+# whose operands are all vector registers issue at up to 1.59 wave
+# instructions per CU per clock in probes on this GPU, so the FP32 figure is the
+# ceiling for this build too, although it uses no packed FP32 instructions.
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 # LDS FP64 atomic add, measured on MI355X: 2.45 lanes per clock per CU, random
 # addresses in an 80 KB table (the interactions kernel's accumulator)
@@ -124,15 +126,14 @@ def kernel_sources_sha():
 def executed(leg, precision, seconds):
     """Executed flops of one call of a leg from its counters (FP32 and FP64
     vector flops together), as TFLOP/s over `seconds`, with the fraction of
-    the published peak of the precision and of the non-packed issue ceiling;
+    the published peak of the precision;
     None where the table does not hold the leg or the kernels have changed."""
     fl = EXECUTED_FLOPS.get((leg, precision))
     if fl is None or EXECUTED_FLOPS_SHA != kernel_sources_sha():
         return None
     tf = (fl[0] + fl[1]) / seconds / 1e12
-    peak = PEAK_FP32_PACKED_TFLOPS if precision == "fp32" else PEAK_VALU_TFLOPS
+    peak = PEAK_FP32_TFLOPS if precision == "fp32" else PEAK_FP64_TFLOPS
     return {"executed_tflops": tf, "frac_of_peak": tf / peak, "peak_tflops": peak,
-            "frac_of_nonpacked_issue_ceiling": tf / PEAK_VALU_TFLOPS,
             "flops_per_call": {"fp32": fl[0], "fp64": fl[1]},
             "source": "SQ_INSTS_VALU_FLOPS_FP32/_FP64 x 64 over one call's dispatches, "
                       "rocprofv3 --pmc of bench.py --flop-call %s:%s" % (leg, precision)}
@@ -986,8 +987,8 @@ def main():
         "fp64": {"value": units / (r64["ms_per_step"] * 1e-3), "ms_per_step": r64["ms_per_step"],
                  "kernel_ms": r64["kernel_ms"], "dtype": "f64",
                  "speedup_fp32_over_fp64": r64["ms_per_step"] / r32["ms_per_step"]},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_PACKED_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_PACKED_TFLOPS,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": measured_traffic(e.launch_shape("values", "fp32", 0)),
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
                      "flops_per_launch": kernel_flops,
@@ -997,11 +998,10 @@ def main():
                      "rows": n_rows, "elements_per_sample": n_vel,
                      "shared_slots_per_sample": n_shared,
                      "kept_prefix_levels_per_sample": n_kept,
-                     "peak_note": "published MI355X FP32 vector peak, which needs packed "
-                                  "two-wide FP32 instructions; this build is compiled without "
-                                  "them, so its issue ceiling is the non-packed one",
-                     "nonpacked_issue_ceiling": PEAK_VALU_TFLOPS,
-                     "frac_of_nonpacked_issue_ceiling": achieved / PEAK_VALU_TFLOPS,
+                     "peak_note": "published MI355X FP32 vector peak; plain FP32 FMAs and "
+                                  "multiplies on vector-register operands issue at up to 1.59 "
+                                  "wave instructions per CU per clock in probes on this GPU "
+                                  "(2 at this peak), so it applies without packed instructions",
                      "kernel": "values_kernel<float, 8, 8, true, 8>", "kernel_ms": r32["kernel_ms"],
                      "kernel_ms_scope": "event pair around each graph replay (zero-fill, "
                                         "values kernel, cast)" if not args.eager else
