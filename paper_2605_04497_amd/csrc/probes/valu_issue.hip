@@ -10,12 +10,18 @@
 // Build and run:
 //   hipcc -O3 --offload-arch=gfx950 -Xclang -target-feature -Xclang -packed-fp32-ops \
 //       paper_2605_04497_amd/csrc/probes/valu_issue.hip -o /tmp/valu_issue && /tmp/valu_issue
+// `/tmp/valu_issue FORM W` runs one case (FORM one of the names printed, FP32),
+// so that a counter run (rocprofv3 --pmc) covers a known instruction count:
+// two launches, of 16 and 20 000 iterations, each of 16 chains on 4 W waves
+// per CU.
 //
 // Memory: every thread writes out[blockIdx.x * 256 + threadIdx.x] once, and
 // thread 0 of each workgroup nothing else; the largest grid is kMaxBlocks
 // workgroups, the size of `out`.
 #include <hip/hip_runtime.h>
 #include <cstdio>
+#include <cstdlib>
+#include <cstring>
 
 namespace {
 
@@ -91,9 +97,29 @@ void run(const char* name, int waves_per_simd, void* out, int instr_per_step) {
 
 }  // namespace
 
-int main() {
+int main(int argc, char** argv) {
   void* out = nullptr;
   if (hipMalloc(&out, sizeof(double) * kMaxBlocks * 256) != hipSuccess) return 1;
+  if (argc == 3) {
+    const int w = atoi(argv[2]);
+    if (w < 1 || w > kMaxWavesPerSimd) {
+      fprintf(stderr, "W must be 1..%d\n", kMaxWavesPerSimd);
+      return 2;
+    }
+    const char* f = argv[1];
+    if (!strcmp(f, "fma")) run<float, 16, kFmaShared>("fma", w, out, 1);
+    else if (!strcmp(f, "mul")) run<float, 16, kMulChain>("mul", w, out, 1);
+    else if (!strcmp(f, "fma-dot")) run<float, 16, kFmaDot>("fma-dot", w, out, 1);
+    else if (!strcmp(f, "cmp-select")) run<float, 16, kCmpSel>("cmp-select", w, out, 4);
+    else if (!strcmp(f, "fma-sgpr")) run<float, 16, kFmaScalar>("fma-sgpr", w, out, 1);
+    else if (!strcmp(f, "mul-sgpr")) run<float, 16, kMulScalar>("mul-sgpr", w, out, 1);
+    else {
+      fprintf(stderr, "unknown form %s\n", f);
+      return 2;
+    }
+    (void)hipFree(out);
+    return 0;
+  }
   for (int w : {4, 8, 16}) run<float, 16, kFmaShared>("fma", w, out, 1);
   for (int w : {4, 8, 16}) run<float, 16, kMulChain>("mul", w, out, 1);
   for (int w : {4, 8, 16}) run<float, 16, kFmaDot>("fma-dot", w, out, 1);
