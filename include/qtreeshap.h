@@ -255,7 +255,9 @@ int qts_shap_interactions(const qts_ensemble* ens, const float* X, int64_t M, in
  * where that takes more than four ranges (F above about 80), straight into
  * the output with FP64 atomics.
  * Errors: QTS_E_UNSUPPORTED in the path form when one feature's triples
- * (k(k-1)/2 of them) do not fit in LDS (F above about 170). */
+ * (k(k-1)/2 of them) do not fit in LDS (F above about 170).  The depth-first
+ * form has no such limit: select it with QTS_PAIRS_DFS, or call qts_autotune
+ * under QTS_PAIRS_AUTO, which takes it where the path form does not fit. */
 int qts_shap_interactions3(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,
                            const double* leaf_values, void* out, qts_precision precision,
                            void* stream);
