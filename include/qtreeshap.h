@@ -60,7 +60,7 @@ enum {
   QTS_E_UNSUPPORTED = -3,   /* tree deeper than 128, path with > 64 unique features;
                                qts_shap_interactions3 in the path form also
                                when one feature's triples do not fit in LDS
-                               (F above about 170) */
+                               (F above about 180 to 203) */
   QTS_E_HIP = -4,           /* a HIP runtime error; its text is in qts_last_error() */
   QTS_E_OOM = -5            /* host or device allocation failed */
 };
@@ -255,7 +255,9 @@ int qts_shap_interactions(const qts_ensemble* ens, const float* X, int64_t M, in
  * where that takes more than four ranges (F above about 80), straight into
  * the output with FP64 atomics.
  * Errors: QTS_E_UNSUPPORTED in the path form when one feature's triples
- * (k(k-1)/2 of them) do not fit in LDS (F above about 170).  The depth-first
+ * (k(k-1)/2 of them) do not fit in LDS: F above 203 for rows of at most 8
+ * features, above about 180 to 200 for longer rows (by row length and
+ * precision).  The depth-first
  * form has no such limit: select it with QTS_PAIRS_DFS, or call qts_autotune
  * under QTS_PAIRS_AUTO, which takes it where the path form does not fit. */
 int qts_shap_interactions3(const qts_ensemble* ens, const float* X, int64_t M, int64_t ldx,

@@ -169,3 +169,30 @@ def test_dfs3_batches_agree(q):
     err = float(np.abs(a - b).max() / np.abs(b).max())
     print("dfs3 batches: max rel diff %.2e" % err, flush=True)
     assert err <= 1e-12
+
+
+def test_dfs3_auto_wide_features(q, oracle_mod):
+    """F = 240, beyond what the path form's third-order kernels hold in LDS
+    (one feature's triples fit up to F = 203 for rows of at most 8 features).
+    Under 'auto' an untuned ensemble takes the path form and reports
+    QTS_E_UNSUPPORTED (a host-side check, before any third-order kernel);
+    after qts_autotune it takes the depth-first form, which matches the
+    oracle in both precisions."""
+    from paper_2605_04497_amd import _lib as L
+    rng = np.random.default_rng(23)
+    F = 240
+    ens = _chains(rng, 3, F, 6)
+    X = rng.standard_normal((3, F)).astype(np.float32)
+    Xd = torch.from_numpy(X).cuda()
+    e = q.Ensemble(ens)
+    with pytest.raises(L.QtsError) as ei:
+        e.shap_interactions3(Xd, "fp32")
+        torch.cuda.synchronize()
+    assert ei.value.code == L.QTS_E_UNSUPPORTED
+    want = packed(oracle_mod.shap_sii3(ens, X, n=8))
+    assert np.abs(want).max() > 0
+    for precision in ("fp32", "fp64"):
+        e.autotune(3, precision)
+        got = e.shap_interactions3(Xd, precision)
+        torch.cuda.synchronize()
+        check(got.double().cpu().numpy(), want, precision, "dfs3 auto, F = 240")
