@@ -29,7 +29,7 @@ METRIC = "sample-tree-leaf paths/s for SHAP, FP32 vs FP64 GPU, at max rel err â‰
 
 # MI355X published vector peaks (256 CUs at 2.4 GHz).  FP64: one wave64 FMA per
 # CU per clock.  FP32: twice that.  Plain (not packed) FP32 FMAs and multiplies
-# whose operands are all vector registers issue at up to 1.69 wave
+# whose operands are all vector registers issue at up to 1.71 wave
 # instructions per CU per clock in probes on this GPU, so the FP32 figure is the
 # ceiling for this build too, although it uses no packed FP32 instructions.
 PEAK_FP64_TFLOPS = 78.6
@@ -999,7 +999,7 @@ def main():
                      "shared_slots_per_sample": n_shared,
                      "kept_prefix_levels_per_sample": n_kept,
                      "peak_note": "published MI355X FP32 vector peak; plain FP32 FMAs and "
-                                  "multiplies on vector-register operands issue at up to 1.69 "
+                                  "multiplies on vector-register operands issue at up to 1.71 "
                                   "wave instructions per CU per clock in probes on this GPU "
                                   "(2 at this peak), so it applies without packed instructions",
                      "kernel": "values_kernel<float, 8, 8, true, 8>", "kernel_ms": r32["kernel_ms"],

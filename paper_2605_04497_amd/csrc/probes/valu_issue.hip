@@ -42,11 +42,11 @@ enum Form {
 };
 
 template <typename T, int NCH, int FORM>
-__global__ __launch_bounds__(256) void probe(T* out, int iters, float sb, float sc) {
+__global__ __launch_bounds__(256) void probe(T* out, int iters, float sb, float sc, double sd) {
   T a[NCH], w[NCH];
   const T v = (T)sb + (T)threadIdx.x * (T)1e-9;
   const T u = (T)sc + (T)threadIdx.x * (T)1e-9;
-  const T s = (T)sb;
+  const T s = sizeof(T) == 8 ? (T)sd : (T)sb;  // a kernel argument: a scalar register
 #pragma unroll
   for (int i = 0; i < NCH; ++i) {
     a[i] = (T)threadIdx.x * (T)1e-3 + (T)i;
@@ -78,10 +78,10 @@ void run(const char* name, int waves_per_simd, void* out, int instr_per_step) {
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   hipLaunchKernelGGL((probe<T, NCH, FORM>), dim3(blocks), dim3(256), 0, 0, (T*)out, 16, 0.999f,
-                     1e-4f);
+                     1e-4f, 0.999);
   (void)hipEventRecord(e0);
   hipLaunchKernelGGL((probe<T, NCH, FORM>), dim3(blocks), dim3(256), 0, 0, (T*)out, iters,
-                     0.999f, 1e-4f);
+                     0.999f, 1e-4f, 0.999);
   (void)hipEventRecord(e1);
   (void)hipEventSynchronize(e1);
   float ms = 0;
@@ -128,6 +128,8 @@ int main(int argc, char** argv) {
   for (int w : {4, 8, 16}) run<float, 16, kMulScalar>("mul-sgpr", w, out, 1);
   for (int w : {4, 8}) run<double, 8, kFmaShared>("fma", w, out, 1);
   for (int w : {4, 8}) run<double, 8, kMulChain>("mul", w, out, 1);
+  for (int w : {4, 8}) run<double, 8, kFmaScalar>("fma-sgpr", w, out, 1);
+  for (int w : {4, 8}) run<double, 8, kMulScalar>("mul-sgpr", w, out, 1);
   (void)hipFree(out);
   return 0;
 }
