@@ -373,6 +373,9 @@ void build_nodes(DeviceTable& d) {
     d.n32.w[m] = (float)w[m];
     d.n64.t[m] = t[m];
     d.n64.w[m] = w[m];
+    // the FP32 short-row walks take the rule as instruction literals
+    if (d.n32.t[m] != rule8_t32(m) || d.n32.w[m] != rule8_w32(m))
+      fail(QTS_E_UNSUPPORTED, "the FP32 8-node rule differs from the kernels' constants");
   }
   // fewer-node rules, padded with zero nodes and weights
   auto rule = [&](int n, NodeConsts<float>& f32, NodeConsts<double>& f64) {

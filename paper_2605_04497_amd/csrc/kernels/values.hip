@@ -62,6 +62,22 @@ __device__ __forceinline__ double to_vgpr(double v) {
   return r;
 }
 
+// Node m and weight m of the 8-node rule in the walks that hold all 8 nodes
+// in one pass: FP32 takes them as instruction literals, FP64 from the kernel
+// argument (an FP32 FMA or multiply reading a scalar register issues at about
+// half the rate of one with a literal or vector operands; FP64 shows no such
+// difference).
+template <typename T>
+__device__ __forceinline__ T node8_t(const NodeConsts<T>& nc, int m) {
+  if constexpr (sizeof(T) == 4) return rule8_t32(m);
+  else return nc.t[m];
+}
+template <typename T>
+__device__ __forceinline__ T node8_w(const NodeConsts<T>& nc, int m) {
+  if constexpr (sizeof(T) == 4) return rule8_w32(m);
+  else return nc.w[m];
+}
+
 // Add a row's leaf-value gradient, summed over the wave's 64 samples.  det:
 // grad_leaf is this sample block's own row of partial sums, and every leaf
 // belongs to one row, so a plain store suffices (and keeps the result
@@ -394,7 +410,7 @@ __device__ __forceinline__ void values_rows_shared(
   // shared slots and are kept from the previous row
   T P[7][NH];
 #pragma unroll
-  for (int m = 0; m < NH; ++m) P[0][m] = nc.w[m];
+  for (int m = 0; m < NH; ++m) P[0][m] = kScalarT ? node8_w(nc, m) : nc.w[m];
   const char* xl = reinterpret_cast<const char*>(xs + lane);
   char* al = reinterpret_cast<char*>(as + lane);
   for (int p = p_first; p < p_last; ++p) {
@@ -449,9 +465,9 @@ __device__ __forceinline__ void values_rows_shared(
         }
         cf[k] = c;
         if (kScalarT) {
-          // t from SGPRs
+          // t as FP32 literals, or from SGPRs (FP64)
 #pragma unroll
-          for (int m = 0; m < NH; ++m) G[k][m] = fmaT(nc.t[m], c, bv);
+          for (int m = 0; m < NH; ++m) G[k][m] = fmaT(node8_t(nc, m), c, bv);
         } else {
 #pragma unroll
           for (int m = 0; m < NH; ++m) G[k][m] = fmaT(tv[m], c, b);
@@ -875,7 +891,7 @@ __device__ __forceinline__ void adjoint_rows_shared(
   // depend only on shared slots and are kept from the previous row
   T P[7][NH];
 #pragma unroll
-  for (int m = 0; m < NH; ++m) P[0][m] = nc.w[m];
+  for (int m = 0; m < NH; ++m) P[0][m] = kScalarT ? node8_w(nc, m) : nc.w[m];
   const char* xl = reinterpret_cast<const char*>(xs + lane);
   const char* gl = reinterpret_cast<const char*>(gs + lane);
   for (int p = p_first; p < p_last; ++p) {
@@ -934,7 +950,7 @@ __device__ __forceinline__ void adjoint_rows_shared(
         gc[k] = *reinterpret_cast<const T*>(gl + go[k]) * c;
         if (kScalarT) {
 #pragma unroll
-          for (int m = 0; m < NH; ++m) G[k][m] = fmaT(nc.t[m], c, bv);
+          for (int m = 0; m < NH; ++m) G[k][m] = fmaT(node8_t(nc, m), c, bv);
         } else {
 #pragma unroll
           for (int m = 0; m < NH; ++m) G[k][m] = fmaT(tv[m], c, bl[k]);
@@ -969,11 +985,11 @@ __device__ __forceinline__ void adjoint_rows_shared(
         for (int m = 0; m < NH; ++m) S[m] *= G[j][m];
       }
     }
-    T sR = R[0], stR = (kScalarT ? nc.t[0] : tv[0]) * R[0];
+    T sR = R[0], stR = (kScalarT ? node8_t(nc, 0) : tv[0]) * R[0];
 #pragma unroll
     for (int m = 1; m < NH; ++m) {
       sR += R[m];
-      stR = fmaT(kScalarT ? nc.t[m] : tv[m], R[m], stR);
+      stR = fmaT(kScalarT ? node8_t(nc, m) : tv[m], R[m], stR);
     }
     const T gq = g0 * q0;
     double gA = (double)fmaT(bA, sR, cA * (stR + gq));

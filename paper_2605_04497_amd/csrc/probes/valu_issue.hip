@@ -39,6 +39,8 @@ enum Form {
   kCmpSel,      // a = a > u ? a * v : a + u (compare, multiply, add, select)
   kFmaScalar,   // a = fma(a, s, u): s a scalar register (kernel argument)
   kMulScalar,   // a = a * s
+  kFmaLiteral,  // a = fma(a, K, u): K a literal constant in the instruction
+  kMulLiteral,  // a = a * K
 };
 
 template <typename T, int NCH, int FORM>
@@ -61,7 +63,9 @@ __global__ __launch_bounds__(256) void probe(T* out, int iters, float sb, float 
       else if (FORM == kFmaDot) a[i] = fm(w[i], v, a[i]);
       else if (FORM == kCmpSel) a[i] = (a[i] > u) ? a[i] * v : a[i] + u;
       else if (FORM == kFmaScalar) a[i] = fm(a[i], s, u);
-      else a[i] = a[i] * s;
+      else if (FORM == kMulScalar) a[i] = a[i] * s;
+      else if (FORM == kFmaLiteral) a[i] = fm(a[i], (T)0.7853981, u);
+      else a[i] = a[i] * (T)0.7853981;
     }
   }
   T r = 0;
@@ -113,6 +117,8 @@ int main(int argc, char** argv) {
     else if (!strcmp(f, "cmp-select")) run<float, 16, kCmpSel>("cmp-select", w, out, 4);
     else if (!strcmp(f, "fma-sgpr")) run<float, 16, kFmaScalar>("fma-sgpr", w, out, 1);
     else if (!strcmp(f, "mul-sgpr")) run<float, 16, kMulScalar>("mul-sgpr", w, out, 1);
+    else if (!strcmp(f, "fma-literal")) run<float, 16, kFmaLiteral>("fma-literal", w, out, 1);
+    else if (!strcmp(f, "mul-literal")) run<float, 16, kMulLiteral>("mul-literal", w, out, 1);
     else {
       fprintf(stderr, "unknown form %s\n", f);
       return 2;
@@ -126,6 +132,8 @@ int main(int argc, char** argv) {
   for (int w : {4, 8}) run<float, 16, kCmpSel>("cmp-select", w, out, 4);
   for (int w : {4, 8, 16}) run<float, 16, kFmaScalar>("fma-sgpr", w, out, 1);
   for (int w : {4, 8, 16}) run<float, 16, kMulScalar>("mul-sgpr", w, out, 1);
+  for (int w : {4, 8, 16}) run<float, 16, kFmaLiteral>("fma-literal", w, out, 1);
+  for (int w : {4, 8, 16}) run<float, 16, kMulLiteral>("mul-literal", w, out, 1);
   for (int w : {4, 8}) run<double, 8, kFmaShared>("fma", w, out, 1);
   for (int w : {4, 8}) run<double, 8, kMulChain>("mul", w, out, 1);
   for (int w : {4, 8}) run<double, 8, kFmaScalar>("fma-sgpr", w, out, 1);

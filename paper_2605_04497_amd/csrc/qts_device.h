@@ -16,6 +16,22 @@ struct NodeConsts {
 
 constexpr int kTileStride = kSamplesPerBlock + 1;  // padded LDS row (bank spread)
 
+// The 8-node rule on [0,1] rounded to FP32, as constants: the FP32 walks that
+// hold all 8 nodes in one pass take its nodes and weights as instruction
+// literals (an FP32 FMA or multiply with a literal operand issues at about
+// twice the rate of one reading a scalar register).  build_nodes checks that
+// they equal the FP32 rounding of the rule it computes (Eq. 10).
+__host__ __device__ constexpr float rule8_t32(int m) {
+  constexpr float t[kNodes] = {0x1.454e34p-6f, 0x1.a06d54p-4f, 0x1.e5dad4p-3f, 0x1.a214dap-2f,
+                               0x1.2ef592p-1f, 0x1.86894ap-1f, 0x1.cbf256p-1f, 0x1.f5d58ep-1f};
+  return t[m];
+}
+__host__ __device__ constexpr float rule8_w32(int m) {
+  constexpr float w[kNodes] = {0x1.9ea1dp-5f, 0x1.c76fb6p-4f, 0x1.413c5p-3f, 0x1.73636p-3f,
+                               0x1.73636p-3f, 0x1.413c5p-3f, 0x1.c76fb6p-4f, 0x1.9ea1dp-5f};
+  return w[m];
+}
+
 // A first-order row of a capacity-8 bucket as the walk over short rows reads
 // it: every field of the row in one record, so a wave fetches the row with a
 // few wide scalar loads from one address, and the LDS byte offsets of the

@@ -50,6 +50,23 @@ def test_gauss_legendre_rule(q, oracle_mod):
         q.gauss_legendre(0)
 
 
+def test_fp32_rule_constants(q):
+    """The FP32 walks over short rows take the 8-node rule as instruction
+    literals (rule8_t32, rule8_w32 in the device header): they must be the
+    FP32 rounding of the rule the library computes (Eq. 10), which the
+    library also checks when it sets up a device."""
+    src = open(os.path.join(ROOT, "paper_2605_04497_amd", "csrc", "qts_device.h")).read()
+
+    def table(name):
+        m = re.search(name + r"\(int m\) \{\s*constexpr float \w+\[kNodes\] = \{([^}]*)\}", src)
+        assert m, name
+        return np.array([float.fromhex(x.strip().rstrip("f")) for x in m.group(1).split(",")])
+
+    t, s, w = q.gauss_legendre(8)
+    assert np.array_equal(table("rule8_t32"), np.float32(t).astype(np.float64))
+    assert np.array_equal(table("rule8_w32"), np.float32(w).astype(np.float64))
+
+
 def _phi_from_table(tab, leaf_values, X, F):
     """Re-evaluate phi from the exported table in numpy (test-only path form)."""
     x, wq = np.polynomial.legendre.leggauss(8)
