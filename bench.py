@@ -45,7 +45,7 @@ LDS_F64_ATOMIC_RATE = 2.45 * 256 * 2.4e9
 # profiles/values_kernel_c2_values.md.  Valid only for the kernel source they
 # were measured on (its SHA-256 prefix); otherwise traffic is reported as null.
 TRAFFIC = {"kernel_source": "paper_2605_04497_amd/csrc/kernels/values.hip",
-           "sha256_16": "c6027b583b5c0e0e", "fetch_bytes": 9.3678e+08, "write_bytes": 1.6800e+09,
+           "sha256_16": "61456a43db1a66e4", "fetch_bytes": 9.3678e+08, "write_bytes": 1.6800e+09,
            "shape": [8, 32768]}
 
 
@@ -71,21 +71,21 @@ KERNEL_SOURCES = ("paper_2605_04497_amd/csrc/kernels/values.hip",
                   "paper_2605_04497_amd/csrc/kernels/interactions.hip",
                   "paper_2605_04497_amd/csrc/kernels/dfs.hip",
                   "paper_2605_04497_amd/csrc/kernels/common.hip")
-EXECUTED_FLOPS_SHA = "4f3cbffc3e8f632a"
+EXECUTED_FLOPS_SHA = "51c12ee84f59c8f8"
 # (leg, precision) -> (FP32 flops, FP64 flops) per call
 EXECUTED_FLOPS = {
     ("values", "fp32"): (2.9722e+12, 2.3578e+06),
-    ("values", "fp64"): (1.7444e+08, 4.3635e+12),
-    ("interactions", "fp32"): (2.0299e+12, 3.7532e+09),
-    ("interactions", "fp64"): (1.0161e+08, 3.0189e+12),
+    ("values", "fp64"): (1.0722e+08, 4.3635e+12),
+    ("interactions", "fp32"): (2.0298e+12, 3.7527e+09),
+    ("interactions", "fp64"): (1.0476e+08, 3.0189e+12),
     ("interactions_dfs", "fp32"): (8.7750e+11, 1.3826e+08),
     ("interactions_dfs", "fp64"): (3.8014e+08, 2.0795e+12),
     ("adjoint", "fp32"): (3.8300e+10, 1.7949e+09),
     ("adjoint", "fp64"): (1.2013e+07, 5.8223e+10),
     ("deep_values", "fp32"): (4.5586e+11, 6.7738e+05),
-    ("deep_values", "fp64"): (4.6610e+07, 5.2106e+11),
+    ("deep_values", "fp64"): (3.9215e+07, 5.2106e+11),
     ("deep_interactions", "fp32"): (2.9683e+12, 3.7794e+08),
-    ("deep_interactions", "fp64"): (1.6640e+08, 3.8921e+12),
+    ("deep_interactions", "fp64"): (1.7664e+08, 3.8937e+12),
     ("deep_interactions_dfs", "fp32"): (5.6340e+11, 2.0386e+08),
     ("deep_interactions_dfs", "fp64"): (2.5984e+08, 1.3728e+12),
     ("deep_third_order", "fp32"): (8.2126e+11, 2.2150e+07),
